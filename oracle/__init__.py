@@ -1,0 +1,212 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes front end of the FP64 CPU oracle.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  `build()` compiles harm_oracle.cpp with g++ (OpenMP, no
+fast-math, no FMA) into liboracle.so next to it.
+"""
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "harm_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+LIB_COUNT = os.path.join(HERE, "liboracle_count.so")
+
+
+def build(counting=False):
+    out = LIB_COUNT if counting else LIB
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math",
+           "-ffp-contract=off", "-o", out, SRC]
+    if counting:
+        cmd[1:1] = ["-DORACLE_COUNTING"]
+    else:
+        cmd[1:1] = ["-fopenmp"]
+    subprocess.check_call(cmd, cwd=HERE)
+    return out
+
+
+class Cfg(C.Structure):
+    _fields_ = [("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int),
+                ("x1min", C.c_double), ("x1max", C.c_double),
+                ("x2min", C.c_double), ("x2max", C.c_double),
+                ("x3min", C.c_double), ("x3max", C.c_double),
+                ("bc", C.c_int * 6), ("metric", C.c_int),
+                ("a", C.c_double), ("hslope", C.c_double),
+                ("gam", C.c_double), ("recon", C.c_int),
+                ("weno_eps", C.c_double), ("newton_tol", C.c_double),
+                ("newton_maxit", C.c_int), ("cfl", C.c_double),
+                ("nthreads", C.c_int)]
+
+
+_lib = None
+_lib_count = None
+
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int)
+
+
+def _declare(lib):
+    P = C.POINTER(Cfg)
+    lib.orc_run.argtypes = [P, _D, C.c_double, C.c_int, _D, _I]
+    lib.orc_run.restype = C.c_long
+    lib.orc_estimate_dt.argtypes = [P, _D]
+    lib.orc_estimate_dt.restype = C.c_double
+    lib.orc_fill_ghosts.argtypes = [P, _D]
+    lib.orc_divb.argtypes = [P, _D, _D, _D, _D]
+    lib.orc_fluxes.argtypes = [P, _D, _D, C.c_int]
+    lib.orc_prims_to_cons.argtypes = [P, _D, _D]
+    lib.orc_cons_to_prims.argtypes = [P, _D, _D, _D, _I]
+    lib.orc_cons_to_prims.restype = C.c_long
+    lib.orc_geom.argtypes = [P, C.c_double, C.c_double, _D, _D, _D, _D]
+    lib.orc_conn.argtypes = [P, C.c_double, C.c_double, _D]
+    lib.orc_point_flux.argtypes = [P, _D, C.c_double, C.c_double, C.c_int, _D, _D, _D]
+    lib.orc_point_source.argtypes = [P, _D, C.c_double, C.c_double, _D]
+    lib.orc_point_u_to_p.argtypes = [P, _D, _D, C.c_double, C.c_double, _D]
+    lib.orc_point_u_to_p.restype = C.c_int
+    lib.orc_weno5.argtypes = [C.c_double] * 6
+    lib.orc_weno5.restype = C.c_double
+    lib.orc_mc_slope.argtypes = [C.c_double] * 3
+    lib.orc_mc_slope.restype = C.c_double
+    return lib
+
+
+def lib(counting=False):
+    global _lib, _lib_count
+    if counting:
+        if _lib_count is None:
+            if not os.path.exists(LIB_COUNT) or os.path.getmtime(LIB_COUNT) < os.path.getmtime(SRC):
+                build(counting=True)
+            _lib_count = _declare(C.CDLL(LIB_COUNT))
+        return _lib_count
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _lib = _declare(C.CDLL(LIB))
+    return _lib
+
+
+def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
+        newton_maxit=30, cfl=0.9, nthreads=None):
+    c = Cfg()
+    c.n1, c.n2, c.n3 = grid.n1, grid.n2, grid.n3
+    c.x1min, c.x1max = grid.x1min, grid.x1max
+    c.x2min, c.x2max = grid.x2min, grid.x2max
+    c.x3min, c.x3max = grid.x3min, grid.x3max
+    for i in range(6):
+        c.bc[i] = int(grid.bc[i])
+    c.metric = int(grid.metric)
+    c.a, c.hslope = grid.a, grid.hslope
+    c.gam, c.recon, c.weno_eps = gam, int(recon), weno_eps
+    c.newton_tol, c.newton_maxit, c.cfl = newton_tol, newton_maxit, cfl
+    c.nthreads = nthreads or os.cpu_count() or 1
+    return c
+
+
+def _ptr(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def run(c, prims, dt, nsteps=1, counting=False, flags=False):
+    """Advance a copy of prims; returns (prims, fails, dts[, per-zone flags])."""
+    P = np.ascontiguousarray(prims, dtype=np.float64).copy()
+    dts = np.zeros(max(nsteps, 1))
+    fl = np.zeros(P.shape[1:], dtype=np.int32) if flags else None
+    fails = lib(counting).orc_run(C.byref(c), _ptr(P), float(dt), int(nsteps), _ptr(dts),
+                                  fl.ctypes.data_as(_I) if flags else None)
+    if flags:
+        return P, int(fails), dts, fl
+    return P, int(fails), dts
+
+
+def estimate_dt(c, prims):
+    P = np.ascontiguousarray(prims, dtype=np.float64).copy()
+    return lib().orc_estimate_dt(C.byref(c), _ptr(P))
+
+
+def fill_ghosts(c, prims):
+    P = np.ascontiguousarray(prims, dtype=np.float64).copy()
+    lib().orc_fill_ghosts(C.byref(c), _ptr(P))
+    return P
+
+
+def divb(c, prims, field=False):
+    P = np.ascontiguousarray(prims, dtype=np.float64)
+    mx, mean = C.c_double(), C.c_double()
+    f = np.zeros(P.shape[1:]) if field else None
+    lib().orc_divb(C.byref(c), _ptr(P), C.byref(mx), C.byref(mean),
+                   _ptr(f) if field else None)
+    return (mx.value, mean.value, f) if field else (mx.value, mean.value)
+
+
+def fluxes(c, prims, ct=True):
+    P = np.ascontiguousarray(prims, dtype=np.float64)
+    F = np.zeros((3,) + P.shape)
+    lib().orc_fluxes(C.byref(c), _ptr(P), _ptr(F), int(ct))
+    return F
+
+
+def prims_to_cons(c, prims):
+    P = np.ascontiguousarray(prims, dtype=np.float64)
+    U = np.zeros_like(P)
+    lib().orc_prims_to_cons(C.byref(c), _ptr(P), _ptr(U))
+    return U
+
+
+def cons_to_prims(c, cons, guess):
+    U = np.ascontiguousarray(cons, dtype=np.float64)
+    G = np.ascontiguousarray(guess, dtype=np.float64)
+    P = np.zeros_like(U)
+    flags = np.zeros(U.shape[1:], dtype=np.int32)
+    n = lib().orc_cons_to_prims(C.byref(c), _ptr(U), _ptr(G), _ptr(P),
+                                flags.ctypes.data_as(_I))
+    return P, int(n), flags
+
+
+def geom(c, x1, x2):
+    gcov = np.zeros(16)
+    gcon = np.zeros(16)
+    gdet, alpha = C.c_double(), C.c_double()
+    lib().orc_geom(C.byref(c), x1, x2, _ptr(gcov), _ptr(gcon), C.byref(gdet), C.byref(alpha))
+    return gcov.reshape(4, 4), gcon.reshape(4, 4), gdet.value, alpha.value
+
+
+def conn(c, x1, x2):
+    out = np.zeros(64)
+    lib().orc_conn(C.byref(c), x1, x2, _ptr(out))
+    return out.reshape(4, 4, 4)
+
+
+def point_flux(c, prims, x1, x2, d):
+    p = np.ascontiguousarray(prims, dtype=np.float64)
+    out = np.zeros(8)
+    cp, cm = C.c_double(), C.c_double()
+    lib().orc_point_flux(C.byref(c), _ptr(p), x1, x2, int(d), _ptr(out), C.byref(cp), C.byref(cm))
+    return out, cp.value, cm.value
+
+
+def point_source(c, prims, x1, x2):
+    p = np.ascontiguousarray(prims, dtype=np.float64)
+    out = np.zeros(8)
+    lib().orc_point_source(C.byref(c), _ptr(p), x1, x2, _ptr(out))
+    return out
+
+
+def point_u_to_p(c, cons, guess, x1, x2):
+    u = np.ascontiguousarray(cons, dtype=np.float64)
+    g = np.ascontiguousarray(guess, dtype=np.float64)
+    out = np.zeros(8)
+    r = lib().orc_point_u_to_p(C.byref(c), _ptr(u), _ptr(g), x1, x2, _ptr(out))
+    return out, r
+
+
+def weno5(a, b, c_, d, e, eps=1e-26):
+    return lib().orc_weno5(a, b, c_, d, e, eps)
+
+
+def mc_slope(l, c_, r):
+    return lib().orc_mc_slope(l, c_, r)

@@ -1,0 +1,997 @@
+// TEST INFRASTRUCTURE ONLY.  Plain, slow, scalar FP64 CPU reference of one
+// HARM ideal-GRMHD step; only the test-suite, the smoke check and the CPU
+// baseline leg of the benchmark load it.  It shares no code with the HIP
+// library.
+//
+// What it computes (the Algorithm section names the scheme; the stress-energy
+// tensor is the ideal part of the EGRMHD section):
+//   * geometry: Minkowski, or Kerr in modified Kerr-Schild coordinates, with
+//     the metric and connection cached per (x1, x2) as the GRCoordinates
+//     description says (Core section);
+//   * primitive -> conserved / flux with the normal-observer velocity;
+//   * linear MC or WENO5 reconstruction of each primitive (Algorithm section);
+//   * local Lax-Friedrichs fluxes with the fast-magnetosonic speed bound;
+//   * Flux-CT: B fluxes replaced by corner-averaged EMFs;
+//   * flux divergence + geometric source, two-stage SSP Runge-Kutta;
+//   * 1D_W Newton-Raphson inversion of conserved -> primitive (Algorithm and
+//     Performance sections name the 1D_w inverter);
+//   * ghost-zone boundary conditions, CFL time step and the corner div B.
+// Readings where the paper is silent are stated next to the code they shape.
+//
+// State layout: double[8][n3+6][n2+6][n1+6], x1 fastest, variables
+// (rho, u, u~1, u~2, u~3, B1, B2, B3).
+//
+// Build: g++ -O2 -fopenmp -fPIC -shared (no -ffast-math; x86-64 code without
+// FMA, so every operation is individually rounded).
+
+#include <cmath>
+#include <cstring>
+#include <cstdlib>
+#include <vector>
+#include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifdef ORACLE_COUNTING
+#include "flopcount.hpp"
+typedef CountedReal real;
+#else
+typedef double real;
+using std::sqrt;
+using std::fabs;
+#endif
+
+namespace {
+
+const int NV = 8, NG = 3;
+enum { RHO = 0, UU = 1, U1 = 2, U2 = 3, U3 = 4, B1 = 5, B2 = 6, B3 = 7 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_POLAR = 2, BC_FROZEN = 3 };
+enum { MINKOWSKI = 0, KERR_MKS = 1 };
+enum { RECON_MC = 0, RECON_WENO5 = 1 };
+
+}  // namespace
+
+extern "C" {
+typedef struct {
+  int n1, n2, n3;
+  double x1min, x1max, x2min, x2max, x3min, x3max;
+  int bc[6];
+  int metric;
+  double a, hslope;
+  double gam;          // adiabatic index
+  int recon;
+  double weno_eps;
+  double newton_tol;
+  int newton_maxit;
+  double cfl;
+  int nthreads;
+} orc_cfg;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- geometry --
+
+struct Geom {
+  real gcov[4][4], gcon[4][4], gdet, alpha;
+};
+
+// Kerr-Schild metric (M = 1) and its first derivatives with respect to r and
+// theta, written out from the closed form.
+//   Sigma = r^2 + a^2 cos^2 th,  z = 2 r / Sigma,
+//   g_tt = z - 1, g_tr = z, g_tph = -a z s^2, g_rr = 1 + z,
+//   g_rph = -a s^2 (1 + z), g_thth = Sigma, g_phph = s^2 (Sigma + a^2 s^2 (1+z)).
+void ks_metric(real a, real r, real th, real g[4][4], real dgr[4][4], real dgth[4][4]) {
+  real s = std::sin(th), c = std::cos(th);
+  real s2 = s * s, c2 = c * c;
+  real sig = r * r + a * a * c2;
+  real z = 2.0 * r / sig;
+  real sig_r = 2.0 * r, sig_th = -2.0 * a * a * c * s;
+  real z_r = 2.0 / sig - 2.0 * r * sig_r / (sig * sig);
+  real z_th = -2.0 * r * sig_th / (sig * sig);
+  real s2_th = 2.0 * s * c;
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) g[m][n] = dgr[m][n] = dgth[m][n] = 0.0;
+  g[0][0] = z - 1.0;            dgr[0][0] = z_r;  dgth[0][0] = z_th;
+  g[0][1] = z;                  dgr[0][1] = z_r;  dgth[0][1] = z_th;
+  g[0][3] = -a * z * s2;        dgr[0][3] = -a * z_r * s2;
+  dgth[0][3] = -a * (z_th * s2 + z * s2_th);
+  g[1][1] = 1.0 + z;            dgr[1][1] = z_r;  dgth[1][1] = z_th;
+  g[1][3] = -a * s2 * (1.0 + z); dgr[1][3] = -a * s2 * z_r;
+  dgth[1][3] = -a * (s2_th * (1.0 + z) + s2 * z_th);
+  g[2][2] = sig;                dgr[2][2] = sig_r; dgth[2][2] = sig_th;
+  real inner = sig + a * a * s2 * (1.0 + z);
+  g[3][3] = s2 * inner;
+  dgr[3][3] = s2 * (sig_r + a * a * s2 * z_r);
+  dgth[3][3] = s2_th * inner + s2 * (sig_th + a * a * (s2_th * (1.0 + z) + s2 * z_th));
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < m; n++) { g[m][n] = g[n][m]; dgr[m][n] = dgr[n][m]; dgth[m][n] = dgth[n][m]; }
+}
+
+// Metric at a point.  Modified KS: r = exp(x1), th = pi x2 + (1-h)/2 sin(2 pi x2),
+// ph = x3, so g_MKS[m][n] = L_m L_n g_KS[m][n] with L = (1, r, dth/dx2, 1).
+// The inverse is the closed-form KS inverse scaled by 1/(L_m L_n); sqrt(-g)
+// uses |sin th| so that zones continued past a pole stay finite.
+void geom_point(const orc_cfg& c, real x1, real x2, Geom& G) {
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) G.gcov[m][n] = G.gcon[m][n] = 0.0;
+  if (c.metric == MINKOWSKI) {
+    G.gcov[0][0] = G.gcon[0][0] = -1.0;
+    for (int i = 1; i < 4; i++) G.gcov[i][i] = G.gcon[i][i] = 1.0;
+    G.gdet = 1.0;
+    G.alpha = 1.0;
+    return;
+  }
+  const real a = c.a, h = c.hslope;
+  real r = std::exp(x1);
+  real th = M_PI * x2 + 0.5 * (1.0 - h) * std::sin(2.0 * M_PI * x2);
+  real dth = M_PI * (1.0 + (1.0 - h) * std::cos(2.0 * M_PI * x2));
+  real L[4] = {1.0, r, dth, 1.0};
+  real g[4][4], dgr[4][4], dgth[4][4];
+  ks_metric(a, r, th, g, dgr, dgth);
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) G.gcov[m][n] = g[m][n] * L[m] * L[n];
+  real s = std::sin(th), cth = std::cos(th);
+  real s2 = s * s;
+  real sig = r * r + a * a * cth * cth;
+  real z = 2.0 * r / sig;
+  real del = r * r - 2.0 * r + a * a;
+  real gi[4][4];
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) gi[m][n] = 0.0;
+  gi[0][0] = -(1.0 + z);
+  gi[0][1] = gi[1][0] = z;
+  gi[1][1] = del / sig;
+  gi[1][3] = gi[3][1] = a / sig;
+  gi[2][2] = 1.0 / sig;
+  gi[3][3] = 1.0 / (sig * s2);
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) G.gcon[m][n] = gi[m][n] / (L[m] * L[n]);
+  G.gdet = sig * fabs(s) * r * dth;
+  G.alpha = 1.0 / sqrt(-G.gcon[0][0]);
+}
+
+// Connection Gamma^l_{mn} = 1/2 g^{lk} (d_m g_kn + d_n g_km - d_k g_mn) at a
+// point, from analytic metric derivatives (only d/dx1 and d/dx2 are nonzero).
+void conn_point(const orc_cfg& c, real x1, real x2, real conn[4][4][4]) {
+  for (int l = 0; l < 4; l++)
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) conn[l][m][n] = 0.0;
+  if (c.metric == MINKOWSKI) return;
+  const real a = c.a, h = c.hslope;
+  real r = std::exp(x1);
+  real th = M_PI * x2 + 0.5 * (1.0 - h) * std::sin(2.0 * M_PI * x2);
+  real dth = M_PI * (1.0 + (1.0 - h) * std::cos(2.0 * M_PI * x2));
+  real d2th = -2.0 * M_PI * M_PI * (1.0 - h) * std::sin(2.0 * M_PI * x2);
+  real L[4] = {1.0, r, dth, 1.0};
+  real g[4][4], dgr[4][4], dgth[4][4];
+  ks_metric(a, r, th, g, dgr, dgth);
+  // dg[k][m][n] = d g_MKS[m][n] / d x^k
+  real dg[4][4][4];
+  for (int k = 0; k < 4; k++)
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) dg[k][m][n] = 0.0;
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) {
+      real LL = L[m] * L[n];
+      // x1: dL_1/dx1 = r = L_1, d g_KS/dx1 = r d g_KS/dr
+      real f1 = (m == 1 ? 1.0 : 0.0) + (n == 1 ? 1.0 : 0.0);
+      dg[1][m][n] = LL * (f1 * g[m][n] + r * dgr[m][n]);
+      // x2: dL_2/dx2 = d2th, d g_KS/dx2 = dth d g_KS/dth
+      real f2 = (m == 2 ? 1.0 : 0.0) + (n == 2 ? 1.0 : 0.0);
+      dg[2][m][n] = LL * (f2 * (d2th / dth) * g[m][n] + dth * dgth[m][n]);
+    }
+  Geom G;
+  geom_point(c, x1, x2, G);
+  for (int l = 0; l < 4; l++)
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) {
+        real sum = 0.0;
+        for (int k = 0; k < 4; k++)
+          sum += G.gcon[l][k] * (dg[m][k][n] + dg[n][k][m] - dg[k][m][n]);
+        conn[l][m][n] = 0.5 * sum;
+      }
+}
+
+// --------------------------------------------------- primitive -> fluxes --
+
+struct FluidState {
+  real ucon[4], ucov[4], bcon[4], bcov[4], bsq;
+};
+
+void lower(const real v[4], const Geom& G, real out[4]) {
+  for (int m = 0; m < 4; m++) {
+    real s = 0.0;
+    for (int n = 0; n < 4; n++) s += G.gcov[m][n] * v[n];
+    out[m] = s;
+  }
+}
+
+// Four-velocity from the normal-observer velocity u~ (McKinney & Gammie form):
+// gamma = sqrt(1 + g_ij u~i u~j), u^t = gamma/alpha, u^i = u~i - gamma alpha g^{ti};
+// field four-vector b^t = B^i u_i, b^i = (B^i + b^t u^i)/u^t.
+void fluid_state(const real P[NV], const Geom& G, FluidState& S) {
+  real qsq = 0.0;
+  for (int i = 1; i < 4; i++)
+    for (int j = 1; j < 4; j++) qsq += G.gcov[i][j] * P[U1 + i - 1] * P[U1 + j - 1];
+  real gamma = sqrt(1.0 + qsq);
+  S.ucon[0] = gamma / G.alpha;
+  for (int i = 1; i < 4; i++) S.ucon[i] = P[U1 + i - 1] - gamma * G.alpha * G.gcon[0][i];
+  lower(S.ucon, G, S.ucov);
+  S.bcon[0] = 0.0;
+  for (int i = 1; i < 4; i++) S.bcon[0] += P[B1 + i - 1] * S.ucov[i];
+  for (int i = 1; i < 4; i++) S.bcon[i] = (P[B1 + i - 1] + S.bcon[0] * S.ucon[i]) / S.ucon[0];
+  lower(S.bcon, G, S.bcov);
+  S.bsq = 0.0;
+  for (int m = 0; m < 4; m++) S.bsq += S.bcon[m] * S.bcov[m];
+}
+
+// Mixed stress-energy T^mu_nu = (rho+u+p+b^2) u^mu u_nu + (p + b^2/2) delta - b^mu b_nu.
+real tmunu(const real P[NV], const FluidState& S, real gam, int mu, int nu) {
+  real p = (gam - 1.0) * P[UU];
+  real w = P[RHO] + P[UU] + p + S.bsq;
+  real ptot = p + 0.5 * S.bsq;
+  return w * S.ucon[mu] * S.ucov[nu] + (mu == nu ? ptot : 0.0) - S.bcon[mu] * S.bcov[nu];
+}
+
+// Conserved variables (d = 0) or fluxes along x^d (d = 1..3):
+// sqrt(-g) (rho u^d, T^d_t + rho u^d, T^d_1, T^d_2, T^d_3, b^k u^d - b^d u^k).
+// The energy slot carries T^d_t + rho u^d (rest-mass energy removed).
+void prim_to_flux(const real P[NV], const FluidState& S, const Geom& G, real gam, int d, real F[NV]) {
+  F[RHO] = G.gdet * P[RHO] * S.ucon[d];
+  F[UU] = G.gdet * (tmunu(P, S, gam, d, 0) + P[RHO] * S.ucon[d]);
+  for (int i = 1; i < 4; i++) F[U1 + i - 1] = G.gdet * tmunu(P, S, gam, d, i);
+  for (int k = 1; k < 4; k++) {
+    if (d == 0)
+      F[B1 + k - 1] = G.gdet * P[B1 + k - 1];
+    else
+      F[B1 + k - 1] = G.gdet * (S.bcon[k] * S.ucon[d] - S.bcon[d] * S.ucon[k]);
+  }
+}
+
+// Characteristic speeds dx^d/dt of the fast magnetosonic bound: roots of
+// (k.u)^2 (1 - c^2) = c^2 k.k for the covector k = (-v, e_d), with
+// c^2 = cs^2 + vA^2 - cs^2 vA^2, cs^2 = gam p / w, vA^2 = b^2/(b^2 + w), w = rho + gam u.
+void vchar(const real P[NV], const FluidState& S, const Geom& G, real gam, int d,
+           real& cmax, real& cmin) {
+  real p = (gam - 1.0) * P[UU];
+  real w = P[RHO] + gam * P[UU];
+  real cs2 = gam * p / w;
+  real va2 = S.bsq / (S.bsq + w);
+  real c2 = cs2 + va2 - cs2 * va2;
+  real Au = S.ucon[d], Bu = S.ucon[0];
+  real Asq = G.gcon[d][d], Bsq = G.gcon[0][0], AB = G.gcon[0][d];
+  real A = Bu * Bu - c2 * (Bsq + Bu * Bu);
+  real B = -2.0 * (Au * Bu - c2 * (AB + Au * Bu));
+  real C = Au * Au - c2 * (Asq + Au * Au);
+  real disc = B * B - 4.0 * A * C;
+  if (disc < 0.0) disc = 0.0;
+  real sq = sqrt(disc);
+  real v1 = (-B + sq) / (2.0 * A);
+  real v2 = (-B - sq) / (2.0 * A);
+  cmax = v1 > v2 ? v1 : v2;
+  cmin = v1 > v2 ? v2 : v1;
+}
+
+// ---------------------------------------------------------- reconstruction --
+
+// Monotonised-central limited slope of zone c with neighbours l, r.
+real mc_slope(real l, real c, real r) {
+  real dl = c - l, dr = r - c, dc = r - l;
+  if (dl * dr <= 0.0) return 0.0;
+  real m = fabs(2.0 * dl);
+  if (fabs(2.0 * dr) < m) m = fabs(2.0 * dr);
+  if (fabs(0.5 * dc) < m) m = fabs(0.5 * dc);
+  return dc > 0.0 ? m : -m;
+}
+
+// WENO5 value at the right edge of zone c from point values (a,b,c,d,e):
+// Jiang-Shu smoothness indicators, linear weights (1/10, 6/10, 3/10), power 2.
+real weno5(real a, real b, real c, real d, real e, real eps) {
+  real p0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  real p1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  real p2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  real t;
+  t = a - 2.0 * b + c; real s0 = 13.0 / 12.0 * t * t;
+  t = a - 4.0 * b + 3.0 * c; s0 += 0.25 * t * t;
+  t = b - 2.0 * c + d; real s1 = 13.0 / 12.0 * t * t;
+  t = b - d; s1 += 0.25 * t * t;
+  t = c - 2.0 * d + e; real s2 = 13.0 / 12.0 * t * t;
+  t = 3.0 * c - 4.0 * d + e; s2 += 0.25 * t * t;
+  real a0 = 0.1 / ((eps + s0) * (eps + s0));
+  real a1 = 0.6 / ((eps + s1) * (eps + s1));
+  real a2 = 0.3 / ((eps + s2) * (eps + s2));
+  return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
+// ------------------------------------------------------------------ grid --
+
+struct Grid {
+  orc_cfg c;
+  int n[3];
+  int s1, s2, s3;     // padded extents
+  long nz;            // padded zones per variable
+  real dx[3], xmin[3];
+  // geometry cached per padded (i, j): centre, x1 face, x2 face, x1-x2 corner
+  std::vector<Geom> gC, gF1, gF2, gCorner;
+  std::vector<real> conn;  // 64 per (i, j)
+  bool pole_lo, pole_hi;   // x2 boundaries that sit on the polar axis
+
+  explicit Grid(const orc_cfg& cfg) : c(cfg) {
+    n[0] = c.n1; n[1] = c.n2; n[2] = c.n3;
+    s1 = c.n1 + 2 * NG; s2 = c.n2 + 2 * NG; s3 = c.n3 + 2 * NG;
+    nz = (long)s1 * s2 * s3;
+    xmin[0] = c.x1min; xmin[1] = c.x2min; xmin[2] = c.x3min;
+    dx[0] = (c.x1max - c.x1min) / c.n1;
+    dx[1] = (c.x2max - c.x2min) / c.n2;
+    dx[2] = (c.x3max - c.x3min) / c.n3;
+    // In modified KS the faces x2 = 0 and x2 = 1 are the polar axis (theta = 0, pi).
+    pole_lo = c.metric == KERR_MKS && std::fabs(c.x2min) < 1e-10;
+    pole_hi = c.metric == KERR_MKS && std::fabs(c.x2max - 1.0) < 1e-10;
+    long n2d = (long)s1 * s2;
+    gC.resize(n2d); gF1.resize(n2d); gF2.resize(n2d); gCorner.resize(n2d);
+    conn.resize(n2d * 64);
+    for (int j = -NG; j < c.n2 + NG; j++)
+      for (int i = -NG; i < c.n1 + NG; i++) {
+        long q = (long)(j + NG) * s1 + (i + NG);
+        real xc1 = xmin[0] + (i + 0.5) * dx[0], xc2 = xmin[1] + (j + 0.5) * dx[1];
+        real xf1 = xmin[0] + i * dx[0], xf2 = xmin[1] + j * dx[1];
+        geom_point(c, xc1, xc2, gC[q]);
+        geom_point(c, xf1, xc2, gF1[q]);
+        if (!((pole_lo && j == 0) || (pole_hi && j == c.n2)))
+          geom_point(c, xc1, xf2, gF2[q]);
+        if (!((pole_lo && j == 0) || (pole_hi && j == c.n2)))
+          geom_point(c, xf1, xf2, gCorner[q]);
+        real cn[4][4][4];
+        conn_point(c, xc1, xc2, cn);
+        for (int l = 0; l < 4; l++)
+          for (int m = 0; m < 4; m++)
+            for (int nn = 0; nn < 4; nn++) conn[q * 64 + l * 16 + m * 4 + nn] = cn[l][m][nn];
+      }
+  }
+  long id(int i, int j, int k) const {
+    return ((long)(k + NG) * s2 + (j + NG)) * s1 + (i + NG);
+  }
+  long id2(int i, int j) const { return (long)(j + NG) * s1 + (i + NG); }
+  // x3 faces lie at the zone-centre (x1, x2), and the metric does not depend on x3.
+  const Geom& face_geom(int d, int i, int j) const {
+    if (d == 1) return gF1[id2(i, j)];
+    if (d == 2) return gF2[id2(i, j)];
+    return gC[id2(i, j)];
+  }
+  bool pole_face(int d, int j) const {
+    return d == 2 && ((pole_lo && j == 0) || (pole_hi && j == c.n2));
+  }
+};
+
+inline real& V(std::vector<real>& a, const Grid& g, int v, int i, int j, int k) {
+  return a[v * g.nz + g.id(i, j, k)];
+}
+inline real Vc(const std::vector<real>& a, const Grid& g, int v, int i, int j, int k) {
+  return a[v * g.nz + g.id(i, j, k)];
+}
+
+// ------------------------------------------------------------ boundaries --
+
+// Ghost fill, one axis after another (x1, then x2 over the x1 ghosts too,
+// then x3 over everything), so edge and corner ghosts are consistent.
+//   periodic: wrap;  outflow: copy the nearest interior zone (all prims);
+//   polar: mirror across the axis, flipping u~2 and B2;  frozen: untouched.
+void fill_ghosts(const Grid& g, std::vector<real>& P) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  for (int v = 0; v < NV; v++) {
+    // x1
+    for (int k = 0; k < n3; k++)
+      for (int j = 0; j < n2; j++)
+        for (int m = 1; m <= NG; m++) {
+          int lo = -m, hi = n1 - 1 + m;
+          if (g.c.bc[0] == BC_PERIODIC) V(P, g, v, lo, j, k) = V(P, g, v, ((lo % n1) + n1) % n1, j, k);
+          else if (g.c.bc[0] == BC_OUTFLOW) V(P, g, v, lo, j, k) = V(P, g, v, 0, j, k);
+          if (g.c.bc[1] == BC_PERIODIC) V(P, g, v, hi, j, k) = V(P, g, v, hi % n1, j, k);
+          else if (g.c.bc[1] == BC_OUTFLOW) V(P, g, v, hi, j, k) = V(P, g, v, n1 - 1, j, k);
+        }
+    // x2
+    real flip = (v == U2 || v == B2) ? -1.0 : 1.0;
+    for (int k = 0; k < n3; k++)
+      for (int i = -NG; i < n1 + NG; i++)
+        for (int m = 1; m <= NG; m++) {
+          int lo = -m, hi = n2 - 1 + m;
+          if (g.c.bc[2] == BC_PERIODIC) V(P, g, v, i, lo, k) = V(P, g, v, i, ((lo % n2) + n2) % n2, k);
+          else if (g.c.bc[2] == BC_OUTFLOW) V(P, g, v, i, lo, k) = V(P, g, v, i, 0, k);
+          else if (g.c.bc[2] == BC_POLAR) V(P, g, v, i, lo, k) = flip * V(P, g, v, i, m - 1, k);
+          if (g.c.bc[3] == BC_PERIODIC) V(P, g, v, i, hi, k) = V(P, g, v, i, hi % n2, k);
+          else if (g.c.bc[3] == BC_OUTFLOW) V(P, g, v, i, hi, k) = V(P, g, v, i, n2 - 1, k);
+          else if (g.c.bc[3] == BC_POLAR) V(P, g, v, i, hi, k) = flip * V(P, g, v, i, n2 - m, k);
+        }
+    // x3
+    for (int j = -NG; j < n2 + NG; j++)
+      for (int i = -NG; i < n1 + NG; i++)
+        for (int m = 1; m <= NG; m++) {
+          int lo = -m, hi = n3 - 1 + m;
+          if (g.c.bc[4] == BC_PERIODIC) V(P, g, v, i, j, lo) = V(P, g, v, i, j, ((lo % n3) + n3) % n3);
+          else if (g.c.bc[4] == BC_OUTFLOW) V(P, g, v, i, j, lo) = V(P, g, v, i, j, 0);
+          if (g.c.bc[5] == BC_PERIODIC) V(P, g, v, i, j, hi) = V(P, g, v, i, j, hi % n3);
+          else if (g.c.bc[5] == BC_OUTFLOW) V(P, g, v, i, j, hi) = V(P, g, v, i, j, n3 - 1);
+        }
+  }
+}
+
+// ----------------------------------------------------------------- fluxes --
+
+// Left and right states at the lower face (along d) of zone (i, j, k).
+void reconstruct(const Grid& g, const std::vector<real>& P, int d, int i, int j, int k,
+                 real qL[NV], real qR[NV]) {
+  int di = d == 1, dj = d == 2, dk = d == 3;
+  for (int v = 0; v < NV; v++) {
+    real q[6];  // zones -3 .. +2 relative to (i, j, k) along d
+    for (int s = -3; s <= 2; s++) q[s + 3] = Vc(P, g, v, i + s * di, j + s * dj, k + s * dk);
+    if (g.c.recon == RECON_MC) {
+      qL[v] = q[2] + 0.5 * mc_slope(q[1], q[2], q[3]);
+      qR[v] = q[3] - 0.5 * mc_slope(q[2], q[3], q[4]);
+    } else {
+      qL[v] = weno5(q[0], q[1], q[2], q[3], q[4], g.c.weno_eps);
+      qR[v] = weno5(q[5], q[4], q[3], q[2], q[1], g.c.weno_eps);
+    }
+  }
+}
+
+// Local Lax-Friedrichs flux at the lower d-face of zone (i, j, k):
+// F = (F_L + F_R)/2 - c_max (U_R - U_L)/2, c_max = max(0, c+_L, c+_R, -c-_L, -c-_R).
+// Faces on the polar axis carry no flux (sqrt(-g) = 0 there).
+void face_flux(const Grid& g, const std::vector<real>& P, int d, int i, int j, int k, real F[NV]) {
+  if (g.pole_face(d, j)) {
+    for (int v = 0; v < NV; v++) F[v] = 0.0;
+    return;
+  }
+  real qL[NV], qR[NV];
+  reconstruct(g, P, d, i, j, k, qL, qR);
+  const Geom& G = g.face_geom(d, i, j);
+  FluidState SL, SR;
+  fluid_state(qL, G, SL);
+  fluid_state(qR, G, SR);
+  real FL[NV], FR[NV], UL[NV], UR[NV];
+  prim_to_flux(qL, SL, G, g.c.gam, d, FL);
+  prim_to_flux(qR, SR, G, g.c.gam, d, FR);
+  prim_to_flux(qL, SL, G, g.c.gam, 0, UL);
+  prim_to_flux(qR, SR, G, g.c.gam, 0, UR);
+  real cpl, cml, cpr, cmr;
+  vchar(qL, SL, G, g.c.gam, d, cpl, cml);
+  vchar(qR, SR, G, g.c.gam, d, cpr, cmr);
+  real cmax = 0.0;
+  if (cpl > cmax) cmax = cpl;
+  if (cpr > cmax) cmax = cpr;
+  if (-cml > cmax) cmax = -cml;
+  if (-cmr > cmax) cmax = -cmr;
+  for (int v = 0; v < NV; v++) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * cmax * (UR[v] - UL[v]);
+}
+
+// Fluxes along every direction on the faces the update and Flux-CT need:
+// x1 faces i in [0, n1] over j in [-1, n2], k in [-1, n3] (and cyclically).
+void compute_fluxes(const Grid& g, const std::vector<real>& P, std::vector<real> F[3]) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  for (int d = 1; d <= 3; d++) {
+    int lo[3] = {-1, -1, -1}, hi[3] = {n1, n2, n3};  // inclusive
+    lo[d - 1] = 0;
+#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+    for (int k = lo[2]; k <= hi[2]; k++)
+      for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+          real f[NV];
+          face_flux(g, P, d, i, j, k, f);
+          for (int v = 0; v < NV; v++) V(F[d - 1], g, v, i, j, k) = f[v];
+        }
+  }
+}
+
+// Flux-CT (Toth 2000).  The EMF on the edge at the lower corner of zone
+// (i, j, k) averages the four face fluxes of the transverse field around it:
+//   emf3 = [F1(B2) + F1(B2)_{j-1} - F2(B1) - F2(B1)_{i-1}] / 4
+//   emf2 = [F3(B1) + F3(B1)_{i-1} - F1(B3) - F1(B3)_{k-1}] / 4
+//   emf1 = [F2(B3) + F2(B3)_{k-1} - F3(B2) - F3(B2)_{j-1}] / 4
+// and the field fluxes are rebuilt from edge averages; the normal ones vanish.
+// Edges on the polar axis (sqrt(-g) = 0) carry zero emf1 and emf3, consistent
+// with the zero flux through the pole faces.
+void flux_ct(const Grid& g, std::vector<real> F[3]) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  std::vector<real> e1(g.nz, 0.0), e2(g.nz, 0.0), e3(g.nz, 0.0);
+  std::vector<real>& F1 = F[0];
+  std::vector<real>& F2 = F[1];
+  std::vector<real>& F3 = F[2];
+#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+  for (int k = 0; k <= n3; k++)
+    for (int j = 0; j <= n2; j++)
+      for (int i = 0; i <= n1; i++) {
+        bool pole = (g.pole_lo && j == 0) || (g.pole_hi && j == n2);
+        long q = g.id(i, j, k);
+        e3[q] = pole ? 0.0
+                     : 0.25 * (Vc(F1, g, B2, i, j, k) + Vc(F1, g, B2, i, j - 1, k) -
+                               Vc(F2, g, B1, i, j, k) - Vc(F2, g, B1, i - 1, j, k));
+        e2[q] = 0.25 * (Vc(F3, g, B1, i, j, k) + Vc(F3, g, B1, i - 1, j, k) -
+                        Vc(F1, g, B3, i, j, k) - Vc(F1, g, B3, i, j, k - 1));
+        e1[q] = pole ? 0.0
+                     : 0.25 * (Vc(F2, g, B3, i, j, k) + Vc(F2, g, B3, i, j, k - 1) -
+                               Vc(F3, g, B2, i, j, k) - Vc(F3, g, B2, i, j - 1, k));
+      }
+  auto E = [&](std::vector<real>& e, int i, int j, int k) -> real { return e[g.id(i, j, k)]; };
+#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+  for (int k = 0; k <= n3; k++)
+    for (int j = 0; j <= n2; j++)
+      for (int i = 0; i <= n1; i++) {
+        if (j < n2 && k < n3) {
+          V(F1, g, B1, i, j, k) = 0.0;
+          V(F1, g, B2, i, j, k) = 0.5 * (E(e3, i, j, k) + E(e3, i, j + 1, k));
+          V(F1, g, B3, i, j, k) = -0.5 * (E(e2, i, j, k) + E(e2, i, j, k + 1));
+        }
+        if (i < n1 && k < n3) {
+          V(F2, g, B1, i, j, k) = -0.5 * (E(e3, i, j, k) + E(e3, i + 1, j, k));
+          V(F2, g, B2, i, j, k) = 0.0;
+          V(F2, g, B3, i, j, k) = 0.5 * (E(e1, i, j, k) + E(e1, i, j, k + 1));
+        }
+        if (i < n1 && j < n2) {
+          V(F3, g, B1, i, j, k) = 0.5 * (E(e2, i, j, k) + E(e2, i + 1, j, k));
+          V(F3, g, B2, i, j, k) = -0.5 * (E(e1, i, j, k) + E(e1, i, j + 1, k));
+          V(F3, g, B3, i, j, k) = 0.0;
+        }
+      }
+}
+
+// ------------------------------------------------------- source, update --
+
+// Geometric source sqrt(-g) T^k_l Gamma^l_{nu k} for the four momentum-energy
+// slots (the energy equation has rest mass removed, which has no source).
+void source_point(const Geom& G, const real* cn, real gam, const real P[NV], real S[NV]) {
+  FluidState st;
+  fluid_state(P, G, st);
+  real T[4][4];
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) T[m][n] = tmunu(P, st, gam, m, n);
+  for (int v = 0; v < NV; v++) S[v] = 0.0;
+  for (int nu = 0; nu < 4; nu++) {
+    real s = 0.0;
+    for (int k = 0; k < 4; k++)
+      for (int l = 0; l < 4; l++) s += T[k][l] * cn[l * 16 + nu * 4 + k];
+    S[UU + nu] = G.gdet * s;
+  }
+}
+
+void source(const Grid& g, const real P[NV], int i, int j, real S[NV]) {
+  source_point(g.gC[g.id2(i, j)], &g.conn[g.id2(i, j) * 64], g.c.gam, P, S);
+}
+
+// ------------------------------------------------------------------ U -> P --
+
+// 1D_W inversion (Noble et al. 2006): with D = alpha U_rho/sqrt(-g),
+// Q_mu = alpha T^t_mu, Bn^i = alpha B^i and n_mu = (-alpha, 0, 0, 0), solve
+//   f(W) = Q.n + W - p(W, v^2) + Bn^2 (1 + v^2)/2 - (Q.Bn)^2/(2 W^2) = 0
+// with v^2(W) = [Qt^2 W^2 + (Q.Bn)^2 (Bn^2 + 2W)] / [(Bn^2 + W)^2 W^2] and
+// p = (gam-1)/gam [W (1 - v^2) - D sqrt(1 - v^2)], by Newton from the guess's
+// W = (rho + gam u) gamma^2, to |dW/W| < tol (at most maxit iterations) and
+// one further iteration.  A starting W with v^2 >= 1 is doubled until
+// v^2 < 1, and steps that would leave W > 0, v^2 < 1 are halved.  Returns 0 on success; on failure the hydro prims
+// are the guess.  B^i = U_B^i / sqrt(-g) in every case.
+int u_to_p(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[NV], real P[NV]) {
+  const real gam = c.gam;
+  for (int k = 0; k < 3; k++) P[B1 + k] = U[B1 + k] / G.gdet;
+  real alpha = G.alpha;
+  real D = alpha * U[RHO] / G.gdet;
+  real Qcov[4];
+  Qcov[0] = alpha * (U[UU] / G.gdet - U[RHO] / G.gdet);
+  for (int i = 1; i < 4; i++) Qcov[i] = alpha * U[UU + i] / G.gdet;
+  real Bn[4] = {0.0, alpha * P[B1], alpha * P[B2], alpha * P[B3]};
+  real ncov[4] = {-alpha, 0.0, 0.0, 0.0};
+  real ncon[4], Qcon[4];
+  for (int m = 0; m < 4; m++) {
+    ncon[m] = 0.0;
+    Qcon[m] = 0.0;
+    for (int n = 0; n < 4; n++) {
+      ncon[m] += G.gcon[m][n] * ncov[n];
+      Qcon[m] += G.gcon[m][n] * Qcov[n];
+    }
+  }
+  real Qdotn = 0.0, QdotQ = 0.0, QdotB = 0.0, Bsq = 0.0;
+  for (int m = 0; m < 4; m++) {
+    Qdotn += Qcov[m] * ncon[m];
+    QdotQ += Qcov[m] * Qcon[m];
+  }
+  for (int i = 1; i < 4; i++) {
+    QdotB += Qcov[i] * Bn[i];
+    for (int j = 1; j < 4; j++) Bsq += G.gcov[i][j] * Bn[i] * Bn[j];
+  }
+  real Qtsq = QdotQ + Qdotn * Qdotn;
+  real QB2 = QdotB * QdotB;
+  const real gfac = (gam - 1.0) / gam;
+
+  auto failed = [&]() {
+    for (int v = 0; v < 5; v++) P[v] = guess[v];
+    return 1;
+  };
+  auto vsq_of = [&](real W) {
+    return (Qtsq * W * W + QB2 * (Bsq + 2.0 * W)) / ((Bsq + W) * (Bsq + W) * W * W);
+  };
+  auto newton_step = [&](real W) {
+    real v2 = vsq_of(W);
+    real sq = sqrt(1.0 - v2);
+    real p = gfac * (W * (1.0 - v2) - D * sq);
+    real f = Qdotn + W - p + 0.5 * Bsq * (1.0 + v2) - QB2 / (2.0 * W * W);
+    real dv2 = -2.0 * (Qtsq + QB2 * (3.0 * W * W + 3.0 * W * Bsq + Bsq * Bsq) / (W * W * W)) /
+               ((W + Bsq) * (W + Bsq) * (W + Bsq));
+    real dpdW = gfac * (1.0 - v2);
+    real dpdv2 = gfac * (-W + D / (2.0 * sq));
+    real df = 1.0 - (dpdW + dpdv2 * dv2) + 0.5 * Bsq * dv2 + QB2 / (W * W * W);
+    return -f / df;
+  };
+
+  // initial W from the guess prims
+  real qsq = 0.0;
+  for (int i = 1; i < 4; i++)
+    for (int j = 1; j < 4; j++) qsq += G.gcov[i][j] * guess[U1 + i - 1] * guess[U1 + j - 1];
+  real W = (guess[RHO] + gam * guess[UU]) * (1.0 + qsq);
+  // v^2(W) falls with W: a guess below the physical range is doubled into it.
+  for (int b = 0; b < 60 && !(vsq_of(W) < 1.0); b++) W = 2.0 * W;
+  bool conv = false;
+  for (int it = 0; it < c.newton_maxit; it++) {
+    real dW = newton_step(W);
+    real Wn = W + dW;
+    // A step that leaves the physical range (W <= 0 or v^2 >= 1) is halved
+    // until it is back inside, at most 20 times.
+    for (int b = 0; b < 20 && !(Wn > 0.0 && vsq_of(Wn) < 1.0); b++) {
+      dW = 0.5 * dW;
+      Wn = W + dW;
+    }
+    if (!std::isfinite((double)Wn) || Wn <= 0.0) return failed();
+    W = Wn;
+    if (fabs(dW) < c.newton_tol * fabs(W)) { conv = true; break; }
+  }
+  if (!conv) return failed();
+  W = W + newton_step(W);
+  if (!std::isfinite((double)W) || W <= 0.0) return failed();
+
+  real v2 = vsq_of(W);
+  if (!(v2 >= 0.0 && v2 < 1.0)) return failed();
+  real gamma = 1.0 / sqrt(1.0 - v2);
+  real rho = D / gamma;
+  real u = (W * (1.0 - v2) - rho) / gam;
+  if (!(rho > 0.0) || !(u > 0.0)) return failed();
+  real pre = gamma / (W + Bsq);
+  real ut[3];
+  for (int i = 1; i < 4; i++) {
+    real Qt = Qcon[i] + ncon[i] * Qdotn;
+    ut[i - 1] = pre * (Qt + QdotB * Bn[i] / W);
+    if (!std::isfinite((double)ut[i - 1])) return failed();
+  }
+  P[RHO] = rho;
+  P[UU] = u;
+  P[U1] = ut[0];
+  P[U2] = ut[1];
+  P[U3] = ut[2];
+  return 0;
+}
+
+// ------------------------------------------------------------------ step --
+
+void cons_at(const Grid& g, const real P[NV], int i, int j, real U[NV]) {
+  const Geom& G = g.gC[g.id2(i, j)];
+  FluidState S;
+  fluid_state(P, G, S);
+  prim_to_flux(P, S, G, g.c.gam, 0, U);
+}
+
+// dU/dt = -[(dF1/dx1 + dF2/dx2) + dF3/dx3] + S at zone (i, j, k).
+void rhs(const Grid& g, const std::vector<real> F[3], const real P[NV], int i, int j, int k, real L[NV]) {
+  real S[NV];
+  source(g, P, i, j, S);
+  for (int v = 0; v < NV; v++) {
+    real d1 = (Vc(F[0], g, v, i + 1, j, k) - Vc(F[0], g, v, i, j, k)) / g.dx[0];
+    real d2 = (Vc(F[1], g, v, i, j + 1, k) - Vc(F[1], g, v, i, j, k)) / g.dx[1];
+    real d3 = (Vc(F[2], g, v, i, j, k + 1) - Vc(F[2], g, v, i, j, k)) / g.dx[2];
+    L[v] = -((d1 + d2) + d3) + S[v];
+  }
+}
+
+// One SSPRK2 (Heun) step:
+//   U1 = Un + dt L(Pn);                  P1   = U_to_P(U1; guess Pn)
+//   Un+1 = (Un + U1)/2 + (dt L(P1))/2;   Pn+1 = U_to_P(Un+1; guess P1)
+// Ghosts are refilled from each stage's prims before it runs.
+long step(const Grid& g, std::vector<real>& P, real dt, int* flags) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  std::vector<real> F[3];
+  for (int d = 0; d < 3; d++) F[d].assign(NV * g.nz, 0.0);
+  std::vector<real> Un(NV * g.nz, 0.0), U1v(NV * g.nz, 0.0);
+  std::vector<real> P1 = P;
+  long fails = 0;
+
+  for (int stage = 0; stage < 2; stage++) {
+    std::vector<real>& Pin = stage == 0 ? P : P1;
+    fill_ghosts(g, Pin);
+    compute_fluxes(g, Pin, F);
+    flux_ct(g, F);
+    std::vector<real> Pout = Pin;
+#pragma omp parallel for schedule(static) num_threads(g.c.nthreads) reduction(+ : fails)
+    for (int k = 0; k < n3; k++)
+      for (int j = 0; j < n2; j++)
+        for (int i = 0; i < n1; i++) {
+          real p[NV], L[NV], Unew[NV], guess[NV], pn[NV];
+          for (int v = 0; v < NV; v++) p[v] = Vc(Pin, g, v, i, j, k);
+          rhs(g, F, p, i, j, k, L);
+          if (stage == 0) {
+            real u0[NV];
+            cons_at(g, p, i, j, u0);
+            for (int v = 0; v < NV; v++) {
+              Unew[v] = u0[v] + dt * L[v];
+              V(Un, g, v, i, j, k) = u0[v];
+              V(U1v, g, v, i, j, k) = Unew[v];
+            }
+          } else {
+            for (int v = 0; v < NV; v++)
+              Unew[v] = 0.5 * (Vc(Un, g, v, i, j, k) + Vc(U1v, g, v, i, j, k)) + 0.5 * (dt * L[v]);
+          }
+          for (int v = 0; v < NV; v++) guess[v] = p[v];
+          int f = u_to_p(g.c, g.gC[g.id2(i, j)], Unew, guess, pn);
+          fails += f;
+          if (flags && f) flags[g.id(i, j, k)] += 1 << stage;
+          for (int v = 0; v < NV; v++) V(Pout, g, v, i, j, k) = pn[v];
+        }
+    if (stage == 0) P1 = Pout;
+    else P = Pout;
+  }
+  return fails;
+}
+
+// CFL time step: cfl / max over interior zones of sum_d max(|c+|, |c-|)/dx_d,
+// over the directions that have more than one zone.
+real estimate_dt(const Grid& g, std::vector<real>& P) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  real smax = 0.0;
+  for (int k = 0; k < n3; k++)
+    for (int j = 0; j < n2; j++)
+      for (int i = 0; i < n1; i++) {
+        real p[NV];
+        for (int v = 0; v < NV; v++) p[v] = Vc(P, g, v, i, j, k);
+        const Geom& G = g.gC[g.id2(i, j)];
+        FluidState S;
+        fluid_state(p, G, S);
+        real s = 0.0;
+        for (int d = 1; d <= 3; d++) {
+          if (g.n[d - 1] == 1) continue;
+          real cp, cm;
+          vchar(p, S, G, g.c.gam, d, cp, cm);
+          real cmx = fabs(cp) > fabs(cm) ? fabs(cp) : fabs(cm);
+          s += cmx / g.dx[d - 1];
+        }
+        if (s > smax) smax = s;
+      }
+  return g.c.cfl / smax;
+}
+
+// Corner-centred divergence of B from the conserved field sqrt(-g) B^d:
+// sum_d [sum of the four zones on the + side - the four on the - side]/(4 dx_d),
+// divided by sqrt(-g) at the corner.  Corners on non-periodic boundaries
+// (and so on the poles) are excluded.
+void divb(const Grid& g, std::vector<real>& P, real* out_max, real* out_mean, real* field) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  fill_ghosts(g, P);
+  int ilo = g.c.bc[0] == BC_PERIODIC ? 0 : 1, ihi = g.c.bc[1] == BC_PERIODIC ? n1 - 1 : n1 - 1;
+  int jlo = g.c.bc[2] == BC_PERIODIC ? 0 : 1, jhi = n2 - 1;
+  int klo = g.c.bc[4] == BC_PERIODIC ? 0 : 1, khi = n3 - 1;
+  (void)ihi;
+  real mx = 0.0, sum = 0.0;
+  long cnt = 0;
+  auto UB = [&](int d, int i, int j, int k) -> real {
+    return g.gC[g.id2(i, j)].gdet * Vc(P, g, B1 + d, i, j, k);
+  };
+  for (int k = klo; k <= khi; k++)
+    for (int j = jlo; j <= jhi; j++)
+      for (int i = ilo; i <= n1 - 1; i++) {
+        real dv = 0.0;
+        dv += (UB(0, i, j, k) + UB(0, i, j - 1, k) + UB(0, i, j, k - 1) + UB(0, i, j - 1, k - 1) -
+               UB(0, i - 1, j, k) - UB(0, i - 1, j - 1, k) - UB(0, i - 1, j, k - 1) - UB(0, i - 1, j - 1, k - 1)) /
+              (4.0 * g.dx[0]);
+        dv += (UB(1, i, j, k) + UB(1, i - 1, j, k) + UB(1, i, j, k - 1) + UB(1, i - 1, j, k - 1) -
+               UB(1, i, j - 1, k) - UB(1, i - 1, j - 1, k) - UB(1, i, j - 1, k - 1) - UB(1, i - 1, j - 1, k - 1)) /
+              (4.0 * g.dx[1]);
+        dv += (UB(2, i, j, k) + UB(2, i - 1, j, k) + UB(2, i, j - 1, k) + UB(2, i - 1, j - 1, k) -
+               UB(2, i, j, k - 1) - UB(2, i - 1, j, k - 1) - UB(2, i, j - 1, k - 1) - UB(2, i - 1, j - 1, k - 1)) /
+              (4.0 * g.dx[2]);
+        real val = fabs(dv) / g.gCorner[g.id2(i, j)].gdet;
+        if (field) field[g.id(i, j, k)] = val;
+        if (val > mx) mx = val;
+        sum += val;
+        cnt++;
+      }
+  *out_max = mx;
+  *out_mean = cnt ? sum / (real)(double)cnt : 0.0;
+}
+
+void load(const Grid& g, const double* src, std::vector<real>& dst) {
+  dst.resize(NV * g.nz);
+  for (long q = 0; q < NV * g.nz; q++) dst[q] = src[q];
+}
+void store(const Grid& g, const std::vector<real>& src, double* dst) {
+  for (long q = 0; q < NV * g.nz; q++) dst[q] = (double)src[q];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI ----
+
+extern "C" {
+
+// Advance the padded prims in place by `nsteps` SSPRK2 steps of size dt
+// (dt <= 0: recompute the CFL dt before each step).  Returns the number of
+// zone inversions that failed; the dt actually used per step go to dts and,
+// when flags is not null, failures are added per padded zone (1: first
+// stage, 2: second stage).
+long orc_run(const orc_cfg* c, double* prims, double dt, int nsteps, double* dts, int* flags) {
+  Grid g(*c);
+  std::vector<real> P;
+  load(g, prims, P);
+  long fails = 0;
+  for (int s = 0; s < nsteps; s++) {
+    real h = dt;
+    if (dt <= 0.0) {
+      fill_ghosts(g, P);
+      h = estimate_dt(g, P);
+    }
+    if (dts) dts[s] = (double)h;
+    fails += step(g, P, h, flags);
+  }
+  fill_ghosts(g, P);
+  store(g, P, prims);
+  return fails;
+}
+
+double orc_estimate_dt(const orc_cfg* c, double* prims) {
+  Grid g(*c);
+  std::vector<real> P;
+  load(g, prims, P);
+  fill_ghosts(g, P);
+  return (double)estimate_dt(g, P);
+}
+
+void orc_fill_ghosts(const orc_cfg* c, double* prims) {
+  Grid g(*c);
+  std::vector<real> P;
+  load(g, prims, P);
+  fill_ghosts(g, P);
+  store(g, P, prims);
+}
+
+void orc_divb(const orc_cfg* c, const double* prims, double* out_max, double* out_mean, double* field) {
+  Grid g(*c);
+  std::vector<real> P;
+  load(g, prims, P);
+  real mx, mean;
+  std::vector<real> fld;
+  if (field) fld.assign(g.nz, 0.0);
+  divb(g, P, &mx, &mean, field ? fld.data() : nullptr);
+  *out_max = (double)mx;
+  *out_mean = (double)mean;
+  if (field)
+    for (long q = 0; q < g.nz; q++) field[q] = (double)fld[q];
+}
+
+// Face fluxes of one stage from the given prims (ghosts filled here), after
+// Flux-CT when ct != 0.  F is 3 x 8 x padded zones; entry (i, j, k) of
+// direction d is the flux through the lower d-face of zone (i, j, k).
+void orc_fluxes(const orc_cfg* c, const double* prims, double* F, int ct) {
+  Grid g(*c);
+  std::vector<real> P;
+  load(g, prims, P);
+  fill_ghosts(g, P);
+  std::vector<real> Fv[3];
+  for (int d = 0; d < 3; d++) Fv[d].assign(NV * g.nz, 0.0);
+  compute_fluxes(g, P, Fv);
+  if (ct) flux_ct(g, Fv);
+  for (int d = 0; d < 3; d++)
+    for (long q = 0; q < NV * g.nz; q++) F[d * NV * g.nz + q] = (double)Fv[d][q];
+}
+
+// Conserved variables at zone centres of the interior (padded layout).
+void orc_prims_to_cons(const orc_cfg* c, const double* prims, double* cons) {
+  Grid g(*c);
+  for (int k = 0; k < c->n3; k++)
+    for (int j = 0; j < c->n2; j++)
+      for (int i = 0; i < c->n1; i++) {
+        real p[NV], u[NV];
+        for (int v = 0; v < NV; v++) p[v] = prims[v * g.nz + g.id(i, j, k)];
+        cons_at(g, p, i, j, u);
+        for (int v = 0; v < NV; v++) cons[v * g.nz + g.id(i, j, k)] = (double)u[v];
+      }
+}
+
+// Inversion at zone centres of the interior; returns the failure count and
+// writes a per-zone flag (0/1) when flags is not null.
+long orc_cons_to_prims(const orc_cfg* c, const double* cons, const double* guess, double* prims,
+                       int* flags) {
+  Grid g(*c);
+  long fails = 0;
+  for (int k = 0; k < c->n3; k++)
+    for (int j = 0; j < c->n2; j++)
+      for (int i = 0; i < c->n1; i++) {
+        real u[NV], gs[NV], p[NV];
+        long q = g.id(i, j, k);
+        for (int v = 0; v < NV; v++) { u[v] = cons[v * g.nz + q]; gs[v] = guess[v * g.nz + q]; }
+        int f = u_to_p(*c, g.gC[g.id2(i, j)], u, gs, p);
+        fails += f;
+        if (flags) flags[q] = f;
+        for (int v = 0; v < NV; v++) prims[v * g.nz + q] = (double)p[v];
+      }
+  return fails;
+}
+
+// ---- point functions (pins) ----
+
+void orc_geom(const orc_cfg* c, double x1, double x2, double* gcov, double* gcon, double* gdet,
+              double* alpha) {
+  Geom G;
+  geom_point(*c, x1, x2, G);
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) {
+      gcov[m * 4 + n] = (double)G.gcov[m][n];
+      gcon[m * 4 + n] = (double)G.gcon[m][n];
+    }
+  *gdet = (double)G.gdet;
+  *alpha = (double)G.alpha;
+}
+
+void orc_conn(const orc_cfg* c, double x1, double x2, double* conn) {
+  real cn[4][4][4];
+  conn_point(*c, x1, x2, cn);
+  for (int l = 0; l < 4; l++)
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) conn[l * 16 + m * 4 + n] = (double)cn[l][m][n];
+}
+
+// d = 0: conserved; d = 1..3: flux.  Also returns c+ and c- along d (d >= 1).
+void orc_point_flux(const orc_cfg* c, const double* prims, double x1, double x2, int d, double* out,
+                    double* cmax, double* cmin) {
+  Geom G;
+  geom_point(*c, x1, x2, G);
+  real p[NV], f[NV];
+  for (int v = 0; v < NV; v++) p[v] = prims[v];
+  FluidState S;
+  fluid_state(p, G, S);
+  prim_to_flux(p, S, G, c->gam, d, f);
+  for (int v = 0; v < NV; v++) out[v] = (double)f[v];
+  if (d >= 1) {
+    real cp, cm;
+    vchar(p, S, G, c->gam, d, cp, cm);
+    *cmax = (double)cp;
+    *cmin = (double)cm;
+  }
+}
+
+void orc_point_source(const orc_cfg* c, const double* prims, double x1, double x2, double* out) {
+  Geom G;
+  geom_point(*c, x1, x2, G);
+  real cn[4][4][4];
+  conn_point(*c, x1, x2, cn);
+  real flat[64];
+  for (int l = 0; l < 4; l++)
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) flat[l * 16 + m * 4 + n] = cn[l][m][n];
+  real p[NV], s[NV];
+  for (int v = 0; v < NV; v++) p[v] = prims[v];
+  source_point(G, flat, c->gam, p, s);
+  for (int v = 0; v < NV; v++) out[v] = (double)s[v];
+}
+
+int orc_point_u_to_p(const orc_cfg* c, const double* cons, const double* guess, double x1, double x2,
+                     double* prims) {
+  Geom G;
+  geom_point(*c, x1, x2, G);
+  real u[NV], gs[NV], p[NV];
+  for (int v = 0; v < NV; v++) { u[v] = cons[v]; gs[v] = guess[v]; }
+  int r = u_to_p(*c, G, u, gs, p);
+  for (int v = 0; v < NV; v++) prims[v] = (double)p[v];
+  return r;
+}
+
+double orc_weno5(double a, double b, double c, double d, double e, double eps) {
+  return (double)weno5(a, b, c, d, e, eps);
+}
+
+double orc_mc_slope(double l, double c, double r) { return (double)mc_slope(l, c, r); }
+
+}  // extern "C"

@@ -1,0 +1,453 @@
+"""Pins of the FP64 CPU oracle against what the physics and mathematics fix.
+
+None of these re-types an oracle formula: each compares it with an
+independent closed form, an invariant, a special case or a convergence rate.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import (GridSpec, linear_mode, interior, BC_PERIODIC,
+                       METRIC_MINKOWSKI, METRIC_KERR_MKS, RECON_MC, RECON_WENO5)
+from workloads.torus import fm_ell, torus_grid, fm_torus, _mks_metric
+
+A_SPIN, HSLOPE = 0.9375, 0.3
+
+
+def kerr_cfg(gam=13.0 / 9.0):
+    return oracle.cfg(torus_grid(8, 8, 1), gam=gam)
+
+
+def flat_cfg(gam=4.0 / 3.0):
+    return oracle.cfg(GridSpec(4, 4, 4), gam=gam)
+
+
+def random_points(rng, n, inside_horizon=True):
+    lo = math.log(1.05) if inside_horizon else math.log(1.5)
+    x1 = rng.uniform(lo, math.log(1000.0), n)
+    x2 = rng.uniform(0.02, 0.98, n)
+    return x1, x2
+
+
+# ------------------------------------------------------------------ geometry
+
+def test_metric_inverse_det_and_horizon():
+    """g_{mu nu} g^{nu l} = delta; sqrt(-g) equals sqrt(-det g); g^{rr} = 0 at r+."""
+    c = kerr_cfg()
+    rng = np.random.default_rng(0)
+    for x1, x2 in zip(*random_points(rng, 50)):
+        gcov, gcon, gdet, alpha = oracle.geom(c, x1, x2)
+        assert np.allclose(gcov @ gcon, np.eye(4), atol=1e-12, rtol=0)
+        assert gdet == pytest.approx(math.sqrt(-np.linalg.det(gcov)), rel=1e-12)
+        assert alpha ** 2 * -gcon[0, 0] == pytest.approx(1.0, rel=1e-14)
+    rplus = 1.0 + math.sqrt(1.0 - A_SPIN ** 2)
+    _, gcon, _, _ = oracle.geom(c, math.log(rplus), 0.3)
+    assert abs(gcon[1, 1]) < 1e-14
+
+
+def test_metric_matches_independent_initial_data_metric():
+    """Two separately written modified-KS metrics agree."""
+    c = kerr_cfg()
+    rng = np.random.default_rng(1)
+    x1, x2 = random_points(rng, 20)
+    g_w, gdet_w, _, _ = _mks_metric(x1, x2, A_SPIN, HSLOPE)
+    for q in range(20):
+        gcov, _, gdet, _ = oracle.geom(c, x1[q], x2[q])
+        assert np.allclose(gcov, g_w[:, :, q], rtol=1e-13, atol=1e-13)
+        assert gdet == pytest.approx(gdet_w[q], rel=1e-13)
+
+
+def _fd_connection(c, x1, x2, h=1e-4):
+    """Gamma from Richardson-extrapolated central differences of the metric."""
+    def dg(axis):
+        def cd(hh):
+            e = np.zeros(2)
+            e[axis] = hh
+            gp = oracle.geom(c, x1 + e[0], x2 + e[1])[0]
+            gm = oracle.geom(c, x1 - e[0], x2 - e[1])[0]
+            return (gp - gm) / (2 * hh)
+        return (4 * cd(h / 2) - cd(h)) / 3
+    d = np.zeros((4, 4, 4))
+    d[1], d[2] = dg(0), dg(1)
+    gcon = oracle.geom(c, x1, x2)[1]
+    G = np.zeros((4, 4, 4))
+    for l in range(4):
+        for m in range(4):
+            for n in range(4):
+                G[l, m, n] = 0.5 * sum(gcon[l, k] * (d[m, k, n] + d[n, k, m] - d[k, m, n])
+                                       for k in range(4))
+    return G
+
+
+def test_connection_against_finite_differences():
+    c = kerr_cfg()
+    rng = np.random.default_rng(2)
+    for x1, x2 in zip(*random_points(rng, 12)):
+        G = oracle.conn(c, x1, x2)
+        Gfd = _fd_connection(c, x1, x2)
+        scale = np.abs(G).max()
+        assert np.abs(G - Gfd).max() < 1e-8 * scale
+
+
+def test_connection_circular_geodesic():
+    """Circular equatorial orbits (Bardeen-Press-Teukolsky E, L) have
+    du^mu/dtau = -Gamma^mu_{ab} u^a u^b = 0 in stationary coordinates."""
+    c = kerr_cfg()
+    a = A_SPIN
+    for r in (3.0, 6.0, 12.0, 40.0):
+        sr = math.sqrt(r)
+        den = r ** 0.75 * math.sqrt(r ** 1.5 - 3 * sr + 2 * a)
+        E = (r ** 1.5 - 2 * sr + a) / den
+        L = (r * r - 2 * a * sr + a * a) / den
+        dl = r * r - 2 * r + a * a
+        A = (r * r + a * a) ** 2 - a * a * dl
+        gtt, gtp = -A / (r * r * dl), -2 * a * r / (r * r * dl)
+        gpp = (dl - a * a) / (r * r * dl)
+        ut = -gtt * E + gtp * L
+        up = -gtp * E + gpp * L
+        u = np.array([ut, 0.0, 0.0, up])       # u^r = 0 so BL -> KS -> MKS keeps it
+        G = oracle.conn(c, math.log(r), 0.5)
+        gcov = oracle.geom(c, math.log(r), 0.5)[0]
+        assert u @ gcov @ u == pytest.approx(-1.0, abs=1e-13)
+        acc = np.einsum("mab,a,b->m", G, u, u)
+        assert np.abs(acc).max() < 1e-13 * max(1.0, np.abs(G).max() * ut * ut)
+
+
+def test_minkowski_geometry_is_trivial():
+    c = flat_cfg()
+    gcov, gcon, gdet, alpha = oracle.geom(c, 0.3, 0.7)
+    assert np.array_equal(gcov, np.diag([-1.0, 1, 1, 1]))
+    assert gdet == 1.0 and alpha == 1.0
+    assert not oracle.conn(c, 0.3, 0.7).any()
+
+
+# ------------------------------------------------------- prims, fluxes, speeds
+
+def test_flat_conserved_and_fluxes_closed_form():
+    """Flat space: moving hydro and magnetised rest states in closed form."""
+    gam = 5.0 / 3.0
+    c = flat_cfg(gam)
+    rho, u, v = 0.7, 0.4, 0.6
+    g = 1 / math.sqrt(1 - v * v)
+    p = (gam - 1) * u
+    w = rho + u + p
+    P = np.array([rho, u, g * v, 0, 0, 0, 0, 0])
+    U = oracle.point_flux(c, P, 0.1, 0.1, 0)[0]
+    F1 = oracle.point_flux(c, P, 0.1, 0.1, 1)[0]
+    ref_U = [rho * g, -(w * g * g - p) + rho * g, w * g * g * v, 0, 0, 0, 0, 0]
+    ref_F = [rho * g * v, -w * g * g * v + rho * g * v, w * g * g * v * v + p, 0, 0, 0, 0, 0]
+    assert np.allclose(U, ref_U, rtol=1e-14, atol=1e-15)
+    assert np.allclose(F1, ref_F, rtol=1e-14, atol=1e-15)
+    B = np.array([0.3, -0.5, 0.2])
+    P = np.array([rho, u, 0, 0, 0, *B])
+    b2 = B @ B
+    U = oracle.point_flux(c, P, 0.1, 0.1, 0)[0]
+    assert np.allclose(U, [rho, -(u + 0.5 * b2), 0, 0, 0, *B], rtol=1e-14, atol=1e-15)
+    for d in (1, 2, 3):
+        F = oracle.point_flux(c, P, 0.1, 0.1, d)[0]
+        Tdi = [(p + 0.5 * b2 if i == d - 1 else 0.0) - B[d - 1] * B[i] for i in range(3)]
+        assert np.allclose(F, [0, 0, *Tdi, 0, 0, 0], rtol=1e-14, atol=1e-15)
+
+
+def test_signal_speeds_closed_forms():
+    """Rest: +-c_ms; boost along d: relativistic velocity addition; boost
+    transverse to d: c / sqrt(gamma^2 (1 - c^2) + c^2)."""
+    gam = 4.0 / 3.0
+    c = flat_cfg(gam)
+    # background of the fast-mode test: p = 1/3, w = 7/3, c_ms^2 = 13/30
+    P = np.array([1.0, 1.0, 0, 0, 0, 1.0, 0, 0])
+    for d in (1, 2, 3):
+        _, cp, cm = oracle.point_flux(c, P, 0.1, 0.1, d)
+        assert cp == pytest.approx(math.sqrt(13 / 30), rel=1e-15)
+        assert cm == pytest.approx(-math.sqrt(13 / 30), rel=1e-15)
+    rho, u = 1.0, 0.5
+    cs2 = gam * (gam - 1) * u / (rho + gam * u)
+    cs = math.sqrt(cs2)
+    v = 0.8
+    g = 1 / math.sqrt(1 - v * v)
+    P = np.array([rho, u, g * v, 0, 0, 0, 0, 0])
+    _, cp, cm = oracle.point_flux(c, P, 0.1, 0.1, 1)
+    assert cp == pytest.approx((v + cs) / (1 + v * cs), rel=1e-14)
+    assert cm == pytest.approx((v - cs) / (1 - v * cs), rel=1e-14)
+    _, cp, cm = oracle.point_flux(c, P, 0.1, 0.1, 2)
+    lam = cs / math.sqrt(g * g * (1 - cs2) + cs2)
+    assert cp == pytest.approx(lam, rel=1e-14)
+    assert cm == pytest.approx(-lam, rel=1e-14)
+
+
+def _random_prims(rng, n, c, x1, x2):
+    """Fuzzed prims: rho in [1e-6, 1], u/rho in [1e-3, 10], normal-frame
+    four-velocity up to ~5 and b^2/rho up to ~50, scaled per coordinate by
+    sqrt(g_ii) so that the physical values stay in those ranges."""
+    rho = 10 ** rng.uniform(-6, 0, n)
+    u = rho * 10 ** rng.uniform(-3, 1, n)
+    ut = rng.normal(size=(3, n)) * 10 ** rng.uniform(-2, 0.5, n)
+    sig = 10 ** rng.uniform(-3, 1.7, n)
+    B = rng.normal(size=(3, n))
+    B *= np.sqrt(sig * rho / (B * B).sum(0))
+    P = np.vstack([rho, u, ut, B]).T
+    for q in range(n):
+        gcov = oracle.geom(c, x1[q], x2[q])[0]
+        for i in range(3):
+            s = math.sqrt(gcov[1 + i, 1 + i])
+            P[q, 2 + i] /= s
+            P[q, 5 + i] /= s
+    return P
+
+
+@pytest.mark.parametrize("metric", ["flat", "kerr"])
+def test_prim_cons_round_trip(metric):
+    """P -> U -> P through the 1D_W inversion, from a 5% perturbed guess,
+    at random points (Kerr: also inside the horizon)."""
+    rng = np.random.default_rng(3)
+    c = flat_cfg(13 / 9) if metric == "flat" else kerr_cfg()
+    n = 400
+    x1, x2 = random_points(rng, n)
+    prims = _random_prims(rng, n, c, x1, x2)
+    worst = 0.0
+    for q in range(n):
+        P = prims[q]
+        U = oracle.point_flux(c, P, x1[q], x2[q], 0)[0]
+        guess = P * (1 + 0.05 * rng.uniform(-1, 1, 8))
+        out, fail = oracle.point_u_to_p(c, U, guess, x1[q], x2[q])
+        assert fail == 0
+        assert np.array_equal(out[5:], U[5:] / oracle.geom(c, x1[q], x2[q])[2])
+        rel = np.abs(out - P) / np.abs(P)
+        # velocity components are compared against the velocity magnitude
+        rel[2:5] = np.abs(out[2:5] - P[2:5]) / np.abs(P[2:5]).max()
+        worst = max(worst, rel[:5].max())
+    assert worst < 1e-8
+
+
+def test_inversion_failure_keeps_guess():
+    """An energy deficit with v^2 >= 1 cannot be inverted: flagged, guess kept."""
+    c = flat_cfg(4 / 3)
+    P = np.array([1.0, 1.0, 0.5, 0, 0, 0.1, 0, 0])
+    U = oracle.point_flux(c, P, 0.1, 0.1, 0)[0]
+    U[2] *= 50.0                    # momentum far beyond the available energy
+    guess = P.copy()
+    out, fail = oracle.point_u_to_p(c, U, guess, 0.1, 0.1)
+    assert fail == 1
+    assert np.array_equal(out[:5], guess[:5])
+    assert np.array_equal(out[5:], U[5:])
+
+
+# ---------------------------------------------------------- reconstruction
+
+def test_weno5_fifth_order_on_cell_averages():
+    """Applied to cell averages of a smooth function WENO5 reaches its design
+    order at the zone edge."""
+    f_int = lambda x: -np.cos(x) + 0.1 * x ** 3
+    f = lambda x: np.sin(x) + 0.3 * x * x
+    errs = []
+    for h in (0.1, 0.05, 0.025):
+        x0 = 0.4
+        centres = x0 + h * np.arange(-2, 3)
+        avg = (f_int(centres + h / 2) - f_int(centres - h / 2)) / h
+        w = oracle.weno5(*avg, 1e-40)
+        errs.append(abs(w - f(x0 + h / 2)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders.min() > 4.5
+
+
+def test_weno5_exact_for_linear_and_nonoscillatory():
+    a, b = 0.37, -1.9
+    vals = [a + b * s for s in range(5)]
+    assert oracle.weno5(*vals) == pytest.approx(a + b * 2.5, rel=1e-14)
+    # a jump between the 3rd and 4th points: the edge value stays within [c, d]
+    w = oracle.weno5(1.0, 1.0, 1.0, 0.0, 0.0)
+    assert 0.0 <= w <= 1.0 and abs(w - 1.0) < 1e-6
+    # mirror symmetry: reversed data give the value at the other edge
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        q = rng.normal(size=5)
+        assert oracle.weno5(*q) == pytest.approx(-oracle.weno5(*(-q)), rel=1e-14)
+
+
+def test_mc_limiter_cases():
+    # van Leer's monotonised-central slope: minmod(2 dl, 2 dr, dc/2)
+    assert oracle.mc_slope(0.0, 1.0, 2.0) == 1.0
+    assert oracle.mc_slope(0.0, 1.0, 5.0) == 2.0
+    assert oracle.mc_slope(0.0, 4.0, 5.0) == 2.0
+    assert oracle.mc_slope(0.0, 1.0, 1.0) == 0.0
+    assert oracle.mc_slope(1.0, 2.0, 0.0) == 0.0
+    assert oracle.mc_slope(5.0, 4.0, 0.0) == -2.0
+    assert oracle.mc_slope(0.0, 2.0, 3.0) == 1.5
+    assert oracle.mc_slope(3.0, 1.0, 0.0) == -1.5
+
+
+# ------------------------------------------------------------- whole step
+
+def test_uniform_state_is_preserved():
+    """Constant prims in flat space: flux differences vanish identically."""
+    g = GridSpec(8, 8, 8)
+    c = oracle.cfg(g, gam=5 / 3, recon=RECON_WENO5)
+    P = np.zeros((8, 14, 14, 14))
+    P[:] = np.array([0.8, 0.3, 0.2, -0.1, 0.3, 0.4, 0.1, -0.2])[:, None, None, None]
+    out, fails, _ = oracle.run(c, P, 0.01, 3)
+    assert fails == 0
+    assert np.abs(interior(out) - interior(P)).max() < 1e-14
+
+
+def _random_smooth_state(g, rng, amp=0.05):
+    x1, x2, x3 = g.centers()
+    X3, X2, X1 = np.meshgrid(x3, x2, x1, indexing="ij")
+    P = np.zeros((8,) + X1.shape)
+    base = [1.0, 0.8, 0.0, 0.0, 0.0, 0.5, 0.3, -0.2]
+    for v in range(5):
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        P[v] = base[v] + amp * np.sin(2 * np.pi * X1 + ph[0]) * np.cos(2 * np.pi * X2 + ph[1]) \
+            * np.cos(2 * np.pi * X3 + ph[2])
+    # divergence-free field at corners: B = B0 + curl A with A built per zone
+    # is not needed here; constant B plus a field varying only transversely
+    P[5] = base[5] + amp * np.sin(2 * np.pi * (X2 + X3))
+    P[6] = base[6] + amp * np.sin(2 * np.pi * (X1 + X3))
+    P[7] = base[7] + amp * np.sin(2 * np.pi * (X1 + X2))
+    return P
+
+
+def test_conservation_on_periodic_grid():
+    g = GridSpec(12, 12, 12)
+    c = oracle.cfg(g, gam=4 / 3, recon=RECON_WENO5)
+    rng = np.random.default_rng(5)
+    P = _random_smooth_state(g, rng)
+    U0 = interior(oracle.prims_to_cons(c, P)).sum(axis=(1, 2, 3))
+    out, fails, _ = oracle.run(c, P, -1, 3)
+    assert fails == 0
+    U1 = interior(oracle.prims_to_cons(c, out)).sum(axis=(1, 2, 3))
+    scale = np.abs(interior(oracle.prims_to_cons(c, P))).sum(axis=(1, 2, 3)).max()
+    assert np.abs(U1 - U0).max() < 1e-14 * scale
+
+
+def test_flux_ct_keeps_corner_divergence():
+    """An initial field with zero corner divergence keeps it to roundoff."""
+    g = GridSpec(12, 12, 12)
+    c = oracle.cfg(g, gam=4 / 3, recon=RECON_MC)
+    rng = np.random.default_rng(6)
+    P = _random_smooth_state(g, rng, amp=0.1)
+    mx0, _ = oracle.divb(c, P)
+    assert mx0 < 1e-13
+    out, fails, _ = oracle.run(c, P, -1, 4)
+    assert fails == 0
+    mx1, mean1 = oracle.divb(c, out)
+    scale = np.abs(interior(out[5:8])).max() / g.dx[0]
+    assert mx1 < 1e-14 * scale
+
+
+def test_flux_ct_divergence_on_torus():
+    g, P, _ = fm_torus(16, 16, 4)
+    c = oracle.cfg(g, gam=13 / 9, recon=RECON_MC)
+    mx0, _ = oracle.divb(c, P)
+    out, fails, _ = oracle.run(c, P, -1, 2)
+    mx1, _ = oracle.divb(c, out)
+    scale = np.abs(interior(P[5:7])).max() / g.dx[0]
+    assert mx0 < 1e-13 * scale
+    assert mx1 < 1e-13 * scale
+
+
+def test_permutation_symmetry():
+    """The same wave in the x1-x2 plane and in the x2-x3 plane."""
+    rng = np.random.default_rng(7)
+    n = 12
+    gA = GridSpec(n, n, 1)
+    gB = GridSpec(1, n, n)
+    cA = oracle.cfg(gA, recon=RECON_WENO5)
+    cB = oracle.cfg(gB, recon=RECON_WENO5)
+    PA = _random_smooth_state(gA, rng, amp=0.05)
+    # rotate (x1, x2, x3) -> (x2, x3, x1): variable order and axes
+    PB = np.empty((8, n + 6, n + 6, 7))
+    for v_src, v_dst in ((0, 0), (1, 1), (2, 3), (3, 4), (4, 2), (5, 6), (6, 7), (7, 5)):
+        # A[k=0..6 (x3), j (x2), i (x1)] -> B[k (x3) = A's x2, j (x2) = A's x1, i (x1) = A's x3]
+        PB[v_dst] = np.transpose(PA[v_src], (1, 2, 0))
+    outA, _, _ = oracle.run(cA, PA, 0.01, 2)
+    outB, _, _ = oracle.run(cB, PB, 0.01, 2)
+    for v_src, v_dst in ((0, 0), (1, 1), (2, 3), (3, 4), (4, 2), (5, 6), (6, 7), (7, 5)):
+        a = interior(outA[v_src])
+        b = np.transpose(interior(outB[v_dst]), (2, 0, 1))
+        assert np.abs(a - b).max() < 1e-13
+
+
+def test_torus_axisymmetry_bitwise_and_equatorial_mirror():
+    g, P, _ = fm_torus(48, 48, 4, noise=0.0, magnetised=False)
+    c = oracle.cfg(g, gam=13 / 9, recon=RECON_WENO5)
+    out, fails, _, flags = oracle.run(c, P, -1, 2, flags=True)
+    # without floors a few atmosphere zones at the torus edge cannot be
+    # inverted (they keep their stage-input prims); never the torus body
+    assert fails < 0.1 * g.nzones
+    assert not (interior(flags) & (interior(P[0]) > 0.05)).any()
+    I = interior(out)
+    for k in range(1, 4):
+        assert np.array_equal(I[:, k], I[:, 0])
+    # theta -> pi - theta is x2 -> 1 - x2: mirror j, flip u~2
+    M = I[:, :, ::-1, :].copy()
+    M[3] *= -1
+    scale = np.abs(I).max(axis=(1, 2, 3))[:, None, None, None] + 1e-300
+    assert (np.abs(M - I) / scale)[:5].max() < 1e-11
+
+
+def test_ghost_fill_polar_and_outflow():
+    g = torus_grid(6, 6, 2)
+    c = oracle.cfg(g)
+    rng = np.random.default_rng(8)
+    P = rng.normal(size=(8, 8, 12, 12))
+    out = oracle.fill_ghosts(c, P)
+    # x2 mirror at the lower pole with u~2 and B2 flipped
+    for v in range(8):
+        s = -1 if v in (3, 6) else 1
+        assert np.array_equal(out[v, 3:5, 2, 3:9], s * out[v, 3:5, 3, 3:9])
+        assert np.array_equal(out[v, 3:5, 0, 3:9], s * out[v, 3:5, 5, 3:9])
+        assert np.array_equal(out[v, 3:5, 9, 3:9], s * out[v, 3:5, 8, 3:9])
+    # x1 outflow copies the edge zone, x3 periodic wraps
+    assert np.array_equal(out[:, 3:5, 3:9, 0], out[:, 3:5, 3:9, 3])
+    assert np.array_equal(out[:, 3:5, 3:9, 11], out[:, 3:5, 3:9, 8])
+    assert np.array_equal(out[:, 2], out[:, 4])
+    assert np.array_equal(out[:, 5], out[:, 3])
+
+
+# ---------------------------------------------------- convergence (the paper's
+# regression criterion: L1 error slope between -1.9 and -2.1)
+
+def _mode_errors(name, recon, ns, ndim=2):
+    errs = []
+    for n in ns:
+        g, P, exact, info = linear_mode(name, n, ndim=ndim)
+        c = oracle.cfg(g, recon=recon)
+        T = 2 * np.pi / info["omega"] if info["omega"] > 0 else 1.0
+        dt = oracle.estimate_dt(c, P)
+        ns_ = int(np.ceil(T / dt))
+        out, fails, _ = oracle.run(c, P, T / ns_, ns_)
+        assert fails == 0
+        Pe = exact(T)
+        r = info["r"]
+        errs.append([np.mean(np.abs(interior(out[v] - Pe[v]))) for v in range(8) if abs(r[v]) > 0])
+    return np.array(errs)
+
+
+@pytest.mark.parametrize("name", ["fast", "alfven", "slow"])
+def test_linear_mode_convergence_weno5(name):
+    e = _mode_errors(name, RECON_WENO5, (32, 64))
+    slope = np.log2(e[0] / e[1])
+    assert np.all((slope > 1.9) & (slope < 2.1)), slope
+
+
+def test_linear_mode_convergence_mc_fast():
+    e = _mode_errors("fast", RECON_MC, (64, 128))
+    slope = np.log2(e[0] / e[1])
+    assert np.all((slope > 1.9) & (slope < 2.1)), slope
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", ["alfven", "slow"])
+def test_linear_mode_convergence_mc(name):
+    e = _mode_errors(name, RECON_MC, (64, 128))
+    slope = np.log2(e[0] / e[1])
+    assert np.all((slope > 1.9) & (slope < 2.1)), slope
+
+
+def test_entropy_mode_at_least_second_order():
+    for recon in (RECON_MC, RECON_WENO5):
+        e = _mode_errors("entropy", recon, (16, 32))
+        assert np.all(np.log2(e[0] / e[1]) > 1.9)

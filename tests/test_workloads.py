@@ -1,0 +1,74 @@
+"""Pins of the seeded initial data against closed forms."""
+
+import math
+
+import numpy as np
+import pytest
+
+from workloads import linear_mode, fm_torus, torus_pack, interior, NG
+from workloads.linear_modes import select_mode
+from workloads.torus import fm_ell, fm_lnh, _mks_metric, _bsq
+
+
+def test_mode_speeds_match_rest_frame_dispersion_relation():
+    """Phase speeds are the roots of
+    v^4 - [vA^2 + cs^2 (1 - vA^2 cos^2) ... ] v^2 + cs^2 vA^2 cos^2 = 0."""
+    gam, rho, u = 4 / 3, 1.0, 1.0
+    p = (gam - 1) * u
+    w = rho + u + p
+    cs2 = gam * p / w
+    va2 = 1.0 / (1.0 + w)              # |B| = 1
+    cos2 = 0.5                         # k along (1,1,0), B along x
+    b = va2 + cs2 * (1 - va2) + cs2 * va2 * cos2
+    c = cs2 * va2 * cos2
+    fast = math.sqrt((b + math.sqrt(b * b - 4 * c)) / 2)
+    slow = math.sqrt((b - math.sqrt(b * b - 4 * c)) / 2)
+    assert select_mode("fast")[0] == pytest.approx(fast, rel=1e-13)
+    assert select_mode("slow")[0] == pytest.approx(slow, rel=1e-13)
+    assert select_mode("alfven")[0] == pytest.approx(math.sqrt(va2 * cos2), rel=1e-13)
+
+
+def test_mode_perturbations_are_divergence_free_and_normalised():
+    for name in ("fast", "slow", "alfven"):
+        s, r = select_mode(name)
+        assert np.linalg.norm(r) == pytest.approx(1.0)
+        assert abs(r[5] + r[6]) < 1e-14          # k . dB = 0 for k = (1, 1, 0)
+
+
+def test_fm_torus_constants():
+    a, rmax, rin = 0.9375, 12.0, 6.0
+    ell = fm_ell(a, rmax)
+    assert ell == pytest.approx(4.281284468531897, rel=1e-14)
+    r = np.linspace(rin, 40.0, 340001)
+    lnh = fm_lnh(r, np.full_like(r, np.pi / 2), a, ell, rin)
+    assert abs(lnh[0]) < 1e-14
+    assert r[np.argmax(lnh)] == pytest.approx(rmax, abs=2e-4)
+
+
+def test_fm_torus_state():
+    n = 32
+    g, P, info = fm_torus(n, n, 4)
+    assert np.isfinite(P).all()
+    I = interior(P)
+    assert I[0].max() == pytest.approx(1.0, rel=0.05)        # perturbation is on u only
+    x1, x2, _ = g.centers()
+    X2, X1 = np.meshgrid(x2, x1, indexing="ij")
+    gcov, gdet, gtt, gt1 = _mks_metric(X1, X2, g.a, g.hslope)
+    # minimum plasma beta over magnetised zones equals 100
+    gc = np.broadcast_to(gcov[:, :, None], (4, 4) + P.shape[1:])
+    bsq = _bsq(P, gc, gtt[None], gt1[None])
+    bi = interior(bsq)
+    m = bi > 0
+    beta = 2 * (13 / 9 - 1) * interior(P[1])[m] / bi[m]
+    assert beta.min() == pytest.approx(100.0, rel=1e-12)
+
+
+def test_pack_is_seeded_and_uses_global_data():
+    g, blocks, _ = torus_pack(nblocks=12, n_global=32, sizes=(8, 16), probs=(0.5, 0.5), seed=3)
+    g2, blocks2, _ = torus_pack(nblocks=12, n_global=32, sizes=(8, 16), probs=(0.5, 0.5), seed=3)
+    _, P, _ = fm_torus(32, 32, 32)
+    for b, b2 in zip(blocks, blocks2):
+        assert b["offset"] == b2["offset"] and np.array_equal(b["prims"], b2["prims"])
+        i0, j0, k0 = b["offset"]
+        n = b["n"]
+        assert np.array_equal(b["prims"], P[:, k0:k0 + n + 2 * NG, j0:j0 + n + 2 * NG, i0:i0 + n + 2 * NG])

@@ -1,0 +1,36 @@
+"""Uneven packs of torus meshblocks with frozen ghosts.
+
+Each block is a seeded sub-box [i0, i0+n) x [j0, j0+n) x [k0, k0+n) of the
+n_global^3 torus grid, n drawn from `sizes` with probabilities `probs`, the
+offsets uniform in [0, n_global - n].  Its ghost zones hold the global
+initial data (frozen, Dirichlet), so every block is an independent domain
+whose coordinates are the matching sub-range of the global grid.
+"""
+
+import numpy as np
+
+from .spec import GridSpec, NG, BC_FROZEN
+from .torus import fm_torus
+
+
+def torus_pack(nblocks=320, n_global=128, sizes=(16, 32, 64),
+               probs=(0.6, 0.3, 0.1), seed=7, torus_seed=1, gamma=13.0 / 9.0):
+    g, P, info = fm_torus(n_global, n_global, n_global, seed=torus_seed,
+                          gamma=gamma)
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(sizes), size=nblocks, p=np.asarray(probs))
+    d1, d2, d3 = g.dx
+    blocks = []
+    for n in ns:
+        n = int(n)
+        i0, j0, k0 = (int(v) for v in rng.integers(0, n_global - n + 1, size=3))
+        sub = np.ascontiguousarray(
+            P[:, k0:k0 + n + 2 * NG, j0:j0 + n + 2 * NG, i0:i0 + n + 2 * NG])
+        bg = GridSpec(n, n, n,
+                      x1min=g.x1min + i0 * d1, x1max=g.x1min + (i0 + n) * d1,
+                      x2min=g.x2min + j0 * d2, x2max=g.x2min + (j0 + n) * d2,
+                      x3min=g.x3min + k0 * d3, x3max=g.x3min + (k0 + n) * d3,
+                      bc=(BC_FROZEN,) * 6, metric=g.metric, a=g.a,
+                      hslope=g.hslope)
+        blocks.append(dict(n=n, offset=(i0, j0, k0), grid=bg, prims=sub))
+    return g, blocks, info
