@@ -1,0 +1,149 @@
+/* grmhd.h -- C ABI of the MI355X (gfx950) HARM ideal-GRMHD step.
+ *
+ * One call advances every zone of a logically Cartesian grid by one
+ * two-stage SSP Runge-Kutta step of the HARM scheme (Algorithm section of the
+ * KHARMA paper): linear-MC or WENO5 reconstruction, local Lax-Friedrichs
+ * fluxes of the ideal stress-energy tensor (EGRMHD section, ideal part),
+ * Flux-CT magnetic-field transport, geometric source terms from cached
+ * metric and connection (Core section, GRCoordinates), and the 1D_W
+ * conserved->primitive inversion named in the Algorithm and Performance
+ * sections.  Metrics: flat Minkowski (Cartesian) or Kerr (M = 1) in modified
+ * Kerr-Schild coordinates r = exp(x1), theta = pi x2 + (1-h)/2 sin(2 pi x2),
+ * phi = x3.
+ *
+ * Conventions
+ *   - State ("prims"): float64 array [8][n3+6][n2+6][n1+6], x1 fastest,
+ *     variables (rho, u, u~1, u~2, u~3, B1, B2, B3); u~ is the velocity
+ *     relative to the normal observer, B^i = *F^{it}.  Three ghost layers
+ *     per side.  The flux array of debug calls is [3][8][same].
+ *   - Every pointer marked "device" is device memory the caller owns (in
+ *     practice torch tensors).  The library never allocates device memory:
+ *     all scratch lives in the caller's workspace of grmhd_workspace_bytes()
+ *     bytes, borrowed for the context's lifetime.
+ *   - All work is enqueued on the hipStream_t given at creation, in order.
+ *     Calls that return host values (estimate_dt, divb, get_status,
+ *     cons_to_prims' count) synchronise that stream; the rest are
+ *     asynchronous.
+ *   - Every function returns 0 (GRMHD_OK) or a negative GRMHD_E_* code and
+ *     never throws; grmhd_strerror() names the code.  A context is not
+ *     thread-safe.
+ *   - A zone whose inversion fails is not an error: it keeps its stage-input
+ *     hydro prims (B always follows the conserved field) and is counted.
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { GRMHD_OK = 0, GRMHD_E_ARG = -1, GRMHD_E_HIP = -2, GRMHD_E_STATE = -3,
+       GRMHD_E_NOMEM = -4 };
+enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KERR_MKS = 1 };
+enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1 };
+enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
+enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2,
+       GRMHD_BC_FROZEN = 3 };
+
+typedef struct grmhd_ctx grmhd_ctx;
+
+/* Interior zone counts and coordinate extents; bc order x1-,x1+,x2-,x2+,x3-,x3+.
+ * ng must be 3.  Periodic axes need n >= 1, polar axes n >= 3.  In modified
+ * KS an x2 boundary at exactly 0 or 1 is the polar axis: its faces carry no
+ * flux and its edges no EMF, whatever the ghost treatment. */
+typedef struct {
+  int n1, n2, n3, ng;
+  double x1min, x1max, x2min, x2max, x3min, x3max;
+  int bc[6];
+} grmhd_grid;
+
+typedef struct {
+  int metric;     /* GRMHD_METRIC_* */
+  double a;       /* black-hole spin (Kerr only) */
+  double hslope;  /* theta squeeze h of modified KS */
+} grmhd_metric;
+
+typedef struct {
+  double gamma_ad;    /* adiabatic index, p = (gamma_ad - 1) u */
+  double cfl;         /* Courant number of grmhd_estimate_dt */
+  double weno_eps;    /* WENO5 smoothness regulariser */
+  double newton_tol;  /* relative |dW/W| stopping tolerance of 1D_W */
+  int newton_maxit;   /* Newton iteration cap (one more step follows convergence) */
+  int recon;          /* GRMHD_RECON_* */
+  int precision;      /* GRMHD_PREC_*: MIXED = FP32 reconstruction, fluxes, EMFs */
+  int floors;         /* must be 0 (no floors on this path) */
+} grmhd_params;
+
+/* Bytes of device workspace a context with this grid and parameters needs. */
+size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params);
+
+/* Create a context over caller-owned device workspace (>= grmhd_workspace_bytes,
+ * 256-byte aligned) and a hipStream_t (NULL = default stream).  Computes the
+ * geometry tables on the device (metric and connection at zone centres,
+ * faces and corners of every (x1, x2) column).  E_ARG on bad sizes or enums. */
+int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* metric,
+                 const grmhd_params* params, void* d_workspace, size_t ws_bytes,
+                 void* hip_stream);
+
+/* Copy padded prims (device, layout above) into the context's state. */
+int grmhd_load_prims(grmhd_ctx* ctx, const double* d_prims);
+
+/* One SSPRK2 step of size dt: U1 = Un + dt L(Pn), P1 = U_to_P(U1; Pn);
+ * Un+1 = (Un + U1)/2 + dt L(P1)/2, Pn+1 = U_to_P(Un+1; P1).  Ghosts are
+ * refilled before each stage.  Asynchronous. */
+int grmhd_step(grmhd_ctx* ctx, double dt);
+
+/* CFL step: cfl / max over interior zones of sum_d max|c+-_d| / dx_d (axes
+ * with more than one zone), from the current prims.  Synchronises. */
+int grmhd_estimate_dt(grmhd_ctx* ctx, double* dt_out);
+
+/* Copy the current padded prims (ghosts filled) to device memory d_out. */
+int grmhd_get_prims(grmhd_ctx* ctx, double* d_out);
+
+/* Corner-centred div B of the current state, |div| / sqrt(-g) at interior
+ * corners (corners on non-periodic boundaries excluded): max and mean to the
+ * host; the per-corner field to d_divb (device, padded scalar layout) unless
+ * it is NULL.  Synchronises. */
+int grmhd_divb(grmhd_ctx* ctx, double* d_divb_or_null, double* max_out, double* mean_out);
+
+/* Inversion failures accumulated since creation (or the last reset), and
+ * floor activations (always 0).  Synchronises. */
+int grmhd_get_status(grmhd_ctx* ctx, long long* n_inv_fail, long long* n_floor);
+int grmhd_reset_status(grmhd_ctx* ctx);
+
+/* Conserved variables at interior zone centres of d_prims into d_cons (both
+ * device, padded layout; ghosts of d_cons untouched). */
+int grmhd_prims_to_cons(grmhd_ctx* ctx, const double* d_prims, double* d_cons);
+
+/* 1D_W inversion at interior zones: d_cons, d_guess -> d_prims, per-zone
+ * failure flags (device int32, padded scalar layout, may be NULL); the
+ * failure count to *n_fail.  Synchronises. */
+int grmhd_cons_to_prims(grmhd_ctx* ctx, const double* d_cons, const double* d_guess,
+                        double* d_prims, int* d_flags, long long* n_fail);
+
+/* Face fluxes of one stage evaluated from d_prims (ghosts filled from it),
+ * with Flux-CT applied to the B components of interior faces.  d_flux is
+ * [3][8][padded] float64 (device).  For testing and inspection. */
+int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
+
+/* Per-kernel-class timing with HIP events recorded on the context's stream
+ * around every launch while enabled (enabling clears earlier records).
+ * Classes: 0 ghost fill, 1-3 fluxes along x1..x3, 4 EMFs, 5 stage-1 update,
+ * 6 stage-2 update, 7 dt reduction.  The report sums elapsed milliseconds and
+ * counts launches per class into arrays of nclass >= 8 entries.  Both
+ * synchronise the stream.  For measurement; the step itself is unchanged. */
+int grmhd_timing(grmhd_ctx* ctx, int enable);
+int grmhd_timing_report(grmhd_ctx* ctx, double* total_ms, long long* launches, int nclass);
+
+const char* grmhd_strerror(int code);
+
+/* Release the host side of the context; the workspace stays the caller's. */
+int grmhd_destroy(grmhd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRMHD_H */

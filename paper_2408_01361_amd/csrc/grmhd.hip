@@ -1,0 +1,1072 @@
+// HIP kernels (gfx950) and the C ABI of the HARM ideal-GRMHD step.
+//
+// Per stage the step runs, on one stream:
+//   bc      ghost zones from the stage's prims (index remap per axis)
+//   flux d  per face along d: reconstruct 8 prims left/right, evaluate the
+//           face state, flux, conserved variables and characteristic speeds
+//           for both sides, and form the local Lax-Friedrichs flux (the paper
+//           keeps speeds, P->U and the Riemann solve in one kernel, Solvers
+//           section) -- d = 1, 2, 3
+//   emf     Flux-CT edge EMFs from the transverse B fluxes
+//   update  per zone: flux divergence (B fluxes rebuilt from edge EMFs),
+//           geometric source, SSPRK2 combination and the 1D_W inversion
+// with every intermediate resident in the caller's HBM workspace.  Layouts
+// are variable-major and x1-fastest, so each wavefront's loads and stores of
+// one variable are contiguous.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <new>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "../../include/grmhd.h"
+#include "geometry.hpp"
+#include "physics.hpp"
+
+using namespace grmhd;
+
+namespace {
+
+constexpr int NG = 3;
+constexpr int BLOCK = 256;
+constexpr int MAX_PARTIALS = 65536;
+
+// Everything a kernel needs to know about the grid, passed by value.
+struct Dev {
+  int n1, n2, n3;
+  int s1, s2, s3;     // padded extents
+  long nz;            // padded zones per variable
+  long plane;         // s1 * s2
+  double dx1, dx2, dx3;
+  double x1min, x2min;
+  int bc[6];
+  int pole_lo, pole_hi;
+  double gam, weno_eps, tol;
+  int maxit;
+  SpaceTime st;
+};
+
+__device__ __forceinline__ long zid(const Dev& g, int i, int j, int k) {
+  return ((long)(k + NG) * g.s2 + (j + NG)) * g.s1 + (i + NG);
+}
+__device__ __forceinline__ long pid(const Dev& g, int i, int j) {
+  return (long)(j + NG) * g.s1 + (i + NG);
+}
+
+// Box of (i, j, k), inclusive bounds, enumerated x1-fastest by a 1-D grid.
+struct Box {
+  int lo1, lo2, lo3, n1, n2, n3;
+  long count() const { return (long)n1 * n2 * n3; }
+};
+__device__ __forceinline__ bool box_index(const Box& b, long t, int& i, int& j, int& k) {
+  if (t >= (long)b.n1 * b.n2 * b.n3) return false;
+  int n12 = b.n1 * b.n2;
+  int kk = (int)(t / n12);
+  int r = (int)(t - (long)kk * n12);
+  int jj = r / b.n1;
+  i = b.lo1 + (r - jj * b.n1);
+  j = b.lo2 + jj;
+  k = b.lo3 + kk;
+  return true;
+}
+
+inline Box make_box(int lo1, int hi1, int lo2, int hi2, int lo3, int hi3) {
+  return Box{lo1, lo2, lo3, hi1 - lo1 + 1, hi2 - lo2 + 1, hi3 - lo3 + 1};
+}
+
+inline unsigned blocks_for(long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+// ------------------------------------------------------------- geometry --
+
+// Tables over the padded (x1, x2) plane: metric at zone centres, x1 faces,
+// x2 faces; sqrt(-g) at (x1, x2) corners; connection at centres.  x3 faces
+// share the centre values (nothing depends on x3).  Pole faces and corners
+// are left zero: nothing reads them.
+__global__ void k_geometry(Dev g, double* tabC, double* tabF1, double* tabF2, double* corner,
+                           double* conn) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= g.plane) return;
+  int i = (int)(t % g.s1) - NG, j = (int)(t / g.s1) - NG;
+  double xc1 = g.x1min + (i + 0.5) * g.dx1, xc2 = g.x2min + (j + 0.5) * g.dx2;
+  double xf1 = g.x1min + i * g.dx1, xf2 = g.x2min + j * g.dx2;
+  bool pole = (g.pole_lo && j == 0) || (g.pole_hi && j == g.n2);
+  double gcov[10], gcon[10], gdet, alpha;
+  auto put = [&](double* tab) {
+    for (int f = 0; f < 10; f++) {
+      tab[(G_COV + f) * g.plane + t] = gcov[f];
+      tab[(G_CON + f) * g.plane + t] = gcon[f];
+    }
+    tab[G_DET * g.plane + t] = gdet;
+    tab[G_ALPHA * g.plane + t] = alpha;
+  };
+  metric_point(g.st, xc1, xc2, gcov, gcon, gdet, alpha);
+  put(tabC);
+  metric_point(g.st, xf1, xc2, gcov, gcon, gdet, alpha);
+  put(tabF1);
+  if (!pole) {
+    metric_point(g.st, xc1, xf2, gcov, gcon, gdet, alpha);
+    put(tabF2);
+    metric_point(g.st, xf1, xf2, gcov, gcon, gdet, alpha);
+    corner[t] = gdet;
+  } else {
+    for (int f = 0; f < G_NF; f++) tabF2[f * g.plane + t] = 0.0;
+    corner[t] = 0.0;
+  }
+  double cn[40];
+  connection_point(g.st, xc1, xc2, cn);
+  for (int q = 0; q < 40; q++) conn[q * g.plane + t] = cn[q];
+}
+
+// ------------------------------------------------------------ boundaries --
+
+// Source index along one axis of a ghost coordinate, or the coordinate itself
+// when the axis is interior there or frozen.  Sets flip for a polar mirror.
+__device__ __forceinline__ int bc_map(int x, int n, int bclo, int bchi, bool& flip) {
+  if (x < 0) {
+    if (bclo == GRMHD_BC_PERIODIC) return ((x % n) + n) % n;
+    if (bclo == GRMHD_BC_OUTFLOW) return 0;
+    if (bclo == GRMHD_BC_POLAR) { flip = true; return -x - 1; }
+    return x;
+  }
+  if (x >= n) {
+    if (bchi == GRMHD_BC_PERIODIC) return x % n;
+    if (bchi == GRMHD_BC_OUTFLOW) return n - 1;
+    if (bchi == GRMHD_BC_POLAR) { flip = true; return 2 * n - 1 - x; }
+    return x;
+  }
+  return x;
+}
+
+// One thread per padded zone; ghost zones of non-frozen axes copy from the
+// zone their per-axis maps point to (always interior along those axes, so
+// nothing read here is written here).  Polar mirrors flip u~2 and B2.
+__global__ void k_bc(Dev g, double* P) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= g.nz) return;
+  int i = (int)(t % g.s1) - NG;
+  long r = t / g.s1;
+  int j = (int)(r % g.s2) - NG, k = (int)(r / g.s2) - NG;
+  bool gi = i < 0 || i >= g.n1, gj = j < 0 || j >= g.n2, gk = k < 0 || k >= g.n3;
+  if (!(gi || gj || gk)) return;
+  bool f1 = false, f2 = false, f3 = false;
+  int si = bc_map(i, g.n1, g.bc[0], g.bc[1], f1);
+  int sj = bc_map(j, g.n2, g.bc[2], g.bc[3], f2);
+  int sk = bc_map(k, g.n3, g.bc[4], g.bc[5], f3);
+  if (si == i && sj == j && sk == k) return;  // frozen
+  long src = zid(g, si, sj, sk);
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    double x = P[v * g.nz + src];
+    if (f2 && (v == U2 || v == B2)) x = -x;
+    P[v * g.nz + t] = x;
+  }
+}
+
+// ----------------------------------------------------------------- fluxes --
+
+template <int RECON, typename R>
+__device__ __forceinline__ void recon_pair(const double* __restrict__ P, long nz, long c, long s,
+                                           R eps, R qL[NVAR], R qR[NVAR]) {
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    const double* q = P + v * nz + c;
+    if (RECON == GRMHD_RECON_MC) {
+      R m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s];
+      qL[v] = m1 + (R)0.5 * mc_slope(m2, m1, p0);
+      qR[v] = p0 - (R)0.5 * mc_slope(m1, p0, p1);
+    } else {
+      R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
+        p2 = (R)q[2 * s];
+      qL[v] = weno5(m3, m2, m1, p0, p1, eps);
+      qR[v] = weno5(p2, p1, p0, m1, m2, eps);
+    }
+  }
+}
+
+// Local Lax-Friedrichs flux through the lower d-face of zone (i, j, k) for
+// every face of `box`; pole faces get zero flux.  FT is the stored type.
+template <int D, int RECON, typename R, typename FT>
+__global__ void __launch_bounds__(BLOCK) k_flux(Dev g, Box box, const double* __restrict__ P,
+                                                const double* __restrict__ tab, FT* __restrict__ F) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  long c = zid(g, i, j, k);
+  if (D == 2 && ((g.pole_lo && j == 0) || (g.pole_hi && j == g.n2))) {
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) F[v * g.nz + c] = (FT)0;
+    return;
+  }
+  const long s = D == 1 ? 1 : (D == 2 ? (long)g.s1 : g.plane);
+  R qL[NVAR], qR[NVAR];
+  recon_pair<RECON, R>(P, g.nz, c, s, (R)g.weno_eps, qL, qR);
+  PointMetric<R> m;
+  load_metric<R>(tab, g.plane, pid(g, i, j), m);
+  const R gam = (R)g.gam;
+  R FL[NVAR], UL[NVAR], cpl, cml;
+  {
+    Fluid<R> f;
+    fluid_state(qL, m, f);
+    prim_to_flux(qL, f, m, gam, D, FL);
+    prim_to_flux(qL, f, m, gam, 0, UL);
+    char_speeds(qL, f, m, gam, D, cpl, cml);
+  }
+  R FR[NVAR], UR[NVAR], cpr, cmr;
+  {
+    Fluid<R> f;
+    fluid_state(qR, m, f);
+    prim_to_flux(qR, f, m, gam, D, FR);
+    prim_to_flux(qR, f, m, gam, 0, UR);
+    char_speeds(qR, f, m, gam, D, cpr, cmr);
+  }
+  R cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
+  cmax = fmax(cmax, (R)0);
+#pragma unroll
+  for (int v = 0; v < NVAR; v++)
+    F[v * g.nz + c] = (FT)((R)0.5 * (FL[v] + FR[v]) - (R)0.5 * cmax * (UR[v] - UL[v]));
+}
+
+// Flux-CT edge EMFs at the lower (x1, x2, x3) corner of zone (i, j, k):
+//   E3 = [F1(B2) + F1(B2)_{j-1} - F2(B1) - F2(B1)_{i-1}]/4
+//   E2 = [F3(B1) + F3(B1)_{i-1} - F1(B3) - F1(B3)_{k-1}]/4
+//   E1 = [F2(B3) + F2(B3)_{k-1} - F3(B2) - F3(B2)_{j-1}]/4
+// E1 and E3 vanish on polar edges (sqrt(-g) = 0 there).
+template <typename FT>
+__global__ void __launch_bounds__(BLOCK) k_emf(Dev g, Box box, const FT* __restrict__ F1,
+                                               const FT* __restrict__ F2, const FT* __restrict__ F3,
+                                               FT* __restrict__ E1, FT* __restrict__ E2,
+                                               FT* __restrict__ E3) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  long c = zid(g, i, j, k);
+  const long nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
+  bool pole = (g.pole_lo && j == 0) || (g.pole_hi && j == g.n2);
+  const FT q = (FT)0.25;
+  FT e3 = q * (F1[B2 * nz + c] + F1[B2 * nz + c - sj] - F2[B1 * nz + c] - F2[B1 * nz + c - si]);
+  FT e2 = q * (F3[B1 * nz + c] + F3[B1 * nz + c - si] - F1[B3 * nz + c] - F1[B3 * nz + c - sk]);
+  FT e1 = q * (F2[B3 * nz + c] + F2[B3 * nz + c - sk] - F3[B2 * nz + c] - F3[B2 * nz + c - sj]);
+  E1[c] = pole ? (FT)0 : e1;
+  E2[c] = e2;
+  E3[c] = pole ? (FT)0 : e3;
+}
+
+// Rebuild the B components of interior-face fluxes from the EMFs (as the
+// update does on the fly); used by the flux inspection entry point only.
+template <typename FT>
+__global__ void k_ct_fluxes(Dev g, Box box, FT* F1, FT* F2, FT* F3, const FT* E1, const FT* E2,
+                            const FT* E3) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  long c = zid(g, i, j, k);
+  const long nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
+  const FT h = (FT)0.5;
+  if (j < g.n2 && k < g.n3) {
+    F1[B1 * nz + c] = (FT)0;
+    F1[B2 * nz + c] = h * (E3[c] + E3[c + sj]);
+    F1[B3 * nz + c] = -h * (E2[c] + E2[c + sk]);
+  }
+  if (i < g.n1 && k < g.n3) {
+    F2[B1 * nz + c] = -h * (E3[c] + E3[c + si]);
+    F2[B2 * nz + c] = (FT)0;
+    F2[B3 * nz + c] = h * (E1[c] + E1[c + sk]);
+  }
+  if (i < g.n1 && j < g.n2) {
+    F3[B1 * nz + c] = h * (E2[c] + E2[c + si]);
+    F3[B2 * nz + c] = -h * (E1[c] + E1[c + sj]);
+    F3[B3 * nz + c] = (FT)0;
+  }
+}
+
+// ---------------------------------------------------------------- U -> P --
+
+// 1D_W (Noble et al. 2006) Newton solve for W = w gamma^2 with the normal
+// observer n_mu = (-alpha, 0, 0, 0): D = alpha U_rho/sqrt(-g),
+// Q_mu = alpha T^t_mu, Bn^i = alpha B^i.  Residual
+//   Q.n + W - p(W) + Bn^2 (1 + v^2)/2 - (Q.Bn)^2/(2 W^2),
+//   v^2 = [Qt^2 W^2 + (Q.Bn)^2 (Bn^2 + 2W)] / [(Bn^2 + W)^2 W^2],
+//   p = (gam-1)/gam [W (1 - v^2) - D sqrt(1 - v^2)].
+// Start from the guess's W (doubled while v^2 >= 1); steps leaving W > 0,
+// v^2 < 1 are halved (at most 20 times); stop at |dW| < tol W or maxit, then
+// one more step.  Returns 1 (and the guess's hydro prims) on failure.
+__device__ int invert_1dw(const Dev& g, const PointMetric<double>& m, const double U[NVAR],
+                          const double guess[NVAR], double P[NVAR]) {
+  const double gam = g.gam;
+  const double ig = 1.0 / m.gdet;
+  P[B1] = U[B1] * ig;
+  P[B2] = U[B2] * ig;
+  P[B3] = U[B3] * ig;
+  const double al = m.alpha;
+  const double D = al * U[RHO] * ig;
+  double Q[4] = {al * (U[UU] * ig - U[RHO] * ig), al * U[U1] * ig, al * U[U2] * ig, al * U[U3] * ig};
+  double Bn1 = al * P[B1], Bn2 = al * P[B2], Bn3 = al * P[B3];
+  // n^mu = g^{mu t} (-alpha); Q^mu = g^{mu nu} Q_nu
+  double ncon[4], Qup[4];
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    ncon[a] = -al * m.gcon[sidx(a, 0)];
+    Qup[a] = m.gcon[sidx(a, 0)] * Q[0] + m.gcon[sidx(a, 1)] * Q[1] + m.gcon[sidx(a, 2)] * Q[2] +
+             m.gcon[sidx(a, 3)] * Q[3];
+  }
+  double Qn = Q[0] * ncon[0] + Q[1] * ncon[1] + Q[2] * ncon[2] + Q[3] * ncon[3];
+  double QQ = Q[0] * Qup[0] + Q[1] * Qup[1] + Q[2] * Qup[2] + Q[3] * Qup[3];
+  double QB = Q[1] * Bn1 + Q[2] * Bn2 + Q[3] * Bn3;
+  double Bsq = m.gcov[sidx(1, 1)] * Bn1 * Bn1 + m.gcov[sidx(2, 2)] * Bn2 * Bn2 +
+               m.gcov[sidx(3, 3)] * Bn3 * Bn3 +
+               2.0 * (m.gcov[sidx(1, 2)] * Bn1 * Bn2 + m.gcov[sidx(1, 3)] * Bn1 * Bn3 +
+                      m.gcov[sidx(2, 3)] * Bn2 * Bn3);
+  double Qt2 = QQ + Qn * Qn;
+  double QB2 = QB * QB;
+  const double gf = (gam - 1.0) / gam;
+
+  auto vsq = [&](double W) {
+    double WB = Bsq + W;
+    return (Qt2 * W * W + QB2 * (Bsq + 2.0 * W)) / (WB * WB * W * W);
+  };
+  auto step = [&](double W) {
+    double v2 = vsq(W);
+    double sq = sqrt(1.0 - v2);
+    double pr = gf * (W * (1.0 - v2) - D * sq);
+    double W2 = W * W, WB = W + Bsq;
+    double f = Qn + W - pr + 0.5 * Bsq * (1.0 + v2) - QB2 / (2.0 * W2);
+    double dv2 = -2.0 * (Qt2 + QB2 * (3.0 * W2 + 3.0 * W * Bsq + Bsq * Bsq) / (W2 * W)) / (WB * WB * WB);
+    double dpdW = gf * (1.0 - v2);
+    double dpdv2 = gf * (-W + D / (2.0 * sq));
+    double df = 1.0 - (dpdW + dpdv2 * dv2) + 0.5 * Bsq * dv2 + QB2 / (W2 * W);
+    return -f / df;
+  };
+  auto fail = [&]() {
+#pragma unroll
+    for (int v = 0; v < 5; v++) P[v] = guess[v];
+    return 1;
+  };
+
+  const double g1 = guess[U1], g2 = guess[U2], g3 = guess[U3];
+  double qsq = m.gcov[sidx(1, 1)] * g1 * g1 + m.gcov[sidx(2, 2)] * g2 * g2 + m.gcov[sidx(3, 3)] * g3 * g3 +
+               2.0 * (m.gcov[sidx(1, 2)] * g1 * g2 + m.gcov[sidx(1, 3)] * g1 * g3 +
+                      m.gcov[sidx(2, 3)] * g2 * g3);
+  double W = (guess[RHO] + gam * guess[UU]) * (1.0 + qsq);
+  for (int b = 0; b < 60 && !(vsq(W) < 1.0); b++) W *= 2.0;
+  bool conv = false;
+  for (int it = 0; it < g.maxit; it++) {
+    double dW = step(W);
+    double Wn = W + dW;
+    for (int b = 0; b < 20 && !(Wn > 0.0 && vsq(Wn) < 1.0); b++) {
+      dW *= 0.5;
+      Wn = W + dW;
+    }
+    if (!isfinite(Wn) || Wn <= 0.0) return fail();
+    W = Wn;
+    if (fabs(dW) < g.tol * fabs(W)) {
+      conv = true;
+      break;
+    }
+  }
+  if (!conv) return fail();
+  W += step(W);
+  if (!isfinite(W) || W <= 0.0) return fail();
+  double v2 = vsq(W);
+  if (!(v2 >= 0.0 && v2 < 1.0)) return fail();
+  double gamma = 1.0 / sqrt(1.0 - v2);
+  double rho = D / gamma;
+  double u = (W * (1.0 - v2) - rho) / gam;
+  if (!(rho > 0.0) || !(u > 0.0)) return fail();
+  double pre = gamma / (W + Bsq);
+  double ut1 = pre * ((Qup[1] + ncon[1] * Qn) + QB * Bn1 / W);
+  double ut2 = pre * ((Qup[2] + ncon[2] * Qn) + QB * Bn2 / W);
+  double ut3 = pre * ((Qup[3] + ncon[3] * Qn) + QB * Bn3 / W);
+  if (!isfinite(ut1) || !isfinite(ut2) || !isfinite(ut3)) return fail();
+  P[RHO] = rho;
+  P[UU] = u;
+  P[U1] = ut1;
+  P[U2] = ut2;
+  P[U3] = ut3;
+  return 0;
+}
+
+// ----------------------------------------------------------------- update --
+
+__device__ __forceinline__ void load_conn(const double* __restrict__ conn, long plane, long q,
+                                          double cn[40]) {
+#pragma unroll
+  for (int f = 0; f < 40; f++) cn[f] = conn[f * plane + q];
+}
+
+// sqrt(-g) T^k_l Gamma^l_{nu k} into S[UU + nu].
+__device__ __forceinline__ void geometric_source(const double p[NVAR], const Fluid<double>& f,
+                                                 const PointMetric<double>& m, const double cn[40],
+                                                 double gam, double S[4]) {
+  double T[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) tmunu_row(p, f, gam, k, T[k]);
+#pragma unroll
+  for (int nu = 0; nu < 4; nu++) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+      for (int l = 0; l < 4; l++) s += T[k][l] * cn[l * 10 + sidx(nu, k)];
+    S[nu] = m.gdet * s;
+  }
+}
+
+// One stage for every interior zone.  STAGE 1: V = (Un + U1)/2 with
+// Un = U(Pin), U1 = Un + dt L(Pin); STAGE 2: U = V + dt L(Pin)/2.  Then
+// Pout = U_to_P(U; guess Pin).  B fluxes come from the edge EMFs.
+template <int STAGE, typename FT>
+__global__ void __launch_bounds__(BLOCK) k_update(Dev g, Box box, const double* __restrict__ Pin,
+                                                  double* __restrict__ Pout, double* __restrict__ V,
+                                                  const FT* __restrict__ F1, const FT* __restrict__ F2,
+                                                  const FT* __restrict__ F3, const FT* __restrict__ E1,
+                                                  const FT* __restrict__ E2, const FT* __restrict__ E3,
+                                                  const double* __restrict__ tabC,
+                                                  const double* __restrict__ conn, double dt,
+                                                  unsigned long long* fails) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  const long c = zid(g, i, j, k), nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
+  const long q2 = pid(g, i, j);
+  double p[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) p[v] = Pin[v * nz + c];
+  PointMetric<double> m;
+  load_metric<double>(tabC, g.plane, q2, m);
+  Fluid<double> f;
+  fluid_state(p, m, f);
+
+  double L[NVAR];
+  {
+    double cn[40];
+    load_conn(conn, g.plane, q2, cn);
+    double S[4];
+    geometric_source(p, f, m, cn, g.gam, S);
+    const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      double d1 = ((double)F1[v * nz + c + si] - (double)F1[v * nz + c]) / g.dx1;
+      double d2 = ((double)F2[v * nz + c + sj] - (double)F2[v * nz + c]) / g.dx2;
+      double d3 = ((double)F3[v * nz + c + sk] - (double)F3[v * nz + c]) / g.dx3;
+      L[v] = -((d1 + d2) + d3) + (v == RHO ? 0.0 : S[v - 1]);
+    }
+    (void)i1; (void)i2; (void)i3;
+    // Flux-CT fluxes of B: F1(B2) = (E3 + E3_{j+1})/2, F1(B3) = -(E2 + E2_{k+1})/2,
+    // F2(B1) = -(E3 + E3_{i+1})/2, F2(B3) = (E1 + E1_{k+1})/2,
+    // F3(B1) = (E2 + E2_{i+1})/2, F3(B2) = -(E1 + E1_{j+1})/2; normal ones zero.
+    auto e = [&](const FT* E, long o) { return (double)E[c + o]; };
+    double f1b2_p = 0.5 * (e(E3, si) + e(E3, si + sj)), f1b2_m = 0.5 * (e(E3, 0) + e(E3, sj));
+    double f1b3_p = -0.5 * (e(E2, si) + e(E2, si + sk)), f1b3_m = -0.5 * (e(E2, 0) + e(E2, sk));
+    double f2b1_p = -0.5 * (e(E3, sj) + e(E3, sj + si)), f2b1_m = -0.5 * (e(E3, 0) + e(E3, si));
+    double f2b3_p = 0.5 * (e(E1, sj) + e(E1, sj + sk)), f2b3_m = 0.5 * (e(E1, 0) + e(E1, sk));
+    double f3b1_p = 0.5 * (e(E2, sk) + e(E2, sk + si)), f3b1_m = 0.5 * (e(E2, 0) + e(E2, si));
+    double f3b2_p = -0.5 * (e(E1, sk) + e(E1, sk + sj)), f3b2_m = -0.5 * (e(E1, 0) + e(E1, sj));
+    L[B1] = -(((0.0 - 0.0) / g.dx1 + (f2b1_p - f2b1_m) / g.dx2) + (f3b1_p - f3b1_m) / g.dx3);
+    L[B2] = -(((f1b2_p - f1b2_m) / g.dx1 + (0.0 - 0.0) / g.dx2) + (f3b2_p - f3b2_m) / g.dx3);
+    L[B3] = -(((f1b3_p - f1b3_m) / g.dx1 + (f2b3_p - f2b3_m) / g.dx2) + (0.0 - 0.0) / g.dx3);
+  }
+
+  double U[NVAR];
+  if (STAGE == 1) {
+    double U0[NVAR];
+    prim_to_flux(p, f, m, g.gam, 0, U0);
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) {
+      U[v] = U0[v] + dt * L[v];
+      V[v * nz + c] = 0.5 * (U0[v] + U[v]);
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) U[v] = V[v * nz + c] + 0.5 * (dt * L[v]);
+  }
+  double out[NVAR];
+  int bad = invert_1dw(g, m, U, p, out);
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
+  if (bad) atomicAdd(fails, 1ull);
+}
+
+// ------------------------------------------------------- reductions etc. --
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Block-wide max and sum in a fixed order (wavefront butterflies, then the
+// wavefront results in index order): deterministic for a given launch shape.
+__device__ void block_reduce(double& mx, double& sm) {
+  __shared__ double smx[BLOCK / 64], ssm[BLOCK / 64];
+  mx = wave_max(mx);
+  sm = wave_sum(sm);
+  int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) {
+    smx[w] = mx;
+    ssm[w] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = smx[0], b = ssm[0];
+    for (int q = 1; q < BLOCK / 64; q++) {
+      a = fmax(a, smx[q]);
+      b += ssm[q];
+    }
+    mx = a;
+    sm = b;
+  }
+}
+
+// Per zone sum_d max(|c+|, |c-|)/dx_d over axes with more than one zone;
+// block maxima to partial[].
+__global__ void __launch_bounds__(BLOCK) k_dt_partial(Dev g, Box box, const double* __restrict__ P,
+                                                      const double* __restrict__ tabC,
+                                                      double* partial) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  double s = 0.0;
+  if (box_index(box, t, i, j, k)) {
+    long c = zid(g, i, j, k);
+    double p[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) p[v] = P[v * g.nz + c];
+    PointMetric<double> m;
+    load_metric<double>(tabC, g.plane, pid(g, i, j), m);
+    Fluid<double> f;
+    fluid_state(p, m, f);
+    double cp, cm;
+    if (g.n1 > 1) {
+      char_speeds(p, f, m, g.gam, 1, cp, cm);
+      s += fmax(fabs(cp), fabs(cm)) / g.dx1;
+    }
+    if (g.n2 > 1) {
+      char_speeds(p, f, m, g.gam, 2, cp, cm);
+      s += fmax(fabs(cp), fabs(cm)) / g.dx2;
+    }
+    if (g.n3 > 1) {
+      char_speeds(p, f, m, g.gam, 3, cp, cm);
+      s += fmax(fabs(cp), fabs(cm)) / g.dx3;
+    }
+  }
+  double sm = 0.0;
+  block_reduce(s, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Corner-centred div B (conserved field sqrt(-g) B^d, four zones per side)
+// over the corner box; block max and sum of |div|/sqrt(-g)_corner.
+__global__ void __launch_bounds__(BLOCK) k_divb_partial(Dev g, Box box, const double* __restrict__ P,
+                                                        const double* __restrict__ tabC,
+                                                        const double* __restrict__ corner,
+                                                        double* field, double* pmax, double* psum) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  double val = 0.0;
+  if (box_index(box, t, i, j, k)) {
+    const long nz = g.nz;
+    auto ub = [&](int d, int a, int b, int cc) {
+      return tabC[G_DET * g.plane + pid(g, a, b)] * P[(B1 + d) * nz + zid(g, a, b, cc)];
+    };
+    double d1 = (ub(0, i, j, k) + ub(0, i, j - 1, k) + ub(0, i, j, k - 1) + ub(0, i, j - 1, k - 1)) -
+                (ub(0, i - 1, j, k) + ub(0, i - 1, j - 1, k) + ub(0, i - 1, j, k - 1) +
+                 ub(0, i - 1, j - 1, k - 1));
+    double d2 = (ub(1, i, j, k) + ub(1, i - 1, j, k) + ub(1, i, j, k - 1) + ub(1, i - 1, j, k - 1)) -
+                (ub(1, i, j - 1, k) + ub(1, i - 1, j - 1, k) + ub(1, i, j - 1, k - 1) +
+                 ub(1, i - 1, j - 1, k - 1));
+    double d3 = (ub(2, i, j, k) + ub(2, i - 1, j, k) + ub(2, i, j - 1, k) + ub(2, i - 1, j - 1, k)) -
+                (ub(2, i, j, k - 1) + ub(2, i - 1, j, k - 1) + ub(2, i, j - 1, k - 1) +
+                 ub(2, i - 1, j - 1, k - 1));
+    double dv = d1 / (4.0 * g.dx1) + d2 / (4.0 * g.dx2) + d3 / (4.0 * g.dx3);
+    val = fabs(dv) / corner[pid(g, i, j)];
+    if (field) field[zid(g, i, j, k)] = val;
+  }
+  double mx = val, sm = val;
+  block_reduce(mx, sm);
+  if (threadIdx.x == 0) {
+    pmax[blockIdx.x] = mx;
+    psum[blockIdx.x] = sm;
+  }
+}
+
+// Single-block final pass over n partials: out[0] = max, out[1] = sum.
+__global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* pmax, const double* psum,
+                                                        int n, double* out) {
+  double mx = 0.0, sm = 0.0;
+  for (int q = threadIdx.x; q < n; q += BLOCK) {
+    mx = fmax(mx, pmax[q]);
+    if (psum) sm += psum[q];
+  }
+  block_reduce(mx, sm);
+  if (threadIdx.x == 0) {
+    out[0] = mx;
+    out[1] = sm;
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_prims_to_cons(Dev g, Box box, const double* __restrict__ P,
+                                                         double* __restrict__ U,
+                                                         const double* __restrict__ tabC) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  long c = zid(g, i, j, k);
+  double p[NVAR], u[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) p[v] = P[v * g.nz + c];
+  PointMetric<double> m;
+  load_metric<double>(tabC, g.plane, pid(g, i, j), m);
+  Fluid<double> f;
+  fluid_state(p, m, f);
+  prim_to_flux(p, f, m, g.gam, 0, u);
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) U[v * g.nz + c] = u[v];
+}
+
+__global__ void __launch_bounds__(BLOCK) k_cons_to_prims(Dev g, Box box, const double* __restrict__ U,
+                                                         const double* __restrict__ G,
+                                                         double* __restrict__ P, int* flags,
+                                                         const double* __restrict__ tabC,
+                                                         unsigned long long* fails) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  long c = zid(g, i, j, k);
+  double u[NVAR], gs[NVAR], p[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    u[v] = U[v * g.nz + c];
+    gs[v] = G[v * g.nz + c];
+  }
+  PointMetric<double> m;
+  load_metric<double>(tabC, g.plane, pid(g, i, j), m);
+  int bad = invert_1dw(g, m, u, gs, p);
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) P[v * g.nz + c] = p[v];
+  if (flags) flags[c] = bad;
+  if (bad) atomicAdd(fails, 1ull);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- host side --
+
+struct grmhd_ctx {
+  grmhd_grid grid;
+  grmhd_metric metric;
+  grmhd_params params;
+  hipStream_t stream;
+  Dev dev;
+  // workspace carve (device)
+  double *P, *P1, *V;
+  void *F[3], *E[3];
+  double *tabC, *tabF1, *tabF2, *corner, *conn;
+  double *pmax, *psum, *result;
+  unsigned long long* fails;
+  // optional per-kernel-class timing with HIP events on the context's stream
+  bool timing = false;
+  struct Mark { hipEvent_t a, b; int cls; };
+  Mark* marks = nullptr;
+  int nmarks = 0, capmarks = 0;
+};
+
+namespace {
+
+struct Carve {
+  size_t off = 0;
+  template <typename T>
+  T* take(char* base, size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
+  if (!g || !p) return false;
+  if (g->ng != NG || g->n1 < 1 || g->n2 < 1 || g->n3 < 1) return false;
+  if ((long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * (g->n3 + 2 * NG) * NVAR > (1L << 40)) return false;
+  for (int a = 0; a < 6; a++)
+    if (g->bc[a] < GRMHD_BC_PERIODIC || g->bc[a] > GRMHD_BC_FROZEN) return false;
+  int n[3] = {g->n1, g->n2, g->n3};
+  for (int a = 0; a < 3; a++) {
+    bool per = g->bc[2 * a] == GRMHD_BC_PERIODIC || g->bc[2 * a + 1] == GRMHD_BC_PERIODIC;
+    if (per && g->bc[2 * a] != g->bc[2 * a + 1]) return false;
+    if ((g->bc[2 * a] == GRMHD_BC_POLAR || g->bc[2 * a + 1] == GRMHD_BC_POLAR) && (a != 1 || n[a] < NG))
+      return false;
+    if ((g->bc[2 * a] == GRMHD_BC_OUTFLOW || g->bc[2 * a + 1] == GRMHD_BC_OUTFLOW) && n[a] < 1)
+      return false;
+  }
+  if (!(g->x1max > g->x1min && g->x2max > g->x2min && g->x3max > g->x3min)) return false;
+  if (p->recon != GRMHD_RECON_MC && p->recon != GRMHD_RECON_WENO5) return false;
+  if (p->precision != GRMHD_PREC_FP64 && p->precision != GRMHD_PREC_MIXED) return false;
+  if (p->floors != 0 || !(p->gamma_ad > 1.0) || p->newton_maxit < 1 || !(p->newton_tol > 0.0))
+    return false;
+  return true;
+}
+
+size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
+  long nz = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * (g->n3 + 2 * NG);
+  long plane = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG);
+  Carve cv;
+  double *P = cv.take<double>(base, NVAR * nz), *P1 = cv.take<double>(base, NVAR * nz);
+  double* V = cv.take<double>(base, NVAR * nz);
+  double* F[3];
+  double* E[3];
+  for (int d = 0; d < 3; d++) F[d] = cv.take<double>(base, NVAR * nz);
+  for (int d = 0; d < 3; d++) E[d] = cv.take<double>(base, nz);
+  double* tabC = cv.take<double>(base, G_NF * plane);
+  double* tabF1 = cv.take<double>(base, G_NF * plane);
+  double* tabF2 = cv.take<double>(base, G_NF * plane);
+  double* corner = cv.take<double>(base, plane);
+  double* conn = cv.take<double>(base, NCONN * plane);
+  double* pmax = cv.take<double>(base, MAX_PARTIALS);
+  double* psum = cv.take<double>(base, MAX_PARTIALS);
+  double* result = cv.take<double>(base, 8);
+  unsigned long long* fails = cv.take<unsigned long long>(base, 8);
+  if (c) {
+    c->P = P; c->P1 = P1; c->V = V;
+    for (int d = 0; d < 3; d++) { c->F[d] = F[d]; c->E[d] = E[d]; }
+    c->tabC = tabC; c->tabF1 = tabF1; c->tabF2 = tabF2; c->corner = corner; c->conn = conn;
+    c->pmax = pmax; c->psum = psum; c->result = result; c->fails = fails;
+  }
+  return cv.off;
+}
+
+int hip_check() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
+
+enum { T_BC = 0, T_FLUX1, T_FLUX2, T_FLUX3, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_NCLASS };
+
+// Brackets one launch with a pair of events when timing is enabled.
+struct Timed {
+  grmhd_ctx* c;
+  int slot = -1;
+  Timed(grmhd_ctx* ctx, int cls) : c(ctx) {
+    if (!c->timing) return;
+    if (c->nmarks == c->capmarks) {
+      int cap = c->capmarks ? 2 * c->capmarks : 256;
+      auto* m = (grmhd_ctx::Mark*)realloc(c->marks, sizeof(grmhd_ctx::Mark) * cap);
+      if (!m) return;
+      for (int q = c->capmarks; q < cap; q++) {
+        hipEventCreate(&m[q].a);
+        hipEventCreate(&m[q].b);
+      }
+      c->marks = m;
+      c->capmarks = cap;
+    }
+    slot = c->nmarks++;
+    c->marks[slot].cls = cls;
+    hipEventRecord(c->marks[slot].a, c->stream);
+  }
+  ~Timed() {
+    if (slot >= 0) hipEventRecord(c->marks[slot].b, c->stream);
+  }
+};
+
+int fill_ghosts(grmhd_ctx* c, double* P) {
+  Timed tm(c, T_BC);
+  k_bc<<<blocks_for(c->dev.nz), BLOCK, 0, c->stream>>>(c->dev, P);
+  return hip_check();
+}
+
+// Flux and EMF kernels of one stage, reading the (ghost-filled) prims P.
+template <typename R, typename FT>
+int stage_fluxes(grmhd_ctx* c, const double* P) {
+  const Dev& g = c->dev;
+  FT* F1 = (FT*)c->F[0];
+  FT* F2 = (FT*)c->F[1];
+  FT* F3 = (FT*)c->F[2];
+  Box b1 = make_box(0, g.n1, -1, g.n2, -1, g.n3);
+  Box b2 = make_box(-1, g.n1, 0, g.n2, -1, g.n3);
+  Box b3 = make_box(-1, g.n1, -1, g.n2, 0, g.n3);
+  if (c->params.recon == GRMHD_RECON_MC) {
+    { Timed tm(c, T_FLUX1); k_flux<1, GRMHD_RECON_MC, R, FT><<<blocks_for(b1.count()), BLOCK, 0, c->stream>>>(g, b1, P, c->tabF1, F1); }
+    { Timed tm(c, T_FLUX2); k_flux<2, GRMHD_RECON_MC, R, FT><<<blocks_for(b2.count()), BLOCK, 0, c->stream>>>(g, b2, P, c->tabF2, F2); }
+    { Timed tm(c, T_FLUX3); k_flux<3, GRMHD_RECON_MC, R, FT><<<blocks_for(b3.count()), BLOCK, 0, c->stream>>>(g, b3, P, c->tabC, F3); }
+  } else {
+    { Timed tm(c, T_FLUX1); k_flux<1, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b1.count()), BLOCK, 0, c->stream>>>(g, b1, P, c->tabF1, F1); }
+    { Timed tm(c, T_FLUX2); k_flux<2, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b2.count()), BLOCK, 0, c->stream>>>(g, b2, P, c->tabF2, F2); }
+    { Timed tm(c, T_FLUX3); k_flux<3, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b3.count()), BLOCK, 0, c->stream>>>(g, b3, P, c->tabC, F3); }
+  }
+  Box be = make_box(0, g.n1, 0, g.n2, 0, g.n3);
+  Timed tm(c, T_EMF);
+  k_emf<FT><<<blocks_for(be.count()), BLOCK, 0, c->stream>>>(g, be, F1, F2, F3, (FT*)c->E[0],
+                                                                (FT*)c->E[1], (FT*)c->E[2]);
+  return hip_check();
+}
+
+template <int STAGE, typename FT>
+int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt) {
+  const Dev& g = c->dev;
+  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  Timed tm(c, STAGE == 1 ? T_UPDATE1 : T_UPDATE2);
+  k_update<STAGE, FT><<<blocks_for(bz.count()), BLOCK, 0, c->stream>>>(
+      g, bz, Pin, Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1], (const FT*)c->F[2],
+      (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2], c->tabC, c->conn, dt, c->fails);
+  return hip_check();
+}
+
+template <typename R, typename FT>
+int do_step(grmhd_ctx* c, double dt) {
+  int rc;
+  if ((rc = fill_ghosts(c, c->P))) return rc;
+  if ((rc = stage_fluxes<R, FT>(c, c->P))) return rc;
+  if ((rc = stage_update<1, FT>(c, c->P, c->P1, dt))) return rc;
+  if ((rc = fill_ghosts(c, c->P1))) return rc;
+  if ((rc = stage_fluxes<R, FT>(c, c->P1))) return rc;
+  return stage_update<2, FT>(c, c->P1, c->P, dt);
+}
+
+int sync(grmhd_ctx* c) { return hipStreamSynchronize(c->stream) == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
+  if (!grid_ok(grid, params)) return 0;
+  return carve(nullptr, nullptr, grid);
+}
+
+int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* metric,
+                 const grmhd_params* params, void* d_workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out || !metric || !grid_ok(grid, params) || !d_workspace) return GRMHD_E_ARG;
+  if (metric->metric != GRMHD_METRIC_MINKOWSKI && metric->metric != GRMHD_METRIC_KERR_MKS)
+    return GRMHD_E_ARG;
+  if (((uintptr_t)d_workspace & 255) != 0) return GRMHD_E_ARG;
+  if (ws_bytes < carve(nullptr, nullptr, grid)) return GRMHD_E_NOMEM;
+  grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
+  if (!c) return GRMHD_E_NOMEM;
+  c->grid = *grid;
+  c->metric = *metric;
+  c->params = *params;
+  c->stream = (hipStream_t)hip_stream;
+  carve(c, (char*)d_workspace, grid);
+  Dev& g = c->dev;
+  g.n1 = grid->n1; g.n2 = grid->n2; g.n3 = grid->n3;
+  g.s1 = g.n1 + 2 * NG; g.s2 = g.n2 + 2 * NG; g.s3 = g.n3 + 2 * NG;
+  g.nz = (long)g.s1 * g.s2 * g.s3;
+  g.plane = (long)g.s1 * g.s2;
+  g.dx1 = (grid->x1max - grid->x1min) / g.n1;
+  g.dx2 = (grid->x2max - grid->x2min) / g.n2;
+  g.dx3 = (grid->x3max - grid->x3min) / g.n3;
+  g.x1min = grid->x1min;
+  g.x2min = grid->x2min;
+  for (int a = 0; a < 6; a++) g.bc[a] = grid->bc[a];
+  bool kerr = metric->metric == GRMHD_METRIC_KERR_MKS;
+  g.pole_lo = kerr && fabs(grid->x2min) < 1e-10;
+  g.pole_hi = kerr && fabs(grid->x2max - 1.0) < 1e-10;
+  g.gam = params->gamma_ad;
+  g.weno_eps = params->weno_eps;
+  g.tol = params->newton_tol;
+  g.maxit = params->newton_maxit;
+  g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
+  k_geometry<<<blocks_for(g.plane), BLOCK, 0, c->stream>>>(g, c->tabC, c->tabF1, c->tabF2, c->corner,
+                                                           c->conn);
+  if (hipMemsetAsync(c->fails, 0, sizeof(unsigned long long), c->stream) != hipSuccess ||
+      hip_check() != GRMHD_OK) {
+    delete c;
+    return GRMHD_E_HIP;
+  }
+  *out = c;
+  return GRMHD_OK;
+}
+
+int grmhd_load_prims(grmhd_ctx* c, const double* d_prims) {
+  if (!c || !d_prims) return GRMHD_E_ARG;
+  size_t bytes = sizeof(double) * NVAR * c->dev.nz;
+  if (hipMemcpyAsync(c->P, d_prims, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  // the stage buffer carries the same (frozen) ghosts
+  if (hipMemcpyAsync(c->P1, d_prims, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  return GRMHD_OK;
+}
+
+int grmhd_step(grmhd_ctx* c, double dt) {
+  if (!c || !(dt > 0.0) || !isfinite(dt)) return GRMHD_E_ARG;
+  if (c->params.precision == GRMHD_PREC_FP64) return do_step<double, double>(c, dt);
+  return do_step<float, float>(c, dt);
+}
+
+int grmhd_estimate_dt(grmhd_ctx* c, double* dt_out) {
+  if (!c || !dt_out) return GRMHD_E_ARG;
+  int rc;
+  if ((rc = fill_ghosts(c, c->P))) return rc;
+  const Dev& g = c->dev;
+  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  unsigned nb = blocks_for(bz.count());
+  if (nb > MAX_PARTIALS) return GRMHD_E_ARG;
+  {
+    Timed tm(c, T_DT);
+    k_dt_partial<<<nb, BLOCK, 0, c->stream>>>(g, bz, c->P, c->tabC, c->pmax);
+    k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, nullptr, (int)nb, c->result);
+  }
+  if ((rc = hip_check())) return rc;
+  double smax = 0.0;
+  if (hipMemcpyAsync(&smax, c->result, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  if ((rc = sync(c))) return rc;
+  if (!(smax > 0.0) || !isfinite(smax)) return GRMHD_E_STATE;
+  *dt_out = c->params.cfl / smax;
+  return GRMHD_OK;
+}
+
+int grmhd_get_prims(grmhd_ctx* c, double* d_out) {
+  if (!c || !d_out) return GRMHD_E_ARG;
+  int rc;
+  if ((rc = fill_ghosts(c, c->P))) return rc;
+  if (hipMemcpyAsync(d_out, c->P, sizeof(double) * NVAR * c->dev.nz, hipMemcpyDeviceToDevice,
+                     c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  return GRMHD_OK;
+}
+
+int grmhd_divb(grmhd_ctx* c, double* d_divb, double* max_out, double* mean_out) {
+  if (!c || !max_out || !mean_out) return GRMHD_E_ARG;
+  int rc;
+  if ((rc = fill_ghosts(c, c->P))) return rc;
+  const Dev& g = c->dev;
+  int ilo = g.bc[0] == GRMHD_BC_PERIODIC ? 0 : 1;
+  int jlo = g.bc[2] == GRMHD_BC_PERIODIC ? 0 : 1;
+  int klo = g.bc[4] == GRMHD_BC_PERIODIC ? 0 : 1;
+  Box b = make_box(ilo, g.n1 - 1, jlo, g.n2 - 1, klo, g.n3 - 1);
+  long cnt = b.n1 > 0 && b.n2 > 0 && b.n3 > 0 ? b.count() : 0;
+  if (cnt == 0) {
+    *max_out = *mean_out = 0.0;
+    return GRMHD_OK;
+  }
+  unsigned nb = blocks_for(cnt);
+  if (nb > MAX_PARTIALS) return GRMHD_E_ARG;
+  k_divb_partial<<<nb, BLOCK, 0, c->stream>>>(g, b, c->P, c->tabC, c->corner, d_divb, c->pmax, c->psum);
+  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, c->psum, (int)nb, c->result);
+  if ((rc = hip_check())) return rc;
+  double res[2];
+  if (hipMemcpyAsync(res, c->result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  if ((rc = sync(c))) return rc;
+  *max_out = res[0];
+  *mean_out = res[1] / (double)cnt;
+  return GRMHD_OK;
+}
+
+int grmhd_get_status(grmhd_ctx* c, long long* n_inv_fail, long long* n_floor) {
+  if (!c || !n_inv_fail || !n_floor) return GRMHD_E_ARG;
+  unsigned long long f = 0;
+  if (hipMemcpyAsync(&f, c->fails, sizeof(f), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  int rc = sync(c);
+  if (rc) return rc;
+  *n_inv_fail = (long long)f;
+  *n_floor = 0;
+  return GRMHD_OK;
+}
+
+int grmhd_reset_status(grmhd_ctx* c) {
+  if (!c) return GRMHD_E_ARG;
+  return hipMemsetAsync(c->fails, 0, sizeof(unsigned long long), c->stream) == hipSuccess ? GRMHD_OK
+                                                                                        : GRMHD_E_HIP;
+}
+
+int grmhd_prims_to_cons(grmhd_ctx* c, const double* d_prims, double* d_cons) {
+  if (!c || !d_prims || !d_cons) return GRMHD_E_ARG;
+  const Dev& g = c->dev;
+  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  k_prims_to_cons<<<blocks_for(bz.count()), BLOCK, 0, c->stream>>>(g, bz, d_prims, d_cons, c->tabC);
+  return hip_check();
+}
+
+int grmhd_cons_to_prims(grmhd_ctx* c, const double* d_cons, const double* d_guess, double* d_prims,
+                        int* d_flags, long long* n_fail) {
+  if (!c || !d_cons || !d_guess || !d_prims || !n_fail) return GRMHD_E_ARG;
+  const Dev& g = c->dev;
+  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  unsigned long long* cnt = c->fails + 1;
+  if (hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream) != hipSuccess) return GRMHD_E_HIP;
+  k_cons_to_prims<<<blocks_for(bz.count()), BLOCK, 0, c->stream>>>(g, bz, d_cons, d_guess, d_prims, d_flags,
+                                                                   c->tabC, cnt);
+  int rc = hip_check();
+  if (rc) return rc;
+  unsigned long long f = 0;
+  if (hipMemcpyAsync(&f, cnt, sizeof(f), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  if ((rc = sync(c))) return rc;
+  *n_fail = (long long)f;
+  return GRMHD_OK;
+}
+
+int grmhd_fluxes(grmhd_ctx* c, const double* d_prims, double* d_flux) {
+  if (!c || !d_prims || !d_flux) return GRMHD_E_ARG;
+  if (c->params.precision != GRMHD_PREC_FP64) return GRMHD_E_STATE;
+  int rc;
+  if ((rc = grmhd_load_prims(c, d_prims))) return rc;
+  if ((rc = fill_ghosts(c, c->P))) return rc;
+  if ((rc = stage_fluxes<double, double>(c, c->P))) return rc;
+  const Dev& g = c->dev;
+  Box be = make_box(0, g.n1, 0, g.n2, 0, g.n3);
+  k_ct_fluxes<double><<<blocks_for(be.count()), BLOCK, 0, c->stream>>>(
+      g, be, (double*)c->F[0], (double*)c->F[1], (double*)c->F[2], (const double*)c->E[0],
+      (const double*)c->E[1], (const double*)c->E[2]);
+  if ((rc = hip_check())) return rc;
+  size_t bytes = sizeof(double) * NVAR * g.nz;
+  for (int d = 0; d < 3; d++)
+    if (hipMemcpyAsync(d_flux + d * NVAR * g.nz, c->F[d], bytes, hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+      return GRMHD_E_HIP;
+  return GRMHD_OK;
+}
+
+const char* grmhd_strerror(int code) {
+  switch (code) {
+    case GRMHD_OK: return "ok";
+    case GRMHD_E_ARG: return "invalid argument";
+    case GRMHD_E_HIP: return "HIP runtime error";
+    case GRMHD_E_STATE: return "invalid state for this call";
+    case GRMHD_E_NOMEM: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+int grmhd_timing(grmhd_ctx* c, int enable) {
+  if (!c) return GRMHD_E_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GRMHD_E_HIP;
+  c->timing = enable != 0;
+  c->nmarks = 0;
+  return GRMHD_OK;
+}
+
+int grmhd_timing_report(grmhd_ctx* c, double* total_ms, long long* launches, int nclass) {
+  if (!c || !total_ms || !launches || nclass < T_NCLASS) return GRMHD_E_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GRMHD_E_HIP;
+  for (int q = 0; q < nclass; q++) {
+    total_ms[q] = 0.0;
+    launches[q] = 0;
+  }
+  for (int q = 0; q < c->nmarks; q++) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->marks[q].a, c->marks[q].b) != hipSuccess) return GRMHD_E_HIP;
+    total_ms[c->marks[q].cls] += ms;
+    launches[c->marks[q].cls] += 1;
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_destroy(grmhd_ctx* c) {
+  if (!c) return GRMHD_E_ARG;
+  for (int q = 0; q < c->capmarks; q++) {
+    hipEventDestroy(c->marks[q].a);
+    hipEventDestroy(c->marks[q].b);
+  }
+  free(c->marks);
+  delete c;
+  return GRMHD_OK;
+}
+
+}  // extern "C"

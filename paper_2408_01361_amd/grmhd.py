@@ -1,0 +1,223 @@
+"""ctypes binding of libgrmhd.so (include/grmhd.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module passes raw device
+pointers of torch tensors and the current torch stream.  There is no
+fallback: importing it without the built library raises.
+"""
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrmhd.so")
+
+OK, E_ARG, E_HIP, E_STATE, E_NOMEM = 0, -1, -2, -3, -4
+METRIC_MINKOWSKI, METRIC_KERR_MKS = 0, 1
+RECON_MC, RECON_WENO5 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN = 0, 1, 2, 3
+NG, NVAR = 3, 8
+
+
+class GrmhdError(RuntimeError):
+    pass
+
+
+class grmhd_grid(C.Structure):
+    _fields_ = [("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int), ("ng", C.c_int),
+                ("x1min", C.c_double), ("x1max", C.c_double), ("x2min", C.c_double),
+                ("x2max", C.c_double), ("x3min", C.c_double), ("x3max", C.c_double),
+                ("bc", C.c_int * 6)]
+
+
+class grmhd_metric(C.Structure):
+    _fields_ = [("metric", C.c_int), ("a", C.c_double), ("hslope", C.c_double)]
+
+
+class grmhd_params(C.Structure):
+    _fields_ = [("gamma_ad", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double),
+                ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("recon", C.c_int),
+                ("precision", C.c_int), ("floors", C.c_int)]
+
+
+EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_step",
+           "grmhd_estimate_dt", "grmhd_get_prims", "grmhd_divb", "grmhd_get_status",
+           "grmhd_reset_status", "grmhd_prims_to_cons", "grmhd_cons_to_prims", "grmhd_fluxes",
+           "grmhd_timing", "grmhd_timing_report", "grmhd_strerror", "grmhd_destroy")
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2408_01361_amd.build.build()")
+    lib = C.CDLL(path)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)
+    G, M, P = C.POINTER(grmhd_grid), C.POINTER(grmhd_metric), C.POINTER(grmhd_params)
+    sig = {
+        "grmhd_workspace_bytes": (C.c_size_t, [G, P]),
+        "grmhd_create": (C.c_int, [C.POINTER(vp), G, M, P, vp, C.c_size_t, vp]),
+        "grmhd_load_prims": (C.c_int, [vp, vp]),
+        "grmhd_step": (C.c_int, [vp, C.c_double]),
+        "grmhd_estimate_dt": (C.c_int, [vp, dp]),
+        "grmhd_get_prims": (C.c_int, [vp, vp]),
+        "grmhd_divb": (C.c_int, [vp, vp, dp, dp]),
+        "grmhd_get_status": (C.c_int, [vp, ip, ip]),
+        "grmhd_reset_status": (C.c_int, [vp]),
+        "grmhd_prims_to_cons": (C.c_int, [vp, vp, vp]),
+        "grmhd_cons_to_prims": (C.c_int, [vp, vp, vp, vp, vp, ip]),
+        "grmhd_fluxes": (C.c_int, [vp, vp, vp]),
+        "grmhd_timing": (C.c_int, [vp, C.c_int]),
+        "grmhd_timing_report": (C.c_int, [vp, dp, ip, C.c_int]),
+        "grmhd_strerror": (C.c_char_p, [C.c_int]),
+        "grmhd_destroy": (C.c_int, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise GrmhdError(f"grmhd error {rc}: {lib().grmhd_strerror(rc).decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise GrmhdError("device tensor expected")
+    if not t.is_contiguous():
+        raise GrmhdError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_grid(spec):
+    """grmhd_grid from any object with n1..n3, x?min/x?max and bc."""
+    g = grmhd_grid()
+    g.n1, g.n2, g.n3, g.ng = spec.n1, spec.n2, spec.n3, NG
+    g.x1min, g.x1max, g.x2min, g.x2max = spec.x1min, spec.x1max, spec.x2min, spec.x2max
+    g.x3min, g.x3max = spec.x3min, spec.x3max
+    for i in range(6):
+        g.bc[i] = int(spec.bc[i])
+    return g
+
+
+class Grmhd:
+    """One grid's state and workspace on a CUDA (HIP) device.
+
+    Python owns the workspace tensor; the library borrows it for the
+    context's lifetime and enqueues on the torch stream current at creation.
+    """
+
+    def __init__(self, spec, gamma_ad, recon=RECON_WENO5, precision=PREC_FP64, cfl=0.9,
+                 weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda",
+                 stream=None, strict=False):
+        self.spec = spec
+        self.grid = make_grid(spec)
+        self.metric = grmhd_metric(int(spec.metric), float(spec.a), float(spec.hslope))
+        self.params = grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
+                                   int(newton_maxit), int(recon), int(precision), 0)
+        self.strict = strict
+        L = lib()
+        nbytes = L.grmhd_workspace_bytes(C.byref(self.grid), C.byref(self.params))
+        if nbytes == 0:
+            raise GrmhdError("invalid grid or parameters")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.shape = (NVAR, spec.n3 + 2 * NG, spec.n2 + 2 * NG, spec.n1 + 2 * NG)
+        ctx = C.c_void_p()
+        _check(L.grmhd_create(C.byref(ctx), C.byref(self.grid), C.byref(self.metric),
+                              C.byref(self.params), C.c_void_p(self._ws_ptr), nbytes,
+                              C.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            lib().grmhd_destroy(ctx)
+            self.ctx = None
+
+    def load(self, prims):
+        p = prims.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(p.shape) == self.shape, (p.shape, self.shape)
+        self._keep = p
+        _check(lib().grmhd_load_prims(self.ctx, _ptr(p)))
+
+    def step(self, dt):
+        _check(lib().grmhd_step(self.ctx, float(dt)))
+        if self.strict and self.status()[0]:
+            raise GrmhdError("inversion failures")
+
+    def dt(self):
+        out = C.c_double()
+        _check(lib().grmhd_estimate_dt(self.ctx, C.byref(out)))
+        return out.value
+
+    def prims(self):
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(lib().grmhd_get_prims(self.ctx, _ptr(out)))
+        return out
+
+    def divb(self, field=False):
+        mx, mean = C.c_double(), C.c_double()
+        f = torch.zeros(self.shape[1:], dtype=torch.float64, device=self.device) if field else None
+        _check(lib().grmhd_divb(self.ctx, _ptr(f), C.byref(mx), C.byref(mean)))
+        return (mx.value, mean.value, f) if field else (mx.value, mean.value)
+
+    def status(self):
+        a, b = C.c_longlong(), C.c_longlong()
+        _check(lib().grmhd_get_status(self.ctx, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def reset_status(self):
+        _check(lib().grmhd_reset_status(self.ctx))
+
+    def prims_to_cons(self, prims):
+        p = prims.to(device=self.device, dtype=torch.float64).contiguous()
+        out = torch.zeros_like(p)
+        _check(lib().grmhd_prims_to_cons(self.ctx, _ptr(p), _ptr(out)))
+        return out
+
+    def cons_to_prims(self, cons, guess):
+        u = cons.to(device=self.device, dtype=torch.float64).contiguous()
+        g = guess.to(device=self.device, dtype=torch.float64).contiguous()
+        out = torch.zeros_like(u)
+        flags = torch.zeros(self.shape[1:], dtype=torch.int32, device=self.device)
+        n = C.c_longlong()
+        _check(lib().grmhd_cons_to_prims(self.ctx, _ptr(u), _ptr(g), _ptr(out), _ptr(flags),
+                                         C.byref(n)))
+        return out, n.value, flags
+
+    def fluxes(self, prims):
+        p = prims.to(device=self.device, dtype=torch.float64).contiguous()
+        out = torch.zeros((3,) + self.shape, dtype=torch.float64, device=self.device)
+        _check(lib().grmhd_fluxes(self.ctx, _ptr(p), _ptr(out)))
+        return out
+
+    TIMING_CLASSES = ("bc", "flux1", "flux2", "flux3", "emf", "update1", "update2", "dt")
+
+    def timing(self, enable=True):
+        _check(lib().grmhd_timing(self.ctx, int(enable)))
+
+    def timing_report(self):
+        n = len(self.TIMING_CLASSES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_longlong * n)()
+        _check(lib().grmhd_timing_report(self.ctx, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.TIMING_CLASSES)}

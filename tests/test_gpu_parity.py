@@ -1,0 +1,208 @@
+"""GPU-vs-oracle parity of the HIP path, through the C ABI.
+
+The bar (per step, FP64): relative L1 of every primitive over interior zones,
+sum|P_gpu - P_oracle| / sum|P_oracle|, at most 1e-12; failure flags equal;
+div B at roundoff.  Inputs are the seeded workloads, identical on both sides;
+both sides advance with the oracle's dt.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import linear_mode, fm_torus, interior, GridSpec, RECON_MC, RECON_WENO5
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gr():
+    from paper_2408_01361_amd import grmhd
+    return grmhd
+
+
+def rel_l1(a, b):
+    """Per-variable relative L1 of interior zones, and the worst of them."""
+    A, B = interior(a), interior(b)
+    out = []
+    for v in range(A.shape[0]):
+        den = np.abs(B[v]).sum()
+        num = np.abs(A[v] - B[v]).sum()
+        if den == 0.0:
+            out.append(0.0 if num == 0.0 else np.inf)
+        else:
+            out.append(num / den)
+    return np.array(out)
+
+
+def run_gpu(grid, P, gam, recon, dts, precision=0):
+    torch = _torch()
+    gr = _gr()
+    s = gr.Grmhd(grid, gam, recon=recon, precision=precision)
+    s.load(torch.from_numpy(P))
+    for dt in dts:
+        s.step(dt)
+    out = s.prims().cpu().numpy()
+    torch.cuda.synchronize()
+    return out, s.status()[0], s
+
+
+CASES = {
+    "fast32_mc": lambda: (linear_mode("fast", 32, ndim=3)[0:2], 4 / 3, RECON_MC),
+    "fast16_weno": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, RECON_WENO5),
+    "alfven24x20_mc_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, RECON_MC),
+    "torus24_weno": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, RECON_WENO5),
+    "torus20x28x6_mc": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, RECON_MC),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_step_parity(case):
+    (grid, P), gam, recon = CASES[case]()
+    c = oracle.cfg(grid, gam=gam, recon=recon)
+    nsteps = 2
+    ref, fails, dts, flags = oracle.run(c, P, -1, nsteps, flags=True)
+    out, gfails, _ = run_gpu(grid, P, gam, recon, dts)
+    r = rel_l1(out, ref)
+    print(case, "dts", dts, "fails", fails, gfails, "rel L1", r)
+    assert gfails == fails
+    assert r.max() <= TOL, r
+
+
+def test_prims_to_cons_and_inversion_parity():
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(16, 24, 8)
+    c = oracle.cfg(grid, gam=13 / 9)
+    s = gr.Grmhd(grid, 13 / 9)
+    U_ref = oracle.prims_to_cons(c, P)
+    U = s.prims_to_cons(torch.from_numpy(P)).cpu().numpy()
+    assert rel_l1(U, U_ref).max() <= 1e-14
+    rng = np.random.default_rng(11)
+    guess = P * (1 + 0.03 * rng.uniform(-1, 1, P.shape))
+    P_ref, n_ref, f_ref = oracle.cons_to_prims(c, U_ref, guess)
+    P_gpu, n_gpu, f_gpu = s.cons_to_prims(torch.from_numpy(U_ref), torch.from_numpy(guess))
+    assert n_gpu == n_ref
+    assert np.array_equal(interior(f_gpu.cpu().numpy()), interior(f_ref))
+    assert rel_l1(P_gpu.cpu().numpy(), P_ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("recon", [RECON_MC, RECON_WENO5])
+def test_flux_parity(recon):
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(16, 16, 8)
+    c = oracle.cfg(grid, gam=13 / 9, recon=recon)
+    F_ref = oracle.fluxes(c, P, ct=True)
+    s = gr.Grmhd(grid, 13 / 9, recon=recon)
+    F = s.fluxes(torch.from_numpy(P)).cpu().numpy()
+    n1, n2, n3 = grid.n1, grid.n2, grid.n3
+    sl = [np.s_[:, 3:3 + n3, 3:3 + n2, 3:4 + n1], np.s_[:, 3:3 + n3, 3:4 + n2, 3:3 + n1],
+          np.s_[:, 3:4 + n3, 3:3 + n2, 3:3 + n1]]
+    for d in range(3):
+        a, b = F[d][sl[d]], F_ref[d][sl[d]]
+        scale = np.abs(b).max(axis=(1, 2, 3)) + 1e-300
+        err = np.abs(a - b).max(axis=(1, 2, 3)) / scale
+        assert err.max() < 1e-12, (d, err)
+
+
+def test_dt_and_divb_parity():
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(24, 24, 8)
+    c = oracle.cfg(grid, gam=13 / 9, recon=RECON_WENO5)
+    s = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    s.load(torch.from_numpy(P))
+    assert s.dt() == pytest.approx(oracle.estimate_dt(c, P), rel=1e-14)
+    mx, mean = s.divb()
+    omx, omean = oracle.divb(c, P)
+    assert mx == pytest.approx(omx, rel=1e-6, abs=1e-18)
+    g2, P2, _, _ = linear_mode("fast", 16, ndim=3)
+    c2 = oracle.cfg(g2, recon=RECON_MC)
+    s2 = gr.Grmhd(g2, 4 / 3, recon=RECON_MC)
+    s2.load(torch.from_numpy(P2))
+    assert s2.dt() == pytest.approx(oracle.estimate_dt(c2, P2), rel=1e-14)
+
+
+def test_divb_stays_at_roundoff_on_gpu():
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(32, 32, 16)
+    s = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    s.load(torch.from_numpy(P))
+    for _ in range(5):
+        s.step(s.dt())
+    mx, mean = s.divb()
+    scale = np.abs(interior(P[5:7])).max() / grid.dx[0]
+    assert mx < 1e-13 * scale
+
+
+def test_determinism_and_restart_equivalence():
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(24, 24, 8)
+    a = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    a.load(torch.from_numpy(P))
+    dt = a.dt()
+    for _ in range(4):
+        a.step(dt)
+    A = a.prims().cpu().numpy()
+    b = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    b.load(torch.from_numpy(P))
+    for _ in range(2):
+        b.step(dt)
+    mid = b.prims()
+    c = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    c.load(mid)
+    for _ in range(2):
+        c.step(dt)
+    C_ = c.prims().cpu().numpy()
+    a2 = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    a2.load(torch.from_numpy(P))
+    for _ in range(4):
+        a2.step(dt)
+    assert np.array_equal(interior(A), interior(a2.prims().cpu().numpy()))
+    assert np.array_equal(interior(A), interior(C_))
+
+
+def test_unperturbed_torus_stays_bitwise_axisymmetric():
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(24, 24, 8, noise=0.0)
+    s = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    s.load(torch.from_numpy(P))
+    dt = s.dt()
+    for _ in range(3):
+        s.step(dt)
+    I = interior(s.prims().cpu().numpy())
+    for k in range(1, I.shape[1]):
+        assert np.array_equal(I[:, k], I[:, 0])
+
+
+def test_mixed_precision_error_is_bounded_and_divb_fp64():
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(32, 32, 16)
+    s64 = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    s32 = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5, precision=gr.PREC_MIXED)
+    s64.load(torch.from_numpy(P))
+    s32.load(torch.from_numpy(P))
+    dt = s64.dt()
+    for _ in range(3):
+        s64.step(dt)
+        s32.step(dt)
+    a, b = s32.prims().cpu().numpy(), s64.prims().cpu().numpy()
+    r = rel_l1(a, b)
+    print("mixed vs fp64 rel L1 per var", r)
+    assert r[0] < 1e-4
+    mx, _ = s32.divb()
+    scale = np.abs(interior(P[5:7])).max() / grid.dx[0]
+    assert mx < 1e-13 * scale
