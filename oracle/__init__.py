@@ -71,6 +71,9 @@ def _declare(lib):
     lib.orc_weno5.restype = C.c_double
     lib.orc_mc_slope.argtypes = [C.c_double] * 3
     lib.orc_mc_slope.restype = C.c_double
+    L = C.POINTER(C.c_longlong)
+    lib.orc_count_face.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, C.c_int, L]
+    lib.orc_count_zone_update.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, C.c_double, L]
     return lib
 
 
@@ -210,3 +213,18 @@ def weno5(a, b, c_, d, e, eps=1e-26):
 
 def mc_slope(l, c_, r):
     return lib().orc_mc_slope(l, c_, r)
+
+
+def count_face(c, prims, d, i, j, k):
+    """(add, mul, div, sqrt, transcendental) of one face flux (counting build)."""
+    out = (C.c_longlong * 5)()
+    P = np.ascontiguousarray(prims, dtype=np.float64)
+    lib(True).orc_count_face(C.byref(c), _ptr(P), d, i, j, k, out)
+    return list(out)
+
+
+def count_zone_update(c, prims, i, j, k, dt):
+    out = (C.c_longlong * 5)()
+    P = np.ascontiguousarray(prims, dtype=np.float64)
+    lib(True).orc_count_zone_update(C.byref(c), _ptr(P), i, j, k, float(dt), out)
+    return list(out)

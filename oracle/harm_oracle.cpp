@@ -36,10 +36,15 @@
 #ifdef ORACLE_COUNTING
 #include "flopcount.hpp"
 typedef CountedReal real;
+FlopTally g_flops;
 #else
 typedef double real;
 using std::sqrt;
 using std::fabs;
+using std::sin;
+using std::cos;
+using std::exp;
+using std::isfinite;
 #endif
 
 namespace {
@@ -83,7 +88,7 @@ struct Geom {
 //   g_tt = z - 1, g_tr = z, g_tph = -a z s^2, g_rr = 1 + z,
 //   g_rph = -a s^2 (1 + z), g_thth = Sigma, g_phph = s^2 (Sigma + a^2 s^2 (1+z)).
 void ks_metric(real a, real r, real th, real g[4][4], real dgr[4][4], real dgth[4][4]) {
-  real s = std::sin(th), c = std::cos(th);
+  real s = sin(th), c = cos(th);
   real s2 = s * s, c2 = c * c;
   real sig = r * r + a * a * c2;
   real z = 2.0 * r / sig;
@@ -124,15 +129,15 @@ void geom_point(const orc_cfg& c, real x1, real x2, Geom& G) {
     return;
   }
   const real a = c.a, h = c.hslope;
-  real r = std::exp(x1);
-  real th = M_PI * x2 + 0.5 * (1.0 - h) * std::sin(2.0 * M_PI * x2);
-  real dth = M_PI * (1.0 + (1.0 - h) * std::cos(2.0 * M_PI * x2));
+  real r = exp(x1);
+  real th = M_PI * x2 + 0.5 * (1.0 - h) * sin(2.0 * M_PI * x2);
+  real dth = M_PI * (1.0 + (1.0 - h) * cos(2.0 * M_PI * x2));
   real L[4] = {1.0, r, dth, 1.0};
   real g[4][4], dgr[4][4], dgth[4][4];
   ks_metric(a, r, th, g, dgr, dgth);
   for (int m = 0; m < 4; m++)
     for (int n = 0; n < 4; n++) G.gcov[m][n] = g[m][n] * L[m] * L[n];
-  real s = std::sin(th), cth = std::cos(th);
+  real s = sin(th), cth = cos(th);
   real s2 = s * s;
   real sig = r * r + a * a * cth * cth;
   real z = 2.0 * r / sig;
@@ -160,10 +165,10 @@ void conn_point(const orc_cfg& c, real x1, real x2, real conn[4][4][4]) {
       for (int n = 0; n < 4; n++) conn[l][m][n] = 0.0;
   if (c.metric == MINKOWSKI) return;
   const real a = c.a, h = c.hslope;
-  real r = std::exp(x1);
-  real th = M_PI * x2 + 0.5 * (1.0 - h) * std::sin(2.0 * M_PI * x2);
-  real dth = M_PI * (1.0 + (1.0 - h) * std::cos(2.0 * M_PI * x2));
-  real d2th = -2.0 * M_PI * M_PI * (1.0 - h) * std::sin(2.0 * M_PI * x2);
+  real r = exp(x1);
+  real th = M_PI * x2 + 0.5 * (1.0 - h) * sin(2.0 * M_PI * x2);
+  real dth = M_PI * (1.0 + (1.0 - h) * cos(2.0 * M_PI * x2));
+  real d2th = -2.0 * M_PI * M_PI * (1.0 - h) * sin(2.0 * M_PI * x2);
   real L[4] = {1.0, r, dth, 1.0};
   real g[4][4], dgr[4][4], dgth[4][4];
   ks_metric(a, r, th, g, dgr, dgth);
@@ -598,7 +603,10 @@ int u_to_p(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[N
     QdotB += Qcov[i] * Bn[i];
     for (int j = 1; j < 4; j++) Bsq += G.gcov[i][j] * Bn[i] * Bn[j];
   }
+  // Qt is the projection of Q orthogonal to n, a spacelike vector: a negative
+  // square can only be roundoff (a fluid at rest with the normal observer).
   real Qtsq = QdotQ + Qdotn * Qdotn;
+  if (Qtsq < 0.0) Qtsq = 0.0;
   real QB2 = QdotB * QdotB;
   const real gfac = (gam - 1.0) / gam;
 
@@ -639,13 +647,13 @@ int u_to_p(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[N
       dW = 0.5 * dW;
       Wn = W + dW;
     }
-    if (!std::isfinite((double)Wn) || Wn <= 0.0) return failed();
+    if (!isfinite((real)Wn) || Wn <= 0.0) return failed();
     W = Wn;
     if (fabs(dW) < c.newton_tol * fabs(W)) { conv = true; break; }
   }
   if (!conv) return failed();
   W = W + newton_step(W);
-  if (!std::isfinite((double)W) || W <= 0.0) return failed();
+  if (!isfinite((real)W) || W <= 0.0) return failed();
 
   real v2 = vsq_of(W);
   if (!(v2 >= 0.0 && v2 < 1.0)) return failed();
@@ -658,7 +666,7 @@ int u_to_p(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[N
   for (int i = 1; i < 4; i++) {
     real Qt = Qcon[i] + ncon[i] * Qdotn;
     ut[i - 1] = pre * (Qt + QdotB * Bn[i] / W);
-    if (!std::isfinite((double)ut[i - 1])) return failed();
+    if (!isfinite((real)ut[i - 1])) return failed();
   }
   P[RHO] = rho;
   P[UU] = u;
@@ -993,5 +1001,61 @@ double orc_weno5(double a, double b, double c, double d, double e, double eps) {
 }
 
 double orc_mc_slope(double l, double c, double r) { return (double)mc_slope(l, c, r); }
+
+// ---- operation counts (counting build; zeros otherwise) ----
+
+static void tally_out(long long* out) {
+#ifdef ORACLE_COUNTING
+  out[0] = g_flops.add; out[1] = g_flops.mul; out[2] = g_flops.div;
+  out[3] = g_flops.sqrt; out[4] = g_flops.trans;
+  g_flops = FlopTally();
+#else
+  for (int q = 0; q < 5; q++) out[q] = 0;
+#endif
+}
+
+static void tally_reset() {
+#ifdef ORACLE_COUNTING
+  g_flops = FlopTally();
+#endif
+}
+
+// Operations of one face flux along d at zone (i, j, k) of the given prims
+// (ghosts filled first, outside the count): reconstruction of the 8 prims,
+// both face states, fluxes, conserved variables, speeds and the LLF flux.
+void orc_count_face(const orc_cfg* c, const double* prims, int d, int i, int j, int k, long long* out) {
+  Grid g(*c);
+  std::vector<real> P;
+  load(g, prims, P);
+  fill_ghosts(g, P);
+  real f[NV];
+  tally_reset();
+  face_flux(g, P, d, i, j, k, f);
+  tally_out(out);
+}
+
+// Operations of the EMF and corrected-B-flux work of one zone (three edges,
+// six rebuilt fluxes) are counted analytically by the caller; this counts
+// one zone's update: source, flux divergence, RK combination (stage 1, with
+// U(P)) and the inversion.
+void orc_count_zone_update(const orc_cfg* c, const double* prims, int i, int j, int k, double dt,
+                           long long* out) {
+  Grid g(*c);
+  std::vector<real> P;
+  load(g, prims, P);
+  fill_ghosts(g, P);
+  std::vector<real> F[3];
+  for (int d = 0; d < 3; d++) F[d].assign(NV * g.nz, 0.0);
+  compute_fluxes(g, P, F);
+  flux_ct(g, F);
+  real p[NV], L[NV], u0[NV], U[NV], pn[NV];
+  for (int v = 0; v < NV; v++) p[v] = Vc(P, g, v, i, j, k);
+  tally_reset();
+  rhs(g, F, p, i, j, k, L);
+  cons_at(g, p, i, j, u0);
+  for (int v = 0; v < NV; v++) U[v] = u0[v] + (real)dt * L[v];
+  u_to_p(g.c, g.gC[g.id2(i, j)], U, p, pn);
+  tally_out(out);
+}
 
 }  // extern "C"

@@ -174,8 +174,8 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ P, long nz
     const double* q = P + v * nz + c;
     if (RECON == GRMHD_RECON_MC) {
       R m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s];
-      qL[v] = m1 + (R)0.5 * mc_slope(m2, m1, p0);
-      qR[v] = p0 - (R)0.5 * mc_slope(m1, p0, p1);
+      qL[v] = mc_left(m2, m1, p0);
+      qR[v] = mc_right(m1, p0, p1);
     } else {
       R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
         p2 = (R)q[2 * s];
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(BLOCK) k_flux(Dev g, Box box, const double* __
   cmax = fmax(cmax, (R)0);
 #pragma unroll
   for (int v = 0; v < NVAR; v++)
-    F[v * g.nz + c] = (FT)((R)0.5 * (FL[v] + FR[v]) - (R)0.5 * cmax * (UR[v] - UL[v]));
+    F[v * g.nz + c] = (FT)llf(FL[v], FR[v], UL[v], UR[v], cmax);
 }
 
 // Flux-CT edge EMFs at the lower (x1, x2, x3) corner of zone (i, j, k):
@@ -294,14 +294,15 @@ __global__ void k_ct_fluxes(Dev g, Box box, FT* F1, FT* F2, FT* F3, const FT* E1
 // one more step.  Returns 1 (and the guess's hydro prims) on failure.
 __device__ int invert_1dw(const Dev& g, const PointMetric<double>& m, const double U[NVAR],
                           const double guess[NVAR], double P[NVAR]) {
+#pragma clang fp contract(off)
   const double gam = g.gam;
-  const double ig = 1.0 / m.gdet;
-  P[B1] = U[B1] * ig;
-  P[B2] = U[B2] * ig;
-  P[B3] = U[B3] * ig;
+  const double gd = m.gdet;
+  P[B1] = U[B1] / gd;
+  P[B2] = U[B2] / gd;
+  P[B3] = U[B3] / gd;
   const double al = m.alpha;
-  const double D = al * U[RHO] * ig;
-  double Q[4] = {al * (U[UU] * ig - U[RHO] * ig), al * U[U1] * ig, al * U[U2] * ig, al * U[U3] * ig};
+  const double D = al * U[RHO] / gd;
+  double Q[4] = {al * (U[UU] / gd - U[RHO] / gd), al * U[U1] / gd, al * U[U2] / gd, al * U[U3] / gd};
   double Bn1 = al * P[B1], Bn2 = al * P[B2], Bn3 = al * P[B3];
   // n^mu = g^{mu t} (-alpha); Q^mu = g^{mu nu} Q_nu
   double ncon[4], Qup[4];
@@ -318,7 +319,8 @@ __device__ int invert_1dw(const Dev& g, const PointMetric<double>& m, const doub
                m.gcov[sidx(3, 3)] * Bn3 * Bn3 +
                2.0 * (m.gcov[sidx(1, 2)] * Bn1 * Bn2 + m.gcov[sidx(1, 3)] * Bn1 * Bn3 +
                       m.gcov[sidx(2, 3)] * Bn2 * Bn3);
-  double Qt2 = QQ + Qn * Qn;
+  // |Q projected orthogonal to n|^2 is non-negative; roundoff below zero is cleared
+  double Qt2 = fmax(QQ + Qn * Qn, 0.0);
   double QB2 = QB * QB;
   const double gf = (gam - 1.0) / gam;
 
@@ -332,7 +334,7 @@ __device__ int invert_1dw(const Dev& g, const PointMetric<double>& m, const doub
     double pr = gf * (W * (1.0 - v2) - D * sq);
     double W2 = W * W, WB = W + Bsq;
     double f = Qn + W - pr + 0.5 * Bsq * (1.0 + v2) - QB2 / (2.0 * W2);
-    double dv2 = -2.0 * (Qt2 + QB2 * (3.0 * W2 + 3.0 * W * Bsq + Bsq * Bsq) / (W2 * W)) / (WB * WB * WB);
+    double dv2 = -2.0 * (Qt2 + QB2 * (3.0 * W * W + 3.0 * W * Bsq + Bsq * Bsq) / (W2 * W)) / (WB * WB * WB);
     double dpdW = gf * (1.0 - v2);
     double dpdv2 = gf * (-W + D / (2.0 * sq));
     double df = 1.0 - (dpdW + dpdv2 * dv2) + 0.5 * Bsq * dv2 + QB2 / (W2 * W);
@@ -399,6 +401,7 @@ __device__ __forceinline__ void load_conn(const double* __restrict__ conn, long 
 __device__ __forceinline__ void geometric_source(const double p[NVAR], const Fluid<double>& f,
                                                  const PointMetric<double>& m, const double cn[40],
                                                  double gam, double S[4]) {
+#pragma clang fp contract(off)
   double T[4][4];
 #pragma unroll
   for (int k = 0; k < 4; k++) tmunu_row(p, f, gam, k, T[k]);
@@ -425,6 +428,8 @@ __global__ void __launch_bounds__(BLOCK) k_update(Dev g, Box box, const double* 
                                                   const double* __restrict__ tabC,
                                                   const double* __restrict__ conn, double dt,
                                                   unsigned long long* fails) {
+  // the FP64 update is rounded operation by operation, in the order written
+#pragma clang fp contract(off)
   long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   int i, j, k;
   if (!box_index(box, t, i, j, k)) return;
@@ -444,7 +449,6 @@ __global__ void __launch_bounds__(BLOCK) k_update(Dev g, Box box, const double* 
     load_conn(conn, g.plane, q2, cn);
     double S[4];
     geometric_source(p, f, m, cn, g.gam, S);
-    const double i1 = 1.0 / g.dx1, i2 = 1.0 / g.dx2, i3 = 1.0 / g.dx3;
 #pragma unroll
     for (int v = 0; v < 5; v++) {
       double d1 = ((double)F1[v * nz + c + si] - (double)F1[v * nz + c]) / g.dx1;
@@ -452,7 +456,6 @@ __global__ void __launch_bounds__(BLOCK) k_update(Dev g, Box box, const double* 
       double d3 = ((double)F3[v * nz + c + sk] - (double)F3[v * nz + c]) / g.dx3;
       L[v] = -((d1 + d2) + d3) + (v == RHO ? 0.0 : S[v - 1]);
     }
-    (void)i1; (void)i2; (void)i3;
     // Flux-CT fluxes of B: F1(B2) = (E3 + E3_{j+1})/2, F1(B3) = -(E2 + E2_{k+1})/2,
     // F2(B1) = -(E3 + E3_{i+1})/2, F2(B3) = (E1 + E1_{k+1})/2,
     // F3(B1) = (E2 + E2_{i+1})/2, F3(B2) = -(E1 + E1_{j+1})/2; normal ones zero.
@@ -463,9 +466,9 @@ __global__ void __launch_bounds__(BLOCK) k_update(Dev g, Box box, const double* 
     double f2b3_p = 0.5 * (e(E1, sj) + e(E1, sj + sk)), f2b3_m = 0.5 * (e(E1, 0) + e(E1, sk));
     double f3b1_p = 0.5 * (e(E2, sk) + e(E2, sk + si)), f3b1_m = 0.5 * (e(E2, 0) + e(E2, si));
     double f3b2_p = -0.5 * (e(E1, sk) + e(E1, sk + sj)), f3b2_m = -0.5 * (e(E1, 0) + e(E1, sj));
-    L[B1] = -(((0.0 - 0.0) / g.dx1 + (f2b1_p - f2b1_m) / g.dx2) + (f3b1_p - f3b1_m) / g.dx3);
-    L[B2] = -(((f1b2_p - f1b2_m) / g.dx1 + (0.0 - 0.0) / g.dx2) + (f3b2_p - f3b2_m) / g.dx3);
-    L[B3] = -(((f1b3_p - f1b3_m) / g.dx1 + (f2b3_p - f2b3_m) / g.dx2) + (0.0 - 0.0) / g.dx3);
+    L[B1] = -((f2b1_p - f2b1_m) / g.dx2 + (f3b1_p - f3b1_m) / g.dx3);
+    L[B2] = -((f1b2_p - f1b2_m) / g.dx1 + (f3b2_p - f3b2_m) / g.dx3);
+    L[B3] = -((f1b3_p - f1b3_m) / g.dx1 + (f2b3_p - f2b3_m) / g.dx2);
   }
 
   double U[NVAR];
@@ -755,8 +758,11 @@ struct Timed {
       auto* m = (grmhd_ctx::Mark*)realloc(c->marks, sizeof(grmhd_ctx::Mark) * cap);
       if (!m) return;
       for (int q = c->capmarks; q < cap; q++) {
-        hipEventCreate(&m[q].a);
-        hipEventCreate(&m[q].b);
+        if (hipEventCreate(&m[q].a) != hipSuccess || hipEventCreate(&m[q].b) != hipSuccess) {
+          c->marks = m;
+          c->timing = false;  // no events: stop timing rather than fail the step
+          return;
+        }
       }
       c->marks = m;
       c->capmarks = cap;
@@ -1061,8 +1067,8 @@ int grmhd_timing_report(grmhd_ctx* c, double* total_ms, long long* launches, int
 int grmhd_destroy(grmhd_ctx* c) {
   if (!c) return GRMHD_E_ARG;
   for (int q = 0; q < c->capmarks; q++) {
-    hipEventDestroy(c->marks[q].a);
-    hipEventDestroy(c->marks[q].b);
+    (void)hipEventDestroy(c->marks[q].a);
+    (void)hipEventDestroy(c->marks[q].b);
   }
   free(c->marks);
   delete c;
