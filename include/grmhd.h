@@ -128,6 +128,54 @@ int grmhd_cons_to_prims(grmhd_ctx* ctx, const double* d_cons, const double* d_gu
  * [3][8][padded] float64 (device).  For testing and inspection. */
 int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
 
+/* Adjoint of one step (vector-Jacobian product), FP64 only.
+ * Given the step's input prims d_prims_in (device, padded) and step size dt,
+ * and the adjoint of its output prims d_gprims_out (device, padded; only
+ * interior entries are read), writes the adjoint of the input prims to
+ * d_gprims_in (device, padded; ghost entries zero: ghosts are functions of the
+ * interior through the boundary conditions, frozen ghosts are constants) and
+ * the derivative with respect to the adiabatic index to *g_gamma (host).
+ * The step is recomputed from d_prims_in (per-step checkpointing); the
+ * inversion is differentiated by the implicit-function theorem, limiter and
+ * max() branches by the branch taken.  Scratch comes from d_vjp_ws (device,
+ * 256-byte aligned, >= grmhd_vjp_workspace_bytes()).  Neither the context's
+ * state nor its failure count changes.  Synchronises.  E_STATE for the mixed
+ * precision path. */
+size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params);
+int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const double* d_gprims_out,
+                   double* d_gprims_in, double* g_gamma, void* d_vjp_ws, size_t vjp_ws_bytes);
+
+/* ---- Batched uneven meshblock packs (FP64) ----
+ * A pack holds nblocks cubic blocks of n[b]^3 zones, block b being the
+ * sub-box starting at interior zone offsets_ijk[3b..3b+2] of the global grid
+ * (same metric and parameters); every block has frozen (Dirichlet) ghost
+ * zones, and x2 block faces on the polar axis carry no flux.  One pack step is
+ * one persistent cooperative launch per RK2 stage that processes every block.
+ * Packed prims: the blocks' padded arrays [8][n+6][n+6][n+6], concatenated in
+ * block order (device).  Tile shapes per block size (t1*t2*t3 <= 256) only
+ * change speed.  Errors as for single contexts; E_ARG for blocks outside the
+ * global grid or a non-FP64 precision. */
+typedef struct grmhd_pack grmhd_pack;
+size_t grmhd_pack_workspace_bytes(int nblocks, const int* n);
+int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* offsets_ijk,
+                      const grmhd_grid* global, const grmhd_metric* metric,
+                      const grmhd_params* params, void* d_workspace, size_t ws_bytes,
+                      void* hip_stream);
+int grmhd_pack_set_tiles(grmhd_pack* pack, int n, int t1, int t2, int t3);
+int grmhd_pack_load_prims(grmhd_pack* pack, const double* d_prims);
+int grmhd_pack_step(grmhd_pack* pack, double dt);
+int grmhd_pack_get_prims(grmhd_pack* pack, double* d_out);
+int grmhd_pack_get_status(grmhd_pack* pack, long long* n_inv_fail);
+/* Cooperative grid size and length (doubles) of the packed prims. */
+int grmhd_pack_info(grmhd_pack* pack, int* grid_blocks, long long* prim_doubles);
+int grmhd_pack_destroy(grmhd_pack* pack);
+
+/* Work order of the heavy kernels: each XCD takes a contiguous run of
+ * workgroups in which kg consecutive x3 planes of one (x1, x2) chunk follow
+ * each other (flux/EMF and update kernels separately; default 8).  Any
+ * kg >= 1 gives the same results; only speed changes.  E_ARG if kg < 1. */
+int grmhd_set_schedule(grmhd_ctx* ctx, int kg_flux, int kg_update);
+
 /* Per-kernel-class timing with HIP events recorded on the context's stream
  * around every launch while enabled (enabling clears earlier records).
  * Classes: 0 ghost fill, 1-3 fluxes along x1..x3, 4 EMFs, 5 stage-1 update,

@@ -1,0 +1,441 @@
+// Hand-written adjoint (vector-Jacobian product) of one SSPRK2 step.
+//
+// The reverse sweep is written out stage by stage: the inversion is
+// differentiated by the implicit-function theorem (lambda_U = (dU/dP)^-T
+// lambda_P at the recovered prims; a zone whose inversion failed passes its
+// hydro adjoint to the guess), the RK combination and flux divergence are
+// transposed explicitly, Flux-CT is transposed through its edge EMFs, every
+// face flux is transposed through its stencil, and ghost fills are transposed
+// by gathering each ghost's adjoint back onto the zone it was copied from
+// (with the polar sign flips).  Only the local Jacobians of the per-point
+// physics (a face flux with respect to its stencil, the source and the
+// conserved variables with respect to one zone's prims) come from
+// forward-mode dual numbers, one input direction at a time.  Every sum is a
+// gather in a fixed order: the result is deterministic.
+//
+// Included inside the anonymous namespace of grmhd.hip.
+
+template <int RECON>
+struct Stencil {
+  static constexpr int W = RECON == GRMHD_RECON_MC ? 4 : 6;  // zones per face
+  static constexpr int H = W / 2;                            // zones left of the face
+  static constexpr int NSEED = NVAR * W + 1;                 // + gamma
+};
+
+// Face flux along D as a function of its stencil, with one input direction
+// (seed = v * W + s: variable v of stencil zone s; seed = NVAR * W: gamma).
+template <int D, int RECON>
+__device__ __forceinline__ void face_flux_dual(const Dev& g, const double* __restrict__ P, long c,
+                                               long s, const PointMetric<Dual>& m, int seed,
+                                               Dual F[NVAR]) {
+  using St = Stencil<RECON>;
+  Dual qL[NVAR], qR[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    Dual q[St::W];
+#pragma unroll
+    for (int z = 0; z < St::W; z++) q[z] = Dual(P[v * g.nz + c + (z - St::H) * s], seed == v * St::W + z ? 1.0 : 0.0);
+    if (RECON == GRMHD_RECON_MC) {
+      qL[v] = mc_left(q[0], q[1], q[2]);
+      qR[v] = mc_right(q[1], q[2], q[3]);
+    } else {
+      Dual eps(g.weno_eps);
+      qL[v] = weno5(q[0], q[1], q[2], q[3], q[4], eps);
+      qR[v] = weno5(q[5], q[4], q[3], q[2], q[1], eps);
+    }
+  }
+  const Dual gam(g.gam, seed == NVAR * St::W ? 1.0 : 0.0);
+  Dual FL[NVAR], UL[NVAR], FR[NVAR], UR[NVAR], cpl, cml, cpr, cmr;
+  {
+    Fluid<Dual> f;
+    fluid_state(qL, m, f);
+    prim_to_flux(qL, f, m, gam, D, FL);
+    prim_to_flux(qL, f, m, gam, 0, UL);
+    char_speeds(qL, f, m, gam, D, cpl, cml);
+  }
+  {
+    Fluid<Dual> f;
+    fluid_state(qR, m, f);
+    prim_to_flux(qR, f, m, gam, D, FR);
+    prim_to_flux(qR, f, m, gam, 0, UR);
+    char_speeds(qR, f, m, gam, D, cpr, cmr);
+  }
+  Dual cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
+  cmax = fmax(cmax, Dual(0.0));
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) F[v] = llf(FL[v], FR[v], UL[v], UR[v], cmax);
+}
+
+__device__ __forceinline__ void load_metric_dual(const double* __restrict__ tab, long plane, long q,
+                                                 PointMetric<Dual>& m) {
+  PointMetric<double> md;
+  load_metric<double>(tab, plane, q, md);
+#pragma unroll
+  for (int f = 0; f < 10; f++) {
+    m.gcov[f] = Dual(md.gcov[f]);
+    m.gcon[f] = Dual(md.gcon[f]);
+  }
+  m.gdet = Dual(md.gdet);
+  m.alpha = Dual(md.alpha);
+}
+
+// Adjoint of the Flux-CT EMFs on every padded edge position (zero outside
+// the edge box [0, n]^3 and on polar edges), from the stage adjoint lambda_L
+// of the field components (zero in ghost zones).  With the rebuilt fluxes
+// Ft1(B2) = (E3 + E3_{j+1})/2 etc., lambda_Ft(face f) = (LL(f) - LL(f - e_d))/dx_d.
+__global__ void __launch_bounds__(BLOCK) k_adj_emf(Dev g, const double* __restrict__ LL,
+                                                   double* __restrict__ LE1, double* __restrict__ LE2,
+                                                   double* __restrict__ LE3) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= g.nz) return;
+  int i = (int)(t % g.s1) - NG;
+  long r = t / g.s1;
+  int j = (int)(r % g.s2) - NG, k = (int)(r / g.s2) - NG;
+  if (i < 0 || j < 0 || k < 0 || i > g.n1 || j > g.n2 || k > g.n3) {
+    LE1[t] = LE2[t] = LE3[t] = 0.0;
+    return;
+  }
+  const long nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
+  auto lf = [&](int v, long f, long sd, double dx) { return (LL[v * nz + f] - LL[v * nz + f - sd]) / dx; };
+  bool pole = (g.pole_lo && j == 0) || (g.pole_hi && j == g.n2);
+  // E3 enters Ft1(B2) at faces (i,j),(i,j-1) with +1/2 and Ft2(B1) at (i,j),(i-1,j) with -1/2
+  double e3 = 0.5 * (lf(B2, t, si, g.dx1) + lf(B2, t - sj, si, g.dx1)) -
+              0.5 * (lf(B1, t, sj, g.dx2) + lf(B1, t - si, sj, g.dx2));
+  // E2 enters Ft3(B1) at (i,k),(i-1,k) with +1/2 and Ft1(B3) at (i,k),(i,k-1) with -1/2
+  double e2 = 0.5 * (lf(B1, t, sk, g.dx3) + lf(B1, t - si, sk, g.dx3)) -
+              0.5 * (lf(B3, t, si, g.dx1) + lf(B3, t - sk, si, g.dx1));
+  // E1 enters Ft2(B3) at (j,k),(j,k-1) with +1/2 and Ft3(B2) at (j,k),(j-1,k) with -1/2
+  double e1 = 0.5 * (lf(B3, t, sj, g.dx2) + lf(B3, t - sk, sj, g.dx2)) -
+              0.5 * (lf(B2, t, sk, g.dx3) + lf(B2, t - sj, sk, g.dx3));
+  LE1[t] = pole ? 0.0 : e1;
+  LE2[t] = e2;
+  LE3[t] = pole ? 0.0 : e3;
+}
+
+// Per face of the forward flux box: the adjoint of the LLF flux (hydro slots
+// from the divergence, field slots through the EMF averages), pushed through
+// the face's local Jacobian onto its stencil: LS[(v*W + s) * nz + face], and
+// the gamma part added to GF[face].
+template <int D, int RECON>
+__global__ void __launch_bounds__(BLOCK) k_adj_face(Dev g, Box box, const double* __restrict__ P,
+                                                    const double* __restrict__ tab,
+                                                    const double* __restrict__ LL,
+                                                    const double* __restrict__ LE1,
+                                                    const double* __restrict__ LE2,
+                                                    const double* __restrict__ LE3,
+                                                    double* __restrict__ LS, double* __restrict__ GF) {
+  using St = Stencil<RECON>;
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  const long c = zid(g, i, j, k), nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
+  const long s = D == 1 ? si : (D == 2 ? sj : sk);
+  const double dx = D == 1 ? g.dx1 : (D == 2 ? g.dx2 : g.dx3);
+  double lam[NVAR];
+#pragma unroll
+  for (int v = 0; v < 5; v++) lam[v] = (LL[v * nz + c] - LL[v * nz + c - s]) / dx;
+  const double q = 0.25;
+  if (D == 1) {
+    lam[B1] = 0.0;
+    lam[B2] = q * (LE3[c] + LE3[c + sj]);
+    lam[B3] = -q * (LE2[c] + LE2[c + sk]);
+  } else if (D == 2) {
+    lam[B1] = -q * (LE3[c] + LE3[c + si]);
+    lam[B2] = 0.0;
+    lam[B3] = q * (LE1[c] + LE1[c + sk]);
+  } else {
+    lam[B1] = q * (LE2[c] + LE2[c + si]);
+    lam[B2] = -q * (LE1[c] + LE1[c + sj]);
+    lam[B3] = 0.0;
+  }
+  bool zero = true;
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) zero = zero && lam[v] == 0.0;
+  if (zero || (D == 2 && ((g.pole_lo && j == 0) || (g.pole_hi && j == g.n2)))) {
+    for (int sd = 0; sd < St::NSEED - 1; sd++) LS[sd * nz + c] = 0.0;
+    return;
+  }
+  PointMetric<Dual> m;
+  load_metric_dual(tab, g.plane, pid(g, i, j), m);
+  for (int sd = 0; sd < St::NSEED; sd++) {
+    Dual F[NVAR];
+    face_flux_dual<D, RECON>(g, P, c, s, m, sd, F);
+    double acc = 0.0;
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) acc += F[v].d * lam[v];
+    if (sd < St::NSEED - 1)
+      LS[sd * nz + c] = acc;
+    else
+      GF[c] += acc;
+  }
+}
+
+// Gather of the stencil adjoints onto every padded zone: zone z is slot s of
+// the D-face f = z + (H - s) e_D.
+template <int RECON>
+__device__ __forceinline__ void gather_dir(const Dev& g, const Box& fb, const double* __restrict__ LS,
+                                           int D, int i, int j, int k, double acc[NVAR]) {
+  using St = Stencil<RECON>;
+  for (int s = 0; s < St::W; s++) {
+    int o = St::H - s;
+    int fi = i + (D == 1 ? o : 0), fj = j + (D == 2 ? o : 0), fk = k + (D == 3 ? o : 0);
+    if (fi < fb.lo1 || fi >= fb.lo1 + fb.n1 || fj < fb.lo2 || fj >= fb.lo2 + fb.n2 || fk < fb.lo3 ||
+        fk >= fb.lo3 + fb.n3)
+      continue;
+    long f = zid(g, fi, fj, fk);
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) acc[v] += LS[(v * St::W + s) * g.nz + f];
+  }
+}
+
+template <int RECON>
+__global__ void __launch_bounds__(BLOCK) k_adj_gather(Dev g, Box b1, Box b2, Box b3,
+                                                      const double* __restrict__ LS1,
+                                                      const double* __restrict__ LS2,
+                                                      const double* __restrict__ LS3,
+                                                      double* __restrict__ LPh) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= g.nz) return;
+  int i = (int)(t % g.s1) - NG;
+  long r = t / g.s1;
+  int j = (int)(r % g.s2) - NG, k = (int)(r / g.s2) - NG;
+  double acc[NVAR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  gather_dir<RECON>(g, b1, LS1, 1, i, j, k, acc);
+  gather_dir<RECON>(g, b2, LS2, 2, i, j, k, acc);
+  gather_dir<RECON>(g, b3, LS3, 3, i, j, k, acc);
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) LPh[v * g.nz + t] = acc[v];
+}
+
+// Padded positions along one axis whose ghost fill copies interior x (x
+// itself included), with the polar sign.
+__device__ __forceinline__ int bc_preimages(int x, int n, int bclo, int bchi, int ys[7], bool fl[7]) {
+  int cnt = 0;
+  ys[cnt] = x;
+  fl[cnt++] = false;
+  for (int y = -NG; y < 0; y++) {
+    bool f = false;
+    if (bclo == GRMHD_BC_FROZEN) continue;
+    if (bc_map(y, n, bclo, bchi, f) == x) { ys[cnt] = y; fl[cnt++] = f; }
+  }
+  for (int y = n; y < n + NG; y++) {
+    bool f = false;
+    if (bchi == GRMHD_BC_FROZEN) continue;
+    if (bc_map(y, n, bclo, bchi, f) == x) { ys[cnt] = y; fl[cnt++] = f; }
+  }
+  return cnt;
+}
+
+// Per interior zone: the ghost-fill transpose of the gathered stencil
+// adjoint, plus the local terms: source^T lambda_L, (stage 1) U^T lambda_U0,
+// and the guess adjoint of a failed inversion.  Gamma parts go to GZ.
+template <bool STAGE1>
+__global__ void __launch_bounds__(BLOCK) k_adj_zone(Dev g, Box box, const double* __restrict__ Pin,
+                                                    const double* __restrict__ tabC,
+                                                    const double* __restrict__ conn,
+                                                    const double* __restrict__ LPh,
+                                                    const double* __restrict__ LL,
+                                                    const double* __restrict__ LU0,
+                                                    const double* __restrict__ LG,
+                                                    double* __restrict__ LP, double* __restrict__ GZ) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  const long c = zid(g, i, j, k), nz = g.nz;
+  double acc[NVAR];
+  int y1[7], y2[7], y3[7];
+  bool f1[7], f2[7], f3[7];
+  int n1 = bc_preimages(i, g.n1, g.bc[0], g.bc[1], y1, f1);
+  int n2 = bc_preimages(j, g.n2, g.bc[2], g.bc[3], y2, f2);
+  int n3 = bc_preimages(k, g.n3, g.bc[4], g.bc[5], y3, f3);
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) acc[v] = 0.0;
+  for (int a = 0; a < n1; a++)
+    for (int b = 0; b < n2; b++)
+      for (int e = 0; e < n3; e++) {
+        long q = zid(g, y1[a], y2[b], y3[e]);
+        bool flip = f1[a] ^ f2[b] ^ f3[e];
+#pragma unroll
+        for (int v = 0; v < NVAR; v++) {
+          double x = LPh[v * nz + q];
+          acc[v] += (flip && (v == U2 || v == B2)) ? -x : x;
+        }
+      }
+  // local Jacobians of the source (and the conserved variables) by seeds
+  PointMetric<Dual> m;
+  load_metric_dual(tabC, g.plane, pid(g, i, j), m);
+  double cn[40];
+  load_conn(conn, g.plane, pid(g, i, j), cn);
+  double lL[NVAR], lU[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    lL[v] = LL[v * nz + c];
+    lU[v] = STAGE1 ? LU0[v * nz + c] : 0.0;
+  }
+  double gz = 0.0;
+  for (int sd = 0; sd <= NVAR; sd++) {
+    Dual p[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) p[v] = Dual(Pin[v * nz + c], sd == v ? 1.0 : 0.0);
+    Dual gam(g.gam, sd == NVAR ? 1.0 : 0.0);
+    Fluid<Dual> f;
+    fluid_state(p, m, f);
+    double d = 0.0;
+    // source: sqrt(-g) T^k_l Gamma^l_{nu k}
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) {
+      Dual sacc(0.0);
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) {
+        Dual T[4];
+        tmunu_row(p, f, gam, kk, T);
+#pragma unroll
+        for (int l = 0; l < 4; l++) sacc = sacc + T[l] * Dual(cn[l * 10 + sidx(nu, kk)]);
+      }
+      d += (m.gdet * sacc).d * lL[UU + nu];
+    }
+    if (STAGE1) {
+      Dual U[NVAR];
+      prim_to_flux(p, f, m, gam, 0, U);
+#pragma unroll
+      for (int v = 0; v < NVAR; v++) d += U[v].d * lU[v];
+    }
+    if (sd < NVAR)
+      acc[sd] += d;
+    else
+      gz = d;
+  }
+#pragma unroll
+  for (int v = 0; v < 5; v++) acc[v] += LG[v * nz + c];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) LP[v * nz + c] = acc[v];
+  GZ[c] += gz;
+}
+
+// Implicit-function adjoint of the inversion at the recovered prims P:
+// lambda_U = (dU/dP)^-T lambda_P, and -lambda_U . dU/dgamma into GZ.  A zone
+// whose inversion failed kept its guess's hydro prims: lambda goes to the
+// guess (LG) and only B^i = U_B^i / sqrt(-g) carries lambda to U.
+// Ghost entries of LU and LG are zero.
+__global__ void __launch_bounds__(BLOCK) k_adj_ift(Dev g, const double* __restrict__ P,
+                                                   const unsigned char* __restrict__ flags,
+                                                   const double* __restrict__ tabC,
+                                                   const double* __restrict__ LP,
+                                                   double* __restrict__ LU, double* __restrict__ LG,
+                                                   double* __restrict__ GZ) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= g.nz) return;
+  const long nz = g.nz;
+  int i = (int)(t % g.s1) - NG;
+  long r = t / g.s1;
+  int j = (int)(r % g.s2) - NG, k = (int)(r / g.s2) - NG;
+  if (i < 0 || j < 0 || k < 0 || i >= g.n1 || j >= g.n2 || k >= g.n3) {
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) LU[v * nz + t] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; v++) LG[v * nz + t] = 0.0;
+    return;
+  }
+  double lp[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) lp[v] = LP[v * nz + t];
+  PointMetric<Dual> m;
+  load_metric_dual(tabC, g.plane, pid(g, i, j), m);
+  if (flags[t]) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      LG[v * nz + t] = lp[v];
+      LU[v * nz + t] = 0.0;
+    }
+#pragma unroll
+    for (int v = 5; v < NVAR; v++) LU[v * nz + t] = lp[v] / m.gdet.v;
+    return;
+  }
+  // J[a][b] = dU_a / dP_b; column NVAR: dU/dgamma
+  double J[NVAR][NVAR + 1];
+  for (int sd = 0; sd <= NVAR; sd++) {
+    Dual p[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) p[v] = Dual(P[v * nz + t], sd == v ? 1.0 : 0.0);
+    Dual gam(g.gam, sd == NVAR ? 1.0 : 0.0);
+    Fluid<Dual> f;
+    fluid_state(p, m, f);
+    Dual U[NVAR];
+    prim_to_flux(p, f, m, gam, 0, U);
+#pragma unroll
+    for (int a = 0; a < NVAR; a++) J[a][sd] = U[a].d;
+  }
+  // solve J^T x = lp: Gaussian elimination with partial pivoting on A = J^T
+  double A[NVAR][NVAR], x[NVAR];
+#pragma unroll
+  for (int a = 0; a < NVAR; a++) {
+#pragma unroll
+    for (int b = 0; b < NVAR; b++) A[a][b] = J[b][a];
+    x[a] = lp[a];
+  }
+  for (int col = 0; col < NVAR; col++) {
+    int piv = col;
+    double best = fabs(A[col][col]);
+    for (int rr = col + 1; rr < NVAR; rr++)
+      if (fabs(A[rr][col]) > best) { best = fabs(A[rr][col]); piv = rr; }
+    if (piv != col) {
+      for (int b = 0; b < NVAR; b++) { double tmp = A[col][b]; A[col][b] = A[piv][b]; A[piv][b] = tmp; }
+      double tmp = x[col]; x[col] = x[piv]; x[piv] = tmp;
+    }
+    for (int rr = col + 1; rr < NVAR; rr++) {
+      double fct = A[rr][col] / A[col][col];
+      for (int b = col; b < NVAR; b++) A[rr][b] -= fct * A[col][b];
+      x[rr] -= fct * x[col];
+    }
+  }
+  for (int rr = NVAR - 1; rr >= 0; rr--) {
+    double s = x[rr];
+    for (int b = rr + 1; b < NVAR; b++) s -= A[rr][b] * x[b];
+    x[rr] = s / A[rr][rr];
+  }
+  double gz = 0.0;
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    LU[v * nz + t] = x[v];
+    gz -= x[v] * J[v][NVAR];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; v++) LG[v * nz + t] = 0.0;
+  GZ[t] += gz;
+}
+
+// Elementwise combinations of the reverse RK sweep over all padded zones.
+// mode 0 (after the stage-2 inversion): LV = LU, LL = (dt/2) LU.
+// mode 1 (after the stage-1 inversion): LU1 = LU + LV/2, LU0 = LV/2 + LU1,
+//         LL = dt LU1 (LU0 written into LV).
+__global__ void __launch_bounds__(BLOCK) k_adj_rk(long n, int mode, double dt, double* __restrict__ LU,
+                                                  double* __restrict__ LV, double* __restrict__ LL) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (mode == 0) {
+    LV[t] = LU[t];
+    LL[t] = 0.5 * dt * LU[t];
+  } else {
+    double lu1 = LU[t] + 0.5 * LV[t];
+    double lu0 = 0.5 * LV[t] + lu1;
+    LV[t] = lu0;
+    LL[t] = dt * lu1;
+  }
+}
+
+// Sum of the gamma parts: per-block partial sums of GZ + GF1 + GF2 + GF3.
+__global__ void __launch_bounds__(BLOCK) k_adj_gsum(long nz, const double* __restrict__ GZ,
+                                                    const double* __restrict__ GF1,
+                                                    const double* __restrict__ GF2,
+                                                    const double* __restrict__ GF3, double* pmax,
+                                                    double* psum) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (t < nz) s = ((GZ[t] + GF1[t]) + GF2[t]) + GF3[t];
+  double mx = 0.0;
+  block_reduce(mx, s);
+  if (threadIdx.x == 0) {
+    pmax[blockIdx.x] = 0.0;
+    psum[blockIdx.x] = s;
+  }
+}

@@ -1,0 +1,45 @@
+// Forward-mode dual number (value and one directional derivative) used to
+// form the local Jacobians of the per-point physics in the hand-written
+// adjoint.  Comparisons act on the value, so min/max and limiter branches
+// select the derivative of the branch taken (a subgradient at ties).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace grmhd {
+namespace ad {
+
+struct Dual {
+  double v, d;
+  __device__ Dual() : v(0.0), d(0.0) {}
+  __device__ Dual(double x) : v(x), d(0.0) {}
+  __device__ Dual(double x, double dx) : v(x), d(dx) {}
+};
+
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+__device__ __forceinline__ Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+__device__ __forceinline__ Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
+__device__ __forceinline__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
+__device__ __forceinline__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
+__device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+__device__ __forceinline__ bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+__device__ __forceinline__ Dual sqrt(Dual a) {
+  double s = ::sqrt(a.v);
+  return Dual(s, s > 0.0 ? 0.5 * a.d / s : 0.0);
+}
+__device__ __forceinline__ Dual fabs(Dual a) { return a.v < 0.0 ? -a : a; }
+__device__ __forceinline__ Dual fmin(Dual a, Dual b) { return b.v < a.v ? b : a; }
+__device__ __forceinline__ Dual fmax(Dual a, Dual b) { return b.v > a.v ? b : a; }
+
+}  // namespace ad
+using ad::Dual;
+}  // namespace grmhd

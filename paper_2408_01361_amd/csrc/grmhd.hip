@@ -13,9 +13,11 @@
 // with every intermediate resident in the caller's HBM workspace.  Layouts
 // are variable-major and x1-fastest, so each wavefront's loads and stores of
 // one variable are contiguous.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <vector>
 #include <new>
 #include <stdint.h>
 #include <stdlib.h>
@@ -77,6 +79,46 @@ inline Box make_box(int lo1, int hi1, int lo2, int hi2, int lo3, int hi3) {
 }
 
 inline unsigned blocks_for(long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+// Scheduled enumeration of a box for the heavy kernels.  A workgroup covers
+// BLOCK consecutive (x1, x2) positions of one x3 plane.  Workgroups are
+// dispatched round-robin over the 8 XCDs, so workgroup b is renumbered to
+// give each XCD one contiguous range of work; within it kg consecutive x3
+// planes of the same (x1, x2) chunk follow each other, so that chunk's 2-D
+// geometry and the x3 stencil stay in that XCD's L2.  Any kg >= 1 covers the
+// box exactly once.
+struct Sched {
+  Box b;
+  int kg;       // x3 planes per chunk run
+  int nchunk;   // workgroups per plane
+  int kgroups;  // ceil(n3 / kg)
+};
+inline Sched make_sched(const Box& b, int kg) {
+  if (kg < 1) kg = 1;
+  if (kg > b.n3) kg = b.n3;
+  long nij = (long)b.n1 * b.n2;
+  return Sched{b, kg, (int)((nij + BLOCK - 1) / BLOCK), (b.n3 + kg - 1) / kg};
+}
+inline unsigned blocks_for(const Sched& s) { return (unsigned)((long)s.nchunk * s.kgroups * s.kg); }
+
+__device__ __forceinline__ bool sched_index(const Sched& s, int& i, int& j, int& k) {
+  const unsigned nb = gridDim.x, bid = blockIdx.x;
+  const unsigned x = bid & 7u, slot = bid >> 3;
+  const unsigned q = nb >> 3, r = nb & 7u;
+  const unsigned w = x * q + (x < r ? x : r) + slot;
+  const int kin = (int)(w % (unsigned)s.kg);
+  const unsigned rest = w / (unsigned)s.kg;
+  const int chunk = (int)(rest % (unsigned)s.nchunk);
+  const int kgrp = (int)(rest / (unsigned)s.nchunk);
+  const int kk = kgrp * s.kg + kin;
+  const int ij = chunk * BLOCK + (int)threadIdx.x;
+  if (kk >= s.b.n3 || ij >= s.b.n1 * s.b.n2) return false;
+  const int jj = ij / s.b.n1;
+  i = s.b.lo1 + (ij - jj * s.b.n1);
+  j = s.b.lo2 + jj;
+  k = s.b.lo3 + kk;
+  return true;
+}
 
 // ------------------------------------------------------------- geometry --
 
@@ -188,11 +230,9 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ P, long nz
 // Local Lax-Friedrichs flux through the lower d-face of zone (i, j, k) for
 // every face of `box`; pole faces get zero flux.  FT is the stored type.
 template <int D, int RECON, typename R, typename FT>
-__global__ void __launch_bounds__(BLOCK) k_flux(Dev g, Box box, const double* __restrict__ P,
-                                                const double* __restrict__ tab, FT* __restrict__ F) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (!box_index(box, t, i, j, k)) return;
+__device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict__ P,
+                                          const double* __restrict__ tab, FT* __restrict__ F, int i,
+                                          int j, int k) {
   long c = zid(g, i, j, k);
   if (D == 2 && ((g.pole_lo && j == 0) || (g.pole_hi && j == g.n2))) {
 #pragma unroll
@@ -228,19 +268,23 @@ __global__ void __launch_bounds__(BLOCK) k_flux(Dev g, Box box, const double* __
     F[v * g.nz + c] = (FT)llf(FL[v], FR[v], UL[v], UR[v], cmax);
 }
 
+template <int D, int RECON, typename R, typename FT>
+__global__ void __launch_bounds__(BLOCK) k_flux(Dev g, Sched box, const double* __restrict__ P,
+                                                const double* __restrict__ tab, FT* __restrict__ F) {
+  int i, j, k;
+  if (!sched_index(box, i, j, k)) return;
+  flux_face<D, RECON, R, FT>(g, P, tab, F, i, j, k);
+}
+
 // Flux-CT edge EMFs at the lower (x1, x2, x3) corner of zone (i, j, k):
 //   E3 = [F1(B2) + F1(B2)_{j-1} - F2(B1) - F2(B1)_{i-1}]/4
 //   E2 = [F3(B1) + F3(B1)_{i-1} - F1(B3) - F1(B3)_{k-1}]/4
 //   E1 = [F2(B3) + F2(B3)_{k-1} - F3(B2) - F3(B2)_{j-1}]/4
 // E1 and E3 vanish on polar edges (sqrt(-g) = 0 there).
 template <typename FT>
-__global__ void __launch_bounds__(BLOCK) k_emf(Dev g, Box box, const FT* __restrict__ F1,
-                                               const FT* __restrict__ F2, const FT* __restrict__ F3,
-                                               FT* __restrict__ E1, FT* __restrict__ E2,
-                                               FT* __restrict__ E3) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (!box_index(box, t, i, j, k)) return;
+__device__ __forceinline__ void emf_edge(const Dev& g, const FT* __restrict__ F1, const FT* __restrict__ F2,
+                                         const FT* __restrict__ F3, FT* __restrict__ E1,
+                                         FT* __restrict__ E2, FT* __restrict__ E3, int i, int j, int k) {
   long c = zid(g, i, j, k);
   const long nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
   bool pole = (g.pole_lo && j == 0) || (g.pole_hi && j == g.n2);
@@ -251,6 +295,16 @@ __global__ void __launch_bounds__(BLOCK) k_emf(Dev g, Box box, const FT* __restr
   E1[c] = pole ? (FT)0 : e1;
   E2[c] = e2;
   E3[c] = pole ? (FT)0 : e3;
+}
+
+template <typename FT>
+__global__ void __launch_bounds__(BLOCK) k_emf(Dev g, Sched box, const FT* __restrict__ F1,
+                                               const FT* __restrict__ F2, const FT* __restrict__ F3,
+                                               FT* __restrict__ E1, FT* __restrict__ E2,
+                                               FT* __restrict__ E3) {
+  int i, j, k;
+  if (!sched_index(box, i, j, k)) return;
+  emf_edge<FT>(g, F1, F2, F3, E1, E2, E3, i, j, k);
 }
 
 // Rebuild the B components of interior-face fluxes from the EMFs (as the
@@ -420,19 +474,17 @@ __device__ __forceinline__ void geometric_source(const double p[NVAR], const Flu
 // Un = U(Pin), U1 = Un + dt L(Pin); STAGE 2: U = V + dt L(Pin)/2.  Then
 // Pout = U_to_P(U; guess Pin).  B fluxes come from the edge EMFs.
 template <int STAGE, typename FT>
-__global__ void __launch_bounds__(BLOCK) k_update(Dev g, Box box, const double* __restrict__ Pin,
-                                                  double* __restrict__ Pout, double* __restrict__ V,
-                                                  const FT* __restrict__ F1, const FT* __restrict__ F2,
-                                                  const FT* __restrict__ F3, const FT* __restrict__ E1,
-                                                  const FT* __restrict__ E2, const FT* __restrict__ E3,
-                                                  const double* __restrict__ tabC,
-                                                  const double* __restrict__ conn, double dt,
-                                                  unsigned long long* fails) {
+__device__ __forceinline__ void update_zone(const Dev& g, const double* __restrict__ Pin,
+                                            double* __restrict__ Pout, double* __restrict__ V,
+                                            const FT* __restrict__ F1, const FT* __restrict__ F2,
+                                            const FT* __restrict__ F3, const FT* __restrict__ E1,
+                                            const FT* __restrict__ E2, const FT* __restrict__ E3,
+                                            const double* __restrict__ tabC,
+                                            const double* __restrict__ conn, double dt,
+                                            unsigned long long* fails, unsigned char* __restrict__ flags,
+                                            int i, int j, int k) {
   // the FP64 update is rounded operation by operation, in the order written
 #pragma clang fp contract(off)
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (!box_index(box, t, i, j, k)) return;
   const long c = zid(g, i, j, k), nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
   const long q2 = pid(g, i, j);
   double p[NVAR];
@@ -488,7 +540,23 @@ __global__ void __launch_bounds__(BLOCK) k_update(Dev g, Box box, const double* 
   int bad = invert_1dw(g, m, U, p, out);
 #pragma unroll
   for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
+  if (flags) flags[c] = (unsigned char)bad;
   if (bad) atomicAdd(fails, 1ull);
+}
+
+template <int STAGE, typename FT>
+__global__ void __launch_bounds__(BLOCK) k_update(Dev g, Sched box, const double* __restrict__ Pin,
+                                                  double* __restrict__ Pout, double* __restrict__ V,
+                                                  const FT* __restrict__ F1, const FT* __restrict__ F2,
+                                                  const FT* __restrict__ F3, const FT* __restrict__ E1,
+                                                  const FT* __restrict__ E2, const FT* __restrict__ E3,
+                                                  const double* __restrict__ tabC,
+                                                  const double* __restrict__ conn, double dt,
+                                                  unsigned long long* fails,
+                                                  unsigned char* __restrict__ flags) {
+  int i, j, k;
+  if (!sched_index(box, i, j, k)) return;
+  update_zone<STAGE, FT>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i, j, k);
 }
 
 // ------------------------------------------------------- reductions etc. --
@@ -656,6 +724,9 @@ __global__ void __launch_bounds__(BLOCK) k_cons_to_prims(Dev g, Box box, const d
   if (bad) atomicAdd(fails, 1ull);
 }
 
+#include "adjoint.hpp"
+#include "pack.hpp"
+
 }  // namespace
 
 // ------------------------------------------------------------- host side --
@@ -672,6 +743,8 @@ struct grmhd_ctx {
   double *tabC, *tabF1, *tabF2, *corner, *conn;
   double *pmax, *psum, *result;
   unsigned long long* fails;
+  // x3 planes per chunk run of the flux/EMF and update schedules
+  int kg_flux = 8, kg_update = 8;
   // optional per-kernel-class timing with HIP events on the context's stream
   bool timing = false;
   struct Mark { hipEvent_t a, b; int cls; };
@@ -769,10 +842,10 @@ struct Timed {
     }
     slot = c->nmarks++;
     c->marks[slot].cls = cls;
-    hipEventRecord(c->marks[slot].a, c->stream);
+    (void)hipEventRecord(c->marks[slot].a, c->stream);
   }
   ~Timed() {
-    if (slot >= 0) hipEventRecord(c->marks[slot].b, c->stream);
+    if (slot >= 0) (void)hipEventRecord(c->marks[slot].b, c->stream);
   }
 };
 
@@ -789,33 +862,35 @@ int stage_fluxes(grmhd_ctx* c, const double* P) {
   FT* F1 = (FT*)c->F[0];
   FT* F2 = (FT*)c->F[1];
   FT* F3 = (FT*)c->F[2];
-  Box b1 = make_box(0, g.n1, -1, g.n2, -1, g.n3);
-  Box b2 = make_box(-1, g.n1, 0, g.n2, -1, g.n3);
-  Box b3 = make_box(-1, g.n1, -1, g.n2, 0, g.n3);
+  Sched b1 = make_sched(make_box(0, g.n1, -1, g.n2, -1, g.n3), c->kg_flux);
+  Sched b2 = make_sched(make_box(-1, g.n1, 0, g.n2, -1, g.n3), c->kg_flux);
+  Sched b3 = make_sched(make_box(-1, g.n1, -1, g.n2, 0, g.n3), c->kg_flux);
   if (c->params.recon == GRMHD_RECON_MC) {
-    { Timed tm(c, T_FLUX1); k_flux<1, GRMHD_RECON_MC, R, FT><<<blocks_for(b1.count()), BLOCK, 0, c->stream>>>(g, b1, P, c->tabF1, F1); }
-    { Timed tm(c, T_FLUX2); k_flux<2, GRMHD_RECON_MC, R, FT><<<blocks_for(b2.count()), BLOCK, 0, c->stream>>>(g, b2, P, c->tabF2, F2); }
-    { Timed tm(c, T_FLUX3); k_flux<3, GRMHD_RECON_MC, R, FT><<<blocks_for(b3.count()), BLOCK, 0, c->stream>>>(g, b3, P, c->tabC, F3); }
+    { Timed tm(c, T_FLUX1); k_flux<1, GRMHD_RECON_MC, R, FT><<<blocks_for(b1), BLOCK, 0, c->stream>>>(g, b1, P, c->tabF1, F1); }
+    { Timed tm(c, T_FLUX2); k_flux<2, GRMHD_RECON_MC, R, FT><<<blocks_for(b2), BLOCK, 0, c->stream>>>(g, b2, P, c->tabF2, F2); }
+    { Timed tm(c, T_FLUX3); k_flux<3, GRMHD_RECON_MC, R, FT><<<blocks_for(b3), BLOCK, 0, c->stream>>>(g, b3, P, c->tabC, F3); }
   } else {
-    { Timed tm(c, T_FLUX1); k_flux<1, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b1.count()), BLOCK, 0, c->stream>>>(g, b1, P, c->tabF1, F1); }
-    { Timed tm(c, T_FLUX2); k_flux<2, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b2.count()), BLOCK, 0, c->stream>>>(g, b2, P, c->tabF2, F2); }
-    { Timed tm(c, T_FLUX3); k_flux<3, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b3.count()), BLOCK, 0, c->stream>>>(g, b3, P, c->tabC, F3); }
+    { Timed tm(c, T_FLUX1); k_flux<1, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b1), BLOCK, 0, c->stream>>>(g, b1, P, c->tabF1, F1); }
+    { Timed tm(c, T_FLUX2); k_flux<2, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b2), BLOCK, 0, c->stream>>>(g, b2, P, c->tabF2, F2); }
+    { Timed tm(c, T_FLUX3); k_flux<3, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b3), BLOCK, 0, c->stream>>>(g, b3, P, c->tabC, F3); }
   }
-  Box be = make_box(0, g.n1, 0, g.n2, 0, g.n3);
+  Sched be = make_sched(make_box(0, g.n1, 0, g.n2, 0, g.n3), c->kg_flux);
   Timed tm(c, T_EMF);
-  k_emf<FT><<<blocks_for(be.count()), BLOCK, 0, c->stream>>>(g, be, F1, F2, F3, (FT*)c->E[0],
+  k_emf<FT><<<blocks_for(be), BLOCK, 0, c->stream>>>(g, be, F1, F2, F3, (FT*)c->E[0],
                                                                 (FT*)c->E[1], (FT*)c->E[2]);
   return hip_check();
 }
 
 template <int STAGE, typename FT>
-int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt) {
+int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
+                 unsigned long long* fails = nullptr, unsigned char* flags = nullptr) {
   const Dev& g = c->dev;
-  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
   Timed tm(c, STAGE == 1 ? T_UPDATE1 : T_UPDATE2);
-  k_update<STAGE, FT><<<blocks_for(bz.count()), BLOCK, 0, c->stream>>>(
+  k_update<STAGE, FT><<<blocks_for(bz), BLOCK, 0, c->stream>>>(
       g, bz, Pin, Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1], (const FT*)c->F[2],
-      (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2], c->tabC, c->conn, dt, c->fails);
+      (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2], c->tabC, c->conn, dt,
+      fails ? fails : c->fails, flags);
   return hip_check();
 }
 
@@ -1040,6 +1115,142 @@ const char* grmhd_strerror(int code) {
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+struct VjpCarve {
+  double *A, *B, *C, *LU, *LV, *LL, *LP, *LPh, *LG, *LE[3], *LS[3], *GZ, *GF[3];
+  unsigned char *fl1, *fl2;
+  unsigned long long* fails;
+};
+
+size_t vjp_carve(const grmhd_grid* g, int recon, char* base, VjpCarve* out) {
+  long nz = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * (g->n3 + 2 * NG);
+  int W = recon == GRMHD_RECON_MC ? Stencil<GRMHD_RECON_MC>::W : Stencil<GRMHD_RECON_WENO5>::W;
+  Carve cv;
+  VjpCarve v;
+  v.A = cv.take<double>(base, NVAR * nz);
+  v.B = cv.take<double>(base, NVAR * nz);
+  v.C = cv.take<double>(base, NVAR * nz);
+  v.LU = cv.take<double>(base, NVAR * nz);
+  v.LV = cv.take<double>(base, NVAR * nz);
+  v.LL = cv.take<double>(base, NVAR * nz);
+  v.LP = cv.take<double>(base, NVAR * nz);
+  v.LPh = cv.take<double>(base, NVAR * nz);
+  v.LG = cv.take<double>(base, 5 * nz);
+  for (int d = 0; d < 3; d++) v.LE[d] = cv.take<double>(base, nz);
+  for (int d = 0; d < 3; d++) v.LS[d] = cv.take<double>(base, (long)NVAR * W * nz);
+  v.GZ = cv.take<double>(base, nz);
+  for (int d = 0; d < 3; d++) v.GF[d] = cv.take<double>(base, nz);
+  v.fl1 = cv.take<unsigned char>(base, nz);
+  v.fl2 = cv.take<unsigned char>(base, nz);
+  v.fails = cv.take<unsigned long long>(base, 8);
+  if (out) *out = v;
+  return cv.off;
+}
+
+template <int RECON>
+int adj_stage(grmhd_ctx* c, const VjpCarve& w, const double* Pin, bool stage1, double* LPout) {
+  const Dev& g = c->dev;
+  const long nz = g.nz;
+  k_adj_emf<<<blocks_for(nz), BLOCK, 0, c->stream>>>(g, w.LL, w.LE[0], w.LE[1], w.LE[2]);
+  Box b1 = make_box(0, g.n1, -1, g.n2, -1, g.n3);
+  Box b2 = make_box(-1, g.n1, 0, g.n2, -1, g.n3);
+  Box b3 = make_box(-1, g.n1, -1, g.n2, 0, g.n3);
+  k_adj_face<1, RECON><<<blocks_for(b1.count()), BLOCK, 0, c->stream>>>(g, b1, Pin, c->tabF1, w.LL, w.LE[0],
+                                                                      w.LE[1], w.LE[2], w.LS[0], w.GF[0]);
+  k_adj_face<2, RECON><<<blocks_for(b2.count()), BLOCK, 0, c->stream>>>(g, b2, Pin, c->tabF2, w.LL, w.LE[0],
+                                                                      w.LE[1], w.LE[2], w.LS[1], w.GF[1]);
+  k_adj_face<3, RECON><<<blocks_for(b3.count()), BLOCK, 0, c->stream>>>(g, b3, Pin, c->tabC, w.LL, w.LE[0],
+                                                                      w.LE[1], w.LE[2], w.LS[2], w.GF[2]);
+  k_adj_gather<RECON><<<blocks_for(nz), BLOCK, 0, c->stream>>>(g, b1, b2, b3, w.LS[0], w.LS[1], w.LS[2],
+                                                               w.LPh);
+  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  if (stage1)
+    k_adj_zone<true><<<blocks_for(bz.count()), BLOCK, 0, c->stream>>>(g, bz, Pin, c->tabC, c->conn, w.LPh,
+                                                                      w.LL, w.LV, w.LG, LPout, w.GZ);
+  else
+    k_adj_zone<false><<<blocks_for(bz.count()), BLOCK, 0, c->stream>>>(g, bz, Pin, c->tabC, c->conn, w.LPh,
+                                                                       w.LL, nullptr, w.LG, LPout, w.GZ);
+  return hip_check();
+}
+
+template <int RECON>
+int step_vjp(grmhd_ctx* c, const VjpCarve& w, const double* d_in, double dt, const double* d_gout,
+             double* d_gin, double* g_gamma) {
+  const Dev& g = c->dev;
+  const long nz = g.nz;
+  const size_t bytes = sizeof(double) * NVAR * nz;
+  int rc;
+  // forward recompute from the checkpoint: A = P^n, B = P^(1), C = P^(n+1)
+  if (hipMemcpyAsync(w.A, d_in, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(w.B, d_in, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(w.C, d_in, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipMemsetAsync(w.fl1, 0, nz, c->stream) != hipSuccess ||
+      hipMemsetAsync(w.fl2, 0, nz, c->stream) != hipSuccess ||
+      hipMemsetAsync(w.GZ, 0, sizeof(double) * nz, c->stream) != hipSuccess ||
+      hipMemsetAsync(d_gin, 0, bytes, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  for (int d = 0; d < 3; d++)
+    if (hipMemsetAsync(w.GF[d], 0, sizeof(double) * nz, c->stream) != hipSuccess) return GRMHD_E_HIP;
+  if ((rc = fill_ghosts(c, w.A))) return rc;
+  if ((rc = stage_fluxes<double, double>(c, w.A))) return rc;
+  if ((rc = stage_update<1, double>(c, w.A, w.B, dt, w.fails, w.fl1))) return rc;
+  if ((rc = fill_ghosts(c, w.B))) return rc;
+  if ((rc = stage_fluxes<double, double>(c, w.B))) return rc;
+  if ((rc = stage_update<2, double>(c, w.B, w.C, dt, w.fails, w.fl2))) return rc;
+  // reverse sweep
+  k_adj_ift<<<blocks_for(nz), BLOCK, 0, c->stream>>>(g, w.C, w.fl2, c->tabC, d_gout, w.LU, w.LG, w.GZ);
+  k_adj_rk<<<blocks_for(NVAR * nz), BLOCK, 0, c->stream>>>(NVAR * nz, 0, dt, w.LU, w.LV, w.LL);
+  if ((rc = hip_check())) return rc;
+  if ((rc = adj_stage<RECON>(c, w, w.B, false, w.LP))) return rc;
+  k_adj_ift<<<blocks_for(nz), BLOCK, 0, c->stream>>>(g, w.B, w.fl1, c->tabC, w.LP, w.LU, w.LG, w.GZ);
+  k_adj_rk<<<blocks_for(NVAR * nz), BLOCK, 0, c->stream>>>(NVAR * nz, 1, dt, w.LU, w.LV, w.LL);
+  if ((rc = hip_check())) return rc;
+  if ((rc = adj_stage<RECON>(c, w, w.A, true, d_gin))) return rc;
+  unsigned nb = blocks_for(nz);
+  if (nb > MAX_PARTIALS) return GRMHD_E_ARG;
+  k_adj_gsum<<<nb, BLOCK, 0, c->stream>>>(nz, w.GZ, w.GF[0], w.GF[1], w.GF[2], c->pmax, c->psum);
+  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, c->psum, (int)nb, c->result);
+  if ((rc = hip_check())) return rc;
+  double res[2];
+  if (hipMemcpyAsync(res, c->result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  if ((rc = sync(c))) return rc;
+  *g_gamma = res[1];
+  return GRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
+  if (!grid_ok(grid, params)) return 0;
+  return vjp_carve(grid, params->recon, nullptr, nullptr);
+}
+
+int grmhd_step_vjp(grmhd_ctx* c, const double* d_prims_in, double dt, const double* d_gprims_out,
+                   double* d_gprims_in, double* g_gamma, void* d_vjp_ws, size_t vjp_ws_bytes) {
+  if (!c || !d_prims_in || !d_gprims_out || !d_gprims_in || !g_gamma || !d_vjp_ws) return GRMHD_E_ARG;
+  if (!(dt > 0.0) || !isfinite(dt)) return GRMHD_E_ARG;
+  if (c->params.precision != GRMHD_PREC_FP64) return GRMHD_E_STATE;
+  if (((uintptr_t)d_vjp_ws & 255) != 0) return GRMHD_E_ARG;
+  if (vjp_ws_bytes < vjp_carve(&c->grid, c->params.recon, nullptr, nullptr)) return GRMHD_E_NOMEM;
+  VjpCarve w;
+  vjp_carve(&c->grid, c->params.recon, (char*)d_vjp_ws, &w);
+  if (c->params.recon == GRMHD_RECON_MC) return step_vjp<GRMHD_RECON_MC>(c, w, d_prims_in, dt, d_gprims_out, d_gprims_in, g_gamma);
+  return step_vjp<GRMHD_RECON_WENO5>(c, w, d_prims_in, dt, d_gprims_out, d_gprims_in, g_gamma);
+}
+
+int grmhd_set_schedule(grmhd_ctx* c, int kg_flux, int kg_update) {
+  if (!c || kg_flux < 1 || kg_update < 1) return GRMHD_E_ARG;
+  c->kg_flux = kg_flux;
+  c->kg_update = kg_update;
+  return GRMHD_OK;
+}
+
 int grmhd_timing(grmhd_ctx* c, int enable) {
   if (!c) return GRMHD_E_ARG;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return GRMHD_E_HIP;
@@ -1072,6 +1283,251 @@ int grmhd_destroy(grmhd_ctx* c) {
   }
   free(c->marks);
   delete c;
+  return GRMHD_OK;
+}
+
+
+// ---------------------------------------------------------------- packs --
+
+}  // extern "C"
+
+struct grmhd_pack {
+  grmhd_params params;
+  grmhd_metric metric;
+  hipStream_t stream;
+  int nb;
+  std::vector<BlockView> views;
+  std::vector<long> prim_off;  // offset (doubles) of each block in the packed prims
+  long prim_total;
+  BlockView* d_views;
+  int* d_pre;
+  unsigned* d_counters;
+  unsigned long long* d_fails;
+  int grid_blocks;
+};
+
+namespace {
+
+size_t pack_carve(int nb, const int* n, char* base, grmhd_pack* pk) {
+  Carve cv;
+  long prim_total = 0;
+  for (int b = 0; b < nb; b++) {
+    long s = n[b] + 2 * NG;
+    long nz = s * s * s, plane = s * s;
+    BlockView v;
+    memset(&v, 0, sizeof(v));
+    v.P = cv.take<double>(base, NVAR * nz);
+    v.P1 = cv.take<double>(base, NVAR * nz);
+    v.V = cv.take<double>(base, NVAR * nz);
+    for (int d = 0; d < 3; d++) v.F[d] = cv.take<double>(base, NVAR * nz);
+    for (int d = 0; d < 3; d++) v.E[d] = cv.take<double>(base, nz);
+    v.tabC = cv.take<double>(base, G_NF * plane);
+    v.tabF1 = cv.take<double>(base, G_NF * plane);
+    v.tabF2 = cv.take<double>(base, G_NF * plane);
+    v.corner = cv.take<double>(base, plane);
+    v.conn = cv.take<double>(base, NCONN * plane);
+    if (pk) {
+      pk->views.push_back(v);
+      pk->prim_off.push_back(prim_total);
+    }
+    prim_total += NVAR * nz;
+  }
+  BlockView* dv = cv.take<BlockView>(base, nb);
+  int* pre = cv.take<int>(base, PH_N * (nb + 1));
+  unsigned* cnt = cv.take<unsigned>(base, 64);
+  unsigned long long* fails = cv.take<unsigned long long>(base, 8);
+  if (pk) {
+    pk->d_views = dv;
+    pk->d_pre = pre;
+    pk->d_counters = cnt;
+    pk->d_fails = fails;
+    pk->prim_total = prim_total;
+  }
+  return cv.off;
+}
+
+int default_tile(int n, int& t1, int& t2, int& t3) {
+  if (n >= 64) { t1 = 64; t2 = 4; t3 = 1; }
+  else if (n >= 32) { t1 = 32; t2 = 8; t3 = 1; }
+  else { t1 = 16; t2 = 16; t3 = 1; }
+  return 0;
+}
+
+int pack_upload(grmhd_pack* pk) {
+  std::vector<int> pre(PH_N * (pk->nb + 1));
+  for (int ph = 0; ph < PH_N; ph++) {
+    int acc = 0;
+    for (int b = 0; b < pk->nb; b++) {
+      pre[ph * (pk->nb + 1) + b] = acc;
+      acc += block_items(pk->views[b], ph);
+    }
+    pre[ph * (pk->nb + 1) + pk->nb] = acc;
+  }
+  if (hipMemcpy(pk->d_views, pk->views.data(), sizeof(BlockView) * pk->nb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pk->d_pre, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return GRMHD_E_HIP;
+  return GRMHD_OK;
+}
+
+template <int RECON>
+int pack_launch(grmhd_pack* pk, int stage, double dt) {
+  if (hipMemsetAsync(pk->d_counters, 0, sizeof(unsigned) * PH_N, pk->stream) != hipSuccess) return GRMHD_E_HIP;
+  const BlockView* views = pk->d_views;
+  int nb = pk->nb;
+  const int* pre = pk->d_pre;
+  unsigned* cnt = pk->d_counters;
+  unsigned long long* fails = pk->d_fails;
+  void* args[] = {(void*)&views, (void*)&nb, (void*)&pre, (void*)&cnt, (void*)&dt, (void*)&fails};
+  const void* fn = stage == 1 ? (const void*)k_pack_stage<1, RECON> : (const void*)k_pack_stage<2, RECON>;
+  if (hipLaunchCooperativeKernel(fn, dim3(pk->grid_blocks), dim3(BLOCK), args, 0, pk->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  return hip_check();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t grmhd_pack_workspace_bytes(int nblocks, const int* n) {
+  if (nblocks < 1 || !n) return 0;
+  for (int b = 0; b < nblocks; b++)
+    if (n[b] < 1) return 0;
+  return pack_carve(nblocks, n, nullptr, nullptr);
+}
+
+int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* offsets_ijk,
+                      const grmhd_grid* global, const grmhd_metric* metric, const grmhd_params* params,
+                      void* d_ws, size_t ws_bytes, void* stream) {
+  if (!out || nblocks < 1 || !n || !offsets_ijk || !global || !metric || !params || !d_ws) return GRMHD_E_ARG;
+  if (!grid_ok(global, params) || params->precision != GRMHD_PREC_FP64) return GRMHD_E_ARG;
+  if (((uintptr_t)d_ws & 255) != 0) return GRMHD_E_ARG;
+  for (int b = 0; b < nblocks; b++) {
+    const int* o = offsets_ijk + 3 * b;
+    if (n[b] < 1 || o[0] < 0 || o[1] < 0 || o[2] < 0 || o[0] + n[b] > global->n1 || o[1] + n[b] > global->n2 ||
+        o[2] + n[b] > global->n3)
+      return GRMHD_E_ARG;
+  }
+  if (ws_bytes < pack_carve(nblocks, n, nullptr, nullptr)) return GRMHD_E_NOMEM;
+  grmhd_pack* pk = new (std::nothrow) grmhd_pack();
+  if (!pk) return GRMHD_E_NOMEM;
+  pk->params = *params;
+  pk->metric = *metric;
+  pk->stream = (hipStream_t)stream;
+  pk->nb = nblocks;
+  pack_carve(nblocks, n, (char*)d_ws, pk);
+  const double gd1 = (global->x1max - global->x1min) / global->n1;
+  const double gd2 = (global->x2max - global->x2min) / global->n2;
+  const double gd3 = (global->x3max - global->x3min) / global->n3;
+  bool kerr = metric->metric == GRMHD_METRIC_KERR_MKS;
+  for (int b = 0; b < nblocks; b++) {
+    const int* o = offsets_ijk + 3 * b;
+    Dev& g = pk->views[b].g;
+    g.n1 = g.n2 = g.n3 = n[b];
+    g.s1 = g.s2 = g.s3 = n[b] + 2 * NG;
+    g.nz = (long)g.s1 * g.s2 * g.s3;
+    g.plane = (long)g.s1 * g.s2;
+    double x1lo = global->x1min + o[0] * gd1, x2lo = global->x2min + o[1] * gd2;
+    double x1hi = global->x1min + (o[0] + n[b]) * gd1, x2hi = global->x2min + (o[1] + n[b]) * gd2;
+    double x3lo = global->x3min + o[2] * gd3, x3hi = global->x3min + (o[2] + n[b]) * gd3;
+    g.dx1 = (x1hi - x1lo) / n[b];
+    g.dx2 = (x2hi - x2lo) / n[b];
+    g.dx3 = (x3hi - x3lo) / n[b];
+    g.x1min = x1lo;
+    g.x2min = x2lo;
+    for (int a = 0; a < 6; a++) g.bc[a] = GRMHD_BC_FROZEN;
+    g.pole_lo = kerr && fabs(x2lo) < 1e-10;
+    g.pole_hi = kerr && fabs(x2hi - 1.0) < 1e-10;
+    g.gam = params->gamma_ad;
+    g.weno_eps = params->weno_eps;
+    g.tol = params->newton_tol;
+    g.maxit = params->newton_maxit;
+    g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
+    BlockView& v = pk->views[b];
+    default_tile(n[b], v.t1, v.t2, v.t3);
+    k_geometry<<<blocks_for(g.plane), BLOCK, 0, pk->stream>>>(g, v.tabC, v.tabF1, v.tabF2, v.corner, v.conn);
+  }
+  int per_cu = 0, ncu = 0, dev = 0;
+  const void* fn = params->recon == GRMHD_RECON_MC ? (const void*)k_pack_stage<1, GRMHD_RECON_MC>
+                                                   : (const void*)k_pack_stage<1, GRMHD_RECON_WENO5>;
+  if (hip_check() || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, 0) != hipSuccess || per_cu < 1 ||
+      hipMemsetAsync(pk->d_fails, 0, sizeof(unsigned long long), pk->stream) != hipSuccess ||
+      pack_upload(pk) != GRMHD_OK) {
+    delete pk;
+    return GRMHD_E_HIP;
+  }
+  pk->grid_blocks = per_cu * ncu;
+  *out = pk;
+  return GRMHD_OK;
+}
+
+int grmhd_pack_set_tiles(grmhd_pack* pk, int n, int t1, int t2, int t3) {
+  if (!pk || t1 < 1 || t2 < 1 || t3 < 1 || t1 * t2 * t3 > BLOCK) return GRMHD_E_ARG;
+  if (hipStreamSynchronize(pk->stream) != hipSuccess) return GRMHD_E_HIP;
+  for (int b = 0; b < pk->nb; b++)
+    if (pk->views[b].g.n1 == n) {
+      pk->views[b].t1 = t1;
+      pk->views[b].t2 = t2;
+      pk->views[b].t3 = t3;
+    }
+  return pack_upload(pk);
+}
+
+int grmhd_pack_load_prims(grmhd_pack* pk, const double* d_prims) {
+  if (!pk || !d_prims) return GRMHD_E_ARG;
+  for (int b = 0; b < pk->nb; b++) {
+    size_t bytes = sizeof(double) * NVAR * pk->views[b].g.nz;
+    const double* src = d_prims + pk->prim_off[b];
+    if (hipMemcpyAsync(pk->views[b].P, src, bytes, hipMemcpyDeviceToDevice, pk->stream) != hipSuccess ||
+        hipMemcpyAsync(pk->views[b].P1, src, bytes, hipMemcpyDeviceToDevice, pk->stream) != hipSuccess)
+      return GRMHD_E_HIP;
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_pack_step(grmhd_pack* pk, double dt) {
+  if (!pk || !(dt > 0.0) || !isfinite(dt)) return GRMHD_E_ARG;
+  int rc;
+  for (int stage = 1; stage <= 2; stage++) {
+    rc = pk->params.recon == GRMHD_RECON_MC ? pack_launch<GRMHD_RECON_MC>(pk, stage, dt)
+                                            : pack_launch<GRMHD_RECON_WENO5>(pk, stage, dt);
+    if (rc) return rc;
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_pack_get_prims(grmhd_pack* pk, double* d_out) {
+  if (!pk || !d_out) return GRMHD_E_ARG;
+  for (int b = 0; b < pk->nb; b++) {
+    size_t bytes = sizeof(double) * NVAR * pk->views[b].g.nz;
+    if (hipMemcpyAsync(d_out + pk->prim_off[b], pk->views[b].P, bytes, hipMemcpyDeviceToDevice, pk->stream) !=
+        hipSuccess)
+      return GRMHD_E_HIP;
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_pack_get_status(grmhd_pack* pk, long long* n_inv_fail) {
+  if (!pk || !n_inv_fail) return GRMHD_E_ARG;
+  unsigned long long f = 0;
+  if (hipMemcpyAsync(&f, pk->d_fails, sizeof(f), hipMemcpyDeviceToHost, pk->stream) != hipSuccess ||
+      hipStreamSynchronize(pk->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  *n_inv_fail = (long long)f;
+  return GRMHD_OK;
+}
+
+int grmhd_pack_info(grmhd_pack* pk, int* grid_blocks, long long* prim_doubles) {
+  if (!pk || !grid_blocks || !prim_doubles) return GRMHD_E_ARG;
+  *grid_blocks = pk->grid_blocks;
+  *prim_doubles = pk->prim_total;
+  return GRMHD_OK;
+}
+
+int grmhd_pack_destroy(grmhd_pack* pk) {
+  if (!pk) return GRMHD_E_ARG;
+  delete pk;
   return GRMHD_OK;
 }
 

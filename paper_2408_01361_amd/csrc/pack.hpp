@@ -1,0 +1,140 @@
+// Batched uneven meshblock packs: one persistent, cooperative launch per
+// RK2 stage advances every block of a pack.  The launch runs three phases
+// separated by grid-wide barriers -- face fluxes of every block along x1..x3,
+// edge EMFs, then the zone update with the inversion -- and within each phase
+// its workgroups take (block, tile) work items from an atomic counter, so
+// uneven block sizes balance dynamically.  Tile shapes (T1 x T2 x T3 = BLOCK
+// threads) are chosen per block size (an autotuner picks them); the per-face,
+// per-edge and per-zone work is the same device code as the single-block
+// kernels, so a block advanced in a pack matches the same block advanced
+// alone bit for bit.  Ghost zones are frozen (Dirichlet).
+//
+// Included inside the anonymous namespace of grmhd.hip.
+
+struct BlockView {
+  Dev g;
+  double *P, *P1, *V;
+  double *F[3], *E[3];
+  double *tabC, *tabF1, *tabF2, *corner, *conn;
+  int t1, t2, t3;  // tile shape
+  int pad;
+};
+
+enum { PH_FLUX = 0, PH_EMF = 1, PH_UPDATE = 2, PH_N = 3 };
+
+// Boxes of the three phases of a block (flux boxes per direction).
+__host__ __device__ inline Box phase_box(const Dev& g, int ph, int d) {
+  if (ph == PH_FLUX) {
+    if (d == 1) return Box{0, -1, -1, g.n1 + 1, g.n2 + 2, g.n3 + 2};
+    if (d == 2) return Box{-1, 0, -1, g.n1 + 2, g.n2 + 1, g.n3 + 2};
+    return Box{-1, -1, 0, g.n1 + 2, g.n2 + 2, g.n3 + 1};
+  }
+  if (ph == PH_EMF) return Box{0, 0, 0, g.n1 + 1, g.n2 + 1, g.n3 + 1};
+  return Box{0, 0, 0, g.n1, g.n2, g.n3};
+}
+
+__host__ __device__ inline int tiles_of(const Box& b, int t1, int t2, int t3) {
+  return ((b.n1 + t1 - 1) / t1) * ((b.n2 + t2 - 1) / t2) * ((b.n3 + t3 - 1) / t3);
+}
+
+// Work items of a block in a phase (the flux phase holds all three directions).
+__host__ __device__ inline int block_items(const BlockView& b, int ph) {
+  if (ph == PH_FLUX)
+    return tiles_of(phase_box(b.g, PH_FLUX, 1), b.t1, b.t2, b.t3) +
+           tiles_of(phase_box(b.g, PH_FLUX, 2), b.t1, b.t2, b.t3) +
+           tiles_of(phase_box(b.g, PH_FLUX, 3), b.t1, b.t2, b.t3);
+  return tiles_of(phase_box(b.g, ph, 0), b.t1, b.t2, b.t3);
+}
+
+// Position of this thread in tile `lt` of box b, if inside.
+__device__ __forceinline__ bool tile_pos(const Box& b, int t1, int t2, int t3, int lt, int& i, int& j,
+                                         int& k) {
+  int nt1 = (b.n1 + t1 - 1) / t1, nt2 = (b.n2 + t2 - 1) / t2;
+  int a = lt % nt1, rest = lt / nt1;
+  int bb = rest % nt2, cc = rest / nt2;
+  int th = threadIdx.x;
+  int x = th % t1, y = (th / t1) % t2, z = th / (t1 * t2);
+  int ii = a * t1 + x, jj = bb * t2 + y, kk = cc * t3 + z;
+  if (z >= t3 || ii >= b.n1 || jj >= b.n2 || kk >= b.n3) return false;
+  i = b.lo1 + ii;
+  j = b.lo2 + jj;
+  k = b.lo3 + kk;
+  return true;
+}
+
+template <int RECON>
+__device__ void pack_flux_item(const BlockView& b, const double* __restrict__ Pin, int lt) {
+  const Dev& g = b.g;
+  for (int d = 1; d <= 3; d++) {
+    Box bx = phase_box(g, PH_FLUX, d);
+    int nt = tiles_of(bx, b.t1, b.t2, b.t3);
+    if (lt >= nt) {
+      lt -= nt;
+      continue;
+    }
+    int i, j, k;
+    if (tile_pos(bx, b.t1, b.t2, b.t3, lt, i, j, k)) {
+      if (d == 1)
+        flux_face<1, RECON, double, double>(g, Pin, b.tabF1, b.F[0], i, j, k);
+      else if (d == 2)
+        flux_face<2, RECON, double, double>(g, Pin, b.tabF2, b.F[1], i, j, k);
+      else
+        flux_face<3, RECON, double, double>(g, Pin, b.tabC, b.F[2], i, j, k);
+    }
+    return;
+  }
+}
+
+// Block of a work item: the last block whose item offset is <= item.
+__device__ __forceinline__ int find_block(const int* __restrict__ pre, int nb, int item) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (pre[mid] <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// One RK2 stage of every block.  pre holds, per phase, nb + 1 item offsets
+// (the last is the phase's total); counters[ph] must be zero at launch.
+// Every workgroup leaves each phase's loop once the counter passes the total
+// and then meets every grid barrier, so the launch always drains.
+template <int STAGE, int RECON>
+__global__ void __launch_bounds__(BLOCK) k_pack_stage(const BlockView* __restrict__ bv, int nb,
+                                                      const int* __restrict__ pre,
+                                                      unsigned* counters, double dt,
+                                                      unsigned long long* fails) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ int s_item;
+  for (int ph = 0; ph < PH_N; ph++) {
+    const int* p = pre + ph * (nb + 1);
+    const int total = p[nb];
+    for (;;) {
+      if (threadIdx.x == 0) s_item = (int)atomicAdd(&counters[ph], 1u);
+      __syncthreads();
+      const int item = s_item;
+      __syncthreads();
+      if (item >= total) break;
+      const int blk = find_block(p, nb, item);
+      const BlockView& b = bv[blk];
+      const int lt = item - p[blk];
+      const double* Pin = STAGE == 1 ? b.P : b.P1;
+      if (ph == PH_FLUX) {
+        pack_flux_item<RECON>(b, Pin, lt);
+      } else if (ph == PH_EMF) {
+        int i, j, k;
+        if (tile_pos(phase_box(b.g, PH_EMF, 0), b.t1, b.t2, b.t3, lt, i, j, k))
+          emf_edge<double>(b.g, b.F[0], b.F[1], b.F[2], b.E[0], b.E[1], b.E[2], i, j, k);
+      } else {
+        int i, j, k;
+        if (tile_pos(phase_box(b.g, PH_UPDATE, 0), b.t1, b.t2, b.t3, lt, i, j, k))
+          update_zone<STAGE, double>(b.g, Pin, STAGE == 1 ? b.P1 : b.P, b.V, b.F[0], b.F[1], b.F[2],
+                                     b.E[0], b.E[1], b.E[2], b.tabC, b.conn, dt, fails, nullptr, i, j, k);
+      }
+    }
+    grid.sync();
+  }
+}

@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "dual.hpp"
+
 namespace grmhd {
 
 enum { RHO = 0, UU = 1, U1 = 2, U2 = 3, U3 = 4, B1 = 5, B2 = 6, B3 = 7, NVAR = 8 };
@@ -71,24 +73,39 @@ using R = float;
 #include "physics_body.inc"
 }  // namespace f32
 
+// Dual numbers: local Jacobians for the adjoint.
+namespace fdual {
+using R = Dual;
+#include "physics_body.inc"
+}  // namespace fdual
+
 using f64::lower4;
 using f32::lower4;
+using fdual::lower4;
 using f64::fluid_state;
 using f32::fluid_state;
+using fdual::fluid_state;
 using f64::tmunu_row;
 using f32::tmunu_row;
+using fdual::tmunu_row;
 using f64::prim_to_flux;
 using f32::prim_to_flux;
+using fdual::prim_to_flux;
 using f64::char_speeds;
 using f32::char_speeds;
+using fdual::char_speeds;
 using f64::mc_slope;
 using f32::mc_slope;
+using fdual::mc_slope;
 using f64::mc_left;
 using f32::mc_left;
+using fdual::mc_left;
 using f64::mc_right;
 using f32::mc_right;
+using fdual::mc_right;
 using f64::llf;
 using f32::llf;
+using fdual::llf;
 
 // WENO5 value at the right edge of zone c from point values a..e.  The three
 // nonlinear weights d_k/(eps + beta_k)^2 are formed over a common
@@ -134,6 +151,25 @@ __device__ __forceinline__ float weno5(float a, float b, float c, float d, float
   float w1 = 0.6f / (0.1f / (r01 * r01) + 0.6f + 0.3f * (r12 * r12));
   float w2 = 0.3f / (0.1f / (r02 * r02) + 0.6f / (r12 * r12) + 0.3f);
   return w0 * p0 + w1 * p1 + w2 * p2;
+}
+
+// Dual-number WENO5 in the same single-division form as the FP64 one.
+__device__ __forceinline__ Dual weno5(Dual a, Dual b, Dual c, Dual d, Dual e, Dual eps) {
+  const Dual k1312 = 13.0 / 12.0;
+  Dual p0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  Dual p1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  Dual p2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  Dual t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+  Dual t1 = b - 2.0 * c + d, u1 = b - d;
+  Dual t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+  Dual s0 = eps + (k1312 * t0 * t0 + 0.25 * u0 * u0);
+  Dual s1 = eps + (k1312 * t1 * t1 + 0.25 * u1 * u1);
+  Dual s2 = eps + (k1312 * t2 * t2 + 0.25 * u2 * u2);
+  s0 *= s0;
+  s1 *= s1;
+  s2 *= s2;
+  Dual w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
+  return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
 }
 
 }  // namespace grmhd

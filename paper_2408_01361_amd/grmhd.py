@@ -45,7 +45,10 @@ class grmhd_params(C.Structure):
 EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_step",
            "grmhd_estimate_dt", "grmhd_get_prims", "grmhd_divb", "grmhd_get_status",
            "grmhd_reset_status", "grmhd_prims_to_cons", "grmhd_cons_to_prims", "grmhd_fluxes",
-           "grmhd_timing", "grmhd_timing_report", "grmhd_strerror", "grmhd_destroy")
+           "grmhd_pack_workspace_bytes", "grmhd_pack_create", "grmhd_pack_set_tiles",
+           "grmhd_pack_load_prims", "grmhd_pack_step", "grmhd_pack_get_prims",
+           "grmhd_pack_get_status", "grmhd_pack_info", "grmhd_pack_destroy",
+           "grmhd_vjp_workspace_bytes", "grmhd_step_vjp", "grmhd_set_schedule", "grmhd_timing", "grmhd_timing_report", "grmhd_strerror", "grmhd_destroy")
 
 
 def load_library(path=LIB_PATH):
@@ -67,6 +70,19 @@ def load_library(path=LIB_PATH):
         "grmhd_prims_to_cons": (C.c_int, [vp, vp, vp]),
         "grmhd_cons_to_prims": (C.c_int, [vp, vp, vp, vp, vp, ip]),
         "grmhd_fluxes": (C.c_int, [vp, vp, vp]),
+        "grmhd_pack_workspace_bytes": (C.c_size_t, [C.c_int, C.POINTER(C.c_int)]),
+        "grmhd_pack_create": (C.c_int, [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                        G, M, P, vp, C.c_size_t, vp]),
+        "grmhd_pack_set_tiles": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int]),
+        "grmhd_pack_load_prims": (C.c_int, [vp, vp]),
+        "grmhd_pack_step": (C.c_int, [vp, C.c_double]),
+        "grmhd_pack_get_prims": (C.c_int, [vp, vp]),
+        "grmhd_pack_get_status": (C.c_int, [vp, ip]),
+        "grmhd_pack_info": (C.c_int, [vp, C.POINTER(C.c_int), ip]),
+        "grmhd_pack_destroy": (C.c_int, [vp]),
+        "grmhd_vjp_workspace_bytes": (C.c_size_t, [G, P]),
+        "grmhd_step_vjp": (C.c_int, [vp, vp, C.c_double, vp, vp, dp, vp, C.c_size_t]),
+        "grmhd_set_schedule": (C.c_int, [vp, C.c_int, C.c_int]),
         "grmhd_timing": (C.c_int, [vp, C.c_int]),
         "grmhd_timing_report": (C.c_int, [vp, dp, ip, C.c_int]),
         "grmhd_strerror": (C.c_char_p, [C.c_int]),
@@ -212,6 +228,27 @@ class Grmhd:
 
     TIMING_CLASSES = ("bc", "flux1", "flux2", "flux3", "emf", "update1", "update2", "dt")
 
+    def step_vjp(self, prims_in, dt, gprims_out):
+        """Adjoint of one step: (d loss/d prims_in, d loss/d gamma_ad)."""
+        L = lib()
+        if getattr(self, "_vjp_ws", None) is None:
+            nb = L.grmhd_vjp_workspace_bytes(C.byref(self.grid), C.byref(self.params))
+            if nb == 0:
+                raise GrmhdError("invalid grid or parameters")
+            self._vjp_ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            self._vjp_nb = nb
+        off = (-self._vjp_ws.data_ptr()) % 256
+        p = prims_in.to(device=self.device, dtype=torch.float64).contiguous()
+        go = gprims_out.to(device=self.device, dtype=torch.float64).contiguous()
+        gi = torch.empty_like(p)
+        gg = C.c_double()
+        _check(L.grmhd_step_vjp(self.ctx, _ptr(p), float(dt), _ptr(go), _ptr(gi), C.byref(gg),
+                                C.c_void_p(self._vjp_ws.data_ptr() + off), self._vjp_nb))
+        return gi, gg.value
+
+    def set_schedule(self, kg_flux, kg_update):
+        _check(lib().grmhd_set_schedule(self.ctx, int(kg_flux), int(kg_update)))
+
     def timing(self, enable=True):
         _check(lib().grmhd_timing(self.ctx, int(enable)))
 
@@ -221,3 +258,66 @@ class Grmhd:
         cnt = (C.c_longlong * n)()
         _check(lib().grmhd_timing_report(self.ctx, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.TIMING_CLASSES)}
+
+
+class Pack:
+    """A pack of cubic blocks (sub-boxes of one global grid) advanced together
+    by one persistent launch per RK2 stage."""
+
+    def __init__(self, global_spec, sizes, offsets, gamma_ad, recon=RECON_WENO5, cfl=0.9,
+                 weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda", stream=None):
+        L = lib()
+        self.nb = len(sizes)
+        self.sizes = [int(n) for n in sizes]
+        self._n = (C.c_int * self.nb)(*self.sizes)
+        flat = [int(v) for o in offsets for v in o]
+        self._off = (C.c_int * (3 * self.nb))(*flat)
+        self.grid = make_grid(global_spec)
+        self.metric = grmhd_metric(int(global_spec.metric), float(global_spec.a),
+                                   float(global_spec.hslope))
+        self.params = grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
+                                   int(newton_maxit), int(recon), PREC_FP64, 0)
+        nbytes = L.grmhd_pack_workspace_bytes(self.nb, self._n)
+        if nbytes == 0:
+            raise GrmhdError("invalid pack")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.grmhd_pack_create(C.byref(h), self.nb, self._n, self._off, C.byref(self.grid),
+                                   C.byref(self.metric), C.byref(self.params),
+                                   C.c_void_p(self.workspace.data_ptr() + off), nbytes,
+                                   C.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+        gb, nd = C.c_int(), C.c_longlong()
+        _check(L.grmhd_pack_info(self.h, C.byref(gb), C.byref(nd)))
+        self.grid_blocks, self.prim_doubles = gb.value, nd.value
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().grmhd_pack_destroy(h)
+            self.h = None
+
+    def set_tiles(self, n, t1, t2, t3):
+        _check(lib().grmhd_pack_set_tiles(self.h, int(n), int(t1), int(t2), int(t3)))
+
+    def load(self, packed):
+        p = packed.to(device=self.device, dtype=torch.float64).contiguous()
+        assert p.numel() == self.prim_doubles
+        self._keep = p
+        _check(lib().grmhd_pack_load_prims(self.h, _ptr(p)))
+
+    def step(self, dt):
+        _check(lib().grmhd_pack_step(self.h, float(dt)))
+
+    def prims(self):
+        out = torch.empty(self.prim_doubles, dtype=torch.float64, device=self.device)
+        _check(lib().grmhd_pack_get_prims(self.h, _ptr(out)))
+        return out
+
+    def status(self):
+        n = C.c_longlong()
+        _check(lib().grmhd_pack_get_status(self.h, C.byref(n)))
+        return n.value

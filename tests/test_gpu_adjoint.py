@@ -1,0 +1,112 @@
+"""The hand-written adjoint of the RK2 step, through torch.autograd, against
+central finite differences (h = 1e-6 along seeded relative directions).
+
+Loss: sum over the inner five radial zones (all x2, x3) of rho * u after the
+steps, dt fixed from the initial state.  Directions v = P * xi on the
+interior prims (xi ~ N(0, 1), seeded) together with dgamma = gamma * xi_g.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import fm_torus, interior, RECON_MC, RECON_WENO5, NG
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_01361_amd import grmhd as gr
+    from paper_2408_01361_amd import autograd as ag
+    return torch, gr, ag
+
+
+def loss_np(P, nr=5):
+    I = interior(P)
+    return float((I[0, :, :, :nr] * I[1, :, :, :nr]).sum())
+
+
+def gpu_loss(torch, gr, grid, P, gam, recon, dt, nsteps):
+    s = gr.Grmhd(grid, gam, recon=recon)
+    s.load(torch.from_numpy(P).cuda())
+    for _ in range(nsteps):
+        s.step(dt)
+    return loss_np(s.prims().cpu().numpy())
+
+
+def adjoint_vs_fd(n, nsteps, recon, ndir, seed=5, h=1e-6):
+    torch, gr, ag = _setup()
+    gam = 13.0 / 9.0
+    grid, P, _ = fm_torus(n, n, n)
+    s = gr.Grmhd(grid, gam, recon=recon)
+    s.load(torch.from_numpy(P).cuda())
+    dt = s.dt()
+    x = torch.from_numpy(P).cuda().requires_grad_(True)
+    gt = torch.tensor(gam, dtype=torch.float64, device="cuda", requires_grad=True)
+    out = ag.run(x, gt, s, dt, nsteps)
+    I = out[:, NG:-NG, NG:-NG, NG:-NG]
+    L = (I[0, :, :, :5] * I[1, :, :, :5]).sum()
+    L.backward()
+    gP = x.grad.cpu().numpy()
+    gG = float(gt.grad)
+    assert np.all(gP[:, :NG] == 0) and np.all(gP[:, :, :NG] == 0)   # ghosts carry no gradient
+    rng = np.random.default_rng(seed)
+    rows = []
+    for q in range(ndir):
+        v = np.zeros_like(P)
+        interior(v)[...] = interior(P) * rng.normal(size=interior(P).shape)
+        vg = gam * rng.normal()
+        lp = gpu_loss(torch, gr, grid, P + h * v, gam + h * vg, recon, dt, nsteps)
+        lm = gpu_loss(torch, gr, grid, P - h * v, gam - h * vg, recon, dt, nsteps)
+        fd = (lp - lm) / (2 * h)
+        ad = float((gP * v).sum()) + gG * vg
+        rows.append((fd, ad, abs(fd - ad) / max(abs(fd), 1e-300)))
+        print(f"dir {q}: fd {fd:.12e} adjoint {ad:.12e} rel {rows[-1][2]:.2e}", flush=True)
+    return np.array(rows), gP, gG, (grid, P, dt)
+
+
+def test_adjoint_small_mc_and_weno():
+    for recon in (RECON_MC, RECON_WENO5):
+        rows, _, _, _ = adjoint_vs_fd(16, 2, recon, 6)
+        assert np.median(rows[:, 2]) < 1e-6, rows
+        assert rows[:, 2].max() < 1e-4, rows
+
+
+def test_adjoint_torus64_mc_8_steps():
+    """The 64^3 torus, MC, 8 steps, gradients w.r.t. the initial prims and
+    gamma, 20 seeded directions."""
+    rows, gP, gG, (grid, P, dt) = adjoint_vs_fd(64, 8, RECON_MC, 20)
+    print("median rel", np.median(rows[:, 2]), "max rel", rows[:, 2].max(), "dL/dgamma", gG)
+    assert np.median(rows[:, 2]) < 1e-6
+    assert (rows[:, 2] < 1e-4).mean() >= 0.9
+
+
+def test_adjoint_against_oracle_fd():
+    """The same gradient against central differences of the CPU oracle."""
+    torch, gr, ag = _setup()
+    gam = 13.0 / 9.0
+    grid, P, _ = fm_torus(24, 24, 8)
+    s = gr.Grmhd(grid, gam, recon=RECON_MC)
+    s.load(torch.from_numpy(P).cuda())
+    dt = s.dt()
+    x = torch.from_numpy(P).cuda().requires_grad_(True)
+    gt = torch.tensor(gam, dtype=torch.float64, device="cuda", requires_grad=True)
+    out = ag.run(x, gt, s, dt, 3)
+    I = out[:, NG:-NG, NG:-NG, NG:-NG]
+    (I[0, :, :, :5] * I[1, :, :, :5]).sum().backward()
+    gP, gG = x.grad.cpu().numpy(), float(gt.grad)
+    rng = np.random.default_rng(9)
+    h = 1e-6
+    for _ in range(4):
+        v = np.zeros_like(P)
+        interior(v)[...] = interior(P) * rng.normal(size=interior(P).shape)
+        vg = gam * rng.normal()
+        Lp = loss_np(oracle.run(oracle.cfg(grid, gam=gam + h * vg, recon=RECON_MC), P + h * v, dt, 3)[0])
+        Lm = loss_np(oracle.run(oracle.cfg(grid, gam=gam - h * vg, recon=RECON_MC), P - h * v, dt, 3)[0])
+        fd = (Lp - Lm) / (2 * h)
+        ad = float((gP * v).sum()) + gG * vg
+        print("oracle fd", fd, "adjoint", ad)
+        assert abs(fd - ad) <= 1e-5 * abs(fd)
