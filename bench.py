@@ -1,22 +1,22 @@
 """Throughput of the HARM ideal-GRMHD step on one MI355X.
 
-Workload (default): the magnetised Fishbone-Moncrief torus in Kerr a = 0.9375,
+Headline workload: the magnetised Fishbone-Moncrief torus in Kerr a = 0.9375,
 modified Kerr-Schild coordinates (h = 0.3, r from 0.95 r+ to 1000), r_in = 6,
 r_max = 12, gamma = 13/9, beta_min = 100, u perturbed by +-4 % (seed 1),
-128^3 zones, WENO5, FP64.  A step is one SSPRK2 step (both stages: ghost
+128^3 zones, WENO5, FP64.  A step is one SSPRK2 step -- both stages: ghost
 fill, reconstruction + face states + LLF fluxes along x1..x3, Flux-CT EMFs,
-divergence + source + RK combine + 1D_W inversion) plus the CFL dt
+divergence + source + RK combination + 1D_W inversion -- plus the CFL dt
 reduction that chooses it.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line: zone-cycles per second, the roofline of the dominant
-kernel (its time from HIP events recorded on the library's stream during the
-timed region), and the FP64 CPU oracle timed on a bounded sample.
+One JSON line: zone-cycles per second, the roofline of the dominant kernel
+(its duration from HIP events recorded on the library's stream over the timed
+region), the FP64 CPU oracle timed on a bounded sample, and the reduced-
+precision and batched forms measured against plain FP64 on the same GPU.
 """
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -24,17 +24,20 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Published MI355X peaks used for the roofline fraction.
+# Published MI355X peaks.
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
-PEAK_FP32_TFLOPS = 157.3
 
-# Algorithmic cost per unit of the per-class kernels: bytes that must cross
-# HBM at least once, and flops counted by the oracle's counting build
-# (oracle/count_flops.py; every +, -, *, /, sqrt is one flop).  A flux unit is
-# one face, an update unit one zone.
-FLOPS_PER_FACE = {("weno5", "fp64"): None, ("mc", "fp64"): None}
-FLOPS_PER_ZONE_UPDATE = None
+# Algorithmic work per unit (a flux unit is one face, an update unit one
+# zone), flops from the oracle's counting build (every +, -, *, /, sqrt is
+# one flop; python -m oracle.count_flops), bytes that must cross HBM once:
+#   flux:   read 8 prims + write 8 flux components           = 128 B per face
+#   update: read prims, the V register (or write it), 5 hydro flux components
+#           per direction, 3 EMFs; write prims               = 336 B per zone
+# (the 2-D geometry tables, 22-62 doubles per (x1, x2) column, amortise over
+# the x3 extent and are left out).
+FLOPS = {"weno5": {"flux": 1734.0, "update": 1199.8}, "mc": {"flux": 735.3, "update": 1184.3}}
+BYTES = {"flux": 128.0, "update": 336.0}
 
 
 def parse():
@@ -44,10 +47,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128, help="zones per axis of the torus")
     ap.add_argument("--recon", choices=("weno5", "mc"), default="weno5")
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="approximate CPU time budget of the oracle baseline")
+                    help="approximate CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the reduced-precision and batched measurements")
+    ap.add_argument("--no-tune", action="store_true")
     return ap.parse_args()
 
 
@@ -58,7 +63,6 @@ def oracle_baseline(grid, P, gam, recon, budget_s):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     c = oracle.cfg(grid, gam=gam, recon=recon, nthreads=threads)
     nz = grid.n1 * grid.n2 * grid.n3
-    dt = oracle.estimate_dt(c, P)
     steps, t = 0, 0.0
     Q = P
     while t < budget_s and steps < 50:
@@ -67,57 +71,181 @@ def oracle_baseline(grid, P, gam, recon, budget_s):
         t += time.perf_counter() - t0
         steps += 1
     return {"value": nz * steps / t, "unit": "zone-cycles/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} full SSPRK2 step(s) of the same {grid.n1}x{grid.n2}x{grid.n3} "
-                      f"torus with per-step CFL dt, {t:.1f} s"}
+            "sample": f"{steps} full SSPRK2 step(s) of the same {grid.n1}^3 torus (CFL dt each "
+                      f"step), {t:.1f} s wall"}
+
+
+def traffic_from_profile(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(fields["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2408_01361_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".inc")):
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def time_steps(torch, solver, steps, use_dt=True, dt=None):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.step(solver.dt() if use_dt else dt)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def extras(torch, gr, np, args):
+    """Reduced precision (192^3, 50 steps) and batched packs (320 blocks),
+    each against plain FP64 on this GPU."""
+    from workloads import fm_torus, torus_pack, interior, RECON_WENO5
+    from paper_2408_01361_amd import autotune
+    out = {}
+    gam = 13.0 / 9.0
+    n = 192
+    grid, P, _ = fm_torus(n, n, n, seed=1, gamma=gam)
+    Pt = torch.from_numpy(P).cuda()
+    res = {}
+    for name, prec in (("fp64", gr.PREC_FP64), ("mixed", gr.PREC_MIXED)):
+        s = gr.Grmhd(grid, gam, recon=RECON_WENO5, precision=prec)
+        s.load(Pt)
+        dt = s.dt()
+        if not args.no_tune:
+            autotune.tune_schedule(s, dt)
+            s.load(Pt)
+        err = {}
+        t = 0.0
+        done = 0
+        for upto in (1, 10, 50):
+            t += time_steps(torch, s, upto - done, use_dt=False, dt=dt)
+            done = upto
+            err[upto] = s.prims().cpu().numpy()
+        res[name] = (t, err, s.divb(), s.status()[0])
+        del s
+    t64, e64, _, _ = res["fp64"]
+    t32, e32, divb32, f32 = res["mixed"]
+    rel = {}
+    for k in (1, 10, 50):
+        a, b = interior(e32[k][0]), interior(e64[k][0])
+        rel[str(k)] = float(np.abs(a - b).sum() / np.abs(b).sum())
+    out["mixed_precision"] = {
+        "workload": f"same torus at {n}^3, WENO5, 50 RK2 steps at the initial CFL dt",
+        "zone_cycles_per_s": n ** 3 * 50 / t32, "fp64_zone_cycles_per_s": n ** 3 * 50 / t64,
+        "speedup_vs_fp64": t64 / t32, "rho_rel_l1_vs_fp64_after_steps": rel,
+        "divb_max_mixed": divb32[0], "inversion_failures": f32}
+    del Pt, res, e64, e32
+    # batched uneven packs of the 128^3 torus
+    g, blocks, _ = torus_pack(nblocks=320, n_global=128, sizes=(16, 32, 64), probs=(0.6, 0.3, 0.1),
+                              seed=7, torus_seed=1, gamma=gam)
+    flat = torch.from_numpy(np.concatenate([b["prims"].ravel() for b in blocks])).cuda()
+    pk = gr.Pack(g, [b["n"] for b in blocks], [b["offset"] for b in blocks], gam, recon=RECON_WENO5)
+    pk.load(flat)
+    _, Pg, _ = fm_torus(128, 128, 128, seed=1, gamma=gam)
+    single = gr.Grmhd(g, gam, recon=RECON_WENO5)
+    single.load(torch.from_numpy(Pg).cuda())
+    dt = single.dt()
+    del single
+    tiles = {}
+    if not args.no_tune:
+        tiles, _ = autotune.tune_pack(pk, dt)
+        pk.load(flat)
+    zones = sum(b["n"] ** 3 for b in blocks)
+    for _ in range(2):
+        pk.step(dt)
+    torch.cuda.synchronize()
+    steps = 10
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pk.step(dt)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    out["batched"] = {
+        "workload": "320 frozen-ghost blocks of the 128^3 torus, n in {16,32,64} (60/30/10 %, seed 7), "
+                    "WENO5, FP64, one persistent launch per RK2 stage, 10 steps at fixed dt",
+        "interior_zones": zones, "zone_cycles_per_s": zones * steps / tp,
+        "cooperative_workgroups": pk.grid_blocks,
+        "tiles": {str(k): list(v) for k, v in tiles.items()}, "inversion_failures": pk.status()}
+    return out
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part "
-                                   "of it (pass --gpus 1)"}))
+        print(json.dumps({"error": "this build measures one GPU; runs on several GPUs are not "
+                                   "part of it (use --gpus 1)"}))
         sys.exit(2)
     import numpy as np
     import torch
     from workloads import fm_torus, RECON_MC, RECON_WENO5
     from paper_2408_01361_amd import grmhd as gr
+    from paper_2408_01361_amd import autotune
 
     n = args.n
     gam = 13.0 / 9.0
     recon = RECON_WENO5 if args.recon == "weno5" else RECON_MC
-    prec = gr.PREC_FP64 if args.precision == "fp64" else gr.PREC_MIXED
     grid, P, info = fm_torus(n, n, n, seed=1, gamma=gam)
-    s = gr.Grmhd(grid, gam, recon=recon, precision=prec)
-    s.load(torch.from_numpy(P).cuda())
+    Pt = torch.from_numpy(P).cuda()
+    s = gr.Grmhd(grid, gam, recon=recon, precision=gr.PREC_FP64)
+    s.load(Pt)
+    sched = None
+    if not args.no_tune:
+        sched, _ = autotune.tune_schedule(s, s.dt())
+        s.load(Pt)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         s.step(s.dt())
-    torch.cuda.synchronize()
-
     s.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.step(s.dt())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    el = time_steps(torch, s, args.steps)
     rep = s.timing_report()
     s.timing(False)
     fails = s.status()[0]
-
     nz = n ** 3
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    zcps = nz * args.steps / (t1 - t0)
+    ms_step = el * 1e3 / args.steps
+    zcps = nz * args.steps / el
 
-    # dominant kernel class by event time
-    dom = max(rep, key=lambda k: rep[k][0])
-    dom_ms, dom_launches = rep[dom]
-    avg_ms = dom_ms / max(dom_launches, 1)
+    # roofline of the dominant kernel class
+    cls = {k: v for k, v in rep.items() if v[1] > 0}
+    dom = max(cls, key=lambda k: cls[k][0])
+    ms, launches = cls[dom]
+    avg_s = ms * 1e-3 / launches
+    kind = "flux" if dom.startswith("flux") else ("update" if dom.startswith("update") else None)
+    roof = {"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
+            "kernel": dom, "avg_us": avg_s * 1e6}
+    if kind:
+        units = (n + 1) * (n + 2) * (n + 2) if kind == "flux" else nz
+        flops = FLOPS[args.recon][kind] * units
+        nbytes = BYTES[kind] * units
+        f_alu = flops / avg_s / 1e12 / PEAK_FP64_TFLOPS
+        f_hbm = nbytes / avg_s / 1e9 / PEAK_HBM_GBS
+        if f_alu >= f_hbm:
+            roof.update(bound="alu", achieved=flops / avg_s / 1e12, peak=PEAK_FP64_TFLOPS,
+                        unit="TFLOP/s", frac=f_alu)
+        else:
+            roof.update(bound="hbm", achieved=nbytes / avg_s / 1e9, peak=PEAK_HBM_GBS, unit="GB/s",
+                        frac=f_hbm)
+        roof["algorithmic_flops_per_launch"] = flops
+        roof["algorithmic_bytes_per_launch"] = nbytes
+        roof["hbm_frac_algorithmic"] = f_hbm
+        roof["traffic"] = traffic_from_profile(dom, f"torus{n}_{args.recon}")
     kernels = {k: {"ms_total": round(v[0], 4), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / max(v[1], 1), 2)} for k, v in rep.items()}
-    roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": None, "traffic": None, "kernel": dom, "avg_us": round(1e3 * avg_ms, 2)}
-
     out = {
         "metric": "zone-cycles/sec per RK2 step (FP64 vs mixed vs batched) + % HBM roofline",
         "value": zcps,
@@ -129,14 +257,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == gr.PREC_FP64 else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"magnetised FM torus, Kerr a=0.9375 MKS, {n}^3, "
-                               f"{args.recon.upper()}, {args.precision}, SSPRK2 + 1D_W + Flux-CT",
-                   "zones": nz, "gamma_ad": gam, "seed": 1, "inversion_failures": fails},
+        "config": {"workload": f"magnetised FM torus, Kerr a=0.9375 MKS h=0.3, {n}^3, "
+                               f"{args.recon.upper()}, FP64, SSPRK2 + LLF + Flux-CT + 1D_W, CFL dt "
+                               f"each step", "zones": nz, "gamma_ad": gam, "seed": 1,
+                   "inversion_failures": fails, "schedule_kg": sched},
         "roofline": roof,
         "kernels": kernels,
+        # whole step against HBM: the method's minimum (read and write the 8-variable
+        # state and the stage register: 6 x 64 B per zone-cycle) and this design's
+        # kernel sequence (2 stages x (3 flux passes + update))
+        "hbm_frac_step_min_384B": zcps * 384.0 / 1e9 / PEAK_HBM_GBS,
+        "hbm_frac_step_design_bytes": zcps * 2 * (3 * BYTES["flux"] + BYTES["update"]) / 1e9 / PEAK_HBM_GBS,
     }
+    del s
+    if not args.no_extras:
+        out.update(extras(torch, gr, np, args))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_baseline(grid, P, gam, recon, args.cpu_seconds)
     print(json.dumps(out))
