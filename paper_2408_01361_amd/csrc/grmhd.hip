@@ -1446,12 +1446,16 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
     default_tile(n[b], v.t1, v.t2, v.t3);
     k_geometry<<<blocks_for(g.plane), BLOCK, 0, pk->stream>>>(g, v.tabC, v.tabF1, v.tabF2, v.corner, v.conn);
   }
-  int per_cu = 0, ncu = 0, dev = 0;
-  const void* fn = params->recon == GRMHD_RECON_MC ? (const void*)k_pack_stage<1, GRMHD_RECON_MC>
-                                                   : (const void*)k_pack_stage<1, GRMHD_RECON_WENO5>;
+  // co-resident workgroups per CU: the smaller of the two stage kernels'
+  int per_cu = 0, per_cu2 = 0, ncu = 0, dev = 0;
+  const bool mc = params->recon == GRMHD_RECON_MC;
+  const void* fn1 = mc ? (const void*)k_pack_stage<1, GRMHD_RECON_MC> : (const void*)k_pack_stage<1, GRMHD_RECON_WENO5>;
+  const void* fn2 = mc ? (const void*)k_pack_stage<2, GRMHD_RECON_MC> : (const void*)k_pack_stage<2, GRMHD_RECON_WENO5>;
   if (hip_check() || hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, 0) != hipSuccess || per_cu < 1 ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn1, BLOCK, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, fn2, BLOCK, 0) != hipSuccess ||
+      (per_cu = per_cu < per_cu2 ? per_cu : per_cu2) < 1 ||
       hipMemsetAsync(pk->d_fails, 0, sizeof(unsigned long long), pk->stream) != hipSuccess ||
       pack_upload(pk) != GRMHD_OK) {
     delete pk;

@@ -63,19 +63,22 @@ struct Fluid {
 namespace f64 {
 using R = double;
 #pragma clang fp contract(off)
+__device__ __forceinline__ R fdiv(R a, R b) { return a / b; }
 #include "physics_body.inc"
 }  // namespace f64
 
-// FP32: contraction into fused multiply-adds allowed.
+// FP32: contraction into fused multiply-adds allowed, fast divisions.
 namespace f32 {
 using R = float;
 #pragma clang fp contract(fast)
+__device__ __forceinline__ R fdiv(R a, R b) { return a * __builtin_amdgcn_rcpf(b); }
 #include "physics_body.inc"
 }  // namespace f32
 
 // Dual numbers: local Jacobians for the adjoint.
 namespace fdual {
 using R = Dual;
+__device__ __forceinline__ R fdiv(R a, R b) { return a / b; }
 #include "physics_body.inc"
 }  // namespace fdual
 
@@ -109,14 +112,15 @@ using fdual::llf;
 
 // WENO5 value at the right edge of zone c from point values a..e.  The three
 // nonlinear weights d_k/(eps + beta_k)^2 are formed over a common
-// denominator, so one division normalises them.
-#pragma clang fp contract(off)
+// denominator, so one division normalises them.  (Contraction is allowed
+// here: no flat-space test depends on WENO5 rounding.)
+#pragma clang fp contract(fast)
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e, double eps) {
   typedef double R;
-  const R k1312 = 13.0 / 12.0;
-  R p0 = ((R)2 * a - (R)7 * b + (R)11 * c) / (R)6;
-  R p1 = (-b + (R)5 * c + (R)2 * d) / (R)6;
-  R p2 = ((R)2 * c + (R)5 * d - e) / (R)6;
+  const R r6 = 1.0 / 6.0, k1312 = 13.0 / 12.0;
+  R p0 = ((R)2 * a - (R)7 * b + (R)11 * c) * r6;
+  R p1 = (-b + (R)5 * c + (R)2 * d) * r6;
+  R p2 = ((R)2 * c + (R)5 * d - e) * r6;
   R t0 = a - (R)2 * b + c, u0 = a - (R)4 * b + (R)3 * c;
   R t1 = b - (R)2 * c + d, u1 = b - d;
   R t2 = c - (R)2 * d + e, u2 = (R)3 * c - (R)4 * d + e;
@@ -130,11 +134,10 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
 }
 
-#pragma clang fp contract(fast)
-
-// FP32 form: the weights are written through ratios of (eps + beta_k), so
-// that no product of squared indicators underflows the single-precision range;
-// a ratio that overflows drives its weight to the correct limit of zero.
+// FP32 form: the indicators are normalised by the smallest (eps + beta_k),
+// so the smoothest stencil keeps its linear weight, the others' ratios can
+// only shrink (underflow to zero weight, never to 0/0), and the divisions are
+// hardware reciprocals (v_rcp_f32).
 __device__ __forceinline__ float weno5(float a, float b, float c, float d, float e, float eps) {
   const float r6 = 1.0f / 6.0f, k1312 = 13.0f / 12.0f;
   float p0 = (2.0f * a - 7.0f * b + 11.0f * c) * r6;
@@ -146,11 +149,11 @@ __device__ __forceinline__ float weno5(float a, float b, float c, float d, float
   float s0 = eps + (k1312 * t0 * t0 + 0.25f * u0 * u0);
   float s1 = eps + (k1312 * t1 * t1 + 0.25f * u1 * u1);
   float s2 = eps + (k1312 * t2 * t2 + 0.25f * u2 * u2);
-  float r01 = s0 / s1, r02 = s0 / s2, r12 = s1 / s2;
-  float w0 = 0.1f / (0.1f + 0.6f * (r01 * r01) + 0.3f * (r02 * r02));
-  float w1 = 0.6f / (0.1f / (r01 * r01) + 0.6f + 0.3f * (r12 * r12));
-  float w2 = 0.3f / (0.1f / (r02 * r02) + 0.6f / (r12 * r12) + 0.3f);
-  return w0 * p0 + w1 * p1 + w2 * p2;
+  float im = __builtin_amdgcn_rcpf(fminf(fminf(s0, s1), s2));
+  float r0 = s0 * im, r1 = s1 * im, r2 = s2 * im;
+  float w0 = 0.1f * __builtin_amdgcn_rcpf(r0 * r0), w1 = 0.6f * __builtin_amdgcn_rcpf(r1 * r1),
+        w2 = 0.3f * __builtin_amdgcn_rcpf(r2 * r2);
+  return (w0 * p0 + w1 * p1 + w2 * p2) * __builtin_amdgcn_rcpf(w0 + w1 + w2);
 }
 
 // Dual-number WENO5 in the same single-division form as the FP64 one.
