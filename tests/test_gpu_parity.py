@@ -1,15 +1,23 @@
 """GPU-vs-oracle parity of the HIP path, through the C ABI.
 
-The bar (per step, FP64): relative L1 of every primitive over interior zones,
-sum|P_gpu - P_oracle| / sum|P_oracle|, at most 1e-12; failure flags equal;
-div B at roundoff.  Inputs are the seeded workloads, identical on both sides;
-both sides advance with the oracle's dt.
+The bar (per step, FP64): relative L1 of every primitive over interior zones
+(parity_util.rel_l1) at most 1e-12; failure flags equal; div B at roundoff.
+Inputs are the seeded workloads, identical on both sides; both sides advance
+with the oracle's dt.
+
+WENO5 linear modes are held to 1e-11 instead: their u~1, u~2, B2 are pure
+1e-4 perturbations moved by differences of O(1) background fluxes, and the
+GPU's WENO5 weights are rounded differently from the oracle's (one division
+instead of four, contraction allowed); the oracle against itself compiled
+with FMA contraction differs by 8e-12 there.  The MC path, which the
+fast-mode workload uses, is held to 1e-12 and agrees bit for bit in flat space.
 """
 
 import numpy as np
 import pytest
 
 import oracle
+from parity_util import rel_l1
 from workloads import linear_mode, fm_torus, interior, GridSpec, RECON_MC, RECON_WENO5
 
 pytestmark = pytest.mark.gpu
@@ -29,20 +37,6 @@ def _gr():
     return grmhd
 
 
-def rel_l1(a, b):
-    """Per-variable relative L1 of interior zones, and the worst of them."""
-    A, B = interior(a), interior(b)
-    out = []
-    for v in range(A.shape[0]):
-        den = np.abs(B[v]).sum()
-        num = np.abs(A[v] - B[v]).sum()
-        if den == 0.0:
-            out.append(0.0 if num == 0.0 else np.inf)
-        else:
-            out.append(num / den)
-    return np.array(out)
-
-
 def run_gpu(grid, P, gam, recon, dts, precision=0):
     torch = _torch()
     gr = _gr()
@@ -56,17 +50,20 @@ def run_gpu(grid, P, gam, recon, dts, precision=0):
 
 
 CASES = {
-    "fast32_mc": lambda: (linear_mode("fast", 32, ndim=3)[0:2], 4 / 3, RECON_MC),
-    "fast16_weno": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, RECON_WENO5),
-    "alfven24x20_mc_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, RECON_MC),
-    "torus24_weno": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, RECON_WENO5),
-    "torus20x28x6_mc": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, RECON_MC),
+    "fast32_mc": lambda: (linear_mode("fast", 32, ndim=3)[0:2], 4 / 3, RECON_MC, TOL),
+    "fast16_weno": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, RECON_WENO5, 1e-11),
+    "alfven24x20_mc_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, RECON_MC, TOL),
+    "slow20_mc_2d": lambda: (linear_mode("slow", 20, ndim=2)[0:2], 4 / 3, RECON_MC, TOL),
+    "torus24_weno": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, RECON_WENO5, TOL),
+    "torus20x28x6_mc": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, RECON_MC, TOL),
+    "torus_unmag_16x20x4_weno": lambda: (fm_torus(16, 20, 4, magnetised=False)[0:2], 13 / 9,
+                                         RECON_WENO5, TOL),
 }
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_step_parity(case):
-    (grid, P), gam, recon = CASES[case]()
+    (grid, P), gam, recon, tol = CASES[case]()
     c = oracle.cfg(grid, gam=gam, recon=recon)
     nsteps = 2
     ref, fails, dts, flags = oracle.run(c, P, -1, nsteps, flags=True)
@@ -74,7 +71,7 @@ def test_step_parity(case):
     r = rel_l1(out, ref)
     print(case, "dts", dts, "fails", fails, gfails, "rel L1", r)
     assert gfails == fails
-    assert r.max() <= TOL, r
+    assert r.max() <= tol, r
 
 
 def test_prims_to_cons_and_inversion_parity():
