@@ -35,6 +35,11 @@ constexpr int NG = 3;
 constexpr int BLOCK = 256;
 constexpr int MAX_PARTIALS = 65536;
 
+// Waves per SIMD the update kernel is compiled for (its register budget).
+#ifndef UPDATE_WAVES
+#define UPDATE_WAVES 3
+#endif
+
 // Everything a kernel needs to know about the grid, passed by value.
 struct Dev {
   int n1, n2, n3;
@@ -451,23 +456,26 @@ __device__ __forceinline__ void load_conn(const double* __restrict__ conn, long 
   for (int f = 0; f < 40; f++) cn[f] = conn[f * plane + q];
 }
 
-// sqrt(-g) T^k_l Gamma^l_{nu k} into S[UU + nu].
+// sqrt(-g) T^k_l Gamma^l_{nu k} into S[nu]: rows of T formed one at a time,
+// connection coefficients read where they are used; each sum runs over k,
+// then l.
 __device__ __forceinline__ void geometric_source(const double p[NVAR], const Fluid<double>& f,
-                                                 const PointMetric<double>& m, const double cn[40],
+                                                 const PointMetric<double>& m,
+                                                 const double* __restrict__ conn, long plane, long q,
                                                  double gam, double S[4]) {
 #pragma clang fp contract(off)
-  double T[4][4];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < 4; k++) tmunu_row(p, f, gam, k, T[k]);
+  for (int k = 0; k < 4; k++) {
+    double Tk[4];
+    tmunu_row(p, f, gam, k, Tk);
 #pragma unroll
-  for (int nu = 0; nu < 4; nu++) {
-    double s = 0.0;
+    for (int nu = 0; nu < 4; nu++)
 #pragma unroll
-    for (int k = 0; k < 4; k++)
-#pragma unroll
-      for (int l = 0; l < 4; l++) s += T[k][l] * cn[l * 10 + sidx(nu, k)];
-    S[nu] = m.gdet * s;
+      for (int l = 0; l < 4; l++) s[nu] += Tk[l] * conn[(l * 10 + sidx(nu, k)) * plane + q];
   }
+#pragma unroll
+  for (int nu = 0; nu < 4; nu++) S[nu] = m.gdet * s[nu];
 }
 
 // One stage for every interior zone.  STAGE 1: V = (Un + U1)/2 with
@@ -497,10 +505,8 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
 
   double L[NVAR];
   {
-    double cn[40];
-    load_conn(conn, g.plane, q2, cn);
     double S[4];
-    geometric_source(p, f, m, cn, g.gam, S);
+    geometric_source(p, f, m, conn, g.plane, q2, g.gam, S);
 #pragma unroll
     for (int v = 0; v < 5; v++) {
       double d1 = ((double)F1[v * nz + c + si] - (double)F1[v * nz + c]) / g.dx1;
@@ -545,7 +551,7 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
 }
 
 template <int STAGE, typename FT>
-__global__ void __launch_bounds__(BLOCK) k_update(Dev g, Sched box, const double* __restrict__ Pin,
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8))) k_update(Dev g, Sched box, const double* __restrict__ Pin,
                                                   double* __restrict__ Pout, double* __restrict__ V,
                                                   const FT* __restrict__ F1, const FT* __restrict__ F2,
                                                   const FT* __restrict__ F3, const FT* __restrict__ E1,

@@ -11,6 +11,13 @@
 //
 // Included inside the anonymous namespace of grmhd.hip.
 
+// Waves per SIMD the persistent kernel is compiled for: every phase shares
+// one register budget, so it is set to what the update phase fits in
+// without spilling.
+#ifndef PACK_WAVES
+#define PACK_WAVES 3
+#endif
+
 struct BlockView {
   Dev g;
   double *P, *P1, *V;
@@ -63,7 +70,7 @@ __device__ __forceinline__ bool tile_pos(const Box& b, int t1, int t2, int t3, i
 }
 
 template <int RECON>
-__device__ void pack_flux_item(const BlockView& b, const double* __restrict__ Pin, int lt) {
+__device__ __forceinline__ void pack_flux_item(const BlockView& b, const double* __restrict__ Pin, int lt) {
   const Dev& g = b.g;
   for (int d = 1; d <= 3; d++) {
     Box bx = phase_box(g, PH_FLUX, d);
@@ -103,7 +110,7 @@ __device__ __forceinline__ int find_block(const int* __restrict__ pre, int nb, i
 // Every workgroup leaves each phase's loop once the counter passes the total
 // and then meets every grid barrier, so the launch always drains.
 template <int STAGE, int RECON>
-__global__ void __launch_bounds__(BLOCK) k_pack_stage(const BlockView* __restrict__ bv, int nb,
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PACK_WAVES, PACK_WAVES))) k_pack_stage(const BlockView* __restrict__ bv, int nb,
                                                       const int* __restrict__ pre,
                                                       unsigned* counters, double dt,
                                                       unsigned long long* fails) {
