@@ -21,7 +21,7 @@
  *     all scratch lives in the caller's workspace of grmhd_workspace_bytes()
  *     bytes, borrowed for the context's lifetime.
  *   - All work is enqueued on the hipStream_t given at creation, in order.
- *     Calls that return host values (estimate_dt, divb, get_status,
+ *     Calls that return host values (estimate_dt, last_dt, divb, get_status,
  *     cons_to_prims' count) synchronise that stream; the rest are
  *     asynchronous.
  *   - Every function returns 0 (GRMHD_OK) or a negative GRMHD_E_* code and
@@ -98,6 +98,17 @@ int grmhd_step(grmhd_ctx* ctx, double dt);
 /* CFL step: cfl / max over interior zones of sum_d max|c+-_d| / dx_d (axes
  * with more than one zone), from the current prims.  Synchronises. */
 int grmhd_estimate_dt(grmhd_ctx* ctx, double* dt_out);
+
+/* One step of the CFL size without a host round trip: the dt reduction of
+ * grmhd_estimate_dt runs on the device and both stages read its result there
+ * (the per-step global dt of the Core section's reductions).  Asynchronous.
+ * If the maximum signal rate is not positive and finite the step is taken
+ * with dt = 0 (state unchanged) and grmhd_last_dt reports E_STATE. */
+int grmhd_step_cfl(grmhd_ctx* ctx);
+
+/* The dt of the last reduction (grmhd_step_cfl or grmhd_estimate_dt) to
+ * *dt_out (host); E_STATE if it was not usable.  Synchronises. */
+int grmhd_last_dt(grmhd_ctx* ctx, double* dt_out);
 
 /* Copy the current padded prims (ghosts filled) to device memory d_out. */
 int grmhd_get_prims(grmhd_ctx* ctx, double* d_out);

@@ -35,7 +35,7 @@ __device__ __forceinline__ void face_flux_dual(const Dev& g, const double* __res
     Dual q[St::W];
 #pragma unroll
     for (int z = 0; z < St::W; z++) q[z] = Dual(P[v * g.nz + c + (z - St::H) * s], seed == v * St::W + z ? 1.0 : 0.0);
-    if (RECON == GRMHD_RECON_MC) {
+    if constexpr (RECON == GRMHD_RECON_MC) {
       qL[v] = mc_left(q[0], q[1], q[2]);
       qR[v] = mc_right(q[1], q[2], q[3]);
     } else {
@@ -429,9 +429,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_gsum(long nz, const double* __res
                                                     const double* __restrict__ GF2,
                                                     const double* __restrict__ GF3, double* pmax,
                                                     double* psum) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   double s = 0.0;
-  if (t < nz) s = ((GZ[t] + GF1[t]) + GF2[t]) + GF3[t];
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nz; t += stride)
+    s += ((GZ[t] + GF1[t]) + GF2[t]) + GF3[t];
   double mx = 0.0;
   block_reduce(mx, s);
   if (threadIdx.x == 0) {

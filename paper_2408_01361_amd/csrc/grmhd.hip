@@ -65,7 +65,7 @@ __device__ __forceinline__ long pid(const Dev& g, int i, int j) {
 // Box of (i, j, k), inclusive bounds, enumerated x1-fastest by a 1-D grid.
 struct Box {
   int lo1, lo2, lo3, n1, n2, n3;
-  long count() const { return (long)n1 * n2 * n3; }
+  __host__ __device__ long count() const { return (long)n1 * n2 * n3; }
 };
 __device__ __forceinline__ bool box_index(const Box& b, long t, int& i, int& j, int& k) {
   if (t >= (long)b.n1 * b.n2 * b.n3) return false;
@@ -186,28 +186,60 @@ __device__ __forceinline__ int bc_map(int x, int n, int bclo, int bchi, bool& fl
   return x;
 }
 
-// One thread per padded zone; ghost zones of non-frozen axes copy from the
+// Ghost shell of the padded grid, enumerated without touching interior
+// zones: the 6 x3 ghost planes (all x1, x2), then the 6 x2 ghost rows of every
+// interior x3 plane (all x1), then the 6 x1 ghost zones of every interior
+// (x2, x3) row.  Count = 6 s1 s2 + 6 n3 s1 + 6 n3 n2 = s1 s2 s3 - n1 n2 n3.
+__host__ __device__ inline long ghost_count(const Dev& g) {
+  return 6L * g.plane + 6L * g.n3 * g.s1 + 6L * g.n3 * g.n2;
+}
+__device__ __forceinline__ void ghost_index(const Dev& g, long t, int& i, int& j, int& k) {
+  auto side = [](int l, int n) { return l < NG ? l - NG : n + (l - NG); };
+  if (t < 6L * g.plane) {
+    int l = (int)(t / g.plane);
+    long r = t - (long)l * g.plane;
+    k = side(l, g.n3);
+    j = (int)(r / g.s1) - NG;
+    i = (int)(r - (long)(j + NG) * g.s1) - NG;
+    return;
+  }
+  t -= 6L * g.plane;
+  const long row6 = 6L * g.s1;
+  if (t < (long)g.n3 * row6) {
+    k = (int)(t / row6);
+    long r = t - (long)k * row6;
+    int l = (int)(r / g.s1);
+    j = side(l, g.n2);
+    i = (int)(r - (long)l * g.s1) - NG;
+    return;
+  }
+  t -= (long)g.n3 * row6;
+  const int col6 = 6 * g.n2;
+  k = (int)(t / col6);
+  int r = (int)(t - (long)k * col6);
+  j = r / 6;
+  i = side(r - 6 * j, g.n1);
+}
+
+// One thread per ghost zone; ghost zones of non-frozen axes copy from the
 // zone their per-axis maps point to (always interior along those axes, so
 // nothing read here is written here).  Polar mirrors flip u~2 and B2.
-__global__ void k_bc(Dev g, double* P) {
+__global__ void __launch_bounds__(BLOCK) k_bc(Dev g, double* P) {
   long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= g.nz) return;
-  int i = (int)(t % g.s1) - NG;
-  long r = t / g.s1;
-  int j = (int)(r % g.s2) - NG, k = (int)(r / g.s2) - NG;
-  bool gi = i < 0 || i >= g.n1, gj = j < 0 || j >= g.n2, gk = k < 0 || k >= g.n3;
-  if (!(gi || gj || gk)) return;
+  if (t >= ghost_count(g)) return;
+  int i, j, k;
+  ghost_index(g, t, i, j, k);
   bool f1 = false, f2 = false, f3 = false;
   int si = bc_map(i, g.n1, g.bc[0], g.bc[1], f1);
   int sj = bc_map(j, g.n2, g.bc[2], g.bc[3], f2);
   int sk = bc_map(k, g.n3, g.bc[4], g.bc[5], f3);
   if (si == i && sj == j && sk == k) return;  // frozen
-  long src = zid(g, si, sj, sk);
+  const long src = zid(g, si, sj, sk), dst = zid(g, i, j, k);
 #pragma unroll
   for (int v = 0; v < NVAR; v++) {
     double x = P[v * g.nz + src];
     if (f2 && (v == U2 || v == B2)) x = -x;
-    P[v * g.nz + t] = x;
+    P[v * g.nz + dst] = x;
   }
 }
 
@@ -558,10 +590,12 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDA
                                                   const FT* __restrict__ E2, const FT* __restrict__ E3,
                                                   const double* __restrict__ tabC,
                                                   const double* __restrict__ conn, double dt,
+                                                  const double* __restrict__ dt_dev,
                                                   unsigned long long* fails,
                                                   unsigned char* __restrict__ flags) {
   int i, j, k;
   if (!sched_index(box, i, j, k)) return;
+  if (dt_dev) dt = *dt_dev;
   update_zone<STAGE, FT>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i, j, k);
 }
 
@@ -602,14 +636,16 @@ __device__ void block_reduce(double& mx, double& sm) {
 }
 
 // Per zone sum_d max(|c+|, |c-|)/dx_d over axes with more than one zone;
-// block maxima to partial[].
+// block maxima to partial[].  Grid-stride over the box, so any grid size
+// reduces through at most MAX_PARTIALS partials.
 __global__ void __launch_bounds__(BLOCK) k_dt_partial(Dev g, Box box, const double* __restrict__ P,
                                                       const double* __restrict__ tabC,
                                                       double* partial) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  int i, j, k;
   double s = 0.0;
-  if (box_index(box, t, i, j, k)) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < box.count(); t += stride) {
+    int i, j, k;
+    box_index(box, t, i, j, k);
     long c = zid(g, i, j, k);
     double p[NVAR];
 #pragma unroll
@@ -618,19 +654,20 @@ __global__ void __launch_bounds__(BLOCK) k_dt_partial(Dev g, Box box, const doub
     load_metric<double>(tabC, g.plane, pid(g, i, j), m);
     Fluid<double> f;
     fluid_state(p, m, f);
-    double cp, cm;
+    double cp, cm, z = 0.0;
     if (g.n1 > 1) {
       char_speeds(p, f, m, g.gam, 1, cp, cm);
-      s += fmax(fabs(cp), fabs(cm)) / g.dx1;
+      z += fmax(fabs(cp), fabs(cm)) / g.dx1;
     }
     if (g.n2 > 1) {
       char_speeds(p, f, m, g.gam, 2, cp, cm);
-      s += fmax(fabs(cp), fabs(cm)) / g.dx2;
+      z += fmax(fabs(cp), fabs(cm)) / g.dx2;
     }
     if (g.n3 > 1) {
       char_speeds(p, f, m, g.gam, 3, cp, cm);
-      s += fmax(fabs(cp), fabs(cm)) / g.dx3;
+      z += fmax(fabs(cp), fabs(cm)) / g.dx3;
     }
+    s = fmax(s, z);
   }
   double sm = 0.0;
   block_reduce(s, sm);
@@ -643,10 +680,11 @@ __global__ void __launch_bounds__(BLOCK) k_divb_partial(Dev g, Box box, const do
                                                         const double* __restrict__ tabC,
                                                         const double* __restrict__ corner,
                                                         double* field, double* pmax, double* psum) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  int i, j, k;
-  double val = 0.0;
-  if (box_index(box, t, i, j, k)) {
+  double mx = 0.0, sm = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < box.count(); t += stride) {
+    int i, j, k;
+    box_index(box, t, i, j, k);
     const long nz = g.nz;
     auto ub = [&](int d, int a, int b, int cc) {
       return tabC[G_DET * g.plane + pid(g, a, b)] * P[(B1 + d) * nz + zid(g, a, b, cc)];
@@ -661,10 +699,11 @@ __global__ void __launch_bounds__(BLOCK) k_divb_partial(Dev g, Box box, const do
                 (ub(2, i, j, k - 1) + ub(2, i - 1, j, k - 1) + ub(2, i, j - 1, k - 1) +
                  ub(2, i - 1, j - 1, k - 1));
     double dv = d1 / (4.0 * g.dx1) + d2 / (4.0 * g.dx2) + d3 / (4.0 * g.dx3);
-    val = fabs(dv) / corner[pid(g, i, j)];
+    const double val = fabs(dv) / corner[pid(g, i, j)];
     if (field) field[zid(g, i, j, k)] = val;
+    mx = fmax(mx, val);
+    sm += val;
   }
-  double mx = val, sm = val;
   block_reduce(mx, sm);
   if (threadIdx.x == 0) {
     pmax[blockIdx.x] = mx;
@@ -672,9 +711,13 @@ __global__ void __launch_bounds__(BLOCK) k_divb_partial(Dev g, Box box, const do
   }
 }
 
-// Single-block final pass over n partials: out[0] = max, out[1] = sum.
+// Single-block final pass over n partials: out[0] = max, out[1] = sum.  With
+// cfl > 0 (the dt reduction) also out[2] = cfl / max, the step the update
+// kernels read on the device, and out[3] = 0 when that dt is usable, 1 when
+// the maximum signal speed is not positive and finite (out[2] is then 0, so a
+// step taken with it leaves the state unchanged).
 __global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* pmax, const double* psum,
-                                                        int n, double* out) {
+                                                        int n, double* out, double cfl) {
   double mx = 0.0, sm = 0.0;
   for (int q = threadIdx.x; q < n; q += BLOCK) {
     mx = fmax(mx, pmax[q]);
@@ -684,6 +727,11 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* pmax, cons
   if (threadIdx.x == 0) {
     out[0] = mx;
     out[1] = sm;
+    if (cfl > 0.0) {
+      const bool ok = mx > 0.0 && isfinite(mx);
+      out[2] = ok ? cfl / mx : 0.0;
+      out[3] = ok ? 0.0 : 1.0;
+    }
   }
 }
 
@@ -857,7 +905,7 @@ struct Timed {
 
 int fill_ghosts(grmhd_ctx* c, double* P) {
   Timed tm(c, T_BC);
-  k_bc<<<blocks_for(c->dev.nz), BLOCK, 0, c->stream>>>(c->dev, P);
+  k_bc<<<blocks_for(ghost_count(c->dev)), BLOCK, 0, c->stream>>>(c->dev, P);
   return hip_check();
 }
 
@@ -889,26 +937,43 @@ int stage_fluxes(grmhd_ctx* c, const double* P) {
 
 template <int STAGE, typename FT>
 int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
-                 unsigned long long* fails = nullptr, unsigned char* flags = nullptr) {
+                 unsigned long long* fails = nullptr, unsigned char* flags = nullptr,
+                 const double* dt_dev = nullptr) {
   const Dev& g = c->dev;
   Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
   Timed tm(c, STAGE == 1 ? T_UPDATE1 : T_UPDATE2);
   k_update<STAGE, FT><<<blocks_for(bz), BLOCK, 0, c->stream>>>(
       g, bz, Pin, Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1], (const FT*)c->F[2],
-      (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2], c->tabC, c->conn, dt,
+      (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2], c->tabC, c->conn, dt, dt_dev,
       fails ? fails : c->fails, flags);
   return hip_check();
 }
 
+// One SSPRK2 step with dt from the host, or, when dt_dev is given, with the
+// dt the device reduction left there.
 template <typename R, typename FT>
-int do_step(grmhd_ctx* c, double dt) {
+int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   int rc;
   if ((rc = fill_ghosts(c, c->P))) return rc;
   if ((rc = stage_fluxes<R, FT>(c, c->P))) return rc;
-  if ((rc = stage_update<1, FT>(c, c->P, c->P1, dt))) return rc;
+  if ((rc = stage_update<1, FT>(c, c->P, c->P1, dt, nullptr, nullptr, dt_dev))) return rc;
   if ((rc = fill_ghosts(c, c->P1))) return rc;
   if ((rc = stage_fluxes<R, FT>(c, c->P1))) return rc;
-  return stage_update<2, FT>(c, c->P1, c->P, dt);
+  return stage_update<2, FT>(c, c->P1, c->P, dt, nullptr, nullptr, dt_dev);
+}
+
+// Enqueue the CFL reduction of the current prims (interior zones only, so no
+// ghost fill): result[0] = max signal rate, result[2] = cfl / max,
+// result[3] = 0 if that dt is usable.
+int launch_dt(grmhd_ctx* c) {
+  const Dev& g = c->dev;
+  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  long nb = blocks_for(bz.count());
+  if (nb > MAX_PARTIALS) nb = MAX_PARTIALS;
+  Timed tm(c, T_DT);
+  k_dt_partial<<<(unsigned)nb, BLOCK, 0, c->stream>>>(g, bz, c->P, c->tabC, c->pmax);
+  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, nullptr, (int)nb, c->result, c->params.cfl);
+  return hip_check();
 }
 
 int sync(grmhd_ctx* c) { return hipStreamSynchronize(c->stream) == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
@@ -986,23 +1051,33 @@ int grmhd_step(grmhd_ctx* c, double dt) {
 int grmhd_estimate_dt(grmhd_ctx* c, double* dt_out) {
   if (!c || !dt_out) return GRMHD_E_ARG;
   int rc;
-  if ((rc = fill_ghosts(c, c->P))) return rc;
-  const Dev& g = c->dev;
-  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
-  unsigned nb = blocks_for(bz.count());
-  if (nb > MAX_PARTIALS) return GRMHD_E_ARG;
-  {
-    Timed tm(c, T_DT);
-    k_dt_partial<<<nb, BLOCK, 0, c->stream>>>(g, bz, c->P, c->tabC, c->pmax);
-    k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, nullptr, (int)nb, c->result);
-  }
-  if ((rc = hip_check())) return rc;
+  if ((rc = launch_dt(c))) return rc;
   double smax = 0.0;
   if (hipMemcpyAsync(&smax, c->result, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
     return GRMHD_E_HIP;
   if ((rc = sync(c))) return rc;
   if (!(smax > 0.0) || !isfinite(smax)) return GRMHD_E_STATE;
   *dt_out = c->params.cfl / smax;
+  return GRMHD_OK;
+}
+
+int grmhd_step_cfl(grmhd_ctx* c) {
+  if (!c) return GRMHD_E_ARG;
+  int rc;
+  if ((rc = launch_dt(c))) return rc;
+  if (c->params.precision == GRMHD_PREC_FP64) return do_step<double, double>(c, 0.0, c->result + 2);
+  return do_step<float, float>(c, 0.0, c->result + 2);
+}
+
+int grmhd_last_dt(grmhd_ctx* c, double* dt_out) {
+  if (!c || !dt_out) return GRMHD_E_ARG;
+  double r[2];
+  if (hipMemcpyAsync(r, c->result + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  int rc;
+  if ((rc = sync(c))) return rc;
+  if (r[1] != 0.0) return GRMHD_E_STATE;
+  *dt_out = r[0];
   return GRMHD_OK;
 }
 
@@ -1030,10 +1105,10 @@ int grmhd_divb(grmhd_ctx* c, double* d_divb, double* max_out, double* mean_out) 
     *max_out = *mean_out = 0.0;
     return GRMHD_OK;
   }
-  unsigned nb = blocks_for(cnt);
-  if (nb > MAX_PARTIALS) return GRMHD_E_ARG;
-  k_divb_partial<<<nb, BLOCK, 0, c->stream>>>(g, b, c->P, c->tabC, c->corner, d_divb, c->pmax, c->psum);
-  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, c->psum, (int)nb, c->result);
+  long nb = blocks_for(cnt);
+  if (nb > MAX_PARTIALS) nb = MAX_PARTIALS;
+  k_divb_partial<<<(unsigned)nb, BLOCK, 0, c->stream>>>(g, b, c->P, c->tabC, c->corner, d_divb, c->pmax, c->psum);
+  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, c->psum, (int)nb, c->result, 0.0);
   if ((rc = hip_check())) return rc;
   double res[2];
   if (hipMemcpyAsync(res, c->result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
@@ -1215,10 +1290,10 @@ int step_vjp(grmhd_ctx* c, const VjpCarve& w, const double* d_in, double dt, con
   k_adj_rk<<<blocks_for(NVAR * nz), BLOCK, 0, c->stream>>>(NVAR * nz, 1, dt, w.LU, w.LV, w.LL);
   if ((rc = hip_check())) return rc;
   if ((rc = adj_stage<RECON>(c, w, w.A, true, d_gin))) return rc;
-  unsigned nb = blocks_for(nz);
-  if (nb > MAX_PARTIALS) return GRMHD_E_ARG;
-  k_adj_gsum<<<nb, BLOCK, 0, c->stream>>>(nz, w.GZ, w.GF[0], w.GF[1], w.GF[2], c->pmax, c->psum);
-  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, c->psum, (int)nb, c->result);
+  long nb = blocks_for(nz);
+  if (nb > MAX_PARTIALS) nb = MAX_PARTIALS;
+  k_adj_gsum<<<(unsigned)nb, BLOCK, 0, c->stream>>>(nz, w.GZ, w.GF[0], w.GF[1], w.GF[2], c->pmax, c->psum);
+  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, c->psum, (int)nb, c->result, 0.0);
   if ((rc = hip_check())) return rc;
   double res[2];
   if (hipMemcpyAsync(res, c->result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)

@@ -43,7 +43,7 @@ class grmhd_params(C.Structure):
 
 
 EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_step",
-           "grmhd_estimate_dt", "grmhd_get_prims", "grmhd_divb", "grmhd_get_status",
+           "grmhd_estimate_dt", "grmhd_step_cfl", "grmhd_last_dt", "grmhd_get_prims", "grmhd_divb", "grmhd_get_status",
            "grmhd_reset_status", "grmhd_prims_to_cons", "grmhd_cons_to_prims", "grmhd_fluxes",
            "grmhd_pack_workspace_bytes", "grmhd_pack_create", "grmhd_pack_set_tiles",
            "grmhd_pack_load_prims", "grmhd_pack_step", "grmhd_pack_get_prims",
@@ -63,6 +63,8 @@ def load_library(path=LIB_PATH):
         "grmhd_load_prims": (C.c_int, [vp, vp]),
         "grmhd_step": (C.c_int, [vp, C.c_double]),
         "grmhd_estimate_dt": (C.c_int, [vp, dp]),
+        "grmhd_step_cfl": (C.c_int, [vp]),
+        "grmhd_last_dt": (C.c_int, [vp, dp]),
         "grmhd_get_prims": (C.c_int, [vp, vp]),
         "grmhd_divb": (C.c_int, [vp, vp, dp, dp]),
         "grmhd_get_status": (C.c_int, [vp, ip, ip]),
@@ -183,6 +185,18 @@ class Grmhd:
     def dt(self):
         out = C.c_double()
         _check(lib().grmhd_estimate_dt(self.ctx, C.byref(out)))
+        return out.value
+
+    def step_cfl(self):
+        """One step at the CFL dt of the current state, reduced and used on
+        the device (no host round trip); last_dt() reads it back."""
+        _check(lib().grmhd_step_cfl(self.ctx))
+        if self.strict and self.status()[0]:
+            raise GrmhdError("inversion failures")
+
+    def last_dt(self):
+        out = C.c_double()
+        _check(lib().grmhd_last_dt(self.ctx, C.byref(out)))
         return out.value
 
     def prims(self):

@@ -2,8 +2,17 @@
 central finite differences (h = 1e-6 along seeded relative directions).
 
 Loss: sum over the inner five radial zones (all x2, x3) of rho * u after the
-steps, dt fixed from the initial state.  Directions v = P * xi on the
-interior prims (xi ~ N(0, 1), seeded) together with dgamma = gamma * xi_g.
+steps, dt fixed from the initial state.
+
+Directions: v_var(i, j, k) = xi_var(i) * P_var(i, j, k) on the interior prims,
+xi ~ N(0, 1) seeded per variable and radial index, together with
+dgamma = gamma * xi_g.  A perturbation of this form leaves every region where
+a primitive has zero gradient (the axisymmetric fields along x3, the
+theta-independent atmosphere along x2, the zero field outside the torus)
+with zero gradient, so no MC limiter or WENO weight is moved off its branch:
+there the step is differentiable and the adjoint is exact.  (White noise on
+such data puts every limiter at its zero-slope kink, where the step has
+direction-dependent one-sided derivatives but no gradient.)
 """
 
 import numpy as np
@@ -22,6 +31,14 @@ def _setup():
     from paper_2408_01361_amd import grmhd as gr
     from paper_2408_01361_amd import autograd as ag
     return torch, gr, ag
+
+
+def direction(rng, P):
+    v = np.zeros_like(P)
+    I = interior(P)
+    xi = rng.normal(size=(8, 1, 1, I.shape[3]))
+    interior(v)[...] = I * xi
+    return v
 
 
 def loss_np(P, nr=5):
@@ -56,8 +73,7 @@ def adjoint_vs_fd(n, nsteps, recon, ndir, seed=5, h=1e-6):
     rng = np.random.default_rng(seed)
     rows = []
     for q in range(ndir):
-        v = np.zeros_like(P)
-        interior(v)[...] = interior(P) * rng.normal(size=interior(P).shape)
+        v = direction(rng, P)
         vg = gam * rng.normal()
         lp = gpu_loss(torch, gr, grid, P + h * v, gam + h * vg, recon, dt, nsteps)
         lm = gpu_loss(torch, gr, grid, P - h * v, gam - h * vg, recon, dt, nsteps)
@@ -85,7 +101,12 @@ def test_adjoint_torus64_mc_8_steps():
 
 
 def test_adjoint_against_oracle_fd():
-    """The same gradient against central differences of the CPU oracle."""
+    """The same gradient against central differences of the CPU oracle.
+
+    h = 1e-7 here: on this coarse 24 x 24 x 8 torus (288 inversion failures in
+    three steps) two of the four seeded directions cross a limiter branch
+    switch between 1e-7 and 1e-6 -- the oracle's forward and backward
+    difference quotients disagree at h = 1e-6 and agree at 1e-7."""
     torch, gr, ag = _setup()
     gam = 13.0 / 9.0
     grid, P, _ = fm_torus(24, 24, 8)
@@ -99,10 +120,9 @@ def test_adjoint_against_oracle_fd():
     (I[0, :, :, :5] * I[1, :, :, :5]).sum().backward()
     gP, gG = x.grad.cpu().numpy(), float(gt.grad)
     rng = np.random.default_rng(9)
-    h = 1e-6
+    h = 1e-7
     for _ in range(4):
-        v = np.zeros_like(P)
-        interior(v)[...] = interior(P) * rng.normal(size=interior(P).shape)
+        v = direction(rng, P)
         vg = gam * rng.normal()
         Lp = loss_np(oracle.run(oracle.cfg(grid, gam=gam + h * vg, recon=RECON_MC), P + h * v, dt, 3)[0])
         Lm = loss_np(oracle.run(oracle.cfg(grid, gam=gam - h * vg, recon=RECON_MC), P - h * v, dt, 3)[0])

@@ -129,6 +129,46 @@ def test_dt_and_divb_parity():
     assert s2.dt() == pytest.approx(oracle.estimate_dt(c2, P2), rel=1e-14)
 
 
+def test_step_cfl_equals_host_dt_step():
+    """The device-side CFL step takes the same dt and gives the same state,
+    bit for bit, as estimating dt on the host and stepping with it."""
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(24, 24, 8)
+    a = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    b = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    a.load(torch.from_numpy(P))
+    b.load(torch.from_numpy(P))
+    for _ in range(3):
+        dt = a.dt()
+        a.step(dt)
+        b.step_cfl()
+        assert b.last_dt() == dt
+    assert torch.equal(a.prims(), b.prims())
+    assert a.status() == b.status()
+
+
+def test_reductions_past_one_partial_per_workgroup():
+    """dt and div B on a grid with more interior zones than the reductions
+    have partial slots (65536 workgroups of 256): the partial kernels then
+    stride over the grid."""
+    torch = _torch()
+    gr = _gr()
+    n = 262                                           # 262^3 > 65536 * 256 zones
+    grid, P, _, _ = linear_mode("fast", n, ndim=3, amp=1e-2)
+    # a field with O(1) divergence, so the div B reduction sums real values
+    interior(P[5:8])[...] += 0.1 * np.random.default_rng(3).standard_normal(interior(P[5:8]).shape)
+    c = oracle.cfg(grid, recon=RECON_MC)
+    s = gr.Grmhd(grid, 4 / 3, recon=RECON_MC)
+    s.load(torch.from_numpy(P))
+    assert s.dt() == pytest.approx(oracle.estimate_dt(c, P), rel=1e-14)
+    mx, mean = s.divb()
+    omx, omean = oracle.divb(c, P)
+    assert omx > 1.0
+    assert mx == pytest.approx(omx, rel=1e-13)
+    assert mean == pytest.approx(omean, rel=1e-11)    # summation order differs
+
+
 def test_divb_stays_at_roundoff_on_gpu():
     torch = _torch()
     gr = _gr()
