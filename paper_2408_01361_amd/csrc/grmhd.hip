@@ -14,6 +14,7 @@
 // are variable-major and x1-fastest, so each wavefront's loads and stores of
 // one variable are contiguous.
 #include <hip/hip_cooperative_groups.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -106,8 +107,10 @@ inline Sched make_sched(const Box& b, int kg) {
 }
 inline unsigned blocks_for(const Sched& s) { return (unsigned)((long)s.nchunk * s.kgroups * s.kg); }
 
-__device__ __forceinline__ bool sched_index(const Sched& s, int& i, int& j, int& k) {
-  const unsigned nb = gridDim.x, bid = blockIdx.x;
+// bid / nb: this workgroup's index and the workgroup count of the launch (or
+// of its part that covers this box, when the part starts at a multiple of 8).
+__device__ __forceinline__ bool sched_index(const Sched& s, unsigned bid, unsigned nb, int& i, int& j,
+                                            int& k) {
   const unsigned x = bid & 7u, slot = bid >> 3;
   const unsigned q = nb >> 3, r = nb & 7u;
   const unsigned w = x * q + (x < r ? x : r) + slot;
@@ -264,23 +267,14 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ P, long nz
   }
 }
 
-// Local Lax-Friedrichs flux through the lower d-face of zone (i, j, k) for
-// every face of `box`; pole faces get zero flux.  FT is the stored type.
-template <int D, int RECON, typename R, typename FT>
-__device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict__ P,
-                                          const double* __restrict__ tab, FT* __restrict__ F, int i,
-                                          int j, int k) {
-  long c = zid(g, i, j, k);
-  if (D == 2 && ((g.pole_lo && j == 0) || (g.pole_hi && j == g.n2))) {
-#pragma unroll
-    for (int v = 0; v < NVAR; v++) F[v * g.nz + c] = (FT)0;
-    return;
-  }
-  const long s = D == 1 ? 1 : (D == 2 ? (long)g.s1 : g.plane);
-  R qL[NVAR], qR[NVAR];
-  recon_pair<RECON, R>(P, g.nz, c, s, (R)g.weno_eps, qL, qR);
+// Local Lax-Friedrichs flux of one face from its left and right states qL,
+// qR, with the face metric at table position q2; stored at padded index c.
+template <int D, typename R, typename FT>
+__device__ __forceinline__ void face_llf(const Dev& g, const R qL[NVAR], const R qR[NVAR],
+                                         const double* __restrict__ tab, long q2, FT* __restrict__ F,
+                                         long c) {
   PointMetric<R> m;
-  load_metric<R>(tab, g.plane, pid(g, i, j), m);
+  load_metric<R>(tab, g.plane, q2, m);
   const R gam = (R)g.gam;
   R FL[NVAR], UL[NVAR], cpl, cml;
   {
@@ -305,12 +299,51 @@ __device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict
     F[v * g.nz + c] = (FT)llf(FL[v], FR[v], UL[v], UR[v], cmax);
 }
 
+template <int D>
+__device__ __forceinline__ bool pole_face(const Dev& g, int j) {
+  return D == 2 && ((g.pole_lo && j == 0) || (g.pole_hi && j == g.n2));
+}
+
+// Local Lax-Friedrichs flux through the lower d-face of zone (i, j, k); pole
+// faces get zero flux.  FT is the stored type.
 template <int D, int RECON, typename R, typename FT>
-__global__ void __launch_bounds__(BLOCK) k_flux(Dev g, Sched box, const double* __restrict__ P,
-                                                const double* __restrict__ tab, FT* __restrict__ F) {
+__device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict__ P,
+                                          const double* __restrict__ tab, FT* __restrict__ F, int i,
+                                          int j, int k) {
+  long c = zid(g, i, j, k);
+  if (pole_face<D>(g, j)) {
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) F[v * g.nz + c] = (FT)0;
+    return;
+  }
+  const long s = D == 1 ? 1 : (D == 2 ? (long)g.s1 : g.plane);
+  R qL[NVAR], qR[NVAR];
+  recon_pair<RECON, R>(P, g.nz, c, s, (R)g.weno_eps, qL, qR);
+  face_llf<D, R, FT>(g, qL, qR, tab, pid(g, i, j), F, c);
+}
+
+#ifndef FLUX_WAVES
+#define FLUX_WAVES 4
+#endif
+
+// All three face directions in one launch: workgroups [0, nb1) take x1
+// faces, [nb1, nb1 + nb2) x2 faces, the rest x3 faces (nb1 and nb2 are
+// multiples of 8, so each part keeps the XCD-aware order of its schedule).
+template <int RECON, typename R, typename FT>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FLUX_WAVES, 8)))
+k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsigned nb3,
+           const double* __restrict__ P, const double* __restrict__ tabF1,
+           const double* __restrict__ tabF2, const double* __restrict__ tabC, FT* __restrict__ F1,
+           FT* __restrict__ F2, FT* __restrict__ F3) {
+  const unsigned b = blockIdx.x;
   int i, j, k;
-  if (!sched_index(box, i, j, k)) return;
-  flux_face<D, RECON, R, FT>(g, P, tab, F, i, j, k);
+  if (b < nb1) {
+    if (sched_index(b1, b, nb1, i, j, k)) flux_face<1, RECON, R, FT>(g, P, tabF1, F1, i, j, k);
+  } else if (b < nb1 + nb2) {
+    if (sched_index(b2, b - nb1, nb2, i, j, k)) flux_face<2, RECON, R, FT>(g, P, tabF2, F2, i, j, k);
+  } else {
+    if (sched_index(b3, b - nb1 - nb2, nb3, i, j, k)) flux_face<3, RECON, R, FT>(g, P, tabC, F3, i, j, k);
+  }
 }
 
 // Flux-CT edge EMFs at the lower (x1, x2, x3) corner of zone (i, j, k):
@@ -340,7 +373,7 @@ __global__ void __launch_bounds__(BLOCK) k_emf(Dev g, Sched box, const FT* __res
                                                FT* __restrict__ E1, FT* __restrict__ E2,
                                                FT* __restrict__ E3) {
   int i, j, k;
-  if (!sched_index(box, i, j, k)) return;
+  if (!sched_index(box, blockIdx.x, gridDim.x, i, j, k)) return;
   emf_edge<FT>(g, F1, F2, F3, E1, E2, E3, i, j, k);
 }
 
@@ -594,7 +627,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDA
                                                   unsigned long long* fails,
                                                   unsigned char* __restrict__ flags) {
   int i, j, k;
-  if (!sched_index(box, i, j, k)) return;
+  if (!sched_index(box, blockIdx.x, gridDim.x, i, j, k)) return;
   if (dt_dev) dt = *dt_dev;
   update_zone<STAGE, FT>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i, j, k);
 }
@@ -636,7 +669,7 @@ __device__ void block_reduce(double& mx, double& sm) {
 }
 
 // Per zone sum_d max(|c+|, |c-|)/dx_d over axes with more than one zone;
-// block maxima to partial[].  Grid-stride over the box, so any grid size
+// workgroup maxima to partial[].  Grid-stride over the box, so any grid size
 // reduces through at most MAX_PARTIALS partials.
 __global__ void __launch_bounds__(BLOCK) k_dt_partial(Dev g, Box box, const double* __restrict__ P,
                                                       const double* __restrict__ tabC,
@@ -713,8 +746,8 @@ __global__ void __launch_bounds__(BLOCK) k_divb_partial(Dev g, Box box, const do
 
 // Single-block final pass over n partials: out[0] = max, out[1] = sum.  With
 // cfl > 0 (the dt reduction) also out[2] = cfl / max, the step the update
-// kernels read on the device, and out[3] = 0 when that dt is usable, 1 when
-// the maximum signal speed is not positive and finite (out[2] is then 0, so a
+// kernels can read on the device, and out[3] = 0 when that dt is usable, 1
+// when the maximum rate is not positive and finite (out[2] is then 0, so a
 // step taken with it leaves the state unchanged).
 __global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* pmax, const double* psum,
                                                         int n, double* out, double cfl) {
@@ -872,42 +905,51 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
 
 int hip_check() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
 
-enum { T_BC = 0, T_FLUX1, T_FLUX2, T_FLUX3, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_NCLASS };
+enum { T_BC = 0, T_FLUX, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_NCLASS };
 
-// Brackets one launch with a pair of events when timing is enabled.
-struct Timed {
-  grmhd_ctx* c;
-  int slot = -1;
-  Timed(grmhd_ctx* ctx, int cls) : c(ctx) {
-    if (!c->timing) return;
-    if (c->nmarks == c->capmarks) {
-      int cap = c->capmarks ? 2 * c->capmarks : 256;
-      auto* m = (grmhd_ctx::Mark*)realloc(c->marks, sizeof(grmhd_ctx::Mark) * cap);
-      if (!m) return;
-      for (int q = c->capmarks; q < cap; q++) {
-        if (hipEventCreate(&m[q].a) != hipSuccess || hipEventCreate(&m[q].b) != hipSuccess) {
-          c->marks = m;
-          c->timing = false;  // no events: stop timing rather than fail the step
-          return;
-        }
-      }
-      c->marks = m;
-      c->capmarks = cap;
-    }
-    slot = c->nmarks++;
-    c->marks[slot].cls = cls;
-    (void)hipEventRecord(c->marks[slot].a, c->stream);
-  }
-  ~Timed() {
-    if (slot >= 0) (void)hipEventRecord(c->marks[slot].b, c->stream);
-  }
+// Start/stop events of one launch of class cls while timing is enabled (null
+// events otherwise, or when no more events can be created).
+struct EvPair {
+  hipEvent_t a = nullptr, b = nullptr;
 };
+EvPair timing_events(grmhd_ctx* c, int cls) {
+  EvPair e;
+  if (!c->timing) return e;
+  if (c->nmarks == c->capmarks) {
+    int cap = c->capmarks ? 2 * c->capmarks : 256;
+    auto* m = (grmhd_ctx::Mark*)realloc(c->marks, sizeof(grmhd_ctx::Mark) * cap);
+    if (!m) return e;
+    c->marks = m;
+    for (int q = c->capmarks; q < cap; q++) {
+      if (hipEventCreate(&m[q].a) != hipSuccess || hipEventCreate(&m[q].b) != hipSuccess) {
+        c->timing = false;  // no events: stop timing rather than fail the step
+        return e;
+      }
+      c->capmarks = q + 1;
+    }
+  }
+  const int slot = c->nmarks++;
+  c->marks[slot].cls = cls;
+  e.a = c->marks[slot].a;
+  e.b = c->marks[slot].b;
+  return e;
+}
 
-int fill_ghosts(grmhd_ctx* c, double* P) {
-  Timed tm(c, T_BC);
-  k_bc<<<blocks_for(ghost_count(c->dev)), BLOCK, 0, c->stream>>>(c->dev, P);
+// Launch a kernel of class cls on the context's stream.  While timing, the
+// start and stop events travel with the dispatch itself (hipExtLaunchKernel),
+// so timing adds no marker packets between kernels.
+template <typename F, typename... Args>
+int launch(grmhd_ctx* c, int cls, F kernel, unsigned nblocks, Args... args) {
+  EvPair e = timing_events(c, cls);
+  hipExtLaunchKernelGGL(kernel, dim3(nblocks), dim3(BLOCK), 0, c->stream, e.a, e.b, 0, args...);
   return hip_check();
 }
+
+int fill_ghosts(grmhd_ctx* c, double* P) {
+  return launch(c, T_BC, k_bc, blocks_for(ghost_count(c->dev)), c->dev, P);
+}
+
+inline unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
 
 // Flux and EMF kernels of one stage, reading the (ghost-filled) prims P.
 template <typename R, typename FT>
@@ -919,20 +961,19 @@ int stage_fluxes(grmhd_ctx* c, const double* P) {
   Sched b1 = make_sched(make_box(0, g.n1, -1, g.n2, -1, g.n3), c->kg_flux);
   Sched b2 = make_sched(make_box(-1, g.n1, 0, g.n2, -1, g.n3), c->kg_flux);
   Sched b3 = make_sched(make_box(-1, g.n1, -1, g.n2, 0, g.n3), c->kg_flux);
-  if (c->params.recon == GRMHD_RECON_MC) {
-    { Timed tm(c, T_FLUX1); k_flux<1, GRMHD_RECON_MC, R, FT><<<blocks_for(b1), BLOCK, 0, c->stream>>>(g, b1, P, c->tabF1, F1); }
-    { Timed tm(c, T_FLUX2); k_flux<2, GRMHD_RECON_MC, R, FT><<<blocks_for(b2), BLOCK, 0, c->stream>>>(g, b2, P, c->tabF2, F2); }
-    { Timed tm(c, T_FLUX3); k_flux<3, GRMHD_RECON_MC, R, FT><<<blocks_for(b3), BLOCK, 0, c->stream>>>(g, b3, P, c->tabC, F3); }
-  } else {
-    { Timed tm(c, T_FLUX1); k_flux<1, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b1), BLOCK, 0, c->stream>>>(g, b1, P, c->tabF1, F1); }
-    { Timed tm(c, T_FLUX2); k_flux<2, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b2), BLOCK, 0, c->stream>>>(g, b2, P, c->tabF2, F2); }
-    { Timed tm(c, T_FLUX3); k_flux<3, GRMHD_RECON_WENO5, R, FT><<<blocks_for(b3), BLOCK, 0, c->stream>>>(g, b3, P, c->tabC, F3); }
-  }
+  const unsigned n1 = round8(blocks_for(b1)), n2 = round8(blocks_for(b2)), n3 = blocks_for(b3);
+  const double* Pc = P;
+  int rc;
+  if (c->params.recon == GRMHD_RECON_MC)
+    rc = launch(c, T_FLUX, k_flux_all<GRMHD_RECON_MC, R, FT>, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3,
+                Pc, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3);
+  else
+    rc = launch(c, T_FLUX, k_flux_all<GRMHD_RECON_WENO5, R, FT>, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3,
+                Pc, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3);
+  if (rc) return rc;
   Sched be = make_sched(make_box(0, g.n1, 0, g.n2, 0, g.n3), c->kg_flux);
-  Timed tm(c, T_EMF);
-  k_emf<FT><<<blocks_for(be), BLOCK, 0, c->stream>>>(g, be, F1, F2, F3, (FT*)c->E[0],
-                                                                (FT*)c->E[1], (FT*)c->E[2]);
-  return hip_check();
+  return launch(c, T_EMF, k_emf<FT>, blocks_for(be), g, be, (const FT*)F1, (const FT*)F2, (const FT*)F3,
+                (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2]);
 }
 
 template <int STAGE, typename FT>
@@ -941,12 +982,10 @@ int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
                  const double* dt_dev = nullptr) {
   const Dev& g = c->dev;
   Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
-  Timed tm(c, STAGE == 1 ? T_UPDATE1 : T_UPDATE2);
-  k_update<STAGE, FT><<<blocks_for(bz), BLOCK, 0, c->stream>>>(
-      g, bz, Pin, Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1], (const FT*)c->F[2],
-      (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2], c->tabC, c->conn, dt, dt_dev,
-      fails ? fails : c->fails, flags);
-  return hip_check();
+  return launch(c, STAGE == 1 ? T_UPDATE1 : T_UPDATE2, k_update<STAGE, FT>, blocks_for(bz), g, bz, Pin,
+                Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1], (const FT*)c->F[2],
+                (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2], (const double*)c->tabC,
+                (const double*)c->conn, dt, dt_dev, fails ? fails : c->fails, flags);
 }
 
 // One SSPRK2 step with dt from the host, or, when dt_dev is given, with the
@@ -970,9 +1009,11 @@ int launch_dt(grmhd_ctx* c) {
   Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
   long nb = blocks_for(bz.count());
   if (nb > MAX_PARTIALS) nb = MAX_PARTIALS;
-  Timed tm(c, T_DT);
-  k_dt_partial<<<(unsigned)nb, BLOCK, 0, c->stream>>>(g, bz, c->P, c->tabC, c->pmax);
-  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, nullptr, (int)nb, c->result, c->params.cfl);
+  EvPair e = timing_events(c, T_DT);
+  hipExtLaunchKernelGGL(k_dt_partial, dim3((unsigned)nb), dim3(BLOCK), 0, c->stream, e.a, nullptr, 0, g,
+                        bz, (const double*)c->P, (const double*)c->tabC, c->pmax);
+  hipExtLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, c->stream, nullptr, e.b, 0,
+                        (const double*)c->pmax, (const double*)nullptr, (int)nb, c->result, c->params.cfl);
   return hip_check();
 }
 
@@ -1022,7 +1063,10 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
   k_geometry<<<blocks_for(g.plane), BLOCK, 0, c->stream>>>(g, c->tabC, c->tabF1, c->tabF2, c->corner,
                                                            c->conn);
+  // failure count zero; no dt reduced yet (result[3] = 1)
+  static const double result0[8] = {0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
   if (hipMemsetAsync(c->fails, 0, sizeof(unsigned long long), c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->result, result0, sizeof(result0), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hip_check() != GRMHD_OK) {
     delete c;
     return GRMHD_E_HIP;

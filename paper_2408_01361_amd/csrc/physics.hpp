@@ -110,53 +110,91 @@ using f64::llf;
 using f32::llf;
 using fdual::llf;
 
-// WENO5 value at the right edge of zone c from point values a..e.  The three
-// nonlinear weights d_k/(eps + beta_k)^2 are formed over a common
-// denominator, so one division normalises them.  (Contraction is allowed
-// here: no flat-space test depends on WENO5 rounding.)
+// WENO5 (Jiang-Shu weights d_k / (eps + beta_k)^2, d = (1, 6, 3)/10) from
+// point values a..e of zones c-2..c+2: the value at the right edge of zone c.
+// The smoothness indicator of each three-zone stencil is formed by an
+// expression that is symmetric under reversing the stencil -- (x + z) - 2y,
+// fma(-4, y, fma(3, centre, outer)), y - z squared -- so a zone's left-edge
+// value, weno5(e, d, c, b, a), could reuse its right edge's indicators and
+// weight products bit for bit.  Arranged for few
+// operations: every indicator is scaled by 12 (12 beta_k = 13 t_k^2 + 3 u_k^2,
+// with 12 eps), which leaves the weights unchanged; the factors 1/10 of d and
+// 1/6 of the candidate polynomials cancel or move into the single division
+// that normalises the weights over a common denominator.
+//
+// FP64: contraction into fused multiply-adds allowed (no flat-space test
+// depends on WENO5 rounding).
 #pragma clang fp contract(fast)
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e, double eps) {
-  typedef double R;
-  const R r6 = 1.0 / 6.0, k1312 = 13.0 / 12.0;
-  R p0 = ((R)2 * a - (R)7 * b + (R)11 * c) * r6;
-  R p1 = (-b + (R)5 * c + (R)2 * d) * r6;
-  R p2 = ((R)2 * c + (R)5 * d - e) * r6;
-  R t0 = a - (R)2 * b + c, u0 = a - (R)4 * b + (R)3 * c;
-  R t1 = b - (R)2 * c + d, u1 = b - d;
-  R t2 = c - (R)2 * d + e, u2 = (R)3 * c - (R)4 * d + e;
-  R s0 = eps + (k1312 * t0 * t0 + (R)0.25 * u0 * u0);
-  R s1 = eps + (k1312 * t1 * t1 + (R)0.25 * u1 * u1);
-  R s2 = eps + (k1312 * t2 * t2 + (R)0.25 * u2 * u2);
+namespace wd {
+typedef double R;
+// (eps + beta)^2 of the stencils (a, b, c), (b, c, d), (c, d, e), scaled by 144
+__device__ __forceinline__ void indicators(R a, R b, R c, R d, R e, R eps, R& s0, R& s1, R& s2) {
+  const R eps12 = (R)12 * eps;
+  R t0 = (a + c) - (R)2 * b, u0 = fma((R)-4, b, fma((R)3, c, a));
+  R t1 = (b + d) - (R)2 * c, u1 = b - d;
+  R t2 = (c + e) - (R)2 * d, u2 = fma((R)-4, d, fma((R)3, c, e));
+  s0 = fma((R)13 * t0, t0, fma((R)3 * u0, u0, eps12));
+  s1 = fma((R)13 * t1, t1, fma((R)3 * u1, u1, eps12));
+  s2 = fma((R)13 * t2, t2, fma((R)3 * u2, u2, eps12));
   s0 *= s0;
   s1 *= s1;
   s2 *= s2;
-  R w0 = (R)0.1 * (s1 * s2), w1 = (R)0.6 * (s0 * s2), w2 = (R)0.3 * (s0 * s1);
-  return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+}
+// weighted value with weight products w0 = s1 s2, w1 = 6 s0 s2, w2 = 3 s0 s1
+__device__ __forceinline__ R combine(R a, R b, R c, R d, R e, R s12, R s02, R s01) {
+  R p0 = fma((R)11, c, fma((R)-7, b, (R)2 * a));
+  R p1 = fma((R)2, d, fma((R)5, c, -b));
+  R p2 = fma((R)5, d, fma((R)2, c, -e));
+  R w0 = s12, w1 = (R)6 * s02, w2 = (R)3 * s01;
+  return fma(w0, p0, fma(w1, p1, w2 * p2)) / ((R)6 * ((w0 + w1) + w2));
+}
+}  // namespace wd
+
+__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e, double eps) {
+  double s0, s1, s2;
+  wd::indicators(a, b, c, d, e, eps, s0, s1, s2);
+  return wd::combine(a, b, c, d, e, s1 * s2, s0 * s2, s0 * s1);
 }
 
 // FP32 form: the indicators are normalised by the smallest (eps + beta_k),
 // so the smoothest stencil keeps its linear weight, the others' ratios can
 // only shrink (underflow to zero weight, never to 0/0), and the divisions are
-// hardware reciprocals (v_rcp_f32).
-__device__ __forceinline__ float weno5(float a, float b, float c, float d, float e, float eps) {
-  const float r6 = 1.0f / 6.0f, k1312 = 13.0f / 12.0f;
-  float p0 = (2.0f * a - 7.0f * b + 11.0f * c) * r6;
-  float p1 = (-b + 5.0f * c + 2.0f * d) * r6;
-  float p2 = (2.0f * c + 5.0f * d - e) * r6;
-  float t0 = a - 2.0f * b + c, u0 = a - 4.0f * b + 3.0f * c;
-  float t1 = b - 2.0f * c + d, u1 = b - d;
-  float t2 = c - 2.0f * d + e, u2 = 3.0f * c - 4.0f * d + e;
-  float s0 = eps + (k1312 * t0 * t0 + 0.25f * u0 * u0);
-  float s1 = eps + (k1312 * t1 * t1 + 0.25f * u1 * u1);
-  float s2 = eps + (k1312 * t2 * t2 + 0.25f * u2 * u2);
-  float im = __builtin_amdgcn_rcpf(fminf(fminf(s0, s1), s2));
-  float r0 = s0 * im, r1 = s1 * im, r2 = s2 * im;
-  float w0 = 0.1f * __builtin_amdgcn_rcpf(r0 * r0), w1 = 0.6f * __builtin_amdgcn_rcpf(r1 * r1),
-        w2 = 0.3f * __builtin_amdgcn_rcpf(r2 * r2);
+// hardware reciprocals (v_rcp_f32).  Same symmetric indicator forms.
+namespace wf {
+typedef float R;
+__device__ __forceinline__ void indicators(R a, R b, R c, R d, R e, R eps, R& q0, R& q1, R& q2) {
+  const R k1312 = 13.0f / 12.0f;
+  R t0 = (a + c) - 2.0f * b, u0 = fmaf(-4.0f, b, fmaf(3.0f, c, a));
+  R t1 = (b + d) - 2.0f * c, u1 = b - d;
+  R t2 = (c + e) - 2.0f * d, u2 = fmaf(-4.0f, d, fmaf(3.0f, c, e));
+  R s0 = eps + (k1312 * t0 * t0 + 0.25f * u0 * u0);
+  R s1 = eps + (k1312 * t1 * t1 + 0.25f * u1 * u1);
+  R s2 = eps + (k1312 * t2 * t2 + 0.25f * u2 * u2);
+  R im = __builtin_amdgcn_rcpf(fminf(fminf(s0, s1), s2));
+  R r0 = s0 * im, r1 = s1 * im, r2 = s2 * im;
+  // 1 / (normalised (eps + beta_k))^2
+  q0 = __builtin_amdgcn_rcpf(r0 * r0);
+  q1 = __builtin_amdgcn_rcpf(r1 * r1);
+  q2 = __builtin_amdgcn_rcpf(r2 * r2);
+}
+__device__ __forceinline__ R combine(R a, R b, R c, R d, R e, R q0, R q1, R q2) {
+  const R r6 = 1.0f / 6.0f;
+  R p0 = (2.0f * a - 7.0f * b + 11.0f * c) * r6;
+  R p1 = (-b + 5.0f * c + 2.0f * d) * r6;
+  R p2 = (2.0f * c + 5.0f * d - e) * r6;
+  R w0 = 0.1f * q0, w1 = 0.6f * q1, w2 = 0.3f * q2;
   return (w0 * p0 + w1 * p1 + w2 * p2) * __builtin_amdgcn_rcpf(w0 + w1 + w2);
 }
+}  // namespace wf
 
-// Dual-number WENO5 in the same single-division form as the FP64 one.
+__device__ __forceinline__ float weno5(float a, float b, float c, float d, float e, float eps) {
+  float q0, q1, q2;
+  wf::indicators(a, b, c, d, e, eps, q0, q1, q2);
+  return wf::combine(a, b, c, d, e, q0, q1, q2);
+}
+
+// Dual-number WENO5: the same weights, in the plain single-division form;
+// only its derivative part is used (local Jacobians of the adjoint).
 __device__ __forceinline__ Dual weno5(Dual a, Dual b, Dual c, Dual d, Dual e, Dual eps) {
   const Dual k1312 = 13.0 / 12.0;
   Dual p0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;

@@ -164,11 +164,12 @@ class Grmhd:
                               C.byref(self.params), C.c_void_p(self._ws_ptr), nbytes,
                               C.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
+        self._lib = L          # kept for __del__ at interpreter exit
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
         if ctx:
-            lib().grmhd_destroy(ctx)
+            self._lib.grmhd_destroy(ctx)
             self.ctx = None
 
     def load(self, prims):
@@ -240,7 +241,7 @@ class Grmhd:
         _check(lib().grmhd_fluxes(self.ctx, _ptr(p), _ptr(out)))
         return out
 
-    TIMING_CLASSES = ("bc", "flux1", "flux2", "flux3", "emf", "update1", "update2", "dt")
+    TIMING_CLASSES = ("bc", "flux", "emf", "update1", "update2", "dt")
 
     def step_vjp(self, prims_in, dt, gprims_out):
         """Adjoint of one step: (d loss/d prims_in, d loss/d gamma_ad)."""
@@ -304,6 +305,7 @@ class Pack:
                                    C.c_void_p(self.workspace.data_ptr() + off), nbytes,
                                    C.c_void_p(self.stream.cuda_stream)))
         self.h = h
+        self._lib = L
         gb, nd = C.c_int(), C.c_longlong()
         _check(L.grmhd_pack_info(self.h, C.byref(gb), C.byref(nd)))
         self.grid_blocks, self.prim_doubles = gb.value, nd.value
@@ -311,7 +313,7 @@ class Pack:
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            lib().grmhd_pack_destroy(h)
+            self._lib.grmhd_pack_destroy(h)
             self.h = None
 
     def set_tiles(self, n, t1, t2, t3):

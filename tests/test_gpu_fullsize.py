@@ -1,0 +1,159 @@
+"""GPU-vs-oracle parity at the full workload sizes, in the launch
+configuration bench.py times (default schedule, device-side CFL step), and
+at the edges of the parameter space: one-zone axes, ragged sizes, and a grid
+larger than one reduction partial per workgroup.
+
+The oracle runs whole steps here (OpenMP over x3 planes), so every zone is
+compared, to the same bar as the small cases: relative L1 per primitive at
+most 1e-12 per step, failure counts equal.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import GROUPS, rel_l1
+from workloads import (GridSpec, fm_torus, interior, linear_mode, torus_pack, BC_PERIODIC,
+                       METRIC_MINKOWSKI, RECON_MC, RECON_WENO5)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_01361_amd import grmhd as gr
+    return torch, gr
+
+
+def test_torus128_weno5_full_step_as_benchmarked():
+    """The benchmark workload itself: 128^3 magnetised torus, WENO5, FP64, one
+    device-side CFL step; dt and every zone against the oracle."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    grid, P, _ = fm_torus(128, 128, 128, seed=1, gamma=gam)
+    s = gr.Grmhd(grid, gam, recon=RECON_WENO5)
+    s.load(torch.from_numpy(P).cuda())
+    s.step_cfl()
+    dt = s.last_dt()
+    out = s.prims().cpu().numpy()
+    c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, nthreads=THREADS)
+    assert dt == pytest.approx(oracle.estimate_dt(c, P), rel=1e-14)
+    ref, fails, _ = oracle.run(c, P, dt, 1)
+    rel = rel_l1(out, ref)
+    print("128^3 WENO5 rel L1", rel, "failures", fails)
+    assert rel.max() <= TOL, rel
+    assert s.status()[0] == fails
+
+
+def test_torus192_fp64_full_step():
+    """The reduced-precision workload's grid in FP64 (the reference its error
+    is stated against): 192^3, WENO5, one step."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    grid, P, _ = fm_torus(192, 192, 192, seed=1, gamma=gam)
+    c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, nthreads=THREADS)
+    dt = oracle.estimate_dt(c, P)
+    s = gr.Grmhd(grid, gam, recon=RECON_WENO5)
+    s.load(torch.from_numpy(P).cuda())
+    s.step(dt)
+    out = s.prims().cpu().numpy()
+    ref, fails, _ = oracle.run(c, P, dt, 1)
+    rel = rel_l1(out, ref)
+    print("192^3 WENO5 rel L1", rel)
+    assert rel.max() <= TOL, rel
+    assert s.status()[0] == fails
+
+
+def test_full_pack_320_blocks_against_oracle():
+    """The batched workload: all 320 blocks, one pack step against the oracle
+    block by block (relative L1 over the whole pack)."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    g, blocks, _ = torus_pack(nblocks=320, n_global=128, sizes=(16, 32, 64), probs=(0.6, 0.3, 0.1),
+                              seed=7, torus_seed=1, gamma=gam)
+    _, Pg, _ = fm_torus(128, 128, 128, seed=1, gamma=gam)
+    dt = oracle.estimate_dt(oracle.cfg(g, gam=gam, recon=RECON_WENO5, nthreads=THREADS), Pg)
+    pk = gr.Pack(g, [b["n"] for b in blocks], [b["offset"] for b in blocks], gam, recon=RECON_WENO5)
+    pk.load(torch.from_numpy(np.concatenate([b["prims"].ravel() for b in blocks])).cuda())
+    pk.step(dt)
+    flat = pk.prims().cpu().numpy()
+    num, den, o, fails = np.zeros(8), np.zeros(8), 0, 0
+    for b in blocks:
+        n = b["n"] + 6
+        out = flat[o:o + 8 * n ** 3].reshape(8, n, n, n)
+        o += 8 * n ** 3
+        ref, f, _ = oracle.run(oracle.cfg(b["grid"], gam=gam, recon=RECON_WENO5, nthreads=THREADS),
+                               b["prims"], dt, 1)
+        fails += f
+        A, B = interior(out), interior(ref)
+        for v in range(8):
+            num[v] += np.abs(A[v] - B[v]).sum()
+            den[v] += sum(np.abs(B[w]).sum() for w in GROUPS[v])
+    rel = num / den
+    print("pack rel L1", rel, "failures", fails, pk.status())
+    assert rel.max() <= TOL, rel
+    assert pk.status() == fails
+
+
+@pytest.mark.parametrize("shape,recon", [((37, 1, 1), RECON_WENO5), ((1, 29, 1), RECON_MC),
+                                         ((1, 1, 23), RECON_WENO5), ((17, 13, 5), RECON_MC),
+                                         ((19, 3, 7), RECON_WENO5)])
+def test_one_zone_axes_and_ragged_sizes(shape, recon):
+    """Grids with one-zone axes (the step is then 1-D or 2-D) and sizes that
+    fill no tile or wavefront evenly; a seeded random smooth state in flat
+    space with all eight primitives varying."""
+    torch, gr = _setup()
+    n1, n2, n3 = shape
+    grid = GridSpec(n1, n2, n3, bc=(BC_PERIODIC,) * 6, metric=METRIC_MINKOWSKI)
+    x1, x2, x3 = grid.centers()
+    X3, X2, X1 = np.meshgrid(x3, x2, x1, indexing="ij")
+    rng = np.random.default_rng(sum(shape))
+    base = np.array([1.0, 1.0, 0.1, -0.2, 0.15, 0.8, 0.3, -0.4])
+    P = np.empty((8,) + X1.shape)
+    for v in range(8):
+        a, ph = rng.uniform(0.05, 0.2, 3), rng.uniform(0, 2 * np.pi, 3)
+        P[v] = base[v] * (1 + 0.0) + a[0] * np.sin(2 * np.pi * X1 + ph[0]) \
+            + a[1] * np.sin(2 * np.pi * X2 + ph[1]) + a[2] * np.sin(2 * np.pi * X3 + ph[2])
+    P[0] = np.abs(P[0]) + 0.5
+    P[1] = np.abs(P[1]) + 0.5
+    c = oracle.cfg(grid, gam=4 / 3, recon=recon)
+    dt = oracle.estimate_dt(c, P)
+    ref, fails, _ = oracle.run(c, P, dt, 2)
+    s = gr.Grmhd(grid, 4 / 3, recon=recon)
+    s.load(torch.from_numpy(P).cuda())
+    s.step(dt)
+    s.step(dt)
+    out = s.prims().cpu().numpy()
+    rel = rel_l1(out, ref)
+    print(shape, rel)
+    assert fails == 0 and s.status()[0] == 0
+    assert rel.max() <= TOL, rel
+    mx, _ = s.divb()
+    assert mx < 1e-12 * max(1.0, np.abs(interior(P[5:8])).max() * max(shape))
+
+
+def test_large_grid_256():
+    """256^3 torus (16.8 M zones: more interior zones than reduction
+    partials of one zone per thread), WENO5, one step, every zone."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    grid, P, _ = fm_torus(256, 256, 256, seed=1, gamma=gam)
+    c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, nthreads=THREADS)
+    s = gr.Grmhd(grid, gam, recon=RECON_WENO5)
+    s.load(torch.from_numpy(P).cuda())
+    dt = s.dt()
+    assert dt == pytest.approx(oracle.estimate_dt(c, P), rel=1e-14)
+    s.step(dt)
+    out = s.prims().cpu().numpy()
+    ref, fails, _ = oracle.run(c, P, dt, 1)
+    rel = rel_l1(out, ref)
+    print("256^3 rel L1", rel, fails)
+    assert rel.max() <= TOL, rel
+    assert s.status()[0] == fails
