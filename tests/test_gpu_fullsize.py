@@ -135,8 +135,11 @@ def test_one_zone_axes_and_ragged_sizes(shape, recon):
     print(shape, rel)
     assert fails == 0 and s.status()[0] == 0
     assert rel.max() <= TOL, rel
-    mx, _ = s.divb()
-    assert mx < 1e-12 * max(1.0, np.abs(interior(P[5:8])).max() * max(shape))
+    # the random field is not divergence-free; Flux-CT keeps its corner
+    # divergence unchanged to roundoff
+    mx, mean = s.divb()
+    mx0, mean0 = oracle.divb(c, P)
+    assert mx == pytest.approx(mx0, rel=1e-9) and mean == pytest.approx(mean0, rel=1e-9)
 
 
 def test_large_grid_256():
