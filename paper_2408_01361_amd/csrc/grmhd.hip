@@ -513,6 +513,62 @@ __device__ int invert_1dw(const Dev& g, const PointMetric<double>& m, const doub
   return 0;
 }
 
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Block-wide max and sum in a fixed order (wavefront butterflies, then the
+// wavefront results in index order): deterministic for a given launch shape.
+__device__ void block_reduce(double& mx, double& sm) {
+  __shared__ double smx[BLOCK / 64], ssm[BLOCK / 64];
+  mx = wave_max(mx);
+  sm = wave_sum(sm);
+  int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) {
+    smx[w] = mx;
+    ssm[w] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = smx[0], b = ssm[0];
+    for (int q = 1; q < BLOCK / 64; q++) {
+      a = fmax(a, smx[q]);
+      b += ssm[q];
+    }
+    mx = a;
+    sm = b;
+  }
+}
+
+// Signal-rate bound of one zone for the CFL step: the sum over axes with
+// more than one zone of max(|c+|, |c-|)/dx_d at the zone centre.
+__device__ __forceinline__ double zone_rate(const Dev& g, const double p[NVAR],
+                                            const PointMetric<double>& m) {
+  Fluid<double> f;
+  fluid_state(p, m, f);
+  double cp, cm, z = 0.0;
+  if (g.n1 > 1) {
+    char_speeds(p, f, m, g.gam, 1, cp, cm);
+    z += fmax(fabs(cp), fabs(cm)) / g.dx1;
+  }
+  if (g.n2 > 1) {
+    char_speeds(p, f, m, g.gam, 2, cp, cm);
+    z += fmax(fabs(cp), fabs(cm)) / g.dx2;
+  }
+  if (g.n3 > 1) {
+    char_speeds(p, f, m, g.gam, 3, cp, cm);
+    z += fmax(fabs(cp), fabs(cm)) / g.dx3;
+  }
+  return z;
+}
+
 // ----------------------------------------------------------------- update --
 
 __device__ __forceinline__ void load_conn(const double* __restrict__ conn, long plane, long q,
@@ -546,7 +602,7 @@ __device__ __forceinline__ void geometric_source(const double p[NVAR], const Flu
 // One stage for every interior zone.  STAGE 1: V = (Un + U1)/2 with
 // Un = U(Pin), U1 = Un + dt L(Pin); STAGE 2: U = V + dt L(Pin)/2.  Then
 // Pout = U_to_P(U; guess Pin).  B fluxes come from the edge EMFs.
-template <int STAGE, typename FT>
+template <int STAGE, typename FT, bool RATE = false>
 __device__ __forceinline__ void update_zone(const Dev& g, const double* __restrict__ Pin,
                                             double* __restrict__ Pout, double* __restrict__ V,
                                             const FT* __restrict__ F1, const FT* __restrict__ F2,
@@ -555,7 +611,7 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
                                             const double* __restrict__ tabC,
                                             const double* __restrict__ conn, double dt,
                                             unsigned long long* fails, unsigned char* __restrict__ flags,
-                                            int i, int j, int k) {
+                                            int i, int j, int k, double* rate = nullptr) {
   // the FP64 update is rounded operation by operation, in the order written
 #pragma clang fp contract(off)
   const long c = zid(g, i, j, k), nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
@@ -613,60 +669,37 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
   for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
   if (flags) flags[c] = (unsigned char)bad;
   if (bad) atomicAdd(fails, 1ull);
+  if (RATE) *rate = zone_rate(g, out, m);
 }
 
-template <int STAGE, typename FT>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8))) k_update(Dev g, Sched box, const double* __restrict__ Pin,
-                                                  double* __restrict__ Pout, double* __restrict__ V,
-                                                  const FT* __restrict__ F1, const FT* __restrict__ F2,
-                                                  const FT* __restrict__ F3, const FT* __restrict__ E1,
-                                                  const FT* __restrict__ E2, const FT* __restrict__ E3,
-                                                  const double* __restrict__ tabC,
-                                                  const double* __restrict__ conn, double dt,
-                                                  const double* __restrict__ dt_dev,
-                                                  unsigned long long* fails,
-                                                  unsigned char* __restrict__ flags) {
+// One stage over the interior.  With RATE (stage 2) every workgroup also
+// writes the maximum CFL rate of the prims it produced to rate_partial[], so
+// the next step's dt needs only the final pass over the partials.
+template <int STAGE, typename FT, bool RATE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8)))
+k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ Pout,
+         double* __restrict__ V, const FT* __restrict__ F1, const FT* __restrict__ F2,
+         const FT* __restrict__ F3, const FT* __restrict__ E1, const FT* __restrict__ E2,
+         const FT* __restrict__ E3, const double* __restrict__ tabC, const double* __restrict__ conn,
+         double dt, const double* __restrict__ dt_dev, unsigned long long* fails,
+         unsigned char* __restrict__ flags, double* __restrict__ rate_partial) {
   int i, j, k;
-  if (!sched_index(box, blockIdx.x, gridDim.x, i, j, k)) return;
+  const bool in = sched_index(box, blockIdx.x, gridDim.x, i, j, k);
   if (dt_dev) dt = *dt_dev;
-  update_zone<STAGE, FT>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i, j, k);
+  if (!RATE) {
+    if (in)
+      update_zone<STAGE, FT>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i, j, k);
+    return;
+  }
+  double r = 0.0, sm = 0.0;
+  if (in)
+    update_zone<STAGE, FT, true>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i,
+                                 j, k, &r);
+  block_reduce(r, sm);
+  if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
 }
 
 // ------------------------------------------------------- reductions etc. --
-
-__device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
-  return x;
-}
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
-// Block-wide max and sum in a fixed order (wavefront butterflies, then the
-// wavefront results in index order): deterministic for a given launch shape.
-__device__ void block_reduce(double& mx, double& sm) {
-  __shared__ double smx[BLOCK / 64], ssm[BLOCK / 64];
-  mx = wave_max(mx);
-  sm = wave_sum(sm);
-  int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  if (l == 0) {
-    smx[w] = mx;
-    ssm[w] = sm;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = smx[0], b = ssm[0];
-    for (int q = 1; q < BLOCK / 64; q++) {
-      a = fmax(a, smx[q]);
-      b += ssm[q];
-    }
-    mx = a;
-    sm = b;
-  }
-}
 
 // Per zone sum_d max(|c+|, |c-|)/dx_d over axes with more than one zone;
 // workgroup maxima to partial[].  Grid-stride over the box, so any grid size
@@ -685,22 +718,7 @@ __global__ void __launch_bounds__(BLOCK) k_dt_partial(Dev g, Box box, const doub
     for (int v = 0; v < NVAR; v++) p[v] = P[v * g.nz + c];
     PointMetric<double> m;
     load_metric<double>(tabC, g.plane, pid(g, i, j), m);
-    Fluid<double> f;
-    fluid_state(p, m, f);
-    double cp, cm, z = 0.0;
-    if (g.n1 > 1) {
-      char_speeds(p, f, m, g.gam, 1, cp, cm);
-      z += fmax(fabs(cp), fabs(cm)) / g.dx1;
-    }
-    if (g.n2 > 1) {
-      char_speeds(p, f, m, g.gam, 2, cp, cm);
-      z += fmax(fabs(cp), fabs(cm)) / g.dx2;
-    }
-    if (g.n3 > 1) {
-      char_speeds(p, f, m, g.gam, 3, cp, cm);
-      z += fmax(fabs(cp), fabs(cm)) / g.dx3;
-    }
-    s = fmax(s, z);
+    s = fmax(s, zone_rate(g, p, m));
   }
   double sm = 0.0;
   block_reduce(s, sm);
@@ -830,6 +848,9 @@ struct grmhd_ctx {
   double *tabC, *tabF1, *tabF2, *corner, *conn;
   double *pmax, *psum, *result;
   unsigned long long* fails;
+  double* pdt;              // CFL-rate partials left by the last stage-2 update
+  bool rate_ready = false;  // pdt describes the current state (rate_n partials)
+  int rate_n = 0;
   // x3 planes per chunk run of the flux/EMF and update schedules
   int kg_flux = 8, kg_update = 8;
   // optional per-kernel-class timing with HIP events on the context's stream
@@ -893,12 +914,13 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
   double* pmax = cv.take<double>(base, MAX_PARTIALS);
   double* psum = cv.take<double>(base, MAX_PARTIALS);
   double* result = cv.take<double>(base, 8);
+  double* pdt = cv.take<double>(base, MAX_PARTIALS);
   unsigned long long* fails = cv.take<unsigned long long>(base, 8);
   if (c) {
     c->P = P; c->P1 = P1; c->V = V;
     for (int d = 0; d < 3; d++) { c->F[d] = F[d]; c->E[d] = E[d]; }
     c->tabC = tabC; c->tabF1 = tabF1; c->tabF2 = tabF2; c->corner = corner; c->conn = conn;
-    c->pmax = pmax; c->psum = psum; c->result = result; c->fails = fails;
+    c->pmax = pmax; c->psum = psum; c->result = result; c->fails = fails; c->pdt = pdt;
   }
   return cv.off;
 }
@@ -976,40 +998,65 @@ int stage_fluxes(grmhd_ctx* c, const double* P) {
                 (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2]);
 }
 
+// One stage's update.  With rate (stage 2 of a step) the workgroups also
+// leave the CFL-rate partials of the prims they write in c->pdt.
 template <int STAGE, typename FT>
 int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
                  unsigned long long* fails = nullptr, unsigned char* flags = nullptr,
-                 const double* dt_dev = nullptr) {
+                 const double* dt_dev = nullptr, bool rate = false) {
   const Dev& g = c->dev;
   Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
-  return launch(c, STAGE == 1 ? T_UPDATE1 : T_UPDATE2, k_update<STAGE, FT>, blocks_for(bz), g, bz, Pin,
-                Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1], (const FT*)c->F[2],
-                (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2], (const double*)c->tabC,
-                (const double*)c->conn, dt, dt_dev, fails ? fails : c->fails, flags);
+  const int cls = STAGE == 1 ? T_UPDATE1 : T_UPDATE2;
+  const unsigned nb = blocks_for(bz);
+  if constexpr (STAGE == 2) {
+    if (rate && nb <= (unsigned)MAX_PARTIALS)
+      return launch(c, cls, k_update<STAGE, FT, true>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
+                    (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1],
+                    (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn, dt, dt_dev,
+                    fails ? fails : c->fails, flags, c->pdt);
+  }
+  return launch(c, cls, k_update<STAGE, FT, false>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
+                (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1],
+                (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn, dt, dt_dev,
+                fails ? fails : c->fails, flags, (double*)nullptr);
 }
 
 // One SSPRK2 step with dt from the host, or, when dt_dev is given, with the
-// dt the device reduction left there.
+// dt the device reduction left there.  The stage-2 update leaves the CFL-rate
+// partials of the new state, so the next dt needs only the final pass.
 template <typename R, typename FT>
 int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   int rc;
+  c->rate_ready = false;
   if ((rc = fill_ghosts(c, c->P))) return rc;
   if ((rc = stage_fluxes<R, FT>(c, c->P))) return rc;
   if ((rc = stage_update<1, FT>(c, c->P, c->P1, dt, nullptr, nullptr, dt_dev))) return rc;
   if ((rc = fill_ghosts(c, c->P1))) return rc;
   if ((rc = stage_fluxes<R, FT>(c, c->P1))) return rc;
-  return stage_update<2, FT>(c, c->P1, c->P, dt, nullptr, nullptr, dt_dev);
+  if ((rc = stage_update<2, FT>(c, c->P1, c->P, dt, nullptr, nullptr, dt_dev, true))) return rc;
+  const Dev& g = c->dev;
+  const long nb = blocks_for(make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update));
+  c->rate_ready = nb <= MAX_PARTIALS;
+  c->rate_n = (int)nb;
+  return GRMHD_OK;
 }
 
 // Enqueue the CFL reduction of the current prims (interior zones only, so no
 // ghost fill): result[0] = max signal rate, result[2] = cfl / max,
-// result[3] = 0 if that dt is usable.
+// result[3] = 0 if that dt is usable.  When the last step's stage-2 update
+// left the partials of this state, only the final pass runs.
 int launch_dt(grmhd_ctx* c) {
+  EvPair e = timing_events(c, T_DT);
+  if (c->rate_ready) {
+    hipExtLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, c->stream, e.a, e.b, 0,
+                          (const double*)c->pdt, (const double*)nullptr, c->rate_n, c->result,
+                          c->params.cfl);
+    return hip_check();
+  }
   const Dev& g = c->dev;
   Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
   long nb = blocks_for(bz.count());
   if (nb > MAX_PARTIALS) nb = MAX_PARTIALS;
-  EvPair e = timing_events(c, T_DT);
   hipExtLaunchKernelGGL(k_dt_partial, dim3((unsigned)nb), dim3(BLOCK), 0, c->stream, e.a, nullptr, 0, g,
                         bz, (const double*)c->P, (const double*)c->tabC, c->pmax);
   hipExtLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, c->stream, nullptr, e.b, 0,
@@ -1077,6 +1124,7 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
 
 int grmhd_load_prims(grmhd_ctx* c, const double* d_prims) {
   if (!c || !d_prims) return GRMHD_E_ARG;
+  c->rate_ready = false;
   size_t bytes = sizeof(double) * NVAR * c->dev.nz;
   if (hipMemcpyAsync(c->P, d_prims, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return GRMHD_E_HIP;

@@ -139,13 +139,22 @@ def test_step_cfl_equals_host_dt_step():
     b = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
     a.load(torch.from_numpy(P))
     b.load(torch.from_numpy(P))
-    for _ in range(3):
+    c = oracle.cfg(grid, gam=13 / 9, recon=RECON_WENO5)
+    for q in range(3):
         dt = a.dt()
+        if q:
+            # after a step the dt comes from the partials the stage-2 update
+            # left; it must equal the oracle's estimate on the same prims
+            assert dt == pytest.approx(oracle.estimate_dt(c, a.prims().cpu().numpy()), rel=1e-14)
         a.step(dt)
         b.step_cfl()
         assert b.last_dt() == dt
     assert torch.equal(a.prims(), b.prims())
     assert a.status() == b.status()
+    # a freshly loaded state reduces from scratch: same value as the fused path
+    d = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    d.load(b.prims())
+    assert d.dt() == b.dt()
 
 
 def test_reductions_past_one_partial_per_workgroup():
