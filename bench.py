@@ -207,8 +207,50 @@ def extras(torch, gr, np, args):
                     "WENO5, FP64, one persistent launch per RK2 stage, 10 steps at fixed dt",
         "interior_zones": zones, "zone_cycles_per_s": zones * steps / tp,
         "cooperative_workgroups": pk.grid_blocks,
-        "tiles": {str(k): list(v) for k, v in tiles.items()}, "inversion_failures": pk.status()}
+        "tiles": {str(k): list(v) for k, v in tiles.items()},
+        "tiles_note": "per block size: t1 x t2 x t3 zones, or [0, 0, 0] = runs of 256 consecutive "
+                      "positions of each box",
+        "inversion_failures": pk.status()}
+    out["adjoint"] = adjoint_extra(torch, gr)
     return out
+
+
+def adjoint_extra(torch, gr):
+    """Gradient of sum_{i<5} rho u after 8 steps of the 64^3 torus (MC, FP64,
+    fixed dt) with respect to the initial prims and gamma: the forward pass
+    with per-step checkpoints and the hand-written backward, timed apart."""
+    from workloads import fm_torus, RECON_MC, NG
+    from paper_2408_01361_amd import autograd as ag
+    gam, n, nsteps = 13.0 / 9.0, 64, 8
+    grid, P, _ = fm_torus(n, n, n, seed=1, gamma=gam)
+    s = gr.Grmhd(grid, gam, recon=RECON_MC)
+    Pt = torch.from_numpy(P).cuda()
+    s.load(Pt)
+    dt = s.dt()
+
+    def one():
+        x = Pt.clone().requires_grad_(True)
+        gt = torch.tensor(gam, dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ag.run(x, gt, s, dt, nsteps)
+        I = out[:, NG:-NG, NG:-NG, NG:-NG]
+        L = (I[0, :, :, :5] * I[1, :, :, :5]).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    one()                            # untimed: workspaces, clocks
+    runs = [one() for _ in range(3)]
+    tf, tb = min(r[0] for r in runs), min(r[1] for r in runs)
+    zc = n ** 3 * nsteps
+    return {"workload": "64^3 torus, MC, FP64, 8 RK2 steps at fixed dt, loss sum_{i<5} rho u; "
+                        "gradient in the initial prims and gamma (best of 3)",
+            "forward_ms_per_step": tf * 1e3 / nsteps, "backward_ms_per_step": tb * 1e3 / nsteps,
+            "backward_over_forward": tb / tf, "gradient_zone_cycles_per_s": zc / (tf + tb)}
 
 
 def main():

@@ -163,8 +163,9 @@ int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const do
  * zones, and x2 block faces on the polar axis carry no flux.  One pack step is
  * one persistent cooperative launch per RK2 stage that processes every block.
  * Packed prims: the blocks' padded arrays [8][n+6][n+6][n+6], concatenated in
- * block order (device).  Tile shapes per block size (t1*t2*t3 <= 256) only
- * change speed.  Errors as for single contexts; E_ARG for blocks outside the
+ * block order (device).  Tile shapes per block size (t1*t2*t3 <= 256, or
+ * (0, 0, 0): runs of 256 consecutive positions of each box in x1-fastest
+ * order, the default) only change speed.  Errors as for single contexts; E_ARG for blocks outside the
  * global grid or a non-FP64 precision. */
 typedef struct grmhd_pack grmhd_pack;
 size_t grmhd_pack_workspace_bytes(int nblocks, const int* n);

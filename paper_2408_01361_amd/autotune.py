@@ -13,7 +13,8 @@ import os
 
 import torch
 
-TILE_CANDIDATES = [(64, 4, 1), (32, 8, 1), (16, 16, 1), (16, 8, 2), (8, 8, 4), (32, 4, 2),
+# (0, 0, 0): linear runs of 256 consecutive positions of each box
+TILE_CANDIDATES = [(0, 0, 0), (64, 4, 1), (32, 8, 1), (16, 16, 1), (16, 8, 2), (8, 8, 4), (32, 4, 2),
                    (16, 4, 4), (8, 4, 8), (4, 8, 8), (128, 2, 1), (64, 2, 2)]
 KG_CANDIDATES = [1, 2, 4, 8, 16, 32]
 

@@ -1519,10 +1519,10 @@ size_t pack_carve(int nb, const int* n, char* base, grmhd_pack* pk) {
   return cv.off;
 }
 
-int default_tile(int n, int& t1, int& t2, int& t3) {
-  if (n >= 64) { t1 = 64; t2 = 4; t3 = 1; }
-  else if (n >= 32) { t1 = 32; t2 = 8; t3 = 1; }
-  else { t1 = 16; t2 = 16; t3 = 1; }
+// Default tiles: linear runs of BLOCK positions (face boxes of n + 1 by n + 2
+// zones fit no power-of-two tile evenly).
+int default_tile(int, int& t1, int& t2, int& t3) {
+  t1 = t2 = t3 = 0;
   return 0;
 }
 
@@ -1640,7 +1640,8 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
 }
 
 int grmhd_pack_set_tiles(grmhd_pack* pk, int n, int t1, int t2, int t3) {
-  if (!pk || t1 < 1 || t2 < 1 || t3 < 1 || t1 * t2 * t3 > BLOCK) return GRMHD_E_ARG;
+  const bool linear = t1 == 0 && t2 == 0 && t3 == 0;
+  if (!pk || (!linear && (t1 < 1 || t2 < 1 || t3 < 1 || t1 * t2 * t3 > BLOCK))) return GRMHD_E_ARG;
   if (hipStreamSynchronize(pk->stream) != hipSuccess) return GRMHD_E_HIP;
   for (int b = 0; b < pk->nb; b++)
     if (pk->views[b].g.n1 == n) {

@@ -3,8 +3,9 @@
 // separated by grid-wide barriers -- face fluxes of every block along x1..x3,
 // edge EMFs, then the zone update with the inversion -- and within each phase
 // its workgroups take (block, tile) work items from an atomic counter, so
-// uneven block sizes balance dynamically.  Tile shapes (T1 x T2 x T3 = BLOCK
-// threads) are chosen per block size (an autotuner picks them); the per-face,
+// uneven block sizes balance dynamically.  Tile shapes (T1 x T2 x T3 <= BLOCK
+// threads, or linear runs of BLOCK positions) are chosen per block size (an
+// autotuner picks them); the per-face,
 // per-edge and per-zone work is the same device code as the single-block
 // kernels, so a block advanced in a pack matches the same block advanced
 // alone bit for bit.  Ghost zones are frozen (Dirichlet).
@@ -40,7 +41,11 @@ __host__ __device__ inline Box phase_box(const Dev& g, int ph, int d) {
   return Box{0, 0, 0, g.n1, g.n2, g.n3};
 }
 
+// Tiles of a box: t1 x t2 x t3 sub-boxes, or, for the linear shape
+// (t1 = 0), runs of BLOCK consecutive positions in x1-fastest order (no
+// thread idles except in a box's last run, whatever the box extents).
 __host__ __device__ inline int tiles_of(const Box& b, int t1, int t2, int t3) {
+  if (t1 == 0) return (int)((b.count() + BLOCK - 1) / BLOCK);
   return ((b.n1 + t1 - 1) / t1) * ((b.n2 + t2 - 1) / t2) * ((b.n3 + t3 - 1) / t3);
 }
 
@@ -56,6 +61,7 @@ __host__ __device__ inline int block_items(const BlockView& b, int ph) {
 // Position of this thread in tile `lt` of box b, if inside.
 __device__ __forceinline__ bool tile_pos(const Box& b, int t1, int t2, int t3, int lt, int& i, int& j,
                                          int& k) {
+  if (t1 == 0) return box_index(b, (long)lt * BLOCK + threadIdx.x, i, j, k);
   int nt1 = (b.n1 + t1 - 1) / t1, nt2 = (b.n2 + t2 - 1) / t2;
   int a = lt % nt1, rest = lt / nt1;
   int bb = rest % nt2, cc = rest / nt2;
