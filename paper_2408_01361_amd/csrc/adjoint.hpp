@@ -8,10 +8,12 @@
 // face flux is transposed through its stencil, and ghost fills are transposed
 // by gathering each ghost's adjoint back onto the zone it was copied from
 // (with the polar sign flips).  Only the local Jacobians of the per-point
-// physics (a face flux with respect to its stencil, the source and the
-// conserved variables with respect to one zone's prims) come from
-// forward-mode dual numbers, one input direction at a time.  Every sum is a
-// gather in a fixed order: the result is deterministic.
+// physics come from forward-mode dual numbers, one input direction at a
+// time: a face flux with respect to each of its two states' prims (then
+// chained with the reconstruction's derivatives with respect to each stencil
+// slot), the source and the conserved variables with respect to one zone's
+// prims.  Every sum is a gather in a fixed order: the result is
+// deterministic.
 //
 // Included inside the anonymous namespace of grmhd.hip.
 
@@ -19,65 +21,83 @@ template <int RECON>
 struct Stencil {
   static constexpr int W = RECON == GRMHD_RECON_MC ? 4 : 6;  // zones per face
   static constexpr int H = W / 2;                            // zones left of the face
-  static constexpr int NSEED = NVAR * W + 1;                 // + gamma
+  static constexpr int NSLOT = NVAR * W;                     // stencil inputs of one face
 };
 
-// Face flux along D as a function of its stencil, with one input direction
-// (seed = v * W + s: variable v of stencil zone s; seed = NVAR * W: gamma).
-template <int D, int RECON>
-__device__ __forceinline__ void face_flux_dual(const Dev& g, const double* __restrict__ P, long c,
-                                               long s, const PointMetric<Dual>& m, int seed,
-                                               Dual F[NVAR]) {
-  using St = Stencil<RECON>;
-  Dual qL[NVAR], qR[NVAR];
-#pragma unroll
-  for (int v = 0; v < NVAR; v++) {
-    Dual q[St::W];
-#pragma unroll
-    for (int z = 0; z < St::W; z++) q[z] = Dual(P[v * g.nz + c + (z - St::H) * s], seed == v * St::W + z ? 1.0 : 0.0);
-    if constexpr (RECON == GRMHD_RECON_MC) {
-      qL[v] = mc_left(q[0], q[1], q[2]);
-      qR[v] = mc_right(q[1], q[2], q[3]);
-    } else {
-      Dual eps(g.weno_eps);
-      qL[v] = weno5(q[0], q[1], q[2], q[3], q[4], eps);
-      qR[v] = weno5(q[5], q[4], q[3], q[2], q[1], eps);
-    }
-  }
-  const Dual gam(g.gam, seed == NVAR * St::W ? 1.0 : 0.0);
-  Dual FL[NVAR], UL[NVAR], FR[NVAR], UR[NVAR], cpl, cml, cpr, cmr;
-  {
-    Fluid<Dual> f;
-    fluid_state(qL, m, f);
-    prim_to_flux(qL, f, m, gam, D, FL);
-    prim_to_flux(qL, f, m, gam, 0, UL);
-    char_speeds(qL, f, m, gam, D, cpl, cml);
-  }
-  {
-    Fluid<Dual> f;
-    fluid_state(qR, m, f);
-    prim_to_flux(qR, f, m, gam, D, FR);
-    prim_to_flux(qR, f, m, gam, 0, UR);
-    char_speeds(qR, f, m, gam, D, cpr, cmr);
-  }
-  Dual cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
-  cmax = fmax(cmax, Dual(0.0));
-#pragma unroll
-  for (int v = 0; v < NVAR; v++) F[v] = llf(FL[v], FR[v], UL[v], UR[v], cmax);
+// One face state in dual arithmetic: its flux along D, conserved variables
+// and characteristic speeds.
+template <int D>
+__device__ __forceinline__ void state_dual(const Dual q[NVAR], const PointMetric<double>& m, Dual gam,
+                                           Dual Fx[NVAR], Dual U[NVAR], Dual& cp, Dual& cm) {
+  Fluid<Dual> f;
+  fluid_state(q, m, f);
+  prim_to_flux(q, f, m, gam, D, Fx);
+  prim_to_flux(q, f, m, gam, 0, U);
+  char_speeds(q, f, m, gam, D, cp, cm);
 }
 
-__device__ __forceinline__ void load_metric_dual(const double* __restrict__ tab, long plane, long q,
-                                                 PointMetric<Dual>& m) {
-  PointMetric<double> md;
-  load_metric<double>(tab, plane, q, md);
-#pragma unroll
-  for (int f = 0; f < 10; f++) {
-    m.gcov[f] = Dual(md.gcov[f]);
-    m.gcon[f] = Dual(md.gcon[f]);
-  }
-  m.gdet = Dual(md.gdet);
-  m.alpha = Dual(md.alpha);
+// The same state in plain FP64 (the side of the face that is not seeded).
+template <int D>
+__device__ __forceinline__ void state_real(const double q[NVAR], const PointMetric<double>& m, double gam,
+                                           double Fx[NVAR], double U[NVAR], double& cp, double& cm) {
+  Fluid<double> f;
+  fluid_state(q, m, f);
+  prim_to_flux(q, f, m, gam, D, Fx);
+  prim_to_flux(q, f, m, gam, 0, U);
+  char_speeds(q, f, m, gam, D, cp, cm);
 }
+
+// lambda . LLF flux, derivative part, from the two face states.
+__device__ __forceinline__ double llf_dot(const Dual FL[NVAR], const Dual UL[NVAR], Dual cpl, Dual cml,
+                                          const Dual FR[NVAR], const Dual UR[NVAR], Dual cpr, Dual cmr,
+                                          const double lam[NVAR]) {
+  Dual cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
+  cmax = fmax(cmax, Dual(0.0));
+  double acc = 0.0;
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) acc += llf(FL[v], FR[v], UL[v], UR[v], cmax).d * lam[v];
+  return acc;
+}
+
+// The same with one state seeded (S: its dual fluxes, conserved variables
+// and speeds) and the other fixed (plain values); left says which side S is.
+__device__ __forceinline__ double llf_dot_one(bool left, const Dual FS[NVAR], const Dual US[NVAR], Dual cps,
+                                              Dual cms, const double FO[NVAR], const double UO[NVAR],
+                                              double cpo, double cmo, const double lam[NVAR]) {
+  const Dual cpl = left ? cps : Dual(cpo), cpr = left ? Dual(cpo) : cps;
+  const Dual cml = left ? cms : Dual(cmo), cmr = left ? Dual(cmo) : cms;
+  Dual cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
+  cmax = fmax(cmax, Dual(0.0));
+  // d/ds of F = (FL + FR)/2 - cmax (UR - UL)/2 with only S and cmax varying
+  double acc = 0.0;
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    const double du = left ? UO[v] - US[v].v : US[v].v - UO[v];
+    const double dU = left ? -US[v].d : US[v].d;
+    acc += (0.5 * FS[v].d - 0.5 * (cmax.d * du + cmax.v * dU)) * lam[v];
+  }
+  return acc;
+}
+
+// Derivatives of a face's left and right reconstructed values of one
+// variable with respect to stencil slot s (q holds the W slot values).
+template <int RECON>
+__device__ __forceinline__ void recon_slot_derivs(const double q[], int s, double eps, double& dL,
+                                                  double& dR) {
+  using St = Stencil<RECON>;
+  Dual x[St::W];
+#pragma unroll
+  for (int z = 0; z < St::W; z++) x[z] = Dual(q[z], z == s ? 1.0 : 0.0);
+  if constexpr (RECON == GRMHD_RECON_MC) {
+    dL = mc_left(x[0], x[1], x[2]).d;
+    dR = mc_right(x[1], x[2], x[3]).d;
+  } else {
+    Dual e(eps);
+    dL = weno5(x[0], x[1], x[2], x[3], x[4], e).d;
+    dR = weno5(x[5], x[4], x[3], x[2], x[1], e).d;
+  }
+}
+
 
 // Adjoint of the Flux-CT EMFs on every padded edge position (zero outside
 // the edge box [0, n]^3 and on polar edges), from the stage adjoint lambda_L
@@ -152,21 +172,61 @@ __global__ void __launch_bounds__(BLOCK) k_adj_face(Dev g, Box box, const double
 #pragma unroll
   for (int v = 0; v < NVAR; v++) zero = zero && lam[v] == 0.0;
   if (zero || (D == 2 && ((g.pole_lo && j == 0) || (g.pole_hi && j == g.n2)))) {
-    for (int sd = 0; sd < St::NSEED - 1; sd++) LS[sd * nz + c] = 0.0;
+    for (int sd = 0; sd < St::NSLOT; sd++) LS[sd * nz + c] = 0.0;
     return;
   }
-  PointMetric<Dual> m;
-  load_metric_dual(tab, g.plane, pid(g, i, j), m);
-  for (int sd = 0; sd < St::NSEED; sd++) {
-    Dual F[NVAR];
-    face_flux_dual<D, RECON>(g, P, c, s, m, sd, F);
-    double acc = 0.0;
+  // chain rule through the face states: lambda . dF/d(stencil slot) =
+  // sum over the two states of (lambda . dF/dq_state[v]) dq_state[v]/dslot;
+  // the first factor takes one dual evaluation of one state per variable,
+  // the second one dual reconstruction per slot
+  PointMetric<double> m;
+  load_metric<double>(tab, g.plane, pid(g, i, j), m);
+  double qL[NVAR], qR[NVAR];
+  recon_pair<RECON, double>(P, nz, c, s, g.weno_eps, qL, qR);
+  const double gam = g.gam;
+  double gL[NVAR], gR[NVAR];
+#pragma unroll 1
+  for (int side = 0; side < 2; side++) {
+    const double* qs = side == 0 ? qL : qR;
+    double FO[NVAR], UO[NVAR], cpo, cmo;
+    state_real<D>(side == 0 ? qR : qL, m, gam, FO, UO, cpo, cmo);
+#pragma unroll 1
+    for (int w = 0; w < NVAR; w++) {
+      Dual q[NVAR], Fx[NVAR], U[NVAR], cp, cm;
 #pragma unroll
-    for (int v = 0; v < NVAR; v++) acc += F[v].d * lam[v];
-    if (sd < St::NSEED - 1)
-      LS[sd * nz + c] = acc;
-    else
-      GF[c] += acc;
+      for (int v = 0; v < NVAR; v++) q[v] = Dual(qs[v], v == w ? 1.0 : 0.0);
+      state_dual<D>(q, m, Dual(gam), Fx, U, cp, cm);
+      const double gw = llf_dot_one(side == 0, Fx, U, cp, cm, FO, UO, cpo, cmo, lam);
+      if (side == 0)
+        gL[w] = gw;
+      else
+        gR[w] = gw;
+    }
+  }
+  {
+    // gamma: both states
+    Dual a[NVAR], b[NVAR], FLd[NVAR], ULd[NVAR], FRd[NVAR], URd[NVAR], cpl, cml, cpr, cmr;
+    const Dual gd(gam, 1.0);
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) {
+      a[v] = Dual(qL[v]);
+      b[v] = Dual(qR[v]);
+    }
+    state_dual<D>(a, m, gd, FLd, ULd, cpl, cml);
+    state_dual<D>(b, m, gd, FRd, URd, cpr, cmr);
+    GF[c] += llf_dot(FLd, ULd, cpl, cml, FRd, URd, cpr, cmr, lam);
+  }
+#pragma unroll 1
+  for (int v = 0; v < NVAR; v++) {
+    double qs[St::W];
+#pragma unroll
+    for (int z = 0; z < St::W; z++) qs[z] = P[v * nz + c + (z - St::H) * s];
+#pragma unroll
+    for (int z = 0; z < St::W; z++) {
+      double dL, dR;
+      recon_slot_derivs<RECON>(qs, z, g.weno_eps, dL, dR);
+      LS[(v * St::W + z) * nz + c] = gL[v] * dL + gR[v] * dR;
+    }
   }
 }
 
@@ -262,8 +322,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_zone(Dev g, Box box, const double
         }
       }
   // local Jacobians of the source (and the conserved variables) by seeds
-  PointMetric<Dual> m;
-  load_metric_dual(tabC, g.plane, pid(g, i, j), m);
+  PointMetric<double> m;
+  load_metric<double>(tabC, g.plane, pid(g, i, j), m);
   double cn[40];
   load_conn(conn, g.plane, pid(g, i, j), cn);
   double lL[NVAR], lU[NVAR];
@@ -290,7 +350,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_zone(Dev g, Box box, const double
         Dual T[4];
         tmunu_row(p, f, gam, kk, T);
 #pragma unroll
-        for (int l = 0; l < 4; l++) sacc = sacc + T[l] * Dual(cn[l * 10 + sidx(nu, kk)]);
+        for (int l = 0; l < 4; l++) sacc = sacc + T[l] * cn[l * 10 + sidx(nu, kk)];
       }
       d += (m.gdet * sacc).d * lL[UU + nu];
     }
@@ -339,8 +399,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_ift(Dev g, const double* __restri
   double lp[NVAR];
 #pragma unroll
   for (int v = 0; v < NVAR; v++) lp[v] = LP[v * nz + t];
-  PointMetric<Dual> m;
-  load_metric_dual(tabC, g.plane, pid(g, i, j), m);
+  PointMetric<double> m;
+  load_metric<double>(tabC, g.plane, pid(g, i, j), m);
   if (flags[t]) {
 #pragma unroll
     for (int v = 0; v < 5; v++) {
@@ -348,7 +408,7 @@ __global__ void __launch_bounds__(BLOCK) k_adj_ift(Dev g, const double* __restri
       LU[v * nz + t] = 0.0;
     }
 #pragma unroll
-    for (int v = 5; v < NVAR; v++) LU[v * nz + t] = lp[v] / m.gdet.v;
+    for (int v = 5; v < NVAR; v++) LU[v * nz + t] = lp[v] / m.gdet;
     return;
   }
   // J[a][b] = dU_a / dP_b; column NVAR: dU/dgamma

@@ -25,6 +25,18 @@ __device__ __forceinline__ Dual operator/(Dual a, Dual b) {
   double q = a.v / b.v;
   return Dual(q, (a.d - q * b.d) / b.v);
 }
+// with a constant (no derivative): the metric and connection coefficients
+__device__ __forceinline__ Dual operator+(Dual a, double b) { return Dual(a.v + b, a.d); }
+__device__ __forceinline__ Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, double b) { return Dual(a.v - b, a.d); }
+__device__ __forceinline__ Dual operator-(double a, Dual b) { return Dual(a - b.v, -b.d); }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+__device__ __forceinline__ Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
+__device__ __forceinline__ Dual operator/(double a, Dual b) {
+  double q = a / b.v;
+  return Dual(q, -q * b.d / b.v);
+}
 __device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
 __device__ __forceinline__ Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
 __device__ __forceinline__ Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }

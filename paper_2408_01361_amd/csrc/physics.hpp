@@ -79,6 +79,7 @@ __device__ __forceinline__ R fdiv(R a, R b) { return a * __builtin_amdgcn_rcpf(b
 namespace fdual {
 using R = Dual;
 __device__ __forceinline__ R fdiv(R a, R b) { return a / b; }
+__device__ __forceinline__ R fdiv(R a, double b) { return a / b; }
 #include "physics_body.inc"
 }  // namespace fdual
 
