@@ -267,24 +267,6 @@ __global__ void __launch_bounds__(BLOCK) k_adj_gather(Dev g, Box b1, Box b2, Box
   for (int v = 0; v < NVAR; v++) LPh[v * g.nz + t] = acc[v];
 }
 
-// Padded positions along one axis whose ghost fill copies interior x (x
-// itself included), with the polar sign.
-__device__ __forceinline__ int bc_preimages(int x, int n, int bclo, int bchi, int ys[7], bool fl[7]) {
-  int cnt = 0;
-  ys[cnt] = x;
-  fl[cnt++] = false;
-  for (int y = -NG; y < 0; y++) {
-    bool f = false;
-    if (bclo == GRMHD_BC_FROZEN) continue;
-    if (bc_map(y, n, bclo, bchi, f) == x) { ys[cnt] = y; fl[cnt++] = f; }
-  }
-  for (int y = n; y < n + NG; y++) {
-    bool f = false;
-    if (bchi == GRMHD_BC_FROZEN) continue;
-    if (bc_map(y, n, bclo, bchi, f) == x) { ys[cnt] = y; fl[cnt++] = f; }
-  }
-  return cnt;
-}
 
 // Per interior zone: the ghost-fill transpose of the gathered stencil
 // adjoint, plus the local terms: source^T lambda_L, (stage 1) U^T lambda_U0,
