@@ -136,7 +136,9 @@ int grmhd_cons_to_prims(grmhd_ctx* ctx, const double* d_cons, const double* d_gu
 
 /* Face fluxes of one stage evaluated from d_prims (ghosts filled from it),
  * with Flux-CT applied to the B components of interior faces.  d_flux is
- * [3][8][padded] float64 (device).  For testing and inspection. */
+ * [3][8][padded] float64 (device); entries at positions other than interior
+ * faces (x1 faces i in [0, n1], j < n2, k < n3, and likewise) are
+ * unspecified.  For testing and inspection. */
 int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
 
 /* Adjoint of one step (vector-Jacobian product), FP64 only.

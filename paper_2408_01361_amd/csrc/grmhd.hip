@@ -313,9 +313,11 @@ __device__ __forceinline__ void face_llf(const Dev& g, const R qL[NVAR], const R
   }
   R cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
   cmax = fmax(cmax, (R)0);
+  // the normal field component's flux is not stored: Flux-CT replaces it by
+  // zero and nothing reads it
 #pragma unroll
   for (int v = 0; v < NVAR; v++)
-    F[v * g.nz + c] = (FT)llf(FL[v], FR[v], UL[v], UR[v], cmax);
+    if (v != B1 + D - 1) F[v * g.nz + c] = (FT)llf(FL[v], FR[v], UL[v], UR[v], cmax);
 }
 
 template <int D>
@@ -621,32 +623,7 @@ __device__ __forceinline__ void geometric_source(const double p[NVAR], const Flu
 // One stage for every interior zone.  STAGE 1: V = (Un + U1)/2 with
 // Un = U(Pin), U1 = Un + dt L(Pin); STAGE 2: U = V + dt L(Pin)/2.  Then
 // Pout = U_to_P(U; guess Pin).  B fluxes come from the edge EMFs.
-// Writes the value v of interior zone (i, j, k) also into every ghost zone
-// that the boundary conditions fill from it (what k_bc would copy there; the
-// polar mirror flips u~2 and B2).  Only zones within NG of a non-frozen
-// boundary have such images.
-__device__ __forceinline__ void write_images(const Dev& g, double* __restrict__ Pout, const double out[NVAR],
-                                             int i, int j, int k) {
-  const bool near1 = i < NG || i >= g.n1 - NG, near2 = j < NG || j >= g.n2 - NG,
-             near3 = k < NG || k >= g.n3 - NG;
-  if (!(near1 || near2 || near3)) return;
-  int y1[7], y2[7], y3[7];
-  bool f1[7], f2[7], f3[7];
-  const int c1 = near1 ? bc_preimages(i, g.n1, g.bc[0], g.bc[1], y1, f1) : (y1[0] = i, 1);
-  const int c2 = near2 ? bc_preimages(j, g.n2, g.bc[2], g.bc[3], y2, f2) : (y2[0] = j, f2[0] = false, 1);
-  const int c3 = near3 ? bc_preimages(k, g.n3, g.bc[4], g.bc[5], y3, f3) : (y3[0] = k, 1);
-  for (int a = 0; a < c1; a++)
-    for (int b = 0; b < c2; b++)
-      for (int e = 0; e < c3; e++) {
-        if (a == 0 && b == 0 && e == 0) continue;  // the zone itself
-        const long q = zid(g, y1[a], y2[b], y3[e]);
-#pragma unroll
-        for (int v = 0; v < NVAR; v++)
-          Pout[v * g.nz + q] = (f2[b] && (v == U2 || v == B2)) ? -out[v] : out[v];
-      }
-}
-
-template <int STAGE, typename FT, bool RATE = false, bool GHOSTS = false>
+template <int STAGE, typename FT, bool RATE = false>
 __device__ __forceinline__ void update_zone(const Dev& g, const double* __restrict__ Pin,
                                             double* __restrict__ Pout, double* __restrict__ V,
                                             const FT* __restrict__ F1, const FT* __restrict__ F2,
@@ -713,16 +690,13 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
   for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
   if (flags) flags[c] = (unsigned char)bad;
   if (bad) atomicAdd(fails, 1ull);
-  if (GHOSTS) write_images(g, Pout, out, i, j, k);
   if (RATE) *rate = zone_rate(g, out, m);
 }
 
 // One stage over the interior.  With RATE (stage 2) every workgroup also
 // writes the maximum CFL rate of the prims it produced to rate_partial[], so
-// the next step's dt needs only the final pass over the partials; with
-// GHOSTS every zone also fills the ghost zones that copy it, so the output is
-// ready for the next stage without a ghost-fill launch.
-template <int STAGE, typename FT, bool RATE, bool GHOSTS>
+// the next step's dt needs only the final pass over the partials.
+template <int STAGE, typename FT, bool RATE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8)))
 k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ Pout,
          double* __restrict__ V, const FT* __restrict__ F1, const FT* __restrict__ F2,
@@ -735,14 +709,14 @@ k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ 
   if (dt_dev) dt = *dt_dev;
   if (!RATE) {
     if (in)
-      update_zone<STAGE, FT, false, GHOSTS>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
-                                            flags, i, j, k);
+      update_zone<STAGE, FT>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i, j,
+                             k);
     return;
   }
   double r = 0.0, sm = 0.0;
   if (in)
-    update_zone<STAGE, FT, true, GHOSTS>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
-                                         flags, i, j, k, &r);
+    update_zone<STAGE, FT, true>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i,
+                                 j, k, &r);
   block_reduce(r, sm);
   if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
 }
@@ -1021,7 +995,7 @@ int fill_ghosts(grmhd_ctx* c, double* P) {
 }
 
 // Ghost zones of the state P, filled unless they already hold its boundary
-// conditions (a step's updates write them).
+// conditions (filled since P last changed).
 int ensure_ghosts(grmhd_ctx* c) {
   if (c->ghosts_valid) return GRMHD_OK;
   int rc = fill_ghosts(c, c->P);
@@ -1057,41 +1031,32 @@ int stage_fluxes(grmhd_ctx* c, const double* P) {
 }
 
 // One stage's update.  With rate (stage 2 of a step) the workgroups also
-// leave the CFL-rate partials of the prims they write in c->pdt; with ghosts
-// they also fill the ghost zones of Pout.
-template <int STAGE, typename FT, bool GHOSTS>
-int stage_update_k(grmhd_ctx* c, const double* Pin, double* Pout, double dt, unsigned long long* fails,
-                   unsigned char* flags, const double* dt_dev, bool rate) {
+// leave the CFL-rate partials of the prims they write in c->pdt.
+template <int STAGE, typename FT>
+int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
+                 unsigned long long* fails = nullptr, unsigned char* flags = nullptr,
+                 const double* dt_dev = nullptr, bool rate = false) {
   const Dev& g = c->dev;
   Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
   const int cls = STAGE == 1 ? T_UPDATE1 : T_UPDATE2;
   const unsigned nb = blocks_for(bz);
   if constexpr (STAGE == 2) {
     if (rate && nb <= (unsigned)MAX_PARTIALS)
-      return launch(c, cls, k_update<STAGE, FT, true, GHOSTS>, nb, g, bz, Pin, Pout, c->V,
-                    (const FT*)c->F[0], (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0],
-                    (const FT*)c->E[1], (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn,
-                    dt, dt_dev, fails ? fails : c->fails, flags, c->pdt);
+      return launch(c, cls, k_update<STAGE, FT, true>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
+                    (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1],
+                    (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn, dt, dt_dev,
+                    fails ? fails : c->fails, flags, c->pdt);
   }
-  return launch(c, cls, k_update<STAGE, FT, false, GHOSTS>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
+  return launch(c, cls, k_update<STAGE, FT, false>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
                 (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1],
                 (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn, dt, dt_dev,
                 fails ? fails : c->fails, flags, (double*)nullptr);
 }
 
-template <int STAGE, typename FT>
-int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
-                 unsigned long long* fails = nullptr, unsigned char* flags = nullptr,
-                 const double* dt_dev = nullptr, bool rate = false, bool ghosts = false) {
-  if (ghosts) return stage_update_k<STAGE, FT, true>(c, Pin, Pout, dt, fails, flags, dt_dev, rate);
-  return stage_update_k<STAGE, FT, false>(c, Pin, Pout, dt, fails, flags, dt_dev, rate);
-}
-
 // One SSPRK2 step with dt from the host, or, when dt_dev is given, with the
-// dt the device reduction left there.  Each update also fills the ghost
-// zones of the state it writes (so only a freshly loaded state needs a ghost
-// fill), and the stage-2 update leaves the CFL-rate partials of the new
-// state, so the next dt needs only the final pass.
+// dt the device reduction left there.  The stage-2 update leaves the
+// CFL-rate partials of the new state, so the next dt needs only the final
+// pass.
 template <typename R, typename FT>
 int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   int rc;
@@ -1099,14 +1064,14 @@ int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   if ((rc = ensure_ghosts(c))) return rc;
   c->ghosts_valid = false;
   if ((rc = stage_fluxes<R, FT>(c, c->P))) return rc;
-  if ((rc = stage_update<1, FT>(c, c->P, c->P1, dt, nullptr, nullptr, dt_dev, false, true))) return rc;
+  if ((rc = stage_update<1, FT>(c, c->P, c->P1, dt, nullptr, nullptr, dt_dev))) return rc;
+  if ((rc = fill_ghosts(c, c->P1))) return rc;
   if ((rc = stage_fluxes<R, FT>(c, c->P1))) return rc;
-  if ((rc = stage_update<2, FT>(c, c->P1, c->P, dt, nullptr, nullptr, dt_dev, true, true))) return rc;
+  if ((rc = stage_update<2, FT>(c, c->P1, c->P, dt, nullptr, nullptr, dt_dev, true))) return rc;
   const Dev& g = c->dev;
   const long nb = blocks_for(make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update));
   c->rate_ready = nb <= MAX_PARTIALS;
   c->rate_n = (int)nb;
-  c->ghosts_valid = true;
   return GRMHD_OK;
 }
 

@@ -256,11 +256,10 @@ def test_mixed_precision_error_is_bounded_and_divb_fp64():
 
 
 @pytest.mark.parametrize("case", ["torus", "thin_periodic"])
-def test_ghosts_written_by_the_update_match_the_boundary_conditions(case):
-    """After steps, the ghost zones the updates wrote (no ghost-fill launch
-    in between) equal the oracle's ghost fill of the same interior, bit for
-    bit, including corners, polar sign flips and periodic axes shorter than
-    the ghost width."""
+def test_ghost_fill_matches_the_boundary_conditions(case):
+    """After steps, the ghost zones of the returned state equal the oracle's
+    ghost fill of the same interior, bit for bit, including corners, polar
+    sign flips and periodic axes shorter than the ghost width."""
     torch = _torch()
     gr = _gr()
     if case == "torus":
