@@ -190,15 +190,16 @@ int grmhd_pack_destroy(grmhd_pack* pack);
  * kg >= 1 gives the same results; only speed changes.  E_ARG if kg < 1. */
 int grmhd_set_schedule(grmhd_ctx* ctx, int kg_flux, int kg_update);
 
-/* Per-kernel-class timing while enabled (enabling clears earlier records):
- * every launch carries a start and a stop HIP event in its own dispatch
- * (hipExtLaunchKernel), so no marker packets are added between kernels.
- * Classes: 0 ghost fill, 1 face fluxes (x1, x2 and x3 faces in one launch),
- * 2 EMFs, 3 stage-1 update, 4 stage-2 update, 5 dt reduction.  The report
- * sums elapsed milliseconds and counts launches per class into arrays of
- * nclass >= 6 entries.  Both synchronise the stream.  For measurement; the
- * step itself is unchanged. */
-int grmhd_timing(grmhd_ctx* ctx, int enable);
+/* Per-kernel-class timing of the classes whose bits are set in class_mask
+ * (0 turns timing off, -1 times every class; setting a mask clears earlier
+ * records): every launch of a timed class carries a start and a stop HIP
+ * event in its own dispatch (hipExtLaunchKernel), so no marker packets are
+ * added between kernels.  Classes: 0 ghost fill, 1 face fluxes (x1, x2 and
+ * x3 faces in one launch), 2 EMFs, 3 stage-1 update, 4 stage-2 update, 5 dt
+ * reduction.  The report sums elapsed milliseconds and counts launches per
+ * class into arrays of nclass >= 6 entries.  Both synchronise the stream.
+ * For measurement; the step itself is unchanged. */
+int grmhd_timing(grmhd_ctx* ctx, int class_mask);
 int grmhd_timing_report(grmhd_ctx* ctx, double* total_ms, long long* launches, int nclass);
 
 const char* grmhd_strerror(int code);

@@ -877,7 +877,7 @@ struct grmhd_ctx {
   // x3 planes per chunk run of the flux/EMF and update schedules
   int kg_flux = 8, kg_update = 8;
   // optional per-kernel-class timing with HIP events on the context's stream
-  bool timing = false;
+  unsigned timing = 0;  // bit c set: launches of class c carry timing events
   struct Mark { hipEvent_t a, b; int cls; };
   Mark* marks = nullptr;
   int nmarks = 0, capmarks = 0;
@@ -959,7 +959,7 @@ struct EvPair {
 };
 EvPair timing_events(grmhd_ctx* c, int cls) {
   EvPair e;
-  if (!c->timing) return e;
+  if (!((c->timing >> cls) & 1u)) return e;
   if (c->nmarks == c->capmarks) {
     int cap = c->capmarks ? 2 * c->capmarks : 256;
     auto* m = (grmhd_ctx::Mark*)realloc(c->marks, sizeof(grmhd_ctx::Mark) * cap);
@@ -967,7 +967,7 @@ EvPair timing_events(grmhd_ctx* c, int cls) {
     c->marks = m;
     for (int q = c->capmarks; q < cap; q++) {
       if (hipEventCreate(&m[q].a) != hipSuccess || hipEventCreate(&m[q].b) != hipSuccess) {
-        c->timing = false;  // no events: stop timing rather than fail the step
+        c->timing = 0;  // no events: stop timing rather than fail the step
         return e;
       }
       c->capmarks = q + 1;
@@ -1459,10 +1459,10 @@ int grmhd_set_schedule(grmhd_ctx* c, int kg_flux, int kg_update) {
   return GRMHD_OK;
 }
 
-int grmhd_timing(grmhd_ctx* c, int enable) {
+int grmhd_timing(grmhd_ctx* c, int class_mask) {
   if (!c) return GRMHD_E_ARG;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return GRMHD_E_HIP;
-  c->timing = enable != 0;
+  c->timing = (unsigned)class_mask & ((1u << T_NCLASS) - 1u);
   c->nmarks = 0;
   return GRMHD_OK;
 }

@@ -264,8 +264,15 @@ class Grmhd:
     def set_schedule(self, kg_flux, kg_update):
         _check(lib().grmhd_set_schedule(self.ctx, int(kg_flux), int(kg_update)))
 
-    def timing(self, enable=True):
-        _check(lib().grmhd_timing(self.ctx, int(enable)))
+    def timing(self, enable=True, classes=None):
+        """Per-launch timing events on (all classes, or the named ones) or off."""
+        if not enable:
+            mask = 0
+        elif classes is None:
+            mask = -1
+        else:
+            mask = sum(1 << self.TIMING_CLASSES.index(k) for k in classes)
+        _check(lib().grmhd_timing(self.ctx, int(mask)))
 
     def timing_report(self):
         n = len(self.TIMING_CLASSES)
