@@ -2,17 +2,19 @@
 //
 // Per stage the step runs, on one stream:
 //   bc      ghost zones from the stage's prims (index remap per axis)
-//   flux d  per face along d: reconstruct 8 prims left/right, evaluate the
-//           face state, flux, conserved variables and characteristic speeds
-//           for both sides, and form the local Lax-Friedrichs flux (the paper
-//           keeps speeds, P->U and the Riemann solve in one kernel, Solvers
-//           section) -- d = 1, 2, 3
+//   flux    per face, for the x1, x2 and x3 faces in one launch: reconstruct
+//           8 prims left/right, evaluate the face state, flux, conserved
+//           variables and characteristic speeds for both sides, and form the
+//           local Lax-Friedrichs flux (the paper keeps speeds, P->U and the
+//           Riemann solve in one kernel, Solvers section)
 //   emf     Flux-CT edge EMFs from the transverse B fluxes
 //   update  per zone: flux divergence (B fluxes rebuilt from edge EMFs),
-//           geometric source, SSPRK2 combination and the 1D_W inversion
-// with every intermediate resident in the caller's HBM workspace.  Layouts
-// are variable-major and x1-fastest, so each wavefront's loads and stores of
-// one variable are contiguous.
+//           geometric source, SSPRK2 combination and the 1D_W inversion;
+//           stage 2 also reduces the next step's CFL rate per workgroup
+// with every intermediate resident in the caller's HBM workspace, and a
+// single-workgroup pass over the CFL partials before the step when its dt
+// is taken on the device.  Layouts are variable-major and x1-fastest, so
+// each wavefront's loads and stores of one variable are contiguous.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>

@@ -157,41 +157,38 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   return wd::combine(a, b, c, d, e, s1 * s2, s0 * s2, s0 * s1);
 }
 
-// FP32 form: the indicators are normalised by the smallest (eps + beta_k),
-// so the smoothest stencil keeps its linear weight, the others' ratios can
-// only shrink (underflow to zero weight, never to 0/0), and the divisions are
-// hardware reciprocals (v_rcp_f32).  Same symmetric indicator forms.
+// FP32 form.  The indicators are scaled by 12 as in the FP64 form and then
+// normalised by the smallest one, r_k = s_k / min s in [1, 1e6] (clamped:
+// a stencil 1e6 times rougher than the smoothest keeps a relative weight
+// below 1e-12 either way, under FP32 resolution); the weights d_k / r_k^2 are
+// formed over the common denominator as in the FP64 form, so the products
+// stay below 1e25 (no overflow, no 0/0), and the two divisions are hardware
+// reciprocals (v_rcp_f32).
 namespace wf {
 typedef float R;
-__device__ __forceinline__ void indicators(R a, R b, R c, R d, R e, R eps, R& q0, R& q1, R& q2) {
-  const R k1312 = 13.0f / 12.0f;
+__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
+  const R eps12 = 12.0f * eps;
   R t0 = (a + c) - 2.0f * b, u0 = fmaf(-4.0f, b, fmaf(3.0f, c, a));
   R t1 = (b + d) - 2.0f * c, u1 = b - d;
   R t2 = (c + e) - 2.0f * d, u2 = fmaf(-4.0f, d, fmaf(3.0f, c, e));
-  R s0 = eps + (k1312 * t0 * t0 + 0.25f * u0 * u0);
-  R s1 = eps + (k1312 * t1 * t1 + 0.25f * u1 * u1);
-  R s2 = eps + (k1312 * t2 * t2 + 0.25f * u2 * u2);
-  R im = __builtin_amdgcn_rcpf(fminf(fminf(s0, s1), s2));
-  R r0 = s0 * im, r1 = s1 * im, r2 = s2 * im;
-  // 1 / (normalised (eps + beta_k))^2
-  q0 = __builtin_amdgcn_rcpf(r0 * r0);
-  q1 = __builtin_amdgcn_rcpf(r1 * r1);
-  q2 = __builtin_amdgcn_rcpf(r2 * r2);
-}
-__device__ __forceinline__ R combine(R a, R b, R c, R d, R e, R q0, R q1, R q2) {
-  const R r6 = 1.0f / 6.0f;
-  R p0 = (2.0f * a - 7.0f * b + 11.0f * c) * r6;
-  R p1 = (-b + 5.0f * c + 2.0f * d) * r6;
-  R p2 = (2.0f * c + 5.0f * d - e) * r6;
-  R w0 = 0.1f * q0, w1 = 0.6f * q1, w2 = 0.3f * q2;
-  return (w0 * p0 + w1 * p1 + w2 * p2) * __builtin_amdgcn_rcpf(w0 + w1 + w2);
+  R s0 = fmaf(13.0f * t0, t0, fmaf(3.0f * u0, u0, eps12));
+  R s1 = fmaf(13.0f * t1, t1, fmaf(3.0f * u1, u1, eps12));
+  R s2 = fmaf(13.0f * t2, t2, fmaf(3.0f * u2, u2, eps12));
+  const R im = __builtin_amdgcn_rcpf(fminf(fminf(s0, s1), s2));
+  R r0 = fminf(s0 * im, 1e6f), r1 = fminf(s1 * im, 1e6f), r2 = fminf(s2 * im, 1e6f);
+  r0 *= r0;
+  r1 *= r1;
+  r2 *= r2;
+  R p0 = fmaf(11.0f, c, fmaf(-7.0f, b, 2.0f * a));
+  R p1 = fmaf(2.0f, d, fmaf(5.0f, c, -b));
+  R p2 = fmaf(5.0f, d, fmaf(2.0f, c, -e));
+  R w0 = r1 * r2, w1 = 6.0f * (r0 * r2), w2 = 3.0f * (r0 * r1);
+  return fmaf(w0, p0, fmaf(w1, p1, w2 * p2)) * __builtin_amdgcn_rcpf(6.0f * ((w0 + w1) + w2));
 }
 }  // namespace wf
 
 __device__ __forceinline__ float weno5(float a, float b, float c, float d, float e, float eps) {
-  float q0, q1, q2;
-  wf::indicators(a, b, c, d, e, eps, q0, q1, q2);
-  return wf::combine(a, b, c, d, e, q0, q1, q2);
+  return wf::weno5(a, b, c, d, e, eps);
 }
 
 // Dual-number WENO5: the same weights, in the plain single-division form;

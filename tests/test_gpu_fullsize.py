@@ -160,3 +160,25 @@ def test_large_grid_256():
     print("256^3 rel L1", rel, fails)
     assert rel.max() <= TOL, rel
     assert s.status()[0] == fails
+
+
+def test_mixed_precision_192_against_oracle():
+    """The reduced-precision workload (192^3 torus, WENO5, FP32 fluxes and
+    EMFs) against the FP64 oracle after one step: the stated density error
+    (about 7e-10 relative L1) and div B at roundoff (the CT update is FP64)."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    grid, P, _ = fm_torus(192, 192, 192, seed=1, gamma=gam)
+    c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, nthreads=THREADS)
+    dt = oracle.estimate_dt(c, P)
+    s = gr.Grmhd(grid, gam, recon=RECON_WENO5, precision=gr.PREC_MIXED)
+    s.load(torch.from_numpy(P).cuda())
+    s.step(dt)
+    out = s.prims().cpu().numpy()
+    ref, _, _ = oracle.run(c, P, dt, 1)
+    rho = np.abs(interior(out)[0] - interior(ref)[0]).sum() / np.abs(interior(ref)[0]).sum()
+    rel = rel_l1(out, ref)
+    print("mixed 192^3 vs oracle: rho rel L1", rho, "per variable", rel)
+    assert rho < 5e-9
+    mx, _ = s.divb()
+    assert mx < 1e-13 * np.abs(interior(P[5:8])).max() / grid.dx[0]
