@@ -18,8 +18,8 @@ import pytest
 
 import oracle
 from parity_util import rel_l1
-from workloads import (linear_mode, fm_torus, interior, GridSpec, BC_PERIODIC, METRIC_MINKOWSKI,
-                       RECON_MC, RECON_WENO5)
+from workloads import (linear_mode, fm_torus, bondi, interior, GridSpec, BC_PERIODIC,
+                       METRIC_MINKOWSKI, RECON_MC, RECON_WENO5)
 
 pytestmark = pytest.mark.gpu
 
@@ -59,6 +59,9 @@ CASES = {
     "torus20x28x6_mc": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, RECON_MC, TOL),
     "torus_unmag_16x20x4_weno": lambda: (fm_torus(16, 20, 4, magnetised=False)[0:2], 13 / 9,
                                          RECON_WENO5, TOL),
+    # Michel accretion, Schwarzschild (a = 0): frozen radial ghosts, polar x2
+    "bondi32x16_mc": lambda: (bondi(32, 16)[0:2], 4 / 3, RECON_MC, TOL),
+    "bondi24x12x2_weno": lambda: (bondi(24, 12, 2)[0:2], 4 / 3, RECON_WENO5, TOL),
 }
 
 

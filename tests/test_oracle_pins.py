@@ -451,3 +451,52 @@ def test_entropy_mode_at_least_second_order():
     for recon in (RECON_MC, RECON_WENO5):
         e = _mode_errors("entropy", recon, (16, 32))
         assert np.all(np.log2(e[0] / e[1]) > 1.9)
+
+
+# ------------------------------------------------------ stationary equilibria
+
+def _equilibrium_drift(make, recon, sizes, T, mask=None):
+    """Relative L1 change of rho after time T (dt from the CFL estimate,
+    evenly dividing T) for each size; the initial state is a stationary
+    solution of the continuum equations, so the change is truncation error."""
+    out = []
+    for n in sizes:
+        g, P, gam = make(n)
+        c = oracle.cfg(g, gam=gam, recon=recon, nthreads=8)
+        dt = oracle.estimate_dt(c, P)
+        ns_ = int(np.ceil(T / dt))
+        Q, _, _ = oracle.run(c, P, T / ns_, ns_)
+        A, B = interior(Q)[0], interior(P)[0]
+        m = np.ones_like(B, dtype=bool) if mask is None else mask(B)
+        out.append(np.abs(A - B)[m].sum() / np.abs(B)[m].sum())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("recon", [RECON_MC, RECON_WENO5])
+def test_bondi_flow_is_preserved_to_second_order(recon):
+    """Michel accretion onto a Schwarzschild hole (r_c = 8, gamma = 4/3, r
+    from 1.9 to 20, frozen radial ghosts holding the exact solution, polar
+    x2): over t = 10 the density drifts from the stationary solution at
+    second order in the zone size (both x1 and x2 refined)."""
+    from workloads import bondi
+
+    def make(n):
+        g, P, c = bondi(n, n // 2)
+        return g, P, c["gamma"]
+    d = _equilibrium_drift(make, recon, (32, 64), 10.0)
+    order = np.log2(d[0] / d[1])
+    assert d[1] < 5e-4 and 1.8 < order < 2.4, (d, order)
+
+
+@pytest.mark.parametrize("recon", [RECON_MC, RECON_WENO5])
+def test_fm_torus_equilibrium_is_preserved_to_second_order(recon):
+    """The unmagnetised, unperturbed Fishbone-Moncrief torus (axisymmetric,
+    one x3 zone) is stationary: over t = 5 its density in the torus body
+    (rho > 0.3 rho_max, away from the atmosphere, which is not in
+    equilibrium) drifts at second order in the zone size."""
+    def make(n):
+        g, P, _ = fm_torus(n, n, 1, noise=0.0, magnetised=False)
+        return g, P, 13.0 / 9.0
+    d = _equilibrium_drift(make, recon, (32, 64), 5.0, mask=lambda B: B > 0.3)
+    order = np.log2(d[0] / d[1])
+    assert d[1] < 1e-3 and order > 1.8, (d, order)

@@ -72,3 +72,36 @@ def test_pack_is_seeded_and_uses_global_data():
         i0, j0, k0 = b["offset"]
         n = b["n"]
         assert np.array_equal(b["prims"], P[:, k0:k0 + n + 2 * NG, j0:j0 + n + 2 * NG, i0:i0 + n + 2 * NG])
+
+
+def test_michel_solution_constants_and_sonic_point():
+    """The Michel flow: mass flux and Bernoulli constant are the same at every
+    zone centre, the flow is supersonic inside the sonic radius and subsonic
+    outside, and at r_c the sound speed and u^r meet Michel's conditions."""
+    import math
+    from workloads import bondi, michel_constants, michel_rho
+    g, P, c = bondi(48, 4)
+    x1, _, _ = g.centers()
+    r = np.exp(x1)
+    rho = P[0, 3, 3]
+    gam = c["gamma"]
+    theta = c["K"] * rho ** (gam - 1.0)
+    h = 1.0 + gam / (gam - 1.0) * theta
+    ur = -c["mdot"] / (4.0 * math.pi * r * r * rho)
+    bern = h * h * (1.0 - 2.0 / r + ur * ur)
+    assert np.allclose(bern, c["bern"], rtol=1e-12)
+    cs2 = gam * theta / h
+    # the radial velocity measured by a static observer exceeds the sound
+    # speed exactly inside r_c
+    outside = r > 2.0
+    v2 = ur[outside] ** 2 / (1.0 - 2.0 / r[outside] + ur[outside] ** 2)
+    assert np.all((v2 > cs2[outside]) == (r[outside] < c["rc"]))
+    rc = c["rc"]
+    rho_c = michel_rho(rc, c)
+    th_c = c["K"] * rho_c ** (gam - 1.0)
+    urc = c["mdot"] / (4.0 * math.pi * rc * rc * rho_c)
+    assert urc ** 2 == pytest.approx(1.0 / (2.0 * rc), rel=1e-8)
+    cs2c = gam * th_c / (1.0 + gam / (gam - 1.0) * th_c)
+    assert cs2c == pytest.approx(urc ** 2 / (1.0 - 3.0 * urc ** 2), rel=1e-8)
+    c2 = michel_constants(rc=rc, gamma=gam, rho_c=2.0)
+    assert c2["K"] * 2.0 ** (gam - 1.0) == pytest.approx(c["K"], rel=1e-14)
