@@ -71,6 +71,8 @@ typedef struct {
   int newton_maxit;
   double cfl;
   int nthreads;
+  int inverter;        // 0: 1D_W (Noble et al.), 1: Kastaun et al. bracketed recovery
+  double kastaun_wmax; // Lorentz-factor cap of the Kastaun recovery
 } orc_cfg;
 }
 
@@ -676,6 +678,147 @@ int u_to_p(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[N
   return 0;
 }
 
+// Kastaun et al. (2021) recovery, the robust alternative to 1D_W the
+// Algorithm section names.  With the same normal-frame quantities as above
+// (D, the spatial projection S of Q, E = -Q.n, Bn), scaled by D:
+//   r^2 = S.S / D^2,  b^2 = Bn.Bn / D,  rb = S.Bn / D^(3/2),  q = E/D - 1,
+// every fluid quantity follows from mu = 1/(h W) (h the specific enthalpy,
+// W the normal-frame Lorentz factor):
+//   x = 1/(1 + mu b^2),  rbar^2 = x^2 r^2 + mu x (1 + x) rb^2,
+//   qbar = q - b^2/2 - mu^2 x^2 (b^2 r^2 - rb^2)/2,
+//   v^2 = min(mu^2 rbar^2, vmax^2),  W = 1/sqrt(1 - v^2),  rho = D/W,
+//   eps = max(W (qbar - mu rbar^2) + v^2 W^2/(1 + W), 0),
+//   a = p/(rho (1 + eps)) = (gam - 1) eps/(1 + eps),
+//   nu = max((1 + a)(1 + eps)/W, (1 + a)(1 + qbar - mu rbar^2)),
+// and mu is the root of f(mu) = mu - 1/(nu + mu rbar^2).  Since h >= 1,
+// mu <= mu+ with mu+ sqrt(1 + rbar^2(mu+)) = 1; f < 0 at 0 and f >= 0 at mu+,
+// so both roots are bracketed and found by the Illinois (modified regula
+// falsi) iteration, to |d mu| <= tol mu.  Then u = rho eps and
+// u~^i = W v^i with v^i = mu x (S^i/D + mu rb b^i).  No guess is needed; a
+// failure (no bracket, no convergence, eps <= 0, non-finite) keeps the
+// guess's hydro prims as 1D_W does.
+int u_to_p_kastaun(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[NV],
+                   real P[NV]) {
+  const real gam = c.gam;
+  for (int k = 0; k < 3; k++) P[B1 + k] = U[B1 + k] / G.gdet;
+  auto failed = [&]() {
+    for (int v = 0; v < 5; v++) P[v] = guess[v];
+    return 1;
+  };
+  real alpha = G.alpha;
+  real D = alpha * U[RHO] / G.gdet;
+  if (!(D > 0.0) || !isfinite((real)D)) return failed();
+  real Qcov[4];
+  Qcov[0] = alpha * (U[UU] / G.gdet - U[RHO] / G.gdet);
+  for (int i = 1; i < 4; i++) Qcov[i] = alpha * U[UU + i] / G.gdet;
+  real Bn[4] = {0.0, alpha * P[B1], alpha * P[B2], alpha * P[B3]};
+  real ncov[4] = {-alpha, 0.0, 0.0, 0.0};
+  real ncon[4], Qcon[4];
+  for (int m = 0; m < 4; m++) {
+    ncon[m] = 0.0;
+    Qcon[m] = 0.0;
+    for (int n = 0; n < 4; n++) {
+      ncon[m] += G.gcon[m][n] * ncov[n];
+      Qcon[m] += G.gcon[m][n] * Qcov[n];
+    }
+  }
+  real Qdotn = 0.0, QdotQ = 0.0, QdotB = 0.0, Bsq = 0.0;
+  for (int m = 0; m < 4; m++) {
+    Qdotn += Qcov[m] * ncon[m];
+    QdotQ += Qcov[m] * Qcon[m];
+  }
+  for (int i = 1; i < 4; i++) {
+    QdotB += Qcov[i] * Bn[i];
+    for (int j = 1; j < 4; j++) Bsq += G.gcov[i][j] * Bn[i] * Bn[j];
+  }
+  real Ssq = QdotQ + Qdotn * Qdotn;
+  if (Ssq < 0.0) Ssq = 0.0;
+  const real r2 = Ssq / (D * D), b2 = Bsq / D, rb = QdotB / (D * sqrt(D)), q = -Qdotn / D - 1.0;
+  const real rb2 = rb * rb;
+  const real vmax2 = 1.0 - 1.0 / (c.kastaun_wmax * c.kastaun_wmax);
+
+  struct State { real x, rbar2, qbar, v2, W, eps, nu; };
+  auto state = [&](real mu) {
+    State s;
+    s.x = 1.0 / (1.0 + mu * b2);
+    s.rbar2 = s.x * s.x * r2 + mu * s.x * (1.0 + s.x) * rb2;
+    s.qbar = q - 0.5 * b2 - 0.5 * (mu * mu) * (s.x * s.x) * (b2 * r2 - rb2);
+    s.v2 = mu * mu * s.rbar2;
+    if (s.v2 > vmax2) s.v2 = vmax2;
+    s.W = 1.0 / sqrt(1.0 - s.v2);
+    s.eps = s.W * (s.qbar - mu * s.rbar2) + s.v2 * s.W * s.W / (1.0 + s.W);
+    if (s.eps < 0.0) s.eps = 0.0;
+    real a = (gam - 1.0) * s.eps / (1.0 + s.eps);
+    real nuA = (1.0 + a) * (1.0 + s.eps) / s.W, nuB = (1.0 + a) * (1.0 + s.qbar - mu * s.rbar2);
+    s.nu = nuA > nuB ? nuA : nuB;
+    return s;
+  };
+  auto f = [&](real mu) {
+    State s = state(mu);
+    return mu - 1.0 / (s.nu + mu * s.rbar2);
+  };
+  auto fa = [&](real mu) {
+    real x = 1.0 / (1.0 + mu * b2);
+    real rbar2 = x * x * r2 + mu * x * (1.0 + x) * rb2;
+    return mu * sqrt(1.0 + rbar2) - 1.0;
+  };
+  // Illinois iteration for a root of g in [a, b] with g(a) < 0 < g(b): stop
+  // when an iterate moves by at most tol times itself or hits g = 0.
+  auto illinois = [&](auto g, real a, real b, real ga, real gb, real tol, real& root) {
+    int side = 0;
+    real prev = b;
+    for (int it = 0; it < 4 * c.newton_maxit; it++) {
+      real m = (a * gb - b * ga) / (gb - ga);
+      if (!(m > a && m < b)) m = 0.5 * (a + b);
+      real gm = g(m);
+      if (gm == 0.0 || fabs(m - prev) <= tol * m) { root = m; return true; }
+      prev = m;
+      if (gm < 0.0) {
+        a = m; ga = gm;
+        if (side == -1) gb = 0.5 * gb;
+        side = -1;
+      } else {
+        b = m; gb = gm;
+        if (side == 1) ga = 0.5 * ga;
+        side = 1;
+      }
+    }
+    return false;
+  };
+  real mup;
+  if (!illinois(fa, 0.0, 1.0, -1.0, fa(1.0), 1e-12, mup)) return failed();
+  mup = mup * (1.0 + 1e-10);
+  if (mup > 1.0) mup = 1.0;
+  real f0 = f(0.0), f1 = f(mup);
+  if (!(f0 < 0.0) || !(f1 >= 0.0)) return failed();
+  real mu;
+  if (f1 == 0.0)
+    mu = mup;
+  else if (!illinois(f, 0.0, mup, f0, f1, c.newton_tol, mu))
+    return failed();
+  State s = state(mu);
+  real rho = D / s.W;
+  real u = rho * s.eps;
+  if (!(rho > 0.0) || !(u > 0.0) || !isfinite((real)u)) return failed();
+  real pre = s.W * mu * s.x / D;
+  real ut[3];
+  for (int i = 1; i < 4; i++) {
+    real St = Qcon[i] + ncon[i] * Qdotn;
+    ut[i - 1] = pre * (St + mu * QdotB * Bn[i] / D);
+    if (!isfinite((real)ut[i - 1])) return failed();
+  }
+  P[RHO] = rho;
+  P[UU] = u;
+  P[U1] = ut[0];
+  P[U2] = ut[1];
+  P[U3] = ut[2];
+  return 0;
+}
+
+int invert(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[NV], real P[NV]) {
+  return c.inverter == 1 ? u_to_p_kastaun(c, G, U, guess, P) : u_to_p(c, G, U, guess, P);
+}
+
 // ------------------------------------------------------------------ step --
 
 void cons_at(const Grid& g, const real P[NV], int i, int j, real U[NV]) {
@@ -735,7 +878,7 @@ long step(const Grid& g, std::vector<real>& P, real dt, int* flags) {
               Unew[v] = 0.5 * (Vc(Un, g, v, i, j, k) + Vc(U1v, g, v, i, j, k)) + 0.5 * (dt * L[v]);
           }
           for (int v = 0; v < NV; v++) guess[v] = p[v];
-          int f = u_to_p(g.c, g.gC[g.id2(i, j)], Unew, guess, pn);
+          int f = invert(g.c, g.gC[g.id2(i, j)], Unew, guess, pn);
           fails += f;
           if (flags && f) flags[g.id(i, j, k)] += 1 << stage;
           for (int v = 0; v < NV; v++) V(Pout, g, v, i, j, k) = pn[v];
@@ -920,7 +1063,7 @@ long orc_cons_to_prims(const orc_cfg* c, const double* cons, const double* guess
         real u[NV], gs[NV], p[NV];
         long q = g.id(i, j, k);
         for (int v = 0; v < NV; v++) { u[v] = cons[v * g.nz + q]; gs[v] = guess[v * g.nz + q]; }
-        int f = u_to_p(*c, g.gC[g.id2(i, j)], u, gs, p);
+        int f = invert(*c, g.gC[g.id2(i, j)], u, gs, p);
         fails += f;
         if (flags) flags[q] = f;
         for (int v = 0; v < NV; v++) prims[v * g.nz + q] = (double)p[v];
@@ -991,7 +1134,7 @@ int orc_point_u_to_p(const orc_cfg* c, const double* cons, const double* guess, 
   geom_point(*c, x1, x2, G);
   real u[NV], gs[NV], p[NV];
   for (int v = 0; v < NV; v++) { u[v] = cons[v]; gs[v] = guess[v]; }
-  int r = u_to_p(*c, G, u, gs, p);
+  int r = invert(*c, G, u, gs, p);
   for (int v = 0; v < NV; v++) prims[v] = (double)p[v];
   return r;
 }
@@ -1054,7 +1197,7 @@ void orc_count_zone_update(const orc_cfg* c, const double* prims, int i, int j, 
   rhs(g, F, p, i, j, k, L);
   cons_at(g, p, i, j, u0);
   for (int v = 0; v < NV; v++) U[v] = u0[v] + (real)dt * L[v];
-  u_to_p(g.c, g.gC[g.id2(i, j)], U, p, pn);
+  invert(g.c, g.gC[g.id2(i, j)], U, p, pn);
   tally_out(out);
 }
 
