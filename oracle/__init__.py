@@ -39,7 +39,10 @@ class Cfg(C.Structure):
                 ("gam", C.c_double), ("recon", C.c_int),
                 ("weno_eps", C.c_double), ("newton_tol", C.c_double),
                 ("newton_maxit", C.c_int), ("cfl", C.c_double),
-                ("nthreads", C.c_int)]
+                ("nthreads", C.c_int), ("inverter", C.c_int),
+                ("kastaun_wmax", C.c_double)]
+
+INV_1DW, INV_KASTAUN = 0, 1
 
 
 _lib = None
@@ -93,7 +96,7 @@ def lib(counting=False):
 
 
 def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
-        newton_maxit=30, cfl=0.9, nthreads=None):
+        newton_maxit=30, cfl=0.9, nthreads=None, inverter=INV_1DW, kastaun_wmax=1e3):
     c = Cfg()
     c.n1, c.n2, c.n3 = grid.n1, grid.n2, grid.n3
     c.x1min, c.x1max = grid.x1min, grid.x1max
@@ -106,6 +109,7 @@ def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
     c.gam, c.recon, c.weno_eps = gam, int(recon), weno_eps
     c.newton_tol, c.newton_maxit, c.cfl = newton_tol, newton_maxit, cfl
     c.nthreads = nthreads or os.cpu_count() or 1
+    c.inverter, c.kastaun_wmax = int(inverter), float(kastaun_wmax)
     return c
 
 
