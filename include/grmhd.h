@@ -7,7 +7,8 @@
  * Flux-CT magnetic-field transport, geometric source terms from cached
  * metric and connection (Core section, GRCoordinates), and the 1D_W
  * conserved->primitive inversion named in the Algorithm and Performance
- * sections.  Metrics: flat Minkowski (Cartesian) or Kerr (M = 1) in modified
+ * sections (or, selected per context, the bracketed Kastaun et al. 2021
+ * recovery the Algorithm section lists among the robust ones).  Metrics: flat Minkowski (Cartesian) or Kerr (M = 1) in modified
  * Kerr-Schild coordinates r = exp(x1), theta = pi x2 + (1-h)/2 sin(2 pi x2),
  * phi = x3.
  *
@@ -44,6 +45,7 @@ enum { GRMHD_OK = 0, GRMHD_E_ARG = -1, GRMHD_E_HIP = -2, GRMHD_E_STATE = -3,
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KERR_MKS = 1 };
 enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1 };
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
+enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2,
        GRMHD_BC_FROZEN = 3 };
 
@@ -74,6 +76,13 @@ typedef struct {
   int recon;          /* GRMHD_RECON_* */
   int precision;      /* GRMHD_PREC_*: MIXED = FP32 reconstruction, fluxes, EMFs */
   int floors;         /* must be 0 (no floors on this path) */
+  int inverter;       /* GRMHD_INV_*: 1D_W Newton from the stage-input prims,
+                         or the Kastaun et al. root bracket in mu = 1/(h W),
+                         which needs no guess (Illinois iteration stopped at
+                         |d mu| <= newton_tol mu, at most 4 newton_maxit
+                         iterations); both leave a failed zone at its guess */
+  double kastaun_wmax; /* Lorentz-factor cap of the Kastaun recovery (> 1);
+                          ignored by 1D_W */
 } grmhd_params;
 
 /* Bytes of device workspace a context with this grid and parameters needs. */

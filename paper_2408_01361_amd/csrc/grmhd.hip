@@ -55,6 +55,8 @@ struct Dev {
   int pole_lo, pole_hi;
   double gam, weno_eps, tol;
   int maxit;
+  int inverter;       // GRMHD_INV_*
+  double vmax2;       // 1 - 1/W_max^2, the Kastaun recovery's speed cap
   SpaceTime st;
 };
 
@@ -536,6 +538,146 @@ __device__ int invert_1dw(const Dev& g, const PointMetric<double>& m, const doub
   return 0;
 }
 
+// Kastaun et al. (2021) recovery, the bracketed alternative to 1D_W (the
+// Algorithm section names it among the robust inversions).  With D, the
+// spatial projection S of Q and Bn as in 1D_W, scaled by D:
+//   r^2 = S.S/D^2, b^2 = Bn.Bn/D, rb = S.Bn/D^(3/2), q = -Q.n/D - 1,
+// all fluid quantities are functions of mu = 1/(h W):
+//   x = 1/(1 + mu b^2), rbar^2 = x^2 r^2 + mu x (1 + x) rb^2,
+//   qbar = q - b^2/2 - mu^2 x^2 (b^2 r^2 - rb^2)/2,
+//   v^2 = min(mu^2 rbar^2, vmax^2), W = (1 - v^2)^(-1/2), rho = D/W,
+//   eps = max(W (qbar - mu rbar^2) + v^2 W^2/(1 + W), 0),
+//   a = (gam - 1) eps/(1 + eps),
+//   nu = max((1 + a)(1 + eps)/W, (1 + a)(1 + qbar - mu rbar^2)),
+// and mu solves mu = 1/(nu + mu rbar^2).  h >= 1 bounds mu by mu+, the root
+// of mu sqrt(1 + rbar^2(mu)) = 1 (found first, to 1e-12, then widened by
+// 1e-10); the root in [0, mu+] is bracketed and taken by the Illinois
+// (modified regula falsi) iteration to |d mu| <= tol mu, at most 4 maxit
+// iterations each.  No guess is used except as the failure value (the
+// guess's hydro prims, as in 1D_W).  Evaluated in the same operation order
+// as the CPU reference of the method, without contraction.
+__device__ int invert_kastaun(const Dev& g, const PointMetric<double>& m, const double U[NVAR],
+                              const double guess[NVAR], double P[NVAR]) {
+#pragma clang fp contract(off)
+  const double gam = g.gam;
+  const double gd = m.gdet;
+  P[B1] = U[B1] / gd;
+  P[B2] = U[B2] / gd;
+  P[B3] = U[B3] / gd;
+  auto fail = [&]() {
+#pragma unroll
+    for (int v = 0; v < 5; v++) P[v] = guess[v];
+    return 1;
+  };
+  const double al = m.alpha;
+  const double D = al * U[RHO] / gd;
+  if (!(D > 0.0) || !isfinite(D)) return fail();
+  double Q[4] = {al * (U[UU] / gd - U[RHO] / gd), al * U[U1] / gd, al * U[U2] / gd, al * U[U3] / gd};
+  const double Bn[4] = {0.0, al * P[B1], al * P[B2], al * P[B3]};
+  double ncon[4], Qup[4];
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    ncon[a] = m.gcon[sidx(a, 0)] * -al;
+    Qup[a] = m.gcon[sidx(a, 0)] * Q[0] + m.gcon[sidx(a, 1)] * Q[1] + m.gcon[sidx(a, 2)] * Q[2] +
+             m.gcon[sidx(a, 3)] * Q[3];
+  }
+  const double Qn = Q[0] * ncon[0] + Q[1] * ncon[1] + Q[2] * ncon[2] + Q[3] * ncon[3];
+  const double QQ = Q[0] * Qup[0] + Q[1] * Qup[1] + Q[2] * Qup[2] + Q[3] * Qup[3];
+  const double QB = Q[1] * Bn[1] + Q[2] * Bn[2] + Q[3] * Bn[3];
+  double Bsq = 0.0;
+#pragma unroll
+  for (int a = 1; a < 4; a++)
+#pragma unroll
+    for (int b = 1; b < 4; b++) Bsq += m.gcov[sidx(a, b)] * Bn[a] * Bn[b];
+  const double Ssq = fmax(QQ + Qn * Qn, 0.0);
+  const double r2 = Ssq / (D * D), b2 = Bsq / D, rb = QB / (D * sqrt(D)), q = -Qn / D - 1.0;
+  const double rb2 = rb * rb;
+  const double vmax2 = g.vmax2;
+  const int maxit = 4 * g.maxit;
+
+  struct St {
+    double x, rbar2, qbar, W, eps, nu;
+  };
+  auto state = [&](double mu) {
+    St s;
+    s.x = 1.0 / (1.0 + mu * b2);
+    s.rbar2 = s.x * s.x * r2 + mu * s.x * (1.0 + s.x) * rb2;
+    s.qbar = q - 0.5 * b2 - 0.5 * (mu * mu) * (s.x * s.x) * (b2 * r2 - rb2);
+    double v2 = fmin(mu * mu * s.rbar2, vmax2);
+    s.W = 1.0 / sqrt(1.0 - v2);
+    s.eps = fmax(s.W * (s.qbar - mu * s.rbar2) + v2 * s.W * s.W / (1.0 + s.W), 0.0);
+    double a = (gam - 1.0) * s.eps / (1.0 + s.eps);
+    s.nu = fmax((1.0 + a) * (1.0 + s.eps) / s.W, (1.0 + a) * (1.0 + s.qbar - mu * s.rbar2));
+    return s;
+  };
+  auto f = [&](double mu) {
+    St s = state(mu);
+    return mu - 1.0 / (s.nu + mu * s.rbar2);
+  };
+  auto fa = [&](double mu) {
+    double x = 1.0 / (1.0 + mu * b2);
+    double rbar2 = x * x * r2 + mu * x * (1.0 + x) * rb2;
+    return mu * sqrt(1.0 + rbar2) - 1.0;
+  };
+  // root of h in [lo, hi] with h(lo) < 0 <= h(hi); false after maxit steps
+  auto illinois = [&](auto h, double lo, double hi, double hlo, double hhi, double tol, double& root) {
+    int side = 0;
+    double prev = hi;
+    for (int it = 0; it < maxit; it++) {
+      double mid = (lo * hhi - hi * hlo) / (hhi - hlo);
+      if (!(mid > lo && mid < hi)) mid = 0.5 * (lo + hi);
+      double hm = h(mid);
+      if (hm == 0.0 || fabs(mid - prev) <= tol * mid) {
+        root = mid;
+        return true;
+      }
+      prev = mid;
+      if (hm < 0.0) {
+        lo = mid;
+        hlo = hm;
+        if (side == -1) hhi = 0.5 * hhi;
+        side = -1;
+      } else {
+        hi = mid;
+        hhi = hm;
+        if (side == 1) hlo = 0.5 * hlo;
+        side = 1;
+      }
+    }
+    return false;
+  };
+  double mup;
+  if (!illinois(fa, 0.0, 1.0, -1.0, fa(1.0), 1e-12, mup)) return fail();
+  mup = fmin(mup * (1.0 + 1e-10), 1.0);
+  const double f0 = f(0.0), f1 = f(mup);
+  if (!(f0 < 0.0) || !(f1 >= 0.0)) return fail();
+  double mu = mup;
+  if (f1 != 0.0 && !illinois(f, 0.0, mup, f0, f1, g.tol, mu)) return fail();
+  St s = state(mu);
+  const double rho = D / s.W;
+  const double u = rho * s.eps;
+  if (!(rho > 0.0) || !(u > 0.0) || !isfinite(u)) return fail();
+  const double pre = s.W * mu * s.x / D;
+  double ut[3];
+#pragma unroll
+  for (int a = 1; a < 4; a++) {
+    ut[a - 1] = pre * ((Qup[a] + ncon[a] * Qn) + mu * QB * Bn[a] / D);
+    if (!isfinite(ut[a - 1])) return fail();
+  }
+  P[RHO] = rho;
+  P[UU] = u;
+  P[U1] = ut[0];
+  P[U2] = ut[1];
+  P[U3] = ut[2];
+  return 0;
+}
+
+__device__ __forceinline__ int invert(const Dev& g, const PointMetric<double>& m, const double U[NVAR],
+                                      const double guess[NVAR], double P[NVAR]) {
+  if (g.inverter == GRMHD_INV_KASTAUN) return invert_kastaun(g, m, U, guess, P);
+  return invert_1dw(g, m, U, guess, P);
+}
+
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
@@ -687,7 +829,7 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
     for (int v = 0; v < NVAR; v++) U[v] = V[v * nz + c] + 0.5 * (dt * L[v]);
   }
   double out[NVAR];
-  int bad = invert_1dw(g, m, U, p, out);
+  int bad = invert(g, m, U, p, out);
 #pragma unroll
   for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
   if (flags) flags[c] = (unsigned char)bad;
@@ -846,7 +988,7 @@ __global__ void __launch_bounds__(BLOCK) k_cons_to_prims(Dev g, Box box, const d
   }
   PointMetric<double> m;
   load_metric<double>(tabC, g.plane, pid(g, i, j), m);
-  int bad = invert_1dw(g, m, u, gs, p);
+  int bad = invert(g, m, u, gs, p);
 #pragma unroll
   for (int v = 0; v < NVAR; v++) P[v * g.nz + c] = p[v];
   if (flags) flags[c] = bad;
@@ -918,6 +1060,8 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
   if (p->precision != GRMHD_PREC_FP64 && p->precision != GRMHD_PREC_MIXED) return false;
   if (p->floors != 0 || !(p->gamma_ad > 1.0) || p->newton_maxit < 1 || !(p->newton_tol > 0.0))
     return false;
+  if (p->inverter != GRMHD_INV_1DW && p->inverter != GRMHD_INV_KASTAUN) return false;
+  if (p->inverter == GRMHD_INV_KASTAUN && !(p->kastaun_wmax > 1.0)) return false;
   return true;
 }
 
@@ -1143,6 +1287,8 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   g.weno_eps = params->weno_eps;
   g.tol = params->newton_tol;
   g.maxit = params->newton_maxit;
+  g.inverter = params->inverter;
+  g.vmax2 = 1.0 - 1.0 / (params->kastaun_wmax * params->kastaun_wmax);
   g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
   k_geometry<<<blocks_for(g.plane), BLOCK, 0, c->stream>>>(g, c->tabC, c->tabF1, c->tabF2, c->corner,
                                                            c->conn);
@@ -1651,6 +1797,8 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
     g.weno_eps = params->weno_eps;
     g.tol = params->newton_tol;
     g.maxit = params->newton_maxit;
+    g.inverter = params->inverter;
+    g.vmax2 = 1.0 - 1.0 / (params->kastaun_wmax * params->kastaun_wmax);
     g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
     BlockView& v = pk->views[b];
     default_tile(n[b], v.t1, v.t2, v.t3);

@@ -17,6 +17,7 @@ OK, E_ARG, E_HIP, E_STATE, E_NOMEM = 0, -1, -2, -3, -4
 METRIC_MINKOWSKI, METRIC_KERR_MKS = 0, 1
 RECON_MC, RECON_WENO5 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+INV_1DW, INV_KASTAUN = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN = 0, 1, 2, 3
 NG, NVAR = 3, 8
 
@@ -39,7 +40,8 @@ class grmhd_metric(C.Structure):
 class grmhd_params(C.Structure):
     _fields_ = [("gamma_ad", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("recon", C.c_int),
-                ("precision", C.c_int), ("floors", C.c_int)]
+                ("precision", C.c_int), ("floors", C.c_int), ("inverter", C.c_int),
+                ("kastaun_wmax", C.c_double)]
 
 
 EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_step",
@@ -142,12 +144,13 @@ class Grmhd:
 
     def __init__(self, spec, gamma_ad, recon=RECON_WENO5, precision=PREC_FP64, cfl=0.9,
                  weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda",
-                 stream=None, strict=False):
+                 stream=None, strict=False, inverter=INV_1DW, kastaun_wmax=1e3):
         self.spec = spec
         self.grid = make_grid(spec)
         self.metric = grmhd_metric(int(spec.metric), float(spec.a), float(spec.hslope))
         self.params = grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
-                                   int(newton_maxit), int(recon), int(precision), 0)
+                                   int(newton_maxit), int(recon), int(precision), 0,
+                                   int(inverter), float(kastaun_wmax))
         self.strict = strict
         L = lib()
         nbytes = L.grmhd_workspace_bytes(C.byref(self.grid), C.byref(self.params))
@@ -287,7 +290,8 @@ class Pack:
     by one persistent launch per RK2 stage."""
 
     def __init__(self, global_spec, sizes, offsets, gamma_ad, recon=RECON_WENO5, cfl=0.9,
-                 weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda", stream=None):
+                 weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda", stream=None,
+                 inverter=INV_1DW, kastaun_wmax=1e3):
         L = lib()
         self.nb = len(sizes)
         self.sizes = [int(n) for n in sizes]
@@ -298,7 +302,8 @@ class Pack:
         self.metric = grmhd_metric(int(global_spec.metric), float(global_spec.a),
                                    float(global_spec.hslope))
         self.params = grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
-                                   int(newton_maxit), int(recon), PREC_FP64, 0)
+                                   int(newton_maxit), int(recon), PREC_FP64, 0,
+                                   int(inverter), float(kastaun_wmax))
         nbytes = L.grmhd_pack_workspace_bytes(self.nb, self._n)
         if nbytes == 0:
             raise GrmhdError("invalid pack")

@@ -38,10 +38,10 @@ def _gr():
     return grmhd
 
 
-def run_gpu(grid, P, gam, recon, dts, precision=0):
+def run_gpu(grid, P, gam, recon, dts, precision=0, inverter=0):
     torch = _torch()
     gr = _gr()
-    s = gr.Grmhd(grid, gam, recon=recon, precision=precision)
+    s = gr.Grmhd(grid, gam, recon=recon, precision=precision, inverter=inverter)
     s.load(torch.from_numpy(P))
     for dt in dts:
         s.step(dt)
@@ -76,6 +76,89 @@ def test_step_parity(case):
     print(case, "dts", dts, "fails", fails, gfails, "rel L1", r)
     assert gfails == fails
     assert r.max() <= tol, r
+
+
+KASTAUN_CASES = ["fast32_mc", "torus24_weno", "torus20x28x6_mc", "bondi32x16_mc"]
+
+
+@pytest.mark.parametrize("case", KASTAUN_CASES)
+def test_step_parity_kastaun(case):
+    """The same steps with the Kastaun et al. recovery on both sides."""
+    (grid, P), gam, recon, tol = CASES[case]()
+    c = oracle.cfg(grid, gam=gam, recon=recon, inverter=oracle.INV_KASTAUN)
+    ref, fails, dts, flags = oracle.run(c, P, -1, 2, flags=True)
+    out, gfails, _ = run_gpu(grid, P, gam, recon, dts, inverter=oracle.INV_KASTAUN)
+    r = rel_l1(out, ref)
+    print(case, "kastaun dts", dts, "fails", fails, gfails, "rel L1", r)
+    assert gfails == fails
+    assert r.max() <= tol, r
+
+
+def hard_states(grid, seed):
+    """Padded prims of seeded strongly magnetised, fast states over a Kerr
+    grid: normal-frame four-velocity up to ~60, b^2/rho from 1 to 1e4, u/rho
+    down to 1e-5 (each velocity and field component scaled by the zone's
+    sqrt(g_ii)).  Also returns, per zone, the scale rho W^2 (1 + b^2/rho)
+    of the total energy density, to which the conserved variables fix u."""
+    rng = np.random.default_rng(seed)
+    c = oracle.cfg(grid, gam=13 / 9)
+    x1, x2, _ = grid.centers()
+    shape = (grid.n3 + 6, grid.n2 + 6, grid.n1 + 6)
+    n = int(np.prod(shape))
+    rho = 10 ** rng.uniform(-6, 0, n)
+    u = rho * 10 ** rng.uniform(-5, 1, n)
+    ut = rng.normal(size=(3, n)) * 10 ** rng.uniform(0, 1.6, n)
+    sig = 10 ** rng.uniform(0, 4, n)
+    B = rng.normal(size=(3, n))
+    B *= np.sqrt(sig * rho / (B * B).sum(0))
+    P = np.vstack([rho, u, ut, B]).reshape((8,) + shape)
+    for j in range(shape[1]):
+        for i in range(shape[2]):
+            gcov = oracle.geom(c, x1[i], x2[j])[0]
+            for a in range(3):
+                sc = np.sqrt(gcov[1 + a, 1 + a])
+                P[2 + a, :, j, i] /= sc
+                P[5 + a, :, j, i] /= sc
+    esc = (rho * (1 + (ut * ut).sum(0)) * (1 + sig)).reshape(shape)
+    return P, esc
+
+
+def rel_l1_energy_scaled(a, b, esc):
+    """rel_l1, with u measured against the summed energy scale."""
+    r = rel_l1(a, b)
+    r[1] = np.abs(interior(a)[1] - interior(b)[1]).sum() / interior(esc[None])[0].sum()
+    return r
+
+
+def test_kastaun_inversion_parity_on_hard_states():
+    """cons -> prims at hard states: the GPU's Kastaun recovery equals the
+    oracle's (1e-12 relative L1, u against the energy scale since the
+    conserved variables fix it no better; the same zones recovered: all of
+    them), and recovers prims where 1D_W, from the same 20 % perturbed guess,
+    fails on some zones on both sides.  Which zones 1D_W loses here depends
+    on rounding along its Newton path from the poor guess (the GPU and the
+    oracle lose a few different ones), the fragility the bracketed recovery
+    removes; 1D_W's flag parity is held on the torus test below."""
+    torch = _torch()
+    gr = _gr()
+    grid, _, _ = fm_torus(16, 24, 8)
+    P, esc = hard_states(grid, 21)
+    c = oracle.cfg(grid, gam=13 / 9, inverter=oracle.INV_KASTAUN)
+    U = oracle.prims_to_cons(c, P)
+    rng = np.random.default_rng(22)
+    guess = P * (1 + 0.2 * rng.uniform(-1, 1, P.shape))
+    P_ref, n_ref, f_ref = oracle.cons_to_prims(c, U, guess)
+    s = gr.Grmhd(grid, 13 / 9, inverter=gr.INV_KASTAUN)
+    P_gpu, n_gpu, f_gpu = s.cons_to_prims(torch.from_numpy(U), torch.from_numpy(guess))
+    r = rel_l1_energy_scaled(P_gpu.cpu().numpy(), P_ref, esc)
+    print("kastaun fails", n_ref, n_gpu, "rel L1", r)
+    assert n_ref == 0 and n_gpu == 0
+    assert r.max() <= 1e-12, r
+    w = gr.Grmhd(grid, 13 / 9)
+    _, n_w, _ = w.cons_to_prims(torch.from_numpy(U), torch.from_numpy(guess))
+    _, n_wref, _ = oracle.cons_to_prims(oracle.cfg(grid, gam=13 / 9), U, guess)
+    print("1D_W fails", n_wref, n_w)
+    assert n_w > 0 and n_wref > 0
 
 
 def test_prims_to_cons_and_inversion_parity():

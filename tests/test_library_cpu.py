@@ -42,6 +42,14 @@ def test_workspace_and_argument_validation():
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(p2)) == 0
     p3 = grmhd.grmhd_params(13 / 9, 0.9, 1e-26, 1e-14, 30, 0, grmhd.PREC_FP64, 1)
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(p3)) == 0
+    # the Kastaun recovery needs a Lorentz-factor cap above 1; 1D_W ignores it
+    pk = grmhd.grmhd_params(13 / 9, 0.9, 1e-26, 1e-14, 30, 0, grmhd.PREC_FP64, 0,
+                            grmhd.INV_KASTAUN, 1e3)
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(pk)) == nb
+    pk.kastaun_wmax = 1.0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(pk)) == 0
+    pk.inverter = 2
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(pk)) == 0
     # a null workspace is rejected before any device call
     ctx = C.c_void_p()
     m = grmhd.grmhd_metric(1, 0.9375, 0.3)
