@@ -52,6 +52,25 @@ def test_torus128_weno5_full_step_as_benchmarked():
     assert s.status()[0] == fails
 
 
+def test_torus128_weno5_kastaun_full_step():
+    """The benchmark workload with the Kastaun et al. recovery in place of
+    1D_W: one device-side CFL step, every zone against the oracle."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    grid, P, _ = fm_torus(128, 128, 128, seed=1, gamma=gam)
+    s = gr.Grmhd(grid, gam, recon=RECON_WENO5, inverter=gr.INV_KASTAUN)
+    s.load(torch.from_numpy(P).cuda())
+    s.step_cfl()
+    dt = s.last_dt()
+    out = s.prims().cpu().numpy()
+    c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, nthreads=THREADS, inverter=oracle.INV_KASTAUN)
+    ref, fails, _ = oracle.run(c, P, dt, 1)
+    rel = rel_l1(out, ref)
+    print("128^3 WENO5 Kastaun rel L1", rel, "failures", fails)
+    assert rel.max() <= TOL, rel
+    assert s.status()[0] == fails
+
+
 def test_torus192_fp64_full_step():
     """The reduced-precision workload's grid in FP64 (the reference its error
     is stated against): 192^3, WENO5, one step."""

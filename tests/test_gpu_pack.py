@@ -37,8 +37,9 @@ def _unpack(flat, blocks):
     return out
 
 
-@pytest.mark.parametrize("recon", [RECON_MC, RECON_WENO5])
-def test_pack_matches_single_blocks_and_oracle(recon):
+@pytest.mark.parametrize("recon,inv", [(RECON_MC, 0), (RECON_WENO5, 0), (RECON_MC, 1)],
+                         ids=["mc", "weno5", "mc_kastaun"])
+def test_pack_matches_single_blocks_and_oracle(recon, inv):
     torch, gr = _setup()
     g, blocks, _ = torus_pack(nblocks=12, n_global=32, sizes=(8, 16), probs=(0.5, 0.5), seed=4)
     gam = 13 / 9
@@ -47,7 +48,8 @@ def test_pack_matches_single_blocks_and_oracle(recon):
     _, Pg, _ = fm_torus(32, 32, 32)
     single.load(torch.from_numpy(Pg).cuda())
     dt = single.dt()
-    pk = gr.Pack(g, [b["n"] for b in blocks], [b["offset"] for b in blocks], gam, recon=recon)
+    pk = gr.Pack(g, [b["n"] for b in blocks], [b["offset"] for b in blocks], gam, recon=recon,
+                 inverter=inv)
     pk.load(torch.from_numpy(_packed(blocks)).cuda())
     for _ in range(2):
         pk.step(dt)
@@ -55,13 +57,13 @@ def test_pack_matches_single_blocks_and_oracle(recon):
     num = np.zeros(8)
     den = np.zeros(8)
     for b, out in zip(blocks, res):
-        s = gr.Grmhd(b["grid"], gam, recon=recon)
+        s = gr.Grmhd(b["grid"], gam, recon=recon, inverter=inv)
         s.load(torch.from_numpy(b["prims"]).cuda())
         for _ in range(2):
             s.step(dt)
         alone = s.prims().cpu().numpy()
         assert np.array_equal(interior(out), interior(alone)), b["offset"]
-        c = oracle.cfg(b["grid"], gam=gam, recon=recon)
+        c = oracle.cfg(b["grid"], gam=gam, recon=recon, inverter=inv)
         ref, _, _ = oracle.run(c, b["prims"], dt, 2)
         # the pack is one workload: its relative L1 sums over all blocks
         A, B = interior(out), interior(ref)
