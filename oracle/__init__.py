@@ -40,9 +40,18 @@ class Cfg(C.Structure):
                 ("weno_eps", C.c_double), ("newton_tol", C.c_double),
                 ("newton_maxit", C.c_int), ("cfl", C.c_double),
                 ("nthreads", C.c_int), ("inverter", C.c_int),
-                ("kastaun_wmax", C.c_double)]
+                ("kastaun_wmax", C.c_double), ("floors", C.c_int),
+                ("rho_min_geom", C.c_double), ("u_min_geom", C.c_double),
+                ("bsq_over_rho_max", C.c_double), ("bsq_over_u_max", C.c_double),
+                ("u_over_rho_max", C.c_double), ("gamma_max", C.c_double),
+                ("fofc", C.c_int)]
 
 INV_1DW, INV_KASTAUN = 0, 1
+RECON_DONOR = 2
+FL_RHO, FL_U, FL_FLUID_FRAME, FL_GAMMA, FL_TEMP = 1, 2, 4, 8, 16
+# floor and ceiling defaults (HARM-family values; the paper states none)
+FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0,
+                      bsq_over_u_max=5000.0, u_over_rho_max=100.0, gamma_max=50.0)
 
 
 _lib = None
@@ -70,6 +79,9 @@ def _declare(lib):
     lib.orc_point_source.argtypes = [P, _D, C.c_double, C.c_double, _D]
     lib.orc_point_u_to_p.argtypes = [P, _D, _D, C.c_double, C.c_double, _D]
     lib.orc_point_u_to_p.restype = C.c_int
+    lib.orc_point_floors.argtypes = [P, _D, C.c_double, C.c_double]
+    lib.orc_point_floors.restype = C.c_int
+    lib.orc_last_stats.argtypes = [C.POINTER(C.c_longlong)]
     lib.orc_weno5.argtypes = [C.c_double] * 6
     lib.orc_weno5.restype = C.c_double
     lib.orc_mc_slope.argtypes = [C.c_double] * 3
@@ -96,7 +108,8 @@ def lib(counting=False):
 
 
 def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
-        newton_maxit=30, cfl=0.9, nthreads=None, inverter=INV_1DW, kastaun_wmax=1e3):
+        newton_maxit=30, cfl=0.9, nthreads=None, inverter=INV_1DW, kastaun_wmax=1e3,
+        floors=False, fofc=False, **floor_params):
     c = Cfg()
     c.n1, c.n2, c.n3 = grid.n1, grid.n2, grid.n3
     c.x1min, c.x1max = grid.x1min, grid.x1max
@@ -110,6 +123,14 @@ def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
     c.newton_tol, c.newton_maxit, c.cfl = newton_tol, newton_maxit, cfl
     c.nthreads = nthreads or os.cpu_count() or 1
     c.inverter, c.kastaun_wmax = int(inverter), float(kastaun_wmax)
+    c.floors, c.fofc = int(bool(floors)), int(bool(fofc))
+    fp = dict(FLOOR_DEFAULTS)
+    for k, v in floor_params.items():
+        if k not in fp:
+            raise TypeError(f"unknown floor parameter {k}")
+        fp[k] = v
+    for k, v in fp.items():
+        setattr(c, k, float(v))
     return c
 
 
@@ -128,6 +149,15 @@ def run(c, prims, dt, nsteps=1, counting=False, flags=False):
     if flags:
         return P, int(fails), dts, fl
     return P, int(fails), dts
+
+
+def last_stats(counting=False):
+    """Counters of the last run: failed inversions, zones the floors acted
+    on, zones the first-order flux correction marked, fluid-frame fallbacks
+    of the floors."""
+    out = (C.c_longlong * 4)()
+    lib(counting).orc_last_stats(out)
+    return dict(fails=out[0], floor_hits=out[1], fofc_zones=out[2], fluid_frame=out[3])
 
 
 def estimate_dt(c, prims):
@@ -209,6 +239,13 @@ def point_u_to_p(c, cons, guess, x1, x2):
     out = np.zeros(8)
     r = lib().orc_point_u_to_p(C.byref(c), _ptr(u), _ptr(g), x1, x2, _ptr(out))
     return out, r
+
+
+def point_floors(c, prims, x1, x2):
+    """Floors and ceilings of one zone's prims: (new prims, mask)."""
+    p = np.array(prims, dtype=np.float64)
+    m = lib().orc_point_floors(C.byref(c), _ptr(p), x1, x2)
+    return p, m
 
 
 def weno5(a, b, c_, d, e, eps=1e-26):

@@ -53,7 +53,7 @@ const int NV = 8, NG = 3;
 enum { RHO = 0, UU = 1, U1 = 2, U2 = 3, U3 = 4, B1 = 5, B2 = 6, B3 = 7 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_POLAR = 2, BC_FROZEN = 3 };
 enum { MINKOWSKI = 0, KERR_MKS = 1 };
-enum { RECON_MC = 0, RECON_WENO5 = 1 };
+enum { RECON_MC = 0, RECON_WENO5 = 1, RECON_DONOR = 2 };
 
 }  // namespace
 
@@ -73,6 +73,11 @@ typedef struct {
   int nthreads;
   int inverter;        // 0: 1D_W (Noble et al.), 1: Kastaun et al. bracketed recovery
   double kastaun_wmax; // Lorentz-factor cap of the Kastaun recovery
+  int floors;          // 1: density/energy floors and ceilings after every inversion
+  double rho_min_geom, u_min_geom;        // geometric floors rho r^-3/2, u r^-5/2
+  double bsq_over_rho_max, bsq_over_u_max; // magnetisation floors
+  double u_over_rho_max, gamma_max;       // temperature and Lorentz-factor ceilings
+  int fofc;            // 1: first-order flux correction of zones a stage would break
 } orc_cfg;
 }
 
@@ -427,13 +432,17 @@ void fill_ghosts(const Grid& g, std::vector<real>& P) {
 // ----------------------------------------------------------------- fluxes --
 
 // Left and right states at the lower face (along d) of zone (i, j, k).
-void reconstruct(const Grid& g, const std::vector<real>& P, int d, int i, int j, int k,
+// Donor cell: the two zones' own values.
+void reconstruct(const Grid& g, const std::vector<real>& P, int recon, int d, int i, int j, int k,
                  real qL[NV], real qR[NV]) {
   int di = d == 1, dj = d == 2, dk = d == 3;
   for (int v = 0; v < NV; v++) {
     real q[6];  // zones -3 .. +2 relative to (i, j, k) along d
     for (int s = -3; s <= 2; s++) q[s + 3] = Vc(P, g, v, i + s * di, j + s * dj, k + s * dk);
-    if (g.c.recon == RECON_MC) {
+    if (recon == RECON_DONOR) {
+      qL[v] = q[2];
+      qR[v] = q[3];
+    } else if (recon == RECON_MC) {
       qL[v] = q[2] + 0.5 * mc_slope(q[1], q[2], q[3]);
       qR[v] = q[3] - 0.5 * mc_slope(q[2], q[3], q[4]);
     } else {
@@ -446,13 +455,14 @@ void reconstruct(const Grid& g, const std::vector<real>& P, int d, int i, int j,
 // Local Lax-Friedrichs flux at the lower d-face of zone (i, j, k):
 // F = (F_L + F_R)/2 - c_max (U_R - U_L)/2, c_max = max(0, c+_L, c+_R, -c-_L, -c-_R).
 // Faces on the polar axis carry no flux (sqrt(-g) = 0 there).
-void face_flux(const Grid& g, const std::vector<real>& P, int d, int i, int j, int k, real F[NV]) {
+void face_flux(const Grid& g, const std::vector<real>& P, int recon, int d, int i, int j, int k,
+               real F[NV]) {
   if (g.pole_face(d, j)) {
     for (int v = 0; v < NV; v++) F[v] = 0.0;
     return;
   }
   real qL[NV], qR[NV];
-  reconstruct(g, P, d, i, j, k, qL, qR);
+  reconstruct(g, P, recon, d, i, j, k, qL, qR);
   const Geom& G = g.face_geom(d, i, j);
   FluidState SL, SR;
   fluid_state(qL, G, SL);
@@ -485,7 +495,7 @@ void compute_fluxes(const Grid& g, const std::vector<real>& P, std::vector<real>
       for (int j = lo[1]; j <= hi[1]; j++)
         for (int i = lo[0]; i <= hi[0]; i++) {
           real f[NV];
-          face_flux(g, P, d, i, j, k, f);
+          face_flux(g, P, g.c.recon, d, i, j, k, f);
           for (int v = 0; v < NV; v++) V(F[d - 1], g, v, i, j, k) = f[v];
         }
   }
@@ -819,6 +829,93 @@ int invert(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[N
   return c.inverter == 1 ? u_to_p_kastaun(c, G, U, guess, P) : u_to_p(c, G, U, guess, P);
 }
 
+// ---------------------------------------------------------------- floors --
+// Floors and ceilings (Physics section: when the density or internal energy
+// falls below set values, or too far below the magnetic pressure, material
+// and energy are injected, most commonly in the drift frame).  The paper
+// gives no values or formulas; the readings here:
+//   rho_fl = max(rho_min_geom r^-3/2, b^2/bsq_over_rho_max),
+//   u_fl   = max(u_min_geom r^-5/2,   b^2/bsq_over_u_max),
+// r = exp(x1) in modified KS and 1 in flat space.  A zone below either gets
+// drho = max(rho_fl - rho, 0), du = max(u_fl - u, 0) of new material that
+// moves with the drift velocity, the part of the fluid's normal-frame
+// velocity v perpendicular to B (v_D = v - (v.B) B/B.B, spatial metric; the
+// fluid velocity itself where B = 0): the new material's conserved variables
+// are added to the zone's and the sum is inverted with the floored prims as
+// the guess (the field is kept as it was).  If that inversion fails, the
+// floored prims themselves are kept (fluid-frame injection).  Then the
+// ceilings: a normal-frame Lorentz factor above gamma_max scales u~ down to
+// it, and u/rho above u_over_rho_max lowers u.  Returns a mask of what acted.
+enum { FL_RHO = 1, FL_U = 2, FL_FLUID_FRAME = 4, FL_GAMMA = 8, FL_TEMP = 16 };
+
+real spatial_dot(const Geom& G, const real a[3], const real b[3]) {
+  real s = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) s += G.gcov[i + 1][j + 1] * a[i] * b[j];
+  return s;
+}
+
+int apply_floors(const orc_cfg& c, const Geom& G, real x1, real P[NV]) {
+  const real r = c.metric == KERR_MKS ? exp(x1) : 1.0;
+  const real sr = sqrt(r);
+  FluidState S;
+  fluid_state(P, G, S);
+  real rho_fl = c.rho_min_geom / (r * sr);
+  real u_fl = c.u_min_geom / (r * r * sr);
+  real rb = S.bsq / c.bsq_over_rho_max, ub = S.bsq / c.bsq_over_u_max;
+  if (rb > rho_fl) rho_fl = rb;
+  if (ub > u_fl) u_fl = ub;
+  real drho = rho_fl - P[RHO], du = u_fl - P[UU];
+  if (drho < 0.0) drho = 0.0;
+  if (du < 0.0) du = 0.0;
+  int mask = 0;
+  if (drho > 0.0 || du > 0.0) {
+    mask |= (drho > 0.0 ? FL_RHO : 0) | (du > 0.0 ? FL_U : 0);
+    real ut[3] = {P[U1], P[U2], P[U3]}, B[3] = {P[B1], P[B2], P[B3]};
+    real gamma = sqrt(1.0 + spatial_dot(G, ut, ut));
+    real v[3], vd[3];
+    for (int i = 0; i < 3; i++) v[i] = ut[i] / gamma;
+    real BB = spatial_dot(G, B, B);
+    if (BB > 0.0) {
+      real vB = spatial_dot(G, v, B);
+      for (int i = 0; i < 3; i++) vd[i] = v[i] - vB * B[i] / BB;
+    } else {
+      for (int i = 0; i < 3; i++) vd[i] = v[i];
+    }
+    real gd = 1.0 / sqrt(1.0 - spatial_dot(G, vd, vd));
+    real Pd[NV] = {drho, du, gd * vd[0], gd * vd[1], gd * vd[2], 0.0, 0.0, 0.0};
+    real U[NV], dU[NV], guess[NV], Pn[NV];
+    FluidState Sd;
+    fluid_state(Pd, G, Sd);
+    prim_to_flux(P, S, G, c.gam, 0, U);
+    prim_to_flux(Pd, Sd, G, c.gam, 0, dU);
+    for (int v = 0; v < NV; v++) {
+      U[v] = U[v] + dU[v];
+      guess[v] = P[v];
+    }
+    guess[RHO] = P[RHO] + drho;
+    guess[UU] = P[UU] + du;
+    if (invert(c, G, U, guess, Pn) == 0) {
+      for (int v = 0; v < 5; v++) P[v] = Pn[v];
+    } else {
+      for (int v = 0; v < 5; v++) P[v] = guess[v];
+      mask |= FL_FLUID_FRAME;
+    }
+  }
+  real ut[3] = {P[U1], P[U2], P[U3]};
+  real gamma = sqrt(1.0 + spatial_dot(G, ut, ut));
+  if (gamma > c.gamma_max) {
+    real f = sqrt((c.gamma_max * c.gamma_max - 1.0) / (gamma * gamma - 1.0));
+    for (int i = 0; i < 3; i++) P[U1 + i] = ut[i] * f;
+    mask |= FL_GAMMA;
+  }
+  if (P[UU] > c.u_over_rho_max * P[RHO]) {
+    P[UU] = c.u_over_rho_max * P[RHO];
+    mask |= FL_TEMP;
+  }
+  return mask;
+}
+
 // ------------------------------------------------------------------ step --
 
 void cons_at(const Grid& g, const real P[NV], int i, int j, real U[NV]) {
@@ -840,53 +937,142 @@ void rhs(const Grid& g, const std::vector<real> F[3], const real P[NV], int i, i
   }
 }
 
+// Counters of the last orc_run: failed inversions, zones floors acted on,
+// zones whose fluxes the first-order correction replaced, floor injections
+// that fell back to the fluid frame.
+struct RunStats { long fails, floor_hits, fofc_zones, fluid_frame; };
+RunStats g_stats;
+
+// Update every interior zone of one stage from the Flux-CT fluxes F:
+// U = U(Pin) + dt L (stage 1; Un and U1v keep U(Pin) and U) or
+// U = (Un + U1v)/2 + dt L/2 (stage 2), then U_to_P with the stage input as the
+// guess, then floors (stage 1 stores the floored prims' U in U1v).  mark (if
+// not null) gets 1 where the inversion failed or floors acted; the counters
+// add only when count is set.
+void update_pass(const Grid& g, const std::vector<real>& Pin, const std::vector<real> F[3], int stage,
+                 real dt, std::vector<real>& Un, std::vector<real>& U1v, std::vector<real>& Pout,
+                 int* flags, std::vector<char>* mark, bool count) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  long fails = 0, hits = 0, fluid = 0;
+#pragma omp parallel for schedule(static) num_threads(g.c.nthreads) reduction(+ : fails, hits, fluid)
+  for (int k = 0; k < n3; k++)
+    for (int j = 0; j < n2; j++)
+      for (int i = 0; i < n1; i++) {
+        real p[NV], L[NV], Unew[NV], guess[NV], pn[NV];
+        for (int v = 0; v < NV; v++) p[v] = Vc(Pin, g, v, i, j, k);
+        rhs(g, F, p, i, j, k, L);
+        if (stage == 0) {
+          real u0[NV];
+          cons_at(g, p, i, j, u0);
+          for (int v = 0; v < NV; v++) {
+            Unew[v] = u0[v] + dt * L[v];
+            V(Un, g, v, i, j, k) = u0[v];
+            V(U1v, g, v, i, j, k) = Unew[v];
+          }
+        } else {
+          for (int v = 0; v < NV; v++)
+            Unew[v] = 0.5 * (Vc(Un, g, v, i, j, k) + Vc(U1v, g, v, i, j, k)) + 0.5 * (dt * L[v]);
+        }
+        for (int v = 0; v < NV; v++) guess[v] = p[v];
+        int f = invert(g.c, g.gC[g.id2(i, j)], Unew, guess, pn);
+        int fl = 0;
+        if (g.c.floors) {
+          fl = apply_floors(g.c, g.gC[g.id2(i, j)], g.xmin[0] + (i + 0.5) * g.dx[0], pn);
+          if (fl && stage == 0) {
+            real u1[NV];
+            cons_at(g, pn, i, j, u1);
+            for (int v = 0; v < NV; v++) V(U1v, g, v, i, j, k) = u1[v];
+          }
+        }
+        if (mark) (*mark)[g.id(i, j, k)] = (f || fl) ? 1 : 0;
+        if (count) {
+          fails += f;
+          hits += fl != 0;
+          fluid += (fl & FL_FLUID_FRAME) != 0;
+          if (flags && f) flags[g.id(i, j, k)] += 1 << stage;
+        }
+        for (int v = 0; v < NV; v++) V(Pout, g, v, i, j, k) = pn[v];
+      }
+  if (count) {
+    g_stats.fails += fails;
+    g_stats.floor_hits += hits;
+    g_stats.fluid_frame += fluid;
+  }
+}
+
+// Mark of the zone at padded index (i, j, k) for the flux correction:
+// interior zones their own; on a periodic axis a ghost index wraps to the
+// interior zone it copies; other ghosts are never marked.
+bool marked(const Grid& g, const std::vector<char>& mark, int i, int j, int k) {
+  int idx[3] = {i, j, k};
+  for (int a = 0; a < 3; a++) {
+    if (idx[a] >= 0 && idx[a] < g.n[a]) continue;
+    if (g.c.bc[2 * a] != BC_PERIODIC) return false;
+    idx[a] = ((idx[a] % g.n[a]) + g.n[a]) % g.n[a];
+  }
+  return mark[g.id(idx[0], idx[1], idx[2])] != 0;
+}
+
 // One SSPRK2 (Heun) step:
 //   U1 = Un + dt L(Pn);                  P1   = U_to_P(U1; guess Pn)
 //   Un+1 = (Un + U1)/2 + (dt L(P1))/2;   Pn+1 = U_to_P(Un+1; guess P1)
 // Ghosts are refilled from each stage's prims before it runs.
+//
+// First-order flux correction (Algorithm section, after Beckwith & Stone
+// 2011): each stage is first taken with the high-order fluxes; the zones
+// where it would fail the inversion or call on the floors are marked, every
+// face of a marked zone gets the local Lax-Friedrichs flux of donor-cell
+// states instead, Flux-CT is redone on the corrected fluxes and the stage is
+// taken again.  (Stages that mark nothing keep their first result.)
 long step(const Grid& g, std::vector<real>& P, real dt, int* flags) {
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
-  std::vector<real> F[3];
+  std::vector<real> F[3], Fct[3];
   for (int d = 0; d < 3; d++) F[d].assign(NV * g.nz, 0.0);
   std::vector<real> Un(NV * g.nz, 0.0), U1v(NV * g.nz, 0.0);
   std::vector<real> P1 = P;
-  long fails = 0;
+  std::vector<char> mark;
+  long fails0 = g_stats.fails;
 
   for (int stage = 0; stage < 2; stage++) {
     std::vector<real>& Pin = stage == 0 ? P : P1;
     fill_ghosts(g, Pin);
     compute_fluxes(g, Pin, F);
-    flux_ct(g, F);
     std::vector<real> Pout = Pin;
-#pragma omp parallel for schedule(static) num_threads(g.c.nthreads) reduction(+ : fails)
-    for (int k = 0; k < n3; k++)
-      for (int j = 0; j < n2; j++)
-        for (int i = 0; i < n1; i++) {
-          real p[NV], L[NV], Unew[NV], guess[NV], pn[NV];
-          for (int v = 0; v < NV; v++) p[v] = Vc(Pin, g, v, i, j, k);
-          rhs(g, F, p, i, j, k, L);
-          if (stage == 0) {
-            real u0[NV];
-            cons_at(g, p, i, j, u0);
-            for (int v = 0; v < NV; v++) {
-              Unew[v] = u0[v] + dt * L[v];
-              V(Un, g, v, i, j, k) = u0[v];
-              V(U1v, g, v, i, j, k) = Unew[v];
-            }
-          } else {
-            for (int v = 0; v < NV; v++)
-              Unew[v] = 0.5 * (Vc(Un, g, v, i, j, k) + Vc(U1v, g, v, i, j, k)) + 0.5 * (dt * L[v]);
-          }
-          for (int v = 0; v < NV; v++) guess[v] = p[v];
-          int f = invert(g.c, g.gC[g.id2(i, j)], Unew, guess, pn);
-          fails += f;
-          if (flags && f) flags[g.id(i, j, k)] += 1 << stage;
-          for (int v = 0; v < NV; v++) V(Pout, g, v, i, j, k) = pn[v];
+    if (!g.c.fofc) {
+      flux_ct(g, F);
+      update_pass(g, Pin, F, stage, dt, Un, U1v, Pout, flags, nullptr, true);
+    } else {
+      for (int d = 0; d < 3; d++) Fct[d] = F[d];
+      flux_ct(g, Fct);
+      mark.assign(g.nz, 0);
+      update_pass(g, Pin, Fct, stage, dt, Un, U1v, Pout, flags, &mark, false);
+      long nmark = 0;
+      for (long z = 0; z < g.nz; z++) nmark += mark[z];
+      if (nmark > 0) {
+        g_stats.fofc_zones += nmark;
+        // every face the flux pass computed whose either zone is marked
+        for (int d = 1; d <= 3; d++) {
+          int lo[3] = {-1, -1, -1}, hi[3] = {n1, n2, n3};
+          lo[d - 1] = 0;
+          int di = d == 1, dj = d == 2, dk = d == 3;
+          for (int k = lo[2]; k <= hi[2]; k++)
+            for (int j = lo[1]; j <= hi[1]; j++)
+              for (int i = lo[0]; i <= hi[0]; i++) {
+                if (!marked(g, mark, i, j, k) && !marked(g, mark, i - di, j - dj, k - dk)) continue;
+                real f[NV];
+                face_flux(g, Pin, RECON_DONOR, d, i, j, k, f);
+                for (int v = 0; v < NV; v++) V(F[d - 1], g, v, i, j, k) = f[v];
+              }
         }
+        flux_ct(g, F);
+        Pout = Pin;
+        update_pass(g, Pin, F, stage, dt, Un, U1v, Pout, flags, nullptr, true);
+      }
+    }
     if (stage == 0) P1 = Pout;
     else P = Pout;
   }
-  return fails;
+  return g_stats.fails - fails0;
 }
 
 // CFL time step: cfl / max over interior zones of sum_d max(|c+|, |c-|)/dx_d,
@@ -975,6 +1161,7 @@ extern "C" {
 // stage, 2: second stage).
 long orc_run(const orc_cfg* c, double* prims, double dt, int nsteps, double* dts, int* flags) {
   Grid g(*c);
+  g_stats = RunStats{0, 0, 0, 0};
   std::vector<real> P;
   load(g, prims, P);
   long fails = 0;
@@ -990,6 +1177,15 @@ long orc_run(const orc_cfg* c, double* prims, double dt, int nsteps, double* dts
   fill_ghosts(g, P);
   store(g, P, prims);
   return fails;
+}
+
+// Counters of the last orc_run: failed inversions, zones floors acted on,
+// zones the flux correction marked, fluid-frame fallbacks of the floors.
+void orc_last_stats(long long* out) {
+  out[0] = g_stats.fails;
+  out[1] = g_stats.floor_hits;
+  out[2] = g_stats.fofc_zones;
+  out[3] = g_stats.fluid_frame;
 }
 
 double orc_estimate_dt(const orc_cfg* c, double* prims) {
@@ -1139,6 +1335,18 @@ int orc_point_u_to_p(const orc_cfg* c, const double* cons, const double* guess, 
   return r;
 }
 
+// Floors and ceilings of one zone's prims at (x1, x2); returns the mask of
+// what acted (1 rho, 2 u, 4 fluid-frame fallback, 8 Lorentz factor, 16 u/rho).
+int orc_point_floors(const orc_cfg* c, double* prims, double x1, double x2) {
+  Geom G;
+  geom_point(*c, x1, x2, G);
+  real p[NV];
+  for (int v = 0; v < NV; v++) p[v] = prims[v];
+  int m = apply_floors(*c, G, x1, p);
+  for (int v = 0; v < NV; v++) prims[v] = (double)p[v];
+  return m;
+}
+
 double orc_weno5(double a, double b, double c, double d, double e, double eps) {
   return (double)weno5(a, b, c, d, e, eps);
 }
@@ -1173,7 +1381,7 @@ void orc_count_face(const orc_cfg* c, const double* prims, int d, int i, int j, 
   fill_ghosts(g, P);
   real f[NV];
   tally_reset();
-  face_flux(g, P, d, i, j, k, f);
+  face_flux(g, P, g.c.recon, d, i, j, k, f);
   tally_out(out);
 }
 

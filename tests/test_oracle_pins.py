@@ -606,3 +606,212 @@ def test_kastaun_step_matches_1dw_step():
     ak, fk, _ = oracle.run(ck, P, dt, 2)
     assert fk <= fw
     assert rel_l1(ak, aw).max() < 1e-11
+
+
+# ------------------------------------------- floors and first-order correction
+
+def _normal_frame_v(c, P, x1, x2):
+    """Normal-frame 3-velocity v = u~/gamma and the field B, with the spatial
+    metric, of one zone's prims."""
+    g = oracle.geom(c, x1, x2)[0][1:, 1:]
+    ut, B = P[2:5], P[5:8]
+    gamma = math.sqrt(1 + ut @ g @ ut)
+    return ut / gamma, B, g
+
+
+def test_floors_leave_states_above_them_untouched():
+    rng = np.random.default_rng(31)
+    for c in (flat_cfg(), kerr_cfg()):
+        c = oracle.cfg(GridSpec(4, 4, 4) if c.metric == 0 else torus_grid(8, 8, 1),
+                       gam=c.gam, floors=True)
+        x1, x2 = random_points(rng, 50, inside_horizon=False)
+        prims = _random_prims(rng, 50, kerr_cfg(), x1, x2)
+        for q in range(50):
+            P = prims[q].copy()
+            P[0] = max(P[0], 1e-3)
+            P[1] = min(max(P[1], 1e-4), 50 * P[0])
+            out, m = oracle.point_floors(c, P, x1[q], x2[q])
+            if m == 0:
+                assert np.array_equal(out, P)
+            else:
+                # only the magnetisation floor or a ceiling can act on these
+                assert m & (oracle.FL_RHO | oracle.FL_U | oracle.FL_GAMMA), m
+
+
+@pytest.mark.parametrize("metric", ["flat", "kerr"])
+def test_unmagnetised_floor_adds_comoving_material(metric):
+    """With B = 0 the drift frame is the fluid's own: the floored state is the
+    old one with rho and u raised to the floor values and u~ unchanged
+    (conserved variables are linear in rho and u at fixed velocity).  u is
+    held against rho, the energy scale the inversion fixes it to."""
+    rng = np.random.default_rng(32)
+    c = oracle.cfg(GridSpec(4, 4, 4) if metric == "flat" else torus_grid(8, 8, 1), gam=13 / 9,
+                   floors=True)
+    for q in range(40):
+        x1 = rng.uniform(math.log(2.0), math.log(50.0)) if metric == "kerr" else 0.3
+        x2 = rng.uniform(0.1, 0.9)
+        r = math.exp(x1) if metric == "kerr" else 1.0
+        rho_fl, u_fl = 1e-6 * r ** -1.5, 1e-8 * r ** -2.5
+        P = np.zeros(8)
+        P[0] = rho_fl * rng.uniform(0.01, 0.9)
+        P[1] = u_fl * rng.uniform(0.01, 0.9)
+        P[2:5] = rng.normal(size=3) * 0.3
+        out, m = oracle.point_floors(c, P, x1, x2)
+        assert m == oracle.FL_RHO | oracle.FL_U
+        assert abs(out[0] / rho_fl - 1) < 1e-11 and abs(out[1] - u_fl) < 1e-11 * rho_fl, out[:2]
+        assert np.abs(out[2:5] - P[2:5]).max() < 1e-11 * np.abs(P[2:5]).max()
+        assert np.array_equal(out[5:], P[5:])
+
+
+def test_drift_frame_injection_adds_the_drifting_material_flat():
+    """Flat space, closed forms: a magnetised zone below the b^2/rho floor
+    gains exactly the conserved variables of the missing material (drho,
+    du) moving with the E x B drift velocity V = E x B / B^2, E = -v x B:
+    rest mass drho gamma_V, momentum w gamma_V^2 V (none along B), energy
+    slot -(w gamma_V^2 - p) + drho gamma_V, field unchanged bit for bit.
+    (States whose summed conserved variables 1D_W cannot invert from the
+    floored guess fall back to the fluid frame and are skipped.)"""
+    rng = np.random.default_rng(33)
+    gam = 13 / 9
+    c = oracle.cfg(GridSpec(4, 4, 4), gam=gam, floors=True)
+    n = 0
+    for q in range(40):
+        B = rng.normal(size=3) * 10 ** rng.uniform(-2, 0)
+        P = np.zeros(8)
+        P[5:8] = B
+        P[2:5] = rng.normal(size=3) * 10 ** rng.uniform(-1, 0.7)
+        W = math.sqrt(1 + P[2:5] @ P[2:5])
+        v = P[2:5] / W
+        b2 = (B @ B + W * W * (v @ B) ** 2) / (W * W)      # b^mu b_mu
+        P[0] = b2 / 100 * rng.uniform(0.05, 0.8)
+        P[1] = P[0] * rng.uniform(0.01, 1)
+        out, m = oracle.point_floors(c, P, 0.3, 0.3)
+        assert m & oracle.FL_RHO, m
+        if m & (oracle.FL_GAMMA | oracle.FL_FLUID_FRAME):
+            continue
+        n += 1
+        drho = max(1e-6, b2 / 100) - P[0]
+        du = max(max(1e-8, b2 / 5000) - P[1], 0.0)
+        E = -np.cross(v, B)
+        V = np.cross(E, B) / (B @ B)
+        gV = 1 / math.sqrt(1 - V @ V)
+        w = drho + gam * du
+        expect = np.zeros(8)
+        expect[0] = drho * gV
+        expect[1] = -(w * gV * gV - (gam - 1) * du) + drho * gV
+        expect[2:5] = w * gV * gV * V
+        dU = oracle.point_flux(c, out, 0.3, 0.3, 0)[0] - oracle.point_flux(c, P, 0.3, 0.3, 0)[0]
+        scale = np.abs(oracle.point_flux(c, P, 0.3, 0.3, 0)[0][:5]).max()
+        assert np.abs(dU[:5] - expect[:5]).max() < 1e-10 * scale, (dU, expect)
+        assert np.array_equal(out[5:], P[5:])
+    assert n > 25
+
+
+def test_drift_frame_injection_carries_no_momentum_along_b_kerr():
+    """Kerr: the momentum the floor adds, sqrt(-g) T^t_i, has no component
+    along B^i (the injected material moves perpendicular to the field in
+    the normal frame); rest mass is added; the field is kept bit for bit."""
+    rng = np.random.default_rng(35)
+    c = oracle.cfg(torus_grid(8, 8, 1), gam=13 / 9, floors=True)
+    n = 0
+    for q in range(40):
+        x1 = rng.uniform(math.log(3.0), math.log(30.0))
+        x2 = rng.uniform(0.15, 0.85)
+        g = oracle.geom(c, x1, x2)[0][1:, 1:]
+        B = rng.normal(size=3)
+        B /= math.sqrt(B @ g @ B)
+        B *= 10 ** rng.uniform(-2, 0)
+        P = np.zeros(8)
+        P[5:8] = B
+        P[2:5] = rng.normal(size=3) * 10 ** rng.uniform(-1, 0.7) / np.sqrt(np.diag(g))
+        P[0] = (B @ g @ B) / 100 * rng.uniform(1e-4, 5e-3)   # b^2/rho well above 100
+        P[1] = P[0] * rng.uniform(0.01, 1)
+        out, m = oracle.point_floors(c, P, x1, x2)
+        assert m & oracle.FL_RHO, m
+        if m & (oracle.FL_GAMMA | oracle.FL_FLUID_FRAME):
+            continue
+        U0 = oracle.point_flux(c, P, x1, x2, 0)[0]
+        dU = oracle.point_flux(c, out, x1, x2, 0)[0] - U0
+        assert dU[0] > 0 and np.array_equal(out[5:], P[5:])
+        assert abs(dU[2:5] @ B) < 1e-10 * np.abs(U0[2:5]).max() * math.sqrt(B @ g @ B) * 10, (dU, B)
+        n += 1
+    assert n > 25
+
+
+def test_ceilings():
+    """Lorentz factor above gamma_max: u~ scaled along itself to exactly
+    gamma_max; u/rho above u_over_rho_max: u lowered to it."""
+    c = oracle.cfg(torus_grid(8, 8, 1), gam=13 / 9, floors=True)
+    rng = np.random.default_rng(34)
+    for q in range(20):
+        x1, x2 = rng.uniform(math.log(3.0), math.log(30.0)), rng.uniform(0.15, 0.85)
+        g = oracle.geom(c, x1, x2)[0][1:, 1:]
+        P = np.array([1.0, 0.5, 0, 0, 0, 0, 0, 0])
+        d = rng.normal(size=3)
+        d /= math.sqrt(d @ g @ d)
+        P[2:5] = d * 200.0                   # gamma ~ 200
+        out, m = oracle.point_floors(c, P, x1, x2)
+        assert m == oracle.FL_GAMMA
+        gam_new = math.sqrt(1 + out[2:5] @ g @ out[2:5])
+        assert abs(gam_new / 50.0 - 1) < 1e-14
+        assert np.allclose(out[2:5] / np.linalg.norm(out[2:5]), d / np.linalg.norm(d), rtol=0, atol=1e-15)
+        P = np.array([1.0, 500.0, 0.1, 0, 0, 0, 0, 0])
+        out, m = oracle.point_floors(c, P, x1, x2)
+        assert m == oracle.FL_TEMP and out[1] == 100.0 and np.array_equal(out[[0, 2, 3, 4]], P[[0, 2, 3, 4]])
+
+
+def test_donor_cell_converges_at_first_order():
+    """The first-order scheme the flux correction falls back on (donor-cell
+    states, local Lax-Friedrichs): L1 error slope near 1 on the fast mode."""
+    e = _mode_errors("fast", oracle.RECON_DONOR, (64, 128))
+    slope = np.log2(e[0] / e[1])
+    assert np.all((slope > 0.8) & (slope < 1.2)), slope
+
+
+def test_fofc_and_floors_do_nothing_on_smooth_flow():
+    """A smooth linear mode above every floor: the corrected and floored
+    step is the plain step bit for bit, and nothing is marked or floored."""
+    g, P, _, _ = linear_mode("fast", 24, ndim=2)
+    for recon in (RECON_MC, RECON_WENO5):
+        a, fa, _ = oracle.run(oracle.cfg(g, recon=recon), P, -1, 3)
+        b, fb, _ = oracle.run(oracle.cfg(g, recon=recon, floors=True, fofc=True), P, -1, 3)
+        st = oracle.last_stats()
+        assert np.array_equal(a, b)
+        assert st["fofc_zones"] == 0 and st["floor_hits"] == 0
+
+
+def test_fofc_marking_every_zone_is_the_first_order_scheme():
+    """An internal-energy floor (u >= 10) above the temperature ceiling
+    (u <= rho, rho floored at 1) acts on every zone at every stage, so every
+    zone is marked and every face takes the donor-cell flux: the corrected
+    step equals the donor-cell step (with the same floors) bit for bit."""
+    from workloads import magnetised_blast
+    grid, P = magnetised_blast(24)
+    hi = dict(rho_min_geom=1.0, u_min_geom=10.0, u_over_rho_max=1.0)
+    a, fa, _ = oracle.run(oracle.cfg(grid, recon=RECON_WENO5, floors=True, fofc=True, **hi), P, -1, 2)
+    st = oracle.last_stats()
+    assert st["fofc_zones"] == 2 * 2 * 24 * 24
+    b, fb, _ = oracle.run(oracle.cfg(grid, recon=oracle.RECON_DONOR, floors=True, **hi), P, -1, 2)
+    assert np.array_equal(a, b) and fa == fb
+
+
+def test_fofc_removes_failures_conserves_and_keeps_divb():
+    """The magnetised blast (48^2, MC, 4 steps): the plain step loses zones
+    to failed inversions; with the correction none fail, the totals of every
+    conserved variable on the periodic grid are kept to roundoff, and the
+    corner div B stays at roundoff."""
+    from workloads import magnetised_blast
+    grid, P = magnetised_blast(48)
+    c0 = oracle.cfg(grid, recon=RECON_MC)
+    _, f0, _ = oracle.run(c0, P, -1, 4)
+    assert f0 > 0
+    c = oracle.cfg(grid, recon=RECON_MC, fofc=True)
+    out, f1, _ = oracle.run(c, P, -1, 4)
+    st = oracle.last_stats()
+    assert f1 == 0 and st["fofc_zones"] > 0
+    U0 = interior(oracle.prims_to_cons(c, P)).sum(axis=(1, 2, 3))
+    U1 = interior(oracle.prims_to_cons(c, out)).sum(axis=(1, 2, 3))
+    scale = np.abs(interior(oracle.prims_to_cons(c, P))).sum(axis=(1, 2, 3))
+    assert np.all(np.abs(U1 - U0) <= 1e-13 * np.maximum(scale, scale.max() * 1e-3)), (U1 - U0) / scale
+    mx, _ = oracle.divb(c, out)
+    assert mx < 1e-13 * 0.07 / grid.dx[0]

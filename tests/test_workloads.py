@@ -105,3 +105,19 @@ def test_michel_solution_constants_and_sonic_point():
     assert cs2c == pytest.approx(urc ** 2 / (1.0 - 3.0 * urc ** 2), rel=1e-8)
     c2 = michel_constants(rc=rc, gamma=gam, rho_c=2.0)
     assert c2["K"] * 2.0 ** (gam - 1.0) == pytest.approx(c["K"], rel=1e-14)
+
+
+def test_magnetised_blast_set_up():
+    from workloads import magnetised_blast, interior
+    grid, P = magnetised_blast(48)
+    I = interior(P)
+    assert P.shape == (8, 7, 54, 54)
+    rho, u = I[0], I[1]
+    assert rho.max() == pytest.approx(1e-2) and rho.min() == pytest.approx(1e-4)
+    p = u / 3.0                                        # gamma = 4/3
+    assert p.max() == pytest.approx(1.0) and p.min() == pytest.approx(3e-5)
+    assert np.all(I[2:5] == 0) and np.all(I[5] == 0.07) and np.all(I[6:] == 0)
+    # b^2/rho = 49 in the ambient gas, at rest
+    assert (0.07 ** 2 / rho.min()) == pytest.approx(49.0)
+    # symmetric under x -> -x and y -> -y
+    assert np.array_equal(I[0], I[0][:, ::-1, :]) and np.array_equal(I[0], I[0][:, :, ::-1])
