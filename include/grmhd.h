@@ -43,7 +43,7 @@ extern "C" {
 enum { GRMHD_OK = 0, GRMHD_E_ARG = -1, GRMHD_E_HIP = -2, GRMHD_E_STATE = -3,
        GRMHD_E_NOMEM = -4 };
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KERR_MKS = 1 };
-enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1 };
+enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_DONOR = 2 };
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2,
@@ -73,9 +73,11 @@ typedef struct {
   double weno_eps;    /* WENO5 smoothness regulariser */
   double newton_tol;  /* relative |dW/W| stopping tolerance of 1D_W */
   int newton_maxit;   /* Newton iteration cap (one more step follows convergence) */
-  int recon;          /* GRMHD_RECON_* */
+  int recon;          /* GRMHD_RECON_*: MC, WENO5, or DONOR (first order: each
+                         face's states are its two zones' own values) */
   int precision;      /* GRMHD_PREC_*: MIXED = FP32 reconstruction, fluxes, EMFs */
-  int floors;         /* must be 0 (no floors on this path) */
+  int floors;         /* 1: floors and ceilings after every inversion (fields
+                         below); 0: none */
   int inverter;       /* GRMHD_INV_*: 1D_W Newton from the stage-input prims,
                          or the Kastaun et al. root bracket in mu = 1/(h W),
                          which needs no guess (Illinois iteration stopped at
@@ -83,6 +85,26 @@ typedef struct {
                          iterations); both leave a failed zone at its guess */
   double kastaun_wmax; /* Lorentz-factor cap of the Kastaun recovery (> 1);
                           ignored by 1D_W */
+  /* Floors (Physics section: material and energy injected where density or
+   * internal energy fall below set values or too far below the magnetic
+   * pressure, in the drift frame).  After each stage's inversion:
+   *   rho_fl = max(rho_min_geom r^-3/2, b^2/bsq_over_rho_max),
+   *   u_fl   = max(u_min_geom r^-5/2,   b^2/bsq_over_u_max)
+   * (r = exp(x1) in modified KS, 1 in flat space); the missing material
+   * moves with the E x B drift velocity, is added as conserved variables
+   * and the sum re-inverted (fluid-frame fallback if that fails); then the
+   * Lorentz factor is capped at gamma_max and u/rho at u_over_rho_max.  All
+   * must be > 0 (gamma_max > 1) when floors = 1. */
+  double rho_min_geom, u_min_geom, bsq_over_rho_max, bsq_over_u_max;
+  double u_over_rho_max, gamma_max;
+  int fofc;           /* 1: first-order flux correction (Algorithm section,
+                         after Beckwith & Stone 2011): each stage is first
+                         taken with the high-order fluxes; zones whose
+                         inversion fails or that floors act on are marked,
+                         every face of a marked zone gets the LLF flux of
+                         donor-cell states, Flux-CT and the update are
+                         redone (only when some zone was marked).  Single
+                         grids only (packs and the VJP reject it). */
 } grmhd_params;
 
 /* Bytes of device workspace a context with this grid and parameters needs. */
@@ -129,8 +151,13 @@ int grmhd_get_prims(grmhd_ctx* ctx, double* d_out);
 int grmhd_divb(grmhd_ctx* ctx, double* d_divb_or_null, double* max_out, double* mean_out);
 
 /* Inversion failures accumulated since creation (or the last reset), and
- * floor activations (always 0).  Synchronises. */
+ * zones the floors acted on (per stage).  Synchronises. */
 int grmhd_get_status(grmhd_ctx* ctx, long long* n_inv_fail, long long* n_floor);
+/* All counters since creation (or the last reset), out[0..3]: inversion
+ * failures, zones floors acted on, zones the first-order flux correction
+ * marked, floor injections that fell back to the fluid frame (all counted
+ * per stage).  Synchronises. */
+int grmhd_get_counters(grmhd_ctx* ctx, long long* out4);
 int grmhd_reset_status(grmhd_ctx* ctx);
 
 /* Conserved variables at interior zone centres of d_prims into d_cons (both
@@ -147,7 +174,9 @@ int grmhd_cons_to_prims(grmhd_ctx* ctx, const double* d_cons, const double* d_gu
  * with Flux-CT applied to the B components of interior faces.  d_flux is
  * [3][8][padded] float64 (device); entries at positions other than interior
  * faces (x1 faces i in [0, n1], j < n2, k < n3, and likewise) are
- * unspecified.  For testing and inspection. */
+ * unspecified.  The context's reconstruction is used; the first-order flux
+ * correction is not applied (it depends on a provisional update).  For
+ * testing and inspection. */
 int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
 
 /* Adjoint of one step (vector-Jacobian product), FP64 only.
@@ -162,7 +191,9 @@ int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
  * max() branches by the branch taken.  Scratch comes from d_vjp_ws (device,
  * 256-byte aligned, >= grmhd_vjp_workspace_bytes()).  Neither the context's
  * state nor its failure count changes.  Synchronises.  E_STATE for the mixed
- * precision path. */
+ * precision path, floors, the first-order flux correction or donor-cell
+ * reconstruction (the adjoint covers the plain high-order step; the
+ * workspace size is then 0). */
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params);
 int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const double* d_gprims_out,
                    double* d_gprims_in, double* g_gamma, void* d_vjp_ws, size_t vjp_ws_bytes);
@@ -177,7 +208,9 @@ int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const do
  * block order (device).  Tile shapes per block size (t1*t2*t3 <= 256, or
  * (0, 0, 0): runs of 256 consecutive positions of each box in x1-fastest
  * order, the default) only change speed.  Errors as for single contexts; E_ARG for blocks outside the
- * global grid or a non-FP64 precision. */
+ * global grid, a non-FP64 precision, floors, the first-order flux
+ * correction or donor-cell reconstruction (packs advance the plain
+ * high-order step). */
 typedef struct grmhd_pack grmhd_pack;
 size_t grmhd_pack_workspace_bytes(int nblocks, const int* n);
 int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* offsets_ijk,

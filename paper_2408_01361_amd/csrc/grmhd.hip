@@ -57,6 +57,8 @@ struct Dev {
   int maxit;
   int inverter;       // GRMHD_INV_*
   double vmax2;       // 1 - 1/W_max^2, the Kastaun recovery's speed cap
+  int floors;         // floors and ceilings after every inversion of a stage
+  double rho_min_geom, u_min_geom, bsq_over_rho_max, bsq_over_u_max, u_over_rho_max, gamma_max;
   SpaceTime st;
 };
 
@@ -277,7 +279,10 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ P, long nz
 #pragma unroll
   for (int v = 0; v < NVAR; v++) {
     const double* q = P + v * nz + c;
-    if (RECON == GRMHD_RECON_MC) {
+    if (RECON == GRMHD_RECON_DONOR) {
+      qL[v] = (R)q[-s];
+      qR[v] = (R)q[0];
+    } else if (RECON == GRMHD_RECON_MC) {
       R m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s];
       qL[v] = mc_left(m2, m1, p0);
       qR[v] = mc_right(m1, p0, p1);
@@ -392,14 +397,68 @@ __device__ __forceinline__ void emf_edge(const Dev& g, const FT* __restrict__ F1
   E3[c] = pole ? (FT)0 : e3;
 }
 
+// With gate, runs only when *gate is non-zero (the flux correction's second
+// EMF pass); with zero, its first workgroup clears *zero (the mark count of
+// the stage about to be taken).
 template <typename FT>
 __global__ void __launch_bounds__(BLOCK) k_emf(Dev g, Sched box, const FT* __restrict__ F1,
                                                const FT* __restrict__ F2, const FT* __restrict__ F3,
                                                FT* __restrict__ E1, FT* __restrict__ E2,
-                                               FT* __restrict__ E3) {
+                                               FT* __restrict__ E3, const unsigned long long* gate,
+                                               unsigned long long* zero) {
+  if (gate && *gate == 0) return;
+  if (zero && blockIdx.x == 0 && threadIdx.x == 0) *zero = 0;
   int i, j, k;
   if (!sched_index(box, blockIdx.x, gridDim.x, i, j, k)) return;
   emf_edge<FT>(g, F1, F2, F3, E1, E2, E3, i, j, k);
+}
+
+// Mark of the zone at (i, j, k) for the flux correction: interior zones
+// their own; a ghost index on a periodic axis wraps to the zone it copies;
+// other ghosts are never marked.
+__device__ __forceinline__ bool marked(const Dev& g, const unsigned char* __restrict__ mark, int i, int j,
+                                       int k) {
+  int idx[3] = {i, j, k};
+  const int n[3] = {g.n1, g.n2, g.n3};
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    if (idx[a] >= 0 && idx[a] < n[a]) continue;
+    if (g.bc[2 * a] != GRMHD_BC_PERIODIC) return false;
+    idx[a] = ((idx[a] % n[a]) + n[a]) % n[a];
+  }
+  return mark[zid(g, idx[0], idx[1], idx[2])] != 0;
+}
+
+// First-order flux correction: every face of the flux boxes (the same faces
+// the flux launch computes) whose either zone is marked gets the local
+// Lax-Friedrichs flux of donor-cell states.  Runs only when *gate (the mark
+// count) is non-zero; one thread per face, faces of unmarked zones return
+// after two byte loads.
+template <typename R, typename FT>
+__global__ void __launch_bounds__(BLOCK) k_fofc_flux(Dev g, Box b1, Box b2, Box b3, const double* __restrict__ P,
+                                                     const double* __restrict__ tabF1,
+                                                     const double* __restrict__ tabF2,
+                                                     const double* __restrict__ tabC, FT* __restrict__ F1,
+                                                     FT* __restrict__ F2, FT* __restrict__ F3,
+                                                     const unsigned char* __restrict__ mark,
+                                                     const unsigned long long* gate) {
+  if (*gate == 0) return;
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long c1 = b1.count(), c2 = b2.count();
+  int i, j, k;
+  if (t < c1) {
+    box_index(b1, t, i, j, k);
+    if (marked(g, mark, i, j, k) || marked(g, mark, i - 1, j, k))
+      flux_face<1, GRMHD_RECON_DONOR, R, FT>(g, P, tabF1, F1, i, j, k);
+  } else if (t < c1 + c2) {
+    box_index(b2, t - c1, i, j, k);
+    if (marked(g, mark, i, j, k) || marked(g, mark, i, j - 1, k))
+      flux_face<2, GRMHD_RECON_DONOR, R, FT>(g, P, tabF2, F2, i, j, k);
+  } else {
+    if (!box_index(b3, t - c1 - c2, i, j, k)) return;
+    if (marked(g, mark, i, j, k) || marked(g, mark, i, j, k - 1))
+      flux_face<3, GRMHD_RECON_DONOR, R, FT>(g, P, tabC, F3, i, j, k);
+  }
 }
 
 // Rebuild the B components of interior-face fluxes from the EMFs (as the
@@ -678,6 +737,105 @@ __device__ __forceinline__ int invert(const Dev& g, const PointMetric<double>& m
   return invert_1dw(g, m, U, guess, P);
 }
 
+// ---------------------------------------------------------------- floors --
+
+// Floors and ceilings of one zone's prims (the Physics section's injection
+// of material and energy where density or internal energy drop below set
+// values or too far below the magnetic pressure, in the drift frame):
+//   rho_fl = max(rho_min_geom r^-3/2, b^2/bsq_over_rho_max),
+//   u_fl   = max(u_min_geom r^-5/2,   b^2/bsq_over_u_max),
+// r = exp(x1) in modified KS, 1 in flat space.  drho = max(rho_fl - rho, 0)
+// and du = max(u_fl - u, 0) of new material moving with the drift velocity
+// v_D = v - (v.B) B/B.B (normal-frame velocity v, spatial metric; v itself
+// where B = 0) are added as conserved variables and the sum is inverted
+// from the floored prims (B kept as it was); if that fails the floored prims
+// stay (fluid-frame injection).  Then a Lorentz factor above gamma_max
+// scales u~ down to it and u/rho above u_over_rho_max lowers u.  Returns
+// the mask of what acted.  Same operation order as the CPU reference,
+// without contraction.
+enum { FL_RHO = 1, FL_U = 2, FL_FLUID_FRAME = 4, FL_GAMMA = 8, FL_TEMP = 16 };
+
+__device__ __forceinline__ double spatial_dot(const PointMetric<double>& m, const double a[3],
+                                              const double b[3]) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) s += m.gcov[sidx(i + 1, j + 1)] * a[i] * b[j];
+  return s;
+}
+
+__device__ __noinline__ int apply_floors(const Dev& g, const PointMetric<double>& m, double x1,
+                                         double P[NVAR]) {
+#pragma clang fp contract(off)
+  const double r = g.st.kerr ? exp(x1) : 1.0;
+  const double sr = sqrt(r);
+  Fluid<double> f;
+  fluid_state(P, m, f);
+  double rho_fl = g.rho_min_geom / (r * sr);
+  double u_fl = g.u_min_geom / (r * r * sr);
+  const double rb = f.bsq / g.bsq_over_rho_max, ub = f.bsq / g.bsq_over_u_max;
+  if (rb > rho_fl) rho_fl = rb;
+  if (ub > u_fl) u_fl = ub;
+  double drho = rho_fl - P[RHO], du = u_fl - P[UU];
+  if (drho < 0.0) drho = 0.0;
+  if (du < 0.0) du = 0.0;
+  int mask = 0;
+  if (drho > 0.0 || du > 0.0) {
+    mask |= (drho > 0.0 ? FL_RHO : 0) | (du > 0.0 ? FL_U : 0);
+    const double ut[3] = {P[U1], P[U2], P[U3]}, B[3] = {P[B1], P[B2], P[B3]};
+    const double gamma = sqrt(1.0 + spatial_dot(m, ut, ut));
+    double v[3], vd[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) v[i] = ut[i] / gamma;
+    const double BB = spatial_dot(m, B, B);
+    if (BB > 0.0) {
+      const double vB = spatial_dot(m, v, B);
+#pragma unroll
+      for (int i = 0; i < 3; i++) vd[i] = v[i] - vB * B[i] / BB;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; i++) vd[i] = v[i];
+    }
+    const double gd = 1.0 / sqrt(1.0 - spatial_dot(m, vd, vd));
+    double Pd[NVAR] = {drho, du, gd * vd[0], gd * vd[1], gd * vd[2], 0.0, 0.0, 0.0};
+    double U[NVAR], dU[NVAR], guess[NVAR], Pn[NVAR];
+    prim_to_flux(P, f, m, g.gam, 0, U);
+    Fluid<double> fd;
+    fluid_state(Pd, m, fd);
+    prim_to_flux(Pd, fd, m, g.gam, 0, dU);
+#pragma unroll
+    for (int v2 = 0; v2 < NVAR; v2++) {
+      U[v2] = U[v2] + dU[v2];
+      guess[v2] = P[v2];
+    }
+    guess[RHO] = P[RHO] + drho;
+    guess[UU] = P[UU] + du;
+    if (invert(g, m, U, guess, Pn) == 0) {
+#pragma unroll
+      for (int v2 = 0; v2 < 5; v2++) P[v2] = Pn[v2];
+    } else {
+#pragma unroll
+      for (int v2 = 0; v2 < 5; v2++) P[v2] = guess[v2];
+      mask |= FL_FLUID_FRAME;
+    }
+  }
+  const double ut[3] = {P[U1], P[U2], P[U3]};
+  const double gamma = sqrt(1.0 + spatial_dot(m, ut, ut));
+  if (gamma > g.gamma_max) {
+    const double fs = sqrt((g.gamma_max * g.gamma_max - 1.0) / (gamma * gamma - 1.0));
+#pragma unroll
+    for (int i = 0; i < 3; i++) P[U1 + i] = ut[i] * fs;
+    mask |= FL_GAMMA;
+  }
+  if (P[UU] > g.u_over_rho_max * P[RHO]) {
+    P[UU] = g.u_over_rho_max * P[RHO];
+    mask |= FL_TEMP;
+  }
+  return mask;
+}
+
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
@@ -767,7 +925,15 @@ __device__ __forceinline__ void geometric_source(const double p[NVAR], const Flu
 // One stage for every interior zone.  STAGE 1: V = (Un + U1)/2 with
 // Un = U(Pin), U1 = Un + dt L(Pin); STAGE 2: U = V + dt L(Pin)/2.  Then
 // Pout = U_to_P(U; guess Pin).  B fluxes come from the edge EMFs.
-template <int STAGE, typename FT, bool RATE = false>
+// Update modes: PLAIN (no floors), FLOORS (floors when g.floors), and the
+// two passes of a stage under the first-order flux correction: PROVISIONAL
+// (marks zones whose inversion fails or that floors act on, counts nothing
+// else) and FINAL (the same update from the corrected fluxes, counted).
+enum { U_PLAIN = 0, U_FLOORS = 1, U_PROVISIONAL = 2, U_FINAL = 3 };
+// Counter slots of the context's counter array.
+enum { C_FAILS = 0, C_C2P = 1, C_FLOORS = 2, C_FOFC = 3, C_FLUID = 4, C_MARKS = 5 };
+
+template <int STAGE, typename FT, bool RATE = false, int MODE = U_PLAIN>
 __device__ __forceinline__ void update_zone(const Dev& g, const double* __restrict__ Pin,
                                             double* __restrict__ Pout, double* __restrict__ V,
                                             const FT* __restrict__ F1, const FT* __restrict__ F2,
@@ -776,7 +942,8 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
                                             const double* __restrict__ tabC,
                                             const double* __restrict__ conn, double dt,
                                             unsigned long long* fails, unsigned char* __restrict__ flags,
-                                            int i, int j, int k, double* rate = nullptr) {
+                                            int i, int j, int k, double* rate = nullptr,
+                                            unsigned char* __restrict__ mark = nullptr) {
   // the FP64 update is rounded operation by operation, in the order written
 #pragma clang fp contract(off)
   const long c = zid(g, i, j, k), nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
@@ -830,37 +997,73 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
   }
   double out[NVAR];
   int bad = invert(g, m, U, p, out);
+  int fl = 0;
+  if (MODE != U_PLAIN && g.floors) {
+    fl = apply_floors(g, m, g.x1min + (i + 0.5) * g.dx1, out);
+    if (STAGE == 1 && fl) {
+      // the stage register holds the floored state's conserved variables
+      double U0[NVAR], U1[NVAR];
+      Fluid<double> f0, f1;
+      fluid_state(p, m, f0);
+      prim_to_flux(p, f0, m, g.gam, 0, U0);
+      fluid_state(out, m, f1);
+      prim_to_flux(out, f1, m, g.gam, 0, U1);
+#pragma unroll
+      for (int v = 0; v < NVAR; v++) V[v * nz + c] = 0.5 * (U0[v] + U1[v]);
+    }
+  }
 #pragma unroll
   for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
   if (flags) flags[c] = (unsigned char)bad;
-  if (bad) atomicAdd(fails, 1ull);
+  if (MODE == U_PROVISIONAL) {
+    const bool mk = bad || fl;
+    mark[c] = (unsigned char)mk;
+    if (mk) atomicAdd(&fails[C_MARKS], 1ull);
+  } else {
+    if (bad) atomicAdd(&fails[C_FAILS], 1ull);
+    if (fl) {
+      atomicAdd(&fails[C_FLOORS], 1ull);
+      if (fl & FL_FLUID_FRAME) atomicAdd(&fails[C_FLUID], 1ull);
+    }
+  }
   if (RATE) *rate = zone_rate(g, out, m);
 }
 
 // One stage over the interior.  With RATE (stage 2) every workgroup also
 // writes the maximum CFL rate of the prims it produced to rate_partial[], so
 // the next step's dt needs only the final pass over the partials.
-template <int STAGE, typename FT, bool RATE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8)))
+// fails is the context's counter array (C_* slots).  The FINAL pass of the
+// flux correction runs only when the PROVISIONAL pass marked a zone (a
+// grid-uniform test of the mark count), and then adds that count to the
+// correction's running total.
+template <int STAGE, typename FT, bool RATE, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(MODE == U_PLAIN ? UPDATE_WAVES : 2, 8)))
 k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ Pout,
          double* __restrict__ V, const FT* __restrict__ F1, const FT* __restrict__ F2,
          const FT* __restrict__ F3, const FT* __restrict__ E1, const FT* __restrict__ E2,
          const FT* __restrict__ E3, const double* __restrict__ tabC, const double* __restrict__ conn,
          double dt, const double* __restrict__ dt_dev, unsigned long long* fails,
-         unsigned char* __restrict__ flags, double* __restrict__ rate_partial) {
+         unsigned char* __restrict__ flags, double* __restrict__ rate_partial,
+         unsigned char* __restrict__ mark) {
+  if (MODE == U_FINAL) {
+    const unsigned long long nmark = fails[C_MARKS];
+    if (nmark == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&fails[C_FOFC], nmark);
+  }
   int i, j, k;
   const bool in = sched_index(box, blockIdx.x, gridDim.x, i, j, k);
   if (dt_dev) dt = *dt_dev;
   if (!RATE) {
     if (in)
-      update_zone<STAGE, FT>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i, j,
-                             k);
+      update_zone<STAGE, FT, false, MODE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
+                                          flags, i, j, k, nullptr, mark);
     return;
   }
   double r = 0.0, sm = 0.0;
   if (in)
-    update_zone<STAGE, FT, true>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails, flags, i,
-                                 j, k, &r);
+    update_zone<STAGE, FT, true, MODE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
+                                       flags, i, j, k, &r, mark);
   block_reduce(r, sm);
   if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
 }
@@ -1013,7 +1216,8 @@ struct grmhd_ctx {
   void *F[3], *E[3];
   double *tabC, *tabF1, *tabF2, *corner, *conn;
   double *pmax, *psum, *result;
-  unsigned long long* fails;
+  unsigned long long* fails;  // counters, slots C_* (failures, floors, flux-correction marks, ...)
+  unsigned char* mark;        // per zone: marked by the flux correction's provisional pass
   double* pdt;              // CFL-rate partials left by the last stage-2 update
   bool rate_ready = false;  // pdt describes the current state (rate_n partials)
   bool ghosts_valid = false;  // the ghost zones of P hold the boundary conditions of its interior
@@ -1056,9 +1260,13 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
       return false;
   }
   if (!(g->x1max > g->x1min && g->x2max > g->x2min && g->x3max > g->x3min)) return false;
-  if (p->recon != GRMHD_RECON_MC && p->recon != GRMHD_RECON_WENO5) return false;
+  if (p->recon != GRMHD_RECON_MC && p->recon != GRMHD_RECON_WENO5 && p->recon != GRMHD_RECON_DONOR)
+    return false;
   if (p->precision != GRMHD_PREC_FP64 && p->precision != GRMHD_PREC_MIXED) return false;
-  if (p->floors != 0 || !(p->gamma_ad > 1.0) || p->newton_maxit < 1 || !(p->newton_tol > 0.0))
+  if (!(p->gamma_ad > 1.0) || p->newton_maxit < 1 || !(p->newton_tol > 0.0)) return false;
+  if ((p->floors != 0 && p->floors != 1) || (p->fofc != 0 && p->fofc != 1)) return false;
+  if (p->floors && !(p->rho_min_geom > 0.0 && p->u_min_geom > 0.0 && p->bsq_over_rho_max > 0.0 &&
+                     p->bsq_over_u_max > 0.0 && p->u_over_rho_max > 0.0 && p->gamma_max > 1.0))
     return false;
   if (p->inverter != GRMHD_INV_1DW && p->inverter != GRMHD_INV_KASTAUN) return false;
   if (p->inverter == GRMHD_INV_KASTAUN && !(p->kastaun_wmax > 1.0)) return false;
@@ -1085,7 +1293,9 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
   double* result = cv.take<double>(base, 8);
   double* pdt = cv.take<double>(base, MAX_PARTIALS);
   unsigned long long* fails = cv.take<unsigned long long>(base, 8);
+  unsigned char* mark = cv.take<unsigned char>(base, nz);
   if (c) {
+    c->mark = mark;
     c->P = P; c->P1 = P1; c->V = V;
     for (int d = 0; d < 3; d++) { c->F[d] = F[d]; c->E[d] = E[d]; }
     c->tabC = tabC; c->tabF1 = tabF1; c->tabF2 = tabF2; c->corner = corner; c->conn = conn;
@@ -1096,7 +1306,7 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
 
 int hip_check() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
 
-enum { T_BC = 0, T_FLUX, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_NCLASS };
+enum { T_BC = 0, T_FLUX, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_FOFC, T_NCLASS };
 
 // Start/stop events of one launch of class cls while timing is enabled (null
 // events otherwise, or when no more events can be created).
@@ -1153,7 +1363,7 @@ inline unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
 
 // Flux and EMF kernels of one stage, reading the (ghost-filled) prims P.
 template <typename R, typename FT>
-int stage_fluxes(grmhd_ctx* c, const double* P) {
+int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullptr) {
   const Dev& g = c->dev;
   FT* F1 = (FT*)c->F[0];
   FT* F2 = (FT*)c->F[1];
@@ -1167,18 +1377,21 @@ int stage_fluxes(grmhd_ctx* c, const double* P) {
   if (c->params.recon == GRMHD_RECON_MC)
     rc = launch(c, T_FLUX, k_flux_all<GRMHD_RECON_MC, R, FT>, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3,
                 Pc, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3);
+  else if (c->params.recon == GRMHD_RECON_DONOR)
+    rc = launch(c, T_FLUX, k_flux_all<GRMHD_RECON_DONOR, R, FT>, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3,
+                Pc, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3);
   else
     rc = launch(c, T_FLUX, k_flux_all<GRMHD_RECON_WENO5, R, FT>, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3,
                 Pc, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3);
   if (rc) return rc;
   Sched be = make_sched(make_box(0, g.n1, 0, g.n2, 0, g.n3), c->kg_flux);
   return launch(c, T_EMF, k_emf<FT>, blocks_for(be), g, be, (const FT*)F1, (const FT*)F2, (const FT*)F3,
-                (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2]);
+                (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2], (const unsigned long long*)nullptr, zero);
 }
 
 // One stage's update.  With rate (stage 2 of a step) the workgroups also
 // leave the CFL-rate partials of the prims they write in c->pdt.
-template <int STAGE, typename FT>
+template <int STAGE, typename FT, int MODE = U_PLAIN>
 int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
                  unsigned long long* fails = nullptr, unsigned char* flags = nullptr,
                  const double* dt_dev = nullptr, bool rate = false) {
@@ -1188,15 +1401,51 @@ int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
   const unsigned nb = blocks_for(bz);
   if constexpr (STAGE == 2) {
     if (rate && nb <= (unsigned)MAX_PARTIALS)
-      return launch(c, cls, k_update<STAGE, FT, true>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
+      return launch(c, cls, k_update<STAGE, FT, true, MODE>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
                     (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1],
                     (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn, dt, dt_dev,
-                    fails ? fails : c->fails, flags, c->pdt);
+                    fails ? fails : c->fails, flags, c->pdt, c->mark);
   }
-  return launch(c, cls, k_update<STAGE, FT, false>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
+  return launch(c, cls, k_update<STAGE, FT, false, MODE>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
                 (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1],
                 (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn, dt, dt_dev,
-                fails ? fails : c->fails, flags, (double*)nullptr);
+                fails ? fails : c->fails, flags, (double*)nullptr, c->mark);
+}
+
+// One RK2 stage from the ghost-filled prims Pin: fluxes, EMFs, update (with
+// floors when enabled).  Under the first-order flux correction: the
+// provisional update marks zones, the marked zones' faces get donor-cell
+// fluxes, and the EMF and update passes run again; these three launches
+// exit at once when nothing was marked.
+template <int STAGE, typename R, typename FT>
+int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double* dt_dev, bool rate) {
+  int rc;
+  if (!c->params.fofc) {
+    if ((rc = stage_fluxes<R, FT>(c, Pin))) return rc;
+    if (c->params.floors)
+      return stage_update<STAGE, FT, U_FLOORS>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate);
+    return stage_update<STAGE, FT, U_PLAIN>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate);
+  }
+  unsigned long long* nmark = c->fails + C_MARKS;
+  if ((rc = stage_fluxes<R, FT>(c, Pin, nmark))) return rc;
+  if ((rc = stage_update<STAGE, FT, U_PROVISIONAL>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate)))
+    return rc;
+  const Dev& g = c->dev;
+  Box b1 = make_box(0, g.n1, -1, g.n2, -1, g.n3), b2 = make_box(-1, g.n1, 0, g.n2, -1, g.n3),
+      b3 = make_box(-1, g.n1, -1, g.n2, 0, g.n3);
+  FT* F1 = (FT*)c->F[0];
+  FT* F2 = (FT*)c->F[1];
+  FT* F3 = (FT*)c->F[2];
+  if ((rc = launch(c, T_FOFC, k_fofc_flux<R, FT>, blocks_for(b1.count() + b2.count() + b3.count()), g, b1, b2,
+                   b3, Pin, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2,
+                   F3, (const unsigned char*)c->mark, (const unsigned long long*)nmark)))
+    return rc;
+  Sched be = make_sched(make_box(0, g.n1, 0, g.n2, 0, g.n3), c->kg_flux);
+  if ((rc = launch(c, T_EMF, k_emf<FT>, blocks_for(be), g, be, (const FT*)F1, (const FT*)F2, (const FT*)F3,
+                   (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2], (const unsigned long long*)nmark,
+                   (unsigned long long*)nullptr)))
+    return rc;
+  return stage_update<STAGE, FT, U_FINAL>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate);
 }
 
 // One SSPRK2 step with dt from the host, or, when dt_dev is given, with the
@@ -1209,11 +1458,9 @@ int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   c->rate_ready = false;
   if ((rc = ensure_ghosts(c))) return rc;
   c->ghosts_valid = false;
-  if ((rc = stage_fluxes<R, FT>(c, c->P))) return rc;
-  if ((rc = stage_update<1, FT>(c, c->P, c->P1, dt, nullptr, nullptr, dt_dev))) return rc;
+  if ((rc = stage<1, R, FT>(c, c->P, c->P1, dt, dt_dev, false))) return rc;
   if ((rc = fill_ghosts(c, c->P1))) return rc;
-  if ((rc = stage_fluxes<R, FT>(c, c->P1))) return rc;
-  if ((rc = stage_update<2, FT>(c, c->P1, c->P, dt, nullptr, nullptr, dt_dev, true))) return rc;
+  if ((rc = stage<2, R, FT>(c, c->P1, c->P, dt, dt_dev, true))) return rc;
   const Dev& g = c->dev;
   const long nb = blocks_for(make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update));
   c->rate_ready = nb <= MAX_PARTIALS;
@@ -1289,12 +1536,20 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   g.maxit = params->newton_maxit;
   g.inverter = params->inverter;
   g.vmax2 = 1.0 - 1.0 / (params->kastaun_wmax * params->kastaun_wmax);
+  g.floors = params->floors;
+  g.rho_min_geom = params->rho_min_geom;
+  g.u_min_geom = params->u_min_geom;
+  g.bsq_over_rho_max = params->bsq_over_rho_max;
+  g.bsq_over_u_max = params->bsq_over_u_max;
+  g.u_over_rho_max = params->u_over_rho_max;
+  g.gamma_max = params->gamma_max;
   g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
   k_geometry<<<blocks_for(g.plane), BLOCK, 0, c->stream>>>(g, c->tabC, c->tabF1, c->tabF2, c->corner,
                                                            c->conn);
   // failure count zero; no dt reduced yet (result[3] = 1)
   static const double result0[8] = {0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
-  if (hipMemsetAsync(c->fails, 0, sizeof(unsigned long long), c->stream) != hipSuccess ||
+  if (hipMemsetAsync(c->fails, 0, 8 * sizeof(unsigned long long), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->mark, 0, (size_t)g.nz, c->stream) != hipSuccess ||
       hipMemcpyAsync(c->result, result0, sizeof(result0), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hip_check() != GRMHD_OK) {
     delete c;
@@ -1394,22 +1649,35 @@ int grmhd_divb(grmhd_ctx* c, double* d_divb, double* max_out, double* mean_out) 
   return GRMHD_OK;
 }
 
-int grmhd_get_status(grmhd_ctx* c, long long* n_inv_fail, long long* n_floor) {
-  if (!c || !n_inv_fail || !n_floor) return GRMHD_E_ARG;
-  unsigned long long f = 0;
-  if (hipMemcpyAsync(&f, c->fails, sizeof(f), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+int grmhd_get_counters(grmhd_ctx* c, long long* out4) {
+  if (!c || !out4) return GRMHD_E_ARG;
+  unsigned long long f[8];
+  if (hipMemcpyAsync(f, c->fails, sizeof(f), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
     return GRMHD_E_HIP;
   int rc = sync(c);
   if (rc) return rc;
-  *n_inv_fail = (long long)f;
-  *n_floor = 0;
+  out4[0] = (long long)f[C_FAILS];
+  out4[1] = (long long)f[C_FLOORS];
+  out4[2] = (long long)f[C_FOFC];
+  out4[3] = (long long)f[C_FLUID];
+  return GRMHD_OK;
+}
+
+int grmhd_get_status(grmhd_ctx* c, long long* n_inv_fail, long long* n_floor) {
+  if (!c || !n_inv_fail || !n_floor) return GRMHD_E_ARG;
+  long long f[4];
+  int rc = grmhd_get_counters(c, f);
+  if (rc) return rc;
+  *n_inv_fail = f[0];
+  *n_floor = f[1];
   return GRMHD_OK;
 }
 
 int grmhd_reset_status(grmhd_ctx* c) {
   if (!c) return GRMHD_E_ARG;
-  return hipMemsetAsync(c->fails, 0, sizeof(unsigned long long), c->stream) == hipSuccess ? GRMHD_OK
-                                                                                        : GRMHD_E_HIP;
+  return hipMemsetAsync(c->fails, 0, 8 * sizeof(unsigned long long), c->stream) == hipSuccess
+             ? GRMHD_OK
+             : GRMHD_E_HIP;
 }
 
 int grmhd_prims_to_cons(grmhd_ctx* c, const double* d_prims, double* d_cons) {
@@ -1583,7 +1851,8 @@ int step_vjp(grmhd_ctx* c, const VjpCarve& w, const double* d_in, double dt, con
 extern "C" {
 
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
-  if (!grid_ok(grid, params)) return 0;
+  if (!grid_ok(grid, params) || params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR)
+    return 0;
   return vjp_carve(grid, params->recon, nullptr, nullptr);
 }
 
@@ -1592,6 +1861,8 @@ int grmhd_step_vjp(grmhd_ctx* c, const double* d_prims_in, double dt, const doub
   if (!c || !d_prims_in || !d_gprims_out || !d_gprims_in || !g_gamma || !d_vjp_ws) return GRMHD_E_ARG;
   if (!(dt > 0.0) || !isfinite(dt)) return GRMHD_E_ARG;
   if (c->params.precision != GRMHD_PREC_FP64) return GRMHD_E_STATE;
+  // the adjoint covers the plain high-order step (no floors, no correction)
+  if (c->params.floors || c->params.fofc || c->params.recon == GRMHD_RECON_DONOR) return GRMHD_E_STATE;
   if (((uintptr_t)d_vjp_ws & 255) != 0) return GRMHD_E_ARG;
   if (vjp_ws_bytes < vjp_carve(&c->grid, c->params.recon, nullptr, nullptr)) return GRMHD_E_NOMEM;
   VjpCarve w;
@@ -1756,6 +2027,8 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
                       void* d_ws, size_t ws_bytes, void* stream) {
   if (!out || nblocks < 1 || !n || !offsets_ijk || !global || !metric || !params || !d_ws) return GRMHD_E_ARG;
   if (!grid_ok(global, params) || params->precision != GRMHD_PREC_FP64) return GRMHD_E_ARG;
+  // packs advance the plain high-order step
+  if (params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR) return GRMHD_E_ARG;
   if (((uintptr_t)d_ws & 255) != 0) return GRMHD_E_ARG;
   for (int b = 0; b < nblocks; b++) {
     const int* o = offsets_ijk + 3 * b;
@@ -1799,6 +2072,13 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
     g.maxit = params->newton_maxit;
     g.inverter = params->inverter;
     g.vmax2 = 1.0 - 1.0 / (params->kastaun_wmax * params->kastaun_wmax);
+    g.floors = params->floors;
+    g.rho_min_geom = params->rho_min_geom;
+    g.u_min_geom = params->u_min_geom;
+    g.bsq_over_rho_max = params->bsq_over_rho_max;
+    g.bsq_over_u_max = params->bsq_over_u_max;
+    g.u_over_rho_max = params->u_over_rho_max;
+    g.gamma_max = params->gamma_max;
     g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
     BlockView& v = pk->views[b];
     default_tile(n[b], v.t1, v.t2, v.t3);

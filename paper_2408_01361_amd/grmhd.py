@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgrmhd.so")
 
 OK, E_ARG, E_HIP, E_STATE, E_NOMEM = 0, -1, -2, -3, -4
 METRIC_MINKOWSKI, METRIC_KERR_MKS = 0, 1
-RECON_MC, RECON_WENO5 = 0, 1
+RECON_MC, RECON_WENO5, RECON_DONOR = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 INV_1DW, INV_KASTAUN = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN = 0, 1, 2, 3
@@ -41,11 +41,33 @@ class grmhd_params(C.Structure):
     _fields_ = [("gamma_ad", C.c_double), ("cfl", C.c_double), ("weno_eps", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("recon", C.c_int),
                 ("precision", C.c_int), ("floors", C.c_int), ("inverter", C.c_int),
-                ("kastaun_wmax", C.c_double)]
+                ("kastaun_wmax", C.c_double), ("rho_min_geom", C.c_double),
+                ("u_min_geom", C.c_double), ("bsq_over_rho_max", C.c_double),
+                ("bsq_over_u_max", C.c_double), ("u_over_rho_max", C.c_double),
+                ("gamma_max", C.c_double), ("fofc", C.c_int)]
+
+
+# floor and ceiling defaults (HARM-family values; the paper states none)
+FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0,
+                      bsq_over_u_max=5000.0, u_over_rho_max=100.0, gamma_max=50.0)
+
+
+def make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precision, inverter,
+                kastaun_wmax, floors=False, fofc=False, **floor_params):
+    fp = dict(FLOOR_DEFAULTS)
+    for k, v in floor_params.items():
+        if k not in fp:
+            raise TypeError(f"unknown floor parameter {k}")
+        fp[k] = v
+    return grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
+                        int(newton_maxit), int(recon), int(precision), int(bool(floors)),
+                        int(inverter), float(kastaun_wmax), *(float(fp[k]) for k in FLOOR_DEFAULTS),
+                        int(bool(fofc)))
 
 
 EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_step",
            "grmhd_estimate_dt", "grmhd_step_cfl", "grmhd_last_dt", "grmhd_get_prims", "grmhd_divb", "grmhd_get_status",
+           "grmhd_get_counters",
            "grmhd_reset_status", "grmhd_prims_to_cons", "grmhd_cons_to_prims", "grmhd_fluxes",
            "grmhd_pack_workspace_bytes", "grmhd_pack_create", "grmhd_pack_set_tiles",
            "grmhd_pack_load_prims", "grmhd_pack_step", "grmhd_pack_get_prims",
@@ -70,6 +92,7 @@ def load_library(path=LIB_PATH):
         "grmhd_get_prims": (C.c_int, [vp, vp]),
         "grmhd_divb": (C.c_int, [vp, vp, dp, dp]),
         "grmhd_get_status": (C.c_int, [vp, ip, ip]),
+        "grmhd_get_counters": (C.c_int, [vp, ip]),
         "grmhd_reset_status": (C.c_int, [vp]),
         "grmhd_prims_to_cons": (C.c_int, [vp, vp, vp]),
         "grmhd_cons_to_prims": (C.c_int, [vp, vp, vp, vp, vp, ip]),
@@ -144,13 +167,13 @@ class Grmhd:
 
     def __init__(self, spec, gamma_ad, recon=RECON_WENO5, precision=PREC_FP64, cfl=0.9,
                  weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda",
-                 stream=None, strict=False, inverter=INV_1DW, kastaun_wmax=1e3):
+                 stream=None, strict=False, inverter=INV_1DW, kastaun_wmax=1e3, floors=False,
+                 fofc=False, **floor_params):
         self.spec = spec
         self.grid = make_grid(spec)
         self.metric = grmhd_metric(int(spec.metric), float(spec.a), float(spec.hslope))
-        self.params = grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
-                                   int(newton_maxit), int(recon), int(precision), 0,
-                                   int(inverter), float(kastaun_wmax))
+        self.params = make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precision,
+                                  inverter, kastaun_wmax, floors, fofc, **floor_params)
         self.strict = strict
         L = lib()
         nbytes = L.grmhd_workspace_bytes(C.byref(self.grid), C.byref(self.params))
@@ -219,6 +242,14 @@ class Grmhd:
         _check(lib().grmhd_get_status(self.ctx, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def counters(self):
+        """Counts since creation or reset: failed inversions, zones floors
+        acted on, zones the first-order flux correction marked, fluid-frame
+        fallbacks of the floors."""
+        out = (C.c_longlong * 4)()
+        _check(lib().grmhd_get_counters(self.ctx, out))
+        return dict(fails=out[0], floor_hits=out[1], fofc_zones=out[2], fluid_frame=out[3])
+
     def reset_status(self):
         _check(lib().grmhd_reset_status(self.ctx))
 
@@ -244,7 +275,7 @@ class Grmhd:
         _check(lib().grmhd_fluxes(self.ctx, _ptr(p), _ptr(out)))
         return out
 
-    TIMING_CLASSES = ("bc", "flux", "emf", "update1", "update2", "dt")
+    TIMING_CLASSES = ("bc", "flux", "emf", "update1", "update2", "dt", "fofc")
 
     def step_vjp(self, prims_in, dt, gprims_out):
         """Adjoint of one step: (d loss/d prims_in, d loss/d gamma_ad)."""
@@ -301,9 +332,8 @@ class Pack:
         self.grid = make_grid(global_spec)
         self.metric = grmhd_metric(int(global_spec.metric), float(global_spec.a),
                                    float(global_spec.hslope))
-        self.params = grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
-                                   int(newton_maxit), int(recon), PREC_FP64, 0,
-                                   int(inverter), float(kastaun_wmax))
+        self.params = make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, PREC_FP64,
+                                  inverter, kastaun_wmax)
         nbytes = L.grmhd_pack_workspace_bytes(self.nb, self._n)
         if nbytes == 0:
             raise GrmhdError("invalid pack")

@@ -1,0 +1,147 @@
+"""GPU-vs-oracle parity of the floors and the first-order flux correction.
+
+Workloads: the magnetised cylindrical blast (flat space, 48^2, MC and WENO5),
+where the high-order step loses zones to failed inversions, and the coarse
+magnetised torus (Kerr), whose atmosphere zones at the torus edge fail
+without floors.  Both sides advance with the oracle's dt; the bar is the
+step bar (relative L1 of every primitive at most 1e-12) and the same
+counters: failed inversions, floor activations, marked zones, fluid-frame
+fallbacks.  The marks are decided in FP64 on both sides from the same
+operations (flat space: bit for bit)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import rel_l1
+from workloads import (magnetised_blast, fm_torus, linear_mode, interior, RECON_MC, RECON_WENO5)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_01361_amd import grmhd as gr
+    return torch, gr
+
+
+def run_both(grid, P, gam, recon, nsteps, floors, fofc, inverter=0, precision=0, **fp):
+    torch, gr = _setup()
+    c = oracle.cfg(grid, gam=gam, recon=recon, floors=floors, fofc=fofc, inverter=inverter, **fp)
+    ref, fails, dts = oracle.run(c, P, -1, nsteps)
+    st = oracle.last_stats()
+    s = gr.Grmhd(grid, gam, recon=recon, floors=floors, fofc=fofc, inverter=inverter,
+                 precision=precision, **fp)
+    s.load(torch.from_numpy(P).cuda())
+    for dt in dts:
+        s.step(float(dt))
+    out = s.prims().cpu().numpy()
+    return out, ref, s.counters(), st, s, dts
+
+
+CASES = {
+    "blast48_mc_fofc": (lambda: magnetised_blast(48), 4 / 3, RECON_MC, 4, False, True),
+    "blast48_mc_floors_fofc": (lambda: magnetised_blast(48), 4 / 3, RECON_MC, 6, True, True),
+    "blast48_weno_floors_fofc": (lambda: magnetised_blast(48), 4 / 3, RECON_WENO5, 6, True, True),
+    "blast48_weno_floors": (lambda: magnetised_blast(48), 4 / 3, RECON_WENO5, 6, True, False),
+    "torus24_weno_floors_fofc": (lambda: fm_torus(24, 24, 8)[0:2], 13 / 9, RECON_WENO5, 3, True, True),
+    "torus20x28x6_mc_floors": (lambda: fm_torus(20, 28, 6)[0:2], 13 / 9, RECON_MC, 3, True, False),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_floors_fofc_parity(case):
+    make, gam, recon, nsteps, floors, fofc = CASES[case]
+    grid, P = make()
+    out, ref, cnt, st, _, dts = run_both(grid, P, gam, recon, nsteps, floors, fofc)
+    r = rel_l1(out, ref)
+    print(case, "gpu", cnt, "oracle", st, "rel L1", r, flush=True)
+    assert cnt == st
+    assert (st["fofc_zones"] > 0) == fofc or st["floor_hits"] > 0
+    assert r.max() <= TOL, r
+
+
+def test_kastaun_with_floors_and_fofc():
+    grid, P = magnetised_blast(48)
+    out, ref, cnt, st, _, _ = run_both(grid, P, 4 / 3, RECON_WENO5, 6, True, True, inverter=1)
+    r = rel_l1(out, ref)
+    print("kastaun blast", cnt, st, r)
+    assert cnt == st and r.max() <= TOL
+
+
+def test_donor_cell_step_parity():
+    """The first-order scheme alone (donor-cell states everywhere)."""
+    for make, gam in ((lambda: linear_mode("fast", 32, ndim=2)[0:2], 4 / 3),
+                      (lambda: fm_torus(20, 28, 6)[0:2], 13 / 9)):
+        grid, P = make()
+        out, ref, cnt, st, _, _ = run_both(grid, P, gam, oracle.RECON_DONOR, 2, False, False)
+        r = rel_l1(out, ref)
+        print("donor", cnt, st, r)
+        assert cnt["fails"] == st["fails"] and r.max() <= TOL
+
+
+def test_fofc_and_floors_are_a_no_op_on_smooth_flow():
+    """Nothing marked, nothing floored: the step equals the plain one bit for
+    bit on the GPU too."""
+    torch, gr = _setup()
+    grid, P, _, _ = linear_mode("fast", 24, ndim=2)
+    outs = []
+    for fl, fo in ((False, False), (True, True)):
+        s = gr.Grmhd(grid, 4 / 3, recon=RECON_WENO5, floors=fl, fofc=fo)
+        s.load(torch.from_numpy(P).cuda())
+        for _ in range(3):
+            s.step_cfl()
+        outs.append(s.prims().cpu().numpy())
+        c = s.counters()
+        assert c["fofc_zones"] == 0 and c["floor_hits"] == 0
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_fofc_removes_failures_and_keeps_divb_and_cfl():
+    """The blast with the correction: no failures where the plain step has
+    some, corner div B at roundoff, and the device CFL step (its rate
+    partials come from the final pass) equals the oracle's dt."""
+    torch, gr = _setup()
+    grid, P = magnetised_blast(48)
+    plain = gr.Grmhd(grid, 4 / 3, recon=RECON_MC)
+    plain.load(torch.from_numpy(P).cuda())
+    s = gr.Grmhd(grid, 4 / 3, recon=RECON_MC, fofc=True)
+    s.load(torch.from_numpy(P).cuda())
+    for _ in range(4):
+        plain.step_cfl()
+        s.step_cfl()
+    assert plain.status()[0] > 0
+    cnt = s.counters()
+    assert cnt["fails"] == 0 and cnt["fofc_zones"] > 0
+    mx, _ = s.divb()
+    assert mx < 1e-13 * 0.07 / grid.dx[0]
+    out = s.prims().cpu().numpy()
+    s.step_cfl()
+    c = oracle.cfg(grid, gam=4 / 3, recon=RECON_MC, fofc=True)
+    assert s.last_dt() == pytest.approx(oracle.estimate_dt(c, out), rel=1e-14)
+
+
+def test_mixed_precision_with_fofc_runs_and_keeps_divb():
+    """FP32 fluxes with the correction (no oracle: the reduced-precision path
+    is measured against FP64): div B stays at FP64 roundoff, no failures,
+    density within 1e-3 relative L1 of the FP64 run."""
+    torch, gr = _setup()
+    grid, P = magnetised_blast(48)
+    res = []
+    for prec in (gr.PREC_FP64, gr.PREC_MIXED):
+        s = gr.Grmhd(grid, 4 / 3, recon=RECON_MC, fofc=True, floors=True, precision=prec)
+        s.load(torch.from_numpy(P).cuda())
+        dt = s.dt()
+        for _ in range(4):
+            s.step(dt)
+        res.append((s.prims().cpu().numpy(), s.counters(), s.divb()[0]))
+    (a, ca, _), (b, cb, db) = res
+    print("fp64", ca, "mixed", cb)
+    assert cb["fails"] == 0
+    assert db < 1e-13 * 0.07 / grid.dx[0]
+    A, B = interior(a)[0], interior(b)[0]
+    assert np.abs(A - B).sum() / np.abs(A).sum() < 1e-3

@@ -56,3 +56,28 @@ def test_workspace_and_argument_validation():
     assert lib.grmhd_create(C.byref(ctx), C.byref(g), C.byref(m), C.byref(p), None, nb, None) == grmhd.E_ARG
     assert lib.grmhd_step(None, 0.1) == grmhd.E_ARG
     assert lib.grmhd_strerror(grmhd.E_NOMEM) == b"workspace too small"
+
+
+def test_floor_and_correction_parameters_are_validated():
+    from paper_2408_01361_amd import grmhd
+    from workloads import torus_grid
+    lib = grmhd.lib()
+    g = grmhd.make_grid(torus_grid(32, 32, 32))
+    mk = lambda **kw: grmhd.make_params(13 / 9, 0.9, 1e-26, 1e-14, 30, grmhd.RECON_WENO5,
+                                        grmhd.PREC_FP64, 0, 1e3, **kw)
+    ok = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(floors=True, fofc=True)))
+    assert ok > 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(floors=True, gamma_max=1.0))) == 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(floors=True, rho_min_geom=0.0))) == 0
+    # parameters of disabled floors are not looked at
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(floors=False, gamma_max=0.0))) > 0
+    p = mk(fofc=True)
+    p.fofc = 2
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(p)) == 0
+    # the adjoint covers the plain high-order step only
+    assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(fofc=True))) == 0
+    assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(floors=True))) == 0
+    donor = grmhd.make_params(13 / 9, 0.9, 1e-26, 1e-14, 30, grmhd.RECON_DONOR, grmhd.PREC_FP64, 0, 1e3)
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(donor)) > 0
+    assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(donor)) == 0
+    assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk())) > 0
