@@ -248,6 +248,51 @@ def kastaun_extra(torch, gr, grid, P, gam, recon, steps):
     return res
 
 
+def floors_fofc_extra(torch, gr, grid, P, gam, recon, steps):
+    """What the floors and the first-order flux correction cost: the headline
+    torus step plain, with floors, and with floors plus the correction; and
+    the magnetised blast at 1024^2 (flat space), where the correction acts,
+    without and with it (failed inversions and marked zones per run)."""
+    from workloads import magnetised_blast, RECON_MC
+    out = {}
+    Pt = torch.from_numpy(P).cuda()
+    torus = {}
+    for name, kw in (("plain", {}), ("floors", dict(floors=True)),
+                     ("floors_fofc", dict(floors=True, fofc=True))):
+        s = gr.Grmhd(grid, gam, recon=recon, **kw)
+        s.load(Pt)
+        for _ in range(10):          # untimed: clocks settle
+            s.step_cfl()
+        s.load(Pt)
+        s.reset_status()
+        el = time_steps(torch, s, steps)
+        torus[name] = {"zone_cycles_per_s": grid.n1 * grid.n2 * grid.n3 * steps / el,
+                       "ms_per_step": el * 1e3 / steps, "counters": s.counters()}
+        del s
+    torus["workload"] = "the headline torus and step"
+    out["torus"] = torus
+    del Pt
+    n, nsteps = 1024, 20
+    bg, bP = magnetised_blast(n)
+    bPt = torch.from_numpy(bP).cuda()
+    blast = {}
+    for name, kw in (("plain", {}), ("fofc", dict(fofc=True)), ("floors_fofc", dict(floors=True, fofc=True))):
+        s = gr.Grmhd(bg, 4.0 / 3.0, recon=RECON_MC, **kw)
+        s.load(bPt)
+        for _ in range(5):
+            s.step_cfl()
+        s.load(bPt)
+        s.reset_status()
+        el = time_steps(torch, s, nsteps)
+        blast[name] = {"zone_cycles_per_s": n * n * nsteps / el, "ms_per_step": el * 1e3 / nsteps,
+                       "counters": s.counters()}
+        del s
+    blast["workload"] = (f"magnetised cylindrical explosion, flat, {n}^2 x 1, MC, FP64, {nsteps} RK2 "
+                         "steps at the CFL dt from the initial state")
+    out["blast"] = blast
+    return out
+
+
 def adjoint_extra(torch, gr):
     """Gradient of sum_{i<5} rho u after 8 steps of the 64^3 torus (MC, FP64,
     fixed dt) with respect to the initial prims and gamma: the forward pass
@@ -392,6 +437,7 @@ def main():
     if not args.no_extras:
         out.update(extras(torch, gr, np, args))
         out["inverters"] = kastaun_extra(torch, gr, grid, P, gam, recon, args.steps)
+        out["floors_fofc"] = floors_fofc_extra(torch, gr, grid, P, gam, recon, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_baseline(grid, P, gam, recon, args.cpu_seconds)
     print(json.dumps(out))

@@ -238,8 +238,9 @@ int grmhd_set_schedule(grmhd_ctx* ctx, int kg_flux, int kg_update);
  * event in its own dispatch (hipExtLaunchKernel), so no marker packets are
  * added between kernels.  Classes: 0 ghost fill, 1 face fluxes (x1, x2 and
  * x3 faces in one launch), 2 EMFs, 3 stage-1 update, 4 stage-2 update, 5 dt
- * reduction.  The report sums elapsed milliseconds and counts launches per
- * class into arrays of nclass >= 6 entries.  Both synchronise the stream.
+ * reduction, 6 the flux correction's donor-cell face fix, 7 floors.  The
+ * report sums elapsed milliseconds and counts launches per class into
+ * arrays of nclass >= 8 entries.  Both synchronise the stream.
  * For measurement; the step itself is unchanged. */
 int grmhd_timing(grmhd_ctx* ctx, int class_mask);
 int grmhd_timing_report(grmhd_ctx* ctx, double* total_ms, long long* launches, int nclass);

@@ -766,8 +766,54 @@ __device__ __forceinline__ double spatial_dot(const PointMetric<double>& m, cons
   return s;
 }
 
-__device__ __noinline__ int apply_floors(const Dev& g, const PointMetric<double>& m, double x1,
-                                         double P[NVAR]) {
+// Injection of drho, du of material moving with the drift velocity into
+// the zone's prims P (fluid state f); returns FL_FLUID_FRAME if the inversion
+// of the sum failed and the floored prims were kept.  Inlined on purpose: an
+// out-of-line call gives the kernel a private (scratch) segment, and the
+// scratch every wave then reserves cut the floors pass's speed six-fold.
+__device__ __forceinline__ int inject_drift(const Dev& g, const PointMetric<double>& m, const Fluid<double>& f,
+                                         double drho, double du, double P[NVAR]) {
+#pragma clang fp contract(off)
+  const double ut[3] = {P[U1], P[U2], P[U3]}, B[3] = {P[B1], P[B2], P[B3]};
+  const double gamma = sqrt(1.0 + spatial_dot(m, ut, ut));
+  double v[3], vd[3];
+#pragma unroll
+  for (int i = 0; i < 3; i++) v[i] = ut[i] / gamma;
+  const double BB = spatial_dot(m, B, B);
+  if (BB > 0.0) {
+    const double vB = spatial_dot(m, v, B);
+#pragma unroll
+    for (int i = 0; i < 3; i++) vd[i] = v[i] - vB * B[i] / BB;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; i++) vd[i] = v[i];
+  }
+  const double gd = 1.0 / sqrt(1.0 - spatial_dot(m, vd, vd));
+  double Pd[NVAR] = {drho, du, gd * vd[0], gd * vd[1], gd * vd[2], 0.0, 0.0, 0.0};
+  double U[NVAR], dU[NVAR], guess[NVAR], Pn[NVAR];
+  prim_to_flux(P, f, m, g.gam, 0, U);
+  Fluid<double> fd;
+  fluid_state(Pd, m, fd);
+  prim_to_flux(Pd, fd, m, g.gam, 0, dU);
+#pragma unroll
+  for (int v2 = 0; v2 < NVAR; v2++) {
+    U[v2] = U[v2] + dU[v2];
+    guess[v2] = P[v2];
+  }
+  guess[RHO] = P[RHO] + drho;
+  guess[UU] = P[UU] + du;
+  if (invert(g, m, U, guess, Pn) == 0) {
+#pragma unroll
+    for (int v2 = 0; v2 < 5; v2++) P[v2] = Pn[v2];
+    return 0;
+  }
+#pragma unroll
+  for (int v2 = 0; v2 < 5; v2++) P[v2] = guess[v2];
+  return FL_FLUID_FRAME;
+}
+
+__device__ __forceinline__ int apply_floors(const Dev& g, const PointMetric<double>& m, double x1,
+                                            double P[NVAR]) {
 #pragma clang fp contract(off)
   const double r = g.st.kerr ? exp(x1) : 1.0;
   const double sr = sqrt(r);
@@ -782,45 +828,8 @@ __device__ __noinline__ int apply_floors(const Dev& g, const PointMetric<double>
   if (drho < 0.0) drho = 0.0;
   if (du < 0.0) du = 0.0;
   int mask = 0;
-  if (drho > 0.0 || du > 0.0) {
-    mask |= (drho > 0.0 ? FL_RHO : 0) | (du > 0.0 ? FL_U : 0);
-    const double ut[3] = {P[U1], P[U2], P[U3]}, B[3] = {P[B1], P[B2], P[B3]};
-    const double gamma = sqrt(1.0 + spatial_dot(m, ut, ut));
-    double v[3], vd[3];
-#pragma unroll
-    for (int i = 0; i < 3; i++) v[i] = ut[i] / gamma;
-    const double BB = spatial_dot(m, B, B);
-    if (BB > 0.0) {
-      const double vB = spatial_dot(m, v, B);
-#pragma unroll
-      for (int i = 0; i < 3; i++) vd[i] = v[i] - vB * B[i] / BB;
-    } else {
-#pragma unroll
-      for (int i = 0; i < 3; i++) vd[i] = v[i];
-    }
-    const double gd = 1.0 / sqrt(1.0 - spatial_dot(m, vd, vd));
-    double Pd[NVAR] = {drho, du, gd * vd[0], gd * vd[1], gd * vd[2], 0.0, 0.0, 0.0};
-    double U[NVAR], dU[NVAR], guess[NVAR], Pn[NVAR];
-    prim_to_flux(P, f, m, g.gam, 0, U);
-    Fluid<double> fd;
-    fluid_state(Pd, m, fd);
-    prim_to_flux(Pd, fd, m, g.gam, 0, dU);
-#pragma unroll
-    for (int v2 = 0; v2 < NVAR; v2++) {
-      U[v2] = U[v2] + dU[v2];
-      guess[v2] = P[v2];
-    }
-    guess[RHO] = P[RHO] + drho;
-    guess[UU] = P[UU] + du;
-    if (invert(g, m, U, guess, Pn) == 0) {
-#pragma unroll
-      for (int v2 = 0; v2 < 5; v2++) P[v2] = Pn[v2];
-    } else {
-#pragma unroll
-      for (int v2 = 0; v2 < 5; v2++) P[v2] = guess[v2];
-      mask |= FL_FLUID_FRAME;
-    }
-  }
+  if (drho > 0.0 || du > 0.0)
+    mask |= (drho > 0.0 ? FL_RHO : 0) | (du > 0.0 ? FL_U : 0) | inject_drift(g, m, f, drho, du, P);
   const double ut[3] = {P[U1], P[U2], P[U3]};
   const double gamma = sqrt(1.0 + spatial_dot(m, ut, ut));
   if (gamma > g.gamma_max) {
@@ -925,11 +934,12 @@ __device__ __forceinline__ void geometric_source(const double p[NVAR], const Flu
 // One stage for every interior zone.  STAGE 1: V = (Un + U1)/2 with
 // Un = U(Pin), U1 = Un + dt L(Pin); STAGE 2: U = V + dt L(Pin)/2.  Then
 // Pout = U_to_P(U; guess Pin).  B fluxes come from the edge EMFs.
-// Update modes: PLAIN (no floors), FLOORS (floors when g.floors), and the
-// two passes of a stage under the first-order flux correction: PROVISIONAL
-// (marks zones whose inversion fails or that floors act on, counts nothing
-// else) and FINAL (the same update from the corrected fluxes, counted).
-enum { U_PLAIN = 0, U_FLOORS = 1, U_PROVISIONAL = 2, U_FINAL = 3 };
+// Update modes: PLAIN, and the two passes of a stage under the first-order
+// flux correction: PROVISIONAL (marks zones whose inversion fails, counts
+// nothing else) and FINAL (the same update from the corrected fluxes,
+// counted).  Floors run in a kernel of their own after each update pass
+// (k_floors), with the same modes.
+enum { U_PLAIN = 0, U_PROVISIONAL = 2, U_FINAL = 3 };
 // Counter slots of the context's counter array.
 enum { C_FAILS = 0, C_C2P = 1, C_FLOORS = 2, C_FOFC = 3, C_FLUID = 4, C_MARKS = 5 };
 
@@ -997,34 +1007,14 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
   }
   double out[NVAR];
   int bad = invert(g, m, U, p, out);
-  int fl = 0;
-  if (MODE != U_PLAIN && g.floors) {
-    fl = apply_floors(g, m, g.x1min + (i + 0.5) * g.dx1, out);
-    if (STAGE == 1 && fl) {
-      // the stage register holds the floored state's conserved variables
-      double U0[NVAR], U1[NVAR];
-      Fluid<double> f0, f1;
-      fluid_state(p, m, f0);
-      prim_to_flux(p, f0, m, g.gam, 0, U0);
-      fluid_state(out, m, f1);
-      prim_to_flux(out, f1, m, g.gam, 0, U1);
-#pragma unroll
-      for (int v = 0; v < NVAR; v++) V[v * nz + c] = 0.5 * (U0[v] + U1[v]);
-    }
-  }
 #pragma unroll
   for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
   if (flags) flags[c] = (unsigned char)bad;
   if (MODE == U_PROVISIONAL) {
-    const bool mk = bad || fl;
-    mark[c] = (unsigned char)mk;
-    if (mk) atomicAdd(&fails[C_MARKS], 1ull);
-  } else {
-    if (bad) atomicAdd(&fails[C_FAILS], 1ull);
-    if (fl) {
-      atomicAdd(&fails[C_FLOORS], 1ull);
-      if (fl & FL_FLUID_FRAME) atomicAdd(&fails[C_FLUID], 1ull);
-    }
+    mark[c] = (unsigned char)bad;
+    if (bad) atomicAdd(&fails[C_MARKS], 1ull);
+  } else if (bad) {
+    atomicAdd(&fails[C_FAILS], 1ull);
   }
   if (RATE) *rate = zone_rate(g, out, m);
 }
@@ -1037,8 +1027,7 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
 // grid-uniform test of the mark count), and then adds that count to the
 // correction's running total.
 template <int STAGE, typename FT, bool RATE, int MODE>
-__global__ void __launch_bounds__(BLOCK)
-__attribute__((amdgpu_waves_per_eu(MODE == U_PLAIN ? UPDATE_WAVES : 2, 8)))
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8)))
 k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ Pout,
          double* __restrict__ V, const FT* __restrict__ F1, const FT* __restrict__ F2,
          const FT* __restrict__ F3, const FT* __restrict__ E1, const FT* __restrict__ E2,
@@ -1066,6 +1055,67 @@ k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ 
                                        flags, i, j, k, &r, mark);
   block_reduce(r, sm);
   if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
+}
+
+// Floors over the prims one update pass wrote (Pout), zone by zone as the
+// update left them: where they act, the new prims are stored and, in stage
+// 1, the stage register V gets the floored state's conserved variables
+// (recomputed from the stage input Pin).  PROVISIONAL marks the zones floors
+// act on (counting each newly marked zone), PLAIN and FINAL count floor
+// activations; FINAL runs only when the provisional passes marked a zone.
+// With RATE the CFL-rate partials of the final prims are written here (the
+// update then writes none), over the update's schedule.
+template <int STAGE, bool RATE, int MODE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) k_floors(Dev g, Sched box, const double* __restrict__ Pin,
+                                                  double* __restrict__ Pout, double* __restrict__ V,
+                                                  const double* __restrict__ tabC,
+                                                  unsigned long long* fails, unsigned char* __restrict__ mark,
+                                                  double* __restrict__ rate_partial) {
+#pragma clang fp contract(off)
+  if (MODE == U_FINAL && fails[C_MARKS] == 0) return;
+  int i, j, k;
+  const bool in = sched_index(box, blockIdx.x, gridDim.x, i, j, k);
+  double r = 0.0;
+  if (in) {
+    const long c = zid(g, i, j, k), nz = g.nz;
+    double out[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) out[v] = Pout[v * nz + c];
+    PointMetric<double> m;
+    load_metric<double>(tabC, g.plane, pid(g, i, j), m);
+    const int fl = apply_floors(g, m, g.x1min + (i + 0.5) * g.dx1, out);
+    if (fl) {
+#pragma unroll
+      for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
+      if (STAGE == 1) {
+        double p[NVAR], U0[NVAR], U1[NVAR];
+#pragma unroll
+        for (int v = 0; v < NVAR; v++) p[v] = Pin[v * nz + c];
+        Fluid<double> f0, f1;
+        fluid_state(p, m, f0);
+        prim_to_flux(p, f0, m, g.gam, 0, U0);
+        fluid_state(out, m, f1);
+        prim_to_flux(out, f1, m, g.gam, 0, U1);
+#pragma unroll
+        for (int v = 0; v < NVAR; v++) V[v * nz + c] = 0.5 * (U0[v] + U1[v]);
+      }
+      if (MODE == U_PROVISIONAL) {
+        if (mark[c] == 0) {
+          mark[c] = 1;
+          atomicAdd(&fails[C_MARKS], 1ull);
+        }
+      } else {
+        atomicAdd(&fails[C_FLOORS], 1ull);
+        if (fl & FL_FLUID_FRAME) atomicAdd(&fails[C_FLUID], 1ull);
+      }
+    }
+    if (RATE) r = zone_rate(g, out, m);
+  }
+  if (RATE) {
+    double sm = 0.0;
+    block_reduce(r, sm);
+    if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
+  }
 }
 
 // ------------------------------------------------------- reductions etc. --
@@ -1306,7 +1356,7 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
 
 int hip_check() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
 
-enum { T_BC = 0, T_FLUX, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_FOFC, T_NCLASS };
+enum { T_BC = 0, T_FLUX, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_FOFC, T_FLOORS, T_NCLASS };
 
 // Start/stop events of one launch of class cls while timing is enabled (null
 // events otherwise, or when no more events can be created).
@@ -1412,24 +1462,41 @@ int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
                 fails ? fails : c->fails, flags, (double*)nullptr, c->mark);
 }
 
-// One RK2 stage from the ghost-filled prims Pin: fluxes, EMFs, update (with
-// floors when enabled).  Under the first-order flux correction: the
-// provisional update marks zones, the marked zones' faces get donor-cell
-// fluxes, and the EMF and update passes run again; these three launches
+// The floors pass after an update pass (same schedule as the update, so the
+// CFL-rate partials it writes with rate are the ones the dt reduction reads).
+template <int STAGE, int MODE>
+int stage_floors(grmhd_ctx* c, const double* Pin, double* Pout, bool rate) {
+  const Dev& g = c->dev;
+  Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
+  const unsigned nb = blocks_for(bz);
+  if (STAGE == 2 && rate && nb <= (unsigned)MAX_PARTIALS)
+    return launch(c, T_FLOORS, k_floors<STAGE, true, MODE>, nb, g, bz, Pin, Pout, c->V,
+                  (const double*)c->tabC, c->fails, c->mark, c->pdt);
+  return launch(c, T_FLOORS, k_floors<STAGE, false, MODE>, nb, g, bz, Pin, Pout, c->V,
+                (const double*)c->tabC, c->fails, c->mark, (double*)nullptr);
+}
+
+// One RK2 stage from the ghost-filled prims Pin: fluxes, EMFs, update, then
+// floors when enabled (which then write the CFL-rate partials instead of the
+// update).  Under the first-order flux correction: the provisional update
+// and floors passes mark zones, the marked zones' faces get donor-cell
+// fluxes, and the EMF, update and floors passes run again; these launches
 // exit at once when nothing was marked.
 template <int STAGE, typename R, typename FT>
 int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double* dt_dev, bool rate) {
   int rc;
+  const bool floors = c->params.floors != 0;
+  const bool urate = rate && !floors;
   if (!c->params.fofc) {
     if ((rc = stage_fluxes<R, FT>(c, Pin))) return rc;
-    if (c->params.floors)
-      return stage_update<STAGE, FT, U_FLOORS>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate);
-    return stage_update<STAGE, FT, U_PLAIN>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate);
+    if ((rc = stage_update<STAGE, FT, U_PLAIN>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, urate))) return rc;
+    return floors ? stage_floors<STAGE, U_PLAIN>(c, Pin, Pout, rate) : GRMHD_OK;
   }
   unsigned long long* nmark = c->fails + C_MARKS;
   if ((rc = stage_fluxes<R, FT>(c, Pin, nmark))) return rc;
-  if ((rc = stage_update<STAGE, FT, U_PROVISIONAL>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate)))
+  if ((rc = stage_update<STAGE, FT, U_PROVISIONAL>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, urate)))
     return rc;
+  if (floors && (rc = stage_floors<STAGE, U_PROVISIONAL>(c, Pin, Pout, rate))) return rc;
   const Dev& g = c->dev;
   Box b1 = make_box(0, g.n1, -1, g.n2, -1, g.n3), b2 = make_box(-1, g.n1, 0, g.n2, -1, g.n3),
       b3 = make_box(-1, g.n1, -1, g.n2, 0, g.n3);
@@ -1445,7 +1512,8 @@ int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double
                    (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2], (const unsigned long long*)nmark,
                    (unsigned long long*)nullptr)))
     return rc;
-  return stage_update<STAGE, FT, U_FINAL>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate);
+  if ((rc = stage_update<STAGE, FT, U_FINAL>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, urate))) return rc;
+  return floors ? stage_floors<STAGE, U_FINAL>(c, Pin, Pout, rate) : GRMHD_OK;
 }
 
 // One SSPRK2 step with dt from the host, or, when dt_dev is given, with the

@@ -275,7 +275,7 @@ class Grmhd:
         _check(lib().grmhd_fluxes(self.ctx, _ptr(p), _ptr(out)))
         return out
 
-    TIMING_CLASSES = ("bc", "flux", "emf", "update1", "update2", "dt", "fofc")
+    TIMING_CLASSES = ("bc", "flux", "emf", "update1", "update2", "dt", "fofc", "floors")
 
     def step_vjp(self, prims_in, dt, gprims_out):
         """Adjoint of one step: (d loss/d prims_in, d loss/d gamma_ad)."""
