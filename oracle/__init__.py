@@ -44,10 +44,11 @@ class Cfg(C.Structure):
                 ("rho_min_geom", C.c_double), ("u_min_geom", C.c_double),
                 ("bsq_over_rho_max", C.c_double), ("bsq_over_u_max", C.c_double),
                 ("u_over_rho_max", C.c_double), ("gamma_max", C.c_double),
-                ("fofc", C.c_int)]
+                ("fofc", C.c_int), ("ct", C.c_int)]
 
 INV_1DW, INV_KASTAUN = 0, 1
 RECON_DONOR = 2
+CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
 FL_RHO, FL_U, FL_FLUID_FRAME, FL_GAMMA, FL_TEMP = 1, 2, 4, 8, 16
 # floor and ceiling defaults (HARM-family values; the paper states none)
 FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0,
@@ -82,6 +83,10 @@ def _declare(lib):
     lib.orc_point_floors.argtypes = [P, _D, C.c_double, C.c_double]
     lib.orc_point_floors.restype = C.c_int
     lib.orc_last_stats.argtypes = [C.POINTER(C.c_longlong)]
+    lib.orc_run_face.argtypes = [P, _D, _D, C.c_double, C.c_int, _D, _I]
+    lib.orc_run_face.restype = C.c_long
+    lib.orc_face_divb.argtypes = [P, _D, _D, _D]
+    lib.orc_edge_emfs.argtypes = [P, _D, _D, _D]
     lib.orc_weno5.argtypes = [C.c_double] * 6
     lib.orc_weno5.restype = C.c_double
     lib.orc_mc_slope.argtypes = [C.c_double] * 3
@@ -109,7 +114,7 @@ def lib(counting=False):
 
 def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
         newton_maxit=30, cfl=0.9, nthreads=None, inverter=INV_1DW, kastaun_wmax=1e3,
-        floors=False, fofc=False, **floor_params):
+        floors=False, fofc=False, ct=CT_FLUX, **floor_params):
     c = Cfg()
     c.n1, c.n2, c.n3 = grid.n1, grid.n2, grid.n3
     c.x1min, c.x1max = grid.x1min, grid.x1max
@@ -124,6 +129,7 @@ def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
     c.nthreads = nthreads or os.cpu_count() or 1
     c.inverter, c.kastaun_wmax = int(inverter), float(kastaun_wmax)
     c.floors, c.fofc = int(bool(floors)), int(bool(fofc))
+    c.ct = int(ct)
     fp = dict(FLOOR_DEFAULTS)
     for k, v in floor_params.items():
         if k not in fp:
@@ -149,6 +155,38 @@ def run(c, prims, dt, nsteps=1, counting=False, flags=False):
     if flags:
         return P, int(fails), dts, fl
     return P, int(fails), dts
+
+
+def run_face(c, prims, faces, dt, nsteps=1, flags=False):
+    """Face-centred CT: advance copies of prims and face fields
+    ([3][padded], sqrt(-g) B^d on lower d-faces); returns (prims, faces,
+    fails, dts[, flags])."""
+    P = np.ascontiguousarray(prims, dtype=np.float64).copy()
+    Fc = np.ascontiguousarray(faces, dtype=np.float64).copy()
+    assert Fc.shape == (3,) + P.shape[1:]
+    dts = np.zeros(max(nsteps, 1))
+    fl = np.zeros(P.shape[1:], dtype=np.int32) if flags else None
+    fails = lib().orc_run_face(C.byref(c), _ptr(P), _ptr(Fc), float(dt), int(nsteps), _ptr(dts),
+                               fl.ctypes.data_as(_I) if flags else None)
+    if flags:
+        return P, Fc, int(fails), dts, fl
+    return P, Fc, int(fails), dts
+
+
+def edge_emfs(c, prims, faces):
+    """Edge EMFs [3][padded] (E1, E2, E3) of the face-centred scheme c.ct."""
+    P = np.ascontiguousarray(prims, dtype=np.float64)
+    F = np.ascontiguousarray(faces, dtype=np.float64)
+    out = np.zeros(F.shape)
+    lib().orc_edge_emfs(C.byref(c), _ptr(P), _ptr(F), _ptr(out))
+    return out
+
+
+def face_divb(c, faces):
+    F = np.ascontiguousarray(faces, dtype=np.float64)
+    mx, mean = C.c_double(), C.c_double()
+    lib().orc_face_divb(C.byref(c), _ptr(F), C.byref(mx), C.byref(mean))
+    return mx.value, mean.value
 
 
 def last_stats(counting=False):

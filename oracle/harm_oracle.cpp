@@ -78,6 +78,7 @@ typedef struct {
   double bsq_over_rho_max, bsq_over_u_max; // magnetisation floors
   double u_over_rho_max, gamma_max;       // temperature and Lorentz-factor ceilings
   int fofc;            // 1: first-order flux correction of zones a stage would break
+  int ct;              // 0: Flux-CT; face-centred CT with 1: averaged, 2: upwinded edge EMFs
 } orc_cfg;
 }
 
@@ -455,8 +456,10 @@ void reconstruct(const Grid& g, const std::vector<real>& P, int recon, int d, in
 // Local Lax-Friedrichs flux at the lower d-face of zone (i, j, k):
 // F = (F_L + F_R)/2 - c_max (U_R - U_L)/2, c_max = max(0, c+_L, c+_R, -c-_L, -c-_R).
 // Faces on the polar axis carry no flux (sqrt(-g) = 0 there).
+// With face fields phi (face-centred CT), the normal field of both states
+// is the face value phi_d / sqrt(-g) at the face.
 void face_flux(const Grid& g, const std::vector<real>& P, int recon, int d, int i, int j, int k,
-               real F[NV]) {
+               real F[NV], const std::vector<real>* phi = nullptr) {
   if (g.pole_face(d, j)) {
     for (int v = 0; v < NV; v++) F[v] = 0.0;
     return;
@@ -464,6 +467,10 @@ void face_flux(const Grid& g, const std::vector<real>& P, int recon, int d, int 
   real qL[NV], qR[NV];
   reconstruct(g, P, recon, d, i, j, k, qL, qR);
   const Geom& G = g.face_geom(d, i, j);
+  if (phi) {
+    qL[B1 + d - 1] = phi[d - 1][g.id(i, j, k)] / G.gdet;
+    qR[B1 + d - 1] = qL[B1 + d - 1];
+  }
   FluidState SL, SR;
   fluid_state(qL, G, SL);
   fluid_state(qR, G, SR);
@@ -485,7 +492,8 @@ void face_flux(const Grid& g, const std::vector<real>& P, int recon, int d, int 
 
 // Fluxes along every direction on the faces the update and Flux-CT need:
 // x1 faces i in [0, n1] over j in [-1, n2], k in [-1, n3] (and cyclically).
-void compute_fluxes(const Grid& g, const std::vector<real>& P, std::vector<real> F[3]) {
+void compute_fluxes(const Grid& g, const std::vector<real>& P, std::vector<real> F[3],
+                    const std::vector<real>* phi = nullptr) {
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
   for (int d = 1; d <= 3; d++) {
     int lo[3] = {-1, -1, -1}, hi[3] = {n1, n2, n3};  // inclusive
@@ -495,7 +503,7 @@ void compute_fluxes(const Grid& g, const std::vector<real>& P, std::vector<real>
       for (int j = lo[1]; j <= hi[1]; j++)
         for (int i = lo[0]; i <= hi[0]; i++) {
           real f[NV];
-          face_flux(g, P, g.c.recon, d, i, j, k, f);
+          face_flux(g, P, g.c.recon, d, i, j, k, f, phi);
           for (int v = 0; v < NV; v++) V(F[d - 1], g, v, i, j, k) = f[v];
         }
   }
@@ -551,6 +559,184 @@ void flux_ct(const Grid& g, std::vector<real> F[3]) {
           V(F3, g, B3, i, j, k) = 0.0;
         }
       }
+}
+
+// ------------------------------------------------------- face-centred CT --
+// Face-centred constrained transport (Algorithm section: the scheme of Stone
+// & Gardiner, edge EMFs with or without upwinding).  The magnetic state is
+// the face field phi_d = sqrt(-g) B^d on the lower d-face of every zone; the
+// zone-centred B^d is the mean of the zone's two d-faces over sqrt(-g) at its
+// centre.  Edge EMFs, E3 = F^1(B^2) = -F^2(B^1) on x1-x2 edges and
+// cyclically (E1 = F^2(B^3), E2 = F^3(B^1)):
+//  * averaged: the mean of the four face values around the edge;
+//  * upwinded (Gardiner & Stone 2005): that mean plus, along each of the two
+//    in-plane directions, a quarter of (lower minus upper) EMF gradient
+//    across the edge, each gradient the difference of a face value and a
+//    zone-centre EMF (from the zone's prims) over half a zone, taken in the
+//    zone the mass flux through the adjoining face comes from (the mean of
+//    both where that flux is zero).  The sign makes the edge EMF equal the
+//    face EMF for flow that varies along one grid direction only.
+// Edges on the polar axis carry zero E1 and E3, as in Flux-CT.  Faces evolve
+// by Stokes' theorem: d phi_1/dt = dE3/dx2 - dE2/dx3, d phi_2/dt =
+// dE1/dx3 - dE3/dx1, d phi_3/dt = dE2/dx1 - dE1/dx2, so the face divergence
+// sum_d (phi_d(+) - phi_d(-))/dx_d keeps its value to roundoff.
+enum { CT_FLUX = 0, CT_FACE_AVG = 1, CT_FACE_GS = 2 };
+
+// Ghost faces, axis by axis like the zone ghosts.  Along a face array's own
+// axis (faces 0..n are evolved): periodic wraps by n, outflow copies the
+// boundary face, polar mirrors about the axis face with the sign flipped;
+// across it: the zone rules (periodic wrap, outflow copy, polar mirror
+// without flip).  Frozen ghosts keep their values.
+void fill_face_ghosts(const Grid& g, std::vector<real> phi[3]) {
+  for (int d = 0; d < 3; d++) {
+    for (int a = 0; a < 3; a++) {
+      const int n = g.n[a];
+      const int lo_bc = g.c.bc[2 * a], hi_bc = g.c.bc[2 * a + 1];
+      const bool normal = a == d;
+      const int last = normal ? n : n - 1;   // last valid index along a
+      for (int k = -NG; k < g.n[2] + NG; k++)
+        for (int j = -NG; j < g.n[1] + NG; j++)
+          for (int i = -NG; i < g.n[0] + NG; i++) {
+            int idx[3] = {i, j, k};
+            // passes over earlier axes cover their ghosts; later axes only their valid range
+            bool skip = false;
+            for (int b = a + 1; b < 3; b++) {
+              int lb = (b == d) ? g.n[b] : g.n[b] - 1;
+              if (idx[b] < 0 || idx[b] > lb) skip = true;
+            }
+            if (skip) continue;
+            int x = idx[a];
+            if (x >= 0 && x <= last) continue;
+            const int bc = x < 0 ? lo_bc : hi_bc;
+            int src = x;
+            real sgn = 1.0;
+            if (bc == BC_PERIODIC) {
+              src = normal ? (x < 0 ? x + n : x - n) : ((x % n) + n) % n;
+            } else if (bc == BC_OUTFLOW) {
+              src = x < 0 ? 0 : last;
+            } else if (bc == BC_POLAR) {
+              if (normal) {
+                src = x < 0 ? -x : 2 * n - x;
+                sgn = -1.0;
+              } else {
+                src = x < 0 ? -1 - x : 2 * n - 1 - x;
+              }
+            } else {
+              continue;  // frozen
+            }
+            int sidx[3] = {idx[0], idx[1], idx[2]};
+            sidx[a] = src;
+            phi[d][g.id(i, j, k)] = sgn * phi[d][g.id(sidx[0], sidx[1], sidx[2])];
+          }
+    }
+  }
+}
+
+// Edge EMFs at the lower corners of every zone (edges 0..n along each axis)
+// from face fluxes F (not Flux-CT corrected) and, for the upwinded scheme,
+// zone-centre EMFs from the prims P.
+void edge_emfs(const Grid& g, const std::vector<real>& P, const std::vector<real> F[3], int scheme,
+               std::vector<real> E[3]) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  for (int c = 0; c < 3; c++) E[c].assign(g.nz, 0.0);
+  // zone-centre EMFs over zones -1..n: ec[c] = F^a(B^b) with (a, b) cyclic before c
+  std::vector<real> ec[3];
+  if (scheme == CT_FACE_GS) {
+    for (int c = 0; c < 3; c++) ec[c].assign(g.nz, 0.0);
+#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+    for (int k = -1; k <= n3; k++)
+      for (int j = -1; j <= n2; j++)
+        for (int i = -1; i <= n1; i++) {
+          real p[NV];
+          for (int v = 0; v < NV; v++) p[v] = Vc(P, g, v, i, j, k);
+          const Geom& G = g.gC[g.id2(i, j)];
+          FluidState S;
+          fluid_state(p, G, S);
+          real f1[NV], f2[NV], f3[NV];
+          prim_to_flux(p, S, G, g.c.gam, 1, f1);
+          prim_to_flux(p, S, G, g.c.gam, 2, f2);
+          prim_to_flux(p, S, G, g.c.gam, 3, f3);
+          long q = g.id(i, j, k);
+          ec[2][q] = f1[B2];  // E3 = F^1(B^2)
+          ec[0][q] = f2[B3];  // E1 = F^2(B^3)
+          ec[1][q] = f3[B1];  // E2 = F^3(B^1)
+        }
+  }
+  auto up = [](real flux, real lower, real upper) -> real {
+    if (flux > 0.0) return lower;
+    if (flux < 0.0) return upper;
+    return 0.5 * (lower + upper);
+  };
+#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+  for (int k = 0; k <= n3; k++)
+    for (int j = 0; j <= n2; j++)
+      for (int i = 0; i <= n1; i++) {
+        const bool pole = (g.pole_lo && j == 0) || (g.pole_hi && j == n2);
+        const int x[3] = {i, j, k};
+        for (int c = 0; c < 3; c++) {
+          if (pole && c != 1) continue;  // E1 and E3 vanish on the axis
+          const int a = (c + 1) % 3, b = (c + 2) % 3;  // axes of the plane, cyclic
+          const int Bb = B1 + b, Ba = B1 + a;
+          auto at = [&](int da, int db, int* out) {
+            out[0] = x[0]; out[1] = x[1]; out[2] = x[2];
+            out[a] -= da; out[b] -= db;
+          };
+          int p00[3], p10[3], p01[3], p11[3];  // x, x - e_a, x - e_b, x - e_a - e_b
+          at(0, 0, p00); at(1, 0, p10); at(0, 1, p01); at(1, 1, p11);
+          auto ID = [&](const int* q) { return g.id(q[0], q[1], q[2]); };
+          // face values: on a-faces F^a(B^b), on b-faces -F^b(B^a)
+          const real ea0 = F[a][Bb * g.nz + ID(p00)], ea1 = F[a][Bb * g.nz + ID(p01)];
+          const real eb0 = -F[b][Ba * g.nz + ID(p00)], eb1 = -F[b][Ba * g.nz + ID(p10)];
+          real e = 0.25 * (((ea0 + ea1) + eb0) + eb1);
+          if (scheme == CT_FACE_GS) {
+            const std::vector<real>& C = ec[c];
+            // along b, at the edge's a-position: zones in column x (upper a) or x - e_a
+            const real fa0 = F[a][RHO * g.nz + ID(p00)], fa1 = F[a][RHO * g.nz + ID(p01)];
+            const real dbp = up(fa0, C[ID(p10)] - eb1, C[ID(p00)] - eb0);
+            const real dbm = up(fa1, eb1 - C[ID(p11)], eb0 - C[ID(p01)]);
+            // along a, at the edge's b-position: zones in row x (upper b) or x - e_b
+            const real fb0 = F[b][RHO * g.nz + ID(p00)], fb1 = F[b][RHO * g.nz + ID(p10)];
+            const real dap = up(fb0, C[ID(p01)] - ea1, C[ID(p00)] - ea0);
+            const real dam = up(fb1, ea1 - C[ID(p11)], ea0 - C[ID(p10)]);
+            e = e + 0.25 * (dbm - dbp) + 0.25 * (dam - dap);
+          }
+          E[c][g.id(i, j, k)] = e;
+        }
+      }
+}
+
+// Face update of one stage: phi_out = phi_base + h (Stokes' rate), over the
+// evolved faces (0..n along the face's axis, interior across it).
+void face_update(const Grid& g, const std::vector<real> E[3], const std::vector<real> base[3], real h,
+                 std::vector<real> out[3]) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  auto e = [&](int c, int i, int j, int k) { return E[c][g.id(i, j, k)]; };
+  for (int d = 0; d < 3; d++) out[d] = base[d];
+#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+  for (int k = 0; k <= n3; k++)
+    for (int j = 0; j <= n2; j++)
+      for (int i = 0; i <= n1; i++) {
+        long q = g.id(i, j, k);
+        if (j < n2 && k < n3) {
+          real r = (e(2, i, j + 1, k) - e(2, i, j, k)) / g.dx[1] - (e(1, i, j, k + 1) - e(1, i, j, k)) / g.dx[2];
+          out[0][q] = base[0][q] + h * r;
+        }
+        if (i < n1 && k < n3) {
+          real r = (e(0, i, j, k + 1) - e(0, i, j, k)) / g.dx[2] - (e(2, i + 1, j, k) - e(2, i, j, k)) / g.dx[0];
+          out[1][q] = base[1][q] + h * r;
+        }
+        if (i < n1 && j < n2) {
+          real r = (e(1, i + 1, j, k) - e(1, i, j, k)) / g.dx[0] - (e(0, i, j + 1, k) - e(0, i, j, k)) / g.dx[1];
+          out[2][q] = base[2][q] + h * r;
+        }
+      }
+}
+
+// Zone-centred conserved field of zone (i, j, k): the mean of its two faces.
+inline void cell_field(const Grid& g, const std::vector<real> phi[3], int i, int j, int k, real UB[3]) {
+  UB[0] = 0.5 * (phi[0][g.id(i, j, k)] + phi[0][g.id(i + 1, j, k)]);
+  UB[1] = 0.5 * (phi[1][g.id(i, j, k)] + phi[1][g.id(i, j + 1, k)]);
+  UB[2] = 0.5 * (phi[2][g.id(i, j, k)] + phi[2][g.id(i, j, k + 1)]);
 }
 
 // ------------------------------------------------------- source, update --
@@ -951,7 +1137,8 @@ RunStats g_stats;
 // add only when count is set.
 void update_pass(const Grid& g, const std::vector<real>& Pin, const std::vector<real> F[3], int stage,
                  real dt, std::vector<real>& Un, std::vector<real>& U1v, std::vector<real>& Pout,
-                 int* flags, std::vector<char>* mark, bool count) {
+                 int* flags, std::vector<char>* mark, bool count,
+                 const std::vector<real>* phi_new = nullptr) {
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
   long fails = 0, hits = 0, fluid = 0;
 #pragma omp parallel for schedule(static) num_threads(g.c.nthreads) reduction(+ : fails, hits, fluid)
@@ -967,12 +1154,18 @@ void update_pass(const Grid& g, const std::vector<real>& Pin, const std::vector<
           for (int v = 0; v < NV; v++) {
             Unew[v] = u0[v] + dt * L[v];
             V(Un, g, v, i, j, k) = u0[v];
-            V(U1v, g, v, i, j, k) = Unew[v];
           }
         } else {
           for (int v = 0; v < NV; v++)
             Unew[v] = 0.5 * (Vc(Un, g, v, i, j, k) + Vc(U1v, g, v, i, j, k)) + 0.5 * (dt * L[v]);
         }
+        if (phi_new) {  // face-centred CT: the zone's field is the mean of its new faces
+          real UB[3];
+          cell_field(g, phi_new, i, j, k, UB);
+          for (int d = 0; d < 3; d++) Unew[B1 + d] = UB[d];
+        }
+        if (stage == 0)
+          for (int v = 0; v < NV; v++) V(U1v, g, v, i, j, k) = Unew[v];
         for (int v = 0; v < NV; v++) guess[v] = p[v];
         int f = invert(g.c, g.gC[g.id2(i, j)], Unew, guess, pn);
         int fl = 0;
@@ -1024,7 +1217,12 @@ bool marked(const Grid& g, const std::vector<char>& mark, int i, int j, int k) {
 // face of a marked zone gets the local Lax-Friedrichs flux of donor-cell
 // states instead, Flux-CT is redone on the corrected fluxes and the stage is
 // taken again.  (Stages that mark nothing keep their first result.)
-long step(const Grid& g, std::vector<real>& P, real dt, int* flags) {
+//
+// With face-centred CT (phi not null: the face fields, advanced alongside)
+// each stage takes the edge EMFs from the fluxes, advances the faces
+// (phi1 = phin + dt R(Pn); phin+1 = (phin + phi1)/2 + dt R(P1)/2) and sets
+// every zone's conserved field to the mean of its new faces before U_to_P.
+long step(const Grid& g, std::vector<real>& P, real dt, int* flags, std::vector<real>* phi = nullptr) {
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
   std::vector<real> F[3], Fct[3];
   for (int d = 0; d < 3; d++) F[d].assign(NV * g.nz, 0.0);
@@ -1032,20 +1230,43 @@ long step(const Grid& g, std::vector<real>& P, real dt, int* flags) {
   std::vector<real> P1 = P;
   std::vector<char> mark;
   long fails0 = g_stats.fails;
+  std::vector<real> phi1[3], phiV[3], phiOut[3], E[3];
 
   for (int stage = 0; stage < 2; stage++) {
     std::vector<real>& Pin = stage == 0 ? P : P1;
+    std::vector<real>* phiIn = stage == 0 ? phi : phi1;
     fill_ghosts(g, Pin);
-    compute_fluxes(g, Pin, F);
+    if (phi) fill_face_ghosts(g, phiIn);
+    compute_fluxes(g, Pin, F, phi ? phiIn : nullptr);
     std::vector<real> Pout = Pin;
+    // the magnetic part of a stage from fluxes Fx: Flux-CT fluxes (in Fc), or
+    // new face fields (in phiOut) from the edge EMFs
+    auto magnetic = [&](std::vector<real> Fx[3], std::vector<real> Fc[3]) {
+      if (!phi) {
+        for (int d = 0; d < 3; d++) Fc[d] = Fx[d];
+        flux_ct(g, Fc);
+        return;
+      }
+      for (int d = 0; d < 3; d++) Fc[d] = Fx[d];
+      edge_emfs(g, Pin, Fx, g.c.ct, E);
+      if (stage == 0) {
+        face_update(g, E, phi, dt, phiOut);
+        for (int d = 0; d < 3; d++) {
+          phiV[d].resize(g.nz);
+          for (long q = 0; q < g.nz; q++) phiV[d][q] = 0.5 * (phi[d][q] + phiOut[d][q]);
+        }
+      } else {
+        face_update(g, E, phiV, 0.5 * dt, phiOut);
+      }
+    };
+    const std::vector<real>* pnew = phi ? phiOut : nullptr;
     if (!g.c.fofc) {
-      flux_ct(g, F);
-      update_pass(g, Pin, F, stage, dt, Un, U1v, Pout, flags, nullptr, true);
+      magnetic(F, Fct);
+      update_pass(g, Pin, Fct, stage, dt, Un, U1v, Pout, flags, nullptr, true, pnew);
     } else {
-      for (int d = 0; d < 3; d++) Fct[d] = F[d];
-      flux_ct(g, Fct);
+      magnetic(F, Fct);
       mark.assign(g.nz, 0);
-      update_pass(g, Pin, Fct, stage, dt, Un, U1v, Pout, flags, &mark, false);
+      update_pass(g, Pin, Fct, stage, dt, Un, U1v, Pout, flags, &mark, false, pnew);
       long nmark = 0;
       for (long z = 0; z < g.nz; z++) nmark += mark[z];
       if (nmark > 0) {
@@ -1060,17 +1281,24 @@ long step(const Grid& g, std::vector<real>& P, real dt, int* flags) {
               for (int i = lo[0]; i <= hi[0]; i++) {
                 if (!marked(g, mark, i, j, k) && !marked(g, mark, i - di, j - dj, k - dk)) continue;
                 real f[NV];
-                face_flux(g, Pin, RECON_DONOR, d, i, j, k, f);
+                face_flux(g, Pin, RECON_DONOR, d, i, j, k, f, phi ? phiIn : nullptr);
                 for (int v = 0; v < NV; v++) V(F[d - 1], g, v, i, j, k) = f[v];
               }
         }
-        flux_ct(g, F);
+        magnetic(F, Fct);
         Pout = Pin;
-        update_pass(g, Pin, F, stage, dt, Un, U1v, Pout, flags, nullptr, true);
+        update_pass(g, Pin, Fct, stage, dt, Un, U1v, Pout, flags, nullptr, true, pnew);
       }
     }
-    if (stage == 0) P1 = Pout;
-    else P = Pout;
+    if (stage == 0) {
+      P1 = Pout;
+      if (phi)
+        for (int d = 0; d < 3; d++) phi1[d] = phiOut[d];
+    } else {
+      P = Pout;
+      if (phi)
+        for (int d = 0; d < 3; d++) phi[d] = phiOut[d];
+    }
   }
   return g_stats.fails - fails0;
 }
@@ -1177,6 +1405,85 @@ long orc_run(const orc_cfg* c, double* prims, double dt, int nsteps, double* dts
   fill_ghosts(g, P);
   store(g, P, prims);
   return fails;
+}
+
+// Face-centred CT (cfg ct = 1 or 2): as orc_run, with the face fields
+// faces = double[3][padded] (sqrt(-g) B^d on the lower d-face of each zone)
+// advanced alongside; the interior zones' B prims are set from the faces
+// first.  On return the faces' ghosts are filled and the prims' B is the
+// faces' mean.
+long orc_run_face(const orc_cfg* c, double* prims, double* faces, double dt, int nsteps, double* dts,
+                  int* flags) {
+  Grid g(*c);
+  g_stats = RunStats{0, 0, 0, 0};
+  std::vector<real> P, phi[3];
+  load(g, prims, P);
+  for (int d = 0; d < 3; d++) {
+    phi[d].resize(g.nz);
+    for (long q = 0; q < g.nz; q++) phi[d][q] = faces[d * g.nz + q];
+  }
+  for (int k = 0; k < c->n3; k++)
+    for (int j = 0; j < c->n2; j++)
+      for (int i = 0; i < c->n1; i++) {
+        real UB[3];
+        cell_field(g, phi, i, j, k, UB);
+        for (int d = 0; d < 3; d++) V(P, g, B1 + d, i, j, k) = UB[d] / g.gC[g.id2(i, j)].gdet;
+      }
+  long fails = 0;
+  for (int s = 0; s < nsteps; s++) {
+    real h = dt;
+    if (dt <= 0.0) {
+      fill_ghosts(g, P);
+      h = estimate_dt(g, P);
+    }
+    if (dts) dts[s] = (double)h;
+    fails += step(g, P, h, flags, phi);
+  }
+  fill_ghosts(g, P);
+  fill_face_ghosts(g, phi);
+  store(g, P, prims);
+  for (int d = 0; d < 3; d++)
+    for (long q = 0; q < g.nz; q++) faces[d * g.nz + q] = (double)phi[d][q];
+  return fails;
+}
+
+// Edge EMFs (E1, E2, E3 at the lower corners of every zone, edges 0..n) of
+// the face-centred scheme cfg ct from the prims and faces of one state
+// (ghosts filled here); out = double[3][padded], other entries zero.
+void orc_edge_emfs(const orc_cfg* c, const double* prims, const double* faces, double* out) {
+  Grid g(*c);
+  std::vector<real> P, phi[3], F[3], E[3];
+  load(g, prims, P);
+  for (int d = 0; d < 3; d++) {
+    phi[d].resize(g.nz);
+    for (long q = 0; q < g.nz; q++) phi[d][q] = faces[d * g.nz + q];
+    F[d].assign(NV * g.nz, 0.0);
+  }
+  fill_ghosts(g, P);
+  fill_face_ghosts(g, phi);
+  compute_fluxes(g, P, F, phi);
+  edge_emfs(g, P, F, c->ct, E);
+  for (int d = 0; d < 3; d++)
+    for (long q = 0; q < g.nz; q++) out[d * g.nz + q] = (double)E[d][q];
+}
+
+// Face divergence sum_d (phi_d(+) - phi_d(-))/dx_d over interior zones:
+// maximum and mean of its magnitude.
+void orc_face_divb(const orc_cfg* c, const double* faces, double* out_max, double* out_mean) {
+  Grid g(*c);
+  double mx = 0.0, sm = 0.0;
+  auto f = [&](int d, int i, int j, int k) { return faces[d * g.nz + g.id(i, j, k)]; };
+  for (int k = 0; k < c->n3; k++)
+    for (int j = 0; j < c->n2; j++)
+      for (int i = 0; i < c->n1; i++) {
+        double dv = ((f(0, i + 1, j, k) - f(0, i, j, k)) / (double)g.dx[0] +
+                     (f(1, i, j + 1, k) - f(1, i, j, k)) / (double)g.dx[1]) +
+                    (f(2, i, j, k + 1) - f(2, i, j, k)) / (double)g.dx[2];
+        mx = std::max(mx, std::fabs(dv));
+        sm += std::fabs(dv);
+      }
+  *out_max = mx;
+  *out_mean = sm / ((double)c->n1 * c->n2 * c->n3);
 }
 
 // Counters of the last orc_run: failed inversions, zones floors acted on,

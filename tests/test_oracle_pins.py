@@ -815,3 +815,125 @@ def test_fofc_removes_failures_conserves_and_keeps_divb():
     assert np.all(np.abs(U1 - U0) <= 1e-13 * np.maximum(scale, scale.max() * 1e-3)), (U1 - U0) / scale
     mx, _ = oracle.divb(c, out)
     assert mx < 1e-13 * 0.07 / grid.dx[0]
+
+
+# ------------------------------------------------- face-centred constrained transport
+
+def _one_d_state(axis, n=16, seed=41):
+    """Flat periodic grid, prims varying smoothly along one axis only, field
+    divergence-free (constant along that axis); face fields equal to the
+    zone values (nothing varies across the faces)."""
+    rng = np.random.default_rng(seed)
+    dims = [4, 4, 1]
+    dims[axis] = n
+    g = GridSpec(*dims)
+    xs = g.centers()[axis]
+    P = np.zeros((8, dims[2] + 6, dims[1] + 6, dims[0] + 6))
+    shape = [1, 1, 1]
+    shape[2 - axis] = len(xs)
+    prof = lambda a, b: (a + b * np.sin(2 * np.pi * xs + rng.uniform(0, 6.3))).reshape(shape)
+    P[0] = prof(1.0, 0.3)
+    P[1] = prof(0.8, 0.2)
+    for v in (2, 3, 4, 6, 7):
+        P[v] = prof(0.0, 0.3)
+    P[5] = 0.7
+    # rotate so that the field component along `axis` is the constant one
+    order = [axis, (axis + 1) % 3, (axis + 2) % 3]
+    B = np.zeros((3,) + P.shape[1:])
+    B[order[0]] = P[5]
+    B[order[1]] = P[6]
+    B[order[2]] = P[7]
+    P[5:8] = B
+    return g, P, B.copy()
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_face_ct_upwinded_emf_is_the_face_emf_for_one_dimensional_flow(axis):
+    """The sign reading of the upwinded (Gardiner & Stone) edge EMF: for a
+    state that varies along one grid axis only, every edge EMF in the plane
+    of that axis equals the EMF of the face it lies on (the Riemann flux of
+    the transverse field), as a one-dimensional scheme's would; the plain
+    average of the four face values does not."""
+    g, P, F = _one_d_state(axis)
+    flux = oracle.fluxes(oracle.cfg(g, recon=RECON_MC), P, ct=False)
+    for ct, must_equal in ((oracle.CT_FACE_GS, True), (oracle.CT_FACE_AVG, False)):
+        c = oracle.cfg(g, recon=RECON_MC, ct=ct)
+        E = oracle.edge_emfs(c, P, F)
+        I = lambda a: a[3:-3, 3:-3, 3:-3]
+        if axis == 0:
+            # E3 on x1-x2 edges and E2 on x1-x3 edges: the x1-face EMFs F1(B2), -F1(B3)
+            pairs = [(I(E[2]), I(flux[0, 6])), (I(E[1]), -I(flux[0, 7]))]
+        else:
+            # E3 = -F2(B1) and E1 = F2(B3) on x2 faces
+            pairs = [(I(E[2]), -I(flux[1, 5])), (I(E[0]), I(flux[1, 7]))]
+        for e, fface in pairs:
+            err = np.abs(e - fface).max() / np.abs(fface).max()
+            if must_equal:
+                assert err < 1e-14, err
+            else:
+                assert err > 1e-3, err
+
+
+@pytest.mark.parametrize("ct", [1, 2])
+def test_face_ct_uniform_state_and_face_divergence(ct):
+    """A uniform magnetised flow is unchanged; the torus (3 steps) and the
+    blast with the first-order correction keep the face divergence at
+    roundoff."""
+    g = GridSpec(8, 8, 8)
+    P = np.zeros((8, 14, 14, 14))
+    P[:] = np.array([1.0, 0.5, 0.2, -0.1, 0.3, 0.4, 0.2, -0.3])[:, None, None, None]
+    F = P[5:8].copy()
+    out, Fo, fails, _ = oracle.run_face(oracle.cfg(g, ct=ct), P, F, -1, 2)
+    assert fails == 0
+    assert np.abs(interior(out) - interior(P)).max() < 1e-14
+    grid, P, info = fm_torus(24, 24, 8)
+    c = oracle.cfg(grid, gam=13 / 9, recon=RECON_WENO5, ct=ct)
+    out, Fo, _, _ = oracle.run_face(c, P, info["faces"], -1, 3)
+    mx, _ = oracle.face_divb(c, Fo)
+    assert mx < 1e-13 * np.abs(info["faces"]).max() / min(grid.dx)
+    from workloads import magnetised_blast
+    grid, P, Fb = magnetised_blast(48, faces=True)
+    c = oracle.cfg(grid, recon=RECON_MC, ct=ct, fofc=True)
+    out, Fo, _, _ = oracle.run_face(c, P, Fb, -1, 4)
+    assert oracle.last_stats()["fofc_zones"] > 0
+    mx, _ = oracle.face_divb(c, Fo)
+    assert mx < 1e-13 * 0.07 / grid.dx[0]
+
+
+@pytest.mark.parametrize("ct", [1, 2])
+def test_face_ct_conservation_on_periodic_grid(ct):
+    """Every conserved total, and the total face flux through each family of
+    faces, is kept to roundoff on a periodic grid."""
+    from workloads import linear_mode_faces
+    g, P, F, _, _ = linear_mode_faces("alfven", 16, ndim=2, amp=0.05)
+    c = oracle.cfg(g, recon=RECON_WENO5, ct=ct)
+    out, Fo, fails, _ = oracle.run_face(c, P, F, -1, 3)
+    assert fails == 0
+    P0 = oracle.run_face(c, P, F, 1e-30, 0)[0]      # zero steps: B from the faces
+    U0 = interior(oracle.prims_to_cons(c, P0)).sum(axis=(1, 2, 3))
+    U1 = interior(oracle.prims_to_cons(c, out)).sum(axis=(1, 2, 3))
+    scale = np.abs(interior(oracle.prims_to_cons(c, out))).sum(axis=(1, 2, 3)).max()
+    assert np.abs(U1 - U0).max() < 1e-13 * scale
+    fscale = np.abs(interior(F)).sum(axis=(1, 2, 3)).max()
+    for d in range(3):
+        a, b = interior(F[d][None])[0].sum(), interior(Fo[d][None])[0].sum()
+        assert abs(a - b) < 1e-13 * fscale
+
+
+@pytest.mark.parametrize("ct", [1, 2])
+def test_face_ct_linear_mode_convergence(ct):
+    """The paper's regression criterion with face-centred CT: the fast mode
+    (WENO5, 32 -> 64) converges with L1 slopes in [1.9, 2.1]."""
+    from workloads import linear_mode_faces
+    errs = []
+    for n in (32, 64):
+        g, P, F, exact, info = linear_mode_faces("fast", n, ndim=2)
+        c = oracle.cfg(g, recon=RECON_WENO5, ct=ct)
+        T = 2 * np.pi / info["omega"]
+        ns = int(np.ceil(T / oracle.estimate_dt(c, P)))
+        out, _, fails, _ = oracle.run_face(c, P, F, T / ns, ns)
+        assert fails == 0
+        Pe = exact(T)
+        errs.append([np.mean(np.abs(interior(out[v] - Pe[v]))) for v in range(8) if abs(info["r"][v]) > 0])
+    slope = np.log2(np.array(errs[0]) / np.array(errs[1]))
+    assert np.all((slope > 1.9) & (slope < 2.1)), slope

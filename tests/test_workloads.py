@@ -121,3 +121,23 @@ def test_magnetised_blast_set_up():
     assert (0.07 ** 2 / rho.min()) == pytest.approx(49.0)
     # symmetric under x -> -x and y -> -y
     assert np.array_equal(I[0], I[0][:, ::-1, :]) and np.array_equal(I[0], I[0][:, :, ::-1])
+
+
+def test_face_fields_of_the_workloads():
+    """Face fields for face-centred CT: zero face divergence, and (torus)
+    their zone means over sqrt(-g) are the zone-centred B of the prims."""
+    import oracle
+    from workloads import magnetised_blast, linear_mode_faces, torus_grid
+    grid, P, info = fm_torus(24, 24, 8)
+    F = info["faces"]
+    c = oracle.cfg(grid, gam=13 / 9, ct=2)
+    mx, _ = oracle.face_divb(c, F)
+    assert mx < 1e-14 * np.abs(F).max() / min(grid.dx)
+    P0 = oracle.run_face(c, P, F, 1e-30, 0)[0]
+    I0, I = interior(P0), interior(P)
+    assert np.abs(I0[5:7] - I[5:7]).max() < 1e-12 * np.abs(I[5:7]).max()
+    g, P, F, _, _ = linear_mode_faces("fast", 16, ndim=3)
+    mx, _ = oracle.face_divb(oracle.cfg(g, ct=2), F)
+    assert mx < 1e-12
+    g, P, F = magnetised_blast(24, faces=True)
+    assert np.all(F[0] == 0.07) and np.all(F[1:] == 0)

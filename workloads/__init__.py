@@ -13,7 +13,7 @@ x1 fastest, variables (rho, u, u~1, u~2, u~3, B1, B2, B3), ghost width g = 3.
 from .spec import (NG, NVAR, BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN,
                    METRIC_MINKOWSKI, METRIC_KERR_MKS, RECON_MC, RECON_WENO5,
                    GridSpec, padded_shape, interior)
-from .linear_modes import linear_mode, mode_eigensystem, MODES
+from .linear_modes import linear_mode, linear_mode_faces, mode_eigensystem, MODES
 from .torus import fm_torus, torus_grid
 from .packs import torus_pack
 from .bondi import bondi, michel_constants, michel_rho
@@ -22,7 +22,7 @@ from .blast import magnetised_blast, blast_grid
 __all__ = [
     "NG", "NVAR", "BC_PERIODIC", "BC_OUTFLOW", "BC_POLAR", "BC_FROZEN",
     "METRIC_MINKOWSKI", "METRIC_KERR_MKS", "RECON_MC", "RECON_WENO5",
-    "GridSpec", "padded_shape", "interior", "linear_mode", "mode_eigensystem",
+    "GridSpec", "padded_shape", "interior", "linear_mode", "linear_mode_faces", "mode_eigensystem",
     "MODES", "fm_torus", "torus_grid", "torus_pack", "bondi", "michel_constants", "michel_rho",
     "magnetised_blast", "blast_grid",
 ]

@@ -26,8 +26,10 @@ def blast_grid(n, n3=1, half=6.0):
 
 
 def magnetised_blast(n, n3=1, B0=0.07, gamma=4.0 / 3.0, r_in=0.8, r_out=1.0,
-                     rho_in=1e-2, p_in=1.0, rho_out=1e-4, p_out=3e-5, noise=0.0, seed=0):
-    """Grid and padded prims of the explosion."""
+                     rho_in=1e-2, p_in=1.0, rho_out=1e-4, p_out=3e-5, noise=0.0, seed=0,
+                     faces=False):
+    """Grid and padded prims of the explosion (and, with faces, the face
+    fields of face-centred constrained transport: B0 on every x1 face)."""
     grid = blast_grid(n, n3)
     x1, x2, _ = grid.centers()
     X, Y = np.meshgrid(x1, x2, indexing="xy")          # (n2+2g, n1+2g)
@@ -43,4 +45,8 @@ def magnetised_blast(n, n3=1, B0=0.07, gamma=4.0 / 3.0, r_in=0.8, r_out=1.0,
         rng = np.random.default_rng(seed)
         P[1] *= 1.0 + noise * rng.uniform(-1, 1, shape) * (r < r_in)[None]
     P[5] = B0
+    if faces:
+        Bf = np.zeros((3,) + shape)
+        Bf[0] = B0
+        return grid, P, Bf
     return grid, P

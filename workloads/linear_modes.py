@@ -19,6 +19,8 @@ section, ideal part) are
 and a plane wave exp(i(k.x - omega t)) solves (sum_d k_d A_d) X = omega A_0 X.
 """
 
+import math
+
 import numpy as np
 
 from .spec import GridSpec, NG, NVAR, BC_PERIODIC, METRIC_MINKOWSKI
@@ -134,3 +136,32 @@ def linear_mode(name, n, ndim=3, amp=1e-4, rho=1.0, u=1.0, B=(1.0, 0.0, 0.0),
         return P0[:, None, None, None] + amp * r[:, None, None, None] * c[None]
 
     return g, exact(0.0), exact, dict(speed=speed, omega=omega, r=r)
+
+
+def linear_mode_faces(name, n, ndim=3, amp=1e-4, rho=1.0, u=1.0, B=(1.0, 0.0, 0.0),
+                      gamma=4.0 / 3.0, kvec=(2 * np.pi, 2 * np.pi, 0.0)):
+    """linear_mode plus the face fields of face-centred constrained transport:
+    faces[d] = the average of B^d over the lower d-face of every padded zone
+    (flat space, so sqrt(-g) = 1), i.e. B0_d + amp r_Bd cos(k.x_face) times
+    sinc(k_e dx_e / 2) for the two other axes e.  Face averages of a
+    divergence-free field have zero discrete face divergence.  Returns
+    (grid, prims, faces, exact, info)."""
+    g, P, exact, info = linear_mode(name, n, ndim=ndim, amp=amp, rho=rho, u=u, B=B, gamma=gamma,
+                                    kvec=kvec)
+    r = info["r"]
+    x1, x2, x3 = g.centers()
+    dx = g.dx
+    centres = [x1, x2, x3]
+    faces = np.zeros((3,) + P.shape[1:])
+    for d in range(3):
+        xs = [c.copy() for c in centres]
+        xs[d] = xs[d] - 0.5 * dx[d]
+        X3, X2, X1 = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+        fac = 1.0
+        for e in range(3):
+            if e != d:
+                h = 0.5 * kvec[e] * dx[e]
+                fac *= math.sin(h) / h if h != 0.0 else 1.0
+        phase = kvec[0] * X1 + kvec[1] * X2 + kvec[2] * X3
+        faces[d] = B[d] + amp * r[5 + d] * fac * np.cos(phase)
+    return g, P, faces, exact, info

@@ -214,6 +214,10 @@ def fm_torus(n1, n2, n3, a=0.9375, hslope=0.3, rin=6.0, rmax=12.0,
         A = np.maximum(rhoc - 0.2, 0.0)
         B1 = (A[1:, :-1] + A[1:, 1:] - A[:-1, :-1] - A[:-1, 1:]) / (2.0 * d2 * gdet)
         B2 = -(A[:-1, 1:] + A[1:, 1:] - A[:-1, :-1] - A[1:, :-1]) / (2.0 * d1 * gdet)
+        # face fields sqrt(-g) B^d on the lower faces (the zone B above is
+        # their mean over sqrt(-g)): the corner differences of A_phi
+        phi1 = (A[1:, :-1] - A[:-1, :-1]) / d2
+        phi2 = -(A[:-1, 1:] - A[:-1, :-1]) / d1
         P[5] = B1[None]
         P[6] = B2[None]
         gc = np.broadcast_to(gcov[:, :, None], (4, 4) + shape3)
@@ -226,6 +230,11 @@ def fm_torus(n1, n2, n3, a=0.9375, hslope=0.3, rin=6.0, rmax=12.0,
         beta_min_now = np.min(2.0 * pi_[m] / bi[m])
         f = math.sqrt(beta_min_now / beta_min)
         P[5:8] *= f
+        info_faces = np.zeros((3,) + shape3)
+        info_faces[0] = (phi1 * f)[None]
+        info_faces[1] = (phi2 * f)[None]
+    else:
+        info_faces = np.zeros((3,) + shape3)
 
-    info = dict(ell=ell, rho_max_raw=rho_max, gamma=gamma, seed=seed)
+    info = dict(ell=ell, rho_max_raw=rho_max, gamma=gamma, seed=seed, faces=info_faces)
     return grid, P, info
