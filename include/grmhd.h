@@ -46,6 +46,7 @@ enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KERR_MKS = 1 };
 enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_DONOR = 2 };
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1 };
+enum { GRMHD_CT_FLUX = 0, GRMHD_CT_FACE_AVG = 1, GRMHD_CT_FACE_GS = 2 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2,
        GRMHD_BC_FROZEN = 3 };
 
@@ -105,6 +106,18 @@ typedef struct {
                          donor-cell states, Flux-CT and the update are
                          redone (only when some zone was marked).  Single
                          grids only (packs and the VJP reject it). */
+  int ct;             /* GRMHD_CT_*: magnetic-field transport.  FLUX: Flux-CT
+                         (Toth 2000; B lives in the zone prims).  FACE_AVG /
+                         FACE_GS: face-centred constrained transport (the
+                         Stone & Gardiner scheme the Algorithm section names),
+                         the state's field being phi_d = sqrt(-g) B^d on the
+                         lower d-face of every zone (grmhd_load_faces), the
+                         zone B its faces' mean; edge EMFs are the average
+                         of the four face EMFs (AVG) or that average with
+                         Gardiner & Stone (2005) upwinded gradient terms
+                         from zone-centre EMFs, chosen by the sign of the
+                         mass flux (GS).  The face divergence is kept to
+                         roundoff.  Single grids only. */
 } grmhd_params;
 
 /* Bytes of device workspace a context with this grid and parameters needs. */
@@ -118,8 +131,23 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
                  const grmhd_params* params, void* d_workspace, size_t ws_bytes,
                  void* hip_stream);
 
-/* Copy padded prims (device, layout above) into the context's state. */
+/* Copy padded prims (device, layout above) into the context's state.  With
+ * face-centred CT and faces loaded, the interior zones' B is then set to
+ * their faces' mean. */
 int grmhd_load_prims(grmhd_ctx* ctx, const double* d_prims);
+
+/* Face-centred CT only (E_STATE otherwise).  Face fields: float64
+ * [3][n3+6][n2+6][n1+6] (device), component d holding sqrt(-g) B^d on the
+ * lower d-face of every padded zone; ghost faces are refilled from the
+ * boundary conditions before use (frozen ghosts are kept).  load copies
+ * them into the state and sets the interior zones' B prims to the faces'
+ * mean (steps return E_STATE until faces are loaded); get copies the
+ * state's faces out (ghosts filled); face_divb reduces the face divergence
+ * sum_d (phi_d(+) - phi_d(-))/dx_d over interior zones (max and mean of its
+ * magnitude; synchronises). */
+int grmhd_load_faces(grmhd_ctx* ctx, const double* d_faces);
+int grmhd_get_faces(grmhd_ctx* ctx, double* d_faces);
+int grmhd_face_divb(grmhd_ctx* ctx, double* max_out, double* mean_out);
 
 /* One SSPRK2 step of size dt: U1 = Un + dt L(Pn), P1 = U_to_P(U1; Pn);
  * Un+1 = (Un + U1)/2 + dt L(P1)/2, Pn+1 = U_to_P(Un+1; P1).  Ghosts are
@@ -191,9 +219,9 @@ int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
  * max() branches by the branch taken.  Scratch comes from d_vjp_ws (device,
  * 256-byte aligned, >= grmhd_vjp_workspace_bytes()).  Neither the context's
  * state nor its failure count changes.  Synchronises.  E_STATE for the mixed
- * precision path, floors, the first-order flux correction or donor-cell
- * reconstruction (the adjoint covers the plain high-order step; the
- * workspace size is then 0). */
+ * precision path, floors, the first-order flux correction, donor-cell
+ * reconstruction or face-centred CT (the adjoint covers the plain
+ * high-order Flux-CT step; the workspace size is then 0). */
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params);
 int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const double* d_gprims_out,
                    double* d_gprims_in, double* g_gamma, void* d_vjp_ws, size_t vjp_ws_bytes);
@@ -209,8 +237,8 @@ int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const do
  * (0, 0, 0): runs of 256 consecutive positions of each box in x1-fastest
  * order, the default) only change speed.  Errors as for single contexts; E_ARG for blocks outside the
  * global grid, a non-FP64 precision, floors, the first-order flux
- * correction or donor-cell reconstruction (packs advance the plain
- * high-order step). */
+ * correction, donor-cell reconstruction or face-centred CT (packs advance
+ * the plain high-order Flux-CT step). */
 typedef struct grmhd_pack grmhd_pack;
 size_t grmhd_pack_workspace_bytes(int nblocks, const int* n);
 int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* offsets_ijk,
@@ -238,9 +266,11 @@ int grmhd_set_schedule(grmhd_ctx* ctx, int kg_flux, int kg_update);
  * event in its own dispatch (hipExtLaunchKernel), so no marker packets are
  * added between kernels.  Classes: 0 ghost fill, 1 face fluxes (x1, x2 and
  * x3 faces in one launch), 2 EMFs, 3 stage-1 update, 4 stage-2 update, 5 dt
- * reduction, 6 the flux correction's donor-cell face fix, 7 floors.  The
- * report sums elapsed milliseconds and counts launches per class into
- * arrays of nclass >= 8 entries.  Both synchronise the stream.
+ * reduction, 6 the flux correction's donor-cell face fix, 7 floors, 8 the
+ * face update of face-centred CT (its ghost faces count as 0, its zone-centre
+ * and edge EMFs as 2).  The report sums elapsed milliseconds and counts
+ * launches per class into arrays of nclass >= 9 entries.  Both synchronise
+ * the stream.
  * For measurement; the step itself is unchanged. */
 int grmhd_timing(grmhd_ctx* ctx, int class_mask);
 int grmhd_timing_report(grmhd_ctx* ctx, double* total_ms, long long* launches, int nclass);

@@ -575,7 +575,11 @@ void flux_ct(const Grid& g, std::vector<real> F[3]) {
 //    zone-centre EMF (from the zone's prims) over half a zone, taken in the
 //    zone the mass flux through the adjoining face comes from (the mean of
 //    both where that flux is zero).  The sign makes the edge EMF equal the
-//    face EMF for flow that varies along one grid direction only.
+//    face EMF for flow that varies along one grid direction only.  A face
+//    mass flux no larger than 1e-10 of the two zones' mass-current scale,
+//    sqrt(-g) rho (|u^t| + sum_d |u^d|) each, counts as zero: its sign
+//    would be roundoff (flow along or symmetric about the face, e.g. gas at
+//    rest in theta, or the torus's equatorial plane).
 // Edges on the polar axis carry zero E1 and E3, as in Flux-CT.  Faces evolve
 // by Stokes' theorem: d phi_1/dt = dE3/dx2 - dE2/dx3, d phi_2/dt =
 // dE1/dx3 - dE3/dx1, d phi_3/dt = dE2/dx1 - dE1/dx2, so the face divergence
@@ -583,7 +587,7 @@ void flux_ct(const Grid& g, std::vector<real> F[3]) {
 enum { CT_FLUX = 0, CT_FACE_AVG = 1, CT_FACE_GS = 2 };
 
 // Ghost faces, axis by axis like the zone ghosts.  Along a face array's own
-// axis (faces 0..n are evolved): periodic wraps by n, outflow copies the
+// axis (faces 0..n are evolved): periodic wraps modulo n, outflow copies the
 // boundary face, polar mirrors about the axis face with the sign flipped;
 // across it: the zone rules (periodic wrap, outflow copy, polar mirror
 // without flip).  Frozen ghosts keep their values.
@@ -611,7 +615,7 @@ void fill_face_ghosts(const Grid& g, std::vector<real> phi[3]) {
             int src = x;
             real sgn = 1.0;
             if (bc == BC_PERIODIC) {
-              src = normal ? (x < 0 ? x + n : x - n) : ((x % n) + n) % n;
+              src = ((x % n) + n) % n;  // faces n and 0 coincide
             } else if (bc == BC_OUTFLOW) {
               src = x < 0 ? 0 : last;
             } else if (bc == BC_POLAR) {
@@ -640,9 +644,10 @@ void edge_emfs(const Grid& g, const std::vector<real>& P, const std::vector<real
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
   for (int c = 0; c < 3; c++) E[c].assign(g.nz, 0.0);
   // zone-centre EMFs over zones -1..n: ec[c] = F^a(B^b) with (a, b) cyclic before c
-  std::vector<real> ec[3];
+  std::vector<real> ec[3], cs;  // zone-centre EMFs and mass-current scale
   if (scheme == CT_FACE_GS) {
     for (int c = 0; c < 3; c++) ec[c].assign(g.nz, 0.0);
+    cs.assign(g.nz, 0.0);
 #pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
     for (int k = -1; k <= n3; k++)
       for (int j = -1; j <= n2; j++)
@@ -652,7 +657,8 @@ void edge_emfs(const Grid& g, const std::vector<real>& P, const std::vector<real
           const Geom& G = g.gC[g.id2(i, j)];
           FluidState S;
           fluid_state(p, G, S);
-          real f1[NV], f2[NV], f3[NV];
+          real f0[NV], f1[NV], f2[NV], f3[NV];
+          prim_to_flux(p, S, G, g.c.gam, 0, f0);
           prim_to_flux(p, S, G, g.c.gam, 1, f1);
           prim_to_flux(p, S, G, g.c.gam, 2, f2);
           prim_to_flux(p, S, G, g.c.gam, 3, f3);
@@ -660,12 +666,13 @@ void edge_emfs(const Grid& g, const std::vector<real>& P, const std::vector<real
           ec[2][q] = f1[B2];  // E3 = F^1(B^2)
           ec[0][q] = f2[B3];  // E1 = F^2(B^3)
           ec[1][q] = f3[B1];  // E2 = F^3(B^1)
+          cs[q] = ((fabs(f0[RHO]) + fabs(f1[RHO])) + fabs(f2[RHO])) + fabs(f3[RHO]);
         }
   }
-  auto up = [](real flux, real lower, real upper) -> real {
-    if (flux > 0.0) return lower;
-    if (flux < 0.0) return upper;
-    return 0.5 * (lower + upper);
+  // upwind choice by the face mass flux, zero within 1e-10 of its zones' scale
+  auto up = [](real flux, real scale, real lower, real upper) -> real {
+    if (fabs(flux) <= 1e-10 * scale) return 0.5 * (lower + upper);
+    return flux > 0.0 ? lower : upper;
   };
 #pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
   for (int k = 0; k <= n3; k++)
@@ -692,12 +699,14 @@ void edge_emfs(const Grid& g, const std::vector<real>& P, const std::vector<real
             const std::vector<real>& C = ec[c];
             // along b, at the edge's a-position: zones in column x (upper a) or x - e_a
             const real fa0 = F[a][RHO * g.nz + ID(p00)], fa1 = F[a][RHO * g.nz + ID(p01)];
-            const real dbp = up(fa0, C[ID(p10)] - eb1, C[ID(p00)] - eb0);
-            const real dbm = up(fa1, eb1 - C[ID(p11)], eb0 - C[ID(p01)]);
+            const real sa0 = cs[ID(p10)] + cs[ID(p00)], sa1 = cs[ID(p11)] + cs[ID(p01)];
+            const real dbp = up(fa0, sa0, C[ID(p10)] - eb1, C[ID(p00)] - eb0);
+            const real dbm = up(fa1, sa1, eb1 - C[ID(p11)], eb0 - C[ID(p01)]);
             // along a, at the edge's b-position: zones in row x (upper b) or x - e_b
             const real fb0 = F[b][RHO * g.nz + ID(p00)], fb1 = F[b][RHO * g.nz + ID(p10)];
-            const real dap = up(fb0, C[ID(p01)] - ea1, C[ID(p00)] - ea0);
-            const real dam = up(fb1, ea1 - C[ID(p11)], ea0 - C[ID(p10)]);
+            const real sb0 = cs[ID(p01)] + cs[ID(p00)], sb1 = cs[ID(p11)] + cs[ID(p10)];
+            const real dap = up(fb0, sb0, C[ID(p01)] - ea1, C[ID(p00)] - ea0);
+            const real dam = up(fb1, sb1, ea1 - C[ID(p11)], ea0 - C[ID(p10)]);
             e = e + 0.25 * (dbm - dbp) + 0.25 * (dam - dap);
           }
           E[c][g.id(i, j, k)] = e;

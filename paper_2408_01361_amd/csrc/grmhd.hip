@@ -57,6 +57,7 @@ struct Dev {
   int maxit;
   int inverter;       // GRMHD_INV_*
   double vmax2;       // 1 - 1/W_max^2, the Kastaun recovery's speed cap
+  int ct;             // GRMHD_CT_*: Flux-CT, or face-centred CT (averaged / upwinded EMFs)
   int floors;         // floors and ceilings after every inversion of a stage
   double rho_min_geom, u_min_geom, bsq_over_rho_max, bsq_over_u_max, u_over_rho_max, gamma_max;
   SpaceTime st;
@@ -336,10 +337,12 @@ __device__ __forceinline__ bool pole_face(const Dev& g, int j) {
 
 // Local Lax-Friedrichs flux through the lower d-face of zone (i, j, k); pole
 // faces get zero flux.  FT is the stored type.
+// With face fields (face-centred CT, phi not null: sqrt(-g) B^D on the lower
+// D-faces), the normal field of both states is phi / sqrt(-g) at the face.
 template <int D, int RECON, typename R, typename FT>
 __device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict__ P,
                                           const double* __restrict__ tab, FT* __restrict__ F, int i,
-                                          int j, int k) {
+                                          int j, int k, const double* __restrict__ phi = nullptr) {
   long c = zid(g, i, j, k);
   if (pole_face<D>(g, j)) {
 #pragma unroll
@@ -349,7 +352,13 @@ __device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict
   const long s = D == 1 ? 1 : (D == 2 ? (long)g.s1 : g.plane);
   R qL[NVAR], qR[NVAR];
   recon_pair<RECON, R>(P, g.nz, c, s, (R)g.weno_eps, qL, qR);
-  face_llf<D, R, FT>(g, qL, qR, tab, pid(g, i, j), F, c);
+  const long q2 = pid(g, i, j);
+  if (phi) {
+    const R bn = (R)(phi[c] / tab[G_DET * g.plane + q2]);
+    qL[B1 + D - 1] = bn;
+    qR[B1 + D - 1] = bn;
+  }
+  face_llf<D, R, FT>(g, qL, qR, tab, q2, F, c);
 }
 
 #ifndef FLUX_WAVES
@@ -359,20 +368,24 @@ __device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict
 // All three face directions in one launch: workgroups [0, nb1) take x1
 // faces, [nb1, nb1 + nb2) x2 faces, the rest x3 faces (nb1 and nb2 are
 // multiples of 8, so each part keeps the XCD-aware order of its schedule).
-template <int RECON, typename R, typename FT>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FLUX_WAVES, 8)))
+template <int RECON, typename R, typename FT, bool FACE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FACE ? 3 : FLUX_WAVES, 8)))
 k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsigned nb3,
            const double* __restrict__ P, const double* __restrict__ tabF1,
            const double* __restrict__ tabF2, const double* __restrict__ tabC, FT* __restrict__ F1,
-           FT* __restrict__ F2, FT* __restrict__ F3) {
+           FT* __restrict__ F2, FT* __restrict__ F3, const double* __restrict__ ph1,
+           const double* __restrict__ ph2, const double* __restrict__ ph3) {
   const unsigned b = blockIdx.x;
   int i, j, k;
   if (b < nb1) {
-    if (sched_index(b1, b, nb1, i, j, k)) flux_face<1, RECON, R, FT>(g, P, tabF1, F1, i, j, k);
+    if (sched_index(b1, b, nb1, i, j, k))
+      flux_face<1, RECON, R, FT>(g, P, tabF1, F1, i, j, k, FACE ? ph1 : nullptr);
   } else if (b < nb1 + nb2) {
-    if (sched_index(b2, b - nb1, nb2, i, j, k)) flux_face<2, RECON, R, FT>(g, P, tabF2, F2, i, j, k);
+    if (sched_index(b2, b - nb1, nb2, i, j, k))
+      flux_face<2, RECON, R, FT>(g, P, tabF2, F2, i, j, k, FACE ? ph2 : nullptr);
   } else {
-    if (sched_index(b3, b - nb1 - nb2, nb3, i, j, k)) flux_face<3, RECON, R, FT>(g, P, tabC, F3, i, j, k);
+    if (sched_index(b3, b - nb1 - nb2, nb3, i, j, k))
+      flux_face<3, RECON, R, FT>(g, P, tabC, F3, i, j, k, FACE ? ph3 : nullptr);
   }
 }
 
@@ -441,7 +454,10 @@ __global__ void __launch_bounds__(BLOCK) k_fofc_flux(Dev g, Box b1, Box b2, Box 
                                                      const double* __restrict__ tabC, FT* __restrict__ F1,
                                                      FT* __restrict__ F2, FT* __restrict__ F3,
                                                      const unsigned char* __restrict__ mark,
-                                                     const unsigned long long* gate) {
+                                                     const unsigned long long* gate,
+                                                     const double* __restrict__ ph1,
+                                                     const double* __restrict__ ph2,
+                                                     const double* __restrict__ ph3) {
   if (*gate == 0) return;
   long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long c1 = b1.count(), c2 = b2.count();
@@ -449,16 +465,223 @@ __global__ void __launch_bounds__(BLOCK) k_fofc_flux(Dev g, Box b1, Box b2, Box 
   if (t < c1) {
     box_index(b1, t, i, j, k);
     if (marked(g, mark, i, j, k) || marked(g, mark, i - 1, j, k))
-      flux_face<1, GRMHD_RECON_DONOR, R, FT>(g, P, tabF1, F1, i, j, k);
+      flux_face<1, GRMHD_RECON_DONOR, R, FT>(g, P, tabF1, F1, i, j, k, ph1);
   } else if (t < c1 + c2) {
     box_index(b2, t - c1, i, j, k);
     if (marked(g, mark, i, j, k) || marked(g, mark, i, j - 1, k))
-      flux_face<2, GRMHD_RECON_DONOR, R, FT>(g, P, tabF2, F2, i, j, k);
+      flux_face<2, GRMHD_RECON_DONOR, R, FT>(g, P, tabF2, F2, i, j, k, ph2);
   } else {
     if (!box_index(b3, t - c1 - c2, i, j, k)) return;
     if (marked(g, mark, i, j, k) || marked(g, mark, i, j, k - 1))
-      flux_face<3, GRMHD_RECON_DONOR, R, FT>(g, P, tabC, F3, i, j, k);
+      flux_face<3, GRMHD_RECON_DONOR, R, FT>(g, P, tabC, F3, i, j, k, ph3);
   }
+}
+
+// ------------------------------------------------------- face-centred CT --
+// Face-centred constrained transport (Algorithm section: the scheme of Stone
+// & Gardiner; edge EMFs with or without upwinding).  The magnetic state is
+// phi_d = sqrt(-g) B^d on the lower d-face of every zone; a zone's field is
+// the mean of its two faces.  Edge EMFs E3 = F^1(B^2) = -F^2(B^1) on x1-x2
+// edges and cyclically: the averaged scheme is the Flux-CT average of the
+// four face values (k_emf); the upwinded one (Gardiner & Stone 2005) adds,
+// along each in-plane direction, a quarter of (lower minus upper) gradient
+// across the edge, each the difference of a face value and a zone-centre EMF
+// taken in the zone the mass flux through the adjoining face comes from (the
+// mean of both zones where it is zero), so that flow along one grid
+// direction gets its face EMF.  A face mass flux within 1e-10 (FP64; 1e-5
+// for the FP32 fluxes) of its two zones' mass-current scale, sqrt(-g) rho
+// (|u^t| + sum_d |u^d|) each, counts as zero: its sign would be roundoff.
+// Faces evolve by Stokes' theorem (face divergence kept to roundoff).
+
+// Ghost faces: the per-axis maps composed (equal to axis-by-axis passes).
+// Along a face array's own axis (faces 0..n evolve): periodic wraps modulo n,
+// outflow copies the boundary face, polar mirrors about the axis face with
+// the sign flipped; across it the zone maps (polar mirror without flip).
+// Frozen ghosts keep their values.  One thread per padded position of each
+// of the three arrays; interior positions return at once.
+__device__ __forceinline__ void face_map(int x, int n, bool normal, int bc_lo, int bc_hi, int& src,
+                                         bool& flip) {
+  const int last = normal ? n : n - 1;
+  src = x;
+  if (x >= 0 && x <= last) return;
+  const int bc = x < 0 ? bc_lo : bc_hi;
+  if (bc == GRMHD_BC_PERIODIC) {
+    src = ((x % n) + n) % n;  // faces n and 0 coincide
+  } else if (bc == GRMHD_BC_OUTFLOW) {
+    src = x < 0 ? 0 : last;
+  } else if (bc == GRMHD_BC_POLAR) {
+    if (normal) {
+      src = x < 0 ? -x : 2 * n - x;
+      flip = !flip;
+    } else {
+      src = x < 0 ? -1 - x : 2 * n - 1 - x;
+    }
+  }  // frozen: the position keeps its own value
+}
+
+__global__ void __launch_bounds__(BLOCK) k_bc_faces(Dev g, double* __restrict__ ph1, double* __restrict__ ph2,
+                                                    double* __restrict__ ph3) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= 3 * g.nz) return;
+  const int d = (int)(t / g.nz);
+  const long q = t - d * g.nz;
+  const int i = (int)(q % g.s1) - NG, j = (int)((q / g.s1) % g.s2) - NG, k = (int)(q / g.plane) - NG;
+  const int idx[3] = {i, j, k}, n[3] = {g.n1, g.n2, g.n3};
+  int src[3];
+  bool flip = false;
+#pragma unroll
+  for (int a = 0; a < 3; a++) face_map(idx[a], n[a], a == d, g.bc[2 * a], g.bc[2 * a + 1], src[a], flip);
+  if (src[0] == i && src[1] == j && src[2] == k) return;  // interior, or frozen
+  double* ph = d == 0 ? ph1 : (d == 1 ? ph2 : ph3);
+  const double x = ph[zid(g, src[0], src[1], src[2])];
+  ph[q] = flip ? -x : x;
+}
+
+// Zone-centre EMFs (E1, E2, E3) = (F^2(B^3), F^3(B^1), F^1(B^2)) and the
+// mass-current scale |U(rho)| + sum_d |F^d(rho)| from the zone prims, over
+// zones -1..n (the upwinded edge EMFs read them).
+template <typename R, typename FT>
+__global__ void __launch_bounds__(BLOCK) k_cell_emf(Dev g, Box box, const double* __restrict__ P,
+                                                    const double* __restrict__ tabC, FT* __restrict__ C1,
+                                                    FT* __restrict__ C2, FT* __restrict__ C3,
+                                                    FT* __restrict__ S) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  const long c = zid(g, i, j, k);
+  R p[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) p[v] = (R)P[v * g.nz + c];
+  PointMetric<R> m;
+  load_metric<R>(tabC, g.plane, pid(g, i, j), m);
+  Fluid<R> f;
+  fluid_state(p, m, f);
+  R F[NVAR];
+  prim_to_flux(p, f, m, (R)g.gam, 0, F);
+  R sc = fabs(F[RHO]);
+  prim_to_flux(p, f, m, (R)g.gam, 1, F);
+  C3[c] = (FT)F[B2];
+  sc = sc + fabs(F[RHO]);
+  prim_to_flux(p, f, m, (R)g.gam, 2, F);
+  C1[c] = (FT)F[B3];
+  sc = sc + fabs(F[RHO]);
+  prim_to_flux(p, f, m, (R)g.gam, 3, F);
+  C2[c] = (FT)F[B1];
+  sc = sc + fabs(F[RHO]);
+  S[c] = (FT)sc;
+}
+
+// Upwinded (Gardiner & Stone) edge EMFs at the lower corner of zone (i, j,
+// k), edges 0..n; gate/zero as in k_emf.  Same operation order as the CPU
+// reference of the scheme.
+template <typename FT>
+__global__ void __launch_bounds__(BLOCK) k_emf_gs(Dev g, Sched box, const FT* __restrict__ F1,
+                                                  const FT* __restrict__ F2, const FT* __restrict__ F3,
+                                                  const FT* __restrict__ C1, const FT* __restrict__ C2,
+                                                  const FT* __restrict__ C3, const FT* __restrict__ S,
+                                                  FT* __restrict__ E1,
+                                                  FT* __restrict__ E2, FT* __restrict__ E3,
+                                                  const unsigned long long* gate, unsigned long long* zero) {
+#pragma clang fp contract(off)
+  if (gate && *gate == 0) return;
+  if (zero && blockIdx.x == 0 && threadIdx.x == 0) *zero = 0;
+  int i, j, k;
+  if (!sched_index(box, blockIdx.x, gridDim.x, i, j, k)) return;
+  const long c = zid(g, i, j, k), nz = g.nz;
+  const long st[3] = {1, g.s1, g.plane};
+  const bool pole = (g.pole_lo && j == 0) || (g.pole_hi && j == g.n2);
+  const FT* Fd[3] = {F1, F2, F3};
+  const FT* Cd[3] = {C1, C2, C3};
+  FT* Ed[3] = {E1, E2, E3};
+  const FT tiny = sizeof(FT) == 8 ? (FT)1e-10 : (FT)1e-5;
+  auto up = [&](FT flux, FT scale, FT lower, FT upper) -> FT {
+    if (fabs(flux) <= tiny * scale) return (FT)0.5 * (lower + upper);
+    return flux > (FT)0 ? lower : upper;
+  };
+#pragma unroll
+  for (int e = 0; e < 3; e++) {
+    if (pole && e != 1) {
+      Ed[e][c] = (FT)0;
+      continue;
+    }
+    const int a = (e + 1) % 3, b = (e + 2) % 3;  // axes of the edge's plane, cyclic
+    const FT* Fa = Fd[a];
+    const FT* Fb = Fd[b];
+    const FT* C = Cd[e];
+    const long sa = st[a], sb = st[b];
+    const long p00 = c, p10 = c - sa, p01 = c - sb, p11 = c - sa - sb;
+    const FT ea0 = Fa[(B1 + b) * nz + p00], ea1 = Fa[(B1 + b) * nz + p01];
+    const FT eb0 = -Fb[(B1 + a) * nz + p00], eb1 = -Fb[(B1 + a) * nz + p10];
+    FT ed = (FT)0.25 * (((ea0 + ea1) + eb0) + eb1);
+    const FT fa0 = Fa[RHO * nz + p00], fa1 = Fa[RHO * nz + p01];
+    const FT sa0 = S[p10] + S[p00], sa1 = S[p11] + S[p01];
+    const FT dbp = up(fa0, sa0, C[p10] - eb1, C[p00] - eb0);
+    const FT dbm = up(fa1, sa1, eb1 - C[p11], eb0 - C[p01]);
+    const FT fb0 = Fb[RHO * nz + p00], fb1 = Fb[RHO * nz + p10];
+    const FT sb0 = S[p01] + S[p00], sb1 = S[p11] + S[p10];
+    const FT dap = up(fb0, sb0, C[p01] - ea1, C[p00] - ea0);
+    const FT dam = up(fb1, sb1, ea1 - C[p11], ea0 - C[p10]);
+    ed = ed + (FT)0.25 * (dbm - dbp) + (FT)0.25 * (dam - dap);
+    Ed[e][c] = ed;
+  }
+}
+
+// Face update of one stage over the evolved faces (0..n along a face's
+// axis, interior across): stage 1 phi1 = phin + dt R, V = (phin + phi1)/2;
+// stage 2 phin+1 = V + (dt/2) R, with R the Stokes rate
+//   R1 = dE3/dx2 - dE2/dx3, R2 = dE1/dx3 - dE3/dx1, R3 = dE2/dx1 - dE1/dx2.
+// gate as in k_update's final pass.
+template <int STAGE, typename FT>
+__global__ void __launch_bounds__(BLOCK) k_face_update(Dev g, Box box, const FT* __restrict__ E1,
+                                                       const FT* __restrict__ E2, const FT* __restrict__ E3,
+                                                       const double* __restrict__ b1, const double* __restrict__ b2,
+                                                       const double* __restrict__ b3, double* __restrict__ o1,
+                                                       double* __restrict__ o2, double* __restrict__ o3,
+                                                       double* __restrict__ v1, double* __restrict__ v2,
+                                                       double* __restrict__ v3, double dt,
+                                                       const double* __restrict__ dt_dev,
+                                                       const unsigned long long* gate) {
+#pragma clang fp contract(off)
+  if (gate && *gate == 0) return;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  if (dt_dev) dt = *dt_dev;
+  const double h = STAGE == 1 ? dt : 0.5 * dt;
+  const long c = zid(g, i, j, k), si = 1, sj = g.s1, sk = g.plane;
+  auto e = [&](const FT* E, long o) { return (double)E[c + o]; };
+  if (j < g.n2 && k < g.n3) {
+    const double r = (e(E3, sj) - e(E3, 0)) / g.dx2 - (e(E2, sk) - e(E2, 0)) / g.dx3;
+    const double x = b1[c] + h * r;
+    o1[c] = x;
+    if (STAGE == 1) v1[c] = 0.5 * (b1[c] + x);
+  }
+  if (i < g.n1 && k < g.n3) {
+    const double r = (e(E1, sk) - e(E1, 0)) / g.dx3 - (e(E3, si) - e(E3, 0)) / g.dx1;
+    const double x = b2[c] + h * r;
+    o2[c] = x;
+    if (STAGE == 1) v2[c] = 0.5 * (b2[c] + x);
+  }
+  if (i < g.n1 && j < g.n2) {
+    const double r = (e(E2, si) - e(E2, 0)) / g.dx1 - (e(E1, sj) - e(E1, 0)) / g.dx2;
+    const double x = b3[c] + h * r;
+    o3[c] = x;
+    if (STAGE == 1) v3[c] = 0.5 * (b3[c] + x);
+  }
+}
+
+// Interior zones' B prims from the faces (after faces are loaded).
+__global__ void __launch_bounds__(BLOCK) k_cell_b(Dev g, Box box, const double* __restrict__ ph1,
+                                                  const double* __restrict__ ph2, const double* __restrict__ ph3,
+                                                  const double* __restrict__ tabC, double* __restrict__ P) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!box_index(box, t, i, j, k)) return;
+  const long c = zid(g, i, j, k);
+  const double gd = tabC[G_DET * g.plane + pid(g, i, j)];
+  P[B1 * g.nz + c] = 0.5 * (ph1[c] + ph1[c + 1]) / gd;
+  P[B2 * g.nz + c] = 0.5 * (ph2[c] + ph2[c + g.s1]) / gd;
+  P[B3 * g.nz + c] = 0.5 * (ph3[c] + ph3[c + g.plane]) / gd;
 }
 
 // Rebuild the B components of interior-face fluxes from the EMFs (as the
@@ -943,7 +1166,7 @@ enum { U_PLAIN = 0, U_PROVISIONAL = 2, U_FINAL = 3 };
 // Counter slots of the context's counter array.
 enum { C_FAILS = 0, C_C2P = 1, C_FLOORS = 2, C_FOFC = 3, C_FLUID = 4, C_MARKS = 5 };
 
-template <int STAGE, typename FT, bool RATE = false, int MODE = U_PLAIN>
+template <int STAGE, typename FT, bool RATE = false, int MODE = U_PLAIN, bool FACE = false>
 __device__ __forceinline__ void update_zone(const Dev& g, const double* __restrict__ Pin,
                                             double* __restrict__ Pout, double* __restrict__ V,
                                             const FT* __restrict__ F1, const FT* __restrict__ F2,
@@ -953,7 +1176,10 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
                                             const double* __restrict__ conn, double dt,
                                             unsigned long long* fails, unsigned char* __restrict__ flags,
                                             int i, int j, int k, double* rate = nullptr,
-                                            unsigned char* __restrict__ mark = nullptr) {
+                                            unsigned char* __restrict__ mark = nullptr,
+                                            const double* __restrict__ ph1 = nullptr,
+                                            const double* __restrict__ ph2 = nullptr,
+                                            const double* __restrict__ ph3 = nullptr) {
   // the FP64 update is rounded operation by operation, in the order written
 #pragma clang fp contract(off)
   const long c = zid(g, i, j, k), nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
@@ -980,6 +1206,7 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
     // Flux-CT fluxes of B: F1(B2) = (E3 + E3_{j+1})/2, F1(B3) = -(E2 + E2_{k+1})/2,
     // F2(B1) = -(E3 + E3_{i+1})/2, F2(B3) = (E1 + E1_{k+1})/2,
     // F3(B1) = (E2 + E2_{i+1})/2, F3(B2) = -(E1 + E1_{j+1})/2; normal ones zero.
+    if constexpr (!FACE) {
     auto e = [&](const FT* E, long o) { return (double)E[c + o]; };
     double f1b2_p = 0.5 * (e(E3, si) + e(E3, si + sj)), f1b2_m = 0.5 * (e(E3, 0) + e(E3, sj));
     double f1b3_p = -0.5 * (e(E2, si) + e(E2, si + sk)), f1b3_m = -0.5 * (e(E2, 0) + e(E2, sk));
@@ -990,6 +1217,9 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
     L[B1] = -((f2b1_p - f2b1_m) / g.dx2 + (f3b1_p - f3b1_m) / g.dx3);
     L[B2] = -((f1b2_p - f1b2_m) / g.dx1 + (f3b2_p - f3b2_m) / g.dx3);
     L[B3] = -((f1b3_p - f1b3_m) / g.dx1 + (f2b3_p - f2b3_m) / g.dx2);
+    } else {
+      L[B1] = L[B2] = L[B3] = 0.0;
+    }
   }
 
   double U[NVAR];
@@ -1004,6 +1234,11 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
   } else {
 #pragma unroll
     for (int v = 0; v < NVAR; v++) U[v] = V[v * nz + c] + 0.5 * (dt * L[v]);
+  }
+  if constexpr (FACE) {  // face-centred CT: the zone's field is the mean of its new faces
+    U[B1] = 0.5 * (ph1[c] + ph1[c + si]);
+    U[B2] = 0.5 * (ph2[c] + ph2[c + sj]);
+    U[B3] = 0.5 * (ph3[c] + ph3[c + sk]);
   }
   double out[NVAR];
   int bad = invert(g, m, U, p, out);
@@ -1026,7 +1261,7 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
 // flux correction runs only when the PROVISIONAL pass marked a zone (a
 // grid-uniform test of the mark count), and then adds that count to the
 // correction's running total.
-template <int STAGE, typename FT, bool RATE, int MODE>
+template <int STAGE, typename FT, bool RATE, int MODE, bool FACE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8)))
 k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ Pout,
          double* __restrict__ V, const FT* __restrict__ F1, const FT* __restrict__ F2,
@@ -1034,7 +1269,8 @@ k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ 
          const FT* __restrict__ E3, const double* __restrict__ tabC, const double* __restrict__ conn,
          double dt, const double* __restrict__ dt_dev, unsigned long long* fails,
          unsigned char* __restrict__ flags, double* __restrict__ rate_partial,
-         unsigned char* __restrict__ mark) {
+         unsigned char* __restrict__ mark, const double* __restrict__ ph1,
+         const double* __restrict__ ph2, const double* __restrict__ ph3) {
   if (MODE == U_FINAL) {
     const unsigned long long nmark = fails[C_MARKS];
     if (nmark == 0) return;
@@ -1045,14 +1281,14 @@ k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ 
   if (dt_dev) dt = *dt_dev;
   if (!RATE) {
     if (in)
-      update_zone<STAGE, FT, false, MODE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
-                                          flags, i, j, k, nullptr, mark);
+      update_zone<STAGE, FT, false, MODE, FACE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt,
+                                                fails, flags, i, j, k, nullptr, mark, ph1, ph2, ph3);
     return;
   }
   double r = 0.0, sm = 0.0;
   if (in)
-    update_zone<STAGE, FT, true, MODE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
-                                       flags, i, j, k, &r, mark);
+    update_zone<STAGE, FT, true, MODE, FACE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
+                                             flags, i, j, k, &r, mark, ph1, ph2, ph3);
   block_reduce(r, sm);
   if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
 }
@@ -1142,6 +1378,30 @@ __global__ void __launch_bounds__(BLOCK) k_dt_partial(Dev g, Box box, const doub
   double sm = 0.0;
   block_reduce(s, sm);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Face divergence sum_d (phi_d(+) - phi_d(-))/dx_d over interior zones;
+// workgroup max and sum of its magnitude (grid-stride).
+__global__ void __launch_bounds__(BLOCK) k_face_divb_partial(Dev g, Box box, const double* __restrict__ ph1,
+                                                             const double* __restrict__ ph2,
+                                                             const double* __restrict__ ph3, double* pmax,
+                                                             double* psum) {
+  double mx = 0.0, sm = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < box.count(); t += stride) {
+    int i, j, k;
+    box_index(box, t, i, j, k);
+    const long c = zid(g, i, j, k);
+    const double dv = ((ph1[c + 1] - ph1[c]) / g.dx1 + (ph2[c + g.s1] - ph2[c]) / g.dx2) +
+                      (ph3[c + g.plane] - ph3[c]) / g.dx3;
+    mx = fmax(mx, fabs(dv));
+    sm += fabs(dv);
+  }
+  block_reduce(mx, sm);
+  if (threadIdx.x == 0) {
+    pmax[blockIdx.x] = mx;
+    psum[blockIdx.x] = sm;
+  }
 }
 
 // Corner-centred div B (conserved field sqrt(-g) B^d, four zones per side)
@@ -1268,6 +1528,12 @@ struct grmhd_ctx {
   double *pmax, *psum, *result;
   unsigned long long* fails;  // counters, slots C_* (failures, floors, flux-correction marks, ...)
   unsigned char* mark;        // per zone: marked by the flux correction's provisional pass
+  // face-centred CT: face fields of the state, of stage 1 and the stage
+  // register; zone-centre EMFs (stored type) of the upwinded scheme
+  double *phi[3] = {nullptr, nullptr, nullptr}, *phi1[3] = {nullptr, nullptr, nullptr},
+         *phiV[3] = {nullptr, nullptr, nullptr};
+  void* Ec[4] = {nullptr, nullptr, nullptr, nullptr};  // EMFs, then the mass-current scale
+  bool faces_loaded = false;
   double* pdt;              // CFL-rate partials left by the last stage-2 update
   bool rate_ready = false;  // pdt describes the current state (rate_n partials)
   bool ghosts_valid = false;  // the ghost zones of P hold the boundary conditions of its interior
@@ -1315,6 +1581,7 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
   if (p->precision != GRMHD_PREC_FP64 && p->precision != GRMHD_PREC_MIXED) return false;
   if (!(p->gamma_ad > 1.0) || p->newton_maxit < 1 || !(p->newton_tol > 0.0)) return false;
   if ((p->floors != 0 && p->floors != 1) || (p->fofc != 0 && p->fofc != 1)) return false;
+  if (p->ct != GRMHD_CT_FLUX && p->ct != GRMHD_CT_FACE_AVG && p->ct != GRMHD_CT_FACE_GS) return false;
   if (p->floors && !(p->rho_min_geom > 0.0 && p->u_min_geom > 0.0 && p->bsq_over_rho_max > 0.0 &&
                      p->bsq_over_u_max > 0.0 && p->u_over_rho_max > 0.0 && p->gamma_max > 1.0))
     return false;
@@ -1323,7 +1590,7 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
   return true;
 }
 
-size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
+size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, int ct) {
   long nz = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * (g->n3 + 2 * NG);
   long plane = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG);
   Carve cv;
@@ -1344,8 +1611,25 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
   double* pdt = cv.take<double>(base, MAX_PARTIALS);
   unsigned long long* fails = cv.take<unsigned long long>(base, 8);
   unsigned char* mark = cv.take<unsigned char>(base, nz);
+  double *phi[3] = {}, *phi1[3] = {}, *phiV[3] = {}, *Ec[4] = {};
+  if (ct != GRMHD_CT_FLUX) {
+    for (int d = 0; d < 3; d++) {
+      phi[d] = cv.take<double>(base, nz);
+      phi1[d] = cv.take<double>(base, nz);
+      phiV[d] = cv.take<double>(base, nz);
+      Ec[d] = cv.take<double>(base, nz);
+    }
+    Ec[3] = cv.take<double>(base, nz);
+  }
   if (c) {
     c->mark = mark;
+    for (int d = 0; d < 3; d++) {
+      c->phi[d] = phi[d];
+      c->phi1[d] = phi1[d];
+      c->phiV[d] = phiV[d];
+      c->Ec[d] = Ec[d];
+    }
+    c->Ec[3] = Ec[3];
     c->P = P; c->P1 = P1; c->V = V;
     for (int d = 0; d < 3; d++) { c->F[d] = F[d]; c->E[d] = E[d]; }
     c->tabC = tabC; c->tabF1 = tabF1; c->tabF2 = tabF2; c->corner = corner; c->conn = conn;
@@ -1356,7 +1640,7 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g) {
 
 int hip_check() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
 
-enum { T_BC = 0, T_FLUX, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_FOFC, T_FLOORS, T_NCLASS };
+enum { T_BC = 0, T_FLUX, T_EMF, T_UPDATE1, T_UPDATE2, T_DT, T_FOFC, T_FLOORS, T_FACES, T_NCLASS };
 
 // Start/stop events of one launch of class cls while timing is enabled (null
 // events otherwise, or when no more events can be created).
@@ -1396,24 +1680,55 @@ int launch(grmhd_ctx* c, int cls, F kernel, unsigned nblocks, Args... args) {
   return hip_check();
 }
 
-int fill_ghosts(grmhd_ctx* c, double* P) {
+// Ghost zones of prims P and, with face-centred CT, ghost faces of the face
+// fields ph (the state's or stage 1's).
+int fill_ghosts(grmhd_ctx* c, double* P, double* const* ph = nullptr) {
+  if (ph && ph[0]) {
+    int rc = launch(c, T_BC, k_bc_faces, blocks_for(3 * c->dev.nz), c->dev, ph[0], ph[1], ph[2]);
+    if (rc) return rc;
+  }
   return launch(c, T_BC, k_bc, blocks_for(ghost_count(c->dev)), c->dev, P);
 }
 
-// Ghost zones of the state P, filled unless they already hold its boundary
-// conditions (filled since P last changed).
+// Ghost zones (and faces) of the state, filled unless they already hold its
+// boundary conditions (filled since the state last changed).
 int ensure_ghosts(grmhd_ctx* c) {
   if (c->ghosts_valid) return GRMHD_OK;
-  int rc = fill_ghosts(c, c->P);
+  int rc = fill_ghosts(c, c->P, c->phi);
   if (rc == GRMHD_OK) c->ghosts_valid = true;
   return rc;
+}
+
+// Interior zones' B prims of the state from its face fields.
+int cell_b_from_faces(grmhd_ctx* c) {
+  const Dev& g = c->dev;
+  Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  k_cell_b<<<blocks_for(bz.count()), BLOCK, 0, c->stream>>>(g, bz, c->phi[0], c->phi[1], c->phi[2], c->tabC,
+                                                             c->P);
+  return hip_check();
 }
 
 inline unsigned round8(unsigned n) { return (n + 7u) & ~7u; }
 
 // Flux and EMF kernels of one stage, reading the (ghost-filled) prims P.
+// Edge EMFs of the stage from the fluxes: the Flux-CT average (also the
+// averaged face-centred scheme), or the upwinded scheme from the zone-centre
+// EMFs (computed once per stage, from P).  gate/zero as in k_emf.
+template <typename FT>
+int stage_emfs(grmhd_ctx* c, const unsigned long long* gate, unsigned long long* zero) {
+  const Dev& g = c->dev;
+  Sched be = make_sched(make_box(0, g.n1, 0, g.n2, 0, g.n3), c->kg_flux);
+  if (c->params.ct == GRMHD_CT_FACE_GS)
+    return launch(c, T_EMF, k_emf_gs<FT>, blocks_for(be), g, be, (const FT*)c->F[0], (const FT*)c->F[1],
+                  (const FT*)c->F[2], (const FT*)c->Ec[0], (const FT*)c->Ec[1], (const FT*)c->Ec[2],
+                  (const FT*)c->Ec[3], (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2], gate, zero);
+  return launch(c, T_EMF, k_emf<FT>, blocks_for(be), g, be, (const FT*)c->F[0], (const FT*)c->F[1],
+                (const FT*)c->F[2], (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2], gate, zero);
+}
+
 template <typename R, typename FT>
-int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullptr) {
+int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullptr,
+                 double* const* ph = nullptr) {
   const Dev& g = c->dev;
   FT* F1 = (FT*)c->F[0];
   FT* F2 = (FT*)c->F[1];
@@ -1423,20 +1738,43 @@ int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullp
   Sched b3 = make_sched(make_box(-1, g.n1, -1, g.n2, 0, g.n3), c->kg_flux);
   const unsigned n1 = round8(blocks_for(b1)), n2 = round8(blocks_for(b2)), n3 = blocks_for(b3);
   const double* Pc = P;
+  const double* p1 = ph ? ph[0] : nullptr;
+  const double* p2 = ph ? ph[1] : nullptr;
+  const double* p3 = ph ? ph[2] : nullptr;
+  auto go = [&](auto kernel) {
+    return launch(c, T_FLUX, kernel, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3, Pc, (const double*)c->tabF1,
+                  (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3, p1, p2, p3);
+  };
   int rc;
+  const bool face = ph != nullptr;
   if (c->params.recon == GRMHD_RECON_MC)
-    rc = launch(c, T_FLUX, k_flux_all<GRMHD_RECON_MC, R, FT>, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3,
-                Pc, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3);
+    rc = face ? go(k_flux_all<GRMHD_RECON_MC, R, FT, true>) : go(k_flux_all<GRMHD_RECON_MC, R, FT, false>);
   else if (c->params.recon == GRMHD_RECON_DONOR)
-    rc = launch(c, T_FLUX, k_flux_all<GRMHD_RECON_DONOR, R, FT>, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3,
-                Pc, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3);
+    rc = face ? go(k_flux_all<GRMHD_RECON_DONOR, R, FT, true>) : go(k_flux_all<GRMHD_RECON_DONOR, R, FT, false>);
   else
-    rc = launch(c, T_FLUX, k_flux_all<GRMHD_RECON_WENO5, R, FT>, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3,
-                Pc, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3);
+    rc = face ? go(k_flux_all<GRMHD_RECON_WENO5, R, FT, true>) : go(k_flux_all<GRMHD_RECON_WENO5, R, FT, false>);
   if (rc) return rc;
-  Sched be = make_sched(make_box(0, g.n1, 0, g.n2, 0, g.n3), c->kg_flux);
-  return launch(c, T_EMF, k_emf<FT>, blocks_for(be), g, be, (const FT*)F1, (const FT*)F2, (const FT*)F3,
-                (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2], (const unsigned long long*)nullptr, zero);
+  if (c->params.ct == GRMHD_CT_FACE_GS) {
+    Box bc = make_box(-1, g.n1, -1, g.n2, -1, g.n3);
+    if ((rc = launch(c, T_EMF, k_cell_emf<R, FT>, blocks_for(bc.count()), g, bc, Pc, (const double*)c->tabC,
+                     (FT*)c->Ec[0], (FT*)c->Ec[1], (FT*)c->Ec[2], (FT*)c->Ec[3])))
+      return rc;
+  }
+  return stage_emfs<FT>(c, (const unsigned long long*)nullptr, zero);
+}
+
+// Face fields of one stage from the edge EMFs: stage 1 phi1 = phi + dt R (and
+// the register phiV = (phi + phi1)/2), stage 2 phi = phiV + (dt/2) R.
+template <int STAGE, typename FT>
+int stage_faces(grmhd_ctx* c, double dt, const double* dt_dev, const unsigned long long* gate) {
+  const Dev& g = c->dev;
+  Box bf = make_box(0, g.n1, 0, g.n2, 0, g.n3);
+  double* const* base = STAGE == 1 ? c->phi : c->phiV;
+  double* const* out = STAGE == 1 ? c->phi1 : c->phi;
+  double* const* reg = STAGE == 1 ? c->phiV : c->phi1;  // unused in stage 2
+  return launch(c, T_FACES, k_face_update<STAGE, FT>, blocks_for(bf.count()), g, bf, (const FT*)c->E[0],
+                (const FT*)c->E[1], (const FT*)c->E[2], (const double*)base[0], (const double*)base[1],
+                (const double*)base[2], out[0], out[1], out[2], reg[0], reg[1], reg[2], dt, dt_dev, gate);
 }
 
 // One stage's update.  With rate (stage 2 of a step) the workgroups also
@@ -1446,20 +1784,27 @@ int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
                  unsigned long long* fails = nullptr, unsigned char* flags = nullptr,
                  const double* dt_dev = nullptr, bool rate = false) {
   const Dev& g = c->dev;
+  // face-centred CT: the zones' field from the stage's new faces
+  double* const* ph = c->params.ct == GRMHD_CT_FLUX ? nullptr : (STAGE == 1 ? c->phi1 : c->phi);
+  const double* p1 = ph ? ph[0] : nullptr;
+  const double* p2 = ph ? ph[1] : nullptr;
+  const double* p3 = ph ? ph[2] : nullptr;
   Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
   const int cls = STAGE == 1 ? T_UPDATE1 : T_UPDATE2;
   const unsigned nb = blocks_for(bz);
+  auto go = [&](auto kernel, double* partial) {
+    return launch(c, cls, kernel, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1],
+                  (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2],
+                  (const double*)c->tabC, (const double*)c->conn, dt, dt_dev, fails ? fails : c->fails, flags,
+                  partial, c->mark, p1, p2, p3);
+  };
   if constexpr (STAGE == 2) {
     if (rate && nb <= (unsigned)MAX_PARTIALS)
-      return launch(c, cls, k_update<STAGE, FT, true, MODE>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
-                    (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1],
-                    (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn, dt, dt_dev,
-                    fails ? fails : c->fails, flags, c->pdt, c->mark);
+      return ph ? go(k_update<STAGE, FT, true, MODE, true>, c->pdt)
+                : go(k_update<STAGE, FT, true, MODE, false>, c->pdt);
   }
-  return launch(c, cls, k_update<STAGE, FT, false, MODE>, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0],
-                (const FT*)c->F[1], (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1],
-                (const FT*)c->E[2], (const double*)c->tabC, (const double*)c->conn, dt, dt_dev,
-                fails ? fails : c->fails, flags, (double*)nullptr, c->mark);
+  return ph ? go(k_update<STAGE, FT, false, MODE, true>, (double*)nullptr)
+            : go(k_update<STAGE, FT, false, MODE, false>, (double*)nullptr);
 }
 
 // The floors pass after an update pass (same schedule as the update, so the
@@ -1487,13 +1832,17 @@ int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double
   int rc;
   const bool floors = c->params.floors != 0;
   const bool urate = rate && !floors;
+  const bool faces = c->params.ct != GRMHD_CT_FLUX;
+  double* const* phin = faces ? (STAGE == 1 ? c->phi : c->phi1) : nullptr;
   if (!c->params.fofc) {
-    if ((rc = stage_fluxes<R, FT>(c, Pin))) return rc;
+    if ((rc = stage_fluxes<R, FT>(c, Pin, nullptr, phin))) return rc;
+    if (faces && (rc = stage_faces<STAGE, FT>(c, dt, dt_dev, nullptr))) return rc;
     if ((rc = stage_update<STAGE, FT, U_PLAIN>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, urate))) return rc;
     return floors ? stage_floors<STAGE, U_PLAIN>(c, Pin, Pout, rate) : GRMHD_OK;
   }
   unsigned long long* nmark = c->fails + C_MARKS;
-  if ((rc = stage_fluxes<R, FT>(c, Pin, nmark))) return rc;
+  if ((rc = stage_fluxes<R, FT>(c, Pin, nmark, phin))) return rc;
+  if (faces && (rc = stage_faces<STAGE, FT>(c, dt, dt_dev, nullptr))) return rc;
   if ((rc = stage_update<STAGE, FT, U_PROVISIONAL>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, urate)))
     return rc;
   if (floors && (rc = stage_floors<STAGE, U_PROVISIONAL>(c, Pin, Pout, rate))) return rc;
@@ -1505,13 +1854,12 @@ int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double
   FT* F3 = (FT*)c->F[2];
   if ((rc = launch(c, T_FOFC, k_fofc_flux<R, FT>, blocks_for(b1.count() + b2.count() + b3.count()), g, b1, b2,
                    b3, Pin, (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2,
-                   F3, (const unsigned char*)c->mark, (const unsigned long long*)nmark)))
+                   F3, (const unsigned char*)c->mark, (const unsigned long long*)nmark,
+                   (const double*)(phin ? phin[0] : nullptr), (const double*)(phin ? phin[1] : nullptr),
+                   (const double*)(phin ? phin[2] : nullptr))))
     return rc;
-  Sched be = make_sched(make_box(0, g.n1, 0, g.n2, 0, g.n3), c->kg_flux);
-  if ((rc = launch(c, T_EMF, k_emf<FT>, blocks_for(be), g, be, (const FT*)F1, (const FT*)F2, (const FT*)F3,
-                   (FT*)c->E[0], (FT*)c->E[1], (FT*)c->E[2], (const unsigned long long*)nmark,
-                   (unsigned long long*)nullptr)))
-    return rc;
+  if ((rc = stage_emfs<FT>(c, (const unsigned long long*)nmark, (unsigned long long*)nullptr))) return rc;
+  if (faces && (rc = stage_faces<STAGE, FT>(c, dt, dt_dev, (const unsigned long long*)nmark))) return rc;
   if ((rc = stage_update<STAGE, FT, U_FINAL>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, urate))) return rc;
   return floors ? stage_floors<STAGE, U_FINAL>(c, Pin, Pout, rate) : GRMHD_OK;
 }
@@ -1523,11 +1871,12 @@ int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double
 template <typename R, typename FT>
 int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   int rc;
+  if (c->params.ct != GRMHD_CT_FLUX && !c->faces_loaded) return GRMHD_E_STATE;
   c->rate_ready = false;
   if ((rc = ensure_ghosts(c))) return rc;
   c->ghosts_valid = false;
   if ((rc = stage<1, R, FT>(c, c->P, c->P1, dt, dt_dev, false))) return rc;
-  if ((rc = fill_ghosts(c, c->P1))) return rc;
+  if ((rc = fill_ghosts(c, c->P1, c->phi1))) return rc;
   if ((rc = stage<2, R, FT>(c, c->P1, c->P, dt, dt_dev, true))) return rc;
   const Dev& g = c->dev;
   const long nb = blocks_for(make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update));
@@ -1567,7 +1916,7 @@ extern "C" {
 
 size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
   if (!grid_ok(grid, params)) return 0;
-  return carve(nullptr, nullptr, grid);
+  return carve(nullptr, nullptr, grid, params->ct);
 }
 
 int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* metric,
@@ -1576,14 +1925,14 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   if (metric->metric != GRMHD_METRIC_MINKOWSKI && metric->metric != GRMHD_METRIC_KERR_MKS)
     return GRMHD_E_ARG;
   if (((uintptr_t)d_workspace & 255) != 0) return GRMHD_E_ARG;
-  if (ws_bytes < carve(nullptr, nullptr, grid)) return GRMHD_E_NOMEM;
+  if (ws_bytes < carve(nullptr, nullptr, grid, params->ct)) return GRMHD_E_NOMEM;
   grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
   if (!c) return GRMHD_E_NOMEM;
   c->grid = *grid;
   c->metric = *metric;
   c->params = *params;
   c->stream = (hipStream_t)hip_stream;
-  carve(c, (char*)d_workspace, grid);
+  carve(c, (char*)d_workspace, grid, params->ct);
   Dev& g = c->dev;
   g.n1 = grid->n1; g.n2 = grid->n2; g.n3 = grid->n3;
   g.s1 = g.n1 + 2 * NG; g.s2 = g.n2 + 2 * NG; g.s3 = g.n3 + 2 * NG;
@@ -1605,6 +1954,7 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   g.inverter = params->inverter;
   g.vmax2 = 1.0 - 1.0 / (params->kastaun_wmax * params->kastaun_wmax);
   g.floors = params->floors;
+  g.ct = params->ct;
   g.rho_min_geom = params->rho_min_geom;
   g.u_min_geom = params->u_min_geom;
   g.bsq_over_rho_max = params->bsq_over_rho_max;
@@ -1637,6 +1987,59 @@ int grmhd_load_prims(grmhd_ctx* c, const double* d_prims) {
   // the stage buffer carries the same (frozen) ghosts
   if (hipMemcpyAsync(c->P1, d_prims, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return GRMHD_E_HIP;
+  // face-centred CT: the zones' field is their faces' mean
+  if (c->faces_loaded) return cell_b_from_faces(c);
+  return GRMHD_OK;
+}
+
+int grmhd_load_faces(grmhd_ctx* c, const double* d_faces) {
+  if (!c || !d_faces) return GRMHD_E_ARG;
+  if (c->params.ct == GRMHD_CT_FLUX) return GRMHD_E_STATE;
+  const size_t bytes = sizeof(double) * c->dev.nz;
+  for (int d = 0; d < 3; d++) {
+    // the stage-1 faces carry the same (frozen) ghosts
+    if (hipMemcpyAsync(c->phi[d], d_faces + d * c->dev.nz, bytes, hipMemcpyDeviceToDevice, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->phi1[d], d_faces + d * c->dev.nz, bytes, hipMemcpyDeviceToDevice, c->stream) !=
+            hipSuccess)
+      return GRMHD_E_HIP;
+  }
+  c->faces_loaded = true;
+  c->rate_ready = false;
+  c->ghosts_valid = false;
+  return cell_b_from_faces(c);
+}
+
+int grmhd_get_faces(grmhd_ctx* c, double* d_out) {
+  if (!c || !d_out) return GRMHD_E_ARG;
+  if (c->params.ct == GRMHD_CT_FLUX || !c->faces_loaded) return GRMHD_E_STATE;
+  int rc;
+  if ((rc = ensure_ghosts(c))) return rc;
+  for (int d = 0; d < 3; d++)
+    if (hipMemcpyAsync(d_out + d * c->dev.nz, c->phi[d], sizeof(double) * c->dev.nz, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return GRMHD_E_HIP;
+  return GRMHD_OK;
+}
+
+int grmhd_face_divb(grmhd_ctx* c, double* max_out, double* mean_out) {
+  if (!c || !max_out || !mean_out) return GRMHD_E_ARG;
+  if (c->params.ct == GRMHD_CT_FLUX || !c->faces_loaded) return GRMHD_E_STATE;
+  const Dev& g = c->dev;
+  Box b = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  long nb = blocks_for(b.count());
+  if (nb > MAX_PARTIALS) nb = MAX_PARTIALS;
+  k_face_divb_partial<<<(unsigned)nb, BLOCK, 0, c->stream>>>(g, b, c->phi[0], c->phi[1], c->phi[2], c->pmax,
+                                                              c->psum);
+  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(c->pmax, c->psum, (int)nb, c->result, 0.0);
+  int rc;
+  if ((rc = hip_check())) return rc;
+  double res[2];
+  if (hipMemcpyAsync(res, c->result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  if ((rc = sync(c))) return rc;
+  *max_out = res[0];
+  *mean_out = res[1] / (double)b.count();
   return GRMHD_OK;
 }
 
@@ -1919,7 +2322,8 @@ int step_vjp(grmhd_ctx* c, const VjpCarve& w, const double* d_in, double dt, con
 extern "C" {
 
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
-  if (!grid_ok(grid, params) || params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR)
+  if (!grid_ok(grid, params) || params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR ||
+      params->ct != GRMHD_CT_FLUX)
     return 0;
   return vjp_carve(grid, params->recon, nullptr, nullptr);
 }
@@ -1930,7 +2334,9 @@ int grmhd_step_vjp(grmhd_ctx* c, const double* d_prims_in, double dt, const doub
   if (!(dt > 0.0) || !isfinite(dt)) return GRMHD_E_ARG;
   if (c->params.precision != GRMHD_PREC_FP64) return GRMHD_E_STATE;
   // the adjoint covers the plain high-order step (no floors, no correction)
-  if (c->params.floors || c->params.fofc || c->params.recon == GRMHD_RECON_DONOR) return GRMHD_E_STATE;
+  if (c->params.floors || c->params.fofc || c->params.recon == GRMHD_RECON_DONOR ||
+      c->params.ct != GRMHD_CT_FLUX)
+    return GRMHD_E_STATE;
   if (((uintptr_t)d_vjp_ws & 255) != 0) return GRMHD_E_ARG;
   if (vjp_ws_bytes < vjp_carve(&c->grid, c->params.recon, nullptr, nullptr)) return GRMHD_E_NOMEM;
   VjpCarve w;
@@ -2096,7 +2502,8 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
   if (!out || nblocks < 1 || !n || !offsets_ijk || !global || !metric || !params || !d_ws) return GRMHD_E_ARG;
   if (!grid_ok(global, params) || params->precision != GRMHD_PREC_FP64) return GRMHD_E_ARG;
   // packs advance the plain high-order step
-  if (params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR) return GRMHD_E_ARG;
+  if (params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR || params->ct != GRMHD_CT_FLUX)
+    return GRMHD_E_ARG;
   if (((uintptr_t)d_ws & 255) != 0) return GRMHD_E_ARG;
   for (int b = 0; b < nblocks; b++) {
     const int* o = offsets_ijk + 3 * b;
@@ -2141,6 +2548,7 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
     g.inverter = params->inverter;
     g.vmax2 = 1.0 - 1.0 / (params->kastaun_wmax * params->kastaun_wmax);
     g.floors = params->floors;
+    g.ct = params->ct;
     g.rho_min_geom = params->rho_min_geom;
     g.u_min_geom = params->u_min_geom;
     g.bsq_over_rho_max = params->bsq_over_rho_max;

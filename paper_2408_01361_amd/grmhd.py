@@ -18,6 +18,7 @@ METRIC_MINKOWSKI, METRIC_KERR_MKS = 0, 1
 RECON_MC, RECON_WENO5, RECON_DONOR = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 INV_1DW, INV_KASTAUN = 0, 1
+CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
 BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN = 0, 1, 2, 3
 NG, NVAR = 3, 8
 
@@ -44,7 +45,7 @@ class grmhd_params(C.Structure):
                 ("kastaun_wmax", C.c_double), ("rho_min_geom", C.c_double),
                 ("u_min_geom", C.c_double), ("bsq_over_rho_max", C.c_double),
                 ("bsq_over_u_max", C.c_double), ("u_over_rho_max", C.c_double),
-                ("gamma_max", C.c_double), ("fofc", C.c_int)]
+                ("gamma_max", C.c_double), ("fofc", C.c_int), ("ct", C.c_int)]
 
 
 # floor and ceiling defaults (HARM-family values; the paper states none)
@@ -53,7 +54,7 @@ FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0
 
 
 def make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precision, inverter,
-                kastaun_wmax, floors=False, fofc=False, **floor_params):
+                kastaun_wmax, floors=False, fofc=False, ct=CT_FLUX, **floor_params):
     fp = dict(FLOOR_DEFAULTS)
     for k, v in floor_params.items():
         if k not in fp:
@@ -62,12 +63,12 @@ def make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precis
     return grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
                         int(newton_maxit), int(recon), int(precision), int(bool(floors)),
                         int(inverter), float(kastaun_wmax), *(float(fp[k]) for k in FLOOR_DEFAULTS),
-                        int(bool(fofc)))
+                        int(bool(fofc)), int(ct))
 
 
 EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_step",
            "grmhd_estimate_dt", "grmhd_step_cfl", "grmhd_last_dt", "grmhd_get_prims", "grmhd_divb", "grmhd_get_status",
-           "grmhd_get_counters",
+           "grmhd_get_counters", "grmhd_load_faces", "grmhd_get_faces", "grmhd_face_divb",
            "grmhd_reset_status", "grmhd_prims_to_cons", "grmhd_cons_to_prims", "grmhd_fluxes",
            "grmhd_pack_workspace_bytes", "grmhd_pack_create", "grmhd_pack_set_tiles",
            "grmhd_pack_load_prims", "grmhd_pack_step", "grmhd_pack_get_prims",
@@ -93,6 +94,9 @@ def load_library(path=LIB_PATH):
         "grmhd_divb": (C.c_int, [vp, vp, dp, dp]),
         "grmhd_get_status": (C.c_int, [vp, ip, ip]),
         "grmhd_get_counters": (C.c_int, [vp, ip]),
+        "grmhd_load_faces": (C.c_int, [vp, vp]),
+        "grmhd_get_faces": (C.c_int, [vp, vp]),
+        "grmhd_face_divb": (C.c_int, [vp, dp, dp]),
         "grmhd_reset_status": (C.c_int, [vp]),
         "grmhd_prims_to_cons": (C.c_int, [vp, vp, vp]),
         "grmhd_cons_to_prims": (C.c_int, [vp, vp, vp, vp, vp, ip]),
@@ -168,12 +172,12 @@ class Grmhd:
     def __init__(self, spec, gamma_ad, recon=RECON_WENO5, precision=PREC_FP64, cfl=0.9,
                  weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda",
                  stream=None, strict=False, inverter=INV_1DW, kastaun_wmax=1e3, floors=False,
-                 fofc=False, **floor_params):
+                 fofc=False, ct=CT_FLUX, **floor_params):
         self.spec = spec
         self.grid = make_grid(spec)
         self.metric = grmhd_metric(int(spec.metric), float(spec.a), float(spec.hslope))
         self.params = make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precision,
-                                  inverter, kastaun_wmax, floors, fofc, **floor_params)
+                                  inverter, kastaun_wmax, floors, fofc, ct, **floor_params)
         self.strict = strict
         L = lib()
         nbytes = L.grmhd_workspace_bytes(C.byref(self.grid), C.byref(self.params))
@@ -242,6 +246,24 @@ class Grmhd:
         _check(lib().grmhd_get_status(self.ctx, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def load_faces(self, faces):
+        """Face fields [3, n3+6, n2+6, n1+6] (sqrt(-g) B^d on lower d-faces) of
+        face-centred CT."""
+        f = faces.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(f.shape) == (3,) + tuple(self.shape[1:])
+        self._keep_faces = f
+        _check(lib().grmhd_load_faces(self.ctx, _ptr(f)))
+
+    def faces(self):
+        out = torch.empty((3,) + tuple(self.shape[1:]), dtype=torch.float64, device=self.device)
+        _check(lib().grmhd_get_faces(self.ctx, _ptr(out)))
+        return out
+
+    def face_divb(self):
+        mx, mean = C.c_double(), C.c_double()
+        _check(lib().grmhd_face_divb(self.ctx, C.byref(mx), C.byref(mean)))
+        return mx.value, mean.value
+
     def counters(self):
         """Counts since creation or reset: failed inversions, zones floors
         acted on, zones the first-order flux correction marked, fluid-frame
@@ -275,7 +297,7 @@ class Grmhd:
         _check(lib().grmhd_fluxes(self.ctx, _ptr(p), _ptr(out)))
         return out
 
-    TIMING_CLASSES = ("bc", "flux", "emf", "update1", "update2", "dt", "fofc", "floors")
+    TIMING_CLASSES = ("bc", "flux", "emf", "update1", "update2", "dt", "fofc", "floors", "faces")
 
     def step_vjp(self, prims_in, dt, gprims_out):
         """Adjoint of one step: (d loss/d prims_in, d loss/d gamma_ad)."""

@@ -71,6 +71,30 @@ def test_torus128_weno5_kastaun_full_step():
     assert s.status()[0] == fails
 
 
+def test_torus128_weno5_face_ct_full_step():
+    """The benchmark workload with face-centred CT (upwinded EMFs): one step
+    at the oracle's dt, every zone and every evolved face against the
+    oracle; face divergence at roundoff."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    grid, P, info = fm_torus(128, 128, 128, seed=1, gamma=gam)
+    F = info["faces"]
+    c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, nthreads=THREADS, ct=oracle.CT_FACE_GS)
+    ref, Fref, fails, dts = oracle.run_face(c, P, F, -1, 1)
+    s = gr.Grmhd(grid, gam, recon=RECON_WENO5, ct=gr.CT_FACE_GS)
+    s.load(torch.from_numpy(P).cuda())
+    s.load_faces(torch.from_numpy(F).cuda())
+    s.step(float(dts[0]))
+    out, Fo = s.prims().cpu().numpy(), s.faces().cpu().numpy()
+    rel = rel_l1(out, ref)
+    A, B = Fo[:, 3:-2, 3:-2, 3:-2], Fref[:, 3:-2, 3:-2, 3:-2]
+    rf = np.abs(A - B).sum() / np.abs(B).sum()
+    print("128^3 face-CT rel L1", rel, "faces", rf, "failures", fails)
+    assert rel.max() <= TOL and rf <= TOL
+    assert s.status()[0] == fails
+    assert s.face_divb()[0] < 1e-13 * np.abs(F).max() / min(grid.dx)
+
+
 def test_torus192_fp64_full_step():
     """The reduced-precision workload's grid in FP64 (the reference its error
     is stated against): 192^3, WENO5, one step."""

@@ -81,3 +81,19 @@ def test_floor_and_correction_parameters_are_validated():
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(donor)) > 0
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(donor)) == 0
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk())) > 0
+
+
+def test_face_ct_parameters_and_workspace():
+    from paper_2408_01361_amd import grmhd
+    from workloads import torus_grid
+    lib = grmhd.lib()
+    g = grmhd.make_grid(torus_grid(32, 32, 32))
+    mk = lambda **kw: grmhd.make_params(13 / 9, 0.9, 1e-26, 1e-14, 30, grmhd.RECON_WENO5,
+                                        grmhd.PREC_FP64, 0, 1e3, **kw)
+    base = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk()))
+    face = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(ct=grmhd.CT_FACE_GS)))
+    nz = 38 ** 3
+    assert face >= base + 13 * 8 * nz          # faces, stage faces, register, zone EMFs, mass-current scale
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(ct=3))) == 0
+    assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(ct=grmhd.CT_FACE_AVG))) == 0
+    assert lib.grmhd_load_faces(None, None) == grmhd.E_ARG
