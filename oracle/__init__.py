@@ -46,7 +46,7 @@ class Cfg(C.Structure):
                 ("u_over_rho_max", C.c_double), ("gamma_max", C.c_double),
                 ("fofc", C.c_int), ("ct", C.c_int)]
 
-INV_1DW, INV_KASTAUN = 0, 1
+INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 RECON_DONOR = 2
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
 FL_RHO, FL_U, FL_FLUID_FRAME, FL_GAMMA, FL_TEMP = 1, 2, 4, 8, 16
@@ -87,6 +87,8 @@ def _declare(lib):
     lib.orc_run_face.restype = C.c_long
     lib.orc_face_divb.argtypes = [P, _D, _D, _D]
     lib.orc_edge_emfs.argtypes = [P, _D, _D, _D]
+    lib.orc_qr_solve.argtypes = [_D, _D, _D]
+    lib.orc_qr_solve.restype = C.c_int
     lib.orc_weno5.argtypes = [C.c_double] * 6
     lib.orc_weno5.restype = C.c_double
     lib.orc_mc_slope.argtypes = [C.c_double] * 3
@@ -284,6 +286,15 @@ def point_floors(c, prims, x1, x2):
     p = np.array(prims, dtype=np.float64)
     m = lib().orc_point_floors(C.byref(c), _ptr(p), x1, x2)
     return p, m
+
+
+def qr_solve(A, b):
+    """The implicit solver's pivoted-QR solve of a 5 x 5 system: (y, ok)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    y = np.zeros(5)
+    ok = lib().orc_qr_solve(_ptr(A), _ptr(b), _ptr(y))
+    return y, bool(ok)
 
 
 def weno5(a, b, c_, d, e, eps=1e-26):

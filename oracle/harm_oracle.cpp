@@ -71,7 +71,8 @@ typedef struct {
   int newton_maxit;
   double cfl;
   int nthreads;
-  int inverter;        // 0: 1D_W (Noble et al.), 1: Kastaun et al. bracketed recovery
+  int inverter;        // 0: 1D_W (Noble et al.), 1: Kastaun et al. bracketed recovery,
+                       // 2: the implicit solver's Newton (secant Jacobian, pivoted QR)
   double kastaun_wmax; // Lorentz-factor cap of the Kastaun recovery
   int floors;          // 1: density/energy floors and ceilings after every inversion
   double rho_min_geom, u_min_geom;        // geometric floors rho r^-3/2, u r^-5/2
@@ -1020,7 +1021,165 @@ int u_to_p_kastaun(const orc_cfg& c, const Geom& G, const real U[NV], const real
   return 0;
 }
 
+// The implicit solver's Newton-Raphson used as the recovery (Implicit Solver
+// section: with all fluid variables implicit and only ideal sources it
+// solves U(P) = U* zone by zone).  Unknowns x = (rho, u, u~1, u~2, u~3), B
+// from U*; residual R(x) = (U(x) - U*)_{0..4} / s, s the largest |U*_k|;
+// Jacobian by forward differences (secant) with steps h_k = 1e-7 max(|x_k|,
+// f_k), f = (0, 0, 1e-3, 1e-3, 1e-3); the step solves J dx = -R by a QR
+// decomposition with column pivoting (Householder reflections, the column
+// of largest remaining norm first, ties to the lower index); backtracking
+// line search: lambda = 1, 1/2, ... (at most 8 halvings) until rho and u
+// stay positive and |R| decreases (the last try is taken if none does, if
+// rho and u are positive).  Stop when every |lambda dx_k| <= tol max(|x_k|,
+// f_k), tol = max(newton_tol, 1e-12), or after maxit iterations (failure);
+// failure (also non-finite, rho <= 0, u <= 0) keeps the guess's hydro
+// prims.  The 1e-12 floor: near the root the residual's roundoff makes
+// steps of ~1e-13 relative, so a smaller tolerance is never met; the step
+// that meets it has already brought x to roundoff (the secant Jacobian is
+// accurate to ~1e-7, so each step shrinks the error by about that much).
+void implicit_residual(const orc_cfg& c, const Geom& G, const real x[5], const real B[3], const real Us[NV],
+                       real scale, real R[5]) {
+  real P[NV] = {x[0], x[1], x[2], x[3], x[4], B[0], B[1], B[2]};
+  FluidState S;
+  fluid_state(P, G, S);
+  real U[NV];
+  prim_to_flux(P, S, G, c.gam, 0, U);
+  for (int k = 0; k < 5; k++) R[k] = (U[k] - Us[k]) / scale;
+}
+
+// Solve A y = b (5 x 5) by Householder QR with column pivoting; false if
+// the matrix is numerically singular or non-finite.
+bool qr_pivot_solve(real A[5][5], real b[5], real y[5]) {
+  int perm[5] = {0, 1, 2, 3, 4};
+  real cn[5];
+  for (int j = 0; j < 5; j++) {
+    cn[j] = 0.0;
+    for (int i = 0; i < 5; i++) cn[j] += A[i][j] * A[i][j];
+  }
+  for (int k = 0; k < 5; k++) {
+    // pivot: the column of largest remaining norm (rows k..4)
+    int best = k;
+    for (int j = k + 1; j < 5; j++)
+      if (cn[j] > cn[best]) best = j;
+    if (best != k) {
+      for (int i = 0; i < 5; i++) std::swap(A[i][k], A[i][best]);
+      std::swap(cn[k], cn[best]);
+      std::swap(perm[k], perm[best]);
+    }
+    real nrm = 0.0;
+    for (int i = k; i < 5; i++) nrm += A[i][k] * A[i][k];
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0) || !isfinite((real)nrm)) return false;
+    real alpha = A[k][k] > 0.0 ? -nrm : nrm;
+    // v = a_k - alpha e_k; H = I - 2 v v^T / (v^T v)
+    real v[5];
+    for (int i = 0; i < 5; i++) v[i] = i < k ? 0.0 : A[i][k];
+    v[k] = v[k] - alpha;
+    real vv = 0.0;
+    for (int i = k; i < 5; i++) vv += v[i] * v[i];
+    if (!(vv > 0.0)) return false;
+    for (int j = k; j < 5; j++) {
+      real d = 0.0;
+      for (int i = k; i < 5; i++) d += v[i] * A[i][j];
+      real f = 2.0 * d / vv;
+      for (int i = k; i < 5; i++) A[i][j] = A[i][j] - f * v[i];
+    }
+    real d = 0.0;
+    for (int i = k; i < 5; i++) d += v[i] * b[i];
+    real f = 2.0 * d / vv;
+    for (int i = k; i < 5; i++) b[i] = b[i] - f * v[i];
+    // remaining column norms (rows k+1..4)
+    for (int j = k + 1; j < 5; j++) {
+      cn[j] = 0.0;
+      for (int i = k + 1; i < 5; i++) cn[j] += A[i][j] * A[i][j];
+    }
+  }
+  real z[5];
+  for (int i = 4; i >= 0; i--) {
+    real t = b[i];
+    for (int j = i + 1; j < 5; j++) t = t - A[i][j] * z[j];
+    if (!(fabs(A[i][i]) > 0.0)) return false;
+    z[i] = t / A[i][i];
+  }
+  for (int k = 0; k < 5; k++) y[perm[k]] = z[k];
+  for (int k = 0; k < 5; k++)
+    if (!isfinite((real)y[k])) return false;
+  return true;
+}
+
+int u_to_p_implicit(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[NV], real P[NV]) {
+  for (int k = 0; k < 3; k++) P[B1 + k] = U[B1 + k] / G.gdet;
+  auto failed = [&]() {
+    for (int v = 0; v < 5; v++) P[v] = guess[v];
+    return 1;
+  };
+  const real B[3] = {P[B1], P[B2], P[B3]};
+  real scale = 0.0;
+  for (int k = 0; k < 5; k++)
+    if (fabs(U[k]) > scale) scale = fabs(U[k]);
+  if (!(scale > 0.0) || !isfinite((real)scale)) return failed();
+  const real fl[5] = {0.0, 0.0, 1e-3, 1e-3, 1e-3};
+  real x[5];
+  for (int k = 0; k < 5; k++) x[k] = guess[k];
+  if (!(x[0] > 0.0) || !(x[1] > 0.0)) return failed();
+  real R[5];
+  implicit_residual(c, G, x, B, U, scale, R);
+  real r2 = 0.0;
+  for (int k = 0; k < 5; k++) r2 += R[k] * R[k];
+  bool conv = false;
+  const real tol = c.newton_tol > 1e-12 ? c.newton_tol : 1e-12;
+  for (int it = 0; it < c.newton_maxit && !conv; it++) {
+    real J[5][5];
+    for (int k = 0; k < 5; k++) {
+      real ax = fabs(x[k]);
+      real h = 1e-7 * (ax > fl[k] ? ax : fl[k]);
+      real xp[5];
+      for (int m = 0; m < 5; m++) xp[m] = x[m];
+      xp[k] = x[k] + h;
+      real Rp[5];
+      implicit_residual(c, G, xp, B, U, scale, Rp);
+      real hh = xp[k] - x[k];
+      for (int m = 0; m < 5; m++) J[m][k] = (Rp[m] - R[m]) / hh;
+    }
+    real rhs[5], dx[5];
+    for (int m = 0; m < 5; m++) rhs[m] = -R[m];
+    if (!qr_pivot_solve(J, rhs, dx)) return failed();
+    real lam = 1.0, xn[5], Rn[5], rn2 = 0.0;
+    bool ok = false;
+    for (int ls = 0; ls <= 8; ls++) {
+      for (int m = 0; m < 5; m++) xn[m] = x[m] + lam * dx[m];
+      if (xn[0] > 0.0 && xn[1] > 0.0) {
+        implicit_residual(c, G, xn, B, U, scale, Rn);
+        rn2 = 0.0;
+        for (int m = 0; m < 5; m++) rn2 += Rn[m] * Rn[m];
+        ok = isfinite((real)rn2);
+        if (ok && rn2 < r2) break;
+      } else {
+        ok = false;
+      }
+      if (ls < 8) lam = 0.5 * lam;
+    }
+    if (!ok) return failed();
+    conv = true;
+    for (int m = 0; m < 5; m++) {
+      real ax = fabs(xn[m]);
+      if (fabs(xn[m] - x[m]) > tol * (ax > fl[m] ? ax : fl[m])) conv = false;
+      x[m] = xn[m];
+      R[m] = Rn[m];
+    }
+    r2 = rn2;
+  }
+  if (!conv) return failed();
+  for (int k = 0; k < 5; k++) {
+    if (!isfinite((real)x[k])) return failed();
+    P[k] = x[k];
+  }
+  return 0;
+}
+
 int invert(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[NV], real P[NV]) {
+  if (c.inverter == 2) return u_to_p_implicit(c, G, U, guess, P);
   return c.inverter == 1 ? u_to_p_kastaun(c, G, U, guess, P) : u_to_p(c, G, U, guess, P);
 }
 
@@ -1661,6 +1820,19 @@ int orc_point_floors(const orc_cfg* c, double* prims, double x1, double x2) {
   int m = apply_floors(*c, G, x1, p);
   for (int v = 0; v < NV; v++) prims[v] = (double)p[v];
   return m;
+}
+
+// The implicit solver's 5 x 5 solve (QR with column pivoting): y = A^-1 b
+// for A row-major; returns 0 if the matrix was found singular.
+int orc_qr_solve(const double* A, const double* b, double* y) {
+  real M[5][5], r[5], z[5];
+  for (int i = 0; i < 5; i++) {
+    r[i] = b[i];
+    for (int j = 0; j < 5; j++) M[i][j] = A[5 * i + j];
+  }
+  bool ok = qr_pivot_solve(M, r, z);
+  for (int i = 0; i < 5; i++) y[i] = (double)z[i];
+  return ok ? 1 : 0;
 }
 
 double orc_weno5(double a, double b, double c, double d, double e, double eps) {

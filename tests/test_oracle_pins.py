@@ -937,3 +937,64 @@ def test_face_ct_linear_mode_convergence(ct):
         errs.append([np.mean(np.abs(interior(out[v] - Pe[v]))) for v in range(8) if abs(info["r"][v]) > 0])
     slope = np.log2(np.array(errs[0]) / np.array(errs[1]))
     assert np.all((slope > 1.9) & (slope < 2.1)), slope
+
+
+# ------------------------------------------------------- the implicit solver
+
+def test_implicit_solver_qr_with_pivoting():
+    """The 5 x 5 solve of the implicit solver's Newton step against numpy's
+    LU solve: random systems, a system whose first pivot is zero (row/column
+    pivoting needed), a badly scaled one; a singular matrix is reported."""
+    rng = np.random.default_rng(51)
+    for q in range(50):
+        A = rng.normal(size=(5, 5))
+        b = rng.normal(size=5)
+        y, ok = oracle.qr_solve(A, b)
+        assert ok
+        ref = np.linalg.solve(A, b)
+        assert np.abs(y - ref).max() < 1e-12 * np.abs(ref).max() * np.linalg.cond(A)
+    A = rng.normal(size=(5, 5))
+    A[:, 0] = rng.normal(size=5) * np.array([0, 1, 1, 1, 1])   # zero first pivot
+    b = rng.normal(size=5)
+    y, ok = oracle.qr_solve(A, b)
+    assert ok and np.abs(A @ y - b).max() < 1e-12
+    # badly scaled rows: backward stable (residual at roundoff of |S| |y|)
+    S = np.diag([1e-8, 1.0, 1e4, 1.0, 1e-3]) @ rng.normal(size=(5, 5))
+    y, ok = oracle.qr_solve(S, b)
+    assert ok and np.abs(S @ y - b).max() < 1e-13 * np.abs(S).max() * np.abs(y).max()
+    # two equal columns: no exact solution for a generic b
+    Z = rng.normal(size=(5, 5))
+    Z[:, 3] = Z[:, 1]
+    y, ok = oracle.qr_solve(Z, b)
+    assert not ok or np.abs(Z @ y - b).max() > 1e-6
+
+
+@pytest.mark.parametrize("metric", ["flat", "kerr"])
+def test_implicit_solver_round_trip(metric):
+    """P -> U -> P through the implicit solver's Newton (secant Jacobian,
+    pivoted QR, line search) from a 5 % perturbed guess, on the fuzzed set
+    of the 1D_W round trip: every point recovered, to 1e-10."""
+    rng = np.random.default_rng(3)
+    base = flat_cfg(13 / 9) if metric == "flat" else kerr_cfg()
+    c = oracle.cfg(GridSpec(4, 4, 4) if metric == "flat" else torus_grid(8, 8, 1), gam=13 / 9,
+                   inverter=oracle.INV_IMPLICIT)
+    n = 400
+    x1, x2 = random_points(rng, n)
+    prims = _random_prims(rng, n, base, x1, x2)
+    g2 = np.random.default_rng(4)
+    errs, fails = _round_trip_errors(c, rng, prims, x1, x2, lambda P: P * (1 + 0.05 * g2.uniform(-1, 1, 8)))
+    assert fails == 0 and errs.max() < 1e-10, (fails, errs.max())
+
+
+def test_implicit_solver_step_matches_1dw_step():
+    """Two torus steps with the implicit solver as the recovery equal 1D_W's
+    (same failed zones, prims to 1e-12)."""
+    from parity_util import rel_l1
+    grid, P, _ = fm_torus(16, 20, 4)
+    cw = oracle.cfg(grid, gam=13 / 9, recon=RECON_MC)
+    ci = oracle.cfg(grid, gam=13 / 9, recon=RECON_MC, inverter=oracle.INV_IMPLICIT)
+    dt = oracle.estimate_dt(cw, P)
+    aw, fw, _, flw = oracle.run(cw, P, dt, 2, flags=True)
+    ai, fi, _, fli = oracle.run(ci, P, dt, 2, flags=True)
+    assert fi == fw and np.array_equal(flw, fli)
+    assert rel_l1(ai, aw).max() < 1e-12
