@@ -219,12 +219,14 @@ def extras(torch, gr, np, args):
 
 
 def kastaun_extra(torch, gr, grid, P, gam, recon, steps):
-    """The headline workload with the Kastaun et al. bracketed recovery in
-    place of 1D_W, each timed the same way (whole steps, then the two update
-    kernels, which hold the inversion, with per-launch events)."""
+    """The headline workload with the Kastaun et al. bracketed recovery and
+    with the implicit solver's Newton in place of 1D_W, each timed the same
+    way (whole steps, then the update classes, which hold the inversion --
+    for the implicit recovery the update that stores U* plus the solver's
+    own pass -- with per-launch events)."""
     Pt = torch.from_numpy(P).cuda()
     res = {}
-    for name, inv in (("1dw", gr.INV_1DW), ("kastaun", gr.INV_KASTAUN)):
+    for name, inv in (("1dw", gr.INV_1DW), ("kastaun", gr.INV_KASTAUN), ("implicit", gr.INV_IMPLICIT)):
         s = gr.Grmhd(grid, gam, recon=recon, inverter=inv)
         s.load(Pt)
         for _ in range(10):          # untimed: clocks settle
@@ -240,11 +242,12 @@ def kastaun_extra(torch, gr, grid, P, gam, recon, steps):
         s.timing(False)
         res[name] = {"zone_cycles_per_s": grid.n1 * grid.n2 * grid.n3 * steps / el,
                      "ms_per_step": el * 1e3 / steps,
-                     "update_avg_us": {k: 1e3 * rep[k][0] / max(rep[k][1], 1) for k in ("update1", "update2")},
+                     "update_us_per_step": {k: 1e3 * rep[k][0] / steps for k in ("update1", "update2")},
                      "inversion_failures": fails}
         del s
     res["workload"] = "the headline torus and step, inverter swapped"
     res["kastaun_over_1dw_time"] = res["kastaun"]["ms_per_step"] / res["1dw"]["ms_per_step"]
+    res["implicit_over_1dw_time"] = res["implicit"]["ms_per_step"] / res["1dw"]["ms_per_step"]
     return res
 
 
@@ -291,6 +294,39 @@ def floors_fofc_extra(torch, gr, grid, P, gam, recon, steps):
                          "steps at the CFL dt from the initial state")
     out["blast"] = blast
     return out
+
+
+def face_ct_extra(torch, gr, grid, P, info, gam, recon, steps):
+    """The headline torus step with face-centred CT (averaged and upwinded
+    edge EMFs) beside Flux-CT: whole steps, then a per-class breakdown."""
+    Pt = torch.from_numpy(P).cuda()
+    Ft = torch.from_numpy(info["faces"]).cuda()
+    res = {}
+    for name, ct in (("flux_ct", gr.CT_FLUX), ("face_avg", gr.CT_FACE_AVG), ("face_gs", gr.CT_FACE_GS)):
+        s = gr.Grmhd(grid, gam, recon=recon, ct=ct)
+
+        def load():
+            s.load(Pt)
+            if ct != gr.CT_FLUX:
+                s.load_faces(Ft)
+        load()
+        for _ in range(10):          # untimed: clocks settle
+            s.step_cfl()
+        load()
+        el = time_steps(torch, s, steps)
+        load()
+        s.timing(True)
+        time_steps(torch, s, steps)
+        rep = s.timing_report()
+        s.timing(False)
+        res[name] = {"zone_cycles_per_s": grid.n1 * grid.n2 * grid.n3 * steps / el,
+                     "ms_per_step": el * 1e3 / steps,
+                     "kernels_us_per_step": {k: round(1e3 * v[0] / steps, 1) for k, v in rep.items() if v[1]}}
+        if ct != gr.CT_FLUX:
+            res[name]["face_divb_max"] = s.face_divb()[0]
+        del s
+    res["workload"] = "the headline torus and step; face fields from the same vector potential"
+    return res
 
 
 def adjoint_extra(torch, gr):
@@ -438,6 +474,7 @@ def main():
         out.update(extras(torch, gr, np, args))
         out["inverters"] = kastaun_extra(torch, gr, grid, P, gam, recon, args.steps)
         out["floors_fofc"] = floors_fofc_extra(torch, gr, grid, P, gam, recon, args.steps)
+        out["face_ct"] = face_ct_extra(torch, gr, grid, P, info, gam, recon, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_baseline(grid, P, gam, recon, args.cpu_seconds)
     print(json.dumps(out))

@@ -45,7 +45,7 @@ enum { GRMHD_OK = 0, GRMHD_E_ARG = -1, GRMHD_E_HIP = -2, GRMHD_E_STATE = -3,
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KERR_MKS = 1 };
 enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_DONOR = 2 };
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
-enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1 };
+enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1, GRMHD_INV_IMPLICIT = 2 };
 enum { GRMHD_CT_FLUX = 0, GRMHD_CT_FACE_AVG = 1, GRMHD_CT_FACE_GS = 2 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2,
        GRMHD_BC_FROZEN = 3 };
@@ -83,7 +83,13 @@ typedef struct {
                          or the Kastaun et al. root bracket in mu = 1/(h W),
                          which needs no guess (Illinois iteration stopped at
                          |d mu| <= newton_tol mu, at most 4 newton_maxit
-                         iterations); both leave a failed zone at its guess */
+                         iterations), or IMPLICIT: the implicit solver's
+                         per-zone Newton on U(P) = U* over (rho, u, u~)
+                         (Implicit Solver section: secant Jacobian, QR with
+                         column pivoting, backtracking line search; step
+                         tolerance max(newton_tol, 1e-12)), run as a pass of
+                         its own after the update (not with fofc); all leave
+                         a failed zone at its guess */
   double kastaun_wmax; /* Lorentz-factor cap of the Kastaun recovery (> 1);
                           ignored by 1D_W */
   /* Floors (Physics section: material and energy injected where density or
@@ -220,8 +226,9 @@ int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
  * 256-byte aligned, >= grmhd_vjp_workspace_bytes()).  Neither the context's
  * state nor its failure count changes.  Synchronises.  E_STATE for the mixed
  * precision path, floors, the first-order flux correction, donor-cell
- * reconstruction or face-centred CT (the adjoint covers the plain
- * high-order Flux-CT step; the workspace size is then 0). */
+ * reconstruction, face-centred CT or the implicit recovery (the adjoint
+ * covers the plain high-order Flux-CT step; the workspace size is then
+ * 0). */
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params);
 int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const double* d_gprims_out,
                    double* d_gprims_in, double* g_gamma, void* d_vjp_ws, size_t vjp_ws_bytes);
@@ -237,8 +244,8 @@ int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const do
  * (0, 0, 0): runs of 256 consecutive positions of each box in x1-fastest
  * order, the default) only change speed.  Errors as for single contexts; E_ARG for blocks outside the
  * global grid, a non-FP64 precision, floors, the first-order flux
- * correction, donor-cell reconstruction or face-centred CT (packs advance
- * the plain high-order Flux-CT step). */
+ * correction, donor-cell reconstruction, face-centred CT or the implicit
+ * recovery (packs advance the plain high-order Flux-CT step). */
 typedef struct grmhd_pack grmhd_pack;
 size_t grmhd_pack_workspace_bytes(int nblocks, const int* n);
 int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* offsets_ijk,

@@ -954,6 +954,216 @@ __device__ int invert_kastaun(const Dev& g, const PointMetric<double>& m, const 
   return 0;
 }
 
+// The implicit solver's per-zone Newton-Raphson used as the recovery
+// (Implicit Solver section: with every fluid variable implicit and only
+// ideal sources it solves U(P) = U* zone by zone).  Unknowns x = (rho, u,
+// u~1, u~2, u~3), B from U*; residual R(x) = (U(x) - U*)_{0..4} / s, s the
+// largest |U*_k|; Jacobian by forward differences (secant) with steps
+// h_k = 1e-7 max(|x_k|, f_k), f = (0, 0, 1e-3, 1e-3, 1e-3); the step from a
+// Householder QR of J with column pivoting (largest remaining column norm
+// first, ties to the lower index); backtracking line search lambda = 1,
+// 1/2, ... (at most 8 halvings) until rho, u > 0 and |R| decreases (the last
+// try is taken otherwise, if rho, u > 0); converged when every |lambda dx_k|
+// <= max(tol, 1e-12) max(|x_k|, f_k) (near the root the residual's roundoff
+// makes ~1e-13 steps), failure after maxit iterations or on non-finite
+// values keeps the guess.  Unrolled so that the 5 x 5 system stays in
+// registers (no dynamic indexing); same operation order as the CPU
+// reference of the method, without contraction.
+__device__ __forceinline__ void implicit_residual(const Dev& g, const PointMetric<double>& m, const double x[5],
+                                                  const double B[3], const double Us[NVAR], double scale,
+                                                  double R[5]) {
+#pragma clang fp contract(off)
+  const double P[NVAR] = {x[0], x[1], x[2], x[3], x[4], B[0], B[1], B[2]};
+  Fluid<double> f;
+  fluid_state(P, m, f);
+  double U[NVAR];
+  prim_to_flux(P, f, m, g.gam, 0, U);
+#pragma unroll
+  for (int k = 0; k < 5; k++) R[k] = (U[k] - Us[k]) / scale;
+}
+
+__device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], double y[5]) {
+#pragma clang fp contract(off)
+  int perm[5] = {0, 1, 2, 3, 4};
+  double cn[5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) {
+    cn[j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 5; i++) cn[j] += A[i][j] * A[i][j];
+  }
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    int best = k;
+    double cb = cn[k];
+#pragma unroll
+    for (int j = k + 1; j < 5; j++)
+      if (cn[j] > cb) {
+        cb = cn[j];
+        best = j;
+      }
+#pragma unroll
+    for (int j = k + 1; j < 5; j++)
+      if (j == best) {
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+          const double t = A[i][k];
+          A[i][k] = A[i][j];
+          A[i][j] = t;
+        }
+        const double t = cn[k];
+        cn[k] = cn[j];
+        cn[j] = t;
+        const int tp = perm[k];
+        perm[k] = perm[j];
+        perm[j] = tp;
+      }
+    double nrm = 0.0;
+#pragma unroll
+    for (int i = k; i < 5; i++) nrm += A[i][k] * A[i][k];
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0) || !isfinite(nrm)) return false;
+    const double alpha = A[k][k] > 0.0 ? -nrm : nrm;
+    double v[5];
+#pragma unroll
+    for (int i = 0; i < 5; i++) v[i] = i < k ? 0.0 : A[i][k];
+    v[k] = v[k] - alpha;
+    double vv = 0.0;
+#pragma unroll
+    for (int i = k; i < 5; i++) vv += v[i] * v[i];
+    if (!(vv > 0.0)) return false;
+#pragma unroll
+    for (int j = k; j < 5; j++) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = k; i < 5; i++) d += v[i] * A[i][j];
+      const double f = 2.0 * d / vv;
+#pragma unroll
+      for (int i = k; i < 5; i++) A[i][j] = A[i][j] - f * v[i];
+    }
+    double d = 0.0;
+#pragma unroll
+    for (int i = k; i < 5; i++) d += v[i] * b[i];
+    const double f = 2.0 * d / vv;
+#pragma unroll
+    for (int i = k; i < 5; i++) b[i] = b[i] - f * v[i];
+#pragma unroll
+    for (int j = k + 1; j < 5; j++) {
+      cn[j] = 0.0;
+#pragma unroll
+      for (int i = k + 1; i < 5; i++) cn[j] += A[i][j] * A[i][j];
+    }
+  }
+  double z[5];
+#pragma unroll
+  for (int i = 4; i >= 0; i--) {
+    double t = b[i];
+#pragma unroll
+    for (int j = i + 1; j < 5; j++) t = t - A[i][j] * z[j];
+    if (!(fabs(A[i][i]) > 0.0)) return false;
+    z[i] = t / A[i][i];
+  }
+#pragma unroll
+  for (int mm = 0; mm < 5; mm++) {
+    double val = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; k++)
+      if (perm[k] == mm) val = z[k];
+    y[mm] = val;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; k++)
+    if (!isfinite(y[k])) return false;
+  return true;
+}
+
+__device__ __forceinline__ int invert_implicit(const Dev& g, const PointMetric<double>& m, const double U[NVAR],
+                                               const double guess[NVAR], double P[NVAR]) {
+#pragma clang fp contract(off)
+  const double gd = m.gdet;
+  P[B1] = U[B1] / gd;
+  P[B2] = U[B2] / gd;
+  P[B3] = U[B3] / gd;
+  auto fail = [&]() {
+#pragma unroll
+    for (int v = 0; v < 5; v++) P[v] = guess[v];
+    return 1;
+  };
+  const double B[3] = {P[B1], P[B2], P[B3]};
+  double scale = 0.0;
+#pragma unroll
+  for (int k = 0; k < 5; k++)
+    if (fabs(U[k]) > scale) scale = fabs(U[k]);
+  if (!(scale > 0.0) || !isfinite(scale)) return fail();
+  const double fl[5] = {0.0, 0.0, 1e-3, 1e-3, 1e-3};
+  double x[5];
+#pragma unroll
+  for (int k = 0; k < 5; k++) x[k] = guess[k];
+  if (!(x[0] > 0.0) || !(x[1] > 0.0)) return fail();
+  double R[5];
+  implicit_residual(g, m, x, B, U, scale, R);
+  double r2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 5; k++) r2 += R[k] * R[k];
+  bool conv = false;
+  const double tol = g.tol > 1e-12 ? g.tol : 1e-12;
+  for (int it = 0; it < g.maxit && !conv; it++) {
+    double J[5][5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+      const double ax = fabs(x[k]);
+      const double h = 1e-7 * (ax > fl[k] ? ax : fl[k]);
+      double xp[5];
+#pragma unroll
+      for (int mm = 0; mm < 5; mm++) xp[mm] = x[mm];
+      xp[k] = x[k] + h;
+      double Rp[5];
+      implicit_residual(g, m, xp, B, U, scale, Rp);
+      const double hh = xp[k] - x[k];
+#pragma unroll
+      for (int mm = 0; mm < 5; mm++) J[mm][k] = (Rp[mm] - R[mm]) / hh;
+    }
+    double rhs[5], dx[5];
+#pragma unroll
+    for (int mm = 0; mm < 5; mm++) rhs[mm] = -R[mm];
+    if (!qr_pivot_solve(J, rhs, dx)) return fail();
+    double lam = 1.0, xn[5], Rn[5], rn2 = 0.0;
+    bool ok = false;
+    for (int ls = 0; ls <= 8; ls++) {
+#pragma unroll
+      for (int mm = 0; mm < 5; mm++) xn[mm] = x[mm] + lam * dx[mm];
+      if (xn[0] > 0.0 && xn[1] > 0.0) {
+        implicit_residual(g, m, xn, B, U, scale, Rn);
+        rn2 = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < 5; mm++) rn2 += Rn[mm] * Rn[mm];
+        ok = isfinite(rn2);
+        if (ok && rn2 < r2) break;
+      } else {
+        ok = false;
+      }
+      if (ls < 8) lam = 0.5 * lam;
+    }
+    if (!ok) return fail();
+    conv = true;
+#pragma unroll
+    for (int mm = 0; mm < 5; mm++) {
+      const double ax = fabs(xn[mm]);
+      if (fabs(xn[mm] - x[mm]) > tol * (ax > fl[mm] ? ax : fl[mm])) conv = false;
+      x[mm] = xn[mm];
+      R[mm] = Rn[mm];
+    }
+    r2 = rn2;
+  }
+  if (!conv) return fail();
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    if (!isfinite(x[k])) return fail();
+    P[k] = x[k];
+  }
+  return 0;
+}
+
 __device__ __forceinline__ int invert(const Dev& g, const PointMetric<double>& m, const double U[NVAR],
                                       const double guess[NVAR], double P[NVAR]) {
   if (g.inverter == GRMHD_INV_KASTAUN) return invert_kastaun(g, m, U, guess, P);
@@ -1162,7 +1372,7 @@ __device__ __forceinline__ void geometric_source(const double p[NVAR], const Flu
 // nothing else) and FINAL (the same update from the corrected fluxes,
 // counted).  Floors run in a kernel of their own after each update pass
 // (k_floors), with the same modes.
-enum { U_PLAIN = 0, U_PROVISIONAL = 2, U_FINAL = 3 };
+enum { U_PLAIN = 0, U_PROVISIONAL = 2, U_FINAL = 3, U_STORE = 4 };
 // Counter slots of the context's counter array.
 enum { C_FAILS = 0, C_C2P = 1, C_FLOORS = 2, C_FOFC = 3, C_FLUID = 4, C_MARKS = 5 };
 
@@ -1179,7 +1389,8 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
                                             unsigned char* __restrict__ mark = nullptr,
                                             const double* __restrict__ ph1 = nullptr,
                                             const double* __restrict__ ph2 = nullptr,
-                                            const double* __restrict__ ph3 = nullptr) {
+                                            const double* __restrict__ ph3 = nullptr,
+                                            double* __restrict__ ustar = nullptr) {
   // the FP64 update is rounded operation by operation, in the order written
 #pragma clang fp contract(off)
   const long c = zid(g, i, j, k), nz = g.nz, si = 1, sj = g.s1, sk = g.plane;
@@ -1240,6 +1451,11 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
     U[B2] = 0.5 * (ph2[c] + ph2[c + sj]);
     U[B3] = 0.5 * (ph3[c] + ph3[c + sk]);
   }
+  if constexpr (MODE == U_STORE) {  // the implicit solver recovers the prims in its own pass
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) ustar[v * nz + c] = U[v];
+    return;
+  }
   double out[NVAR];
   int bad = invert(g, m, U, p, out);
 #pragma unroll
@@ -1270,7 +1486,7 @@ k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ 
          double dt, const double* __restrict__ dt_dev, unsigned long long* fails,
          unsigned char* __restrict__ flags, double* __restrict__ rate_partial,
          unsigned char* __restrict__ mark, const double* __restrict__ ph1,
-         const double* __restrict__ ph2, const double* __restrict__ ph3) {
+         const double* __restrict__ ph2, const double* __restrict__ ph3, double* __restrict__ ustar) {
   if (MODE == U_FINAL) {
     const unsigned long long nmark = fails[C_MARKS];
     if (nmark == 0) return;
@@ -1282,13 +1498,13 @@ k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ 
   if (!RATE) {
     if (in)
       update_zone<STAGE, FT, false, MODE, FACE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt,
-                                                fails, flags, i, j, k, nullptr, mark, ph1, ph2, ph3);
+                                                fails, flags, i, j, k, nullptr, mark, ph1, ph2, ph3, ustar);
     return;
   }
   double r = 0.0, sm = 0.0;
   if (in)
     update_zone<STAGE, FT, true, MODE, FACE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
-                                             flags, i, j, k, &r, mark, ph1, ph2, ph3);
+                                             flags, i, j, k, &r, mark, ph1, ph2, ph3, ustar);
   block_reduce(r, sm);
   if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
 }
@@ -1345,6 +1561,44 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8
         if (fl & FL_FLUID_FRAME) atomicAdd(&fails[C_FLUID], 1ull);
       }
     }
+    if (RATE) r = zone_rate(g, out, m);
+  }
+  if (RATE) {
+    double sm = 0.0;
+    block_reduce(r, sm);
+    if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
+  }
+}
+
+// The implicit solver's pass: per zone, the prims whose conserved variables
+// are the U* the update stored, from the stage input as the guess (the
+// update's inversion, for the implicit recovery).  Failures counted and
+// flagged as the update counts them; with RATE the CFL-rate partials of the
+// new prims, over the update's schedule.  Its own register budget (the
+// 5 x 5 Newton system lives in registers).
+template <bool RATE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_implicit(Dev g, Sched box, const double* __restrict__ Pin, const double* __restrict__ ustar,
+           double* __restrict__ Pout, const double* __restrict__ tabC, unsigned long long* fails,
+           unsigned char* __restrict__ flags, double* __restrict__ rate_partial) {
+  int i, j, k;
+  const bool in = sched_index(box, blockIdx.x, gridDim.x, i, j, k);
+  double r = 0.0;
+  if (in) {
+    const long c = zid(g, i, j, k), nz = g.nz;
+    double U[NVAR], p[NVAR], out[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) {
+      U[v] = ustar[v * nz + c];
+      p[v] = Pin[v * nz + c];
+    }
+    PointMetric<double> m;
+    load_metric<double>(tabC, g.plane, pid(g, i, j), m);
+    const int bad = invert_implicit(g, m, U, p, out);
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
+    if (flags) flags[c] = (unsigned char)bad;
+    if (bad) atomicAdd(&fails[C_FAILS], 1ull);
     if (RATE) r = zone_rate(g, out, m);
   }
   if (RATE) {
@@ -1501,7 +1755,7 @@ __global__ void __launch_bounds__(BLOCK) k_cons_to_prims(Dev g, Box box, const d
   }
   PointMetric<double> m;
   load_metric<double>(tabC, g.plane, pid(g, i, j), m);
-  int bad = invert(g, m, u, gs, p);
+  int bad = g.inverter == GRMHD_INV_IMPLICIT ? invert_implicit(g, m, u, gs, p) : invert(g, m, u, gs, p);
 #pragma unroll
   for (int v = 0; v < NVAR; v++) P[v * g.nz + c] = p[v];
   if (flags) flags[c] = bad;
@@ -1534,6 +1788,7 @@ struct grmhd_ctx {
          *phiV[3] = {nullptr, nullptr, nullptr};
   void* Ec[4] = {nullptr, nullptr, nullptr, nullptr};  // EMFs, then the mass-current scale
   bool faces_loaded = false;
+  double* ustar = nullptr;    // implicit recovery: the stage's target conserved variables
   double* pdt;              // CFL-rate partials left by the last stage-2 update
   bool rate_ready = false;  // pdt describes the current state (rate_n partials)
   bool ghosts_valid = false;  // the ghost zones of P hold the boundary conditions of its interior
@@ -1585,12 +1840,15 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
   if (p->floors && !(p->rho_min_geom > 0.0 && p->u_min_geom > 0.0 && p->bsq_over_rho_max > 0.0 &&
                      p->bsq_over_u_max > 0.0 && p->u_over_rho_max > 0.0 && p->gamma_max > 1.0))
     return false;
-  if (p->inverter != GRMHD_INV_1DW && p->inverter != GRMHD_INV_KASTAUN) return false;
+  if (p->inverter != GRMHD_INV_1DW && p->inverter != GRMHD_INV_KASTAUN && p->inverter != GRMHD_INV_IMPLICIT)
+    return false;
+  // the implicit recovery runs in a pass of its own, without the correction's marks
+  if (p->inverter == GRMHD_INV_IMPLICIT && p->fofc) return false;
   if (p->inverter == GRMHD_INV_KASTAUN && !(p->kastaun_wmax > 1.0)) return false;
   return true;
 }
 
-size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, int ct) {
+size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, int ct, int inverter) {
   long nz = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * (g->n3 + 2 * NG);
   long plane = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG);
   Carve cv;
@@ -1621,8 +1879,10 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, int ct) {
     }
     Ec[3] = cv.take<double>(base, nz);
   }
+  double* ustar = inverter == GRMHD_INV_IMPLICIT ? cv.take<double>(base, NVAR * nz) : nullptr;
   if (c) {
     c->mark = mark;
+    c->ustar = ustar;
     for (int d = 0; d < 3; d++) {
       c->phi[d] = phi[d];
       c->phi1[d] = phi1[d];
@@ -1796,7 +2056,7 @@ int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
     return launch(c, cls, kernel, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1],
                   (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2],
                   (const double*)c->tabC, (const double*)c->conn, dt, dt_dev, fails ? fails : c->fails, flags,
-                  partial, c->mark, p1, p2, p3);
+                  partial, c->mark, p1, p2, p3, c->ustar);
   };
   if constexpr (STAGE == 2) {
     if (rate && nb <= (unsigned)MAX_PARTIALS)
@@ -1837,6 +2097,22 @@ int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double
   if (!c->params.fofc) {
     if ((rc = stage_fluxes<R, FT>(c, Pin, nullptr, phin))) return rc;
     if (faces && (rc = stage_faces<STAGE, FT>(c, dt, dt_dev, nullptr))) return rc;
+    if (c->params.inverter == GRMHD_INV_IMPLICIT) {
+      // the update stores U*, the implicit solver's pass recovers the prims
+      if ((rc = stage_update<STAGE, FT, U_STORE>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, false))) return rc;
+      const Dev& g = c->dev;
+      Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
+      const unsigned nb = blocks_for(bz);
+      const int cls = STAGE == 1 ? T_UPDATE1 : T_UPDATE2;
+      if (STAGE == 2 && urate && nb <= (unsigned)MAX_PARTIALS)
+        rc = launch(c, cls, k_implicit<true>, nb, g, bz, Pin, (const double*)c->ustar, Pout,
+                    (const double*)c->tabC, c->fails, (unsigned char*)nullptr, c->pdt);
+      else
+        rc = launch(c, cls, k_implicit<false>, nb, g, bz, Pin, (const double*)c->ustar, Pout,
+                    (const double*)c->tabC, c->fails, (unsigned char*)nullptr, (double*)nullptr);
+      if (rc) return rc;
+      return floors ? stage_floors<STAGE, U_PLAIN>(c, Pin, Pout, rate) : GRMHD_OK;
+    }
     if ((rc = stage_update<STAGE, FT, U_PLAIN>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, urate))) return rc;
     return floors ? stage_floors<STAGE, U_PLAIN>(c, Pin, Pout, rate) : GRMHD_OK;
   }
@@ -1916,7 +2192,7 @@ extern "C" {
 
 size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
   if (!grid_ok(grid, params)) return 0;
-  return carve(nullptr, nullptr, grid, params->ct);
+  return carve(nullptr, nullptr, grid, params->ct, params->inverter);
 }
 
 int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* metric,
@@ -1925,14 +2201,14 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   if (metric->metric != GRMHD_METRIC_MINKOWSKI && metric->metric != GRMHD_METRIC_KERR_MKS)
     return GRMHD_E_ARG;
   if (((uintptr_t)d_workspace & 255) != 0) return GRMHD_E_ARG;
-  if (ws_bytes < carve(nullptr, nullptr, grid, params->ct)) return GRMHD_E_NOMEM;
+  if (ws_bytes < carve(nullptr, nullptr, grid, params->ct, params->inverter)) return GRMHD_E_NOMEM;
   grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
   if (!c) return GRMHD_E_NOMEM;
   c->grid = *grid;
   c->metric = *metric;
   c->params = *params;
   c->stream = (hipStream_t)hip_stream;
-  carve(c, (char*)d_workspace, grid, params->ct);
+  carve(c, (char*)d_workspace, grid, params->ct, params->inverter);
   Dev& g = c->dev;
   g.n1 = grid->n1; g.n2 = grid->n2; g.n3 = grid->n3;
   g.s1 = g.n1 + 2 * NG; g.s2 = g.n2 + 2 * NG; g.s3 = g.n3 + 2 * NG;
@@ -2323,7 +2599,7 @@ extern "C" {
 
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
   if (!grid_ok(grid, params) || params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR ||
-      params->ct != GRMHD_CT_FLUX)
+      params->ct != GRMHD_CT_FLUX || params->inverter == GRMHD_INV_IMPLICIT)
     return 0;
   return vjp_carve(grid, params->recon, nullptr, nullptr);
 }
@@ -2335,7 +2611,7 @@ int grmhd_step_vjp(grmhd_ctx* c, const double* d_prims_in, double dt, const doub
   if (c->params.precision != GRMHD_PREC_FP64) return GRMHD_E_STATE;
   // the adjoint covers the plain high-order step (no floors, no correction)
   if (c->params.floors || c->params.fofc || c->params.recon == GRMHD_RECON_DONOR ||
-      c->params.ct != GRMHD_CT_FLUX)
+      c->params.ct != GRMHD_CT_FLUX || c->params.inverter == GRMHD_INV_IMPLICIT)
     return GRMHD_E_STATE;
   if (((uintptr_t)d_vjp_ws & 255) != 0) return GRMHD_E_ARG;
   if (vjp_ws_bytes < vjp_carve(&c->grid, c->params.recon, nullptr, nullptr)) return GRMHD_E_NOMEM;
@@ -2502,7 +2778,8 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
   if (!out || nblocks < 1 || !n || !offsets_ijk || !global || !metric || !params || !d_ws) return GRMHD_E_ARG;
   if (!grid_ok(global, params) || params->precision != GRMHD_PREC_FP64) return GRMHD_E_ARG;
   // packs advance the plain high-order step
-  if (params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR || params->ct != GRMHD_CT_FLUX)
+  if (params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR || params->ct != GRMHD_CT_FLUX ||
+      params->inverter == GRMHD_INV_IMPLICIT)
     return GRMHD_E_ARG;
   if (((uintptr_t)d_ws & 255) != 0) return GRMHD_E_ARG;
   for (int b = 0; b < nblocks; b++) {

@@ -17,7 +17,7 @@ OK, E_ARG, E_HIP, E_STATE, E_NOMEM = 0, -1, -2, -3, -4
 METRIC_MINKOWSKI, METRIC_KERR_MKS = 0, 1
 RECON_MC, RECON_WENO5, RECON_DONOR = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-INV_1DW, INV_KASTAUN = 0, 1
+INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
 BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN = 0, 1, 2, 3
 NG, NVAR = 3, 8

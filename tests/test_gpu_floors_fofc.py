@@ -73,6 +73,14 @@ def test_kastaun_with_floors_and_fofc():
     assert cnt == st and r.max() <= TOL
 
 
+def test_implicit_recovery_with_floors():
+    grid, P = magnetised_blast(48)
+    out, ref, cnt, st, _, _ = run_both(grid, P, 4 / 3, RECON_WENO5, 6, True, False, inverter=2)
+    r = rel_l1(out, ref)
+    print("implicit blast floors", cnt, st, r)
+    assert cnt == st and r.max() <= TOL
+
+
 def test_donor_cell_step_parity():
     """The first-order scheme alone (donor-cell states everywhere)."""
     for make, gam in ((lambda: linear_mode("fast", 32, ndim=2)[0:2], 4 / 3),

@@ -71,6 +71,25 @@ def test_torus128_weno5_kastaun_full_step():
     assert s.status()[0] == fails
 
 
+def test_torus128_weno5_implicit_recovery_full_step():
+    """The benchmark workload with the implicit solver's Newton as the
+    recovery: one device-side CFL step, every zone against the oracle."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    grid, P, _ = fm_torus(128, 128, 128, seed=1, gamma=gam)
+    s = gr.Grmhd(grid, gam, recon=RECON_WENO5, inverter=gr.INV_IMPLICIT)
+    s.load(torch.from_numpy(P).cuda())
+    s.step_cfl()
+    dt = s.last_dt()
+    out = s.prims().cpu().numpy()
+    c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, nthreads=THREADS, inverter=oracle.INV_IMPLICIT)
+    ref, fails, _ = oracle.run(c, P, dt, 1)
+    rel = rel_l1(out, ref)
+    print("128^3 WENO5 implicit recovery rel L1", rel, "failures", fails)
+    assert rel.max() <= TOL, rel
+    assert s.status()[0] == fails
+
+
 def test_torus128_weno5_face_ct_full_step():
     """The benchmark workload with face-centred CT (upwinded EMFs): one step
     at the oracle's dt, every zone and every evolved face against the

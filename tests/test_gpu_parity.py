@@ -94,6 +94,47 @@ def test_step_parity_kastaun(case):
     assert r.max() <= tol, r
 
 
+IMPLICIT_CASES = ["fast32_mc", "torus24_weno", "torus20x28x6_mc", "bondi32x16_mc"]
+
+
+@pytest.mark.parametrize("case", IMPLICIT_CASES)
+def test_step_parity_implicit_recovery(case):
+    """The same steps with the implicit solver's Newton as the recovery on
+    both sides (its own pass on the GPU)."""
+    (grid, P), gam, recon, tol = CASES[case]()
+    c = oracle.cfg(grid, gam=gam, recon=recon, inverter=oracle.INV_IMPLICIT)
+    ref, fails, dts, flags = oracle.run(c, P, -1, 2, flags=True)
+    out, gfails, s = run_gpu(grid, P, gam, recon, dts, inverter=oracle.INV_IMPLICIT)
+    r = rel_l1(out, ref)
+    print(case, "implicit dts", dts, "fails", fails, gfails, "rel L1", r)
+    assert gfails == fails
+    assert r.max() <= tol, r
+
+
+def test_implicit_recovery_cons_to_prims_and_cfl_step():
+    """cons -> prims with the implicit solver (torus, 3 % perturbed guess)
+    equals the oracle's, flags included; a device CFL step reads the rate
+    partials the implicit pass wrote."""
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(16, 24, 8)
+    c = oracle.cfg(grid, gam=13 / 9, inverter=oracle.INV_IMPLICIT)
+    s = gr.Grmhd(grid, 13 / 9, inverter=gr.INV_IMPLICIT)
+    U = oracle.prims_to_cons(c, P)
+    rng = np.random.default_rng(11)
+    guess = P * (1 + 0.03 * rng.uniform(-1, 1, P.shape))
+    P_ref, n_ref, f_ref = oracle.cons_to_prims(c, U, guess)
+    P_gpu, n_gpu, f_gpu = s.cons_to_prims(torch.from_numpy(U), torch.from_numpy(guess))
+    assert n_gpu == n_ref
+    assert np.array_equal(interior(f_gpu.cpu().numpy()), interior(f_ref))
+    assert rel_l1(P_gpu.cpu().numpy(), P_ref).max() <= 1e-12
+    s.load(torch.from_numpy(P).cuda())
+    s.step_cfl()
+    out = s.prims().cpu().numpy()
+    s.step_cfl()                       # its dt: from the partials of out
+    assert s.last_dt() == pytest.approx(oracle.estimate_dt(c, out), rel=1e-14)
+
+
 def hard_states(grid, seed):
     """Padded prims of seeded strongly magnetised, fast states over a Kerr
     grid: normal-frame four-velocity up to ~60, b^2/rho from 1 to 1e4, u/rho

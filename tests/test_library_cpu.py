@@ -48,7 +48,7 @@ def test_workspace_and_argument_validation():
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(pk)) == nb
     pk.kastaun_wmax = 1.0
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(pk)) == 0
-    pk.inverter = 2
+    pk.inverter = 3
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(pk)) == 0
     # a null workspace is rejected before any device call
     ctx = C.c_void_p()
@@ -97,3 +97,18 @@ def test_face_ct_parameters_and_workspace():
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(ct=3))) == 0
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(ct=grmhd.CT_FACE_AVG))) == 0
     assert lib.grmhd_load_faces(None, None) == grmhd.E_ARG
+
+
+def test_implicit_recovery_parameters():
+    from paper_2408_01361_amd import grmhd
+    from workloads import torus_grid
+    lib = grmhd.lib()
+    g = grmhd.make_grid(torus_grid(32, 32, 32))
+    mk = lambda inv, **kw: grmhd.make_params(13 / 9, 0.9, 1e-26, 1e-14, 30, grmhd.RECON_WENO5,
+                                             grmhd.PREC_FP64, inv, 1e3, **kw)
+    base = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(0)))
+    impl = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INV_IMPLICIT)))
+    assert impl >= base + 8 * 8 * 38 ** 3          # the stored U* of a stage
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INV_IMPLICIT, fofc=True))) == 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(3))) == 0
+    assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INV_IMPLICIT))) == 0
