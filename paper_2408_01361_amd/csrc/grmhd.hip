@@ -1575,10 +1575,10 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8
 // update's inversion, for the implicit recovery).  Failures counted and
 // flagged as the update counts them; with RATE the CFL-rate partials of the
 // new prims, over the update's schedule.  Its own register budget (the
-// 5 x 5 Newton system lives in registers): 2 waves/SIMD (256 VGPRs, a few
-// spilled) ran 28 % faster than 1 wave without spills, and 3 waves slower.
+// 5 x 5 Newton system lives in registers: 270-280 VGPRs, one wave per
+// SIMD, no scratch).
 template <bool RATE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 8)))
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
 k_implicit(Dev g, Sched box, const double* __restrict__ Pin, const double* __restrict__ ustar,
            double* __restrict__ Pout, const double* __restrict__ tabC, unsigned long long* fails,
            unsigned char* __restrict__ flags, double* __restrict__ rate_partial) {

@@ -1,0 +1,90 @@
+"""The paper's regression criterion (Readiness and Testing section: linear
+modes and Bondi accretion converge with L1 error slopes between 1.9 and 2.1)
+applied to the HIP path itself, across the selectable schemes: Flux-CT and
+face-centred CT (averaged and upwinded EMFs), MC and WENO5, and the three
+recoveries.  The exact solutions come from the workloads (linear-mode
+eigenvectors from the continuum equations; the Michel solution), not from
+the oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+from workloads import linear_mode, linear_mode_faces, bondi, interior, RECON_MC, RECON_WENO5
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_01361_amd import grmhd as gr
+    return torch, gr
+
+
+def mode_errors(name, recon, ns, ct=0, inverter=0):
+    torch, gr = _setup()
+    errs = []
+    for n in ns:
+        if ct:
+            g, P, F, exact, info = linear_mode_faces(name, n, ndim=2)
+        else:
+            g, P, exact, info = linear_mode(name, n, ndim=2)
+        s = gr.Grmhd(g, 4 / 3, recon=recon, ct=ct, inverter=inverter)
+        s.load(torch.from_numpy(P).cuda())
+        if ct:
+            s.load_faces(torch.from_numpy(F).cuda())
+        T = 2 * np.pi / info["omega"]
+        dt0 = s.dt()
+        nst = int(math.ceil(T / dt0))
+        for _ in range(nst):
+            s.step(T / nst)
+        assert s.status()[0] == 0
+        out = s.prims().cpu().numpy()
+        Pe = exact(T)
+        r = info["r"]
+        errs.append([np.mean(np.abs(interior(out[v] - Pe[v]))) for v in range(8) if abs(r[v]) > 0])
+    e = np.array(errs)
+    return np.log2(e[0] / e[1])
+
+
+CASES = [
+    ("fast", RECON_WENO5, 0, 0), ("alfven", RECON_WENO5, 0, 0), ("slow", RECON_WENO5, 0, 0),
+    ("fast", RECON_MC, 0, 0),
+    ("fast", RECON_WENO5, 1, 0), ("alfven", RECON_WENO5, 2, 0), ("slow", RECON_WENO5, 2, 0),
+    ("fast", RECON_WENO5, 0, 1), ("fast", RECON_WENO5, 0, 2),
+]
+
+
+@pytest.mark.parametrize("name,recon,ct,inv", CASES,
+                         ids=[f"{c[0]}-{'weno5' if c[1] else 'mc'}-ct{c[2]}-inv{c[3]}" for c in CASES])
+def test_linear_mode_convergence_on_the_gpu(name, recon, ct, inv):
+    ns = (64, 128) if recon == RECON_MC else (32, 64)
+    slope = mode_errors(name, recon, ns, ct=ct, inverter=inv)
+    print(name, recon, ct, inv, "slopes", slope)
+    assert np.all((slope > 1.9) & (slope < 2.1)), slope
+
+
+@pytest.mark.parametrize("recon", [RECON_MC, RECON_WENO5])
+def test_bondi_stays_stationary_at_second_order_on_the_gpu(recon):
+    """Michel accretion (frozen exact ghosts, polar x2): over t = 10 the
+    density's relative L1 drift from the stationary solution falls at second
+    order when n1 and n2 are both doubled."""
+    torch, gr = _setup()
+    drift = []
+    for n in (32, 64):
+        grid, P, c = bondi(n, n // 2)
+        s = gr.Grmhd(grid, c["gamma"], recon=recon)
+        s.load(torch.from_numpy(P).cuda())
+        T = 10.0
+        nst = int(math.ceil(T / s.dt()))
+        for _ in range(nst):
+            s.step(T / nst)
+        out = s.prims().cpu().numpy()
+        A, B = interior(out)[0], interior(P)[0]
+        drift.append(np.abs(A - B).sum() / np.abs(B).sum())
+    order = math.log2(drift[0] / drift[1])
+    print("Bondi drift", drift, "order", order)
+    assert drift[1] < 5e-4 and 1.8 < order < 2.4, (drift, order)
