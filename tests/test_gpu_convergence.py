@@ -29,7 +29,10 @@ def mode_errors(name, recon, ns, ct=0, inverter=0):
     errs = []
     for n in ns:
         if ct:
-            g, P, F, exact, info = linear_mode_faces(name, n, ndim=2)
+            # amplitude 1e-6: the face-centred schemes are accurate enough at
+            # 128^2 to meet the O(amp^2) nonlinear departure of a 1e-4 wave
+            # from the linear solution (the oracle shows the same)
+            g, P, F, exact, info = linear_mode_faces(name, n, ndim=2, amp=1e-6)
         else:
             g, P, exact, info = linear_mode(name, n, ndim=2)
         s = gr.Grmhd(g, 4 / 3, recon=recon, ct=ct, inverter=inverter)
@@ -61,7 +64,9 @@ CASES = [
 @pytest.mark.parametrize("name,recon,ct,inv", CASES,
                          ids=[f"{c[0]}-{'weno5' if c[1] else 'mc'}-ct{c[2]}-inv{c[3]}" for c in CASES])
 def test_linear_mode_convergence_on_the_gpu(name, recon, ct, inv):
-    ns = (64, 128) if recon == RECON_MC else (32, 64)
+    # MC, and the face-centred schemes (whose upwinded slow mode is still
+    # above second order at 32 -> 64), are in the asymptotic range at 64 -> 128
+    ns = (64, 128) if recon == RECON_MC or ct else (32, 64)
     slope = mode_errors(name, recon, ns, ct=ct, inverter=inv)
     print(name, recon, ct, inv, "slopes", slope)
     assert np.all((slope > 1.9) & (slope < 2.1)), slope
