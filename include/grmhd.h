@@ -209,8 +209,9 @@ int grmhd_cons_to_prims(grmhd_ctx* ctx, const double* d_cons, const double* d_gu
  * [3][8][padded] float64 (device); entries at positions other than interior
  * faces (x1 faces i in [0, n1], j < n2, k < n3, and likewise) are
  * unspecified.  The context's reconstruction is used; the first-order flux
- * correction is not applied (it depends on a provisional update).  For
- * testing and inspection. */
+ * correction is not applied (it depends on a provisional update), and with
+ * face-centred CT the face fields are not read (these are the Flux-CT
+ * fluxes of d_prims).  For testing and inspection. */
 int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
 
 /* Adjoint of one step (vector-Jacobian product), FP64 only.

@@ -545,6 +545,7 @@ __global__ void __launch_bounds__(BLOCK) k_cell_emf(Dev g, Box box, const double
                                                     const double* __restrict__ tabC, FT* __restrict__ C1,
                                                     FT* __restrict__ C2, FT* __restrict__ C3,
                                                     FT* __restrict__ S) {
+#pragma clang fp contract(off)
   const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   int i, j, k;
   if (!box_index(box, t, i, j, k)) return;
@@ -556,18 +557,16 @@ __global__ void __launch_bounds__(BLOCK) k_cell_emf(Dev g, Box box, const double
   load_metric<R>(tabC, g.plane, pid(g, i, j), m);
   Fluid<R> f;
   fluid_state(p, m, f);
-  R F[NVAR];
-  prim_to_flux(p, f, m, (R)g.gam, 0, F);
-  R sc = fabs(F[RHO]);
-  prim_to_flux(p, f, m, (R)g.gam, 1, F);
-  C3[c] = (FT)F[B2];
-  sc = sc + fabs(F[RHO]);
-  prim_to_flux(p, f, m, (R)g.gam, 2, F);
-  C1[c] = (FT)F[B3];
-  sc = sc + fabs(F[RHO]);
-  prim_to_flux(p, f, m, (R)g.gam, 3, F);
-  C2[c] = (FT)F[B1];
-  sc = sc + fabs(F[RHO]);
+  // the components prim_to_flux gives for F^d(rho) and F^d(B^k), written
+  // out with the same operations: sqrt(-g) rho u^d, sqrt(-g)(b^k u^d - b^d u^k)
+  const R gr = m.gdet * p[RHO];
+  R sc = fabs(gr * f.ucon[0]);
+  C3[c] = (FT)(m.gdet * (f.bcon[2] * f.ucon[1] - f.bcon[1] * f.ucon[2]));
+  sc = sc + fabs(gr * f.ucon[1]);
+  C1[c] = (FT)(m.gdet * (f.bcon[3] * f.ucon[2] - f.bcon[2] * f.ucon[3]));
+  sc = sc + fabs(gr * f.ucon[2]);
+  C2[c] = (FT)(m.gdet * (f.bcon[1] * f.ucon[3] - f.bcon[3] * f.ucon[1]));
+  sc = sc + fabs(gr * f.ucon[3]);
   S[c] = (FT)sc;
 }
 
