@@ -88,9 +88,23 @@ def oracle_baseline(grid, P, gam, recon, budget_s):
         Q, _, _ = oracle.run(c, Q, -1, 1)
         t += time.perf_counter() - t0
         steps += 1
-    return {"value": nz * steps / t, "unit": "zone-cycles/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} full SSPRK2 step(s) of the same {grid.n1}^3 torus (CFL dt each "
-                      f"step), {t:.1f} s wall"}
+    out = {"value": nz * steps / t, "unit": "zone-cycles/s", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} full SSPRK2 step(s) of the same {grid.n1}^3 torus (CFL dt each "
+                     f"step), {t:.1f} s wall"}
+    # the same on one thread (one step), and the host CPU
+    c1 = oracle.cfg(grid, gam=gam, recon=recon, nthreads=1)
+    t0 = time.perf_counter()
+    oracle.run(c1, P, -1, 1)
+    t1 = time.perf_counter() - t0
+    out["one_thread_value"] = nz / t1
+    out["one_thread_sample"] = f"1 full SSPRK2 step on 1 thread, {t1:.1f} s wall"
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")]
+        out["cpu_model"] = model[0] if model else None
+        out["host_cpus"] = len(model)
+    except OSError:
+        out["cpu_model"] = None
+    return out
 
 
 def traffic_from_profile(kernel, workload):
@@ -329,6 +343,39 @@ def face_ct_extra(torch, gr, grid, P, info, gam, recon, steps):
     return res
 
 
+def timing_protocol_extra(torch, gr, grid, P, gam, recon, steps):
+    """The headline step timed as repeated runs: the median over 5 repeats
+    of the K steps (each from the reloaded initial state), with the device
+    CFL reduction and with a fixed dt (no reduction); and the small
+    workload (fast mode, 32^3, MC), launch-bound, over 1000 steps."""
+    import numpy as np
+    from workloads import linear_mode, RECON_MC
+    Pt = torch.from_numpy(P).cuda()
+    s = gr.Grmhd(grid, gam, recon=recon)
+    s.load(Pt)
+    dt = s.dt()
+    for _ in range(10):
+        s.step_cfl()
+    reps = {"cfl": [], "fixed_dt": []}
+    for _ in range(5):
+        s.load(Pt)
+        reps["cfl"].append(time_steps(torch, s, steps) * 1e3 / steps)
+        s.load(Pt)
+        reps["fixed_dt"].append(time_steps(torch, s, steps, use_dt=False, dt=dt) * 1e3 / steps)
+    del s
+    out = {k: {"median_ms_per_step": float(np.median(v)), "min": min(v), "max": max(v)} for k, v in reps.items()}
+    out["workload"] = "the headline torus and step, 5 repeats of the K steps"
+    g, Pm, _, _ = linear_mode("fast", 32, ndim=3)
+    sm = gr.Grmhd(g, 4.0 / 3.0, recon=RECON_MC)
+    sm.load(torch.from_numpy(Pm).cuda())
+    for _ in range(50):
+        sm.step_cfl()
+    el = time_steps(torch, sm, 1000)
+    out["fast_mode_32"] = {"workload": "fast mode, flat periodic 32^3, MC, FP64, 1000 CFL steps",
+                           "zone_cycles_per_s": 32 ** 3 * 1000 / el, "us_per_step": el * 1e6 / 1000}
+    return out
+
+
 def adjoint_extra(torch, gr):
     """Gradient of sum_{i<5} rho u after 8 steps of the 64^3 torus (MC, FP64,
     fixed dt) with respect to the initial prims and gamma: the forward pass
@@ -475,6 +522,7 @@ def main():
         out["inverters"] = kastaun_extra(torch, gr, grid, P, gam, recon, args.steps)
         out["floors_fofc"] = floors_fofc_extra(torch, gr, grid, P, gam, recon, args.steps)
         out["face_ct"] = face_ct_extra(torch, gr, grid, P, info, gam, recon, args.steps)
+        out["timing_protocol"] = timing_protocol_extra(torch, gr, grid, P, gam, recon, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_baseline(grid, P, gam, recon, args.cpu_seconds)
     print(json.dumps(out))
