@@ -15,6 +15,15 @@
 // single-workgroup pass over the CFL partials before the step when its dt
 // is taken on the device.  Layouts are variable-major and x1-fastest, so
 // each wavefront's loads and stores of one variable are contiguous.
+//
+// Options selected per context add passes to a stage: the Kastaun recovery
+// replaces 1D_W inside the update; the implicit solver's recovery runs as a
+// pass of its own after an update that stores U*; floors run after each
+// update pass; the first-order flux correction repeats the EMF and update
+// passes after a donor-cell fix of the marked zones' faces (launches that
+// exit at once when nothing was marked); face-centred CT fills ghost faces,
+// reads the face field in the flux pass, forms edge EMFs (averaged, or
+// upwinded from zone-centre EMFs) and advances the faces before the update.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -2440,7 +2449,7 @@ int grmhd_cons_to_prims(grmhd_ctx* c, const double* d_cons, const double* d_gues
   if (!c || !d_cons || !d_guess || !d_prims || !n_fail) return GRMHD_E_ARG;
   const Dev& g = c->dev;
   Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
-  unsigned long long* cnt = c->fails + 1;
+  unsigned long long* cnt = c->fails + C_C2P;
   if (hipMemsetAsync(cnt, 0, sizeof(unsigned long long), c->stream) != hipSuccess) return GRMHD_E_HIP;
   k_cons_to_prims<<<blocks_for(bz.count()), BLOCK, 0, c->stream>>>(g, bz, d_cons, d_guess, d_prims, d_flags,
                                                                    c->tabC, cnt);

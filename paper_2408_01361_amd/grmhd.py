@@ -167,6 +167,13 @@ class Grmhd:
 
     Python owns the workspace tensor; the library borrows it for the
     context's lifetime and enqueues on the torch stream current at creation.
+
+    Options (the fields of grmhd_params in include/grmhd.h): recon
+    (RECON_MC, RECON_WENO5, RECON_DONOR), precision (PREC_FP64, PREC_MIXED),
+    inverter (INV_1DW, INV_KASTAUN, INV_IMPLICIT), floors (with the keyword
+    floor parameters of FLOOR_DEFAULTS), fofc (first-order flux correction),
+    ct (CT_FLUX, or face-centred CT_FACE_AVG / CT_FACE_GS, whose face fields
+    load_faces takes).
     """
 
     def __init__(self, spec, gamma_ad, recon=RECON_WENO5, precision=PREC_FP64, cfl=0.9,
