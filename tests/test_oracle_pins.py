@@ -998,3 +998,27 @@ def test_implicit_solver_step_matches_1dw_step():
     ai, fi, _, fli = oracle.run(ci, P, dt, 2, flags=True)
     assert fi == fw and np.array_equal(flw, fli)
     assert rel_l1(ai, aw).max() < 1e-12
+
+
+@pytest.mark.parametrize("ct", [0, 1, 2])
+def test_magnetised_torus_symmetries_with_each_transport(ct):
+    """The unperturbed magnetised torus under Flux-CT and both face-centred
+    schemes: bitwise axisymmetric (identical x3 slices), and equatorially
+    mirror-symmetric to roundoff under theta -> pi - theta with u~2 flipped
+    and B -> (-B1, B2, -B3) (the mirror image of the single-loop field,
+    reversed, which ideal MHD maps onto itself)."""
+    g, P, info = fm_torus(48, 48, 4, noise=0.0, magnetised=True)
+    c = oracle.cfg(g, gam=13 / 9, recon=RECON_WENO5, ct=ct)
+    if ct:
+        out, _, _, _ = oracle.run_face(c, P, info["faces"], -1, 2)
+    else:
+        out, _, _ = oracle.run(c, P, -1, 2)
+    I = interior(out)
+    for k in range(1, 4):
+        assert np.array_equal(I[:, k], I[:, 0])
+    M = I[:, :, ::-1, :].copy()
+    M[3] *= -1
+    M[5] *= -1
+    M[7] *= -1
+    scale = np.abs(I).max(axis=(1, 2, 3))[:, None, None, None] + 1e-300
+    assert (np.abs(M - I) / scale).max() < 1e-11
