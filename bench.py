@@ -135,6 +135,16 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+def _unpack_blocks(flat, blocks):
+    """Per-block padded prims (8, n+6, n+6, n+6) out of a pack's flat state."""
+    out, o = [], 0
+    for b in blocks:
+        m = b["n"] + 6
+        out.append(flat[o:o + 8 * m ** 3].reshape(8, m, m, m))
+        o += 8 * m ** 3
+    return out
+
+
 def time_steps(torch, solver, steps, use_dt=True, dt=None):
     """Wall time of `steps` steps: each at the CFL dt of its input state,
     reduced and applied on the device, or at a fixed dt."""
@@ -219,10 +229,42 @@ def extras(torch, gr, np, args):
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     fails = pk.status() - f0
+    packed = _unpack_blocks(pk.prims().cpu().numpy(), blocks)
+    # the same blocks, each advanced by its own single-grid context (the
+    # plain FP64 kernels, one launch sequence per block), one after another
+    # on the same stream: the per-block baseline of the batched launch
+    ctxs = []
+    for b in blocks:
+        c = gr.Grmhd(b["grid"], gam, recon=RECON_WENO5)
+        c.load(torch.from_numpy(b["prims"]).cuda())
+        ctxs.append(c)
+    for c in ctxs:                   # untimed: one step each
+        c.step(dt)
+    for c, b in zip(ctxs, blocks):
+        c.load(torch.from_numpy(b["prims"]).cuda())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in ctxs:
+            c.step(dt)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    num = den = 0.0
+    for c, q in zip(ctxs, packed):
+        a = interior(c.prims().cpu().numpy())[0]
+        num += float(np.abs(interior(q)[0] - a).sum())
+        den += float(np.abs(a).sum())
+    del ctxs
     out["batched"] = {
         "workload": "320 frozen-ghost blocks of the 128^3 torus, n in {16,32,64} (60/30/10 %, seed 7), "
                     "WENO5, FP64, one persistent launch per RK2 stage, 10 steps at fixed dt",
         "interior_zones": zones, "zone_cycles_per_s": zones * steps / tp,
+        "per_block_zone_cycles_per_s": zones * steps / tb,
+        "speedup_vs_per_block_fp64": tb / tp,
+        "rho_rel_l1_vs_per_block_fp64": num / den,
+        "per_block_note": "the same blocks and steps, each block its own single-grid FP64 context "
+                          "stepped in turn on one stream (one ctypes call and its launches per "
+                          "block and step)",
         "cooperative_workgroups": pk.grid_blocks,
         "tiles": {str(k): list(v) for k, v in tiles.items()},
         "tiles_note": "per block size: t1 x t2 x t3 zones, or [0, 0, 0] = runs of 256 consecutive "
