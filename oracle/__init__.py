@@ -48,6 +48,8 @@ class Cfg(C.Structure):
 
 INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 RECON_DONOR = 2
+RECON_WENOZ = 3
+RECON_VL = 4
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
 FL_RHO, FL_U, FL_FLUID_FRAME, FL_GAMMA, FL_TEMP = 1, 2, 4, 8, 16
 # floor and ceiling defaults (HARM-family values; the paper states none)
@@ -93,6 +95,10 @@ def _declare(lib):
     lib.orc_weno5.restype = C.c_double
     lib.orc_mc_slope.argtypes = [C.c_double] * 3
     lib.orc_mc_slope.restype = C.c_double
+    lib.orc_wenoz.argtypes = [C.c_double] * 6
+    lib.orc_wenoz.restype = C.c_double
+    lib.orc_vl_slope.argtypes = [C.c_double] * 3
+    lib.orc_vl_slope.restype = C.c_double
     L = C.POINTER(C.c_longlong)
     lib.orc_count_face.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, C.c_int, L]
     lib.orc_count_zone_update.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, C.c_double, L]
@@ -303,6 +309,14 @@ def weno5(a, b, c_, d, e, eps=1e-26):
 
 def mc_slope(l, c_, r):
     return lib().orc_mc_slope(l, c_, r)
+
+
+def wenoz(a, b, c_, d, e, eps=1e-26):
+    return lib().orc_wenoz(a, b, c_, d, e, eps)
+
+
+def vl_slope(l, c_, r):
+    return lib().orc_vl_slope(l, c_, r)
 
 
 def count_face(c, prims, d, i, j, k):

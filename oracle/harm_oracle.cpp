@@ -9,7 +9,9 @@
 //     the metric and connection cached per (x1, x2) as the GRCoordinates
 //     description says (Core section);
 //   * primitive -> conserved / flux with the normal-observer velocity;
-//   * linear MC or WENO5 reconstruction of each primitive (Algorithm section);
+//   * linear MC or WENO5 reconstruction of each primitive (Algorithm section),
+//     or, among the further schemes the Solvers section lists, WENO-Z, linear
+//     with van Leer's limiter and donor cell;
 //   * local Lax-Friedrichs fluxes with the fast-magnetosonic speed bound;
 //   * Flux-CT: B fluxes replaced by corner-averaged EMFs;
 //   * flux divergence + geometric source, two-stage SSP Runge-Kutta;
@@ -53,7 +55,7 @@ const int NV = 8, NG = 3;
 enum { RHO = 0, UU = 1, U1 = 2, U2 = 3, U3 = 4, B1 = 5, B2 = 6, B3 = 7 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_POLAR = 2, BC_FROZEN = 3 };
 enum { MINKOWSKI = 0, KERR_MKS = 1 };
-enum { RECON_MC = 0, RECON_WENO5 = 1, RECON_DONOR = 2 };
+enum { RECON_MC = 0, RECON_WENO5 = 1, RECON_DONOR = 2, RECON_WENOZ = 3, RECON_VL = 4 };
 
 }  // namespace
 
@@ -319,6 +321,37 @@ real weno5(real a, real b, real c, real d, real e, real eps) {
   return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
 }
 
+// WENO-Z value at the right edge of zone c (Borges et al. 2008, with the
+// power of Castro, Costa & Don 2011, here 2): the WENO5 candidates and
+// indicators, weights d_k (1 + (tau5 / (eps + beta_k))^2) normalised, where
+// tau5 = |beta_0 - beta_2|.
+real wenoz(real a, real b, real c, real d, real e, real eps) {
+  real p0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  real p1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  real p2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  real t;
+  t = a - 2.0 * b + c; real s0 = 13.0 / 12.0 * t * t;
+  t = a - 4.0 * b + 3.0 * c; s0 += 0.25 * t * t;
+  t = b - 2.0 * c + d; real s1 = 13.0 / 12.0 * t * t;
+  t = b - d; s1 += 0.25 * t * t;
+  t = c - 2.0 * d + e; real s2 = 13.0 / 12.0 * t * t;
+  t = 3.0 * c - 4.0 * d + e; s2 += 0.25 * t * t;
+  real tau = fabs(s0 - s2);
+  real z0 = tau / (eps + s0), z1 = tau / (eps + s1), z2 = tau / (eps + s2);
+  real a0 = 0.1 * (1.0 + z0 * z0);
+  real a1 = 0.6 * (1.0 + z1 * z1);
+  real a2 = 0.3 * (1.0 + z2 * z2);
+  return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
+// Van Leer's limited slope of zone c: the harmonic mean of the two one-sided
+// differences, zero where they differ in sign (an extremum) or one vanishes.
+real vl_slope(real l, real c, real r) {
+  real dl = c - l, dr = r - c;
+  if (dl * dr <= 0.0) return 0.0;
+  return 2.0 * dl * dr / (dl + dr);
+}
+
 // ------------------------------------------------------------------ grid --
 
 struct Grid {
@@ -447,6 +480,12 @@ void reconstruct(const Grid& g, const std::vector<real>& P, int recon, int d, in
     } else if (recon == RECON_MC) {
       qL[v] = q[2] + 0.5 * mc_slope(q[1], q[2], q[3]);
       qR[v] = q[3] - 0.5 * mc_slope(q[2], q[3], q[4]);
+    } else if (recon == RECON_VL) {
+      qL[v] = q[2] + 0.5 * vl_slope(q[1], q[2], q[3]);
+      qR[v] = q[3] - 0.5 * vl_slope(q[2], q[3], q[4]);
+    } else if (recon == RECON_WENOZ) {
+      qL[v] = wenoz(q[0], q[1], q[2], q[3], q[4], g.c.weno_eps);
+      qR[v] = wenoz(q[5], q[4], q[3], q[2], q[1], g.c.weno_eps);
     } else {
       qL[v] = weno5(q[0], q[1], q[2], q[3], q[4], g.c.weno_eps);
       qR[v] = weno5(q[5], q[4], q[3], q[2], q[1], g.c.weno_eps);
@@ -1840,6 +1879,10 @@ double orc_weno5(double a, double b, double c, double d, double e, double eps) {
 }
 
 double orc_mc_slope(double l, double c, double r) { return (double)mc_slope(l, c, r); }
+double orc_wenoz(double a, double b, double c, double d, double e, double eps) {
+  return (double)wenoz(a, b, c, d, e, eps);
+}
+double orc_vl_slope(double l, double c, double r) { return (double)vl_slope(l, c, r); }
 
 // ---- operation counts (counting build; zeros otherwise) ----
 
