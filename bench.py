@@ -307,6 +307,37 @@ def kastaun_extra(torch, gr, grid, P, gam, recon, steps):
     return res
 
 
+def recon_extra(torch, gr, grid, P, gam, steps):
+    """The headline torus and step with each reconstruction: whole steps
+    (CFL dt each step) and the flux class (both stages) with per-launch
+    events; FP64 and, for each, the mixed-precision form."""
+    Pt = torch.from_numpy(P).cuda()
+    res = {}
+    names = (("donor", gr.RECON_DONOR), ("mc", gr.RECON_MC), ("vl", gr.RECON_VL),
+             ("weno5", gr.RECON_WENO5), ("wenoz", gr.RECON_WENOZ))
+    for name, recon in names:
+        row = {}
+        for pname, prec in (("fp64", gr.PREC_FP64), ("mixed", gr.PREC_MIXED)):
+            s = gr.Grmhd(grid, gam, recon=recon, precision=prec)
+            s.load(Pt)
+            for _ in range(10):          # untimed: clocks settle
+                s.step_cfl()
+            s.load(Pt)
+            el = time_steps(torch, s, steps)
+            s.load(Pt)
+            s.timing(True, classes=["flux"])
+            time_steps(torch, s, steps)
+            rep = s.timing_report()
+            s.timing(False)
+            row[pname] = {"zone_cycles_per_s": grid.n1 * grid.n2 * grid.n3 * steps / el,
+                          "ms_per_step": el * 1e3 / steps,
+                          "flux_us_per_step": 1e3 * rep["flux"][0] / steps}
+            del s
+        res[name] = row
+    res["workload"] = "the headline torus and step, reconstruction swapped"
+    return res
+
+
 def floors_fofc_extra(torch, gr, grid, P, gam, recon, steps):
     """What the floors and the first-order flux correction cost: the headline
     torus step plain, with floors, and with floors plus the correction; and
@@ -562,6 +593,7 @@ def main():
     if not args.no_extras:
         out.update(extras(torch, gr, np, args))
         out["inverters"] = kastaun_extra(torch, gr, grid, P, gam, recon, args.steps)
+        out["reconstructions"] = recon_extra(torch, gr, grid, P, gam, args.steps)
         out["floors_fofc"] = floors_fofc_extra(torch, gr, grid, P, gam, recon, args.steps)
         out["face_ct"] = face_ct_extra(torch, gr, grid, P, info, gam, recon, args.steps)
         out["timing_protocol"] = timing_protocol_extra(torch, gr, grid, P, gam, recon, args.steps)

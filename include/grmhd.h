@@ -43,7 +43,8 @@ extern "C" {
 enum { GRMHD_OK = 0, GRMHD_E_ARG = -1, GRMHD_E_HIP = -2, GRMHD_E_STATE = -3,
        GRMHD_E_NOMEM = -4 };
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KERR_MKS = 1 };
-enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_DONOR = 2 };
+enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_DONOR = 2, GRMHD_RECON_WENOZ = 3,
+       GRMHD_RECON_VL = 4 };
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1, GRMHD_INV_IMPLICIT = 2 };
 enum { GRMHD_CT_FLUX = 0, GRMHD_CT_FACE_AVG = 1, GRMHD_CT_FACE_GS = 2 };
@@ -71,11 +72,17 @@ typedef struct {
 typedef struct {
   double gamma_ad;    /* adiabatic index, p = (gamma_ad - 1) u */
   double cfl;         /* Courant number of grmhd_estimate_dt */
-  double weno_eps;    /* WENO5 smoothness regulariser */
+  double weno_eps;    /* WENO5 / WENO-Z smoothness regulariser, in [1e-36, 1]
+                         when either is selected */
   double newton_tol;  /* relative |dW/W| stopping tolerance of 1D_W */
   int newton_maxit;   /* Newton iteration cap (one more step follows convergence) */
   int recon;          /* GRMHD_RECON_*: MC, WENO5, or DONOR (first order: each
-                         face's states are its two zones' own values) */
+                         face's states are its two zones' own values); or two
+                         more of the schemes the Solvers section lists: WENOZ
+                         (WENO-Z weights d_k (1 + (tau5/(eps + beta_k))^2),
+                         Borges et al. 2008 with the power of Castro, Costa &
+                         Don 2011) and VL (linear, van Leer's harmonic-mean
+                         limiter).  Packs and the adjoint take MC or WENO5. */
   int precision;      /* GRMHD_PREC_*: MIXED = FP32 reconstruction, fluxes, EMFs */
   int floors;         /* 1: floors and ceilings after every inversion (fields
                          below); 0: none */
@@ -226,10 +233,10 @@ int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
  * max() branches by the branch taken.  Scratch comes from d_vjp_ws (device,
  * 256-byte aligned, >= grmhd_vjp_workspace_bytes()).  Neither the context's
  * state nor its failure count changes.  Synchronises.  E_STATE for the mixed
- * precision path, floors, the first-order flux correction, donor-cell
- * reconstruction, face-centred CT or the implicit recovery (the adjoint
- * covers the plain high-order Flux-CT step; the workspace size is then
- * 0). */
+ * precision path, floors, the first-order flux correction, a reconstruction
+ * other than MC or WENO5, face-centred CT or the implicit recovery (the
+ * adjoint covers the plain MC / WENO5 Flux-CT step; the workspace size is
+ * then 0). */
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params);
 int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const double* d_gprims_out,
                    double* d_gprims_in, double* g_gamma, void* d_vjp_ws, size_t vjp_ws_bytes);
@@ -245,8 +252,9 @@ int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const do
  * (0, 0, 0): runs of 256 consecutive positions of each box in x1-fastest
  * order, the default) only change speed.  Errors as for single contexts; E_ARG for blocks outside the
  * global grid, a non-FP64 precision, floors, the first-order flux
- * correction, donor-cell reconstruction, face-centred CT or the implicit
- * recovery (packs advance the plain high-order Flux-CT step). */
+ * correction, a reconstruction other than MC or WENO5, face-centred CT or
+ * the implicit recovery (packs advance the plain MC / WENO5 Flux-CT
+ * step). */
 typedef struct grmhd_pack grmhd_pack;
 size_t grmhd_pack_workspace_bytes(int nblocks, const int* n);
 int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* offsets_ijk,

@@ -296,6 +296,15 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ P, long nz
       R m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s];
       qL[v] = mc_left(m2, m1, p0);
       qR[v] = mc_right(m1, p0, p1);
+    } else if (RECON == GRMHD_RECON_VL) {
+      R m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s];
+      qL[v] = vl_left(m2, m1, p0);
+      qR[v] = vl_right(m1, p0, p1);
+    } else if (RECON == GRMHD_RECON_WENOZ) {
+      R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
+        p2 = (R)q[2 * s];
+      qL[v] = wenoz(m3, m2, m1, p0, p1, eps);
+      qR[v] = wenoz(p2, p1, p0, m1, m2, eps);
     } else {
       R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
         p2 = (R)q[2 * s];
@@ -1840,7 +1849,11 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
       return false;
   }
   if (!(g->x1max > g->x1min && g->x2max > g->x2min && g->x3max > g->x3min)) return false;
-  if (p->recon != GRMHD_RECON_MC && p->recon != GRMHD_RECON_WENO5 && p->recon != GRMHD_RECON_DONOR)
+  if (p->recon < GRMHD_RECON_MC || p->recon > GRMHD_RECON_VL) return false;
+  // the WENO weights' products stay normal in FP64 and the FP32 indicators
+  // stay positive for eps >= 1e-36
+  if ((p->recon == GRMHD_RECON_WENO5 || p->recon == GRMHD_RECON_WENOZ) &&
+      !(p->weno_eps >= 1e-36 && p->weno_eps <= 1.0))
     return false;
   if (p->precision != GRMHD_PREC_FP64 && p->precision != GRMHD_PREC_MIXED) return false;
   if (!(p->gamma_ad > 1.0) || p->newton_maxit < 1 || !(p->newton_tol > 0.0)) return false;
@@ -2020,6 +2033,10 @@ int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullp
     rc = face ? go(k_flux_all<GRMHD_RECON_MC, R, FT, true>) : go(k_flux_all<GRMHD_RECON_MC, R, FT, false>);
   else if (c->params.recon == GRMHD_RECON_DONOR)
     rc = face ? go(k_flux_all<GRMHD_RECON_DONOR, R, FT, true>) : go(k_flux_all<GRMHD_RECON_DONOR, R, FT, false>);
+  else if (c->params.recon == GRMHD_RECON_VL)
+    rc = face ? go(k_flux_all<GRMHD_RECON_VL, R, FT, true>) : go(k_flux_all<GRMHD_RECON_VL, R, FT, false>);
+  else if (c->params.recon == GRMHD_RECON_WENOZ)
+    rc = face ? go(k_flux_all<GRMHD_RECON_WENOZ, R, FT, true>) : go(k_flux_all<GRMHD_RECON_WENOZ, R, FT, false>);
   else
     rc = face ? go(k_flux_all<GRMHD_RECON_WENO5, R, FT, true>) : go(k_flux_all<GRMHD_RECON_WENO5, R, FT, false>);
   if (rc) return rc;
@@ -2607,7 +2624,8 @@ int step_vjp(grmhd_ctx* c, const VjpCarve& w, const double* d_in, double dt, con
 extern "C" {
 
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
-  if (!grid_ok(grid, params) || params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR ||
+  if (!grid_ok(grid, params) || params->floors || params->fofc ||
+      (params->recon != GRMHD_RECON_MC && params->recon != GRMHD_RECON_WENO5) ||
       params->ct != GRMHD_CT_FLUX || params->inverter == GRMHD_INV_IMPLICIT)
     return 0;
   return vjp_carve(grid, params->recon, nullptr, nullptr);
@@ -2618,8 +2636,10 @@ int grmhd_step_vjp(grmhd_ctx* c, const double* d_prims_in, double dt, const doub
   if (!c || !d_prims_in || !d_gprims_out || !d_gprims_in || !g_gamma || !d_vjp_ws) return GRMHD_E_ARG;
   if (!(dt > 0.0) || !isfinite(dt)) return GRMHD_E_ARG;
   if (c->params.precision != GRMHD_PREC_FP64) return GRMHD_E_STATE;
-  // the adjoint covers the plain high-order step (no floors, no correction)
-  if (c->params.floors || c->params.fofc || c->params.recon == GRMHD_RECON_DONOR ||
+  // the adjoint covers the plain step with MC or WENO5 (no floors, no
+  // correction)
+  if (c->params.floors || c->params.fofc ||
+      (c->params.recon != GRMHD_RECON_MC && c->params.recon != GRMHD_RECON_WENO5) ||
       c->params.ct != GRMHD_CT_FLUX || c->params.inverter == GRMHD_INV_IMPLICIT)
     return GRMHD_E_STATE;
   if (((uintptr_t)d_vjp_ws & 255) != 0) return GRMHD_E_ARG;
@@ -2786,9 +2806,9 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
                       void* d_ws, size_t ws_bytes, void* stream) {
   if (!out || nblocks < 1 || !n || !offsets_ijk || !global || !metric || !params || !d_ws) return GRMHD_E_ARG;
   if (!grid_ok(global, params) || params->precision != GRMHD_PREC_FP64) return GRMHD_E_ARG;
-  // packs advance the plain high-order step
-  if (params->floors || params->fofc || params->recon == GRMHD_RECON_DONOR || params->ct != GRMHD_CT_FLUX ||
-      params->inverter == GRMHD_INV_IMPLICIT)
+  // packs advance the plain step with MC or WENO5
+  if (params->floors || params->fofc || (params->recon != GRMHD_RECON_MC && params->recon != GRMHD_RECON_WENO5) ||
+      params->ct != GRMHD_CT_FLUX || params->inverter == GRMHD_INV_IMPLICIT)
     return GRMHD_E_ARG;
   if (((uintptr_t)d_ws & 255) != 0) return GRMHD_E_ARG;
   for (int b = 0; b < nblocks; b++) {

@@ -107,6 +107,10 @@ using fdual::mc_left;
 using f64::mc_right;
 using f32::mc_right;
 using fdual::mc_right;
+using f64::vl_left;
+using f32::vl_left;
+using f64::vl_right;
+using f32::vl_right;
 using f64::llf;
 using f32::llf;
 using fdual::llf;
@@ -128,8 +132,8 @@ using fdual::llf;
 #pragma clang fp contract(fast)
 namespace wd {
 typedef double R;
-// (eps + beta)^2 of the stencils (a, b, c), (b, c, d), (c, d, e), scaled by 144
-__device__ __forceinline__ void indicators(R a, R b, R c, R d, R e, R eps, R& s0, R& s1, R& s2) {
+// 12 (eps + beta) of the stencils (a, b, c), (b, c, d), (c, d, e)
+__device__ __forceinline__ void indicators12(R a, R b, R c, R d, R e, R eps, R& s0, R& s1, R& s2) {
   const R eps12 = (R)12 * eps;
   R t0 = (a + c) - (R)2 * b, u0 = fma((R)-4, b, fma((R)3, c, a));
   R t1 = (b + d) - (R)2 * c, u1 = b - d;
@@ -137,6 +141,10 @@ __device__ __forceinline__ void indicators(R a, R b, R c, R d, R e, R eps, R& s0
   s0 = fma((R)13 * t0, t0, fma((R)3 * u0, u0, eps12));
   s1 = fma((R)13 * t1, t1, fma((R)3 * u1, u1, eps12));
   s2 = fma((R)13 * t2, t2, fma((R)3 * u2, u2, eps12));
+}
+// (eps + beta)^2 of the three stencils, scaled by 144
+__device__ __forceinline__ void indicators(R a, R b, R c, R d, R e, R eps, R& s0, R& s1, R& s2) {
+  indicators12(a, b, c, d, e, eps, s0, s1, s2);
   s0 *= s0;
   s1 *= s1;
   s2 *= s2;
@@ -155,6 +163,23 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   double s0, s1, s2;
   wd::indicators(a, b, c, d, e, eps, s0, s1, s2);
   return wd::combine(a, b, c, d, e, s1 * s2, s0 * s2, s0 * s1);
+}
+
+// WENO-Z (Borges et al. 2008, power 2 as in Castro, Costa & Don 2011): the
+// WENO5 candidates and indicators with weights d_k (1 + (tau5 / (eps +
+// beta_k))^2), tau5 = |beta_0 - beta_2|.  Over the common denominator of the
+// squared indicators s_k = (12 (eps + beta_k))^2 (tau5 scaled by 12 alike,
+// T = (12 tau5)^2) the weight products are d_k (s_k + T) prod_{j != k} s_j,
+// formed like WENO5's; with weno_eps >= 1e-36 they stay normal while
+// 12 (eps + beta) < 1e100, i.e. for differences of primitives below ~1e49.
+__device__ __forceinline__ double wenoz(double a, double b, double c, double d, double e, double eps) {
+  double s0, s1, s2;
+  wd::indicators12(a, b, c, d, e, eps, s0, s1, s2);
+  const double tau = fabs(s0 - s2), T = tau * tau;
+  s0 *= s0;
+  s1 *= s1;
+  s2 *= s2;
+  return wd::combine(a, b, c, d, e, (s0 + T) * (s1 * s2), (s1 + T) * (s0 * s2), (s2 + T) * (s0 * s1));
 }
 
 // FP32 form.  The indicators are scaled by 12 as in the FP64 form and then
@@ -189,6 +214,40 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
 
 __device__ __forceinline__ float weno5(float a, float b, float c, float d, float e, float eps) {
   return wf::weno5(a, b, c, d, e, eps);
+}
+
+// FP32 WENO-Z.  With b_k = 12 (eps + beta_k), rho_k = b_k / min b >= 1 and
+// theta = 12 tau5 / min b (clamped at 1e18; beyond it the weights agree
+// with the clamped ones to FP32 resolution), the weights divided by the
+// common factor 1 + theta^2 are d_k (e + q / rho_k^2), e = 1 / (1 + theta^2),
+// q = theta^2 e: each in (0, d_k], the smoothest stencil's equal to d_k, so
+// nothing overflows and the sum never vanishes.  Hardware reciprocals.
+namespace wf {
+__device__ __forceinline__ R wenoz(R a, R b, R c, R d, R e, R eps) {
+  const R eps12 = 12.0f * eps;
+  R t0 = (a + c) - 2.0f * b, u0 = fmaf(-4.0f, b, fmaf(3.0f, c, a));
+  R t1 = (b + d) - 2.0f * c, u1 = b - d;
+  R t2 = (c + e) - 2.0f * d, u2 = fmaf(-4.0f, d, fmaf(3.0f, c, e));
+  R s0 = fmaf(13.0f * t0, t0, fmaf(3.0f * u0, u0, eps12));
+  R s1 = fmaf(13.0f * t1, t1, fmaf(3.0f * u1, u1, eps12));
+  R s2 = fmaf(13.0f * t2, t2, fmaf(3.0f * u2, u2, eps12));
+  const R im = __builtin_amdgcn_rcpf(fminf(fminf(s0, s1), s2));
+  const R th = fminf(fabsf(s0 - s2) * im, 1e18f);
+  const R th2 = th * th;
+  const R ee = __builtin_amdgcn_rcpf(1.0f + th2), q = th2 * ee;
+  R r0 = s0 * im, r1 = s1 * im, r2 = s2 * im;
+  R w0 = fmaf(q, __builtin_amdgcn_rcpf(r0 * r0), ee);
+  R w1 = 6.0f * fmaf(q, __builtin_amdgcn_rcpf(r1 * r1), ee);
+  R w2 = 3.0f * fmaf(q, __builtin_amdgcn_rcpf(r2 * r2), ee);
+  R p0 = fmaf(11.0f, c, fmaf(-7.0f, b, 2.0f * a));
+  R p1 = fmaf(2.0f, d, fmaf(5.0f, c, -b));
+  R p2 = fmaf(5.0f, d, fmaf(2.0f, c, -e));
+  return fmaf(w0, p0, fmaf(w1, p1, w2 * p2)) * __builtin_amdgcn_rcpf(6.0f * ((w0 + w1) + w2));
+}
+}  // namespace wf
+
+__device__ __forceinline__ float wenoz(float a, float b, float c, float d, float e, float eps) {
+  return wf::wenoz(a, b, c, d, e, eps);
 }
 
 // Dual-number WENO5: the same weights, in the plain single-division form;

@@ -83,6 +83,31 @@ def test_floor_and_correction_parameters_are_validated():
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk())) > 0
 
 
+def test_reconstruction_choices_are_validated():
+    from paper_2408_01361_amd import grmhd
+    from workloads import torus_grid
+    lib = grmhd.lib()
+    g = grmhd.make_grid(torus_grid(32, 32, 32))
+    mk = lambda recon, eps=1e-26: grmhd.make_params(13 / 9, 0.9, eps, 1e-14, 30, recon,
+                                                     grmhd.PREC_FP64, 0, 1e3)
+    base = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_WENO5)))
+    for r in (grmhd.RECON_MC, grmhd.RECON_DONOR, grmhd.RECON_WENOZ, grmhd.RECON_VL):
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r))) == base
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(5))) == 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(-1))) == 0
+    # the WENO regulariser must keep the weight products normal ...
+    for r in (grmhd.RECON_WENO5, grmhd.RECON_WENOZ):
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 1e-40))) == 0
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 2.0))) == 0
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 1e-36))) == base
+    # ... and is not looked at by the linear schemes
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_VL, 0.0))) == base
+    # the adjoint and packs take MC or WENO5 only
+    for r in (grmhd.RECON_WENOZ, grmhd.RECON_VL):
+        assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(r))) == 0
+    assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_MC))) > 0
+
+
 def test_face_ct_parameters_and_workspace():
     from paper_2408_01361_amd import grmhd
     from workloads import torus_grid
