@@ -50,6 +50,8 @@ INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 RECON_DONOR = 2
 RECON_WENOZ = 3
 RECON_VL = 4
+RECON_MP5 = 5
+RECON_PPM = 6
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
 FL_RHO, FL_U, FL_FLUID_FRAME, FL_GAMMA, FL_TEMP = 1, 2, 4, 8, 16
 # floor and ceiling defaults (HARM-family values; the paper states none)
@@ -99,6 +101,10 @@ def _declare(lib):
     lib.orc_wenoz.restype = C.c_double
     lib.orc_vl_slope.argtypes = [C.c_double] * 3
     lib.orc_vl_slope.restype = C.c_double
+    lib.orc_mp5.argtypes = [C.c_double] * 5
+    lib.orc_mp5.restype = C.c_double
+    lib.orc_ppm_edges.argtypes = [C.c_double] * 5 + [C.POINTER(C.c_double)] * 2
+    lib.orc_ppm_edges.restype = None
     L = C.POINTER(C.c_longlong)
     lib.orc_count_face.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, C.c_int, L]
     lib.orc_count_zone_update.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, C.c_double, L]
@@ -317,6 +323,17 @@ def wenoz(a, b, c_, d, e, eps=1e-26):
 
 def vl_slope(l, c_, r):
     return lib().orc_vl_slope(l, c_, r)
+
+
+def mp5(a, b, c_, d, e):
+    return lib().orc_mp5(a, b, c_, d, e)
+
+
+def ppm_edges(a, b, c_, d, e):
+    """(left, right) edge values of the middle zone."""
+    l, r = C.c_double(), C.c_double()
+    lib().orc_ppm_edges(a, b, c_, d, e, C.byref(l), C.byref(r))
+    return l.value, r.value
 
 
 def count_face(c, prims, d, i, j, k):

@@ -10,8 +10,8 @@
 //     description says (Core section);
 //   * primitive -> conserved / flux with the normal-observer velocity;
 //   * linear MC or WENO5 reconstruction of each primitive (Algorithm section),
-//     or, among the further schemes the Solvers section lists, WENO-Z, linear
-//     with van Leer's limiter and donor cell;
+//     or, among the further schemes the Solvers section lists, WENO-Z, MP5,
+//     PPM, linear with van Leer's limiter and donor cell;
 //   * local Lax-Friedrichs fluxes with the fast-magnetosonic speed bound;
 //   * Flux-CT: B fluxes replaced by corner-averaged EMFs;
 //   * flux divergence + geometric source, two-stage SSP Runge-Kutta;
@@ -55,7 +55,8 @@ const int NV = 8, NG = 3;
 enum { RHO = 0, UU = 1, U1 = 2, U2 = 3, U3 = 4, B1 = 5, B2 = 6, B3 = 7 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_POLAR = 2, BC_FROZEN = 3 };
 enum { MINKOWSKI = 0, KERR_MKS = 1 };
-enum { RECON_MC = 0, RECON_WENO5 = 1, RECON_DONOR = 2, RECON_WENOZ = 3, RECON_VL = 4 };
+enum { RECON_MC = 0, RECON_WENO5 = 1, RECON_DONOR = 2, RECON_WENOZ = 3, RECON_VL = 4, RECON_MP5 = 5,
+       RECON_PPM = 6 };
 
 }  // namespace
 
@@ -352,6 +353,65 @@ real vl_slope(real l, real c, real r) {
   return 2.0 * dl * dr / (dl + dr);
 }
 
+static real rmin(real a, real b) { return b < a ? b : a; }
+static real rmax(real a, real b) { return b > a ? b : a; }
+static real min3(real a, real b, real c) { return rmin(a, rmin(b, c)); }
+static real max3(real a, real b, real c) { return rmax(a, rmax(b, c)); }
+static real minmod2(real a, real b) {
+  if (a * b <= 0.0) return 0.0;
+  return fabs(a) < fabs(b) ? a : b;
+}
+static real minmod4(real w, real x, real y, real z) {
+  if (!((w > 0.0 && x > 0.0 && y > 0.0 && z > 0.0) || (w < 0.0 && x < 0.0 && y < 0.0 && z < 0.0)))
+    return 0.0;
+  real m = rmin(rmin(fabs(w), fabs(x)), rmin(fabs(y), fabs(z)));
+  return w > 0.0 ? m : -m;
+}
+
+// MP5 value at the right edge of zone c from (a, b, c, d, e) (Suresh & Huynh
+// 1997): the linear fifth-order edge value, kept when it lies between c and
+// the monotonicity-preserving bound c + minmod(d - c, 4 (c - b)); otherwise
+// moved to the nearest point of [v_min, v_max], the interval built from the
+// upper and lower limits with the curvature measures d^M4 (alpha = 4).
+real mp5(real a, real b, real c, real d, real e) {
+  const real alpha = 4.0;
+  real vl = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) / 60.0;
+  real vmp = c + minmod2(d - c, alpha * (c - b));
+  if ((vl - c) * (vl - vmp) <= 0.0) return vl;
+  real djm1 = a + c - 2.0 * b, dj = b + d - 2.0 * c, djp1 = c + e - 2.0 * d;
+  real dm4p = minmod4(4.0 * dj - djp1, 4.0 * djp1 - dj, dj, djp1);
+  real dm4m = minmod4(4.0 * dj - djm1, 4.0 * djm1 - dj, dj, djm1);
+  real vul = c + alpha * (c - b);
+  real vav = 0.5 * (c + d);
+  real vmd = vav - 0.5 * dm4p;
+  real vlc = c + 0.5 * (c - b) + 4.0 / 3.0 * dm4m;
+  real vmin = rmax(min3(c, d, vmd), min3(c, vul, vlc));
+  real vmax = rmin(max3(c, d, vmd), max3(c, vul, vlc));
+  return vl + minmod2(vmin - vl, vmax - vl);
+}
+
+// PPM (Colella & Woodward 1984) edge values of zone c from (a, b, c, d, e):
+// interface values a_{c+-1/2} = x + (y - x)/2 - (da_y - da_x)/6 with the
+// limited slopes da (the monotonised-central slope, their limiter), then the
+// parabola through (aL, c, aR) made monotone in the zone: flattened to c at
+// an extremum, otherwise the edge on the side of an interior extremum moved
+// to 3c - 2 (other edge).
+void ppm_edges(real a, real b, real c, real d, real e, real& aL, real& aR) {
+  real sb = mc_slope(a, b, c), sc = mc_slope(b, c, d), sd = mc_slope(c, d, e);
+  aL = b + 0.5 * (c - b) - (sc - sb) / 6.0;
+  aR = c + 0.5 * (d - c) - (sd - sc) / 6.0;
+  if ((aR - c) * (c - aL) <= 0.0) {
+    aL = c;
+    aR = c;
+    return;
+  }
+  real da = aR - aL, a6 = 6.0 * (c - 0.5 * (aL + aR));
+  if (da * a6 > da * da)
+    aL = 3.0 * c - 2.0 * aR;
+  else if (-(da * da) > da * a6)
+    aR = 3.0 * c - 2.0 * aL;
+}
+
 // ------------------------------------------------------------------ grid --
 
 struct Grid {
@@ -486,6 +546,15 @@ void reconstruct(const Grid& g, const std::vector<real>& P, int recon, int d, in
     } else if (recon == RECON_WENOZ) {
       qL[v] = wenoz(q[0], q[1], q[2], q[3], q[4], g.c.weno_eps);
       qR[v] = wenoz(q[5], q[4], q[3], q[2], q[1], g.c.weno_eps);
+    } else if (recon == RECON_MP5) {
+      qL[v] = mp5(q[0], q[1], q[2], q[3], q[4]);
+      qR[v] = mp5(q[5], q[4], q[3], q[2], q[1]);
+    } else if (recon == RECON_PPM) {
+      real l, r;
+      ppm_edges(q[0], q[1], q[2], q[3], q[4], l, r);  // zone -1: its right edge
+      qL[v] = r;
+      ppm_edges(q[1], q[2], q[3], q[4], q[5], l, r);  // zone 0: its left edge
+      qR[v] = l;
     } else {
       qL[v] = weno5(q[0], q[1], q[2], q[3], q[4], g.c.weno_eps);
       qR[v] = weno5(q[5], q[4], q[3], q[2], q[1], g.c.weno_eps);
@@ -1883,6 +1952,13 @@ double orc_wenoz(double a, double b, double c, double d, double e, double eps) {
   return (double)wenoz(a, b, c, d, e, eps);
 }
 double orc_vl_slope(double l, double c, double r) { return (double)vl_slope(l, c, r); }
+double orc_mp5(double a, double b, double c, double d, double e) { return (double)mp5(a, b, c, d, e); }
+void orc_ppm_edges(double a, double b, double c, double d, double e, double* aL, double* aR) {
+  real l, r;
+  ppm_edges(a, b, c, d, e, l, r);
+  *aL = (double)l;
+  *aR = (double)r;
+}
 
 // ---- operation counts (counting build; zeros otherwise) ----
 

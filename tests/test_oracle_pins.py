@@ -374,6 +374,100 @@ def test_van_leer_slope():
     assert np.log2(np.array(errs[:-1]) / np.array(errs[1:])).min() > 1.8
 
 
+def _extremum_order(fn, hs=(0.08, 0.04, 0.02, 0.01, 0.005)):
+    """Fitted order of an edge value 0.3 h from a smooth maximum of
+    f = cos(pi x) + x^3, from cell averages."""
+    F = lambda x: np.sin(np.pi * x) / np.pi + 0.25 * x ** 4
+    f = lambda x: np.cos(np.pi * x) + x ** 3
+    errs = []
+    for h in hs:
+        xe = -0.3 * h
+        centres = xe - h / 2 + h * np.arange(-2, 3)
+        avg = (F(centres + h / 2) - F(centres - h / 2)) / h
+        errs.append(abs(fn(*avg) - f(xe)))
+    return np.polyfit(np.log(hs), np.log(errs), 1)[0]
+
+
+def _smooth_order(fn, hs=(0.1, 0.05, 0.025, 0.0125)):
+    f_int = lambda x: -np.cos(x) + 0.1 * x ** 3
+    f = lambda x: np.sin(x) + 0.3 * x * x
+    errs = []
+    for h in hs:
+        centres = 0.4 + h * np.arange(-2, 3)
+        avg = (f_int(centres + h / 2) - f_int(centres - h / 2)) / h
+        errs.append(abs(fn(*avg) - f(0.4 + h / 2)))
+    return np.log2(np.array(errs[:-1]) / np.array(errs[1:])).min()
+
+
+def _monotone_samples(n, seed):
+    rng = np.random.default_rng(seed)
+    for _ in range(n):
+        q = np.cumsum(np.abs(rng.normal(size=5)) * np.exp(2 * rng.normal(size=5)))
+        yield q if rng.random() < 0.5 else -q
+
+
+def test_mp5_limiter_inactive_on_smooth_data_and_high_order_at_extrema():
+    """On smooth monotone cell averages MP5 leaves the linear fifth-order edge
+    value untouched (fifth order); at a smooth extremum its curvature-based
+    bounds keep high order where a TVD limit (MC, PPM) clips to second."""
+    F = lambda x: -np.cos(x) + 0.1 * x ** 3
+    for h in (0.1, 0.05, 0.025):
+        avg = (F(0.4 + h * np.arange(-2, 3) + h / 2) - F(0.4 + h * np.arange(-2, 3) - h / 2)) / h
+        a, b, c_, d, e = avg
+        assert oracle.mp5(*avg) == pytest.approx((2 * a - 13 * b + 47 * c_ + 27 * d - 3 * e) / 60,
+                                                 rel=1e-15)
+    assert _smooth_order(oracle.mp5) > 4.5
+    mc_edge = lambda a, b, c_, d, e: c_ + 0.5 * oracle.mc_slope(b, c_, d)
+    assert _extremum_order(oracle.mp5) > 4.0
+    assert _extremum_order(mc_edge) < 2.2
+
+
+def test_mp5_monotonicity_preserving():
+    """Monotone data (20000 random sequences over ten decades of steps):
+    the edge value lies between the two zones that share the edge; a jump
+    gives no overshoot; odd and translation-invariant."""
+    for q in _monotone_samples(20000, 3):
+        v = oracle.mp5(*q)
+        lo, hi = min(q[2], q[3]), max(q[2], q[3])
+        assert lo - 1e-12 * abs(hi) <= v <= hi + 1e-12 * abs(hi), q
+    assert oracle.mp5(1.0, 1.0, 1.0, 0.0, 0.0) == 1.0
+    assert oracle.mp5(0.0, 0.0, 0.0, 1.0, 1.0) == 0.0
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        q = rng.normal(size=5)
+        assert oracle.mp5(*q) == pytest.approx(-oracle.mp5(*(-q)), rel=1e-13, abs=1e-15)
+        assert oracle.mp5(*(q + 2.0)) == pytest.approx(oracle.mp5(*q) + 2.0, rel=1e-13)
+
+
+def test_ppm_edges():
+    """Colella & Woodward's PPM: fourth-order interface values on smooth
+    monotone cell averages (and exact for a cubic); the limited parabola has
+    no extremum inside its zone (|a6| <= |aR - aL|, or flattened to the zone
+    value at an extremum of the data); on monotone data each edge lies
+    between the zones that share it; second order at a smooth extremum."""
+    assert _smooth_order(lambda *q: oracle.ppm_edges(*q)[1]) > 3.8
+    # cubic: cell averages of x^3 - x on unit zones centred at 0..4 (monotone there)
+    F = lambda x: x ** 4 / 4 - x ** 2 / 2
+    centres = np.arange(5.0) + 2.0
+    avg = F(centres + 0.5) - F(centres - 0.5)
+    l, r = oracle.ppm_edges(*avg)
+    f = lambda x: x ** 3 - x
+    assert l == pytest.approx(f(3.5), rel=1e-14) and r == pytest.approx(f(4.5), rel=1e-14)
+    rng = np.random.default_rng(8)
+    for _ in range(20000):
+        q = rng.normal(size=5) * np.exp(rng.normal(size=5))
+        l, r = oracle.ppm_edges(*q)
+        da, a6 = r - l, 6 * (q[2] - 0.5 * (l + r))
+        assert (l == q[2] and r == q[2]) or abs(a6) <= abs(da) * (1 + 1e-12) + 1e-13 * abs(q).max(), q
+    for q in _monotone_samples(20000, 3):
+        l, r = oracle.ppm_edges(*q)
+        for x, (y, z) in ((r, (q[2], q[3])), (l, (q[1], q[2]))):
+            lo, hi = min(y, z), max(y, z)
+            assert lo - 1e-12 * abs(hi) <= x <= hi + 1e-12 * abs(hi), q
+    assert oracle.ppm_edges(0.0, 1.0, 2.0, 1.0, 0.0) == (2.0, 2.0)
+    assert _extremum_order(lambda *q: oracle.ppm_edges(*q)[1]) < 2.2
+
+
 # ------------------------------------------------------------- whole step
 
 def test_uniform_state_is_preserved():
@@ -555,11 +649,27 @@ def test_linear_mode_convergence_wenoz_and_van_leer_fast():
     assert np.all((slope > 1.85) & (slope < 2.15)), slope
 
 
+def test_linear_mode_convergence_mp5_and_ppm_fast():
+    """The fast mode with MP5 (32 -> 64) converges at second order, the
+    step's order.  PPM flattens the parabola in every zone holding an
+    extremum of the data, which a smooth mode has along two lines: that
+    first-order clipping (what extremum-preserving PPMX was made to remove)
+    holds PPM's slope to 1.6-1.9 from 32 to 64, falling towards first order
+    on finer grids."""
+    e = _mode_errors("fast", oracle.RECON_MP5, (32, 64))
+    slope = np.log2(e[0] / e[1])
+    assert np.all((slope > 1.9) & (slope < 2.1)), slope
+    e = _mode_errors("fast", oracle.RECON_PPM, (32, 64))
+    slope = np.log2(e[0] / e[1])
+    assert np.all((slope > 1.6) & (slope < 2.0)), slope
+
+
 def test_entropy_mode_at_least_second_order():
     # van Leer's limiter flattens the mode's extrema more than MC on 16 zones
     # (slope 1.5 from 16 to 32); from 32 on it is second order
     for recon, ns in ((RECON_MC, (16, 32)), (RECON_WENO5, (16, 32)), (oracle.RECON_WENOZ, (16, 32)),
-                      (oracle.RECON_VL, (32, 64))):
+                      (oracle.RECON_VL, (32, 64)), (oracle.RECON_MP5, (16, 32)),
+                      (oracle.RECON_PPM, (16, 32))):
         e = _mode_errors("entropy", recon, ns)
         assert np.all(np.log2(e[0] / e[1]) > 1.9), (recon, np.log2(e[0] / e[1]))
 
