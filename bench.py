@@ -314,7 +314,8 @@ def recon_extra(torch, gr, grid, P, gam, steps):
     Pt = torch.from_numpy(P).cuda()
     res = {}
     names = (("donor", gr.RECON_DONOR), ("mc", gr.RECON_MC), ("vl", gr.RECON_VL),
-             ("weno5", gr.RECON_WENO5), ("wenoz", gr.RECON_WENOZ))
+             ("ppm", gr.RECON_PPM), ("mp5", gr.RECON_MP5), ("weno5", gr.RECON_WENO5),
+             ("wenoz", gr.RECON_WENOZ))
     for name, recon in names:
         row = {}
         for pname, prec in (("fp64", gr.PREC_FP64), ("mixed", gr.PREC_MIXED)):

@@ -305,6 +305,19 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ P, long nz
         p2 = (R)q[2 * s];
       qL[v] = wenoz(m3, m2, m1, p0, p1, eps);
       qR[v] = wenoz(p2, p1, p0, m1, m2, eps);
+    } else if (RECON == GRMHD_RECON_MP5) {
+      R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
+        p2 = (R)q[2 * s];
+      qL[v] = mp5(m3, m2, m1, p0, p1);
+      qR[v] = mp5(p2, p1, p0, m1, m2);
+    } else if (RECON == GRMHD_RECON_PPM) {
+      R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
+        p2 = (R)q[2 * s];
+      R l, r;
+      ppm_edges(m3, m2, m1, p0, p1, l, r);  // zone i-1: its right edge
+      qL[v] = r;
+      ppm_edges(m2, m1, p0, p1, p2, l, r);  // zone i: its left edge
+      qR[v] = l;
     } else {
       R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
         p2 = (R)q[2 * s];
@@ -1849,7 +1862,7 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
       return false;
   }
   if (!(g->x1max > g->x1min && g->x2max > g->x2min && g->x3max > g->x3min)) return false;
-  if (p->recon < GRMHD_RECON_MC || p->recon > GRMHD_RECON_VL) return false;
+  if (p->recon < GRMHD_RECON_MC || p->recon > GRMHD_RECON_PPM) return false;
   // the WENO weights' products stay normal in FP64 and the FP32 indicators
   // stay positive for eps >= 1e-36
   if ((p->recon == GRMHD_RECON_WENO5 || p->recon == GRMHD_RECON_WENOZ) &&
@@ -2037,6 +2050,10 @@ int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullp
     rc = face ? go(k_flux_all<GRMHD_RECON_VL, R, FT, true>) : go(k_flux_all<GRMHD_RECON_VL, R, FT, false>);
   else if (c->params.recon == GRMHD_RECON_WENOZ)
     rc = face ? go(k_flux_all<GRMHD_RECON_WENOZ, R, FT, true>) : go(k_flux_all<GRMHD_RECON_WENOZ, R, FT, false>);
+  else if (c->params.recon == GRMHD_RECON_MP5)
+    rc = face ? go(k_flux_all<GRMHD_RECON_MP5, R, FT, true>) : go(k_flux_all<GRMHD_RECON_MP5, R, FT, false>);
+  else if (c->params.recon == GRMHD_RECON_PPM)
+    rc = face ? go(k_flux_all<GRMHD_RECON_PPM, R, FT, true>) : go(k_flux_all<GRMHD_RECON_PPM, R, FT, false>);
   else
     rc = face ? go(k_flux_all<GRMHD_RECON_WENO5, R, FT, true>) : go(k_flux_all<GRMHD_RECON_WENO5, R, FT, false>);
   if (rc) return rc;

@@ -111,6 +111,10 @@ using f64::vl_left;
 using f32::vl_left;
 using f64::vl_right;
 using f32::vl_right;
+using f64::mp5;
+using f32::mp5;
+using f64::ppm_edges;
+using f32::ppm_edges;
 using f64::llf;
 using f32::llf;
 using fdual::llf;

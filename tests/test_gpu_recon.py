@@ -1,12 +1,13 @@
-"""GPU-vs-oracle parity of the further reconstructions: WENO-Z (power 2)
-and linear reconstruction with van Leer's limiter, through the C ABI.
+"""GPU-vs-oracle parity of the further reconstructions: WENO-Z (power 2),
+linear reconstruction with van Leer's limiter, MP5 and PPM, through the C
+ABI.
 
 Bars as for MC and WENO5: relative L1 per primitive at most 1e-12 per step
 (1e-11 for WENO-Z on a linear mode, whose weights the GPU rounds differently
-from the oracle, as for WENO5), failure counts equal; van Leer's slope is
-evaluated in the oracle's order, so flat space agrees bit for bit.  The
-mixed-precision forms are held against the FP64 GPU path of the same
-reconstruction.
+from the oracle, as for WENO5), failure counts equal; van Leer's slope, MP5
+and PPM are evaluated in the oracle's order, so flat space agrees bit for
+bit.  The mixed-precision forms are held against the FP64 GPU path of the
+same reconstruction.
 """
 
 import os
@@ -22,7 +23,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 THREADS = min(16, os.cpu_count() or 1)
-WENOZ, VL = oracle.RECON_WENOZ, oracle.RECON_VL
+WENOZ, VL, MP5, PPM = oracle.RECON_WENOZ, oracle.RECON_VL, oracle.RECON_MP5, oracle.RECON_PPM
+BITWISE_FLAT = (VL, MP5, PPM)
 
 
 def _setup():
@@ -41,6 +43,14 @@ CASES = {
     "alfven24x20_vl_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, VL, TOL),
     "torus20x28x6_vl": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, VL, TOL),
     "bondi32x16_vl": lambda: (bondi(32, 16)[0:2], 4 / 3, VL, TOL),
+    "fast16_mp5": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, MP5, TOL),
+    "slow20_mp5_2d": lambda: (linear_mode("slow", 20, ndim=2)[0:2], 4 / 3, MP5, TOL),
+    "torus24_mp5": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, MP5, TOL),
+    "bondi24x12x2_mp5": lambda: (bondi(24, 12, 2)[0:2], 4 / 3, MP5, TOL),
+    "fast16_ppm": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, PPM, TOL),
+    "alfven24x20_ppm_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, PPM, TOL),
+    "torus20x28x6_ppm": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, PPM, TOL),
+    "bondi32x16_ppm": lambda: (bondi(32, 16)[0:2], 4 / 3, PPM, TOL),
 }
 
 
@@ -60,11 +70,11 @@ def test_step_parity_further_reconstructions(case):
     print(case, "dts", dts, "fails", fails, s.status()[0], "rel L1", r)
     assert s.status()[0] == fails
     assert r.max() <= tol, r
-    if recon == VL and grid.metric == 0:
+    if recon in BITWISE_FLAT and grid.metric == 0:
         assert np.array_equal(interior(out), interior(ref))
 
 
-@pytest.mark.parametrize("recon", [WENOZ, VL])
+@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM])
 def test_flux_parity_further_reconstructions(recon):
     torch, gr = _setup()
     grid, P, _ = fm_torus(16, 16, 8)
@@ -82,7 +92,7 @@ def test_flux_parity_further_reconstructions(recon):
         assert err.max() < 1e-12, (d, err)
 
 
-@pytest.mark.parametrize("recon", [WENOZ, VL])
+@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM])
 def test_torus128_full_step_further_reconstructions(recon):
     """The benchmark torus (128^3) with each reconstruction: one device-side
     CFL step, every zone against the oracle."""
@@ -103,7 +113,7 @@ def test_torus128_full_step_further_reconstructions(recon):
     assert s.status()[0] == fails
 
 
-@pytest.mark.parametrize("recon", [WENOZ, VL])
+@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM])
 def test_mixed_precision_further_reconstructions(recon):
     """FP32 reconstruction and fluxes against the FP64 GPU path of the same
     reconstruction (3 steps of a 32 x 32 x 16 torus): density within 1e-4
@@ -131,6 +141,6 @@ def test_mixed_precision_further_reconstructions(recon):
 def test_packs_and_adjoint_take_mc_or_weno5_only():
     torch, gr = _setup()
     g, blocks, _ = torus_pack(nblocks=4, n_global=32, sizes=(8,), probs=(1.0,), seed=4)
-    for recon in (WENOZ, VL):
+    for recon in (WENOZ, VL, MP5, PPM):
         with pytest.raises(gr.GrmhdError):
             gr.Pack(g, [b["n"] for b in blocks], [b["offset"] for b in blocks], 13 / 9, recon=recon)

@@ -91,19 +91,21 @@ def test_reconstruction_choices_are_validated():
     mk = lambda recon, eps=1e-26: grmhd.make_params(13 / 9, 0.9, eps, 1e-14, 30, recon,
                                                      grmhd.PREC_FP64, 0, 1e3)
     base = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_WENO5)))
-    for r in (grmhd.RECON_MC, grmhd.RECON_DONOR, grmhd.RECON_WENOZ, grmhd.RECON_VL):
+    for r in (grmhd.RECON_MC, grmhd.RECON_DONOR, grmhd.RECON_WENOZ, grmhd.RECON_VL, grmhd.RECON_MP5,
+              grmhd.RECON_PPM):
         assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r))) == base
-    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(5))) == 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(7))) == 0
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(-1))) == 0
     # the WENO regulariser must keep the weight products normal ...
     for r in (grmhd.RECON_WENO5, grmhd.RECON_WENOZ):
         assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 1e-40))) == 0
         assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 2.0))) == 0
         assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 1e-36))) == base
-    # ... and is not looked at by the linear schemes
-    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_VL, 0.0))) == base
+    # ... and is not looked at by the other schemes
+    for r in (grmhd.RECON_VL, grmhd.RECON_MP5, grmhd.RECON_PPM):
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 0.0))) == base
     # the adjoint and packs take MC or WENO5 only
-    for r in (grmhd.RECON_WENOZ, grmhd.RECON_VL):
+    for r in (grmhd.RECON_WENOZ, grmhd.RECON_VL, grmhd.RECON_MP5, grmhd.RECON_PPM):
         assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(r))) == 0
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_MC))) > 0
 

@@ -651,11 +651,15 @@ def test_linear_mode_convergence_wenoz_and_van_leer_fast():
 
 def test_linear_mode_convergence_mp5_and_ppm_fast():
     """The fast mode with MP5 (32 -> 64) converges at second order, the
-    step's order.  PPM flattens the parabola in every zone holding an
-    extremum of the data, which a smooth mode has along two lines: that
-    first-order clipping (what extremum-preserving PPMX was made to remove)
-    holds PPM's slope to 1.6-1.9 from 32 to 64, falling towards first order
-    on finer grids."""
+    step's order.  PPM's interface value is one number shared by the zones
+    on both sides of a face wherever its limiters are idle, so on smooth
+    data the LLF flux has no jump to dissipate and the step is a central
+    scheme, which SSPRK2 (no stability on the imaginary axis) does not damp:
+    the grid-scale noise seeded where the limiters act (the extremum lines)
+    grows, and the error stops falling near 1.8e-3 of the amplitude from 128^2
+    on (1.79e-9 at 128^2, 1.86e-9 at 256^2 for amplitude 1e-6; with the
+    parabola limiter off it stalls ten times higher).  From 32 to 64 the
+    slope is 1.6-1.9."""
     e = _mode_errors("fast", oracle.RECON_MP5, (32, 64))
     slope = np.log2(e[0] / e[1])
     assert np.all((slope > 1.9) & (slope < 2.1)), slope
