@@ -270,8 +270,70 @@ def extras(torch, gr, np, args):
         "tiles_note": "per block size: t1 x t2 x t3 zones, or [0, 0, 0] = runs of 256 consecutive "
                       "positions of each box",
         "inversion_failures_timed_steps": fails}
+    out["tiling_exchange"] = tiling_extra(torch, gr, np, gam, dt, steps, args)
     out["adjoint"] = adjoint_extra(torch, gr)
     return out
+
+
+def tiling_extra(torch, gr, np, gam, dt, steps, args):
+    """The whole 128^3 torus as an uneven octree-like tiling (blocks of 16,
+    32 and 64) advanced as one pack with the ghost exchange before every
+    stage, against the single 128^3 grid at the same fixed dt: throughput of
+    both and the density L1 of the tiling against the grid after the steps."""
+    from workloads import torus_tiling, interior, RECON_WENO5
+    from paper_2408_01361_amd import autotune
+    g, blocks, P, _ = torus_tiling(128, sizes=(16, 32, 64), split=0.6, seed=5, gamma=gam)
+    flat = torch.from_numpy(np.concatenate([b["prims"].ravel() for b in blocks])).cuda()
+    pk = gr.Pack(g, [b["n"] for b in blocks], [b["offset"] for b in blocks], gam, recon=RECON_WENO5)
+    pk.set_exchange(True)
+    pk.load(flat)
+    if not args.no_tune:
+        autotune.tune_pack(pk, dt)
+        pk.load(flat)
+    for _ in range(3):               # untimed: clocks settle
+        pk.step(dt)
+    pk.load(flat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pk.step(dt)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    packed = _unpack_blocks(pk.prims().cpu().numpy(), blocks)
+    fails_pack = pk.status()
+    pk.set_exchange(False)           # the same pack with frozen ghosts: the exchange's cost
+    pk.load(flat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pk.step(dt)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    del pk, flat
+    s = gr.Grmhd(g, gam, recon=RECON_WENO5)
+    Pt = torch.from_numpy(P).cuda()
+    s.load(Pt)
+    for _ in range(3):
+        s.step(dt)
+    s.load(Pt)
+    s.reset_status()
+    ts = time_steps(torch, s, steps, use_dt=False, dt=dt)
+    ref = interior(s.prims().cpu().numpy())[0]
+    fails_single = s.status()[0]
+    num = 0.0
+    for b, q in zip(blocks, packed):
+        i, j, k = b["offset"]
+        n = b["n"]
+        num += float(np.abs(interior(q)[0] - ref[k:k + n, j:j + n, i:i + n]).sum())
+    zones = 128 ** 3
+    counts = ", ".join(f"{sum(1 for b in blocks if b['n'] == m)} x {m}^3" for m in (16, 32, 64))
+    return {"workload": f"128^3 torus tiled by {len(blocks)} blocks ({counts}), WENO5, FP64, "
+                        f"ghost exchange + one persistent launch per stage, {steps} steps at fixed dt",
+            "zone_cycles_per_s": zones * steps / tp,
+            "frozen_ghosts_zone_cycles_per_s": zones * steps / tf,
+            "single_grid_zone_cycles_per_s": zones * steps / ts,
+            "rho_rel_l1_vs_single_grid": num / float(np.abs(ref).sum()),
+            "inversion_failures": {"tiling": fails_pack, "single_grid": fails_single}}
 
 
 def kastaun_extra(torch, gr, grid, P, gam, recon, steps):

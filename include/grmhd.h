@@ -248,7 +248,8 @@ int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const do
  * A pack holds nblocks cubic blocks of n[b]^3 zones, block b being the
  * sub-box starting at interior zone offsets_ijk[3b..3b+2] of the global grid
  * (same metric and parameters); every block has frozen (Dirichlet) ghost
- * zones, and x2 block faces on the polar axis carry no flux.  One pack step is
+ * zones unless the ghost exchange below is on, and x2 block faces on the
+ * polar axis carry no flux.  One pack step is
  * one persistent cooperative launch per RK2 stage that processes every block.
  * Packed prims: the blocks' padded arrays [8][n+6][n+6][n+6], concatenated in
  * block order (device).  Tile shapes per block size (t1*t2*t3 <= 256, or
@@ -269,6 +270,22 @@ int grmhd_pack_load_prims(grmhd_pack* pack, const double* d_prims);
 int grmhd_pack_step(grmhd_pack* pack, double dt);
 int grmhd_pack_get_prims(grmhd_pack* pack, double* d_out);
 int grmhd_pack_get_status(grmhd_pack* pack, long long* n_inv_fail);
+/* Ghost exchange between the blocks of a pack (the paper's meshblocks with
+ * boundary synchronisation each sub-step; Package structure and Glue
+ * sections), on one GPU.  With it on, before each RK2 stage every ghost zone
+ * of every block takes the value the single global grid would hold there:
+ * the zone of the global grid at that position, mapped by the global
+ * boundary conditions (periodic, outflow, polar mirror with u~2 and B2
+ * flipped), read from the block that owns it; positions on frozen global
+ * axes and zones no block owns keep their values.  Blocks that tile the
+ * global grid then advance as the global grid does.  d_map (device, 4-byte
+ * aligned, >= grmhd_pack_exchange_bytes(global) bytes, one int per global
+ * interior zone) is filled here with the owner map (synchronises) and
+ * borrowed while the exchange is on; d_map = NULL switches it off (frozen
+ * ghosts, the default).  E_ARG for overlapping blocks or more than 65535
+ * blocks, E_NOMEM for a short map. */
+size_t grmhd_pack_exchange_bytes(const grmhd_grid* global);
+int grmhd_pack_set_exchange(grmhd_pack* pack, void* d_map, size_t map_bytes);
 /* Cooperative grid size and length (doubles) of the packed prims. */
 int grmhd_pack_info(grmhd_pack* pack, int* grid_blocks, long long* prim_doubles);
 int grmhd_pack_destroy(grmhd_pack* pack);

@@ -2727,6 +2727,9 @@ struct grmhd_pack {
   unsigned* d_counters;
   unsigned long long* d_fails;
   int grid_blocks;
+  grmhd_grid global;
+  int* d_owner;  // ghost exchange: owner block of every global interior zone, or null (frozen ghosts)
+  int max_nz;    // padded zones of the largest block
 };
 
 namespace {
@@ -2794,6 +2797,12 @@ int pack_upload(grmhd_pack* pk) {
 
 template <int RECON>
 int pack_launch(grmhd_pack* pk, int stage, double dt) {
+  if (pk->d_owner) {
+    PackGlobal G{pk->global.n1, pk->global.n2, pk->global.n3, {0, 0, 0, 0, 0, 0}};
+    for (int a = 0; a < 6; a++) G.bc[a] = pk->global.bc[a];
+    dim3 grid((unsigned)((pk->max_nz + BLOCK - 1) / BLOCK), (unsigned)pk->nb);
+    k_pack_exchange<<<grid, BLOCK, 0, pk->stream>>>(pk->d_views, pk->d_owner, G, stage);
+  }
   if (hipMemsetAsync(pk->d_counters, 0, sizeof(unsigned) * PH_N, pk->stream) != hipSuccess) return GRMHD_E_HIP;
   const BlockView* views = pk->d_views;
   int nb = pk->nb;
@@ -2841,6 +2850,9 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
   pk->metric = *metric;
   pk->stream = (hipStream_t)stream;
   pk->nb = nblocks;
+  pk->global = *global;
+  pk->d_owner = nullptr;
+  pk->max_nz = 0;
   pack_carve(nblocks, n, (char*)d_ws, pk);
   const double gd1 = (global->x1max - global->x1min) / global->n1;
   const double gd2 = (global->x2max - global->x2min) / global->n2;
@@ -2880,6 +2892,10 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
     g.gamma_max = params->gamma_max;
     g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
     BlockView& v = pk->views[b];
+    v.o1 = o[0];
+    v.o2 = o[1];
+    v.o3 = o[2];
+    if (g.nz > pk->max_nz) pk->max_nz = (int)g.nz;
     default_tile(n[b], v.t1, v.t2, v.t3);
     k_geometry<<<blocks_for(g.plane), BLOCK, 0, pk->stream>>>(g, v.tabC, v.tabF1, v.tabF2, v.corner, v.conn);
   }
@@ -2964,6 +2980,39 @@ int grmhd_pack_info(grmhd_pack* pk, int* grid_blocks, long long* prim_doubles) {
   if (!pk || !grid_blocks || !prim_doubles) return GRMHD_E_ARG;
   *grid_blocks = pk->grid_blocks;
   *prim_doubles = pk->prim_total;
+  return GRMHD_OK;
+}
+
+size_t grmhd_pack_exchange_bytes(const grmhd_grid* global) {
+  if (!global || global->n1 < 1 || global->n2 < 1 || global->n3 < 1) return 0;
+  return sizeof(int) * (size_t)global->n1 * global->n2 * global->n3;
+}
+
+int grmhd_pack_set_exchange(grmhd_pack* pk, void* d_map, size_t map_bytes) {
+  if (!pk) return GRMHD_E_ARG;
+  if (!d_map) {
+    pk->d_owner = nullptr;
+    return GRMHD_OK;
+  }
+  const grmhd_grid& G = pk->global;
+  if (((uintptr_t)d_map & 3) != 0 || pk->nb > 65535) return GRMHD_E_ARG;
+  if (map_bytes < grmhd_pack_exchange_bytes(&G)) return GRMHD_E_NOMEM;
+  std::vector<int> own((size_t)G.n1 * G.n2 * G.n3, -1);
+  for (int b = 0; b < pk->nb; b++) {
+    const BlockView& v = pk->views[b];
+    const int n = v.g.n1;
+    for (int k = 0; k < n; k++)
+      for (int j = 0; j < n; j++)
+        for (int i = 0; i < n; i++) {
+          int& o = own[((size_t)(k + v.o3) * G.n2 + (j + v.o2)) * G.n1 + (i + v.o1)];
+          if (o >= 0) return GRMHD_E_ARG;  // blocks overlap
+          o = b;
+        }
+  }
+  if (hipStreamSynchronize(pk->stream) != hipSuccess ||
+      hipMemcpy(d_map, own.data(), sizeof(int) * own.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return GRMHD_E_HIP;
+  pk->d_owner = (int*)d_map;
   return GRMHD_OK;
 }
 

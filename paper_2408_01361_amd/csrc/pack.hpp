@@ -25,7 +25,7 @@ struct BlockView {
   double *F[3], *E[3];
   double *tabC, *tabF1, *tabF2, *corner, *conn;
   int t1, t2, t3;  // tile shape
-  int pad;
+  int o1, o2, o3;  // offset of the block's first interior zone in the global grid
 };
 
 enum { PH_FLUX = 0, PH_EMF = 1, PH_UPDATE = 2, PH_N = 3 };
@@ -149,5 +149,48 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PACK
       }
     }
     grid.sync();
+  }
+}
+
+// Ghost exchange between the blocks of a pack (the blocks tile part or all
+// of one global grid).  Grid: x over the padded positions of the largest
+// block, y over blocks.  A ghost zone of block b at global position G (its
+// local position plus the block offset) takes the value the single global
+// grid would hold there: G is mapped by the global boundary conditions
+// (periodic, outflow, polar mirror with u~2 and B2 flipped; frozen axes and
+// zones no block owns keep their values) to a global interior zone, whose
+// owner block supplies it.  Reads touch interior zones only and writes ghost
+// zones only, so no value read here is written here.
+struct PackGlobal {
+  int n1, n2, n3;
+  int bc[6];
+};
+
+__global__ void __launch_bounds__(BLOCK) k_pack_exchange(const BlockView* __restrict__ views,
+                                                         const int* __restrict__ owner, PackGlobal G,
+                                                         int stage) {
+  const BlockView& b = views[blockIdx.y];
+  const long t = blockIdx.x * (long)BLOCK + threadIdx.x;
+  if (t >= b.g.nz) return;
+  const int s1 = b.g.s1;
+  const int i = (int)(t % s1) - NG, j = (int)((t / s1) % s1) - NG, k = (int)(t / b.g.plane) - NG;
+  const int n = b.g.n1;
+  if (i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n) return;  // interior
+  bool f1 = false, f2 = false, f3 = false;
+  const int gi = bc_map(i + b.o1, G.n1, G.bc[0], G.bc[1], f1);
+  const int gj = bc_map(j + b.o2, G.n2, G.bc[2], G.bc[3], f2);
+  const int gk = bc_map(k + b.o3, G.n3, G.bc[4], G.bc[5], f3);
+  if (gi < 0 || gi >= G.n1 || gj < 0 || gj >= G.n2 || gk < 0 || gk >= G.n3) return;  // frozen
+  const int ob = owner[((long)gk * G.n2 + gj) * G.n1 + gi];
+  if (ob < 0) return;  // no block holds that zone
+  const BlockView& src = views[ob];
+  const long sidx = zid(src.g, gi - src.o1, gj - src.o2, gk - src.o3), didx = zid(b.g, i, j, k);
+  const double* Ps = stage == 1 ? src.P : src.P1;
+  double* Pd = stage == 1 ? b.P : b.P1;
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    double x = Ps[v * src.g.nz + sidx];
+    if (f2 && (v == U2 || v == B2)) x = -x;
+    Pd[v * b.g.nz + didx] = x;
   }
 }

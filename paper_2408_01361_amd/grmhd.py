@@ -73,6 +73,7 @@ EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_s
            "grmhd_pack_workspace_bytes", "grmhd_pack_create", "grmhd_pack_set_tiles",
            "grmhd_pack_load_prims", "grmhd_pack_step", "grmhd_pack_get_prims",
            "grmhd_pack_get_status", "grmhd_pack_info", "grmhd_pack_destroy",
+           "grmhd_pack_exchange_bytes", "grmhd_pack_set_exchange",
            "grmhd_vjp_workspace_bytes", "grmhd_step_vjp", "grmhd_set_schedule", "grmhd_timing", "grmhd_timing_report", "grmhd_strerror", "grmhd_destroy")
 
 
@@ -111,6 +112,8 @@ def load_library(path=LIB_PATH):
         "grmhd_pack_get_status": (C.c_int, [vp, ip]),
         "grmhd_pack_info": (C.c_int, [vp, C.POINTER(C.c_int), ip]),
         "grmhd_pack_destroy": (C.c_int, [vp]),
+        "grmhd_pack_exchange_bytes": (C.c_size_t, [G]),
+        "grmhd_pack_set_exchange": (C.c_int, [vp, vp, C.c_size_t]),
         "grmhd_vjp_workspace_bytes": (C.c_size_t, [G, P]),
         "grmhd_step_vjp": (C.c_int, [vp, vp, C.c_double, vp, vp, dp, vp, C.c_size_t]),
         "grmhd_set_schedule": (C.c_int, [vp, C.c_int, C.c_int]),
@@ -391,6 +394,19 @@ class Pack:
 
     def set_tiles(self, n, t1, t2, t3):
         _check(lib().grmhd_pack_set_tiles(self.h, int(n), int(t1), int(t2), int(t3)))
+
+    def set_exchange(self, on=True):
+        """Ghost exchange between the blocks before every stage (on), or
+        frozen ghosts (off, the default); the owner map lives in a tensor
+        kept here."""
+        L = lib()
+        if not on:
+            _check(L.grmhd_pack_set_exchange(self.h, None, 0))
+            self._owner = None
+            return
+        nbytes = L.grmhd_pack_exchange_bytes(C.byref(self.grid))
+        self._owner = torch.empty(nbytes // 4, dtype=torch.int32, device=self.device)
+        _check(L.grmhd_pack_set_exchange(self.h, _ptr(self._owner), nbytes))
 
     def load(self, packed):
         p = packed.to(device=self.device, dtype=torch.float64).contiguous()

@@ -11,7 +11,8 @@ import pytest
 
 import oracle
 from parity_util import GROUPS
-from workloads import torus_pack, interior, RECON_MC, RECON_WENO5
+from parity_util import rel_l1
+from workloads import torus_pack, torus_tiling, fm_torus, interior, RECON_MC, RECON_WENO5, NG
 
 pytestmark = pytest.mark.gpu
 
@@ -91,3 +92,60 @@ def test_pack_tile_shapes_do_not_change_results():
         outs.append(pk.prims().cpu().numpy())
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
+
+
+def _tiled_interior(flat, blocks, shape):
+    """The global interior assembled from a tiling's blocks."""
+    out = np.zeros((8,) + shape)
+    for b, q in zip(blocks, _unpack(flat, blocks)):
+        i, j, k = b["offset"]
+        n = b["n"]
+        out[:, k:k + n, j:j + n, i:i + n] = interior(q)
+    return out
+
+
+@pytest.mark.parametrize("recon", [RECON_MC, RECON_WENO5])
+def test_tiling_with_ghost_exchange_advances_as_the_global_grid(recon):
+    """An uneven octree-like tiling of the 64^3 torus (48 blocks of 16^3 and
+    2 of 32^3) with the ghost exchange on: two steps match the single global
+    grid on the GPU and the oracle's global run to the parity bar, with the
+    same failure count; with frozen ghosts the blocks drift apart from it."""
+    torch, gr = _setup()
+    gam = 13 / 9
+    g, blocks, P, _ = torus_tiling(64, sizes=(16, 32), split=0.5, seed=3, gamma=gam)
+    print("tiling", len(blocks), "blocks, recon", recon, flush=True)
+    single = gr.Grmhd(g, gam, recon=recon)
+    single.load(torch.from_numpy(P).cuda())
+    dt = single.dt()
+    for _ in range(2):
+        single.step(dt)
+    ref_gpu = interior(single.prims().cpu().numpy())
+    ref, fails, _ = oracle.run(oracle.cfg(g, gam=gam, recon=recon), P, dt, 2)
+    pk = gr.Pack(g, [b["n"] for b in blocks], [b["offset"] for b in blocks], gam, recon=recon)
+    pk.set_exchange(True)
+    pk.load(torch.from_numpy(_packed(blocks)).cuda())
+    for _ in range(2):
+        pk.step(dt)
+    shape = (64, 64, 64)
+    out = _tiled_interior(pk.prims().cpu().numpy(), blocks, shape)
+    pad = lambda A: np.pad(A, ((0, 0), (NG, NG), (NG, NG), (NG, NG)))
+    r_gpu = rel_l1(pad(out), pad(ref_gpu))
+    r_orc = rel_l1(pad(out), ref)
+    print("tiling vs single grid", r_gpu, "vs oracle", r_orc, "fails", pk.status(), single.status()[0], fails)
+    assert r_gpu.max() <= 1e-12 and r_orc.max() <= 1e-12
+    assert pk.status() == single.status()[0] == fails
+    # frozen ghosts: the same tiling no longer advances as the global grid
+    pk.set_exchange(False)
+    pk.load(torch.from_numpy(_packed(blocks)).cuda())
+    for _ in range(2):
+        pk.step(dt)
+    frozen = _tiled_interior(pk.prims().cpu().numpy(), blocks, shape)
+    assert rel_l1(pad(frozen), pad(ref_gpu)).max() > 1e-9
+
+
+def test_ghost_exchange_rejects_overlapping_blocks():
+    torch, gr = _setup()
+    g, blocks, _ = torus_pack(nblocks=4, n_global=32, sizes=(16,), probs=(1.0,), seed=4)
+    pk = gr.Pack(g, [16, 16], [(0, 0, 0), (8, 0, 0)], 13 / 9, recon=RECON_MC)
+    with pytest.raises(gr.GrmhdError):
+        pk.set_exchange(True)

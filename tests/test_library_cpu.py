@@ -110,6 +110,15 @@ def test_reconstruction_choices_are_validated():
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_MC))) > 0
 
 
+def test_pack_exchange_map_size():
+    from paper_2408_01361_amd import grmhd
+    from workloads import torus_grid
+    lib = grmhd.lib()
+    g = grmhd.make_grid(torus_grid(64, 48, 32))
+    assert lib.grmhd_pack_exchange_bytes(C.byref(g)) == 4 * 64 * 48 * 32
+    assert lib.grmhd_pack_set_exchange(None, None, 0) == grmhd.E_ARG
+
+
 def test_face_ct_parameters_and_workspace():
     from paper_2408_01361_amd import grmhd
     from workloads import torus_grid

@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from workloads import linear_mode, fm_torus, torus_pack, interior, NG
+from workloads import linear_mode, fm_torus, torus_pack, torus_tiling, interior, NG
 from workloads.linear_modes import select_mode
 from workloads.torus import fm_ell, fm_lnh, _mks_metric, _bsq
 
@@ -72,6 +72,24 @@ def test_pack_is_seeded_and_uses_global_data():
         i0, j0, k0 = b["offset"]
         n = b["n"]
         assert np.array_equal(b["prims"], P[:, k0:k0 + n + 2 * NG, j0:j0 + n + 2 * NG, i0:i0 + n + 2 * NG])
+
+
+def test_tiling_covers_the_grid_once_with_the_global_data():
+    """The uneven octree-like tiling covers every zone of the grid exactly
+    once, uses every requested size, and each block's padded prims are the
+    global padded prims over its sub-box."""
+    g, blocks, P, _ = torus_tiling(64, sizes=(16, 32), split=0.5, seed=3)
+    cover = np.zeros((64, 64, 64), int)
+    for b in blocks:
+        i, j, k = b["offset"]
+        n = b["n"]
+        cover[k:k + n, j:j + n, i:i + n] += 1
+        assert np.array_equal(b["prims"], P[:, k:k + n + 2 * NG, j:j + n + 2 * NG, i:i + n + 2 * NG])
+        assert b["grid"].x1min == pytest.approx(g.x1min + i * g.dx[0], rel=1e-15, abs=1e-15)
+    assert cover.min() == 1 and cover.max() == 1
+    assert {b["n"] for b in blocks} == {16, 32}
+    _, again, _, _ = torus_tiling(64, sizes=(16, 32), split=0.5, seed=3)
+    assert [b["offset"] for b in again] == [b["offset"] for b in blocks]
 
 
 def test_michel_solution_constants_and_sonic_point():
