@@ -15,7 +15,7 @@ from .spec import (NG, NVAR, BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN,
                    GridSpec, padded_shape, interior)
 from .linear_modes import linear_mode, linear_mode_faces, mode_eigensystem, MODES
 from .torus import fm_torus, torus_grid
-from .packs import torus_pack, torus_tiling
+from .packs import torus_pack, torus_tiling, tiling
 from .bondi import bondi, michel_constants, michel_rho
 from .blast import magnetised_blast, blast_grid
 
@@ -23,6 +23,6 @@ __all__ = [
     "NG", "NVAR", "BC_PERIODIC", "BC_OUTFLOW", "BC_POLAR", "BC_FROZEN",
     "METRIC_MINKOWSKI", "METRIC_KERR_MKS", "RECON_MC", "RECON_WENO5",
     "GridSpec", "padded_shape", "interior", "linear_mode", "linear_mode_faces", "mode_eigensystem",
-    "MODES", "fm_torus", "torus_grid", "torus_pack", "torus_tiling", "bondi", "michel_constants", "michel_rho",
+    "MODES", "fm_torus", "torus_grid", "torus_pack", "torus_tiling", "tiling", "bondi", "michel_constants", "michel_rho",
     "magnetised_blast", "blast_grid",
 ]

@@ -54,13 +54,14 @@ def _block(g, P, n, i0, j0, k0):
     return dict(n=n, offset=(i0, j0, k0), grid=bg, prims=sub)
 
 
-def torus_tiling(n_global=64, sizes=(16, 32), split=0.5, seed=3, torus_seed=1,
-                 gamma=13.0 / 9.0, magnetised=True):
+def tiling(g, P, sizes=(16, 32), split=0.5, seed=3):
+    """Octree-like uneven tiling of the cubic grid g (padded prims P) by
+    blocks of the given sizes (each a power-of-two multiple of the next)."""
     sizes = sorted(int(s) for s in sizes)
     top = sizes[-1]
+    n_global = g.n1
+    assert g.n2 == n_global and g.n3 == n_global
     assert n_global % top == 0 and all(top % s == 0 for s in sizes)
-    g, P, info = fm_torus(n_global, n_global, n_global, seed=torus_seed, gamma=gamma,
-                          magnetised=magnetised)
     rng = np.random.default_rng(seed)
     blocks = []
 
@@ -79,4 +80,11 @@ def torus_tiling(n_global=64, sizes=(16, 32), split=0.5, seed=3, torus_seed=1,
         for j0 in range(0, n_global, top):
             for i0 in range(0, n_global, top):
                 place(top, i0, j0, k0)
-    return g, blocks, P, info
+    return blocks
+
+
+def torus_tiling(n_global=64, sizes=(16, 32), split=0.5, seed=3, torus_seed=1,
+                 gamma=13.0 / 9.0, magnetised=True):
+    g, P, info = fm_torus(n_global, n_global, n_global, seed=torus_seed, gamma=gamma,
+                          magnetised=magnetised)
+    return g, tiling(g, P, sizes, split, seed), P, info
