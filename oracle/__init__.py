@@ -44,7 +44,7 @@ class Cfg(C.Structure):
                 ("rho_min_geom", C.c_double), ("u_min_geom", C.c_double),
                 ("bsq_over_rho_max", C.c_double), ("bsq_over_u_max", C.c_double),
                 ("u_over_rho_max", C.c_double), ("gamma_max", C.c_double),
-                ("fofc", C.c_int), ("ct", C.c_int)]
+                ("fofc", C.c_int), ("ct", C.c_int), ("integrator", C.c_int)]
 
 INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 RECON_DONOR = 2
@@ -53,6 +53,7 @@ RECON_VL = 4
 RECON_MP5 = 5
 RECON_PPM = 6
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
+INTEG_SSPRK2, INTEG_PC, INTEG_RK1 = 0, 1, 2
 FL_RHO, FL_U, FL_FLUID_FRAME, FL_GAMMA, FL_TEMP = 1, 2, 4, 8, 16
 # floor and ceiling defaults (HARM-family values; the paper states none)
 FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0,
@@ -128,7 +129,7 @@ def lib(counting=False):
 
 def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
         newton_maxit=30, cfl=0.9, nthreads=None, inverter=INV_1DW, kastaun_wmax=1e3,
-        floors=False, fofc=False, ct=CT_FLUX, **floor_params):
+        floors=False, fofc=False, ct=CT_FLUX, integrator=INTEG_SSPRK2, **floor_params):
     c = Cfg()
     c.n1, c.n2, c.n3 = grid.n1, grid.n2, grid.n3
     c.x1min, c.x1max = grid.x1min, grid.x1max
@@ -144,6 +145,7 @@ def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
     c.inverter, c.kastaun_wmax = int(inverter), float(kastaun_wmax)
     c.floors, c.fofc = int(bool(floors)), int(bool(fofc))
     c.ct = int(ct)
+    c.integrator = int(integrator)
     fp = dict(FLOOR_DEFAULTS)
     for k, v in floor_params.items():
         if k not in fp:

@@ -83,6 +83,8 @@ typedef struct {
   double u_over_rho_max, gamma_max;       // temperature and Lorentz-factor ceilings
   int fofc;            // 1: first-order flux correction of zones a stage would break
   int ct;              // 0: Flux-CT; face-centred CT with 1: averaged, 2: upwinded edge EMFs
+  int integrator;      // 0: SSPRK2; 1: predictor-corrector (half-step predictor, then the
+                       // full step from U^n with the predicted state's rates); 2: RK1 (forward Euler)
 } orc_cfg;
 }
 
@@ -1427,10 +1429,13 @@ void update_pass(const Grid& g, const std::vector<real>& Pin, const std::vector<
         if (stage == 0) {
           real u0[NV];
           cons_at(g, p, i, j, u0);
+          const real h = g.c.integrator == 1 ? 0.5 * dt : dt;  // the predictor takes half a step
           for (int v = 0; v < NV; v++) {
-            Unew[v] = u0[v] + dt * L[v];
+            Unew[v] = u0[v] + h * L[v];
             V(Un, g, v, i, j, k) = u0[v];
           }
+        } else if (g.c.integrator == 1) {  // corrector: U^n + dt L(P*)
+          for (int v = 0; v < NV; v++) Unew[v] = Vc(Un, g, v, i, j, k) + dt * L[v];
         } else {
           for (int v = 0; v < NV; v++)
             Unew[v] = 0.5 * (Vc(Un, g, v, i, j, k) + Vc(U1v, g, v, i, j, k)) + 0.5 * (dt * L[v]);
@@ -1485,7 +1490,10 @@ bool marked(const Grid& g, const std::vector<char>& mark, int i, int j, int k) {
 // One SSPRK2 (Heun) step:
 //   U1 = Un + dt L(Pn);                  P1   = U_to_P(U1; guess Pn)
 //   Un+1 = (Un + U1)/2 + (dt L(P1))/2;   Pn+1 = U_to_P(Un+1; guess P1)
-// Ghosts are refilled from each stage's prims before it runs.
+// Ghosts are refilled from each stage's prims before it runs.  The other
+// integrators the Solvers section lists change only the combination of the
+// stages: predictor-corrector (a half step gives P*, then the full step from
+// U^n with the rates of P*) and RK1 (one forward-Euler stage).
 //
 // First-order flux correction (Algorithm section, after Beckwith & Stone
 // 2011): each stage is first taken with the high-order fluxes; the zones
@@ -1508,7 +1516,8 @@ long step(const Grid& g, std::vector<real>& P, real dt, int* flags, std::vector<
   long fails0 = g_stats.fails;
   std::vector<real> phi1[3], phiV[3], phiOut[3], E[3];
 
-  for (int stage = 0; stage < 2; stage++) {
+  const int nstages = g.c.integrator == 2 ? 1 : 2;
+  for (int stage = 0; stage < nstages; stage++) {
     std::vector<real>& Pin = stage == 0 ? P : P1;
     std::vector<real>* phiIn = stage == 0 ? phi : phi1;
     fill_ghosts(g, Pin);
@@ -1566,7 +1575,9 @@ long step(const Grid& g, std::vector<real>& P, real dt, int* flags, std::vector<
         update_pass(g, Pin, Fct, stage, dt, Un, U1v, Pout, flags, nullptr, true, pnew);
       }
     }
-    if (stage == 0) {
+    if (nstages == 1) {  // RK1: the one stage is the step
+      P = Pout;
+    } else if (stage == 0) {
       P1 = Pout;
       if (phi)
         for (int d = 0; d < 3; d++) phi1[d] = phiOut[d];

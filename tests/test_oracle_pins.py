@@ -498,6 +498,46 @@ def _random_smooth_state(g, rng, amp=0.05):
     return P
 
 
+def test_integrators_time_order_and_linear_equivalence():
+    """The integrators the Solvers section lists besides SSPRK2: on a fixed
+    16^2 grid (fast mode, MC) the error against a 1024-step SSPRK2 run falls
+    at second order in dt for SSPRK2 and predictor-corrector and at first
+    order for RK1.  With a linear reconstruction (donor cell) the semi-
+    discrete operator is linear up to O(amplitude^2), and every two-stage
+    second-order Runge-Kutta method is the same polynomial in dt A there:
+    predictor-corrector and SSPRK2 then agree to 1e-4 of their time error,
+    which a wrong predictor fraction or corrector base would break."""
+    g, P, _, _ = linear_mode("fast", 16, ndim=2, amp=1e-4)
+    T = 0.2
+
+    def run(integ, nsteps, recon=RECON_MC):
+        c = oracle.cfg(g, recon=recon, integrator=integ)
+        return oracle.run(c, P, T / nsteps, nsteps)[0]
+
+    ref = run(oracle.INTEG_SSPRK2, 1024)
+    for integ, order in ((oracle.INTEG_SSPRK2, 2), (oracle.INTEG_PC, 2), (oracle.INTEG_RK1, 1)):
+        e = [np.abs(interior(run(integ, ns) - ref)).sum() for ns in (16, 32, 64)]
+        slope = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+        assert np.all(np.abs(slope - order) < 0.3), (integ, slope)
+    D = oracle.RECON_DONOR
+    a, b = run(oracle.INTEG_SSPRK2, 16, D), run(oracle.INTEG_PC, 16, D)
+    r = run(oracle.INTEG_SSPRK2, 1024, D)
+    assert np.abs(interior(a - b)).sum() < 1e-4 * np.abs(interior(a - r)).sum()
+
+
+@pytest.mark.parametrize("integ", [1, 2])
+def test_integrators_conserve_on_a_periodic_grid(integ):
+    g = GridSpec(12, 12, 12)
+    c = oracle.cfg(g, gam=4 / 3, recon=RECON_WENO5, integrator=integ)
+    P = _random_smooth_state(g, np.random.default_rng(5))
+    U0 = interior(oracle.prims_to_cons(c, P)).sum(axis=(1, 2, 3))
+    out, fails, _ = oracle.run(c, P, -1, 3)
+    assert fails == 0
+    U1 = interior(oracle.prims_to_cons(c, out)).sum(axis=(1, 2, 3))
+    scale = np.abs(interior(oracle.prims_to_cons(c, P))).sum(axis=(1, 2, 3)).max()
+    assert np.abs(U1 - U0).max() < 1e-14 * scale
+
+
 def test_conservation_on_periodic_grid():
     g = GridSpec(12, 12, 12)
     c = oracle.cfg(g, gam=4 / 3, recon=RECON_WENO5)
