@@ -401,6 +401,25 @@ def recon_extra(torch, gr, grid, P, gam, steps):
     return res
 
 
+def integrator_extra(torch, gr, grid, P, gam, recon, steps):
+    """The headline torus and step with each time integrator (CFL dt each
+    step): SSPRK2, predictor-corrector, RK1."""
+    Pt = torch.from_numpy(P).cuda()
+    res = {}
+    for name, integ in (("ssprk2", gr.INTEG_SSPRK2), ("pc", gr.INTEG_PC), ("rk1", gr.INTEG_RK1)):
+        s = gr.Grmhd(grid, gam, recon=recon, integrator=integ)
+        s.load(Pt)
+        for _ in range(10):          # untimed: clocks settle
+            s.step_cfl()
+        s.load(Pt)
+        el = time_steps(torch, s, steps)
+        res[name] = {"zone_cycles_per_s": grid.n1 * grid.n2 * grid.n3 * steps / el,
+                     "ms_per_step": el * 1e3 / steps}
+        del s
+    res["workload"] = "the headline torus and step, integrator swapped (a step of RK1 is one stage)"
+    return res
+
+
 def floors_fofc_extra(torch, gr, grid, P, gam, recon, steps):
     """What the floors and the first-order flux correction cost: the headline
     torus step plain, with floors, and with floors plus the correction; and
@@ -657,6 +676,7 @@ def main():
         out.update(extras(torch, gr, np, args))
         out["inverters"] = kastaun_extra(torch, gr, grid, P, gam, recon, args.steps)
         out["reconstructions"] = recon_extra(torch, gr, grid, P, gam, args.steps)
+        out["integrators"] = integrator_extra(torch, gr, grid, P, gam, recon, args.steps)
         out["floors_fofc"] = floors_fofc_extra(torch, gr, grid, P, gam, recon, args.steps)
         out["face_ct"] = face_ct_extra(torch, gr, grid, P, info, gam, recon, args.steps)
         out["timing_protocol"] = timing_protocol_extra(torch, gr, grid, P, gam, recon, args.steps)

@@ -48,6 +48,7 @@ enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_DONOR = 2, GRMHD_R
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1, GRMHD_INV_IMPLICIT = 2 };
 enum { GRMHD_CT_FLUX = 0, GRMHD_CT_FACE_AVG = 1, GRMHD_CT_FACE_GS = 2 };
+enum { GRMHD_INTEG_SSPRK2 = 0, GRMHD_INTEG_PC = 1, GRMHD_INTEG_RK1 = 2 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2,
        GRMHD_BC_FROZEN = 3 };
 
@@ -134,6 +135,13 @@ typedef struct {
                          from zone-centre EMFs, chosen by the sign of the
                          mass flux (GS).  The face divergence is kept to
                          roundoff.  Single grids only. */
+  int integrator;     /* GRMHD_INTEG_*: the time integrator (Solvers section's
+                         list).  SSPRK2 (the default and the only one packs,
+                         the VJP and the options above take); PC: predictor-
+                         corrector, U* = U^n + (dt/2) L(P^n), then
+                         U^{n+1} = U^n + dt L(P*); RK1: forward Euler, one
+                         stage per step.  PC and RK1 need Flux-CT without
+                         floors, the correction or the implicit recovery. */
 } grmhd_params;
 
 /* Bytes of device workspace a context with this grid and parameters needs. */

@@ -1406,7 +1406,8 @@ enum { U_PLAIN = 0, U_PROVISIONAL = 2, U_FINAL = 3, U_STORE = 4 };
 // Counter slots of the context's counter array.
 enum { C_FAILS = 0, C_C2P = 1, C_FLOORS = 2, C_FOFC = 3, C_FLUID = 4, C_MARKS = 5 };
 
-template <int STAGE, typename FT, bool RATE = false, int MODE = U_PLAIN, bool FACE = false>
+template <int STAGE, typename FT, bool RATE = false, int MODE = U_PLAIN, bool FACE = false,
+          int INTEG = GRMHD_INTEG_SSPRK2>
 __device__ __forceinline__ void update_zone(const Dev& g, const double* __restrict__ Pin,
                                             double* __restrict__ Pout, double* __restrict__ V,
                                             const FT* __restrict__ F1, const FT* __restrict__ F2,
@@ -1463,18 +1464,24 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
     }
   }
 
+  // SSPRK2: U1 = U^n + dt L(P^n), V = (U^n + U1)/2, U^{n+1} = V + dt L(P1)/2;
+  // predictor-corrector: U* = U^n + (dt/2) L(P^n), V = U^n, U^{n+1} = V + dt L(P*);
+  // RK1: the first stage alone, no register.
   double U[NVAR];
   if (STAGE == 1) {
     double U0[NVAR];
     prim_to_flux(p, f, m, g.gam, 0, U0);
+    const double h = INTEG == GRMHD_INTEG_PC ? 0.5 * dt : dt;
 #pragma unroll
     for (int v = 0; v < NVAR; v++) {
-      U[v] = U0[v] + dt * L[v];
-      V[v * nz + c] = 0.5 * (U0[v] + U[v]);
+      U[v] = U0[v] + h * L[v];
+      if (INTEG == GRMHD_INTEG_SSPRK2) V[v * nz + c] = 0.5 * (U0[v] + U[v]);
+      if (INTEG == GRMHD_INTEG_PC) V[v * nz + c] = U0[v];
     }
   } else {
 #pragma unroll
-    for (int v = 0; v < NVAR; v++) U[v] = V[v * nz + c] + 0.5 * (dt * L[v]);
+    for (int v = 0; v < NVAR; v++)
+      U[v] = INTEG == GRMHD_INTEG_PC ? V[v * nz + c] + dt * L[v] : V[v * nz + c] + 0.5 * (dt * L[v]);
   }
   if constexpr (FACE) {  // face-centred CT: the zone's field is the mean of its new faces
     U[B1] = 0.5 * (ph1[c] + ph1[c + si]);
@@ -1507,7 +1514,7 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
 // flux correction runs only when the PROVISIONAL pass marked a zone (a
 // grid-uniform test of the mark count), and then adds that count to the
 // correction's running total.
-template <int STAGE, typename FT, bool RATE, int MODE, bool FACE>
+template <int STAGE, typename FT, bool RATE, int MODE, bool FACE, int INTEG = GRMHD_INTEG_SSPRK2>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8)))
 k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ Pout,
          double* __restrict__ V, const FT* __restrict__ F1, const FT* __restrict__ F2,
@@ -1527,14 +1534,15 @@ k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ 
   if (dt_dev) dt = *dt_dev;
   if (!RATE) {
     if (in)
-      update_zone<STAGE, FT, false, MODE, FACE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt,
-                                                fails, flags, i, j, k, nullptr, mark, ph1, ph2, ph3, ustar);
+      update_zone<STAGE, FT, false, MODE, FACE, INTEG>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn,
+                                                       dt, fails, flags, i, j, k, nullptr, mark, ph1, ph2,
+                                                       ph3, ustar);
     return;
   }
   double r = 0.0, sm = 0.0;
   if (in)
-    update_zone<STAGE, FT, true, MODE, FACE>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt, fails,
-                                             flags, i, j, k, &r, mark, ph1, ph2, ph3, ustar);
+    update_zone<STAGE, FT, true, MODE, FACE, INTEG>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt,
+                                                    fails, flags, i, j, k, &r, mark, ph1, ph2, ph3, ustar);
   block_reduce(r, sm);
   if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
 }
@@ -1880,6 +1888,11 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
   // the implicit recovery runs in a pass of its own, without the correction's marks
   if (p->inverter == GRMHD_INV_IMPLICIT && p->fofc) return false;
   if (p->inverter == GRMHD_INV_KASTAUN && !(p->kastaun_wmax > 1.0)) return false;
+  // the other integrators take the plain Flux-CT step
+  if (p->integrator < GRMHD_INTEG_SSPRK2 || p->integrator > GRMHD_INTEG_RK1) return false;
+  if (p->integrator != GRMHD_INTEG_SSPRK2 &&
+      (p->floors || p->fofc || p->ct != GRMHD_CT_FLUX || p->inverter == GRMHD_INV_IMPLICIT))
+    return false;
   return true;
 }
 
@@ -2082,7 +2095,7 @@ int stage_faces(grmhd_ctx* c, double dt, const double* dt_dev, const unsigned lo
 
 // One stage's update.  With rate (stage 2 of a step) the workgroups also
 // leave the CFL-rate partials of the prims they write in c->pdt.
-template <int STAGE, typename FT, int MODE = U_PLAIN>
+template <int STAGE, typename FT, int MODE = U_PLAIN, int INTEG = GRMHD_INTEG_SSPRK2>
 int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
                  unsigned long long* fails = nullptr, unsigned char* flags = nullptr,
                  const double* dt_dev = nullptr, bool rate = false) {
@@ -2101,13 +2114,18 @@ int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
                   (const double*)c->tabC, (const double*)c->conn, dt, dt_dev, fails ? fails : c->fails, flags,
                   partial, c->mark, p1, p2, p3, c->ustar);
   };
-  if constexpr (STAGE == 2) {
-    if (rate && nb <= (unsigned)MAX_PARTIALS)
-      return ph ? go(k_update<STAGE, FT, true, MODE, true>, c->pdt)
-                : go(k_update<STAGE, FT, true, MODE, false>, c->pdt);
+  if constexpr (INTEG != GRMHD_INTEG_SSPRK2) {  // the plain Flux-CT path only
+    if (rate && nb <= (unsigned)MAX_PARTIALS) return go(k_update<STAGE, FT, true, MODE, false, INTEG>, c->pdt);
+    return go(k_update<STAGE, FT, false, MODE, false, INTEG>, (double*)nullptr);
+  } else {
+    if constexpr (STAGE == 2) {
+      if (rate && nb <= (unsigned)MAX_PARTIALS)
+        return ph ? go(k_update<STAGE, FT, true, MODE, true>, c->pdt)
+                  : go(k_update<STAGE, FT, true, MODE, false>, c->pdt);
+    }
+    return ph ? go(k_update<STAGE, FT, false, MODE, true>, (double*)nullptr)
+              : go(k_update<STAGE, FT, false, MODE, false>, (double*)nullptr);
   }
-  return ph ? go(k_update<STAGE, FT, false, MODE, true>, (double*)nullptr)
-            : go(k_update<STAGE, FT, false, MODE, false>, (double*)nullptr);
 }
 
 // The floors pass after an update pass (same schedule as the update, so the
@@ -2133,6 +2151,12 @@ int stage_floors(grmhd_ctx* c, const double* Pin, double* Pout, bool rate) {
 template <int STAGE, typename R, typename FT>
 int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double* dt_dev, bool rate) {
   int rc;
+  if (c->params.integrator != GRMHD_INTEG_SSPRK2) {  // plain Flux-CT stages (validated at create)
+    if ((rc = stage_fluxes<R, FT>(c, Pin, nullptr, nullptr))) return rc;
+    if (c->params.integrator == GRMHD_INTEG_PC)
+      return stage_update<STAGE, FT, U_PLAIN, GRMHD_INTEG_PC>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate);
+    return stage_update<STAGE, FT, U_PLAIN, GRMHD_INTEG_RK1>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev, rate);
+  }
   const bool floors = c->params.floors != 0;
   const bool urate = rate && !floors;
   const bool faces = c->params.ct != GRMHD_CT_FLUX;
@@ -2194,10 +2218,17 @@ int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   c->rate_ready = false;
   if ((rc = ensure_ghosts(c))) return rc;
   c->ghosts_valid = false;
-  if ((rc = stage<1, R, FT>(c, c->P, c->P1, dt, dt_dev, false))) return rc;
-  if ((rc = fill_ghosts(c, c->P1, c->phi1))) return rc;
-  if ((rc = stage<2, R, FT>(c, c->P1, c->P, dt, dt_dev, true))) return rc;
   const Dev& g = c->dev;
+  if (c->params.integrator == GRMHD_INTEG_RK1) {  // one stage, its result copied back to the state
+    if ((rc = stage<1, R, FT>(c, c->P, c->P1, dt, dt_dev, true))) return rc;
+    if (hipMemcpyAsync(c->P, c->P1, sizeof(double) * NVAR * g.nz, hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+      return GRMHD_E_HIP;
+  } else {
+    if ((rc = stage<1, R, FT>(c, c->P, c->P1, dt, dt_dev, false))) return rc;
+    if ((rc = fill_ghosts(c, c->P1, c->phi1))) return rc;
+    if ((rc = stage<2, R, FT>(c, c->P1, c->P, dt, dt_dev, true))) return rc;
+  }
   const long nb = blocks_for(make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update));
   c->rate_ready = nb <= MAX_PARTIALS;
   c->rate_n = (int)nb;
@@ -2643,7 +2674,8 @@ extern "C" {
 size_t grmhd_vjp_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
   if (!grid_ok(grid, params) || params->floors || params->fofc ||
       (params->recon != GRMHD_RECON_MC && params->recon != GRMHD_RECON_WENO5) ||
-      params->ct != GRMHD_CT_FLUX || params->inverter == GRMHD_INV_IMPLICIT)
+      params->ct != GRMHD_CT_FLUX || params->inverter == GRMHD_INV_IMPLICIT ||
+      params->integrator != GRMHD_INTEG_SSPRK2)
     return 0;
   return vjp_carve(grid, params->recon, nullptr, nullptr);
 }
@@ -2657,7 +2689,8 @@ int grmhd_step_vjp(grmhd_ctx* c, const double* d_prims_in, double dt, const doub
   // correction)
   if (c->params.floors || c->params.fofc ||
       (c->params.recon != GRMHD_RECON_MC && c->params.recon != GRMHD_RECON_WENO5) ||
-      c->params.ct != GRMHD_CT_FLUX || c->params.inverter == GRMHD_INV_IMPLICIT)
+      c->params.ct != GRMHD_CT_FLUX || c->params.inverter == GRMHD_INV_IMPLICIT ||
+      c->params.integrator != GRMHD_INTEG_SSPRK2)
     return GRMHD_E_STATE;
   if (((uintptr_t)d_vjp_ws & 255) != 0) return GRMHD_E_ARG;
   if (vjp_ws_bytes < vjp_carve(&c->grid, c->params.recon, nullptr, nullptr)) return GRMHD_E_NOMEM;
@@ -2834,7 +2867,8 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
   if (!grid_ok(global, params) || params->precision != GRMHD_PREC_FP64) return GRMHD_E_ARG;
   // packs advance the plain step with MC or WENO5
   if (params->floors || params->fofc || (params->recon != GRMHD_RECON_MC && params->recon != GRMHD_RECON_WENO5) ||
-      params->ct != GRMHD_CT_FLUX || params->inverter == GRMHD_INV_IMPLICIT)
+      params->ct != GRMHD_CT_FLUX || params->inverter == GRMHD_INV_IMPLICIT ||
+      params->integrator != GRMHD_INTEG_SSPRK2)
     return GRMHD_E_ARG;
   if (((uintptr_t)d_ws & 255) != 0) return GRMHD_E_ARG;
   for (int b = 0; b < nblocks; b++) {

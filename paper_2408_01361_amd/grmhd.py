@@ -19,6 +19,7 @@ RECON_MC, RECON_WENO5, RECON_DONOR, RECON_WENOZ, RECON_VL, RECON_MP5, RECON_PPM 
 PREC_FP64, PREC_MIXED = 0, 1
 INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
+INTEG_SSPRK2, INTEG_PC, INTEG_RK1 = 0, 1, 2
 BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN = 0, 1, 2, 3
 NG, NVAR = 3, 8
 
@@ -45,7 +46,8 @@ class grmhd_params(C.Structure):
                 ("kastaun_wmax", C.c_double), ("rho_min_geom", C.c_double),
                 ("u_min_geom", C.c_double), ("bsq_over_rho_max", C.c_double),
                 ("bsq_over_u_max", C.c_double), ("u_over_rho_max", C.c_double),
-                ("gamma_max", C.c_double), ("fofc", C.c_int), ("ct", C.c_int)]
+                ("gamma_max", C.c_double), ("fofc", C.c_int), ("ct", C.c_int),
+                ("integrator", C.c_int)]
 
 
 # floor and ceiling defaults (HARM-family values; the paper states none)
@@ -54,7 +56,8 @@ FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0
 
 
 def make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precision, inverter,
-                kastaun_wmax, floors=False, fofc=False, ct=CT_FLUX, **floor_params):
+                kastaun_wmax, floors=False, fofc=False, ct=CT_FLUX, integrator=INTEG_SSPRK2,
+                **floor_params):
     fp = dict(FLOOR_DEFAULTS)
     for k, v in floor_params.items():
         if k not in fp:
@@ -63,7 +66,7 @@ def make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precis
     return grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
                         int(newton_maxit), int(recon), int(precision), int(bool(floors)),
                         int(inverter), float(kastaun_wmax), *(float(fp[k]) for k in FLOOR_DEFAULTS),
-                        int(bool(fofc)), int(ct))
+                        int(bool(fofc)), int(ct), int(integrator))
 
 
 EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_step",
@@ -178,18 +181,18 @@ class Grmhd:
     inverter (INV_1DW, INV_KASTAUN, INV_IMPLICIT), floors (with the keyword
     floor parameters of FLOOR_DEFAULTS), fofc (first-order flux correction),
     ct (CT_FLUX, or face-centred CT_FACE_AVG / CT_FACE_GS, whose face fields
-    load_faces takes).
+    load_faces takes), integrator (INTEG_SSPRK2, INTEG_PC, INTEG_RK1).
     """
 
     def __init__(self, spec, gamma_ad, recon=RECON_WENO5, precision=PREC_FP64, cfl=0.9,
                  weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda",
                  stream=None, strict=False, inverter=INV_1DW, kastaun_wmax=1e3, floors=False,
-                 fofc=False, ct=CT_FLUX, **floor_params):
+                 fofc=False, ct=CT_FLUX, integrator=INTEG_SSPRK2, **floor_params):
         self.spec = spec
         self.grid = make_grid(spec)
         self.metric = grmhd_metric(int(spec.metric), float(spec.a), float(spec.hslope))
         self.params = make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precision,
-                                  inverter, kastaun_wmax, floors, fofc, ct, **floor_params)
+                                  inverter, kastaun_wmax, floors, fofc, ct, integrator, **floor_params)
         self.strict = strict
         L = lib()
         nbytes = L.grmhd_workspace_bytes(C.byref(self.grid), C.byref(self.params))

@@ -110,6 +110,26 @@ def test_reconstruction_choices_are_validated():
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_MC))) > 0
 
 
+def test_integrator_parameters_are_validated():
+    from paper_2408_01361_amd import grmhd
+    from workloads import torus_grid
+    lib = grmhd.lib()
+    g = grmhd.make_grid(torus_grid(32, 32, 32))
+    mk = lambda integ, **kw: grmhd.make_params(13 / 9, 0.9, 1e-26, 1e-14, 30, grmhd.RECON_WENO5,
+                                               grmhd.PREC_FP64, 0, 1e3, integrator=integ, **kw)
+    base = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INTEG_SSPRK2)))
+    for integ in (grmhd.INTEG_PC, grmhd.INTEG_RK1):
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(integ))) == base
+        # the other integrators take the plain Flux-CT step only
+        for kw in (dict(floors=True), dict(fofc=True), dict(ct=grmhd.CT_FACE_GS)):
+            assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(integ, **kw))) == 0
+        assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(integ))) == 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(3))) == 0
+    p = mk(grmhd.INTEG_PC)
+    p.inverter = grmhd.INV_IMPLICIT
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(p)) == 0
+
+
 def test_pack_exchange_map_size():
     from paper_2408_01361_amd import grmhd
     from workloads import torus_grid
