@@ -1115,7 +1115,9 @@ int u_to_p_kastaun(const orc_cfg& c, const Geom& G, const real U[NV], const real
   State s = state(mu);
   real rho = D / s.W;
   real u = rho * s.eps;
-  if (!(rho > 0.0) || !(u > 0.0) || !isfinite((real)u)) return failed();
+  // eps clamped at 0 is the method's own answer for an energy below the
+  // cold state; with floors on it stands, and the energy floor raises u
+  if (!(rho > 0.0) || !(u > 0.0 || (c.floors && u == 0.0)) || !isfinite((real)u)) return failed();
   real pre = s.W * mu * s.x / D;
   real ut[3];
   for (int i = 1; i < 4; i++) {

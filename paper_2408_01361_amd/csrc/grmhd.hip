@@ -968,7 +968,8 @@ __device__ int invert_kastaun(const Dev& g, const PointMetric<double>& m, const 
   St s = state(mu);
   const double rho = D / s.W;
   const double u = rho * s.eps;
-  if (!(rho > 0.0) || !(u > 0.0) || !isfinite(u)) return fail();
+  // eps clamped at 0 stands when floors are on: the energy floor raises u
+  if (!(rho > 0.0) || !(u > 0.0 || (g.floors && u == 0.0)) || !isfinite(u)) return fail();
   const double pre = s.W * mu * s.x / D;
   double ut[3];
 #pragma unroll

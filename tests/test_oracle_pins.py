@@ -784,6 +784,31 @@ def _round_trip_errors(c, rng, prims, x1, x2, guess_of):
     return np.array(errs), fails
 
 
+def test_kastaun_energy_below_the_cold_state():
+    """Lower a magnetised, moving state's energy below that of its cold
+    (u = 0) state: Kastaun et al.'s recovery clamps the specific energy at
+    0 and returns that cold state -- rest mass, momenta and field of U
+    reproduced to roundoff, only the energy slot off.  With floors on this
+    is the recovered state (the energy floor then raises u); without floors
+    it counts as a failure and the guess is kept."""
+    g = GridSpec(4, 4, 4)
+    P = np.array([1e-3, 1e-9, 0.3, 0.1, -0.2, 0.05, 0.02, 0.01])
+    for floors in (True, False):
+        c = oracle.cfg(g, gam=13 / 9, inverter=oracle.INV_KASTAUN, floors=floors)
+        U = np.asarray(oracle.point_flux(c, P, 0.5, 0.5, 0)[0])
+        for dE in (1e-8, 1e-6, 1e-4):
+            U2 = U.copy()
+            U2[1] += dE          # energy slot T^t_t + rho u^t: larger is less energy
+            out, r = oracle.point_u_to_p(c, U2, P, 0.5, 0.5)
+            if not floors:
+                assert r != 0 and np.array_equal(out[:5], P[:5])
+                continue
+            assert r == 0 and out[1] == 0.0
+            Ur = np.asarray(oracle.point_flux(c, out, 0.5, 0.5, 0)[0])
+            keep = [0, 2, 3, 4, 5, 6, 7]
+            assert np.abs(Ur[keep] - U2[keep]).max() < 1e-14 * np.abs(U2).max()
+            assert Ur[1] < U2[1]
+
 @pytest.mark.parametrize("metric", ["flat", "kerr"])
 def test_kastaun_round_trip_without_a_guess(metric):
     """P -> U -> P through the Kastaun et al. recovery on the fuzzed set of
