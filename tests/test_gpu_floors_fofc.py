@@ -161,10 +161,10 @@ def test_long_torus_run_with_kastaun_floors_and_correction():
     CFL steps (t ~ 70 M): every primitive finite, density at or above its
     geometric floor and internal energy at it to the drift-frame
     injection's re-inversion (1e-6), the field's corner divergence at
-    roundoff, the torus body kept.  Zones of the cold atmosphere whose
-    updated energy leaves no positive internal energy fail their inversion
-    and keep their previous state (a few per cent of the zones per step at
-    this resolution; counted, not asserted)."""
+    roundoff, the torus body kept, and no failed inversion: where the
+    updated energy of a cold atmosphere zone leaves no positive internal
+    energy, the recovery's clamped specific energy stands and the energy
+    floor supplies u (1D_W fails in those zones instead)."""
     torch, gr = _setup()
     grid, P, _ = fm_torus(64, 64, 64)
     s = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5, inverter=gr.INV_KASTAUN, floors=True, fofc=True)
@@ -184,6 +184,7 @@ def test_long_torus_run_with_kastaun_floors_and_correction():
     assert (out[1] >= fl["u_min_geom"] * r ** -2.5 * (1 - 1e-6)).all()
     assert out[0].max() > 0.5 * interior(P)[0].max()
     cnt = s.counters()
+    assert cnt["fails"] == 0, cnt
     mx, _ = s.divb()
     scale = np.abs(interior(P[5:8])).max() / min(grid.dx[:2])
     print("t", t, "counters", cnt, "divb max", mx, "scale", scale)
