@@ -422,7 +422,8 @@ def integrator_extra(torch, gr, grid, P, gam, recon, steps):
 
 def floors_fofc_extra(torch, gr, grid, P, gam, recon, steps):
     """What the floors and the first-order flux correction cost: the headline
-    torus step plain, with floors, and with floors plus the correction; and
+    torus step plain, with floors, with floors plus the correction, and with
+    both and the Kastaun recovery (the production settings); and
     the magnetised blast at 1024^2 (flat space), where the correction acts,
     without and with it (failed inversions and marked zones per run)."""
     from workloads import magnetised_blast, RECON_MC
@@ -430,7 +431,8 @@ def floors_fofc_extra(torch, gr, grid, P, gam, recon, steps):
     Pt = torch.from_numpy(P).cuda()
     torus = {}
     for name, kw in (("plain", {}), ("floors", dict(floors=True)),
-                     ("floors_fofc", dict(floors=True, fofc=True))):
+                     ("floors_fofc", dict(floors=True, fofc=True)),
+                     ("kastaun_floors_fofc", dict(floors=True, fofc=True, inverter=gr.INV_KASTAUN))):
         s = gr.Grmhd(grid, gam, recon=recon, **kw)
         s.load(Pt)
         for _ in range(10):          # untimed: clocks settle
