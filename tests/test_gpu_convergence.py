@@ -1,10 +1,10 @@
 """The paper's regression criterion (Readiness and Testing section: linear
 modes and Bondi accretion converge with L1 error slopes between 1.9 and 2.1)
 applied to the HIP path itself, across the selectable schemes: Flux-CT and
-face-centred CT (averaged and upwinded EMFs), MC and WENO5, and the three
-recoveries.  The exact solutions come from the workloads (linear-mode
-eigenvectors from the continuum equations; the Michel solution), not from
-the oracle."""
+face-centred CT (averaged and upwinded EMFs), MC, WENO5, WENO-Z and MP5,
+and the three recoveries.  The exact solutions come from the workloads
+(linear-mode eigenvectors from the continuum equations; the Michel
+solution), not from the oracle."""
 
 import math
 
@@ -58,11 +58,13 @@ CASES = [
     ("fast", RECON_MC, 0, 0),
     ("fast", RECON_WENO5, 1, 0), ("alfven", RECON_WENO5, 2, 0), ("slow", RECON_WENO5, 2, 0),
     ("fast", RECON_WENO5, 0, 1), ("fast", RECON_WENO5, 0, 2),
+    ("fast", 3, 0, 0), ("alfven", 3, 0, 0), ("fast", 5, 0, 0),   # WENO-Z, MP5
 ]
+RECON_NAMES = {RECON_MC: "mc", RECON_WENO5: "weno5", 3: "wenoz", 5: "mp5"}
 
 
 @pytest.mark.parametrize("name,recon,ct,inv", CASES,
-                         ids=[f"{c[0]}-{'weno5' if c[1] else 'mc'}-ct{c[2]}-inv{c[3]}" for c in CASES])
+                         ids=[f"{c[0]}-{RECON_NAMES[c[1]]}-ct{c[2]}-inv{c[3]}" for c in CASES])
 def test_linear_mode_convergence_on_the_gpu(name, recon, ct, inv):
     # MC, and the face-centred schemes (whose upwinded slow mode is still
     # above second order at 32 -> 64), are in the asymptotic range at 64 -> 128
