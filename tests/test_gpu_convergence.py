@@ -24,7 +24,7 @@ def _setup():
     return torch, gr
 
 
-def mode_errors(name, recon, ns, ct=0, inverter=0):
+def mode_errors(name, recon, ns, ct=0, inverter=0, integrator=0):
     torch, gr = _setup()
     errs = []
     for n in ns:
@@ -35,7 +35,7 @@ def mode_errors(name, recon, ns, ct=0, inverter=0):
             g, P, F, exact, info = linear_mode_faces(name, n, ndim=2, amp=1e-6)
         else:
             g, P, exact, info = linear_mode(name, n, ndim=2)
-        s = gr.Grmhd(g, 4 / 3, recon=recon, ct=ct, inverter=inverter)
+        s = gr.Grmhd(g, 4 / 3, recon=recon, ct=ct, inverter=inverter, integrator=integrator)
         s.load(torch.from_numpy(P).cuda())
         if ct:
             s.load_faces(torch.from_numpy(F).cuda())
@@ -72,6 +72,18 @@ def test_linear_mode_convergence_on_the_gpu(name, recon, ct, inv):
     slope = mode_errors(name, recon, ns, ct=ct, inverter=inv)
     print(name, recon, ct, inv, "slopes", slope)
     assert np.all((slope > 1.9) & (slope < 2.1)), slope
+
+
+def test_predictor_corrector_and_rk1_convergence_on_the_gpu():
+    """The fast mode (WENO5) with the predictor-corrector converges at
+    second order (32 -> 64); with RK1, whose time error is first order and
+    dt scales with the zone size, the slope drops to about one."""
+    slope = mode_errors("fast", RECON_WENO5, (32, 64), integrator=1)
+    print("pc slopes", slope)
+    assert np.all((slope > 1.9) & (slope < 2.1)), slope
+    slope = mode_errors("fast", RECON_WENO5, (32, 64), integrator=2)
+    print("rk1 slopes", slope)
+    assert np.all((slope > 0.8) & (slope < 1.3)), slope
 
 
 @pytest.mark.parametrize("recon", [RECON_MC, RECON_WENO5])
