@@ -3,7 +3,10 @@
 Every block of a pack must match the same block advanced alone through the
 single-block path bit for bit, and the pack as a whole the FP64 oracle
 (frozen ghosts, block by block) to the parity bar; tile shapes change nothing
-in the results.
+in the results.  With the ghost exchange on, blocks that tile a grid must
+advance as that grid: against the single GPU grid and the oracle's global
+run to the parity bar (torus), bit for bit where the block spacings equal
+the grid's exactly (flat periodic fast mode).
 """
 
 import numpy as np
