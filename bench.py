@@ -98,12 +98,28 @@ def oracle_baseline(grid, P, gam, recon, budget_s):
     t1 = time.perf_counter() - t0
     out["one_thread_value"] = nz / t1
     out["one_thread_sample"] = f"1 full SSPRK2 step on 1 thread, {t1:.1f} s wall"
+    out.update(host_cpu())
+    return out
+
+
+def host_cpu():
+    """The host CPU as lscpu reports it (model name, family/model/stepping,
+    sockets, cores, threads), and the CPUs this process may run on."""
+    import subprocess
+    info = {}
     try:
-        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")]
-        out["cpu_model"] = model[0] if model else None
-        out["host_cpus"] = len(model)
-    except OSError:
-        out["cpu_model"] = None
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in txt.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    keys = ("Model name", "Vendor ID", "CPU family", "Model", "Stepping", "Socket(s)",
+            "Core(s) per socket", "Thread(s) per core", "CPU(s)", "CPU max MHz")
+    out = {"cpu_model": info.get("Model name"),
+           "lscpu": {k: info[k] for k in keys if k in info},
+           "host_cpus": len(os.sched_getaffinity(0))}
     return out
 
 
@@ -199,7 +215,7 @@ def extras(torch, gr, np, args):
         "workload": f"same torus at {n}^3, WENO5, 50 RK2 steps at the initial CFL dt",
         "zone_cycles_per_s": n ** 3 * 50 / t32, "fp64_zone_cycles_per_s": n ** 3 * 50 / t64,
         "speedup_vs_fp64": t64 / t32, "rho_rel_l1_vs_fp64_after_steps": rel,
-        "divb_max_mixed": divb32[0], "inversion_failures": f32}
+        "divb_max_mixed": divb32[0], "divb_mean_mixed": divb32[1], "inversion_failures": f32}
     del Pt, res, e64, e32
     # batched uneven packs of the 128^3 torus
     g, blocks, _ = torus_pack(nblocks=320, n_global=128, sizes=(16, 32, 64), probs=(0.6, 0.3, 0.1),

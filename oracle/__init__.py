@@ -2,7 +2,11 @@
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg import
 this package.  `build()` compiles harm_oracle.cpp with g++ (OpenMP, no
-fast-math, no FMA) into liboracle.so next to it.
+fast-math, no FMA) into liboracle.so next to it.  Two more builds of the
+same source serve as measuring instruments: the counting build (every
+floating-point operation tallied) and the FMA build (g++ free to contract
+a*b + c into fused multiply-adds), whose distance from the plain build is
+the rounding noise floor of a result.
 """
 
 import ctypes as C
@@ -15,12 +19,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "harm_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 LIB_COUNT = os.path.join(HERE, "liboracle_count.so")
+LIB_FMA = os.path.join(HERE, "liboracle_fma.so")
 
 
-def build(counting=False):
-    out = LIB_COUNT if counting else LIB
+def build(counting=False, fma=False):
+    out = LIB_COUNT if counting else (LIB_FMA if fma else LIB)
     cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math",
-           "-ffp-contract=off", "-o", out, SRC]
+           "-ffp-contract=fast" if fma else "-ffp-contract=off", "-o", out, SRC]
+    if fma:
+        cmd[1:1] = ["-mfma"]
     if counting:
         cmd[1:1] = ["-DORACLE_COUNTING"]
     else:
@@ -62,6 +69,7 @@ FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0
 
 _lib = None
 _lib_count = None
+_lib_fma = None
 
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int)
@@ -112,8 +120,14 @@ def _declare(lib):
     return lib
 
 
-def lib(counting=False):
-    global _lib, _lib_count
+def lib(counting=False, fma=False):
+    global _lib, _lib_count, _lib_fma
+    if fma:
+        if _lib_fma is None:
+            if not os.path.exists(LIB_FMA) or os.path.getmtime(LIB_FMA) < os.path.getmtime(SRC):
+                build(fma=True)
+            _lib_fma = _declare(C.CDLL(LIB_FMA))
+        return _lib_fma
     if counting:
         if _lib_count is None:
             if not os.path.exists(LIB_COUNT) or os.path.getmtime(LIB_COUNT) < os.path.getmtime(SRC):
@@ -161,19 +175,20 @@ def _ptr(a):
     return a.ctypes.data_as(_D)
 
 
-def run(c, prims, dt, nsteps=1, counting=False, flags=False):
-    """Advance a copy of prims; returns (prims, fails, dts[, per-zone flags])."""
+def run(c, prims, dt, nsteps=1, counting=False, flags=False, fma=False):
+    """Advance a copy of prims; returns (prims, fails, dts[, per-zone flags]).
+    fma: with the FMA build (the rounding noise floor)."""
     P = np.ascontiguousarray(prims, dtype=np.float64).copy()
     dts = np.zeros(max(nsteps, 1))
     fl = np.zeros(P.shape[1:], dtype=np.int32) if flags else None
-    fails = lib(counting).orc_run(C.byref(c), _ptr(P), float(dt), int(nsteps), _ptr(dts),
-                                  fl.ctypes.data_as(_I) if flags else None)
+    fails = lib(counting, fma).orc_run(C.byref(c), _ptr(P), float(dt), int(nsteps), _ptr(dts),
+                                       fl.ctypes.data_as(_I) if flags else None)
     if flags:
         return P, int(fails), dts, fl
     return P, int(fails), dts
 
 
-def run_face(c, prims, faces, dt, nsteps=1, flags=False):
+def run_face(c, prims, faces, dt, nsteps=1, flags=False, fma=False):
     """Face-centred CT: advance copies of prims and face fields
     ([3][padded], sqrt(-g) B^d on lower d-faces); returns (prims, faces,
     fails, dts[, flags])."""
@@ -182,7 +197,7 @@ def run_face(c, prims, faces, dt, nsteps=1, flags=False):
     assert Fc.shape == (3,) + P.shape[1:]
     dts = np.zeros(max(nsteps, 1))
     fl = np.zeros(P.shape[1:], dtype=np.int32) if flags else None
-    fails = lib().orc_run_face(C.byref(c), _ptr(P), _ptr(Fc), float(dt), int(nsteps), _ptr(dts),
+    fails = lib(fma=fma).orc_run_face(C.byref(c), _ptr(P), _ptr(Fc), float(dt), int(nsteps), _ptr(dts),
                                fl.ctypes.data_as(_I) if flags else None)
     if flags:
         return P, Fc, int(fails), dts, fl

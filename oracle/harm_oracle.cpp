@@ -609,7 +609,7 @@ void compute_fluxes(const Grid& g, const std::vector<real>& P, std::vector<real>
   for (int d = 1; d <= 3; d++) {
     int lo[3] = {-1, -1, -1}, hi[3] = {n1, n2, n3};  // inclusive
     lo[d - 1] = 0;
-#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads)
     for (int k = lo[2]; k <= hi[2]; k++)
       for (int j = lo[1]; j <= hi[1]; j++)
         for (int i = lo[0]; i <= hi[0]; i++) {
@@ -634,7 +634,7 @@ void flux_ct(const Grid& g, std::vector<real> F[3]) {
   std::vector<real>& F1 = F[0];
   std::vector<real>& F2 = F[1];
   std::vector<real>& F3 = F[2];
-#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads)
   for (int k = 0; k <= n3; k++)
     for (int j = 0; j <= n2; j++)
       for (int i = 0; i <= n1; i++) {
@@ -650,7 +650,7 @@ void flux_ct(const Grid& g, std::vector<real> F[3]) {
                                Vc(F3, g, B2, i, j, k) - Vc(F3, g, B2, i, j - 1, k));
       }
   auto E = [&](std::vector<real>& e, int i, int j, int k) -> real { return e[g.id(i, j, k)]; };
-#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads)
   for (int k = 0; k <= n3; k++)
     for (int j = 0; j <= n2; j++)
       for (int i = 0; i <= n1; i++) {
@@ -759,7 +759,7 @@ void edge_emfs(const Grid& g, const std::vector<real>& P, const std::vector<real
   if (scheme == CT_FACE_GS) {
     for (int c = 0; c < 3; c++) ec[c].assign(g.nz, 0.0);
     cs.assign(g.nz, 0.0);
-#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads)
     for (int k = -1; k <= n3; k++)
       for (int j = -1; j <= n2; j++)
         for (int i = -1; i <= n1; i++) {
@@ -785,7 +785,7 @@ void edge_emfs(const Grid& g, const std::vector<real>& P, const std::vector<real
     if (fabs(flux) <= 1e-10 * scale) return 0.5 * (lower + upper);
     return flux > 0.0 ? lower : upper;
   };
-#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads)
   for (int k = 0; k <= n3; k++)
     for (int j = 0; j <= n2; j++)
       for (int i = 0; i <= n1; i++) {
@@ -832,7 +832,7 @@ void face_update(const Grid& g, const std::vector<real> E[3], const std::vector<
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
   auto e = [&](int c, int i, int j, int k) { return E[c][g.id(i, j, k)]; };
   for (int d = 0; d < 3; d++) out[d] = base[d];
-#pragma omp parallel for schedule(static) num_threads(g.c.nthreads)
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads)
   for (int k = 0; k <= n3; k++)
     for (int j = 0; j <= n2; j++)
       for (int i = 0; i <= n1; i++) {
@@ -1421,7 +1421,7 @@ void update_pass(const Grid& g, const std::vector<real>& Pin, const std::vector<
                  const std::vector<real>* phi_new = nullptr) {
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
   long fails = 0, hits = 0, fluid = 0;
-#pragma omp parallel for schedule(static) num_threads(g.c.nthreads) reduction(+ : fails, hits, fluid)
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads) reduction(+ : fails, hits, fluid)
   for (int k = 0; k < n3; k++)
     for (int j = 0; j < n2; j++)
       for (int i = 0; i < n1; i++) {
@@ -1593,10 +1593,12 @@ long step(const Grid& g, std::vector<real>& P, real dt, int* flags, std::vector<
 }
 
 // CFL time step: cfl / max over interior zones of sum_d max(|c+|, |c-|)/dx_d,
-// over the directions that have more than one zone.
+// over the directions that have more than one zone.  A zone whose rate is
+// not finite leaves the minimum over zones undefined: the result is NaN.
 real estimate_dt(const Grid& g, std::vector<real>& P) {
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
   real smax = 0.0;
+  bool bad = false;
   for (int k = 0; k < n3; k++)
     for (int j = 0; j < n2; j++)
       for (int i = 0; i < n1; i++) {
@@ -1613,8 +1615,10 @@ real estimate_dt(const Grid& g, std::vector<real>& P) {
           real cmx = fabs(cp) > fabs(cm) ? fabs(cp) : fabs(cm);
           s += cmx / g.dx[d - 1];
         }
+        if (!isfinite(s)) bad = true;
         if (s > smax) smax = s;
       }
+  if (bad) return real(NAN);
   return g.c.cfl / smax;
 }
 

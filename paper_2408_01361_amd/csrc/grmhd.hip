@@ -123,13 +123,19 @@ inline Sched make_sched(const Box& b, int kg) {
 }
 inline unsigned blocks_for(const Sched& s) { return (unsigned)((long)s.nchunk * s.kgroups * s.kg); }
 
+// Logical workgroup index of dispatched workgroup b of nb: workgroups go to
+// the 8 XCDs round-robin, so this gives each XCD one contiguous range.
+__device__ __forceinline__ unsigned xcd_order(unsigned b, unsigned nb) {
+  const unsigned x = b & 7u, slot = b >> 3;
+  const unsigned q = nb >> 3, r = nb & 7u;
+  return x * q + (x < r ? x : r) + slot;
+}
+
 // bid / nb: this workgroup's index and the workgroup count of the launch (or
 // of its part that covers this box, when the part starts at a multiple of 8).
 __device__ __forceinline__ bool sched_index(const Sched& s, unsigned bid, unsigned nb, int& i, int& j,
                                             int& k) {
-  const unsigned x = bid & 7u, slot = bid >> 3;
-  const unsigned q = nb >> 3, r = nb & 7u;
-  const unsigned w = x * q + (x < r ? x : r) + slot;
+  const unsigned w = xcd_order(bid, nb);
   const int kin = (int)(w % (unsigned)s.kg);
   const unsigned rest = w / (unsigned)s.kg;
   const int chunk = (int)(rest % (unsigned)s.nchunk);
@@ -333,32 +339,20 @@ template <int D, typename R, typename FT>
 __device__ __forceinline__ void face_llf(const Dev& g, const R qL[NVAR], const R qR[NVAR],
                                          const double* __restrict__ tab, long q2, FT* __restrict__ F,
                                          long c) {
-  PointMetric<R> m;
-  load_metric<R>(tab, g.plane, q2, m);
+  FaceMetric<R> m;
+  load_face_metric<R>(tab, g.plane, q2, m);
   const R gam = (R)g.gam;
   R FL[NVAR], UL[NVAR], cpl, cml;
-  {
-    Fluid<R> f;
-    fluid_state(qL, m, f);
-    prim_to_flux(qL, f, m, gam, D, FL);
-    prim_to_flux(qL, f, m, gam, 0, UL);
-    char_speeds(qL, f, m, gam, D, cpl, cml);
-  }
+  face_side<D, R>(qL, m, gam, FL, UL, cpl, cml);
   R FR[NVAR], UR[NVAR], cpr, cmr;
-  {
-    Fluid<R> f;
-    fluid_state(qR, m, f);
-    prim_to_flux(qR, f, m, gam, D, FR);
-    prim_to_flux(qR, f, m, gam, 0, UR);
-    char_speeds(qR, f, m, gam, D, cpr, cmr);
-  }
+  face_side<D, R>(qR, m, gam, FR, UR, cpr, cmr);
   R cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
   cmax = fmax(cmax, (R)0);
   // the normal field component's flux is not stored: Flux-CT replaces it by
   // zero and nothing reads it
 #pragma unroll
   for (int v = 0; v < NVAR; v++)
-    if (v != B1 + D - 1) F[v * g.nz + c] = (FT)llf(FL[v], FR[v], UL[v], UR[v], cmax);
+    if (v != B1 + D - 1) F[v * g.nz + c] = (FT)fma((R)-0.5 * cmax, UR[v] - UL[v], (R)0.5 * (FL[v] + FR[v]));
 }
 
 template <int D>
@@ -393,12 +387,13 @@ __device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict
 }
 
 #ifndef FLUX_WAVES
-#define FLUX_WAVES 4
+#define FLUX_WAVES 3
 #endif
 
 // All three face directions in one launch: workgroups [0, nb1) take x1
-// faces, [nb1, nb1 + nb2) x2 faces, the rest x3 faces (nb1 and nb2 are
-// multiples of 8, so each part keeps the XCD-aware order of its schedule).
+// faces (for MC and WENO5 the shared-edge sweep above), [nb1, nb1 + nb2) x2
+// faces, the rest x3 faces (nb1 and nb2 are multiples of 8, so each part
+// keeps the XCD-aware order of its schedule).
 template <int RECON, typename R, typename FT, bool FACE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FACE ? 3 : FLUX_WAVES, 8)))
 k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsigned nb3,
@@ -409,7 +404,9 @@ k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsi
   const unsigned b = blockIdx.x;
   int i, j, k;
   if (b < nb1) {
-    if (sched_index(b1, b, nb1, i, j, k))
+    if (RECON == GRMHD_RECON_MC || RECON == GRMHD_RECON_WENO5)
+      sweep_x1<RECON, R, FT, FACE>(g, xcd_order(b, nb1), P, tabF1, F1, ph1);
+    else if (sched_index(b1, b, nb1, i, j, k))
       flux_face<1, RECON, R, FT>(g, P, tabF1, F1, i, j, k, FACE ? ph1 : nullptr);
   } else if (b < nb1 + nb2) {
     if (sched_index(b2, b - nb1, nb2, i, j, k))
@@ -418,6 +415,100 @@ k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsi
     if (sched_index(b3, b - nb1 - nb2, nb3, i, j, k))
       flux_face<3, RECON, R, FT>(g, P, tabC, F3, i, j, k, FACE ? ph3 : nullptr);
   }
+}
+
+// ------------------------------------------- x1 faces with shared edges --
+//
+// MC and WENO5 give both edge values of a zone from one slope (MC) or one
+// set of smoothness indicators and weight products (WENO5): the indicators
+// of a stencil are symmetric under reversing it, so the left edge, the
+// reversed-stencil evaluation, reuses them bit for bit.  For the x1 faces of
+// these two schemes every lane reconstructs one zone of the box i in
+// [-1, n1], j in [-1, n2], k in [-1, n3] (linearised x1-fastest); each
+// wavefront starts one zone before the last zone of the previous one, and a
+// face takes its left state, the right edge of the zone below it, from the
+// lane below (a cross-lane shift).  Lane 0 and the zones i = -1 give no
+// face.  The face values are those of the per-face evaluation bit for bit.
+
+// Both edges of the zone c of stencil (a, b, c, d, e) along the axis.
+template <int RECON>
+__device__ __forceinline__ void edge_pair(double a, double b, double c, double d, double e, double eps,
+                                          double& left, double& right) {
+  if (RECON == GRMHD_RECON_MC) {
+    (void)a;
+    (void)e;
+    (void)eps;
+    left = mc_right(b, c, d);   // the per-face forms, rounded alike
+    right = mc_left(b, c, d);
+  } else {
+    weno5_pair(a, b, c, d, e, eps, left, right);
+  }
+}
+template <int RECON>
+__device__ __forceinline__ void edge_pair(float a, float b, float c, float d, float e, float eps,
+                                          float& left, float& right) {
+  if (RECON == GRMHD_RECON_MC) {
+    (void)a;
+    (void)e;
+    (void)eps;
+    left = mc_right(b, c, d);
+    right = mc_left(b, c, d);
+  } else {
+    weno5_pair(a, b, c, d, e, eps, left, right);
+  }
+}
+
+// Both edges of every prim of the zone at padded index c along x1.
+template <int RECON, typename R>
+__device__ __forceinline__ void zone_edges_x1(const double* __restrict__ P, long nz, long c, R eps,
+                                              R left[NVAR], R right[NVAR]) {
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    const double* q = P + v * nz + c;
+    const R m1 = (R)q[-1], p0 = (R)q[0], p1 = (R)q[1];
+    const R m2 = RECON == GRMHD_RECON_MC ? p0 : (R)q[-2];
+    const R p2 = RECON == GRMHD_RECON_MC ? p0 : (R)q[2];
+    edge_pair<RECON>(m2, m1, p0, p1, p2, eps, left[v], right[v]);
+  }
+}
+
+// Workgroups of the shared-edge x1 part for a box of n1z zones (4 wavefronts
+// of 63 new zones each), rounded up to a multiple of 8.
+inline unsigned x1_sweep_blocks(long n1z) {
+  const long waves = (n1z + 62) / 63;
+  return (unsigned)(((waves + 3) / 4 + 7) / 8 * 8);
+}
+
+// lb: this workgroup's place in the part (XCD-ordered).
+template <int RECON, typename R, typename FT, bool FACE>
+__device__ __forceinline__ void sweep_x1(const Dev& g, unsigned lb, const double* __restrict__ P,
+                                         const double* __restrict__ tabF1, FT* __restrict__ F1,
+                                         const double* __restrict__ ph1) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int wave = (int)(lb * (BLOCK / 64) + (threadIdx.x >> 6));
+  const unsigned m1 = (unsigned)g.n1 + 2u, m12 = m1 * ((unsigned)g.n2 + 2u);
+  const int t = wave * 63 + lane - 1;
+  const bool valid = t >= 0 && t < (int)(m12 * ((unsigned)g.n3 + 2u));
+  const unsigned tt = valid ? (unsigned)t : 0u;
+  const unsigned kk = tt / m12, r = tt - kk * m12;
+  const unsigned jj = r / m1;
+  const int i = (int)(r - jj * m1) - 1, j = (int)jj - 1, k = (int)kk - 1;
+  const long c = zid(g, i, j, k);
+  R left[NVAR], right[NVAR];
+  zone_edges_x1<RECON, R>(P, g.nz, c, (R)g.weno_eps, left, right);
+  // left state of this zone's lower face: the right edge of the zone below,
+  // held by the lane below (every lane takes part in the shift)
+  R qL[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) qL[v] = __shfl_up(right[v], 1);
+  if (!valid || lane == 0 || i < 0) return;
+  const long q2 = pid(g, i, j);
+  if (FACE) {
+    const R bn = (R)(ph1[c] / tabF1[G_DET * g.plane + q2]);
+    qL[B1] = bn;
+    left[B1] = bn;
+  }
+  face_llf<1, R, FT>(g, qL, left, tabF1, q2, F1, c);
 }
 
 // Flux-CT edge EMFs at the lower (x1, x2, x3) corner of zone (i, j, k):
@@ -1013,7 +1104,17 @@ __device__ __forceinline__ void implicit_residual(const Dev& g, const PointMetri
   for (int k = 0; k < 5; k++) R[k] = (U[k] - Us[k]) / scale;
 }
 
-__device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], double y[5]) {
+// A 5 x 5 matrix of one thread held in LDS: element (i, j) at
+// base[(5 i + j) BLOCK], base = the workgroup's array + threadIdx.x, so the
+// lanes of a wavefront touch consecutive words.  The Newton system lives
+// here rather than in registers, which keeps the solver's register budget
+// far from the per-wave limit.
+struct LdsMat {
+  double* base;
+  __device__ __forceinline__ double& operator()(int i, int j) const { return base[(i * 5 + j) * BLOCK]; }
+};
+
+__device__ __forceinline__ bool qr_pivot_solve(const LdsMat& A, double b[5], double y[5]) {
 #pragma clang fp contract(off)
   int perm[5] = {0, 1, 2, 3, 4};
   double cn[5];
@@ -1021,7 +1122,7 @@ __device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], doub
   for (int j = 0; j < 5; j++) {
     cn[j] = 0.0;
 #pragma unroll
-    for (int i = 0; i < 5; i++) cn[j] += A[i][j] * A[i][j];
+    for (int i = 0; i < 5; i++) cn[j] += A(i, j) * A(i, j);
   }
 #pragma unroll
   for (int k = 0; k < 5; k++) {
@@ -1038,9 +1139,9 @@ __device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], doub
       if (j == best) {
 #pragma unroll
         for (int i = 0; i < 5; i++) {
-          const double t = A[i][k];
-          A[i][k] = A[i][j];
-          A[i][j] = t;
+          const double t = A(i, k);
+          A(i, k) = A(i, j);
+          A(i, j) = t;
         }
         const double t = cn[k];
         cn[k] = cn[j];
@@ -1051,13 +1152,13 @@ __device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], doub
       }
     double nrm = 0.0;
 #pragma unroll
-    for (int i = k; i < 5; i++) nrm += A[i][k] * A[i][k];
+    for (int i = k; i < 5; i++) nrm += A(i, k) * A(i, k);
     nrm = sqrt(nrm);
     if (!(nrm > 0.0) || !isfinite(nrm)) return false;
-    const double alpha = A[k][k] > 0.0 ? -nrm : nrm;
+    const double alpha = A(k, k) > 0.0 ? -nrm : nrm;
     double v[5];
 #pragma unroll
-    for (int i = 0; i < 5; i++) v[i] = i < k ? 0.0 : A[i][k];
+    for (int i = 0; i < 5; i++) v[i] = i < k ? 0.0 : A(i, k);
     v[k] = v[k] - alpha;
     double vv = 0.0;
 #pragma unroll
@@ -1067,10 +1168,10 @@ __device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], doub
     for (int j = k; j < 5; j++) {
       double d = 0.0;
 #pragma unroll
-      for (int i = k; i < 5; i++) d += v[i] * A[i][j];
+      for (int i = k; i < 5; i++) d += v[i] * A(i, j);
       const double f = 2.0 * d / vv;
 #pragma unroll
-      for (int i = k; i < 5; i++) A[i][j] = A[i][j] - f * v[i];
+      for (int i = k; i < 5; i++) A(i, j) = A(i, j) - f * v[i];
     }
     double d = 0.0;
 #pragma unroll
@@ -1082,7 +1183,7 @@ __device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], doub
     for (int j = k + 1; j < 5; j++) {
       cn[j] = 0.0;
 #pragma unroll
-      for (int i = k + 1; i < 5; i++) cn[j] += A[i][j] * A[i][j];
+      for (int i = k + 1; i < 5; i++) cn[j] += A(i, j) * A(i, j);
     }
   }
   double z[5];
@@ -1090,9 +1191,9 @@ __device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], doub
   for (int i = 4; i >= 0; i--) {
     double t = b[i];
 #pragma unroll
-    for (int j = i + 1; j < 5; j++) t = t - A[i][j] * z[j];
-    if (!(fabs(A[i][i]) > 0.0)) return false;
-    z[i] = t / A[i][i];
+    for (int j = i + 1; j < 5; j++) t = t - A(i, j) * z[j];
+    if (!(fabs(A(i, i)) > 0.0)) return false;
+    z[i] = t / A(i, i);
   }
 #pragma unroll
   for (int mm = 0; mm < 5; mm++) {
@@ -1108,8 +1209,9 @@ __device__ __forceinline__ bool qr_pivot_solve(double A[5][5], double b[5], doub
   return true;
 }
 
+// jac: this thread's 25 LDS words for the Jacobian (LdsMat base).
 __device__ __forceinline__ int invert_implicit(const Dev& g, const PointMetric<double>& m, const double U[NVAR],
-                                               const double guess[NVAR], double P[NVAR]) {
+                                               const double guess[NVAR], double P[NVAR], double* jac) {
 #pragma clang fp contract(off)
   const double gd = m.gdet;
   P[B1] = U[B1] / gd;
@@ -1138,21 +1240,30 @@ __device__ __forceinline__ int invert_implicit(const Dev& g, const PointMetric<d
   for (int k = 0; k < 5; k++) r2 += R[k] * R[k];
   bool conv = false;
   const double tol = g.tol > 1e-12 ? g.tol : 1e-12;
+  const LdsMat J{jac};
   for (int it = 0; it < g.maxit && !conv; it++) {
-    double J[5][5];
-#pragma unroll
+    // secant Jacobian, one column per pass (components picked by compare,
+    // so nothing in registers is indexed by the loop counter)
+#pragma unroll 1
     for (int k = 0; k < 5; k++) {
-      const double ax = fabs(x[k]);
-      const double h = 1e-7 * (ax > fl[k] ? ax : fl[k]);
+      double xk = x[0], flk = fl[0];
+#pragma unroll
+      for (int mm = 1; mm < 5; mm++)
+        if (mm == k) {
+          xk = x[mm];
+          flk = fl[mm];
+        }
+      const double ax = fabs(xk);
+      const double h = 1e-7 * (ax > flk ? ax : flk);
+      const double xkh = xk + h;
       double xp[5];
 #pragma unroll
-      for (int mm = 0; mm < 5; mm++) xp[mm] = x[mm];
-      xp[k] = x[k] + h;
+      for (int mm = 0; mm < 5; mm++) xp[mm] = mm == k ? xkh : x[mm];
       double Rp[5];
       implicit_residual(g, m, xp, B, U, scale, Rp);
-      const double hh = xp[k] - x[k];
+      const double hh = xkh - xk;
 #pragma unroll
-      for (int mm = 0; mm < 5; mm++) J[mm][k] = (Rp[mm] - R[mm]) / hh;
+      for (int mm = 0; mm < 5; mm++) J(mm, k) = (Rp[mm] - R[mm]) / hh;
     }
     double rhs[5], dx[5];
 #pragma unroll
@@ -1344,7 +1455,9 @@ __device__ void block_reduce(double& mx, double& sm) {
 }
 
 // Signal-rate bound of one zone for the CFL step: the sum over axes with
-// more than one zone of max(|c+|, |c-|)/dx_d at the zone centre.
+// more than one zone of max(|c+|, |c-|)/dx_d at the zone centre.  A zone
+// whose rate is not finite (a NaN state) reports +inf, so the max-reductions
+// (fmax drops NaN operands) carry it and the step size comes out unusable.
 __device__ __forceinline__ double zone_rate(const Dev& g, const double p[NVAR],
                                             const PointMetric<double>& m) {
   Fluid<double> f;
@@ -1362,7 +1475,7 @@ __device__ __forceinline__ double zone_rate(const Dev& g, const double p[NVAR],
     char_speeds(p, f, m, g.gam, 3, cp, cm);
     z += fmax(fabs(cp), fabs(cm)) / g.dx3;
   }
-  return z;
+  return isfinite(z) ? z : (double)INFINITY;
 }
 
 // ----------------------------------------------------------------- update --
@@ -1613,14 +1726,14 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8
 // are the U* the update stored, from the stage input as the guess (the
 // update's inversion, for the implicit recovery).  Failures counted and
 // flagged as the update counts them; with RATE the CFL-rate partials of the
-// new prims, over the update's schedule.  Its own register budget (the
-// 5 x 5 Newton system lives in registers: 270-280 VGPRs, one wave per
-// SIMD, no scratch).
+// new prims, over the update's schedule.  The 5 x 5 Newton system of each
+// thread lives in LDS (25 doubles per thread, 51 KB per workgroup).
 template <bool RATE>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 8)))
+__global__ void __launch_bounds__(BLOCK)
 k_implicit(Dev g, Sched box, const double* __restrict__ Pin, const double* __restrict__ ustar,
            double* __restrict__ Pout, const double* __restrict__ tabC, unsigned long long* fails,
            unsigned char* __restrict__ flags, double* __restrict__ rate_partial) {
+  __shared__ double jac[25 * BLOCK];
   int i, j, k;
   const bool in = sched_index(box, blockIdx.x, gridDim.x, i, j, k);
   double r = 0.0;
@@ -1634,7 +1747,7 @@ k_implicit(Dev g, Sched box, const double* __restrict__ Pin, const double* __res
     }
     PointMetric<double> m;
     load_metric<double>(tabC, g.plane, pid(g, i, j), m);
-    const int bad = invert_implicit(g, m, U, p, out);
+    const int bad = invert_implicit(g, m, U, p, out, jac + threadIdx.x);
 #pragma unroll
     for (int v = 0; v < NVAR; v++) Pout[v * nz + c] = out[v];
     if (flags) flags[c] = (unsigned char)bad;
@@ -1795,7 +1908,9 @@ __global__ void __launch_bounds__(BLOCK) k_cons_to_prims(Dev g, Box box, const d
   }
   PointMetric<double> m;
   load_metric<double>(tabC, g.plane, pid(g, i, j), m);
-  int bad = g.inverter == GRMHD_INV_IMPLICIT ? invert_implicit(g, m, u, gs, p) : invert(g, m, u, gs, p);
+  __shared__ double jac[25 * BLOCK];
+  int bad = g.inverter == GRMHD_INV_IMPLICIT ? invert_implicit(g, m, u, gs, p, jac + threadIdx.x)
+                                             : invert(g, m, u, gs, p);
 #pragma unroll
   for (int v = 0; v < NVAR; v++) P[v * g.nz + c] = p[v];
   if (flags) flags[c] = bad;
@@ -1858,7 +1973,8 @@ struct Carve {
 bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
   if (!g || !p) return false;
   if (g->ng != NG || g->n1 < 1 || g->n2 < 1 || g->n3 < 1) return false;
-  if ((long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * (g->n3 + 2 * NG) * NVAR > (1L << 40)) return false;
+  // padded zone indices (and the flux kernels' zone counters) fit in 31 bits
+  if ((long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * (g->n3 + 2 * NG) > (1L << 31) - 4096) return false;
   for (int a = 0; a < 6; a++)
     if (g->bc[a] < GRMHD_BC_PERIODIC || g->bc[a] > GRMHD_BC_FROZEN) return false;
   int n[3] = {g->n1, g->n2, g->n3};
@@ -2045,7 +2161,10 @@ int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullp
   Sched b1 = make_sched(make_box(0, g.n1, -1, g.n2, -1, g.n3), c->kg_flux);
   Sched b2 = make_sched(make_box(-1, g.n1, 0, g.n2, -1, g.n3), c->kg_flux);
   Sched b3 = make_sched(make_box(-1, g.n1, -1, g.n2, 0, g.n3), c->kg_flux);
-  const unsigned n1 = round8(blocks_for(b1)), n2 = round8(blocks_for(b2)), n3 = blocks_for(b3);
+  const bool shared = c->params.recon == GRMHD_RECON_MC || c->params.recon == GRMHD_RECON_WENO5;
+  const unsigned n1 = shared ? x1_sweep_blocks((long)(g.n1 + 2) * (g.n2 + 2) * (g.n3 + 2))
+                             : round8(blocks_for(b1));
+  const unsigned n2 = round8(blocks_for(b2)), n3 = blocks_for(b3);
   const double* Pc = P;
   const double* p1 = ph ? ph[0] : nullptr;
   const double* p2 = ph ? ph[1] : nullptr;

@@ -124,24 +124,34 @@ using fdual::llf;
 // The smoothness indicator of each three-zone stencil is formed by an
 // expression that is symmetric under reversing the stencil -- (x + z) - 2y,
 // fma(-4, y, fma(3, centre, outer)), y - z squared -- so a zone's left-edge
-// value, weno5(e, d, c, b, a), could reuse its right edge's indicators and
-// weight products bit for bit.  Arranged for few
-// operations: every indicator is scaled by 12 (12 beta_k = 13 t_k^2 + 3 u_k^2,
-// with 12 eps), which leaves the weights unchanged; the factors 1/10 of d and
-// 1/6 of the candidate polynomials cancel or move into the single division
-// that normalises the weights over a common denominator.
+// value, weno5(e, d, c, b, a), reuses its right edge's indicators and
+// weight products bit for bit (weno5_pair).  Arranged for few operations:
+// every indicator is scaled by 12 (12 beta_k = 13 t_k^2 + 3 u_k^2, with
+// 12 eps), which leaves the weights unchanged; the factors 1/10 of d and 1/6
+// of the candidate polynomials cancel or move into the single quotient that
+// normalises the weights over a common denominator.
 //
-// FP64: contraction into fused multiply-adds allowed (no flat-space test
-// depends on WENO5 rounding).
-#pragma clang fp contract(fast)
+// FP64: only the fused multiply-adds written out (contraction off), so an
+// evaluation rounds the same way in whatever code it is inlined; the
+// normalising quotient comes from the hardware reciprocal refined by Newton
+// steps (within about an ulp of the correctly rounded quotient; the weights'
+// denominator is a sum of positive normal numbers for weno_eps >= 1e-36).
+#pragma clang fp contract(off)
 namespace wd {
 typedef double R;
+__device__ __forceinline__ R qdiv(R n, R d) {
+  R r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, (R)1), r, r);
+  r = fma(fma(-d, r, (R)1), r, r);
+  const R q = n * r;
+  return fma(fma(-d, q, n), r, q);
+}
 // 12 (eps + beta) of the stencils (a, b, c), (b, c, d), (c, d, e)
 __device__ __forceinline__ void indicators12(R a, R b, R c, R d, R e, R eps, R& s0, R& s1, R& s2) {
   const R eps12 = (R)12 * eps;
-  R t0 = (a + c) - (R)2 * b, u0 = fma((R)-4, b, fma((R)3, c, a));
-  R t1 = (b + d) - (R)2 * c, u1 = b - d;
-  R t2 = (c + e) - (R)2 * d, u2 = fma((R)-4, d, fma((R)3, c, e));
+  R t0 = fma((R)-2, b, a + c), u0 = fma((R)-4, b, fma((R)3, c, a));
+  R t1 = fma((R)-2, c, b + d), u1 = b - d;
+  R t2 = fma((R)-2, d, c + e), u2 = fma((R)-4, d, fma((R)3, c, e));
   s0 = fma((R)13 * t0, t0, fma((R)3 * u0, u0, eps12));
   s1 = fma((R)13 * t1, t1, fma((R)3 * u1, u1, eps12));
   s2 = fma((R)13 * t2, t2, fma((R)3 * u2, u2, eps12));
@@ -159,7 +169,7 @@ __device__ __forceinline__ R combine(R a, R b, R c, R d, R e, R s12, R s02, R s0
   R p1 = fma((R)2, d, fma((R)5, c, -b));
   R p2 = fma((R)5, d, fma((R)2, c, -e));
   R w0 = s12, w1 = (R)6 * s02, w2 = (R)3 * s01;
-  return fma(w0, p0, fma(w1, p1, w2 * p2)) / ((R)6 * ((w0 + w1) + w2));
+  return qdiv(fma(w0, p0, fma(w1, p1, w2 * p2)), (R)6 * ((w0 + w1) + w2));
 }
 }  // namespace wd
 
@@ -167,6 +177,17 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   double s0, s1, s2;
   wd::indicators(a, b, c, d, e, eps, s0, s1, s2);
   return wd::combine(a, b, c, d, e, s1 * s2, s0 * s2, s0 * s1);
+}
+
+// Both edges of zone c: left = weno5(e, d, c, b, a), right = weno5(a, b, c,
+// d, e), from one set of indicators (reversing the stencil swaps s0 and s2).
+__device__ __forceinline__ void weno5_pair(double a, double b, double c, double d, double e, double eps,
+                                           double& left, double& right) {
+  double s0, s1, s2;
+  wd::indicators(a, b, c, d, e, eps, s0, s1, s2);
+  const double s12 = s1 * s2, s02 = s0 * s2, s01 = s0 * s1;
+  right = wd::combine(a, b, c, d, e, s12, s02, s01);
+  left = wd::combine(e, d, c, b, a, s01, s02, s12);
 }
 
 // WENO-Z (Borges et al. 2008, power 2 as in Castro, Costa & Don 2011): the
@@ -185,6 +206,9 @@ __device__ __forceinline__ double wenoz(double a, double b, double c, double d, 
   s2 *= s2;
   return wd::combine(a, b, c, d, e, (s0 + T) * (s1 * s2), (s1 + T) * (s0 * s2), (s2 + T) * (s0 * s1));
 }
+
+// FP32 forms: contraction into fused multiply-adds allowed.
+#pragma clang fp contract(fast)
 
 // FP32 form.  The indicators are scaled by 12 as in the FP64 form and then
 // normalised by the smallest one, r_k = s_k / min s in [1, 1e6] (clamped:
@@ -218,6 +242,38 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e, R eps) {
 
 __device__ __forceinline__ float weno5(float a, float b, float c, float d, float e, float eps) {
   return wf::weno5(a, b, c, d, e, eps);
+}
+
+// FP32 form of weno5_pair (the normalised indicators are symmetric too).
+namespace wf {
+__device__ __forceinline__ R wcomb(R a, R b, R c, R d, R e, R w0, R w1, R w2) {
+  R p0 = fmaf(11.0f, c, fmaf(-7.0f, b, 2.0f * a));
+  R p1 = fmaf(2.0f, d, fmaf(5.0f, c, -b));
+  R p2 = fmaf(5.0f, d, fmaf(2.0f, c, -e));
+  return fmaf(w0, p0, fmaf(w1, p1, w2 * p2)) * __builtin_amdgcn_rcpf(6.0f * ((w0 + w1) + w2));
+}
+__device__ __forceinline__ void weno5_pair(R a, R b, R c, R d, R e, R eps, R& left, R& right) {
+  const R eps12 = 12.0f * eps;
+  R t0 = (a + c) - 2.0f * b, u0 = fmaf(-4.0f, b, fmaf(3.0f, c, a));
+  R t1 = (b + d) - 2.0f * c, u1 = b - d;
+  R t2 = (c + e) - 2.0f * d, u2 = fmaf(-4.0f, d, fmaf(3.0f, c, e));
+  R s0 = fmaf(13.0f * t0, t0, fmaf(3.0f * u0, u0, eps12));
+  R s1 = fmaf(13.0f * t1, t1, fmaf(3.0f * u1, u1, eps12));
+  R s2 = fmaf(13.0f * t2, t2, fmaf(3.0f * u2, u2, eps12));
+  const R im = __builtin_amdgcn_rcpf(fminf(fminf(s0, s1), s2));
+  R r0 = fminf(s0 * im, 1e6f), r1 = fminf(s1 * im, 1e6f), r2 = fminf(s2 * im, 1e6f);
+  r0 *= r0;
+  r1 *= r1;
+  r2 *= r2;
+  const R r12 = r1 * r2, r02 = r0 * r2, r01 = r0 * r1;
+  right = wcomb(a, b, c, d, e, r12, 6.0f * r02, 3.0f * r01);
+  left = wcomb(e, d, c, b, a, r01, 6.0f * r02, 3.0f * r12);
+}
+}  // namespace wf
+
+__device__ __forceinline__ void weno5_pair(float a, float b, float c, float d, float e, float eps,
+                                           float& left, float& right) {
+  wf::weno5_pair(a, b, c, d, e, eps, left, right);
 }
 
 // FP32 WENO-Z.  With b_k = 12 (eps + beta_k), rho_k = b_k / min b >= 1 and
@@ -272,6 +328,145 @@ __device__ __forceinline__ Dual weno5(Dual a, Dual b, Dual c, Dual d, Dual e, Du
   s2 *= s2;
   Dual w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
   return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+}
+
+// ---------------------------------------------------------- face physics --
+//
+// The state on one side of a face as the flux kernels need it: conserved
+// variables U, the flux F^d along the face normal and the two fast signal
+// speeds, from the reconstructed prims and the face metric.  The same
+// formulas as fluid_state / prim_to_flux / char_speeds, arranged for the
+// face, where these evaluations dominate the step's arithmetic:
+//   * the face metric holds only the entries that are not identically zero
+//     in the library's two spacetimes: flat space and Kerr in modified
+//     Kerr-Schild coordinates both have g_{2 mu} = g^{2 mu} = 0 for mu != 2
+//     (x2 is orthogonal to the other coordinates), so those table entries,
+//     exactly zero, are never read and their products never formed;
+//   * one reciprocal each of u^t, of w (b^2 + w) (sound and Alfven speeds
+//     together) and of 2A (the two roots) per side, and of the lapse per
+//     face, in place of the eight quotients per side of the written form;
+//   * fused multiply-adds, written out (contraction off), so that a face
+//     rounds the same way in every kernel that evaluates it.
+// In FP64 the reciprocals are the hardware estimate refined by two Newton
+// steps; the results differ from the written form by rounding only.
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ double face_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+__device__ __forceinline__ float face_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename R>
+struct FaceMetric {
+  R gtt, gt1, gt3, g11, g13, g22, g33;   // covariant
+  R ctt, ct1, ct3, c11, c13, c22, c33;   // contravariant
+  R gdet, alpha, ialpha;
+};
+
+template <typename R>
+__device__ __forceinline__ void load_face_metric(const double* __restrict__ tab, long plane, long q,
+                                                 FaceMetric<R>& m) {
+  auto at = [&](int f) { return (R)tab[f * plane + q]; };
+  m.gtt = at(G_COV + sidx(0, 0));
+  m.gt1 = at(G_COV + sidx(0, 1));
+  m.gt3 = at(G_COV + sidx(0, 3));
+  m.g11 = at(G_COV + sidx(1, 1));
+  m.g13 = at(G_COV + sidx(1, 3));
+  m.g22 = at(G_COV + sidx(2, 2));
+  m.g33 = at(G_COV + sidx(3, 3));
+  m.ctt = at(G_CON + sidx(0, 0));
+  m.ct1 = at(G_CON + sidx(0, 1));
+  m.ct3 = at(G_CON + sidx(0, 3));
+  m.c11 = at(G_CON + sidx(1, 1));
+  m.c13 = at(G_CON + sidx(1, 3));
+  m.c22 = at(G_CON + sidx(2, 2));
+  m.c33 = at(G_CON + sidx(3, 3));
+  m.gdet = at(G_DET);
+  m.alpha = at(G_ALPHA);
+  m.ialpha = face_rcp(m.alpha);
+}
+
+// U, F^D (D = 1..3) and the signal speeds cp >= cm of the prims p.
+template <int D, typename R>
+__device__ __forceinline__ void face_side(const R p[NVAR], const FaceMetric<R>& m, R gam, R F[NVAR],
+                                          R U[NVAR], R& cp, R& cm) {
+  const R rho = p[RHO], uu = p[UU], v1 = p[U1], v2 = p[U2], v3 = p[U3];
+  const R Bc1 = p[B1], Bc2 = p[B2], Bc3 = p[B3];
+  // four-velocity: gamma^2 = 1 + g_ij u~i u~j, u^t = gamma / alpha,
+  // u^i = u~i - gamma alpha g^{ti}, lowered with the face metric
+  const R qsq = fma(m.g11 * v1, v1, fma(m.g22 * v2, v2, fma(m.g33 * v3, v3, (R)2 * (m.g13 * v1) * v3)));
+  const R gamma = sqrt((R)1 + qsq);
+  const R ga = gamma * m.alpha;
+  const R ut = gamma * m.ialpha;
+  const R iut = m.alpha * face_rcp(gamma);
+  const R u1 = fma(-ga, m.ct1, v1), u2 = v2, u3 = fma(-ga, m.ct3, v3);
+  const R l0 = fma(m.gtt, ut, fma(m.gt1, u1, m.gt3 * u3));
+  const R l1 = fma(m.gt1, ut, fma(m.g11, u1, m.g13 * u3));
+  const R l2 = m.g22 * u2;
+  const R l3 = fma(m.gt3, ut, fma(m.g13, u1, m.g33 * u3));
+  // magnetic four-vector: b^t = B^i u_i, b^i = (B^i + b^t u^i) / u^t
+  const R bt = fma(Bc1, l1, fma(Bc2, l2, Bc3 * l3));
+  const R b1 = fma(bt, u1, Bc1) * iut, b2 = fma(bt, u2, Bc2) * iut, b3 = fma(bt, u3, Bc3) * iut;
+  const R k0 = fma(m.gtt, bt, fma(m.gt1, b1, m.gt3 * b3));
+  const R k1 = fma(m.gt1, bt, fma(m.g11, b1, m.g13 * b3));
+  const R k2 = m.g22 * b2;
+  const R k3 = fma(m.gt3, bt, fma(m.g13, b1, m.g33 * b3));
+  const R bsq = fma(bt, k0, fma(b1, k1, fma(b2, k2, b3 * k3)));
+  // rows t (conserved variables) and D (flux) of
+  // T^mu_nu = (rho + u + p + b^2) u^mu u_nu + (p + b^2/2) delta^mu_nu - b^mu b_nu
+  const R pg = (gam - (R)1) * uu;
+  const R w = ((rho + uu) + pg) + bsq;
+  const R ptot = fma((R)0.5, bsq, pg);
+  const R ud = D == 1 ? u1 : (D == 2 ? u2 : u3);
+  const R bd = D == 1 ? b1 : (D == 2 ? b2 : b3);
+  const R g = m.gdet;
+  {
+    const R wu = w * ut;
+    const R ru = rho * ut;
+    U[RHO] = g * ru;
+    U[UU] = g * (fma(wu, l0, fma(-bt, k0, ptot)) + ru);
+    U[U1] = g * fma(wu, l1, -bt * k1);
+    U[U2] = g * fma(wu, l2, -bt * k2);
+    U[U3] = g * fma(wu, l3, -bt * k3);
+    U[B1] = g * Bc1;
+    U[B2] = g * Bc2;
+    U[B3] = g * Bc3;
+  }
+  {
+    const R wu = w * ud;
+    const R ru = rho * ud;
+    F[RHO] = g * ru;
+    F[UU] = g * (fma(wu, l0, -bd * k0) + ru);
+    F[U1] = g * fma(wu, l1, fma(-bd, k1, D == 1 ? ptot : (R)0));
+    F[U2] = g * fma(wu, l2, fma(-bd, k2, D == 2 ? ptot : (R)0));
+    F[U3] = g * fma(wu, l3, fma(-bd, k3, D == 3 ? ptot : (R)0));
+    F[B1] = g * fma(b1, ud, -bd * u1);
+    F[B2] = g * fma(b2, ud, -bd * u2);
+    F[B3] = g * fma(b3, ud, -bd * u3);
+  }
+  // fast speeds: roots v of (u^D - v u^t)^2 (1 - c^2) = c^2 (v^2 g^tt - 2 v g^tD + g^DD),
+  // c^2 = cs^2 + vA^2 - cs^2 vA^2, cs^2 = gam p / w, vA^2 = b^2 / (b^2 + w), w = rho + gam u
+  const R we = fma(gam, uu, rho);
+  const R sw = bsq + we;
+  const R rr = face_rcp(we * sw);
+  const R cs2 = ((gam * pg) * sw) * rr;
+  const R va2 = (bsq * we) * rr;
+  const R c2 = fma(-cs2, va2, cs2 + va2);
+  const R cdd = D == 1 ? m.c11 : (D == 2 ? m.c22 : m.c33);
+  const R ctd = D == 1 ? m.ct1 : (D == 2 ? (R)0 : m.ct3);
+  const R ut2 = ut * ut, udt = ud * ut, ud2 = ud * ud;
+  const R A = fma(-c2, m.ctt + ut2, ut2);
+  const R B = (R)-2 * fma(-c2, ctd + udt, udt);
+  const R C = fma(-c2, cdd + ud2, ud2);
+  R disc = fma(B, B, (R)-4 * A * C);
+  disc = disc > (R)0 ? disc : (R)0;
+  const R sq = sqrt(disc);
+  const R i2a = (R)0.5 * face_rcp(A);
+  const R va = (sq - B) * i2a, vb = (-B - sq) * i2a;
+  cp = va > vb ? va : vb;
+  cm = va > vb ? vb : va;
 }
 
 }  // namespace grmhd

@@ -5,8 +5,11 @@ pointers of torch tensors and the current torch stream.  There is no
 fallback: importing it without the built library raises.
 """
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import torch
 
@@ -142,6 +145,18 @@ def lib():
     return _lib
 
 
+# Contexts and packs still open.  They are closed by an exit handler, which
+# runs while the HIP runtime is still up; a finalizer that runs later, during
+# interpreter shutdown, makes no HIP call (the process is ending anyway).
+_open = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_open):
+        obj.close()
+
+
 def _check(rc):
     if rc != OK:
         raise GrmhdError(f"grmhd error {rc}: {lib().grmhd_strerror(rc).decode()}")
@@ -209,13 +224,22 @@ class Grmhd:
                               C.byref(self.params), C.c_void_p(self._ws_ptr), nbytes,
                               C.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
-        self._lib = L          # kept for __del__ at interpreter exit
+        self._lib = L
+        _open.add(self)
 
-    def __del__(self):
+    def close(self):
+        """Release the context (idempotent); the object is unusable after."""
         ctx = getattr(self, "ctx", None)
         if ctx:
-            self._lib.grmhd_destroy(ctx)
             self.ctx = None
+            _open.discard(self)
+            self._lib.grmhd_destroy(ctx)
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may be gone when a late
+        # finalizer runs)
+        if not _finalizing():
+            self.close()
 
     def load(self, prims):
         p = prims.to(device=self.device, dtype=torch.float64).contiguous()
@@ -385,15 +409,24 @@ class Pack:
                                    C.c_void_p(self.stream.cuda_stream)))
         self.h = h
         self._lib = L
+        _open.add(self)
         gb, nd = C.c_int(), C.c_longlong()
         _check(L.grmhd_pack_info(self.h, C.byref(gb), C.byref(nd)))
         self.grid_blocks, self.prim_doubles = gb.value, nd.value
 
-    def __del__(self):
+    def close(self):
+        """Release the pack (idempotent); the object is unusable after."""
         h = getattr(self, "h", None)
         if h:
-            self._lib.grmhd_pack_destroy(h)
             self.h = None
+            _open.discard(self)
+            self._lib.grmhd_pack_destroy(h)
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may be gone when a late
+        # finalizer runs)
+        if not _finalizing():
+            self.close()
 
     def set_tiles(self, n, t1, t2, t3):
         _check(lib().grmhd_pack_set_tiles(self.h, int(n), int(t1), int(t2), int(t3)))

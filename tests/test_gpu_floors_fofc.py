@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity_util import rel_l1
+from parity_util import rel_l1, check, NOISY_MODE
 from workloads import (magnetised_blast, fm_torus, linear_mode, interior, RECON_MC, RECON_WENO5)
 
 pytestmark = pytest.mark.gpu
@@ -32,8 +32,10 @@ def _setup():
 def run_both(grid, P, gam, recon, nsteps, floors, fofc, inverter=0, precision=0, **fp):
     torch, gr = _setup()
     c = oracle.cfg(grid, gam=gam, recon=recon, floors=floors, fofc=fofc, inverter=inverter, **fp)
+    alt, _, _ = oracle.run(c, P, -1, nsteps, fma=True)
     ref, fails, dts = oracle.run(c, P, -1, nsteps)
     st = oracle.last_stats()
+    run_both.alt = alt
     s = gr.Grmhd(grid, gam, recon=recon, floors=floors, fofc=fofc, inverter=inverter,
                  precision=precision, **fp)
     s.load(torch.from_numpy(P).cuda())
@@ -58,38 +60,37 @@ def test_floors_fofc_parity(case):
     make, gam, recon, nsteps, floors, fofc = CASES[case]
     grid, P = make()
     out, ref, cnt, st, _, dts = run_both(grid, P, gam, recon, nsteps, floors, fofc)
-    r = rel_l1(out, ref)
-    print(case, "gpu", cnt, "oracle", st, "rel L1", r, flush=True)
+    print(case, "gpu", cnt, "oracle", st, flush=True)
     assert cnt == st
     assert (st["fofc_zones"] > 0) == fofc or st["floor_hits"] > 0
-    assert r.max() <= TOL, r
+    check(out, ref, label=case, alt=run_both.alt)
 
 
 def test_kastaun_with_floors_and_fofc():
     grid, P = magnetised_blast(48)
     out, ref, cnt, st, _, _ = run_both(grid, P, 4 / 3, RECON_WENO5, 6, True, True, inverter=1)
-    r = rel_l1(out, ref)
-    print("kastaun blast", cnt, st, r)
-    assert cnt == st and r.max() <= TOL
+    print("kastaun blast", cnt, st)
+    assert cnt == st
+    check(out, ref, label="kastaun blast", alt=run_both.alt)
 
 
 def test_implicit_recovery_with_floors():
     grid, P = magnetised_blast(48)
     out, ref, cnt, st, _, _ = run_both(grid, P, 4 / 3, RECON_WENO5, 6, True, False, inverter=2)
-    r = rel_l1(out, ref)
-    print("implicit blast floors", cnt, st, r)
-    assert cnt == st and r.max() <= TOL
+    print("implicit blast floors", cnt, st)
+    assert cnt == st
+    check(out, ref, label="implicit blast floors", alt=run_both.alt)
 
 
 def test_donor_cell_step_parity():
     """The first-order scheme alone (donor-cell states everywhere)."""
-    for make, gam in ((lambda: linear_mode("fast", 32, ndim=2)[0:2], 4 / 3),
-                      (lambda: fm_torus(20, 28, 6)[0:2], 13 / 9)):
+    for make, gam, noisy in ((lambda: linear_mode("fast", 32, ndim=2)[0:2], 4 / 3, NOISY_MODE),
+                             (lambda: fm_torus(20, 28, 6)[0:2], 13 / 9, ())):
         grid, P = make()
-        out, ref, cnt, st, _, _ = run_both(grid, P, gam, oracle.RECON_DONOR, 2, False, False)
-        r = rel_l1(out, ref)
-        print("donor", cnt, st, r)
-        assert cnt["fails"] == st["fails"] and r.max() <= TOL
+        out, ref, cnt, st, _, dts = run_both(grid, P, gam, oracle.RECON_DONOR, 2, False, False)
+        print("donor", cnt, st)
+        assert cnt["fails"] == st["fails"]
+        check(out, ref, noisy, label="donor", alt=run_both.alt)
 
 
 def test_fofc_and_floors_are_a_no_op_on_smooth_flow():

@@ -13,8 +13,8 @@ import numpy as np
 import pytest
 
 import oracle
-from parity_util import GROUPS
-from parity_util import rel_l1
+from parity_util import GROUPS, ZONE_TOL
+from parity_util import rel_l1, zone_rel
 from workloads import (torus_pack, torus_tiling, tiling, linear_mode, interior, RECON_MC, RECON_WENO5,
                        NG)
 
@@ -61,6 +61,7 @@ def test_pack_matches_single_blocks_and_oracle(recon, inv):
     res = _unpack(pk.prims().cpu().numpy(), blocks)
     num = np.zeros(8)
     den = np.zeros(8)
+    zone = np.zeros(8)
     for b, out in zip(blocks, res):
         s = gr.Grmhd(b["grid"], gam, recon=recon, inverter=inv)
         s.load(torch.from_numpy(b["prims"]).cuda())
@@ -70,14 +71,16 @@ def test_pack_matches_single_blocks_and_oracle(recon, inv):
         assert np.array_equal(interior(out), interior(alone)), b["offset"]
         c = oracle.cfg(b["grid"], gam=gam, recon=recon, inverter=inv)
         ref, _, _ = oracle.run(c, b["prims"], dt, 2)
+        zone = np.maximum(zone, zone_rel(out, ref))
         # the pack is one workload: its relative L1 sums over all blocks
         A, B = interior(out), interior(ref)
         for v in range(8):
             num[v] += np.abs(A[v] - B[v]).sum()
             den[v] += sum(np.abs(B[w]).sum() for w in GROUPS[v])
     rel = num / den
-    print("pack vs oracle rel L1", rel)
+    print("pack vs oracle rel L1", rel, "per zone", zone)
     assert rel.max() <= 1e-12, rel
+    assert np.all(zone <= ZONE_TOL), zone
 
 
 def test_pack_tile_shapes_do_not_change_results():
@@ -137,6 +140,8 @@ def test_tiling_with_ghost_exchange_advances_as_the_global_grid(recon):
     r_orc = rel_l1(pad(out), ref)
     print("tiling vs single grid", r_gpu, "vs oracle", r_orc, "fails", pk.status(), single.status()[0], fails)
     assert r_gpu.max() <= 1e-12 and r_orc.max() <= 1e-12
+    z = zone_rel(pad(out), ref)
+    assert np.all(z <= ZONE_TOL), z
     assert pk.status() == single.status()[0] == fails
     # frozen ghosts: the same tiling no longer advances as the global grid
     pk.set_exchange(False)

@@ -1,23 +1,23 @@
 """GPU-vs-oracle parity of the HIP path, through the C ABI.
 
 The bar (per step, FP64): relative L1 of every primitive over interior zones
-(parity_util.rel_l1) at most 1e-12; failure flags equal; div B at roundoff.
-Inputs are the seeded workloads, identical on both sides; both sides advance
-with the oracle's dt.
+at most 1e-12, every zone within the per-zone bars, failure flags equal,
+div B at roundoff (parity_util: rel_l1, zone_rel, check).  Inputs are the
+seeded workloads, identical on both sides; both sides advance with the
+oracle's dt.
 
-WENO5 linear modes are held to 1e-11 instead: their u~1, u~2, B2 are pure
-1e-4 perturbations moved by differences of O(1) background fluxes, and the
-GPU's WENO5 weights are rounded differently from the oracle's (one division
-instead of four, contraction allowed); the oracle against itself compiled
-with FMA contraction differs by 8e-12 there.  The MC path, which the
-fast-mode workload uses, is held to 1e-12 and agrees bit for bit in flat space.
+The face physics and WENO5 of the GPU round differently from the oracle
+(fused multiply-adds, reciprocals); in a linear mode at rest, whose whole
+u~ is the 1e-4 perturbation, that shows at ~1e-12 of the perturbation, and
+those components are held to 3x the oracle's own spread under FMA
+contraction (NOISY_MODE), measured on each case.
 """
 
 import numpy as np
 import pytest
 
 import oracle
-from parity_util import rel_l1
+from parity_util import rel_l1, check, NOISY_MODE
 from workloads import (linear_mode, fm_torus, bondi, interior, GridSpec, BC_PERIODIC,
                        METRIC_MINKOWSKI, RECON_MC, RECON_WENO5)
 
@@ -50,32 +50,39 @@ def run_gpu(grid, P, gam, recon, dts, precision=0, inverter=0):
     return out, s.status()[0], s
 
 
+# case: ((grid, prims), gamma, reconstruction, noisy components)
 CASES = {
-    "fast32_mc": lambda: (linear_mode("fast", 32, ndim=3)[0:2], 4 / 3, RECON_MC, TOL),
-    "fast16_weno": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, RECON_WENO5, 1e-11),
-    "alfven24x20_mc_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, RECON_MC, TOL),
-    "slow20_mc_2d": lambda: (linear_mode("slow", 20, ndim=2)[0:2], 4 / 3, RECON_MC, TOL),
-    "torus24_weno": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, RECON_WENO5, TOL),
-    "torus20x28x6_mc": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, RECON_MC, TOL),
+    "fast32_mc": lambda: (linear_mode("fast", 32, ndim=3)[0:2], 4 / 3, RECON_MC, NOISY_MODE),
+    "fast16_weno": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, RECON_WENO5, NOISY_MODE),
+    "alfven24x20_mc_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, RECON_MC, NOISY_MODE),
+    "slow20_mc_2d": lambda: (linear_mode("slow", 20, ndim=2)[0:2], 4 / 3, RECON_MC, NOISY_MODE),
+    "torus24_weno": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, RECON_WENO5, ()),
+    "torus20x28x6_mc": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, RECON_MC, ()),
     "torus_unmag_16x20x4_weno": lambda: (fm_torus(16, 20, 4, magnetised=False)[0:2], 13 / 9,
-                                         RECON_WENO5, TOL),
+                                         RECON_WENO5, ()),
     # Michel accretion, Schwarzschild (a = 0): frozen radial ghosts, polar x2
-    "bondi32x16_mc": lambda: (bondi(32, 16)[0:2], 4 / 3, RECON_MC, TOL),
-    "bondi24x12x2_weno": lambda: (bondi(24, 12, 2)[0:2], 4 / 3, RECON_WENO5, TOL),
+    "bondi32x16_mc": lambda: (bondi(32, 16)[0:2], 4 / 3, RECON_MC, ()),
+    "bondi24x12x2_weno": lambda: (bondi(24, 12, 2)[0:2], 4 / 3, RECON_WENO5, ()),
 }
+
+
+def oracle_pair(c, P, nsteps, noisy):
+    """The oracle's run (prims, fails, dts, flags) and, for cases with noisy
+    components, the FMA build's run of the same steps."""
+    ref, fails, dts, flags = oracle.run(c, P, -1, nsteps, flags=True)
+    alt = oracle.run(c, P, -1, nsteps, fma=True)[0] if noisy else None
+    return ref, fails, dts, flags, alt
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_step_parity(case):
-    (grid, P), gam, recon, tol = CASES[case]()
+    (grid, P), gam, recon, noisy = CASES[case]()
     c = oracle.cfg(grid, gam=gam, recon=recon)
-    nsteps = 2
-    ref, fails, dts, flags = oracle.run(c, P, -1, nsteps, flags=True)
+    ref, fails, dts, flags, alt = oracle_pair(c, P, 2, noisy)
     out, gfails, _ = run_gpu(grid, P, gam, recon, dts)
-    r = rel_l1(out, ref)
-    print(case, "dts", dts, "fails", fails, gfails, "rel L1", r)
+    print(case, "dts", dts, "fails", fails, gfails)
     assert gfails == fails
-    assert r.max() <= tol, r
+    check(out, ref, noisy, label=case, alt=alt)
 
 
 KASTAUN_CASES = ["fast32_mc", "torus24_weno", "torus20x28x6_mc", "bondi32x16_mc"]
@@ -84,14 +91,13 @@ KASTAUN_CASES = ["fast32_mc", "torus24_weno", "torus20x28x6_mc", "bondi32x16_mc"
 @pytest.mark.parametrize("case", KASTAUN_CASES)
 def test_step_parity_kastaun(case):
     """The same steps with the Kastaun et al. recovery on both sides."""
-    (grid, P), gam, recon, tol = CASES[case]()
+    (grid, P), gam, recon, noisy = CASES[case]()
     c = oracle.cfg(grid, gam=gam, recon=recon, inverter=oracle.INV_KASTAUN)
-    ref, fails, dts, flags = oracle.run(c, P, -1, 2, flags=True)
+    ref, fails, dts, flags, alt = oracle_pair(c, P, 2, noisy)
     out, gfails, _ = run_gpu(grid, P, gam, recon, dts, inverter=oracle.INV_KASTAUN)
-    r = rel_l1(out, ref)
-    print(case, "kastaun dts", dts, "fails", fails, gfails, "rel L1", r)
+    print(case, "kastaun dts", dts, "fails", fails, gfails)
     assert gfails == fails
-    assert r.max() <= tol, r
+    check(out, ref, noisy, label=case, alt=alt)
 
 
 IMPLICIT_CASES = ["fast32_mc", "torus24_weno", "torus20x28x6_mc", "bondi32x16_mc"]
@@ -101,14 +107,13 @@ IMPLICIT_CASES = ["fast32_mc", "torus24_weno", "torus20x28x6_mc", "bondi32x16_mc
 def test_step_parity_implicit_recovery(case):
     """The same steps with the implicit solver's Newton as the recovery on
     both sides (its own pass on the GPU)."""
-    (grid, P), gam, recon, tol = CASES[case]()
+    (grid, P), gam, recon, noisy = CASES[case]()
     c = oracle.cfg(grid, gam=gam, recon=recon, inverter=oracle.INV_IMPLICIT)
-    ref, fails, dts, flags = oracle.run(c, P, -1, 2, flags=True)
+    ref, fails, dts, flags, alt = oracle_pair(c, P, 2, noisy)
     out, gfails, s = run_gpu(grid, P, gam, recon, dts, inverter=oracle.INV_IMPLICIT)
-    r = rel_l1(out, ref)
-    print(case, "implicit dts", dts, "fails", fails, gfails, "rel L1", r)
+    print(case, "implicit dts", dts, "fails", fails, gfails)
     assert gfails == fails
-    assert r.max() <= tol, r
+    check(out, ref, noisy, label=case, alt=alt)
 
 
 def test_implicit_recovery_cons_to_prims_and_cfl_step():
@@ -255,6 +260,55 @@ def test_dt_and_divb_parity():
     s2 = gr.Grmhd(g2, 4 / 3, recon=RECON_MC)
     s2.load(torch.from_numpy(P2))
     assert s2.dt() == pytest.approx(oracle.estimate_dt(c2, P2), rel=1e-14)
+
+
+def test_divb_of_a_known_field_kerr():
+    """Kerr modified KS with sqrt(-g) B^1 = x1 - x1min and sqrt(-g) B^2 =
+    3 x2 at zone centres: corner divergence 4 / sqrt(-g)(corner) at every
+    interior corner.  The GPU's per-corner field, max and mean agree with
+    the oracle's (itself pinned to the closed form) to 1e-13."""
+    torch = _torch()
+    gr = _gr()
+    from workloads.torus import torus_grid
+    g = torus_grid(20, 16, 6)
+    c = oracle.cfg(g, gam=13 / 9)
+    P = np.zeros((8, g.n3 + 6, g.n2 + 6, g.n1 + 6))
+    P[0], P[1] = 1.0, 1.0
+    gdet = oracle.prims_to_cons(c, np.ones_like(P))[5]         # sqrt(-g) B1 with B1 = 1
+    x1, x2, _ = g.centers()
+    X2, X1 = np.meshgrid(x2, x1, indexing="ij")
+    inner = gdet[3, 3:-3, 3:-3]                                # one interior x3 plane
+    P[5, :, 3:-3, 3:-3] = ((X1 - g.x1min)[3:-3, 3:-3] / inner)[None]
+    P[6, :, 3:-3, 3:-3] = (3.0 * X2[3:-3, 3:-3] / inner)[None]
+    omx, omean, ofield = oracle.divb(c, P, field=True)
+    s = gr.Grmhd(g, 13 / 9, recon=RECON_MC)
+    s.load(torch.from_numpy(P))
+    mx, mean, field = s.divb(field=True)
+    field = field.cpu().numpy()
+    assert mx == pytest.approx(omx, rel=1e-13)
+    assert mean == pytest.approx(omean, rel=1e-13)
+    sel = ofield != 0.0
+    assert np.allclose(field[sel], ofield[sel], rtol=1e-13, atol=0.0)
+    assert not field[~sel].any()
+
+
+def test_cfl_step_of_a_state_with_a_nan_zone_is_flagged():
+    """One NaN zone: the host CFL estimate fails with E_STATE, and a device
+    CFL step flags its dt as unusable, instead of taking the other zones'
+    minimum."""
+    torch = _torch()
+    gr = _gr()
+    grid, P, _ = fm_torus(24, 24, 8)
+    P = P.copy()
+    P[1, 3 + 4, 3 + 12, 3 + 10] = np.nan
+    s = gr.Grmhd(grid, 13 / 9, recon=RECON_WENO5)
+    s.load(torch.from_numpy(P))
+    with pytest.raises(gr.GrmhdError, match="-3"):
+        s.dt()
+    s.step_cfl()
+    with pytest.raises(gr.GrmhdError, match="-3"):
+        s.last_dt()
+    torch.cuda.synchronize()
 
 
 def test_step_cfl_equals_host_dt_step():

@@ -2,12 +2,13 @@
 linear reconstruction with van Leer's limiter, MP5 and PPM, through the C
 ABI.
 
-Bars as for MC and WENO5: relative L1 per primitive at most 1e-12 per step
-(1e-11 for WENO-Z on a linear mode, whose weights the GPU rounds differently
-from the oracle, as for WENO5), failure counts equal; van Leer's slope, MP5
-and PPM are evaluated in the oracle's order, so flat space agrees bit for
-bit.  The mixed-precision forms are held against the FP64 GPU path of the
-same reconstruction.
+Bars as for MC and WENO5 (parity_util.check): relative L1 per primitive at
+most 1e-12 per step, every zone within the per-zone bars, failure counts
+equal; the u~ of a linear mode at rest (its whole value the perturbation) is
+held to 3x the oracle's own FMA spread on the case, since the GPU's face
+physics rounds differently from the oracle's written form.  The
+mixed-precision forms are held against the FP64 GPU path of the same
+reconstruction.
 """
 
 import os
@@ -16,7 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity_util import rel_l1
+from parity_util import rel_l1, check, zone_rel, ZONE_TOL, NOISY_MODE
 from workloads import linear_mode, fm_torus, bondi, interior, torus_pack
 
 pytestmark = pytest.mark.gpu
@@ -24,7 +25,6 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 THREADS = min(16, os.cpu_count() or 1)
 WENOZ, VL, MP5, PPM = oracle.RECON_WENOZ, oracle.RECON_VL, oracle.RECON_MP5, oracle.RECON_PPM
-BITWISE_FLAT = (VL, MP5, PPM)
 
 
 def _setup():
@@ -35,43 +35,42 @@ def _setup():
     return torch, gr
 
 
+# case: ((grid, prims), gamma, reconstruction, noisy components)
 CASES = {
-    "fast16_wenoz": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, WENOZ, 1e-11),
-    "torus24_wenoz": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, WENOZ, TOL),
-    "bondi24x12x2_wenoz": lambda: (bondi(24, 12, 2)[0:2], 4 / 3, WENOZ, TOL),
-    "fast32_vl": lambda: (linear_mode("fast", 32, ndim=3)[0:2], 4 / 3, VL, TOL),
-    "alfven24x20_vl_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, VL, TOL),
-    "torus20x28x6_vl": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, VL, TOL),
-    "bondi32x16_vl": lambda: (bondi(32, 16)[0:2], 4 / 3, VL, TOL),
-    "fast16_mp5": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, MP5, TOL),
-    "slow20_mp5_2d": lambda: (linear_mode("slow", 20, ndim=2)[0:2], 4 / 3, MP5, TOL),
-    "torus24_mp5": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, MP5, TOL),
-    "bondi24x12x2_mp5": lambda: (bondi(24, 12, 2)[0:2], 4 / 3, MP5, TOL),
-    "fast16_ppm": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, PPM, TOL),
-    "alfven24x20_ppm_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, PPM, TOL),
-    "torus20x28x6_ppm": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, PPM, TOL),
-    "bondi32x16_ppm": lambda: (bondi(32, 16)[0:2], 4 / 3, PPM, TOL),
+    "fast16_wenoz": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, WENOZ, NOISY_MODE),
+    "torus24_wenoz": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, WENOZ, ()),
+    "bondi24x12x2_wenoz": lambda: (bondi(24, 12, 2)[0:2], 4 / 3, WENOZ, ()),
+    "fast32_vl": lambda: (linear_mode("fast", 32, ndim=3)[0:2], 4 / 3, VL, NOISY_MODE),
+    "alfven24x20_vl_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, VL, NOISY_MODE),
+    "torus20x28x6_vl": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, VL, ()),
+    "bondi32x16_vl": lambda: (bondi(32, 16)[0:2], 4 / 3, VL, ()),
+    "fast16_mp5": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, MP5, NOISY_MODE),
+    "slow20_mp5_2d": lambda: (linear_mode("slow", 20, ndim=2)[0:2], 4 / 3, MP5, NOISY_MODE),
+    "torus24_mp5": lambda: (fm_torus(24, 24, 8)[0:2], 13 / 9, MP5, ()),
+    "bondi24x12x2_mp5": lambda: (bondi(24, 12, 2)[0:2], 4 / 3, MP5, ()),
+    "fast16_ppm": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, PPM, NOISY_MODE),
+    "alfven24x20_ppm_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, PPM, NOISY_MODE),
+    "torus20x28x6_ppm": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, PPM, ()),
+    "bondi32x16_ppm": lambda: (bondi(32, 16)[0:2], 4 / 3, PPM, ()),
 }
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_step_parity_further_reconstructions(case):
     torch, gr = _setup()
-    (grid, P), gam, recon, tol = CASES[case]()
+    (grid, P), gam, recon, noisy = CASES[case]()
     print("case", case, flush=True)
     c = oracle.cfg(grid, gam=gam, recon=recon)
     ref, fails, dts, _ = oracle.run(c, P, -1, 2, flags=True)
+    alt = oracle.run(c, P, -1, 2, fma=True)[0] if noisy else None
     s = gr.Grmhd(grid, gam, recon=recon)
     s.load(torch.from_numpy(P))
     for dt in dts:
         s.step(dt)
     out = s.prims().cpu().numpy()
-    r = rel_l1(out, ref)
-    print(case, "dts", dts, "fails", fails, s.status()[0], "rel L1", r)
+    print(case, "dts", dts, "fails", fails, s.status()[0], )
     assert s.status()[0] == fails
-    assert r.max() <= tol, r
-    if recon in BITWISE_FLAT and grid.metric == 0:
-        assert np.array_equal(interior(out), interior(ref))
+    check(out, ref, noisy, label=case, alt=alt)
 
 
 @pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM])
@@ -107,9 +106,8 @@ def test_torus128_full_step_further_reconstructions(recon):
     c = oracle.cfg(grid, gam=gam, recon=recon, nthreads=THREADS)
     assert dt == pytest.approx(oracle.estimate_dt(c, P), rel=1e-14)
     ref, fails, _ = oracle.run(c, P, dt, 1)
-    rel = rel_l1(out, ref)
-    print("128^3 recon", recon, "rel L1", rel, "failures", fails)
-    assert rel.max() <= TOL, rel
+    print("128^3 recon", recon, "failures", fails)
+    check(out, ref, label="128^3 recon %d" % recon)
     assert s.status()[0] == fails
 
 
