@@ -182,6 +182,24 @@ int grmhd_step(grmhd_ctx* ctx, double dt);
  * with more than one zone), from the current prims.  Synchronises. */
 int grmhd_estimate_dt(grmhd_ctx* ctx, double* dt_out);
 
+/* The CFL step of grmhd_estimate_dt for a prims array d_prims (device,
+ * padded layout; only interior zones are read), without a context and
+ * without allocating anything: for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid it).  The zone-centre metric is evaluated in place, so the result
+ * equals grmhd_estimate_dt's on a context of the same grid, metric and
+ * parameters holding the same prims.  The reduction's scratch is a fixed
+ * device array of the library (2048 workgroup maxima plus four results,
+ * 16.4 KB per GPU, held until the process ends); the reduction strides over
+ * the grid, so every grid grmhd_create accepts fits it.  hip_stream: a
+ * stream of the current device (NULL = default); the call synchronises it.
+ * All calls on one GPU share that scratch: calls that overlap on one GPU
+ * (several host threads or streams) race and must be serialised by the
+ * caller.  E_ARG for bad sizes or enums, E_STATE when the maximum signal
+ * rate is not positive and finite, E_HIP on a runtime error. */
+int grmhd_cfl_dt_noalloc(const grmhd_grid* grid, const grmhd_metric* metric, const grmhd_params* params,
+                         const double* d_prims, double* dt_out, void* hip_stream);
+
 /* One step of the CFL size without a host round trip: the dt reduction of
  * grmhd_estimate_dt runs on the device and both stages read its result there
  * (the per-step global dt of the Core section's reductions).  Asynchronous.

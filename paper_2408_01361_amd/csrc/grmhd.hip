@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <mutex>
 #include <vector>
 #include <new>
 #include <stdint.h>
@@ -2378,32 +2379,9 @@ int launch_dt(grmhd_ctx* c) {
   return hip_check();
 }
 
-int sync(grmhd_ctx* c) { return hipStreamSynchronize(c->stream) == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
-
-}  // namespace
-
-extern "C" {
-
-size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
-  if (!grid_ok(grid, params)) return 0;
-  return carve(nullptr, nullptr, grid, params->ct, params->inverter);
-}
-
-int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* metric,
-                 const grmhd_params* params, void* d_workspace, size_t ws_bytes, void* hip_stream) {
-  if (!out || !metric || !grid_ok(grid, params) || !d_workspace) return GRMHD_E_ARG;
-  if (metric->metric != GRMHD_METRIC_MINKOWSKI && metric->metric != GRMHD_METRIC_KERR_MKS)
-    return GRMHD_E_ARG;
-  if (((uintptr_t)d_workspace & 255) != 0) return GRMHD_E_ARG;
-  if (ws_bytes < carve(nullptr, nullptr, grid, params->ct, params->inverter)) return GRMHD_E_NOMEM;
-  grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
-  if (!c) return GRMHD_E_NOMEM;
-  c->grid = *grid;
-  c->metric = *metric;
-  c->params = *params;
-  c->stream = (hipStream_t)hip_stream;
-  carve(c, (char*)d_workspace, grid, params->ct, params->inverter);
-  Dev& g = c->dev;
+// Kernel-side description of a grid, its metric and parameters.
+Dev make_dev(const grmhd_grid* grid, const grmhd_metric* metric, const grmhd_params* params) {
+  Dev g;
   g.n1 = grid->n1; g.n2 = grid->n2; g.n3 = grid->n3;
   g.s1 = g.n1 + 2 * NG; g.s2 = g.n2 + 2 * NG; g.s3 = g.n3 + 2 * NG;
   g.nz = (long)g.s1 * g.s2 * g.s3;
@@ -2414,7 +2392,7 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   g.x1min = grid->x1min;
   g.x2min = grid->x2min;
   for (int a = 0; a < 6; a++) g.bc[a] = grid->bc[a];
-  bool kerr = metric->metric == GRMHD_METRIC_KERR_MKS;
+  const bool kerr = metric->metric == GRMHD_METRIC_KERR_MKS;
   g.pole_lo = kerr && fabs(grid->x2min) < 1e-10;
   g.pole_hi = kerr && fabs(grid->x2max - 1.0) < 1e-10;
   g.gam = params->gamma_ad;
@@ -2432,6 +2410,116 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   g.u_over_rho_max = params->u_over_rho_max;
   g.gamma_max = params->gamma_max;
   g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
+  return g;
+}
+
+// ------------------------------------------------ CFL step, no allocation --
+//
+// grmhd_cfl_dt_noalloc: the CFL step of a caller's prims array without a
+// context.  The zone-centre metric is evaluated in place (the same
+// metric_point the context's tables hold, so the rates are the same bits)
+// and the reduction's scratch -- the workgroup maxima and the final pass's
+// four results -- is this file-scope device array, one copy per GPU, held
+// until the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns on that GPU (scratch_on_current_device).
+constexpr int NOALLOC_PARTIALS = 2048;
+__device__ __align__(256) double scratch[NOALLOC_PARTIALS + 8];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch (looked up once per device, with the
+// device current).
+int scratch_on_current_device(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return GRMHD_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GRMHD_E_HIP;
+    g_scratch[dev] = (double*)p;
+  }
+  *out = g_scratch[dev];
+  return GRMHD_OK;
+}
+
+// Per zone the CFL signal rate with the metric evaluated at the zone centre;
+// workgroup maxima to partial[] (grid-stride, so any box reduces through the
+// launch's workgroups).
+__global__ void __launch_bounds__(BLOCK) k_dt_partial_point(Dev g, Box box, const double* __restrict__ P,
+                                                            double* partial) {
+  double s = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < box.count(); t += stride) {
+    int i, j, k;
+    box_index(box, t, i, j, k);
+    const long c = zid(g, i, j, k);
+    double p[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) p[v] = P[v * g.nz + c];
+    PointMetric<double> m;
+    const double xc1 = g.x1min + (i + 0.5) * g.dx1, xc2 = g.x2min + (j + 0.5) * g.dx2;
+    metric_point(g.st, xc1, xc2, m.gcov, m.gcon, m.gdet, m.alpha);
+    s = fmax(s, zone_rate(g, p, m));
+  }
+  double sm = 0.0;
+  block_reduce(s, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+int sync(grmhd_ctx* c) { return hipStreamSynchronize(c->stream) == hipSuccess ? GRMHD_OK : GRMHD_E_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
+  if (!grid_ok(grid, params)) return 0;
+  return carve(nullptr, nullptr, grid, params->ct, params->inverter);
+}
+
+int grmhd_cfl_dt_noalloc(const grmhd_grid* grid, const grmhd_metric* metric, const grmhd_params* params,
+                         const double* d_prims, double* dt_out, void* hip_stream) {
+  if (!grid || !metric || !params || !d_prims || !dt_out || !grid_ok(grid, params)) return GRMHD_E_ARG;
+  if (metric->metric != GRMHD_METRIC_MINKOWSKI && metric->metric != GRMHD_METRIC_KERR_MKS)
+    return GRMHD_E_ARG;
+  double* s = nullptr;
+  int rc;
+  if ((rc = scratch_on_current_device(&s))) return rc;
+  const Dev g = make_dev(grid, metric, params);
+  const Box bz = make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1);
+  long nb = blocks_for(bz.count());
+  if (nb > NOALLOC_PARTIALS) nb = NOALLOC_PARTIALS;  // grid-stride: every box fits the scratch
+  hipStream_t st = (hipStream_t)hip_stream;
+  k_dt_partial_point<<<(unsigned)nb, BLOCK, 0, st>>>(g, bz, d_prims, s);
+  k_reduce_final<<<1, BLOCK, 0, st>>>((const double*)s, (const double*)nullptr, (int)nb,
+                                      s + NOALLOC_PARTIALS, params->cfl);
+  double smax = 0.0;
+  if (hipMemcpyAsync(&smax, s + NOALLOC_PARTIALS, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess || hip_check() != GRMHD_OK)
+    return GRMHD_E_HIP;
+  if (!(smax > 0.0) || !isfinite(smax)) return GRMHD_E_STATE;
+  *dt_out = params->cfl / smax;
+  return GRMHD_OK;
+}
+
+int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* metric,
+                 const grmhd_params* params, void* d_workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out || !metric || !grid_ok(grid, params) || !d_workspace) return GRMHD_E_ARG;
+  if (metric->metric != GRMHD_METRIC_MINKOWSKI && metric->metric != GRMHD_METRIC_KERR_MKS)
+    return GRMHD_E_ARG;
+  if (((uintptr_t)d_workspace & 255) != 0) return GRMHD_E_ARG;
+  if (ws_bytes < carve(nullptr, nullptr, grid, params->ct, params->inverter)) return GRMHD_E_NOMEM;
+  grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
+  if (!c) return GRMHD_E_NOMEM;
+  c->grid = *grid;
+  c->metric = *metric;
+  c->params = *params;
+  c->stream = (hipStream_t)hip_stream;
+  carve(c, (char*)d_workspace, grid, params->ct, params->inverter);
+  c->dev = make_dev(grid, metric, params);
+  Dev& g = c->dev;
   k_geometry<<<blocks_for(g.plane), BLOCK, 0, c->stream>>>(g, c->tabC, c->tabF1, c->tabF2, c->corner,
                                                            c->conn);
   // failure count zero; no dt reduced yet (result[3] = 1)

@@ -80,7 +80,7 @@ EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_s
            "grmhd_pack_load_prims", "grmhd_pack_step", "grmhd_pack_get_prims",
            "grmhd_pack_get_status", "grmhd_pack_info", "grmhd_pack_destroy",
            "grmhd_pack_exchange_bytes", "grmhd_pack_set_exchange",
-           "grmhd_vjp_workspace_bytes", "grmhd_step_vjp", "grmhd_set_schedule", "grmhd_timing", "grmhd_timing_report", "grmhd_strerror", "grmhd_destroy")
+           "grmhd_vjp_workspace_bytes", "grmhd_step_vjp", "grmhd_set_schedule", "grmhd_cfl_dt_noalloc", "grmhd_timing", "grmhd_timing_report", "grmhd_strerror", "grmhd_destroy")
 
 
 def load_library(path=LIB_PATH):
@@ -123,6 +123,7 @@ def load_library(path=LIB_PATH):
         "grmhd_vjp_workspace_bytes": (C.c_size_t, [G, P]),
         "grmhd_step_vjp": (C.c_int, [vp, vp, C.c_double, vp, vp, dp, vp, C.c_size_t]),
         "grmhd_set_schedule": (C.c_int, [vp, C.c_int, C.c_int]),
+        "grmhd_cfl_dt_noalloc": (C.c_int, [G, M, P, vp, dp, vp]),
         "grmhd_timing": (C.c_int, [vp, C.c_int]),
         "grmhd_timing_report": (C.c_int, [vp, dp, ip, C.c_int]),
         "grmhd_strerror": (C.c_char_p, [C.c_int]),
@@ -181,6 +182,23 @@ def make_grid(spec):
     for i in range(6):
         g.bc[i] = int(spec.bc[i])
     return g
+
+
+def cfl_dt_noalloc(spec, gamma_ad, prims, recon=RECON_WENO5, cfl=0.9, stream=None, **kw):
+    """CFL step of a device prims tensor without a context or any allocation
+    (grmhd_cfl_dt_noalloc); keyword options as for Grmhd."""
+    grid = make_grid(spec)
+    metric = grmhd_metric(int(spec.metric), float(spec.a), float(spec.hslope))
+    params = make_params(gamma_ad, cfl, kw.pop("weno_eps", 1e-26), kw.pop("newton_tol", 1e-14),
+                         kw.pop("newton_maxit", 30), recon, kw.pop("precision", PREC_FP64),
+                         kw.pop("inverter", INV_1DW), kw.pop("kastaun_wmax", 1e3), **kw)
+    if prims.dtype != torch.float64:
+        raise GrmhdError("float64 prims expected")
+    st = stream if stream is not None else torch.cuda.current_stream(prims.device)
+    out = C.c_double()
+    _check(lib().grmhd_cfl_dt_noalloc(C.byref(grid), C.byref(metric), C.byref(params), _ptr(prims),
+                                      C.byref(out), C.c_void_p(st.cuda_stream)))
+    return out.value
 
 
 class Grmhd:
