@@ -51,7 +51,8 @@ class Cfg(C.Structure):
                 ("rho_min_geom", C.c_double), ("u_min_geom", C.c_double),
                 ("bsq_over_rho_max", C.c_double), ("bsq_over_u_max", C.c_double),
                 ("u_over_rho_max", C.c_double), ("gamma_max", C.c_double),
-                ("fofc", C.c_int), ("ct", C.c_int), ("integrator", C.c_int)]
+                ("fofc", C.c_int), ("ct", C.c_int), ("integrator", C.c_int),
+                ("tau_r", C.c_double), ("chi_emhd", C.c_double), ("nu_emhd", C.c_double)]
 
 INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 RECON_DONOR = 2
@@ -96,6 +97,9 @@ def _declare(lib):
     lib.orc_point_floors.argtypes = [P, _D, C.c_double, C.c_double]
     lib.orc_point_floors.restype = C.c_int
     lib.orc_last_stats.argtypes = [C.POINTER(C.c_longlong)]
+    lib.orc_run_emhd.argtypes = [P, _D, _D, C.c_double, C.c_int, _D]
+    lib.orc_run_emhd.restype = C.c_long
+    lib.orc_cons_emhd.argtypes = [P, _D, _D, _D]
     lib.orc_run_face.argtypes = [P, _D, _D, C.c_double, C.c_int, _D, _I]
     lib.orc_run_face.restype = C.c_long
     lib.orc_face_divb.argtypes = [P, _D, _D, _D]
@@ -143,7 +147,8 @@ def lib(counting=False, fma=False):
 
 def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
         newton_maxit=30, cfl=0.9, nthreads=None, inverter=INV_1DW, kastaun_wmax=1e3,
-        floors=False, fofc=False, ct=CT_FLUX, integrator=INTEG_SSPRK2, **floor_params):
+        floors=False, fofc=False, ct=CT_FLUX, integrator=INTEG_SSPRK2, tau_r=1.0, chi_emhd=0.0,
+        nu_emhd=0.0, **floor_params):
     c = Cfg()
     c.n1, c.n2, c.n3 = grid.n1, grid.n2, grid.n3
     c.x1min, c.x1max = grid.x1min, grid.x1max
@@ -160,6 +165,7 @@ def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
     c.floors, c.fofc = int(bool(floors)), int(bool(fofc))
     c.ct = int(ct)
     c.integrator = int(integrator)
+    c.tau_r, c.chi_emhd, c.nu_emhd = float(tau_r), float(chi_emhd), float(nu_emhd)
     fp = dict(FLOOR_DEFAULTS)
     for k, v in floor_params.items():
         if k not in fp:
@@ -186,6 +192,28 @@ def run(c, prims, dt, nsteps=1, counting=False, flags=False, fma=False):
     if flags:
         return P, int(fails), dts, fl
     return P, int(fails), dts
+
+
+def run_emhd(c, prims, extra, dt, nsteps=1, fma=False):
+    """Extended GRMHD (predictor-corrector): advance copies of prims and of
+    the extra variables ([2][padded]: rescaled heat flux and pressure
+    anisotropy) with the closure constants c.tau_r, c.chi_emhd, c.nu_emhd;
+    returns (prims, extra, fails, dts)."""
+    P = np.ascontiguousarray(prims, dtype=np.float64).copy()
+    X = np.ascontiguousarray(extra, dtype=np.float64).copy()
+    assert X.shape == (2,) + P.shape[1:]
+    dts = np.zeros(max(nsteps, 1))
+    fails = lib(fma=fma).orc_run_emhd(C.byref(c), _ptr(P), _ptr(X), float(dt), int(nsteps), _ptr(dts))
+    return P, X, int(fails), dts
+
+
+def cons_emhd(c, prims, extra):
+    """Conserved variables [10][padded] of Extended GRMHD at interior zones."""
+    P = np.ascontiguousarray(prims, dtype=np.float64)
+    X = np.ascontiguousarray(extra, dtype=np.float64)
+    out = np.zeros((10,) + P.shape[1:])
+    lib().orc_cons_emhd(C.byref(c), _ptr(P), _ptr(X), _ptr(out))
+    return out
 
 
 def run_face(c, prims, faces, dt, nsteps=1, flags=False, fma=False):

@@ -85,6 +85,7 @@ typedef struct {
   int ct;              // 0: Flux-CT; face-centred CT with 1: averaged, 2: upwinded edge EMFs
   int integrator;      // 0: SSPRK2; 1: predictor-corrector (half-step predictor, then the
                        // full step from U^n with the predicted state's rates); 2: RK1 (forward Euler)
+  double tau_r, chi_emhd, nu_emhd;  // Extended GRMHD closure constants (orc_run_emhd)
 } orc_cfg;
 }
 
@@ -487,9 +488,10 @@ inline real Vc(const std::vector<real>& a, const Grid& g, int v, int i, int j, i
 // then x3 over everything), so edge and corner ghosts are consistent.
 //   periodic: wrap;  outflow: copy the nearest interior zone (all prims);
 //   polar: mirror across the axis, flipping u~2 and B2;  frozen: untouched.
-void fill_ghosts(const Grid& g, std::vector<real>& P) {
+// nvar variables of array A; flip: bit v set flips variable v across a polar axis.
+void fill_ghosts_vars(const Grid& g, std::vector<real>& P, int nvar, unsigned flip_mask) {
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
-  for (int v = 0; v < NV; v++) {
+  for (int v = 0; v < nvar; v++) {
     // x1
     for (int k = 0; k < n3; k++)
       for (int j = 0; j < n2; j++)
@@ -501,7 +503,7 @@ void fill_ghosts(const Grid& g, std::vector<real>& P) {
           else if (g.c.bc[1] == BC_OUTFLOW) V(P, g, v, hi, j, k) = V(P, g, v, n1 - 1, j, k);
         }
     // x2
-    real flip = (v == U2 || v == B2) ? -1.0 : 1.0;
+    real flip = ((flip_mask >> v) & 1u) ? -1.0 : 1.0;
     for (int k = 0; k < n3; k++)
       for (int i = -NG; i < n1 + NG; i++)
         for (int m = 1; m <= NG; m++) {
@@ -526,42 +528,59 @@ void fill_ghosts(const Grid& g, std::vector<real>& P) {
   }
 }
 
+void fill_ghosts(const Grid& g, std::vector<real>& P) {
+  fill_ghosts_vars(g, P, NV, (1u << U2) | (1u << B2));
+}
+
 // ----------------------------------------------------------------- fluxes --
 
 // Left and right states at the lower face (along d) of zone (i, j, k).
 // Donor cell: the two zones' own values.
+// Left and right states at the face between zones -1 and 0 of the six
+// values q[0..5] = zones -3 .. +2 along the axis.
+void recon_one(const real q[6], int recon, real eps, real& qL, real& qR) {
+  if (recon == RECON_DONOR) {
+    qL = q[2];
+    qR = q[3];
+  } else if (recon == RECON_MC) {
+    qL = q[2] + 0.5 * mc_slope(q[1], q[2], q[3]);
+    qR = q[3] - 0.5 * mc_slope(q[2], q[3], q[4]);
+  } else if (recon == RECON_VL) {
+    qL = q[2] + 0.5 * vl_slope(q[1], q[2], q[3]);
+    qR = q[3] - 0.5 * vl_slope(q[2], q[3], q[4]);
+  } else if (recon == RECON_WENOZ) {
+    qL = wenoz(q[0], q[1], q[2], q[3], q[4], eps);
+    qR = wenoz(q[5], q[4], q[3], q[2], q[1], eps);
+  } else if (recon == RECON_MP5) {
+    qL = mp5(q[0], q[1], q[2], q[3], q[4]);
+    qR = mp5(q[5], q[4], q[3], q[2], q[1]);
+  } else if (recon == RECON_PPM) {
+    real l, r;
+    ppm_edges(q[0], q[1], q[2], q[3], q[4], l, r);  // zone -1: its right edge
+    qL = r;
+    ppm_edges(q[1], q[2], q[3], q[4], q[5], l, r);  // zone 0: its left edge
+    qR = l;
+  } else {
+    qL = weno5(q[0], q[1], q[2], q[3], q[4], eps);
+    qR = weno5(q[5], q[4], q[3], q[2], q[1], eps);
+  }
+}
+
+// Left and right states at the lower face (along d) of zone (i, j, k) of the
+// nvar variables of array A.  Donor cell: the two zones' own values.
+void reconstruct_vars(const Grid& g, const std::vector<real>& A, int nvar, int recon, int d, int i, int j,
+                      int k, real* qL, real* qR) {
+  int di = d == 1, dj = d == 2, dk = d == 3;
+  for (int v = 0; v < nvar; v++) {
+    real q[6];  // zones -3 .. +2 relative to (i, j, k) along d
+    for (int s = -3; s <= 2; s++) q[s + 3] = Vc(A, g, v, i + s * di, j + s * dj, k + s * dk);
+    recon_one(q, recon, g.c.weno_eps, qL[v], qR[v]);
+  }
+}
+
 void reconstruct(const Grid& g, const std::vector<real>& P, int recon, int d, int i, int j, int k,
                  real qL[NV], real qR[NV]) {
-  int di = d == 1, dj = d == 2, dk = d == 3;
-  for (int v = 0; v < NV; v++) {
-    real q[6];  // zones -3 .. +2 relative to (i, j, k) along d
-    for (int s = -3; s <= 2; s++) q[s + 3] = Vc(P, g, v, i + s * di, j + s * dj, k + s * dk);
-    if (recon == RECON_DONOR) {
-      qL[v] = q[2];
-      qR[v] = q[3];
-    } else if (recon == RECON_MC) {
-      qL[v] = q[2] + 0.5 * mc_slope(q[1], q[2], q[3]);
-      qR[v] = q[3] - 0.5 * mc_slope(q[2], q[3], q[4]);
-    } else if (recon == RECON_VL) {
-      qL[v] = q[2] + 0.5 * vl_slope(q[1], q[2], q[3]);
-      qR[v] = q[3] - 0.5 * vl_slope(q[2], q[3], q[4]);
-    } else if (recon == RECON_WENOZ) {
-      qL[v] = wenoz(q[0], q[1], q[2], q[3], q[4], g.c.weno_eps);
-      qR[v] = wenoz(q[5], q[4], q[3], q[2], q[1], g.c.weno_eps);
-    } else if (recon == RECON_MP5) {
-      qL[v] = mp5(q[0], q[1], q[2], q[3], q[4]);
-      qR[v] = mp5(q[5], q[4], q[3], q[2], q[1]);
-    } else if (recon == RECON_PPM) {
-      real l, r;
-      ppm_edges(q[0], q[1], q[2], q[3], q[4], l, r);  // zone -1: its right edge
-      qL[v] = r;
-      ppm_edges(q[1], q[2], q[3], q[4], q[5], l, r);  // zone 0: its left edge
-      qR[v] = l;
-    } else {
-      qL[v] = weno5(q[0], q[1], q[2], q[3], q[4], g.c.weno_eps);
-      qR[v] = weno5(q[5], q[4], q[3], q[2], q[1], g.c.weno_eps);
-    }
-  }
+  reconstruct_vars(g, P, NV, recon, d, i, j, k, qL, qR);
 }
 
 // Local Lax-Friedrichs flux at the lower d-face of zone (i, j, k):
@@ -1220,23 +1239,16 @@ bool qr_pivot_solve(real A[5][5], real b[5], real y[5]) {
   return true;
 }
 
-int u_to_p_implicit(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[NV], real P[NV]) {
-  for (int k = 0; k < 3; k++) P[B1 + k] = U[B1 + k] / G.gdet;
-  auto failed = [&]() {
-    for (int v = 0; v < 5; v++) P[v] = guess[v];
-    return 1;
-  };
-  const real B[3] = {P[B1], P[B2], P[B3]};
-  real scale = 0.0;
-  for (int k = 0; k < 5; k++)
-    if (fabs(U[k]) > scale) scale = fabs(U[k]);
-  if (!(scale > 0.0) || !isfinite((real)scale)) return failed();
+// The Newton iteration of the implicit solver on the five hydro prims x
+// from the guess x0 (both positive in rho and u): residual(x, R) fills the
+// scaled residual R[5].  Returns 0 with the root in x, 1 on failure.
+template <typename Res>
+int newton_hydro(const orc_cfg& c, const real x0[5], Res residual, real x[5]) {
   const real fl[5] = {0.0, 0.0, 1e-3, 1e-3, 1e-3};
-  real x[5];
-  for (int k = 0; k < 5; k++) x[k] = guess[k];
-  if (!(x[0] > 0.0) || !(x[1] > 0.0)) return failed();
+  for (int k = 0; k < 5; k++) x[k] = x0[k];
+  if (!(x[0] > 0.0) || !(x[1] > 0.0)) return 1;
   real R[5];
-  implicit_residual(c, G, x, B, U, scale, R);
+  residual(x, R);
   real r2 = 0.0;
   for (int k = 0; k < 5; k++) r2 += R[k] * R[k];
   bool conv = false;
@@ -1250,19 +1262,19 @@ int u_to_p_implicit(const orc_cfg& c, const Geom& G, const real U[NV], const rea
       for (int m = 0; m < 5; m++) xp[m] = x[m];
       xp[k] = x[k] + h;
       real Rp[5];
-      implicit_residual(c, G, xp, B, U, scale, Rp);
+      residual(xp, Rp);
       real hh = xp[k] - x[k];
       for (int m = 0; m < 5; m++) J[m][k] = (Rp[m] - R[m]) / hh;
     }
     real rhs[5], dx[5];
     for (int m = 0; m < 5; m++) rhs[m] = -R[m];
-    if (!qr_pivot_solve(J, rhs, dx)) return failed();
+    if (!qr_pivot_solve(J, rhs, dx)) return 1;
     real lam = 1.0, xn[5], Rn[5], rn2 = 0.0;
     bool ok = false;
     for (int ls = 0; ls <= 8; ls++) {
       for (int m = 0; m < 5; m++) xn[m] = x[m] + lam * dx[m];
       if (xn[0] > 0.0 && xn[1] > 0.0) {
-        implicit_residual(c, G, xn, B, U, scale, Rn);
+        residual(xn, Rn);
         rn2 = 0.0;
         for (int m = 0; m < 5; m++) rn2 += Rn[m] * Rn[m];
         ok = isfinite((real)rn2);
@@ -1272,7 +1284,7 @@ int u_to_p_implicit(const orc_cfg& c, const Geom& G, const real U[NV], const rea
       }
       if (ls < 8) lam = 0.5 * lam;
     }
-    if (!ok) return failed();
+    if (!ok) return 1;
     conv = true;
     for (int m = 0; m < 5; m++) {
       real ax = fabs(xn[m]);
@@ -1282,11 +1294,27 @@ int u_to_p_implicit(const orc_cfg& c, const Geom& G, const real U[NV], const rea
     }
     r2 = rn2;
   }
-  if (!conv) return failed();
-  for (int k = 0; k < 5; k++) {
-    if (!isfinite((real)x[k])) return failed();
-    P[k] = x[k];
-  }
+  if (!conv) return 1;
+  for (int k = 0; k < 5; k++)
+    if (!isfinite((real)x[k])) return 1;
+  return 0;
+}
+
+int u_to_p_implicit(const orc_cfg& c, const Geom& G, const real U[NV], const real guess[NV], real P[NV]) {
+  for (int k = 0; k < 3; k++) P[B1 + k] = U[B1 + k] / G.gdet;
+  auto failed = [&]() {
+    for (int v = 0; v < 5; v++) P[v] = guess[v];
+    return 1;
+  };
+  const real B[3] = {P[B1], P[B2], P[B3]};
+  real scale = 0.0;
+  for (int k = 0; k < 5; k++)
+    if (fabs(U[k]) > scale) scale = fabs(U[k]);
+  if (!(scale > 0.0) || !isfinite((real)scale)) return failed();
+  real x[5];
+  auto res = [&](const real xx[5], real R[5]) { implicit_residual(c, G, xx, B, U, scale, R); };
+  if (newton_hydro(c, guess, res, x)) return failed();
+  for (int k = 0; k < 5; k++) P[k] = x[k];
   return 0;
 }
 
@@ -1671,6 +1699,321 @@ void store(const Grid& g, const std::vector<real>& src, double* dst) {
 
 }  // namespace
 
+// ------------------------------------------------------- Extended GRMHD --
+//
+// Extended GRMHD (Implicit Solver and Extended Theory section, EGRMHD
+// subsection, after Chandra et al. 2015 in the variables of Foucart et al.
+// 2016): two more zone-centred variables, the rescaled heat flux and
+// pressure anisotropy
+//   X0 = qt  = q  (tau_R / (chi rho Theta^2))^(1/2),
+//   X1 = dPt = dP (tau_R / (nu rho Theta))^(1/2),     Theta = p / rho.
+// The stress-energy tensor gains q^mu u_nu + q_nu u^mu + Pi^mu_nu with
+// q^mu = q bh^mu, bh = b / |b|, Pi^mu_nu = -dP (bh^mu bh_nu - h^mu_nu / 3),
+// h^mu_nu = delta^mu_nu + u^mu u_nu (both taken as zero where b^2 = 0), and
+//   d_mu(sqrt(-g) X u^mu) = sqrt(-g) [-(X - Xtarget) / tau_R + (X / 2) div u].
+// Readings where the paper defers to the cited papers:
+//   * tau_R, chi, nu are constants;
+//   * the targets are the Chandra et al. closure
+//       q0  = -rho chi bh^mu (d_mu Theta + Theta a_mu),  a_mu = u^nu nabla_nu u_mu,
+//       dP0 = 3 rho nu (bh^mu bh^nu nabla_mu u_nu - div u / 3),
+//     rescaled like the variables, from the stage's explicit state with
+//     centred spatial differences, the time derivatives in them left out;
+//   * div u = d_t u^t + d_i(sqrt(-g) u^i) / sqrt(-g): the spatial part from
+//     the explicit state, the time part (u^t(new) - u^t(step start)) / h in
+//     the new state, like the relaxation -X / tau_R and the X multiplying
+//     div u (the implicit terms);
+//   * the LLF signal speeds are the ideal fast-magnetosonic ones.
+// The step is the predictor-corrector, the integrator the paper allows for
+// a semi-implicit theory: h = dt/2 from the step's state, then h = dt from
+// it again with the explicit rates of the predicted state.  Per zone each
+// stage solves U(P, X) = U^n + h (explicit rate) + h (implicit sources) with
+// the implicit solver's Newton on the five hydro prims: given the hydro
+// state the two X equations are linear in X and are solved for X within
+// every residual evaluation (the root of the joint seven-variable system).
+const int NX = 2;
+
+struct EmhdPar {
+  real tau, chi, nu;
+};
+
+// Physical q and dP of the rescaled variables X.
+void emhd_unscale(const real P[NV], real gam, const EmhdPar& e, const real X[NX], real& q, real& dP) {
+  const real theta = (gam - 1.0) * P[UU] / P[RHO];
+  q = X[0] * theta * sqrt(e.chi * P[RHO] / e.tau);
+  dP = X[1] * sqrt(e.nu * P[RHO] * theta / e.tau);
+}
+
+// Mixed T^mu_nu of Extended GRMHD.
+real tmunu_emhd(const real P[NV], const FluidState& S, real gam, real q, real dP, int mu, int nu) {
+  const real t = tmunu(P, S, gam, mu, nu);
+  if (!(S.bsq > 0.0) || (q == 0.0 && dP == 0.0)) return t;
+  const real bm = S.bcon[mu] / sqrt(S.bsq), bn = S.bcov[nu] / sqrt(S.bsq);
+  const real h = (mu == nu ? 1.0 : 0.0) + S.ucon[mu] * S.ucov[nu];
+  return t + q * bm * S.ucov[nu] + q * bn * S.ucon[mu] - dP * (bm * bn - h / 3.0);
+}
+
+// Conserved variables (d = 0) or fluxes along x^d of the ten variables:
+// sqrt(-g) (rho u^d, T^d_t + rho u^d, T^d_i, b^k u^d - b^d u^k, X u^d).
+void prim_to_flux_emhd(const real P[NV], const real X[NX], const FluidState& S, const Geom& G, real gam,
+                       const EmhdPar& e, int d, real F[NV + NX]) {
+  real q, dP;
+  emhd_unscale(P, gam, e, X, q, dP);
+  F[RHO] = G.gdet * P[RHO] * S.ucon[d];
+  F[UU] = G.gdet * (tmunu_emhd(P, S, gam, q, dP, d, 0) + P[RHO] * S.ucon[d]);
+  for (int i = 1; i < 4; i++) F[U1 + i - 1] = G.gdet * tmunu_emhd(P, S, gam, q, dP, d, i);
+  for (int k = 1; k < 4; k++) {
+    if (d == 0)
+      F[B1 + k - 1] = G.gdet * P[B1 + k - 1];
+    else
+      F[B1 + k - 1] = G.gdet * (S.bcon[k] * S.ucon[d] - S.bcon[d] * S.ucon[k]);
+  }
+  for (int n = 0; n < NX; n++) F[NV + n] = G.gdet * X[n] * S.ucon[d];
+}
+
+// Geometric source sqrt(-g) T^k_l Gamma^l_{nu k} with the extended T.
+void source_point_emhd(const Geom& G, const real* cn, real gam, const EmhdPar& e, const real P[NV],
+                       const real X[NX], real S[NV]) {
+  FluidState st;
+  fluid_state(P, G, st);
+  real q, dP;
+  emhd_unscale(P, gam, e, X, q, dP);
+  real T[4][4];
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) T[m][n] = tmunu_emhd(P, st, gam, q, dP, m, n);
+  for (int v = 0; v < NV; v++) S[v] = 0.0;
+  for (int nu = 0; nu < 4; nu++) {
+    real s = 0.0;
+    for (int k = 0; k < 4; k++)
+      for (int l = 0; l < 4; l++) s += T[k][l] * cn[l * 16 + nu * 4 + k];
+    S[UU + nu] = G.gdet * s;
+  }
+}
+
+// LLF flux of the ten variables at the lower d-face of zone (i, j, k).
+void face_flux_emhd(const Grid& g, const std::vector<real>& P, const std::vector<real>& X, const EmhdPar& e,
+                    int d, int i, int j, int k, real F[NV + NX]) {
+  if (g.pole_face(d, j)) {
+    for (int v = 0; v < NV + NX; v++) F[v] = 0.0;
+    return;
+  }
+  real qL[NV], qR[NV], xL[NX], xR[NX];
+  reconstruct(g, P, g.c.recon, d, i, j, k, qL, qR);
+  reconstruct_vars(g, X, NX, g.c.recon, d, i, j, k, xL, xR);
+  const Geom& G = g.face_geom(d, i, j);
+  FluidState SL, SR;
+  fluid_state(qL, G, SL);
+  fluid_state(qR, G, SR);
+  real FL[NV + NX], FR[NV + NX], UL[NV + NX], UR[NV + NX];
+  prim_to_flux_emhd(qL, xL, SL, G, g.c.gam, e, d, FL);
+  prim_to_flux_emhd(qR, xR, SR, G, g.c.gam, e, d, FR);
+  prim_to_flux_emhd(qL, xL, SL, G, g.c.gam, e, 0, UL);
+  prim_to_flux_emhd(qR, xR, SR, G, g.c.gam, e, 0, UR);
+  real cpl, cml, cpr, cmr;
+  vchar(qL, SL, G, g.c.gam, d, cpl, cml);
+  vchar(qR, SR, G, g.c.gam, d, cpr, cmr);
+  real cmax = 0.0;
+  if (cpl > cmax) cmax = cpl;
+  if (cpr > cmax) cmax = cpr;
+  if (-cml > cmax) cmax = -cml;
+  if (-cmr > cmax) cmax = -cmr;
+  for (int v = 0; v < NV + NX; v++) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * cmax * (UR[v] - UL[v]);
+}
+
+// Fluxes on the faces of compute_fluxes: the eight ideal slots to F, the
+// two X slots to FX.
+void compute_fluxes_emhd(const Grid& g, const std::vector<real>& P, const std::vector<real>& X,
+                         const EmhdPar& e, std::vector<real> F[3], std::vector<real> FX[3]) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  for (int d = 1; d <= 3; d++) {
+    int lo[3] = {-1, -1, -1}, hi[3] = {n1, n2, n3};  // inclusive
+    lo[d - 1] = 0;
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads)
+    for (int k = lo[2]; k <= hi[2]; k++)
+      for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+          real f[NV + NX];
+          face_flux_emhd(g, P, X, e, d, i, j, k, f);
+          for (int v = 0; v < NV; v++) V(F[d - 1], g, v, i, j, k) = f[v];
+          for (int n = 0; n < NX; n++) V(FX[d - 1], g, n, i, j, k) = f[NV + n];
+        }
+  }
+}
+
+// Targets Xtarget and the spatial part of div u at zone (i, j, k) from the
+// explicit state P (ghosts filled).
+void emhd_targets(const Grid& g, const std::vector<real>& P, const EmhdPar& e, int i, int j, int k,
+                  real Xt[NX], real& divu_sp) {
+  const real gam = g.c.gam;
+  auto state = [&](int ii, int jj, int kk, FluidState& S, real& theta) {
+    real p[NV];
+    for (int v = 0; v < NV; v++) p[v] = Vc(P, g, v, ii, jj, kk);
+    fluid_state(p, g.gC[g.id2(ii, jj)], S);
+    theta = (gam - 1.0) * p[UU] / p[RHO];
+  };
+  FluidState S0;
+  real th0;
+  state(i, j, k, S0, th0);
+  const Geom& G = g.gC[g.id2(i, j)];
+  const real* cn = &g.conn[g.id2(i, j) * 64];
+  real dth[3], du[3][4], dgu[3];  // d_a Theta, d_a u_nu, d_a (sqrt(-g) u^a)
+  for (int a = 0; a < 3; a++) {
+    dth[a] = dgu[a] = 0.0;
+    for (int nu = 0; nu < 4; nu++) du[a][nu] = 0.0;
+    if (g.n[a] == 1) continue;
+    const int di = a == 0, dj = a == 1, dk = a == 2;
+    FluidState Sp, Sm;
+    real thp, thm;
+    state(i + di, j + dj, k + dk, Sp, thp);
+    state(i - di, j - dj, k - dk, Sm, thm);
+    const real h2 = 2.0 * g.dx[a];
+    dth[a] = (thp - thm) / h2;
+    for (int nu = 0; nu < 4; nu++) du[a][nu] = (Sp.ucov[nu] - Sm.ucov[nu]) / h2;
+    dgu[a] = (g.gC[g.id2(i + di, j + dj)].gdet * Sp.ucon[a + 1] -
+              g.gC[g.id2(i - di, j - dj)].gdet * Sm.ucon[a + 1]) / h2;
+  }
+  divu_sp = ((dgu[0] + dgu[1]) + dgu[2]) / G.gdet;
+  Xt[0] = Xt[1] = 0.0;
+  if (!(S0.bsq > 0.0)) return;
+  real bh[4];
+  for (int m = 0; m < 4; m++) bh[m] = S0.bcon[m] / sqrt(S0.bsq);
+  // a_nu = u^i d_i u_nu - Gamma^l_{m nu} u^m u_l
+  real acc[4];
+  for (int nu = 0; nu < 4; nu++) {
+    real s = 0.0;
+    for (int a = 0; a < 3; a++) s += S0.ucon[a + 1] * du[a][nu];
+    for (int l = 0; l < 4; l++)
+      for (int m = 0; m < 4; m++) s -= cn[l * 16 + m * 4 + nu] * S0.ucon[m] * S0.ucov[l];
+    acc[nu] = s;
+  }
+  real gq = 0.0;  // bh^mu (d_mu Theta + Theta a_mu)
+  for (int a = 0; a < 3; a++) gq += bh[a + 1] * dth[a];
+  for (int nu = 0; nu < 4; nu++) gq += th0 * bh[nu] * acc[nu];
+  real bbu = 0.0;  // bh^mu bh^nu nabla_mu u_nu
+  for (int a = 0; a < 3; a++)
+    for (int nu = 0; nu < 4; nu++) bbu += bh[a + 1] * bh[nu] * du[a][nu];
+  for (int m = 0; m < 4; m++)
+    for (int nu = 0; nu < 4; nu++)
+      for (int l = 0; l < 4; l++) bbu -= bh[m] * bh[nu] * cn[l * 16 + m * 4 + nu] * S0.ucov[l];
+  const real rho = Vc(P, g, RHO, i, j, k);
+  if (e.chi > 0.0) Xt[0] = -gq * sqrt(e.chi * rho * e.tau) / th0;
+  if (e.nu > 0.0) Xt[1] = 3.0 * (bbu - divu_sp / 3.0) * sqrt(e.nu * rho * e.tau / th0);
+}
+
+// One zone's implicit stage solve.  Urhs: U^n + h (explicit rate) for the
+// eight ideal slots; UrhsX: U^n_X + h (-flux divergence + sqrt(-g) Xtarget
+// / tau_R); ut_n: u^t of the step's starting state.  P, X: the stage input
+// in (the guess), the new state out; returns 1 (and keeps the guess's hydro
+// prims and X) on failure.  B^i = Urhs_B / sqrt(-g) in every case.
+int emhd_solve(const orc_cfg& c, const EmhdPar& e, const Geom& G, const real Urhs[NV], const real UrhsX[NX],
+               real divu_sp, real ut_n, real h, real P[NV], real X[NX]) {
+  for (int k = 0; k < 3; k++) P[B1 + k] = Urhs[B1 + k] / G.gdet;
+  const real B[3] = {P[B1], P[B2], P[B3]};
+  real scale = 0.0;
+  for (int k = 0; k < 5; k++)
+    if (fabs(Urhs[k]) > scale) scale = fabs(Urhs[k]);
+  if (!(scale > 0.0) || !isfinite((real)scale)) return 1;
+  // the X of hydro state x: gdet X (u^t + h/tau - (h/2) div u) = UrhsX
+  auto xsolve = [&](const real Pz[NV], const FluidState& S, real Xz[NX]) {
+    const real ut = S.ucon[0];
+    const real divu = divu_sp + (ut - ut_n) / h;
+    const real coef = G.gdet * ut + h * G.gdet / e.tau - 0.5 * h * G.gdet * divu;
+    for (int n = 0; n < NX; n++) Xz[n] = UrhsX[n] / coef;
+    (void)Pz;
+  };
+  auto res = [&](const real x[5], real R[5]) {
+    const real Pz[NV] = {x[0], x[1], x[2], x[3], x[4], B[0], B[1], B[2]};
+    FluidState S;
+    fluid_state(Pz, G, S);
+    real Xz[NX], U[NV + NX];
+    xsolve(Pz, S, Xz);
+    prim_to_flux_emhd(Pz, Xz, S, G, c.gam, e, 0, U);
+    for (int k = 0; k < 5; k++) R[k] = (U[k] - Urhs[k]) / scale;
+  };
+  real x[5];
+  if (newton_hydro(c, P, res, x)) return 1;
+  real Pn[NV] = {x[0], x[1], x[2], x[3], x[4], B[0], B[1], B[2]};
+  FluidState S;
+  fluid_state(Pn, G, S);
+  real Xn[NX];
+  xsolve(Pn, S, Xn);
+  for (int n = 0; n < NX; n++)
+    if (!isfinite((real)Xn[n])) return 1;
+  for (int k = 0; k < 5; k++) P[k] = x[k];
+  for (int n = 0; n < NX; n++) X[n] = Xn[n];
+  return 0;
+}
+
+// One predictor-corrector step of Extended GRMHD (Flux-CT for the field).
+long step_emhd(const Grid& g, const EmhdPar& e, std::vector<real>& P, std::vector<real>& X, real dt) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  std::vector<real> F[3], FX[3];
+  for (int d = 0; d < 3; d++) {
+    F[d].assign(NV * g.nz, 0.0);
+    FX[d].assign(NX * g.nz, 0.0);
+  }
+  std::vector<real> Un(NV * g.nz, 0.0), UnX(NX * g.nz, 0.0), utn(g.nz, 0.0);
+  std::vector<real> P1 = P, X1 = X;
+  long fails = 0;
+  for (int stage = 0; stage < 2; stage++) {
+    std::vector<real>& Pin = stage == 0 ? P : P1;
+    std::vector<real>& Xin = stage == 0 ? X : X1;
+    fill_ghosts(g, Pin);
+    fill_ghosts_vars(g, Xin, NX, 0u);
+    compute_fluxes_emhd(g, Pin, Xin, e, F, FX);
+    flux_ct(g, F);
+    const real h = stage == 0 ? 0.5 * dt : dt;
+    std::vector<real> Pout = Pin, Xout = Xin;
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads) reduction(+ : fails)
+    for (int k = 0; k < n3; k++)
+      for (int j = 0; j < n2; j++)
+        for (int i = 0; i < n1; i++) {
+          const Geom& G = g.gC[g.id2(i, j)];
+          real p[NV], x[NX];
+          for (int v = 0; v < NV; v++) p[v] = Vc(Pin, g, v, i, j, k);
+          for (int n = 0; n < NX; n++) x[n] = Vc(Xin, g, n, i, j, k);
+          if (stage == 0) {  // U^n and u^t of the step's state
+            FluidState S;
+            fluid_state(p, G, S);
+            real u0[NV + NX];
+            prim_to_flux_emhd(p, x, S, G, g.c.gam, e, 0, u0);
+            for (int v = 0; v < NV; v++) V(Un, g, v, i, j, k) = u0[v];
+            for (int n = 0; n < NX; n++) V(UnX, g, n, i, j, k) = u0[NV + n];
+            utn[g.id(i, j, k)] = S.ucon[0];
+          }
+          real Sg[NV];
+          source_point_emhd(G, &g.conn[g.id2(i, j) * 64], g.c.gam, e, p, x, Sg);
+          real Xt[NX], divu_sp;
+          emhd_targets(g, Pin, e, i, j, k, Xt, divu_sp);
+          real Urhs[NV], UrhsX[NX];
+          for (int v = 0; v < NV; v++) {
+            real d1 = (Vc(F[0], g, v, i + 1, j, k) - Vc(F[0], g, v, i, j, k)) / g.dx[0];
+            real d2 = (Vc(F[1], g, v, i, j + 1, k) - Vc(F[1], g, v, i, j, k)) / g.dx[1];
+            real d3 = (Vc(F[2], g, v, i, j, k + 1) - Vc(F[2], g, v, i, j, k)) / g.dx[2];
+            const real L = -((d1 + d2) + d3) + Sg[v];
+            Urhs[v] = Vc(Un, g, v, i, j, k) + h * L;
+          }
+          for (int n = 0; n < NX; n++) {
+            real d1 = (Vc(FX[0], g, n, i + 1, j, k) - Vc(FX[0], g, n, i, j, k)) / g.dx[0];
+            real d2 = (Vc(FX[1], g, n, i, j + 1, k) - Vc(FX[1], g, n, i, j, k)) / g.dx[1];
+            real d3 = (Vc(FX[2], g, n, i, j, k + 1) - Vc(FX[2], g, n, i, j, k)) / g.dx[2];
+            UrhsX[n] = Vc(UnX, g, n, i, j, k) + h * (-((d1 + d2) + d3) + G.gdet * Xt[n] / e.tau);
+          }
+          const int f = emhd_solve(g.c, e, G, Urhs, UrhsX, divu_sp, utn[g.id(i, j, k)], h, p, x);
+          fails += f;
+          for (int v = 0; v < NV; v++) V(Pout, g, v, i, j, k) = p[v];
+          for (int n = 0; n < NX; n++) V(Xout, g, n, i, j, k) = x[n];
+        }
+    if (stage == 0) {
+      P1 = Pout;
+      X1 = Xout;
+    } else {
+      P = Pout;
+      X = Xout;
+    }
+  }
+  return fails;
+}
+
 // ---------------------------------------------------------------- C ABI ----
 
 extern "C" {
@@ -1698,6 +2041,53 @@ long orc_run(const orc_cfg* c, double* prims, double dt, int nsteps, double* dts
   fill_ghosts(g, P);
   store(g, P, prims);
   return fails;
+}
+
+// Extended GRMHD (predictor-corrector, Flux-CT): advance the padded prims
+// and the padded extra variables x = double[2][padded] (qt, dPt) in place by
+// nsteps steps of size dt (dt <= 0: the ideal CFL dt before each step).
+// Returns the number of zone solves that failed.
+long orc_run_emhd(const orc_cfg* c, double* prims, double* extra, double dt, int nsteps, double* dts) {
+  Grid g(*c);
+  const EmhdPar e{c->tau_r, c->chi_emhd, c->nu_emhd};
+  std::vector<real> P, X(NX * g.nz);
+  load(g, prims, P);
+  for (long q = 0; q < NX * g.nz; q++) X[q] = extra[q];
+  long fails = 0;
+  for (int s = 0; s < nsteps; s++) {
+    real h = dt;
+    if (dt <= 0.0) {
+      fill_ghosts(g, P);
+      h = estimate_dt(g, P);
+    }
+    if (dts) dts[s] = (double)h;
+    fails += step_emhd(g, e, P, X, h);
+  }
+  fill_ghosts(g, P);
+  fill_ghosts_vars(g, X, NX, 0u);
+  store(g, P, prims);
+  for (long q = 0; q < NX * g.nz; q++) extra[q] = (double)X[q];
+  return fails;
+}
+
+// Conserved variables of Extended GRMHD (ten slots: the ideal eight, then
+// sqrt(-g) X u^t) at interior zone centres of prims and extra.
+void orc_cons_emhd(const orc_cfg* c, const double* prims, const double* extra, double* cons) {
+  Grid g(*c);
+  const EmhdPar e{c->tau_r, c->chi_emhd, c->nu_emhd};
+  for (int k = 0; k < c->n3; k++)
+    for (int j = 0; j < c->n2; j++)
+      for (int i = 0; i < c->n1; i++) {
+        const long q = g.id(i, j, k);
+        real p[NV], x[NX], u[NV + NX];
+        for (int v = 0; v < NV; v++) p[v] = prims[v * g.nz + q];
+        for (int n = 0; n < NX; n++) x[n] = extra[n * g.nz + q];
+        const Geom& G = g.gC[g.id2(i, j)];
+        FluidState S;
+        fluid_state(p, G, S);
+        prim_to_flux_emhd(p, x, S, G, g.c.gam, e, 0, u);
+        for (int v = 0; v < NV + NX; v++) cons[v * g.nz + q] = (double)u[v];
+      }
 }
 
 // Face-centred CT (cfg ct = 1 or 2): as orc_run, with the face fields

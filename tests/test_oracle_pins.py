@@ -1456,3 +1456,114 @@ def test_corner_divergence_divides_by_sqrt_minus_g_at_the_corner_kerr():
         assert np.allclose(got[k], expect, rtol=1e-13, atol=0.0)
     assert mx == pytest.approx(expect.max(), rel=1e-13)
     assert mean == pytest.approx(expect.mean(), rel=1e-13)
+
+
+# ------------------------------------------------------------ Extended GRMHD
+
+def _emhd_cfg(g, gam, recon=RECON_MC, tau_r=1.0, chi=0.0, nu=0.0, **kw):
+    return oracle.cfg(g, gam=gam, recon=recon, integrator=oracle.INTEG_PC, tau_r=tau_r, chi_emhd=chi,
+                      nu_emhd=nu, **kw)
+
+
+@pytest.mark.parametrize("which", ["pressure_anisotropy", "heat_flux"])
+def test_emhd_uniform_state_relaxes_at_rate_one_over_tau(which):
+    """A uniform state at rest in flat space has no gradients, so both
+    targets vanish, u^t = 1 stays fixed and div u = 0: each stage leaves
+    only the implicit relaxation, X_new (1 + h / tau_R) = X^n, and the
+    corrector (h = dt, from the step's state) gives X after n steps equal to
+    X0 (1 + dt/tau_R)^-n, which tends to X0 exp(-t/tau_R) at first order in
+    dt.  At rest the anisotropic terms carry no energy or momentum density
+    (b^t = 0 with B along x1; with B = 0 the heat flux has no direction and
+    vanishes), so the hydro state does not change at all."""
+    g = GridSpec(6, 6, 1)
+    P = np.zeros((8, 7, 12, 12))
+    P[0], P[1] = 1.0, 0.8
+    X = np.zeros((2,) + P.shape[1:])
+    if which == "pressure_anisotropy":
+        P[5], X[1], slot = 0.5, 0.3, 1
+    else:
+        X[0], slot = 0.2, 0
+    tau = 0.7
+    c = _emhd_cfg(g, 4.0 / 3.0, tau_r=tau, chi=0.4, nu=0.3)
+    x0 = X[slot, 3, 3, 3]
+    errs = []
+    for n in (10, 20, 40):
+        dt = 0.4 / n
+        out, Xo, fails, _ = oracle.run_emhd(c, P, X, dt, n)
+        assert fails == 0
+        assert np.array_equal(interior(out), interior(P))
+        got = interior(Xo)[slot]
+        assert np.allclose(got, x0 * (1.0 + dt / tau) ** -n, rtol=1e-13, atol=0.0)
+        assert not interior(Xo)[1 - slot].any()
+        errs.append(abs(got[0, 0, 0] - x0 * math.exp(-0.4 / tau)))
+    assert 1.9 < errs[0] / errs[1] < 2.1 and 1.9 < errs[1] / errs[2] < 2.1, errs
+
+
+@pytest.mark.parametrize("case", ["torus", "mode"])
+def test_emhd_without_its_terms_is_the_ideal_implicit_step(case):
+    """chi = nu = 0 and X = 0: the heat flux and anisotropy vanish, X stays
+    zero, and the Extended GRMHD step is the ideal predictor-corrector step
+    with the implicit solver's recovery, bit for bit."""
+    if case == "torus":
+        (g, P), gam, recon = fm_torus(16, 16, 4)[0:2], 13.0 / 9.0, RECON_WENO5
+    else:
+        (g, P), gam, recon = linear_mode("fast", 16, ndim=2)[0:2], 4.0 / 3.0, RECON_MC
+    X = np.zeros((2,) + P.shape[1:])
+    a, Xa, fa, dts = oracle.run_emhd(_emhd_cfg(g, gam, recon=recon), P, X, -1, 3)
+    b, fb, dtb = oracle.run(oracle.cfg(g, gam=gam, recon=recon, integrator=oracle.INTEG_PC,
+                                       inverter=oracle.INV_IMPLICIT), P, -1, 3)
+    assert fa == fb and np.array_equal(dts, dtb)
+    assert np.array_equal(interior(a), interior(b))
+    assert not Xa.any()
+
+
+def test_emhd_conserves_mass_energy_momentum_and_field():
+    """Periodic flat grid, the fast mode with seeded heat flux and pressure
+    anisotropy: the sums of the ideal conserved variables (now with the
+    extended stress-energy tensor) are unchanged to roundoff."""
+    g, P, _, _ = linear_mode("fast", 16, ndim=2)
+    rng = np.random.default_rng(3)
+    X = np.zeros((2,) + P.shape[1:])
+    X[:, 3:-3, 3:-3, 3:-3] = 0.01 * rng.standard_normal((2, 1, 16, 16))
+    c = _emhd_cfg(g, 4.0 / 3.0, tau_r=0.5, chi=0.3, nu=0.2)
+    U0 = interior(oracle.cons_emhd(c, P, X))
+    out, Xo, fails, _ = oracle.run_emhd(c, P, X, -1, 4)
+    assert fails == 0 and np.abs(interior(Xo)).max() > 1e-3
+    U1 = interior(oracle.cons_emhd(c, out, Xo))
+    for group in ([0], [1], [2, 3, 4], [5, 6, 7]):
+        scale = sum(np.abs(U0[v]).sum() for v in group)
+        for v in group:
+            assert abs(U1[v].sum() - U0[v].sum()) <= 1e-13 * scale, v
+
+
+def test_emhd_heat_conduction_follows_the_field():
+    """A hot spot in pressure balance (p uniform, Theta peaked) in a uniform
+    field along x1, heat conduction on (chi = 0.1, tau_R = 0.2; the heat
+    flux's signal speed (chi / tau_R)^(1/2) < 1), no viscosity: the heat
+    flux is along bh = x1, so the temperature excess spreads along x1 (its
+    second moment more than doubles in t = 0.28) while across the field its
+    second moment differs from the run without conduction by under 2 % of
+    the change along the field (the sound waves the conduction launches)."""
+    n = 48
+    g = GridSpec(n, n, 1)
+    x1, x2, _ = g.centers()
+    X2, X1 = np.meshgrid(x2, x1, indexing="ij")
+    gam, p0 = 4.0 / 3.0, 1.0 / 3.0
+    theta = p0 * (1 + 0.2 * np.exp(-((X1 - 0.5) ** 2 + (X2 - 0.5) ** 2) / 0.01))
+    P = np.zeros((8, 7, n + 6, n + 6))
+    P[0], P[1], P[5] = (p0 / theta)[None], p0 / (gam - 1), 1.0
+    X = np.zeros((2,) + P.shape[1:])
+
+    def moments(A):
+        I = interior(A)[:, 0]
+        d = (gam - 1) * I[1] / I[0] - p0
+        Y, Xg = np.meshgrid(x2[3:-3] - 0.5, x1[3:-3] - 0.5, indexing="ij")
+        return (d * Xg ** 2).sum() / d.sum(), (d * Y ** 2).sum() / d.sum()
+
+    sx0, sy0 = moments(P)
+    off, _, f0, _ = oracle.run_emhd(_emhd_cfg(g, gam, tau_r=0.2, chi=0.0), P, X, -1, 20)
+    on, _, f1, _ = oracle.run_emhd(_emhd_cfg(g, gam, tau_r=0.2, chi=0.1), P, X, -1, 20)
+    assert f0 == 0 and f1 == 0
+    (sx_off, sy_off), (sx_on, sy_on) = moments(off), moments(on)
+    assert sx_on > 2.0 * sx0 and abs(sx_off - sx0) < 0.01 * sx0
+    assert abs(sy_on - sy_off) < 0.02 * (sx_on - sx0)
