@@ -40,13 +40,23 @@ struct PointMetric {
 enum { G_COV = 0, G_CON = 10, G_DET = 20, G_ALPHA = 21, G_NF = 22 };
 enum { NCONN = 40 };  // Gamma^l_{mn}, m <= n
 
+// Both spacetimes of the library (flat space, and Kerr in modified
+// Kerr-Schild coordinates) have g_{2 mu} = g^{2 mu} = 0 for mu != 2: x2 is
+// orthogonal to the other coordinates, and the tables hold exact zeros
+// there.  Those six entries are set to the constant zero rather than loaded,
+// which gives the same values (and the same rounding of every expression
+// that reads them) while keeping them out of registers.
+__host__ __device__ constexpr bool x2_offdiag(int f) {
+  return f == sidx(0, 2) || f == sidx(1, 2) || f == sidx(2, 3);
+}
+
 template <typename R>
 __device__ __forceinline__ void load_metric(const double* __restrict__ tab, long plane, long q,
                                    PointMetric<R>& m) {
 #pragma unroll
   for (int f = 0; f < 10; f++) {
-    m.gcov[f] = (R)tab[(G_COV + f) * plane + q];
-    m.gcon[f] = (R)tab[(G_CON + f) * plane + q];
+    m.gcov[f] = x2_offdiag(f) ? (R)0 : (R)tab[(G_COV + f) * plane + q];
+    m.gcon[f] = x2_offdiag(f) ? (R)0 : (R)tab[(G_CON + f) * plane + q];
   }
   m.gdet = (R)tab[G_DET * plane + q];
   m.alpha = (R)tab[G_ALPHA * plane + q];

@@ -88,16 +88,68 @@ def test_adjoint_small_mc_and_weno():
     for recon in (RECON_MC, RECON_WENO5):
         rows, _, _, _ = adjoint_vs_fd(16, 2, recon, 6)
         assert np.median(rows[:, 2]) < 1e-6, rows
-        assert rows[:, 2].max() < 1e-4, rows
+        assert rows[:, 2].max() < 1e-5, rows
 
 
 def test_adjoint_torus64_mc_8_steps():
     """The 64^3 torus, MC, 8 steps, gradients w.r.t. the initial prims and
-    gamma, 20 seeded directions."""
+    gamma, 20 seeded directions: every direction within 1e-5 (measured
+    worst ~1e-6)."""
     rows, gP, gG, (grid, P, dt) = adjoint_vs_fd(64, 8, RECON_MC, 20)
     print("median rel", np.median(rows[:, 2]), "max rel", rows[:, 2].max(), "dL/dgamma", gG)
     assert np.median(rows[:, 2]) < 1e-6
-    assert (rows[:, 2] < 1e-4).mean() >= 0.9
+    assert rows[:, 2].max() < 1e-5, rows
+
+
+@pytest.mark.parametrize("recon", [RECON_MC, RECON_WENO5])
+def test_adjoint_three_dimensional_mode(recon):
+    """A state and directions that vary along x3: the fast mode with
+    k = 2 pi (1, 1, 1) on a flat periodic 16^3 box, 3 steps, loss
+    sum_{i < 5, k < 3} rho u (no symmetry in x3), directions
+    v_var = xi_var P0_var + eta_var (P_var - P0_var) (background and
+    perturbation scaled separately, so no extremum of any primitive moves and
+    no limiter leaves its branch).  An x3 transpose error in the adjoint moves
+    gradient between x3 neighbours, which these directions see."""
+    torch, gr, ag = _setup()
+    from workloads import linear_mode
+    g, P, _, info = linear_mode("fast", 16, ndim=3, kvec=(2 * np.pi, 2 * np.pi, 2 * np.pi))
+    gam = 4.0 / 3.0
+    P0 = np.array([1.0, 1.0, 0, 0, 0, 1.0, 0, 0])
+    s = gr.Grmhd(g, gam, recon=recon)
+    s.load(torch.from_numpy(P).cuda())
+    dt = s.dt()
+    nsteps = 3
+
+    def loss(A):
+        I = interior(A)
+        return float((I[0, :3, :, :5] * I[1, :3, :, :5]).sum())
+
+    x = torch.from_numpy(P).cuda().requires_grad_(True)
+    gt = torch.tensor(gam, dtype=torch.float64, device="cuda", requires_grad=True)
+    out = ag.run(x, gt, s, dt, nsteps)
+    I = out[:, NG:-NG, NG:-NG, NG:-NG]
+    (I[0, :3, :, :5] * I[1, :3, :, :5]).sum().backward()
+    gP, gG = x.grad.cpu().numpy(), float(gt.grad)
+    rng = np.random.default_rng(17)
+    h = 1e-6
+    rel = []
+    for q in range(6):
+        xi, eta = rng.normal(size=8), rng.normal(size=8)
+        v = np.zeros_like(P)
+        interior(v)[...] = (xi * P0)[:, None, None, None] + eta[:, None, None, None] * (interior(P) - P0[:, None, None, None])
+        vg = gam * rng.normal()
+        outs = []
+        for sgn in (1, -1):
+            t = gr.Grmhd(g, gam + sgn * h * vg, recon=recon)
+            t.load(torch.from_numpy(P + sgn * h * v).cuda())
+            for _ in range(nsteps):
+                t.step(dt)
+            outs.append(loss(t.prims().cpu().numpy()))
+        fd = (outs[0] - outs[1]) / (2 * h)
+        ad = float((gP * v).sum()) + gG * vg
+        rel.append(abs(fd - ad) / abs(fd))
+        print(f"3-D mode dir {q}: fd {fd:.12e} adjoint {ad:.12e} rel {rel[-1]:.2e}", flush=True)
+    assert np.median(rel) < 1e-6 and max(rel) < 1e-5, rel
 
 
 def test_adjoint_against_oracle_fd():
