@@ -142,6 +142,27 @@ typedef struct {
                          U^{n+1} = U^n + dt L(P*); RK1: forward Euler, one
                          stage per step.  PC and RK1 need Flux-CT without
                          floors, the correction or the implicit recovery. */
+  int egrmhd;         /* 1: Extended GRMHD (Implicit Solver and Extended Theory
+                         section): two more zone-centred variables, the
+                         rescaled heat flux qt = q (tau_R/(chi rho Theta^2))^1/2
+                         and pressure anisotropy dPt = dP (tau_R/(nu rho
+                         Theta))^1/2, Theta = p/rho, with their stress-energy
+                         terms q^mu u_nu + q_nu u^mu - dP (bh^mu bh_nu - h^mu_nu/3)
+                         (bh = b/|b|, h = delta + u u; none where b^2 = 0) and
+                         the damped evolution d_mu(X u^mu) = -(X - X0)/tau_R +
+                         (X/2) div u toward the Chandra et al. (2015) targets
+                         X0 (from centred spatial gradients of the stage's
+                         explicit state, time derivatives left out); div u's
+                         time part, the relaxation and X are implicit.  Each
+                         stage of the predictor-corrector (integrator must be
+                         PC) solves every zone for the hydro prims and X with
+                         the implicit solver's Newton (the X equations are
+                         linear given the hydro state and are solved within
+                         each residual); the inverter field is not used.
+                         FP64, Flux-CT, MC or WENO5, no floors or correction,
+                         single grids; extra state via grmhd_load_extended. */
+  double tau_r, chi_emhd, nu_emhd;  /* Extended GRMHD closure constants: tau_R > 0,
+                                       chi >= 0, nu >= 0 */
 } grmhd_params;
 
 /* Bytes of device workspace a context with this grid and parameters needs. */
@@ -159,6 +180,14 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
  * face-centred CT and faces loaded, the interior zones' B is then set to
  * their faces' mean. */
 int grmhd_load_prims(grmhd_ctx* ctx, const double* d_prims);
+
+/* Extended GRMHD only (E_STATE otherwise).  The two extra variables as
+ * float64 [2][n3+6][n2+6][n1+6] (device): the rescaled heat flux, then the
+ * rescaled pressure anisotropy.  load copies them into the state (zero after
+ * creation); get copies the state's out, ghosts filled (periodic, outflow
+ * and polar maps as for rho, no sign flips). */
+int grmhd_load_extended(grmhd_ctx* ctx, const double* d_extra);
+int grmhd_get_extended(grmhd_ctx* ctx, double* d_extra);
 
 /* Face-centred CT only (E_STATE otherwise).  Face fields: float64
  * [3][n3+6][n2+6][n1+6] (device), component d holding sqrt(-g) B^d on the
@@ -247,7 +276,8 @@ int grmhd_cons_to_prims(grmhd_ctx* ctx, const double* d_cons, const double* d_gu
  * unspecified.  The context's reconstruction is used; the first-order flux
  * correction is not applied (it depends on a provisional update), and with
  * face-centred CT the face fields are not read (these are the Flux-CT
- * fluxes of d_prims).  For testing and inspection. */
+ * fluxes of d_prims).  E_STATE for Extended GRMHD contexts.  For testing
+ * and inspection. */
 int grmhd_fluxes(grmhd_ctx* ctx, const double* d_prims, double* d_flux);
 
 /* Adjoint of one step (vector-Jacobian product), FP64 only.

@@ -70,6 +70,7 @@ struct Dev {
   int ct;             // GRMHD_CT_*: Flux-CT, or face-centred CT (averaged / upwinded EMFs)
   int floors;         // floors and ceilings after every inversion of a stage
   double rho_min_geom, u_min_geom, bsq_over_rho_max, bsq_over_u_max, u_over_rho_max, gamma_max;
+  double tau, chi, nu;  // Extended GRMHD closure constants
   SpaceTime st;
 };
 
@@ -1521,6 +1522,27 @@ enum { U_PLAIN = 0, U_PROVISIONAL = 2, U_FINAL = 3, U_STORE = 4 };
 // Counter slots of the context's counter array.
 enum { C_FAILS = 0, C_C2P = 1, C_FLOORS = 2, C_FOFC = 3, C_FLUID = 4, C_MARKS = 5 };
 
+// Rate of the zone field at padded index c from the edge EMFs (Flux-CT):
+// F1(B2) = (E3 + E3_{j+1})/2, F1(B3) = -(E2 + E2_{k+1})/2,
+// F2(B1) = -(E3 + E3_{i+1})/2, F2(B3) = (E1 + E1_{k+1})/2,
+// F3(B1) = (E2 + E2_{i+1})/2, F3(B2) = -(E1 + E1_{j+1})/2; normal ones zero.
+template <typename FT>
+__device__ __forceinline__ void ct_field_rate(const Dev& g, const FT* __restrict__ E1, const FT* __restrict__ E2,
+                                              const FT* __restrict__ E3, long c, double L[NVAR]) {
+#pragma clang fp contract(off)
+  const long si = 1, sj = g.s1, sk = g.plane;
+  auto e = [&](const FT* E, long o) { return (double)E[c + o]; };
+  double f1b2_p = 0.5 * (e(E3, si) + e(E3, si + sj)), f1b2_m = 0.5 * (e(E3, 0) + e(E3, sj));
+  double f1b3_p = -0.5 * (e(E2, si) + e(E2, si + sk)), f1b3_m = -0.5 * (e(E2, 0) + e(E2, sk));
+  double f2b1_p = -0.5 * (e(E3, sj) + e(E3, sj + si)), f2b1_m = -0.5 * (e(E3, 0) + e(E3, si));
+  double f2b3_p = 0.5 * (e(E1, sj) + e(E1, sj + sk)), f2b3_m = 0.5 * (e(E1, 0) + e(E1, sk));
+  double f3b1_p = 0.5 * (e(E2, sk) + e(E2, sk + si)), f3b1_m = 0.5 * (e(E2, 0) + e(E2, si));
+  double f3b2_p = -0.5 * (e(E1, sk) + e(E1, sk + sj)), f3b2_m = -0.5 * (e(E1, 0) + e(E1, sj));
+  L[B1] = -((f2b1_p - f2b1_m) / g.dx2 + (f3b1_p - f3b1_m) / g.dx3);
+  L[B2] = -((f1b2_p - f1b2_m) / g.dx1 + (f3b2_p - f3b2_m) / g.dx3);
+  L[B3] = -((f1b3_p - f1b3_m) / g.dx1 + (f2b3_p - f2b3_m) / g.dx2);
+}
+
 template <int STAGE, typename FT, bool RATE = false, int MODE = U_PLAIN, bool FACE = false,
           int INTEG = GRMHD_INTEG_SSPRK2>
 __device__ __forceinline__ void update_zone(const Dev& g, const double* __restrict__ Pin,
@@ -1560,20 +1582,8 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
       double d3 = ((double)F3[v * nz + c + sk] - (double)F3[v * nz + c]) / g.dx3;
       L[v] = -((d1 + d2) + d3) + (v == RHO ? 0.0 : S[v - 1]);
     }
-    // Flux-CT fluxes of B: F1(B2) = (E3 + E3_{j+1})/2, F1(B3) = -(E2 + E2_{k+1})/2,
-    // F2(B1) = -(E3 + E3_{i+1})/2, F2(B3) = (E1 + E1_{k+1})/2,
-    // F3(B1) = (E2 + E2_{i+1})/2, F3(B2) = -(E1 + E1_{j+1})/2; normal ones zero.
     if constexpr (!FACE) {
-    auto e = [&](const FT* E, long o) { return (double)E[c + o]; };
-    double f1b2_p = 0.5 * (e(E3, si) + e(E3, si + sj)), f1b2_m = 0.5 * (e(E3, 0) + e(E3, sj));
-    double f1b3_p = -0.5 * (e(E2, si) + e(E2, si + sk)), f1b3_m = -0.5 * (e(E2, 0) + e(E2, sk));
-    double f2b1_p = -0.5 * (e(E3, sj) + e(E3, sj + si)), f2b1_m = -0.5 * (e(E3, 0) + e(E3, si));
-    double f2b3_p = 0.5 * (e(E1, sj) + e(E1, sj + sk)), f2b3_m = 0.5 * (e(E1, 0) + e(E1, sk));
-    double f3b1_p = 0.5 * (e(E2, sk) + e(E2, sk + si)), f3b1_m = 0.5 * (e(E2, 0) + e(E2, si));
-    double f3b2_p = -0.5 * (e(E1, sk) + e(E1, sk + sj)), f3b2_m = -0.5 * (e(E1, 0) + e(E1, sj));
-    L[B1] = -((f2b1_p - f2b1_m) / g.dx2 + (f3b1_p - f3b1_m) / g.dx3);
-    L[B2] = -((f1b2_p - f1b2_m) / g.dx1 + (f3b2_p - f3b2_m) / g.dx3);
-    L[B3] = -((f1b3_p - f1b3_m) / g.dx1 + (f2b3_p - f2b3_m) / g.dx2);
+      ct_field_rate(g, E1, E2, E3, c, L);
     } else {
       L[B1] = L[B2] = L[B3] = 0.0;
     }
@@ -1920,6 +1930,7 @@ __global__ void __launch_bounds__(BLOCK) k_cons_to_prims(Dev g, Box box, const d
 
 #include "adjoint.hpp"
 #include "pack.hpp"
+#include "emhd.hpp"
 
 }  // namespace
 
@@ -1945,6 +1956,11 @@ struct grmhd_ctx {
   void* Ec[4] = {nullptr, nullptr, nullptr, nullptr};  // EMFs, then the mass-current scale
   bool faces_loaded = false;
   double* ustar = nullptr;    // implicit recovery: the stage's target conserved variables
+  // Extended GRMHD: extra variables of the state and of stage 1, their fluxes,
+  // U^n of them, their stage targets, u^t of the step's state and the
+  // spatial part of div u
+  double *X = nullptr, *X1 = nullptr, *FX[3] = {nullptr, nullptr, nullptr}, *VX = nullptr,
+         *xrhs = nullptr, *utn = nullptr, *divu = nullptr;
   double* pdt;              // CFL-rate partials left by the last stage-2 update
   bool rate_ready = false;  // pdt describes the current state (rate_n partials)
   bool ghosts_valid = false;  // the ghost zones of P hold the boundary conditions of its interior
@@ -2011,10 +2027,21 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
   if (p->integrator != GRMHD_INTEG_SSPRK2 &&
       (p->floors || p->fofc || p->ct != GRMHD_CT_FLUX || p->inverter == GRMHD_INV_IMPLICIT))
     return false;
+  // Extended GRMHD: the semi-implicit predictor-corrector of the plain FP64
+  // Flux-CT step with MC or WENO5
+  if (p->egrmhd != 0 && p->egrmhd != 1) return false;
+  if (p->egrmhd &&
+      (p->integrator != GRMHD_INTEG_PC || p->precision != GRMHD_PREC_FP64 ||
+       (p->recon != GRMHD_RECON_MC && p->recon != GRMHD_RECON_WENO5) || !(p->tau_r > 0.0) ||
+       !(p->chi_emhd >= 0.0) || !(p->nu_emhd >= 0.0) || !isfinite(p->tau_r) || !isfinite(p->chi_emhd) ||
+       !isfinite(p->nu_emhd)))
+    return false;
   return true;
 }
 
-size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, int ct, int inverter) {
+size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, const grmhd_params* prm) {
+  const int ct = prm->ct, inverter = prm->inverter;
+  const bool emhd = prm->egrmhd != 0;
   long nz = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * (g->n3 + 2 * NG);
   long plane = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG);
   Carve cv;
@@ -2045,10 +2072,28 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, int ct, int inverter
     }
     Ec[3] = cv.take<double>(base, nz);
   }
-  double* ustar = inverter == GRMHD_INV_IMPLICIT ? cv.take<double>(base, NVAR * nz) : nullptr;
+  double* ustar = inverter == GRMHD_INV_IMPLICIT || emhd ? cv.take<double>(base, NVAR * nz) : nullptr;
+  double *X = nullptr, *X1 = nullptr, *FX[3] = {}, *VX = nullptr, *xrhs = nullptr, *utn = nullptr,
+         *divu = nullptr;
+  if (emhd) {
+    X = cv.take<double>(base, 2 * nz);
+    X1 = cv.take<double>(base, 2 * nz);
+    for (int d = 0; d < 3; d++) FX[d] = cv.take<double>(base, 2 * nz);
+    VX = cv.take<double>(base, 2 * nz);
+    xrhs = cv.take<double>(base, 2 * nz);
+    utn = cv.take<double>(base, nz);
+    divu = cv.take<double>(base, nz);
+  }
   if (c) {
     c->mark = mark;
     c->ustar = ustar;
+    c->X = X;
+    c->X1 = X1;
+    for (int d = 0; d < 3; d++) c->FX[d] = FX[d];
+    c->VX = VX;
+    c->xrhs = xrhs;
+    c->utn = utn;
+    c->divu = divu;
     for (int d = 0; d < 3; d++) {
       c->phi[d] = phi[d];
       c->phi1[d] = phi1[d];
@@ -2328,6 +2373,52 @@ int stage(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double
   return floors ? stage_floors<STAGE, U_FINAL>(c, Pin, Pout, rate) : GRMHD_OK;
 }
 
+// One Extended GRMHD predictor-corrector stage from the ghost-filled prims
+// Pin and extra variables Xin (their ghosts filled here): fluxes of the ten
+// variables, the EMFs, the update pass, then the implicit pass, which with
+// rate leaves the CFL-rate partials of its prims.
+template <int STAGE>
+int emhd_stage(grmhd_ctx* c, const double* Pin, double* Xin, double* Pout, double* Xout, double dt,
+               const double* dt_dev, bool rate) {
+  const Dev& g = c->dev;
+  int rc;
+  if ((rc = launch(c, T_BC, k_bc_extra, blocks_for(ghost_count(g)), g, Xin))) return rc;
+  Sched b1 = make_sched(make_box(0, g.n1, -1, g.n2, -1, g.n3), c->kg_flux);
+  Sched b2 = make_sched(make_box(-1, g.n1, 0, g.n2, -1, g.n3), c->kg_flux);
+  Sched b3 = make_sched(make_box(-1, g.n1, -1, g.n2, 0, g.n3), c->kg_flux);
+  const unsigned n1 = round8(blocks_for(b1)), n2 = round8(blocks_for(b2)), n3 = blocks_for(b3);
+  double* F1 = (double*)c->F[0];
+  double* F2 = (double*)c->F[1];
+  double* F3 = (double*)c->F[2];
+  auto flux = [&](auto kernel) {
+    return launch(c, T_FLUX, kernel, n1 + n2 + n3, g, b1, b2, b3, n1, n2, n3, Pin, (const double*)Xin,
+                  (const double*)c->tabF1, (const double*)c->tabF2, (const double*)c->tabC, F1, F2, F3, c->FX[0],
+                  c->FX[1], c->FX[2]);
+  };
+  rc = c->params.recon == GRMHD_RECON_MC ? flux(k_flux_emhd<GRMHD_RECON_MC>) : flux(k_flux_emhd<GRMHD_RECON_WENO5>);
+  if (rc) return rc;
+  if ((rc = stage_emfs<double>(c, (const unsigned long long*)nullptr, (unsigned long long*)nullptr))) return rc;
+  Sched bz = make_sched(make_box(0, g.n1 - 1, 0, g.n2 - 1, 0, g.n3 - 1), c->kg_update);
+  const unsigned nb = blocks_for(bz);
+  const int cls = STAGE == 1 ? T_UPDATE1 : T_UPDATE2;
+  if ((rc = launch(c, cls, k_targets_emhd, nb, g, bz, Pin, (const double*)c->tabC, (const double*)c->conn,
+                   c->xrhs, c->divu)))
+    return rc;
+  if ((rc = launch(c, cls, k_update_emhd<STAGE>, nb, g, bz, Pin, (const double*)Xin, c->V, c->VX, c->utn,
+                   (const double*)F1, (const double*)F2, (const double*)F3, (const double*)c->FX[0],
+                   (const double*)c->FX[1], (const double*)c->FX[2], (const double*)c->E[0],
+                   (const double*)c->E[1], (const double*)c->E[2], (const double*)c->tabC,
+                   (const double*)c->conn, dt, dt_dev, c->ustar, c->xrhs)))
+    return rc;
+  auto implicit = [&](auto kernel, double* partial) {
+    return launch(c, cls, kernel, nb, g, bz, Pin, (const double*)Xin, (const double*)c->ustar,
+                  (const double*)c->xrhs, (const double*)c->divu, (const double*)c->utn, Pout, Xout,
+                  (const double*)c->tabC, dt, dt_dev, c->fails, partial);
+  };
+  if (STAGE == 2 && rate && nb <= (unsigned)MAX_PARTIALS) return implicit(k_implicit_emhd<STAGE, true>, c->pdt);
+  return implicit(k_implicit_emhd<STAGE, false>, (double*)nullptr);
+}
+
 // One SSPRK2 step with dt from the host, or, when dt_dev is given, with the
 // dt the device reduction left there.  The stage-2 update leaves the
 // CFL-rate partials of the new state, so the next dt needs only the final
@@ -2340,7 +2431,11 @@ int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   if ((rc = ensure_ghosts(c))) return rc;
   c->ghosts_valid = false;
   const Dev& g = c->dev;
-  if (c->params.integrator == GRMHD_INTEG_RK1) {  // one stage, its result copied back to the state
+  if (c->params.egrmhd) {  // Extended GRMHD: the predictor-corrector with implicit stages
+    if ((rc = emhd_stage<1>(c, c->P, c->X, c->P1, c->X1, dt, dt_dev, false))) return rc;
+    if ((rc = fill_ghosts(c, c->P1))) return rc;
+    if ((rc = emhd_stage<2>(c, c->P1, c->X1, c->P, c->X, dt, dt_dev, true))) return rc;
+  } else if (c->params.integrator == GRMHD_INTEG_RK1) {  // one stage, its result copied back to the state
     if ((rc = stage<1, R, FT>(c, c->P, c->P1, dt, dt_dev, true))) return rc;
     if (hipMemcpyAsync(c->P, c->P1, sizeof(double) * NVAR * g.nz, hipMemcpyDeviceToDevice, c->stream) !=
         hipSuccess)
@@ -2409,6 +2504,9 @@ Dev make_dev(const grmhd_grid* grid, const grmhd_metric* metric, const grmhd_par
   g.bsq_over_u_max = params->bsq_over_u_max;
   g.u_over_rho_max = params->u_over_rho_max;
   g.gamma_max = params->gamma_max;
+  g.tau = params->tau_r;
+  g.chi = params->chi_emhd;
+  g.nu = params->nu_emhd;
   g.st = SpaceTime{kerr ? 1 : 0, metric->a, metric->hslope};
   return g;
 }
@@ -2476,7 +2574,7 @@ extern "C" {
 
 size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params) {
   if (!grid_ok(grid, params)) return 0;
-  return carve(nullptr, nullptr, grid, params->ct, params->inverter);
+  return carve(nullptr, nullptr, grid, params);
 }
 
 int grmhd_cfl_dt_noalloc(const grmhd_grid* grid, const grmhd_metric* metric, const grmhd_params* params,
@@ -2510,14 +2608,14 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   if (metric->metric != GRMHD_METRIC_MINKOWSKI && metric->metric != GRMHD_METRIC_KERR_MKS)
     return GRMHD_E_ARG;
   if (((uintptr_t)d_workspace & 255) != 0) return GRMHD_E_ARG;
-  if (ws_bytes < carve(nullptr, nullptr, grid, params->ct, params->inverter)) return GRMHD_E_NOMEM;
+  if (ws_bytes < carve(nullptr, nullptr, grid, params)) return GRMHD_E_NOMEM;
   grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
   if (!c) return GRMHD_E_NOMEM;
   c->grid = *grid;
   c->metric = *metric;
   c->params = *params;
   c->stream = (hipStream_t)hip_stream;
-  carve(c, (char*)d_workspace, grid, params->ct, params->inverter);
+  carve(c, (char*)d_workspace, grid, params);
   c->dev = make_dev(grid, metric, params);
   Dev& g = c->dev;
   k_geometry<<<blocks_for(g.plane), BLOCK, 0, c->stream>>>(g, c->tabC, c->tabF1, c->tabF2, c->corner,
@@ -2526,6 +2624,8 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   static const double result0[8] = {0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
   if (hipMemsetAsync(c->fails, 0, 8 * sizeof(unsigned long long), c->stream) != hipSuccess ||
       hipMemsetAsync(c->mark, 0, (size_t)g.nz, c->stream) != hipSuccess ||
+      (c->X && hipMemsetAsync(c->X, 0, sizeof(double) * NXV * g.nz, c->stream) != hipSuccess) ||
+      (c->X1 && hipMemsetAsync(c->X1, 0, sizeof(double) * NXV * g.nz, c->stream) != hipSuccess) ||
       hipMemcpyAsync(c->result, result0, sizeof(result0), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hip_check() != GRMHD_OK) {
     delete c;
@@ -2547,6 +2647,28 @@ int grmhd_load_prims(grmhd_ctx* c, const double* d_prims) {
     return GRMHD_E_HIP;
   // face-centred CT: the zones' field is their faces' mean
   if (c->faces_loaded) return cell_b_from_faces(c);
+  return GRMHD_OK;
+}
+
+int grmhd_load_extended(grmhd_ctx* c, const double* d_extra) {
+  if (!c || !d_extra) return GRMHD_E_ARG;
+  if (!c->params.egrmhd) return GRMHD_E_STATE;
+  const size_t bytes = sizeof(double) * NXV * c->dev.nz;
+  // the stage buffer carries the same (frozen) ghosts
+  if (hipMemcpyAsync(c->X, d_extra, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->X1, d_extra, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return GRMHD_E_HIP;
+  return GRMHD_OK;
+}
+
+int grmhd_get_extended(grmhd_ctx* c, double* d_extra) {
+  if (!c || !d_extra) return GRMHD_E_ARG;
+  if (!c->params.egrmhd) return GRMHD_E_STATE;
+  int rc;
+  if ((rc = launch(c, T_BC, k_bc_extra, blocks_for(ghost_count(c->dev)), c->dev, c->X))) return rc;
+  if (hipMemcpyAsync(d_extra, c->X, sizeof(double) * NXV * c->dev.nz, hipMemcpyDeviceToDevice, c->stream) !=
+      hipSuccess)
+    return GRMHD_E_HIP;
   return GRMHD_OK;
 }
 
@@ -2738,7 +2860,7 @@ int grmhd_cons_to_prims(grmhd_ctx* c, const double* d_cons, const double* d_gues
 
 int grmhd_fluxes(grmhd_ctx* c, const double* d_prims, double* d_flux) {
   if (!c || !d_prims || !d_flux) return GRMHD_E_ARG;
-  if (c->params.precision != GRMHD_PREC_FP64) return GRMHD_E_STATE;
+  if (c->params.precision != GRMHD_PREC_FP64 || c->params.egrmhd) return GRMHD_E_STATE;
   int rc;
   if ((rc = grmhd_load_prims(c, d_prims))) return rc;
   if ((rc = ensure_ghosts(c))) return rc;

@@ -50,7 +50,8 @@ class grmhd_params(C.Structure):
                 ("u_min_geom", C.c_double), ("bsq_over_rho_max", C.c_double),
                 ("bsq_over_u_max", C.c_double), ("u_over_rho_max", C.c_double),
                 ("gamma_max", C.c_double), ("fofc", C.c_int), ("ct", C.c_int),
-                ("integrator", C.c_int)]
+                ("integrator", C.c_int), ("egrmhd", C.c_int), ("tau_r", C.c_double),
+                ("chi_emhd", C.c_double), ("nu_emhd", C.c_double)]
 
 
 # floor and ceiling defaults (HARM-family values; the paper states none)
@@ -60,7 +61,7 @@ FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0
 
 def make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precision, inverter,
                 kastaun_wmax, floors=False, fofc=False, ct=CT_FLUX, integrator=INTEG_SSPRK2,
-                **floor_params):
+                egrmhd=False, tau_r=1.0, chi_emhd=0.0, nu_emhd=0.0, **floor_params):
     fp = dict(FLOOR_DEFAULTS)
     for k, v in floor_params.items():
         if k not in fp:
@@ -69,12 +70,14 @@ def make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precis
     return grmhd_params(float(gamma_ad), float(cfl), float(weno_eps), float(newton_tol),
                         int(newton_maxit), int(recon), int(precision), int(bool(floors)),
                         int(inverter), float(kastaun_wmax), *(float(fp[k]) for k in FLOOR_DEFAULTS),
-                        int(bool(fofc)), int(ct), int(integrator))
+                        int(bool(fofc)), int(ct), int(integrator), int(bool(egrmhd)),
+                        float(tau_r), float(chi_emhd), float(nu_emhd))
 
 
 EXPORTS = ("grmhd_workspace_bytes", "grmhd_create", "grmhd_load_prims", "grmhd_step",
            "grmhd_estimate_dt", "grmhd_step_cfl", "grmhd_last_dt", "grmhd_get_prims", "grmhd_divb", "grmhd_get_status",
            "grmhd_get_counters", "grmhd_load_faces", "grmhd_get_faces", "grmhd_face_divb",
+           "grmhd_load_extended", "grmhd_get_extended",
            "grmhd_reset_status", "grmhd_prims_to_cons", "grmhd_cons_to_prims", "grmhd_fluxes",
            "grmhd_pack_workspace_bytes", "grmhd_pack_create", "grmhd_pack_set_tiles",
            "grmhd_pack_load_prims", "grmhd_pack_step", "grmhd_pack_get_prims",
@@ -101,6 +104,8 @@ def load_library(path=LIB_PATH):
         "grmhd_divb": (C.c_int, [vp, vp, dp, dp]),
         "grmhd_get_status": (C.c_int, [vp, ip, ip]),
         "grmhd_get_counters": (C.c_int, [vp, ip]),
+        "grmhd_load_extended": (C.c_int, [vp, vp]),
+        "grmhd_get_extended": (C.c_int, [vp, vp]),
         "grmhd_load_faces": (C.c_int, [vp, vp]),
         "grmhd_get_faces": (C.c_int, [vp, vp]),
         "grmhd_face_divb": (C.c_int, [vp, dp, dp]),
@@ -214,18 +219,23 @@ class Grmhd:
     inverter (INV_1DW, INV_KASTAUN, INV_IMPLICIT), floors (with the keyword
     floor parameters of FLOOR_DEFAULTS), fofc (first-order flux correction),
     ct (CT_FLUX, or face-centred CT_FACE_AVG / CT_FACE_GS, whose face fields
-    load_faces takes), integrator (INTEG_SSPRK2, INTEG_PC, INTEG_RK1).
+    load_faces takes), integrator (INTEG_SSPRK2, INTEG_PC, INTEG_RK1),
+    egrmhd (Extended GRMHD with the closure constants tau_r, chi_emhd,
+    nu_emhd; needs INTEG_PC; its two extra variables via load_extended /
+    extended).
     """
 
     def __init__(self, spec, gamma_ad, recon=RECON_WENO5, precision=PREC_FP64, cfl=0.9,
                  weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda",
                  stream=None, strict=False, inverter=INV_1DW, kastaun_wmax=1e3, floors=False,
-                 fofc=False, ct=CT_FLUX, integrator=INTEG_SSPRK2, **floor_params):
+                 fofc=False, ct=CT_FLUX, integrator=INTEG_SSPRK2, egrmhd=False, tau_r=1.0,
+                 chi_emhd=0.0, nu_emhd=0.0, **floor_params):
         self.spec = spec
         self.grid = make_grid(spec)
         self.metric = grmhd_metric(int(spec.metric), float(spec.a), float(spec.hslope))
         self.params = make_params(gamma_ad, cfl, weno_eps, newton_tol, newton_maxit, recon, precision,
-                                  inverter, kastaun_wmax, floors, fofc, ct, integrator, **floor_params)
+                                  inverter, kastaun_wmax, floors, fofc, ct, integrator, egrmhd,
+                                  tau_r, chi_emhd, nu_emhd, **floor_params)
         self.strict = strict
         L = lib()
         nbytes = L.grmhd_workspace_bytes(C.byref(self.grid), C.byref(self.params))
@@ -302,6 +312,19 @@ class Grmhd:
         a, b = C.c_longlong(), C.c_longlong()
         _check(lib().grmhd_get_status(self.ctx, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def load_extended(self, extra):
+        """Extended GRMHD's rescaled heat flux and pressure anisotropy,
+        [2, n3+6, n2+6, n1+6] (zero after creation)."""
+        x = extra.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(x.shape) == (2,) + tuple(self.shape[1:]), x.shape
+        self._keep_extra = x
+        _check(lib().grmhd_load_extended(self.ctx, _ptr(x)))
+
+    def extended(self):
+        out = torch.empty((2,) + tuple(self.shape[1:]), dtype=torch.float64, device=self.device)
+        _check(lib().grmhd_get_extended(self.ctx, _ptr(out)))
+        return out
 
     def load_faces(self, faces):
         """Face fields [3, n3+6, n2+6, n1+6] (sqrt(-g) B^d on lower d-faces) of

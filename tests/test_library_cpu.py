@@ -168,3 +168,33 @@ def test_implicit_recovery_parameters():
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INV_IMPLICIT, fofc=True))) == 0
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(3))) == 0
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INV_IMPLICIT))) == 0
+
+
+def test_extended_grmhd_parameters_and_workspace():
+    from paper_2408_01361_amd import grmhd
+    from workloads import torus_grid
+    lib = grmhd.lib()
+    g = grmhd.make_grid(torus_grid(32, 32, 32))
+    mk = lambda **kw: grmhd.make_params(13 / 9, 0.9, 1e-26, 1e-14, 30, kw.pop("recon", grmhd.RECON_WENO5),
+                                        kw.pop("precision", grmhd.PREC_FP64), 0, 1e3,
+                                        **{"integrator": grmhd.INTEG_PC, **kw})
+    base = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk()))
+    ext = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(egrmhd=True, tau_r=1.0, chi_emhd=0.1, nu_emhd=0.1)))
+    nz = 38 ** 3
+    # U* of a stage; the state's and stage 1's X, their fluxes, U^n and
+    # right-hand sides of X; u^t of the step start and the spatial div u
+    assert ext >= base + (8 + 2 * 7 + 2) * 8 * nz
+    for mc in (grmhd.RECON_MC, grmhd.RECON_WENO5):
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(egrmhd=True, recon=mc))) > 0
+    bad = [dict(egrmhd=True, integrator=grmhd.INTEG_SSPRK2), dict(egrmhd=True, integrator=grmhd.INTEG_RK1),
+           dict(egrmhd=True, precision=grmhd.PREC_MIXED), dict(egrmhd=True, recon=grmhd.RECON_MP5),
+           dict(egrmhd=True, tau_r=0.0), dict(egrmhd=True, tau_r=float("nan")),
+           dict(egrmhd=True, chi_emhd=-1.0), dict(egrmhd=True, nu_emhd=float("inf"))]
+    for kw in bad:
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(**kw))) == 0, kw
+    p = mk(egrmhd=True)
+    p.egrmhd = 2
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(p)) == 0
+    assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(egrmhd=True))) == 0
+    assert lib.grmhd_load_extended(None, None) == grmhd.E_ARG
+    assert lib.grmhd_get_extended(None, None) == grmhd.E_ARG
