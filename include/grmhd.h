@@ -305,8 +305,9 @@ int grmhd_step_vjp(grmhd_ctx* ctx, const double* d_prims_in, double dt, const do
  * sub-box starting at interior zone offsets_ijk[3b..3b+2] of the global grid
  * (same metric and parameters); every block has frozen (Dirichlet) ghost
  * zones unless the ghost exchange below is on, and x2 block faces on the
- * polar axis carry no flux.  One pack step is
- * one persistent cooperative launch per RK2 stage that processes every block.
+ * polar axis carry no flux.  Each RK2 stage of a pack step is three
+ * launches (face fluxes, edge EMFs, zone update), each over the work items
+ * of every block.
  * Packed prims: the blocks' padded arrays [8][n+6][n+6][n+6], concatenated in
  * block order (device).  Tile shapes per block size (t1*t2*t3 <= 256, or
  * (0, 0, 0): runs of 256 consecutive positions of each box in x1-fastest
@@ -342,7 +343,8 @@ int grmhd_pack_get_status(grmhd_pack* pack, long long* n_inv_fail);
  * blocks, E_NOMEM for a short map. */
 size_t grmhd_pack_exchange_bytes(const grmhd_grid* global);
 int grmhd_pack_set_exchange(grmhd_pack* pack, void* d_map, size_t map_bytes);
-/* Cooperative grid size and length (doubles) of the packed prims. */
+/* Workgroups of one RK2 stage's three launches, and length (doubles) of
+ * the packed prims. */
 int grmhd_pack_info(grmhd_pack* pack, int* grid_blocks, long long* prim_doubles);
 int grmhd_pack_destroy(grmhd_pack* pack);
 

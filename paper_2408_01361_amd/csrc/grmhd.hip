@@ -24,7 +24,6 @@
 // exit at once when nothing was marked); face-centred CT fills ghost faces,
 // reads the face field in the flux pass, forms edge EMFs (averaged, or
 // upwinded from zone-centre EMFs) and advances the faces before the update.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -3087,9 +3086,8 @@ struct grmhd_pack {
   long prim_total;
   BlockView* d_views;
   int* d_pre;
-  unsigned* d_counters;
   unsigned long long* d_fails;
-  int grid_blocks;
+  int items[PH_N];  // work items (workgroups) of each phase launch
   grmhd_grid global;
   int* d_owner;  // ghost exchange: owner block of every global interior zone, or null (frozen ghosts)
   int max_nz;    // padded zones of the largest block
@@ -3123,12 +3121,10 @@ size_t pack_carve(int nb, const int* n, char* base, grmhd_pack* pk) {
   }
   BlockView* dv = cv.take<BlockView>(base, nb);
   int* pre = cv.take<int>(base, PH_N * (nb + 1));
-  unsigned* cnt = cv.take<unsigned>(base, 64);
   unsigned long long* fails = cv.take<unsigned long long>(base, 8);
   if (pk) {
     pk->d_views = dv;
     pk->d_pre = pre;
-    pk->d_counters = cnt;
     pk->d_fails = fails;
     pk->prim_total = prim_total;
   }
@@ -3145,12 +3141,14 @@ int default_tile(int, int& t1, int& t2, int& t3) {
 int pack_upload(grmhd_pack* pk) {
   std::vector<int> pre(PH_N * (pk->nb + 1));
   for (int ph = 0; ph < PH_N; ph++) {
-    int acc = 0;
+    long acc = 0;
     for (int b = 0; b < pk->nb; b++) {
-      pre[ph * (pk->nb + 1) + b] = acc;
+      pre[ph * (pk->nb + 1) + b] = (int)acc;
       acc += block_items(pk->views[b], ph);
     }
-    pre[ph * (pk->nb + 1) + pk->nb] = acc;
+    if (acc > (1L << 30)) return GRMHD_E_ARG;
+    pre[ph * (pk->nb + 1) + pk->nb] = (int)acc;
+    pk->items[ph] = (int)acc;
   }
   if (hipMemcpy(pk->d_views, pk->views.data(), sizeof(BlockView) * pk->nb, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(pk->d_pre, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice) != hipSuccess)
@@ -3166,16 +3164,27 @@ int pack_launch(grmhd_pack* pk, int stage, double dt) {
     dim3 grid((unsigned)((pk->max_nz + BLOCK - 1) / BLOCK), (unsigned)pk->nb);
     k_pack_exchange<<<grid, BLOCK, 0, pk->stream>>>(pk->d_views, pk->d_owner, G, stage);
   }
-  if (hipMemsetAsync(pk->d_counters, 0, sizeof(unsigned) * PH_N, pk->stream) != hipSuccess) return GRMHD_E_HIP;
   const BlockView* views = pk->d_views;
-  int nb = pk->nb;
+  const int nb = pk->nb;
   const int* pre = pk->d_pre;
-  unsigned* cnt = pk->d_counters;
-  unsigned long long* fails = pk->d_fails;
-  void* args[] = {(void*)&views, (void*)&nb, (void*)&pre, (void*)&cnt, (void*)&dt, (void*)&fails};
-  const void* fn = stage == 1 ? (const void*)k_pack_stage<1, RECON> : (const void*)k_pack_stage<2, RECON>;
-  if (hipLaunchCooperativeKernel(fn, dim3(pk->grid_blocks), dim3(BLOCK), args, 0, pk->stream) != hipSuccess)
-    return GRMHD_E_HIP;
+  bool linear = true;
+  for (const BlockView& v : pk->views) linear = linear && v.t1 == 0;
+  auto flux = [&](auto kernel) { kernel<<<pk->items[PH_FLUX], BLOCK, 0, pk->stream>>>(views, nb, pre); };
+  if (stage == 1) {
+    if (linear)
+      flux(k_pack_flux<1, RECON, true>);
+    else
+      flux(k_pack_flux<1, RECON, false>);
+    k_pack_emf<<<pk->items[PH_EMF], BLOCK, 0, pk->stream>>>(views, nb, pre);
+    k_pack_update<1><<<pk->items[PH_UPDATE], BLOCK, 0, pk->stream>>>(views, nb, pre, dt, pk->d_fails);
+  } else {
+    if (linear)
+      flux(k_pack_flux<2, RECON, true>);
+    else
+      flux(k_pack_flux<2, RECON, false>);
+    k_pack_emf<<<pk->items[PH_EMF], BLOCK, 0, pk->stream>>>(views, nb, pre);
+    k_pack_update<2><<<pk->items[PH_UPDATE], BLOCK, 0, pk->stream>>>(views, nb, pre, dt, pk->d_fails);
+  }
   return hip_check();
 }
 
@@ -3263,22 +3272,11 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
     default_tile(n[b], v.t1, v.t2, v.t3);
     k_geometry<<<blocks_for(g.plane), BLOCK, 0, pk->stream>>>(g, v.tabC, v.tabF1, v.tabF2, v.corner, v.conn);
   }
-  // co-resident workgroups per CU: the smaller of the two stage kernels'
-  int per_cu = 0, per_cu2 = 0, ncu = 0, dev = 0;
-  const bool mc = params->recon == GRMHD_RECON_MC;
-  const void* fn1 = mc ? (const void*)k_pack_stage<1, GRMHD_RECON_MC> : (const void*)k_pack_stage<1, GRMHD_RECON_WENO5>;
-  const void* fn2 = mc ? (const void*)k_pack_stage<2, GRMHD_RECON_MC> : (const void*)k_pack_stage<2, GRMHD_RECON_WENO5>;
-  if (hip_check() || hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn1, BLOCK, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, fn2, BLOCK, 0) != hipSuccess ||
-      (per_cu = per_cu < per_cu2 ? per_cu : per_cu2) < 1 ||
-      hipMemsetAsync(pk->d_fails, 0, sizeof(unsigned long long), pk->stream) != hipSuccess ||
+  if (hip_check() || hipMemsetAsync(pk->d_fails, 0, sizeof(unsigned long long), pk->stream) != hipSuccess ||
       pack_upload(pk) != GRMHD_OK) {
     delete pk;
     return GRMHD_E_HIP;
   }
-  pk->grid_blocks = per_cu * ncu;
   *out = pk;
   return GRMHD_OK;
 }
@@ -3342,7 +3340,7 @@ int grmhd_pack_get_status(grmhd_pack* pk, long long* n_inv_fail) {
 
 int grmhd_pack_info(grmhd_pack* pk, int* grid_blocks, long long* prim_doubles) {
   if (!pk || !grid_blocks || !prim_doubles) return GRMHD_E_ARG;
-  *grid_blocks = pk->grid_blocks;
+  *grid_blocks = pk->items[PH_FLUX] + pk->items[PH_EMF] + pk->items[PH_UPDATE];
   *prim_doubles = pk->prim_total;
   return GRMHD_OK;
 }

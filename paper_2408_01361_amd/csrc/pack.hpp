@@ -1,23 +1,18 @@
-// Batched uneven meshblock packs: one persistent, cooperative launch per
-// RK2 stage advances every block of a pack.  The launch runs three phases
-// separated by grid-wide barriers -- face fluxes of every block along x1..x3,
-// edge EMFs, then the zone update with the inversion -- and within each phase
-// its workgroups take (block, tile) work items from an atomic counter, so
-// uneven block sizes balance dynamically.  Tile shapes (T1 x T2 x T3 <= BLOCK
-// threads, or linear runs of BLOCK positions) are chosen per block size (an
-// autotuner picks them); the per-face,
-// per-edge and per-zone work is the same device code as the single-block
-// kernels, so a block advanced in a pack matches the same block advanced
-// alone bit for bit.  Ghost zones are frozen (Dirichlet).
+// Batched uneven meshblock packs: three launches per RK2 stage advance every
+// block of a pack -- face fluxes of every block along x1..x3, edge EMFs,
+// then the zone update with the inversion -- each launch covering the work
+// items of all blocks (one workgroup per item, in XCD order), so uneven
+// block sizes fill the whole GPU together and every phase keeps the
+// register budget of its own single-grid kernel.  Tile shapes (T1 x T2 x T3
+// <= BLOCK threads, or linear runs of BLOCK positions) are chosen per block
+// size (an autotuner picks them); the per-face, per-edge and per-zone work
+// is the same device code as the single-block kernels, so a block advanced
+// in a pack matches the same block advanced alone bit for bit (with the
+// linear tile shape the x1 faces come from the same shared-edge sweep as the
+// single grid's).  Ghost zones are frozen (Dirichlet) unless the ghost
+// exchange fills them before each stage.
 //
 // Included inside the anonymous namespace of grmhd.hip.
-
-// Waves per SIMD the persistent kernel is compiled for: every phase shares
-// one register budget, so it is set to what the update phase fits in
-// without spilling.
-#ifndef PACK_WAVES
-#define PACK_WAVES 3
-#endif
 
 struct BlockView {
   Dev g;
@@ -49,11 +44,22 @@ __host__ __device__ inline int tiles_of(const Box& b, int t1, int t2, int t3) {
   return ((b.n1 + t1 - 1) / t1) * ((b.n2 + t2 - 1) / t2) * ((b.n3 + t3 - 1) / t3);
 }
 
+// Work items of a block's x1 faces: with the linear tile shape, workgroups
+// of the shared-edge sweep (sweep_x1: BLOCK / 64 wavefronts of 63 new zones
+// each over the zones i in [-1, n1], j in [-1, n2], k in [-1, n3]); with a
+// t1 x t2 x t3 shape, tiles of faces.
+__host__ __device__ inline int x1_items(const BlockView& b) {
+  if (b.t1 == 0) {
+    const long n1z = (long)(b.g.n1 + 2) * (b.g.n2 + 2) * (b.g.n3 + 2);
+    return (int)(((n1z + 62) / 63 + BLOCK / 64 - 1) / (BLOCK / 64));
+  }
+  return tiles_of(phase_box(b.g, PH_FLUX, 1), b.t1, b.t2, b.t3);
+}
+
 // Work items of a block in a phase (the flux phase holds all three directions).
 __host__ __device__ inline int block_items(const BlockView& b, int ph) {
   if (ph == PH_FLUX)
-    return tiles_of(phase_box(b.g, PH_FLUX, 1), b.t1, b.t2, b.t3) +
-           tiles_of(phase_box(b.g, PH_FLUX, 2), b.t1, b.t2, b.t3) +
+    return x1_items(b) + tiles_of(phase_box(b.g, PH_FLUX, 2), b.t1, b.t2, b.t3) +
            tiles_of(phase_box(b.g, PH_FLUX, 3), b.t1, b.t2, b.t3);
   return tiles_of(phase_box(b.g, ph, 0), b.t1, b.t2, b.t3);
 }
@@ -61,7 +67,16 @@ __host__ __device__ inline int block_items(const BlockView& b, int ph) {
 // Position of this thread in tile `lt` of box b, if inside.
 __device__ __forceinline__ bool tile_pos(const Box& b, int t1, int t2, int t3, int lt, int& i, int& j,
                                          int& k) {
-  if (t1 == 0) return box_index(b, (long)lt * BLOCK + threadIdx.x, i, j, k);
+  if (t1 == 0) {  // 32-bit index arithmetic: a block's boxes hold far fewer than 2^31 positions
+    const unsigned t = (unsigned)lt * BLOCK + threadIdx.x;
+    const unsigned n1 = (unsigned)b.n1, n12 = n1 * (unsigned)b.n2;
+    if (t >= n12 * (unsigned)b.n3) return false;
+    const unsigned kk = t / n12, r = t - kk * n12, jj = r / n1;
+    i = b.lo1 + (int)(r - jj * n1);
+    j = b.lo2 + (int)jj;
+    k = b.lo3 + (int)kk;
+    return true;
+  }
   int nt1 = (b.n1 + t1 - 1) / t1, nt2 = (b.n2 + t2 - 1) / t2;
   int a = lt % nt1, rest = lt / nt1;
   int bb = rest % nt2, cc = rest / nt2;
@@ -75,27 +90,35 @@ __device__ __forceinline__ bool tile_pos(const Box& b, int t1, int t2, int t3, i
   return true;
 }
 
-template <int RECON>
+// One work item of a block's flux phase: x1 faces, then x2, then x3.  With
+// LINEAR every block of the pack uses the linear tile shape (the x1 faces
+// from the sweep), which keeps the general tile arithmetic out of the
+// kernel.
+template <int RECON, bool LINEAR>
 __device__ __forceinline__ void pack_flux_item(const BlockView& b, const double* __restrict__ Pin, int lt) {
   const Dev& g = b.g;
-  for (int d = 1; d <= 3; d++) {
-    Box bx = phase_box(g, PH_FLUX, d);
-    int nt = tiles_of(bx, b.t1, b.t2, b.t3);
-    if (lt >= nt) {
-      lt -= nt;
-      continue;
+  const int t1 = LINEAR ? 0 : b.t1, t2 = LINEAR ? 0 : b.t2, t3 = LINEAR ? 0 : b.t3;
+  int i, j, k;
+  const int n1t = x1_items(b);
+  if (lt < n1t) {
+    if (LINEAR || t1 == 0) {  // every thread of the workgroup takes part (cross-lane shift)
+      sweep_x1<RECON, double, double, false>(g, (unsigned)lt, Pin, b.tabF1, b.F[0], nullptr);
+      return;
     }
-    int i, j, k;
-    if (tile_pos(bx, b.t1, b.t2, b.t3, lt, i, j, k)) {
-      if (d == 1)
-        flux_face<1, RECON, double, double>(g, Pin, b.tabF1, b.F[0], i, j, k);
-      else if (d == 2)
-        flux_face<2, RECON, double, double>(g, Pin, b.tabF2, b.F[1], i, j, k);
-      else
-        flux_face<3, RECON, double, double>(g, Pin, b.tabC, b.F[2], i, j, k);
-    }
+    if (tile_pos(phase_box(g, PH_FLUX, 1), t1, t2, t3, lt, i, j, k))
+      flux_face<1, RECON, double, double>(g, Pin, b.tabF1, b.F[0], i, j, k);
     return;
   }
+  lt -= n1t;
+  const Box b2 = phase_box(g, PH_FLUX, 2);
+  const int n2t = tiles_of(b2, t1, t2, t3);
+  if (lt < n2t) {
+    if (tile_pos(b2, t1, t2, t3, lt, i, j, k)) flux_face<2, RECON, double, double>(g, Pin, b.tabF2, b.F[1], i, j, k);
+    return;
+  }
+  lt -= n2t;
+  if (tile_pos(phase_box(g, PH_FLUX, 3), t1, t2, t3, lt, i, j, k))
+    flux_face<3, RECON, double, double>(g, Pin, b.tabC, b.F[2], i, j, k);
 }
 
 // Block of a work item: the last block whose item offset is <= item.
@@ -111,45 +134,42 @@ __device__ __forceinline__ int find_block(const int* __restrict__ pre, int nb, i
   return lo;
 }
 
-// One RK2 stage of every block.  pre holds, per phase, nb + 1 item offsets
-// (the last is the phase's total); counters[ph] must be zero at launch.
-// Every workgroup leaves each phase's loop once the counter passes the total
-// and then meets every grid barrier, so the launch always drains.
-template <int STAGE, int RECON>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PACK_WAVES, PACK_WAVES))) k_pack_stage(const BlockView* __restrict__ bv, int nb,
-                                                      const int* __restrict__ pre,
-                                                      unsigned* counters, double dt,
-                                                      unsigned long long* fails) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-  __shared__ int s_item;
-  for (int ph = 0; ph < PH_N; ph++) {
-    const int* p = pre + ph * (nb + 1);
-    const int total = p[nb];
-    for (;;) {
-      if (threadIdx.x == 0) s_item = (int)atomicAdd(&counters[ph], 1u);
-      __syncthreads();
-      const int item = s_item;
-      __syncthreads();
-      if (item >= total) break;
-      const int blk = find_block(p, nb, item);
-      const BlockView& b = bv[blk];
-      const int lt = item - p[blk];
-      const double* Pin = STAGE == 1 ? b.P : b.P1;
-      if (ph == PH_FLUX) {
-        pack_flux_item<RECON>(b, Pin, lt);
-      } else if (ph == PH_EMF) {
-        int i, j, k;
-        if (tile_pos(phase_box(b.g, PH_EMF, 0), b.t1, b.t2, b.t3, lt, i, j, k))
-          emf_edge<double>(b.g, b.F[0], b.F[1], b.F[2], b.E[0], b.E[1], b.E[2], i, j, k);
-      } else {
-        int i, j, k;
-        if (tile_pos(phase_box(b.g, PH_UPDATE, 0), b.t1, b.t2, b.t3, lt, i, j, k))
-          update_zone<STAGE, double>(b.g, Pin, STAGE == 1 ? b.P1 : b.P, b.V, b.F[0], b.F[1], b.F[2],
-                                     b.E[0], b.E[1], b.E[2], b.tabC, b.conn, dt, fails, nullptr, i, j, k);
-      }
-    }
-    grid.sync();
-  }
+// Work item of this workgroup in a phase (pre holds, per phase, nb + 1 item
+// offsets, the last being the phase's total, which is the launch's
+// workgroup count): its block and its item within that block.
+__device__ __forceinline__ int pack_item(int nb, const int* __restrict__ pre, int ph, int& lt) {
+  const int* p = pre + ph * (nb + 1);
+  const int item = (int)xcd_order(blockIdx.x, gridDim.x);
+  const int blk = find_block(p, nb, item);
+  lt = item - p[blk];
+  return blk;
+}
+
+template <int STAGE, int RECON, bool LINEAR>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FLUX_WAVES, 8)))
+k_pack_flux(const BlockView* __restrict__ bv, int nb, const int* __restrict__ pre) {
+  int lt;
+  const BlockView& b = bv[pack_item(nb, pre, PH_FLUX, lt)];
+  pack_flux_item<RECON, LINEAR>(b, STAGE == 1 ? b.P : b.P1, lt);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_pack_emf(const BlockView* __restrict__ bv, int nb,
+                                                    const int* __restrict__ pre) {
+  int lt, i, j, k;
+  const BlockView& b = bv[pack_item(nb, pre, PH_EMF, lt)];
+  if (tile_pos(phase_box(b.g, PH_EMF, 0), b.t1, b.t2, b.t3, lt, i, j, k))
+    emf_edge<double>(b.g, b.F[0], b.F[1], b.F[2], b.E[0], b.E[1], b.E[2], i, j, k);
+}
+
+template <int STAGE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8)))
+k_pack_update(const BlockView* __restrict__ bv, int nb, const int* __restrict__ pre, double dt,
+              unsigned long long* fails) {
+  int lt, i, j, k;
+  const BlockView& b = bv[pack_item(nb, pre, PH_UPDATE, lt)];
+  if (tile_pos(phase_box(b.g, PH_UPDATE, 0), b.t1, b.t2, b.t3, lt, i, j, k))
+    update_zone<STAGE, double>(b.g, STAGE == 1 ? b.P : b.P1, STAGE == 1 ? b.P1 : b.P, b.V, b.F[0], b.F[1],
+                               b.F[2], b.E[0], b.E[1], b.E[2], b.tabC, b.conn, dt, fails, nullptr, i, j, k);
 }
 
 // Ghost exchange between the blocks of a pack (the blocks tile part or all

@@ -420,7 +420,7 @@ class Grmhd:
 
 class Pack:
     """A pack of cubic blocks (sub-boxes of one global grid) advanced together
-    by one persistent launch per RK2 stage."""
+    by three launches per RK2 stage (fluxes, EMFs, update) over all blocks."""
 
     def __init__(self, global_spec, sizes, offsets, gamma_ad, recon=RECON_WENO5, cfl=0.9,
                  weno_eps=1e-26, newton_tol=1e-14, newton_maxit=30, device="cuda", stream=None,

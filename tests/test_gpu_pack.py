@@ -1,4 +1,4 @@
-"""Batched uneven packs: one persistent launch per stage over many blocks.
+"""Batched uneven packs: three launches per stage (fluxes, EMFs, update) over many blocks.
 
 Every block of a pack must match the same block advanced alone through the
 single-block path bit for bit, and the pack as a whole the FP64 oracle
