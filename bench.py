@@ -63,6 +63,14 @@ def parse():
     return ap.parse_args()
 
 
+_T0 = time.time()
+
+
+def progress(what):
+    """One progress line on stderr per finished part of the run."""
+    print(f"[bench] {what} done at {time.time() - _T0:.1f} s", file=sys.stderr, flush=True)
+
+
 def calibration_copy(torch):
     """One elementwise pass over 512 MiB (read 512 MiB, write 512 MiB) before
     anything else: the reference kernel for scaling the HBM byte counters of a
@@ -215,8 +223,11 @@ def extras(torch, gr, np, args):
         "workload": f"same torus at {n}^3, WENO5, 50 RK2 steps at the initial CFL dt",
         "zone_cycles_per_s": n ** 3 * 50 / t32, "fp64_zone_cycles_per_s": n ** 3 * 50 / t64,
         "speedup_vs_fp64": t64 / t32, "rho_rel_l1_vs_fp64_after_steps": rel,
-        "divb_max_mixed": divb32[0], "divb_mean_mixed": divb32[1], "inversion_failures": f32}
+        "divb_max_mixed": divb32[0], "divb_mean_mixed": divb32[1], "inversion_failures": f32,
+        "fp64_reference_note": "the errors are against the FP64 run of this GPU, whose steps match the "
+                               "oracle to 1e-12 relative L1 per step at this size (full-size parity tests)"}
     del Pt, res, e64, e32
+    progress("mixed precision")
     # batched uneven packs of the 128^3 torus
     g, blocks, _ = torus_pack(nblocks=320, n_global=128, sizes=(16, 32, 64), probs=(0.6, 0.3, 0.1),
                               seed=7, torus_seed=1, gamma=gam)
@@ -273,7 +284,8 @@ def extras(torch, gr, np, args):
     del ctxs
     out["batched"] = {
         "workload": "320 frozen-ghost blocks of the 128^3 torus, n in {16,32,64} (60/30/10 %, seed 7), "
-                    "WENO5, FP64, one persistent launch per RK2 stage, 10 steps at fixed dt",
+                    "WENO5, FP64, three launches per RK2 stage (fluxes, EMFs, update) over all blocks, "
+                    "10 steps at fixed dt",
         "interior_zones": zones, "zone_cycles_per_s": zones * steps / tp,
         "per_block_zone_cycles_per_s": zones * steps / tb,
         "speedup_vs_per_block_fp64": tb / tp,
@@ -281,12 +293,14 @@ def extras(torch, gr, np, args):
         "per_block_note": "the same blocks and steps, each block its own single-grid FP64 context "
                           "stepped in turn on one stream (one ctypes call and its launches per "
                           "block and step)",
-        "cooperative_workgroups": pk.grid_blocks,
+        "workgroups_per_stage": pk.grid_blocks,
         "tiles": {str(k): list(v) for k, v in tiles.items()},
         "tiles_note": "per block size: t1 x t2 x t3 zones, or [0, 0, 0] = runs of 256 consecutive "
                       "positions of each box",
         "inversion_failures_timed_steps": fails}
+    progress("batched pack")
     out["tiling_exchange"] = tiling_extra(torch, gr, np, gam, dt, steps, args)
+    progress("tiling with ghost exchange")
     out["adjoint"] = adjoint_extra(torch, gr)
     return out
 
@@ -344,7 +358,7 @@ def tiling_extra(torch, gr, np, gam, dt, steps, args):
     zones = 128 ** 3
     counts = ", ".join(f"{sum(1 for b in blocks if b['n'] == m)} x {m}^3" for m in (16, 32, 64))
     return {"workload": f"128^3 torus tiled by {len(blocks)} blocks ({counts}), WENO5, FP64, "
-                        f"ghost exchange + one persistent launch per stage, {steps} steps at fixed dt",
+                        f"ghost exchange + three launches per stage over all blocks, {steps} steps at fixed dt",
             "zone_cycles_per_s": zones * steps / tp,
             "frozen_ghosts_zone_cycles_per_s": zones * steps / tf,
             "single_grid_zone_cycles_per_s": zones * steps / ts,
@@ -433,6 +447,40 @@ def integrator_extra(torch, gr, grid, P, gam, recon, steps):
                      "ms_per_step": el * 1e3 / steps}
         del s
     res["workload"] = "the headline torus and step, integrator swapped (a step of RK1 is one stage)"
+    return res
+
+
+def egrmhd_extra(torch, gr, grid, P, gam, recon, steps):
+    """Extended GRMHD against the ideal step on the headline torus: the
+    predictor-corrector with the 1D_W recovery (the ideal step of the same
+    integrator), SSPRK2 with the implicit solver's Newton as the recovery
+    (the same per-zone solver without the extra variables), and Extended
+    GRMHD (predictor-corrector; heat flux and pressure anisotropy, tau_R = 1,
+    chi = nu = 0.1, from zero extra variables).  CFL dt each step."""
+    Pt = torch.from_numpy(P).cuda()
+    nz = grid.n1 * grid.n2 * grid.n3
+    res = {}
+    for name, kw in (("ideal_pc_1dw", dict(integrator=gr.INTEG_PC)),
+                     ("ideal_ssprk2_implicit", dict(inverter=gr.INV_IMPLICIT)),
+                     ("egrmhd", dict(integrator=gr.INTEG_PC, egrmhd=True, tau_r=1.0, chi_emhd=0.1,
+                                     nu_emhd=0.1))):
+        s = gr.Grmhd(grid, gam, recon=recon, **kw)
+        s.load(Pt)
+        for _ in range(3):           # untimed: clocks settle
+            s.step_cfl()
+        s.load(Pt)
+        if name == "egrmhd":
+            s.load_extended(torch.zeros((2,) + tuple(Pt.shape[1:]), dtype=torch.float64, device="cuda"))
+        s.reset_status()
+        el = time_steps(torch, s, steps)
+        res[name] = {"zone_cycles_per_s": nz * steps / el, "ms_per_step": el * 1e3 / steps,
+                     "failed_zone_solves": s.status()[0]}
+        s.close()
+    res["slowdown_vs_ideal_pc"] = res["ideal_pc_1dw"]["zone_cycles_per_s"] / res["egrmhd"]["zone_cycles_per_s"]
+    res["slowdown_vs_ideal_ssprk2_implicit"] = (res["ideal_ssprk2_implicit"]["zone_cycles_per_s"] /
+                                                res["egrmhd"]["zone_cycles_per_s"])
+    res["workload"] = ("the headline torus, predictor-corrector; Extended GRMHD with tau_R = 1, "
+                       "chi = nu = 0.1, no floors (failed zone solves keep their state)")
     return res
 
 
@@ -689,17 +737,35 @@ def main():
         "hbm_frac_step_min_384B": zcps * 384.0 / 1e9 / PEAK_HBM_GBS,
         "hbm_frac_step_design_bytes": zcps * 2 * (3 * BYTES["flux"] + BYTES["update"]) / 1e9 / PEAK_HBM_GBS,
     }
-    del s
+    # the headline fractions by name: which roof binds the dominant kernel, its
+    # FP64-ALU and HBM fractions, and the whole step against the HBM roof
+    if kind:
+        out["headline_fractions"] = {
+            "dominant_kernel": dom,
+            "binding_roof": "fp64_alu" if roof["bound"] == "alu" else "hbm",
+            "dominant_kernel_alu_frac": f_alu,
+            "dominant_kernel_hbm_frac": f_hbm,
+            "step_hbm_frac_min_384B": out["hbm_frac_step_min_384B"],
+            "step_hbm_frac_60pct_target_met": out["hbm_frac_step_min_384B"] >= 0.6,
+        }
+    s.close()
+    progress("headline")
     if not args.no_extras:
         out.update(extras(torch, gr, np, args))
-        out["inverters"] = kastaun_extra(torch, gr, grid, P, gam, recon, args.steps)
-        out["reconstructions"] = recon_extra(torch, gr, grid, P, gam, args.steps)
-        out["integrators"] = integrator_extra(torch, gr, grid, P, gam, recon, args.steps)
-        out["floors_fofc"] = floors_fofc_extra(torch, gr, grid, P, gam, recon, args.steps)
-        out["face_ct"] = face_ct_extra(torch, gr, grid, P, info, gam, recon, args.steps)
-        out["timing_protocol"] = timing_protocol_extra(torch, gr, grid, P, gam, recon, args.steps)
+        progress("adjoint")
+        legs = (("inverters", lambda: kastaun_extra(torch, gr, grid, P, gam, recon, args.steps)),
+                ("reconstructions", lambda: recon_extra(torch, gr, grid, P, gam, args.steps)),
+                ("integrators", lambda: integrator_extra(torch, gr, grid, P, gam, recon, args.steps)),
+                ("egrmhd", lambda: egrmhd_extra(torch, gr, grid, P, gam, recon, args.steps)),
+                ("floors_fofc", lambda: floors_fofc_extra(torch, gr, grid, P, gam, recon, args.steps)),
+                ("face_ct", lambda: face_ct_extra(torch, gr, grid, P, info, gam, recon, args.steps)),
+                ("timing_protocol", lambda: timing_protocol_extra(torch, gr, grid, P, gam, recon, args.steps)))
+        for name, leg in legs:
+            out[name] = leg()
+            progress(name)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_baseline(grid, P, gam, recon, args.cpu_seconds)
+        progress("cpu baseline")
     print(json.dumps(out))
 
 
