@@ -176,9 +176,13 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
                  const grmhd_params* params, void* d_workspace, size_t ws_bytes,
                  void* hip_stream);
 
-/* Copy padded prims (device, layout above) into the context's state.  With
- * face-centred CT and faces loaded, the interior zones' B is then set to
- * their faces' mean. */
+/* Copy padded prims (device, layout above) into the context's state: the
+ * primitive state a step treats as fundamental (Glue section: the step
+ * type that exchanges primitive variables; Physics section: the GRMHD
+ * package's rho, u, velocity, with the field of the transport); with
+ * get_prims it is also the checkpoint a restart reloads.  With face-centred
+ * CT and faces loaded, the interior zones' B is then set to their faces'
+ * mean. */
 int grmhd_load_prims(grmhd_ctx* ctx, const double* d_prims);
 
 /* Extended GRMHD only (E_STATE otherwise).  The two extra variables as
@@ -208,7 +212,9 @@ int grmhd_face_divb(grmhd_ctx* ctx, double* max_out, double* mean_out);
 int grmhd_step(grmhd_ctx* ctx, double dt);
 
 /* CFL step: cfl / max over interior zones of sum_d max|c+-_d| / dx_d (axes
- * with more than one zone), from the current prims.  Synchronises. */
+ * with more than one zone), from the current prims (the global reduction of
+ * the Core section's Reductions package, over the fast-magnetosonic speeds
+ * the Solvers section's flux kernels evaluate).  Synchronises. */
 int grmhd_estimate_dt(grmhd_ctx* ctx, double* dt_out);
 
 /* The CFL step of grmhd_estimate_dt for a prims array d_prims (device,
@@ -240,17 +246,23 @@ int grmhd_step_cfl(grmhd_ctx* ctx);
  * *dt_out (host); E_STATE if it was not usable.  Synchronises. */
 int grmhd_last_dt(grmhd_ctx* ctx, double* dt_out);
 
-/* Copy the current padded prims (ghosts filled) to device memory d_out. */
+/* Copy the current padded prims (ghosts filled) to device memory d_out (the
+ * primitive state of the Glue section's step; with load_prims, the
+ * checkpoint). */
 int grmhd_get_prims(grmhd_ctx* ctx, double* d_out);
 
 /* Corner-centred div B of the current state, |div| / sqrt(-g) at interior
  * corners (corners on non-periodic boundaries excluded): max and mean to the
- * host; the per-corner field to d_divb (device, padded scalar layout) unless
- * it is NULL.  Synchronises. */
+ * host (the divergence diagnostic of the Extras section's field transports,
+ * in the corner form Flux-CT keeps at roundoff, Algorithm section); the
+ * per-corner field to d_divb (device, padded scalar layout) unless it is
+ * NULL.  Synchronises. */
 int grmhd_divb(grmhd_ctx* ctx, double* d_divb_or_null, double* max_out, double* mean_out);
 
 /* Inversion failures accumulated since creation (or the last reset), and
- * zones the floors acted on (per stage).  Synchronises. */
+ * zones the floors acted on (per stage): the failure and floor-hit counts
+ * of the Physics section's Inverter and Floors packages, which the
+ * Algorithm section's flux correction exists to reduce.  Synchronises. */
 int grmhd_get_status(grmhd_ctx* ctx, long long* n_inv_fail, long long* n_floor);
 /* All counters since creation (or the last reset), out[0..3]: inversion
  * failures, zones floors acted on, zones the first-order flux correction

@@ -393,54 +393,93 @@ __global__ void __launch_bounds__(BLOCK) k_adj_ift(Dev g, const double* __restri
     for (int v = 5; v < NVAR; v++) LU[v * nz + t] = lp[v] / m.gdet;
     return;
   }
-  // J[a][b] = dU_a / dP_b; column NVAR: dU/dgamma
-  double J[NVAR][NVAR + 1];
+  // Rows of the hydro conserved variables of the Jacobian: Jh[a][b] =
+  // dU_a / dP_b (a < 5), column NVAR dU_a / dgamma.  The field rows are
+  // sqrt(-g) on the diagonal (U_B = sqrt(-g) B, independent of the rest).
+  // One seed direction per pass; the column is stored by compare and select,
+  // so nothing held in registers is indexed by the pass counter.
+  double Jh[5][NVAR + 1];
+  double pv[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) pv[v] = P[v * nz + t];
+#pragma unroll 1
   for (int sd = 0; sd <= NVAR; sd++) {
     Dual p[NVAR];
 #pragma unroll
-    for (int v = 0; v < NVAR; v++) p[v] = Dual(P[v * nz + t], sd == v ? 1.0 : 0.0);
+    for (int v = 0; v < NVAR; v++) p[v] = Dual(pv[v], sd == v ? 1.0 : 0.0);
     Dual gam(g.gam, sd == NVAR ? 1.0 : 0.0);
     Fluid<Dual> f;
     fluid_state(p, m, f);
     Dual U[NVAR];
     prim_to_flux(p, f, m, gam, 0, U);
 #pragma unroll
-    for (int a = 0; a < NVAR; a++) J[a][sd] = U[a].d;
+    for (int c = 0; c <= NVAR; c++)
+      if (c == sd) {
+#pragma unroll
+        for (int a = 0; a < 5; a++) Jh[a][c] = U[a].d;
+      }
   }
-  // solve J^T x = lp: Gaussian elimination with partial pivoting on A = J^T
-  double A[NVAR][NVAR], x[NVAR];
+  // J^T x = lp with J = [[Jhh, Jhb], [0, sqrt(-g) I]]: first Jhh^T x_h = lp_h
+  // (Gaussian elimination with partial pivoting, every index fixed at
+  // compile time so the system stays in registers), then
+  // x_B = (lp_B - Jhb^T x_h) / sqrt(-g).
+  double A[5][5], x[NVAR];
 #pragma unroll
-  for (int a = 0; a < NVAR; a++) {
+  for (int a = 0; a < 5; a++) {
 #pragma unroll
-    for (int b = 0; b < NVAR; b++) A[a][b] = J[b][a];
+    for (int b = 0; b < 5; b++) A[a][b] = Jh[b][a];
     x[a] = lp[a];
   }
-  for (int col = 0; col < NVAR; col++) {
+#pragma unroll
+  for (int col = 0; col < 5; col++) {
     int piv = col;
     double best = fabs(A[col][col]);
-    for (int rr = col + 1; rr < NVAR; rr++)
-      if (fabs(A[rr][col]) > best) { best = fabs(A[rr][col]); piv = rr; }
-    if (piv != col) {
-      for (int b = 0; b < NVAR; b++) { double tmp = A[col][b]; A[col][b] = A[piv][b]; A[piv][b] = tmp; }
-      double tmp = x[col]; x[col] = x[piv]; x[piv] = tmp;
-    }
-    for (int rr = col + 1; rr < NVAR; rr++) {
-      double fct = A[rr][col] / A[col][col];
-      for (int b = col; b < NVAR; b++) A[rr][b] -= fct * A[col][b];
+#pragma unroll
+    for (int rr = col + 1; rr < 5; rr++)
+      if (fabs(A[rr][col]) > best) {
+        best = fabs(A[rr][col]);
+        piv = rr;
+      }
+#pragma unroll
+    for (int rr = col + 1; rr < 5; rr++)
+      if (rr == piv) {
+#pragma unroll
+        for (int b = col; b < 5; b++) {
+          const double tmp = A[col][b];
+          A[col][b] = A[rr][b];
+          A[rr][b] = tmp;
+        }
+        const double tmp = x[col];
+        x[col] = x[rr];
+        x[rr] = tmp;
+      }
+#pragma unroll
+    for (int rr = col + 1; rr < 5; rr++) {
+      const double fct = A[rr][col] / A[col][col];
+#pragma unroll
+      for (int b = col; b < 5; b++) A[rr][b] -= fct * A[col][b];
       x[rr] -= fct * x[col];
     }
   }
-  for (int rr = NVAR - 1; rr >= 0; rr--) {
-    double s = x[rr];
-    for (int b = rr + 1; b < NVAR; b++) s -= A[rr][b] * x[b];
-    x[rr] = s / A[rr][rr];
+#pragma unroll
+  for (int rr = 4; rr >= 0; rr--) {
+    double sum = x[rr];
+#pragma unroll
+    for (int b = rr + 1; b < 5; b++) sum -= A[rr][b] * x[b];
+    x[rr] = sum / A[rr][rr];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    double sum = lp[B1 + k];
+#pragma unroll
+    for (int a = 0; a < 5; a++) sum -= Jh[a][B1 + k] * x[a];
+    x[B1 + k] = sum / m.gdet;
   }
   double gz = 0.0;
 #pragma unroll
-  for (int v = 0; v < NVAR; v++) {
-    LU[v * nz + t] = x[v];
-    gz -= x[v] * J[v][NVAR];
-  }
+  for (int v = 0; v < NVAR; v++) LU[v * nz + t] = x[v];
+#pragma unroll
+  for (int a = 0; a < 5; a++) gz -= x[a] * Jh[a][NVAR];
 #pragma unroll
   for (int v = 0; v < 5; v++) LG[v * nz + t] = 0.0;
   GZ[t] += gz;

@@ -270,92 +270,6 @@ __device__ __forceinline__ void emhd_targets(const Dev& g, const double* __restr
   if (g.nu > 0.0) Xt[1] = 3.0 * (bbu - divu_sp / 3.0) * sqrt(g.nu * rho * g.tau / th0);
 }
 
-// The implicit solver's Newton iteration on the five hydro prims x from the
-// guess x0 (rho, u > 0), with the steps, Jacobian, pivoted QR, line search
-// and stopping rule of invert_implicit: res(x, R) fills the scaled residual
-// R[5]; jac is this thread's 25 LDS words for the Jacobian (LdsMat base).
-// Returns true with the root in x.  (invert_implicit keeps its own copy of
-// the loop: compiled through this template, its kernel produced different
-// and wrong states on torus steps, while this template gives parity here.)
-template <typename Res>
-__device__ __forceinline__ bool newton_hydro(const Dev& g, const double x0[5], Res res, double x[5],
-                                             double* jac) {
-#pragma clang fp contract(off)
-  const double fl[5] = {0.0, 0.0, 1e-3, 1e-3, 1e-3};
-#pragma unroll
-  for (int k = 0; k < 5; k++) x[k] = x0[k];
-  if (!(x[0] > 0.0) || !(x[1] > 0.0)) return false;
-  double R[5];
-  res(x, R);
-  double r2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < 5; k++) r2 += R[k] * R[k];
-  bool conv = false;
-  const double tol = g.tol > 1e-12 ? g.tol : 1e-12;
-  const LdsMat J{jac};
-  for (int it = 0; it < g.maxit && !conv; it++) {
-    // secant Jacobian, one column per pass (components picked by compare,
-    // so nothing in registers is indexed by the loop counter)
-#pragma unroll 1
-    for (int k = 0; k < 5; k++) {
-      double xk = x[0], flk = fl[0];
-#pragma unroll
-      for (int mm = 1; mm < 5; mm++)
-        if (mm == k) {
-          xk = x[mm];
-          flk = fl[mm];
-        }
-      const double ax = fabs(xk);
-      const double h = 1e-7 * (ax > flk ? ax : flk);
-      const double xkh = xk + h;
-      double xp[5];
-#pragma unroll
-      for (int mm = 0; mm < 5; mm++) xp[mm] = mm == k ? xkh : x[mm];
-      double Rp[5];
-      res(xp, Rp);
-      const double hh = xkh - xk;
-#pragma unroll
-      for (int mm = 0; mm < 5; mm++) J(mm, k) = (Rp[mm] - R[mm]) / hh;
-    }
-    double rhs[5], dx[5];
-#pragma unroll
-    for (int mm = 0; mm < 5; mm++) rhs[mm] = -R[mm];
-    if (!qr_pivot_solve(J, rhs, dx)) return false;
-    double lam = 1.0, xn[5], Rn[5], rn2 = 0.0;
-    bool ok = false;
-    for (int ls = 0; ls <= 8; ls++) {
-#pragma unroll
-      for (int mm = 0; mm < 5; mm++) xn[mm] = x[mm] + lam * dx[mm];
-      if (xn[0] > 0.0 && xn[1] > 0.0) {
-        res(xn, Rn);
-        rn2 = 0.0;
-#pragma unroll
-        for (int mm = 0; mm < 5; mm++) rn2 += Rn[mm] * Rn[mm];
-        ok = isfinite(rn2);
-        if (ok && rn2 < r2) break;
-      } else {
-        ok = false;
-      }
-      if (ls < 8) lam = 0.5 * lam;
-    }
-    if (!ok) return false;
-    conv = true;
-#pragma unroll
-    for (int mm = 0; mm < 5; mm++) {
-      const double ax = fabs(xn[mm]);
-      if (fabs(xn[mm] - x[mm]) > tol * (ax > fl[mm] ? ax : fl[mm])) conv = false;
-      x[mm] = xn[mm];
-      R[mm] = Rn[mm];
-    }
-    r2 = rn2;
-  }
-  if (!conv) return false;
-#pragma unroll
-  for (int k = 0; k < 5; k++)
-    if (!isfinite(x[k])) return false;
-  return true;
-}
-
 // Targets pass of a stage: X_target of every interior zone to xt (the
 // update pass reads them there and overwrites them with the X right-hand
 // sides, zone by zone) and the spatial div u to divu.

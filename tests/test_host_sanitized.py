@@ -1,0 +1,166 @@
+"""AddressSanitizer and UndefinedBehaviorSanitizer runs on the host.
+
+1. The library's primitive-variable recoveries -- 1D_W, Kastaun and the
+   implicit solver's Newton-Raphson with its LDS-layout Jacobian -- and its
+   zone-centre metric, compiled from the same source files as the GPU
+   kernels (tests/host/inversion_host.cpp, with a stand-in for the HIP
+   header), on every zone of a torus: conserved variables of the torus with
+   guesses 3 % off, and conserved variables of the state one oracle step
+   later with the step's starting state as the guess (a stage inversion).
+   Any out-of-range access, uninitialised use or undefined operation aborts
+   the run; the recovered prims must also match the oracle's recovery of the
+   same input (failure flags equal, prims to 1e-10 of the zone's scale plus
+   the implicit solver's own stopping resolution, 1e-12 of max(|x|, 1e-3)
+   for velocities, with a factor 10).
+2. The oracle itself (tests/host/oracle_driver.cpp), serially: SSPRK2 steps
+   with each recovery, floors and the first-order flux correction,
+   face-centred CT, Extended GRMHD, the CFL step and div B.  Results must
+   equal the regular (OpenMP) oracle build bit for bit.
+
+A sanitizer report makes the program exit non-zero with the report on
+stderr, which the assertion shows.
+"""
+
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import fm_torus, interior, RECON_MC, RECON_WENO5
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HOST = os.path.join(HERE, "host")
+FLAGS = ["-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+         "-fno-omit-frame-pointer", "-ffp-contract=off", "-Wno-unknown-pragmas"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+           UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+
+
+@pytest.fixture(scope="module")
+def programs(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    d = tmp_path_factory.mktemp("sanitized")
+    out = {}
+    for name, src in (("inversion", "inversion_host.cpp"), ("oracle", "oracle_driver.cpp")):
+        exe = str(d / name)
+        subprocess.run(["g++", *FLAGS, "-I", HOST, "-o", exe, os.path.join(HOST, src)], check=True,
+                       capture_output=True, text=True)
+        out[name] = exe
+    out["dir"] = d
+    return out
+
+
+def _run(exe, d, payload, tag):
+    inp, outp = str(d / (tag + ".in")), str(d / (tag + ".out"))
+    with open(inp, "wb") as f:
+        f.write(payload)
+    r = subprocess.run([exe, inp, outp], capture_output=True, text=True, env=ENV, timeout=600)
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
+    return open(outp, "rb").read()
+
+
+def _inversion_cases(grid, P, U, G):
+    """x1, x2, U[8], guess[8] per interior zone (k, j, i order)."""
+    x1, x2, _ = grid.centers()
+    Ui, Gi = interior(U), interior(G)
+    n3, n2, n1 = Ui.shape[1:]
+    X1 = np.broadcast_to(x1[3:-3][None, None, :], (n3, n2, n1))
+    X2 = np.broadcast_to(x2[3:-3][None, :, None], (n3, n2, n1))
+    cases = np.concatenate([X1.reshape(1, -1), X2.reshape(1, -1), Ui.reshape(8, -1), Gi.reshape(8, -1)])
+    return np.ascontiguousarray(cases.T)
+
+
+@pytest.mark.parametrize("inverter", [oracle.INV_1DW, oracle.INV_KASTAUN, oracle.INV_IMPLICIT],
+                         ids=["1dw", "kastaun", "implicit"])
+@pytest.mark.parametrize("kind", ["perturbed_guess", "stage"])
+def test_library_recoveries_under_sanitizers(programs, inverter, kind):
+    grid, P, _ = fm_torus(16, 24, 8)
+    gam = 13 / 9
+    c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, inverter=inverter)
+    if kind == "perturbed_guess":
+        rng = np.random.default_rng(11)
+        U = oracle.prims_to_cons(c, P)
+        G = P * (1 + 0.03 * rng.uniform(-1, 1, P.shape))
+    else:
+        P1, _, _ = oracle.run(c, P, -1, 1)
+        U = oracle.prims_to_cons(c, P1)
+        G = P
+    cases = _inversion_cases(grid, P, U, G)
+    n = cases.shape[0]
+    hdr = struct.pack("4i5d", n, inverter, 1, c.newton_maxit, gam, c.newton_tol, 1.0 - 1.0 / c.kastaun_wmax ** 2,
+                      grid.a, grid.hslope)
+    raw = _run(programs["inversion"], programs["dir"], hdr + cases.tobytes(), "inv_%d_%s" % (inverter, kind))
+    got = np.frombuffer(raw[:8 * 8 * n], dtype=np.float64).reshape(n, 8)
+    flags = np.frombuffer(raw[8 * 8 * n:], dtype=np.int32)
+    ref, nfail, rflags = oracle.cons_to_prims(c, U, G)
+    rp = interior(ref).reshape(8, -1).T
+    rf = interior(rflags).reshape(-1)
+    assert np.array_equal(flags != 0, rf != 0), (int(flags.sum()), int((rf != 0).sum()))
+    ok = flags == 0
+    # the implicit solver stops when every step is within 1e-12 max(|x|, f),
+    # f = 1e-3 for the velocity components: two converged answers of a
+    # velocity at rest may differ by that much
+    fl = [0.0, 0.0, 1e-3, 1e-3, 1e-3, 0.0, 0.0, 0.0]
+    for v, group in enumerate([[0], [1], [2, 3, 4], [2, 3, 4], [2, 3, 4], [5, 6, 7], [5, 6, 7], [5, 6, 7]]):
+        scale = np.abs(rp[:, group]).sum(axis=1)
+        scale = scale + 1e-10 * scale.max()
+        err = np.abs(got[ok, v] - rp[ok, v])
+        bar = 1e-10 * scale[ok] + 1e-11 * np.maximum(np.abs(rp[ok, v]), fl[v])
+        worst = np.argmax(err / bar) if err.size else 0
+        assert (err <= bar).all(), (v, err[worst], bar[worst])
+
+
+def _oracle_job(programs, job, c, P, extra, dt, nsteps, tag):
+    cb = bytes(memoryview(c))
+    Pf = np.ascontiguousarray(P, dtype=np.float64)
+    Xf = np.ascontiguousarray(extra if extra is not None else np.zeros(0), dtype=np.float64)
+    payload = (struct.pack("iid", job, nsteps, dt) + cb + struct.pack("q", Pf.size) + Pf.tobytes() +
+               struct.pack("q", Xf.size) + Xf.tobytes())
+    raw = _run(programs["oracle"], programs["dir"], payload, tag)
+    fails = struct.unpack("q", raw[:8])[0]
+    o = 8
+    Po = np.frombuffer(raw[o:o + 8 * Pf.size], dtype=np.float64).reshape(Pf.shape)
+    o += 8 * Pf.size
+    Xo = np.frombuffer(raw[o:o + 8 * Xf.size], dtype=np.float64).reshape(Xf.shape)
+    o += 8 * Xf.size
+    tail = np.frombuffer(raw[o:], dtype=np.float64)
+    return fails, Po, Xo, tail
+
+
+@pytest.mark.parametrize("opts", [dict(recon=RECON_WENO5), dict(recon=RECON_MC, inverter=oracle.INV_KASTAUN),
+                                  dict(recon=RECON_WENO5, inverter=oracle.INV_IMPLICIT),
+                                  dict(recon=RECON_MC, floors=True, fofc=True)],
+                         ids=["weno5_1dw", "mc_kastaun", "weno5_implicit", "mc_floors_fofc"])
+def test_oracle_steps_under_sanitizers(programs, opts):
+    grid, P, _ = fm_torus(12, 12, 4)
+    c = oracle.cfg(grid, gam=13 / 9, **opts)
+    fails, Po, _, dts = _oracle_job(programs, 0, c, P, None, -1.0, 2, "step")
+    ref, rfails, rdts = oracle.run(c, P, -1, 2)
+    assert fails == rfails and np.array_equal(dts, rdts)
+    assert np.array_equal(Po, ref)
+
+
+def test_oracle_face_ct_emhd_dt_divb_under_sanitizers(programs):
+    grid, P, info = fm_torus(12, 12, 4)
+    c = oracle.cfg(grid, gam=13 / 9, recon=RECON_WENO5, ct=2)
+    fails, Po, Fo, dts = _oracle_job(programs, 1, c, P, info["faces"], -1.0, 2, "face")
+    ref, Fref, rfails, rdts = oracle.run_face(c, P, info["faces"], -1, 2)
+    assert fails == rfails and np.array_equal(Po, ref) and np.array_equal(Fo, Fref)
+    ce = oracle.cfg(grid, gam=13 / 9, recon=RECON_MC, integrator=oracle.INTEG_PC, tau_r=0.5, chi_emhd=0.2,
+                    nu_emhd=0.2)
+    X = np.zeros((2,) + P.shape[1:])
+    X[:, 3:-3, 3:-3, 3:-3] = 1e-3 * np.random.default_rng(2).standard_normal((2, 4, 12, 12))
+    fails, Po, Xo, dts = _oracle_job(programs, 2, ce, P, X, -1.0, 2, "emhd")
+    ref, Xref, rfails, rdts = oracle.run_emhd(ce, P, X, -1, 2)
+    assert fails == rfails and np.array_equal(Po, ref) and np.array_equal(Xo, Xref)
+    c0 = oracle.cfg(grid, gam=13 / 9)
+    _, _, _, tail = _oracle_job(programs, 3, c0, P, None, 0.0, 0, "dt")
+    assert tail[0] == oracle.estimate_dt(c0, P)
+    mx, mean = oracle.divb(c0, P)
+    assert tail[1] == mx and tail[2] == mean
