@@ -100,6 +100,7 @@ def _declare(lib):
     lib.orc_run_emhd.argtypes = [P, _D, _D, C.c_double, C.c_int, _D]
     lib.orc_run_emhd.restype = C.c_long
     lib.orc_cons_emhd.argtypes = [P, _D, _D, _D]
+    lib.orc_emhd_targets.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, _D]
     lib.orc_run_face.argtypes = [P, _D, _D, C.c_double, C.c_int, _D, _I]
     lib.orc_run_face.restype = C.c_long
     lib.orc_face_divb.argtypes = [P, _D, _D, _D]
@@ -205,6 +206,15 @@ def run_emhd(c, prims, extra, dt, nsteps=1, fma=False):
     dts = np.zeros(max(nsteps, 1))
     fails = lib(fma=fma).orc_run_emhd(C.byref(c), _ptr(P), _ptr(X), float(dt), int(nsteps), _ptr(dts))
     return P, X, int(fails), dts
+
+
+def emhd_targets(c, prims, i, j, k):
+    """Extended GRMHD targets at interior zone (i, j, k): the rescaled
+    heat-flux and anisotropy targets and the spatial part of div u."""
+    P = np.ascontiguousarray(prims, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_emhd_targets(C.byref(c), _ptr(P), int(i), int(j), int(k), _ptr(out))
+    return out[0], out[1], out[2]
 
 
 def cons_emhd(c, prims, extra):

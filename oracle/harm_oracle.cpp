@@ -2090,6 +2090,22 @@ void orc_cons_emhd(const orc_cfg* c, const double* prims, const double* extra, d
       }
 }
 
+// Extended GRMHD targets at interior zone (i, j, k) of padded prims (ghosts
+// filled here on a copy): out[0], out[1] the rescaled heat-flux and
+// anisotropy targets, out[2] the spatial part of div u.
+void orc_emhd_targets(const orc_cfg* c, const double* prims, int i, int j, int k, double* out) {
+  Grid g(*c);
+  const EmhdPar e{c->tau_r, c->chi_emhd, c->nu_emhd};
+  std::vector<real> P;
+  load(g, prims, P);
+  fill_ghosts(g, P);
+  real Xt[NX], divu_sp;
+  emhd_targets(g, P, e, i, j, k, Xt, divu_sp);
+  out[0] = (double)Xt[0];
+  out[1] = (double)Xt[1];
+  out[2] = (double)divu_sp;
+}
+
 // Face-centred CT (cfg ct = 1 or 2): as orc_run, with the face fields
 // faces = double[3][padded] (sqrt(-g) B^d on the lower d-face of each zone)
 // advanced alongside; the interior zones' B prims are set from the faces

@@ -1567,3 +1567,148 @@ def test_emhd_heat_conduction_follows_the_field():
     (sx_off, sy_off), (sx_on, sy_on) = moments(off), moments(on)
     assert sx_on > 2.0 * sx0 and abs(sx_off - sx0) < 0.01 * sx0
     assert abs(sy_on - sy_off) < 0.02 * (sx_on - sx0)
+
+
+# The targets: the heat flux relaxes towards -chi rho bh^mu (d_mu Theta +
+# Theta a_mu) and the anisotropy towards 3 nu rho (bh^mu bh^nu nabla_mu u_nu
+# - div u / 3), each rescaled like its variable.  Closed forms of both for
+# states whose gradients and accelerations are known.
+
+EMHD_TAU, EMHD_CHI, EMHD_NU = 0.6, 0.25, 0.15
+
+
+def _target_scales(rho, theta):
+    """(heat flux per unit of bh.(dTheta + Theta a) / Theta, anisotropy per
+    unit of shear): the rescalings sqrt(chi rho tau_R) and sqrt(nu rho
+    tau_R / Theta)."""
+    return math.sqrt(EMHD_CHI * rho * EMHD_TAU), math.sqrt(EMHD_NU * rho * EMHD_TAU / theta)
+
+
+def _static_schwarzschild(n, r0=8.0, width=0.4):
+    """A fluid at rest (u^i = 0) in the Schwarzschild metric in modified
+    Kerr-Schild coordinates (a = 0), uniform rho and u, radial field: the
+    normal-observer velocity of a static fluid is u~^r = u^t beta^r =
+    u^t (2M/r) / (1 + 2M/r), u^t = (1 - 2M/r)^-1/2, and u~^x1 = u~^r / r."""
+    from workloads import BC_OUTFLOW
+    g = GridSpec(n, n, 1, x1min=math.log(r0) - width / 2, x1max=math.log(r0) + width / 2, x2min=0.3,
+                 x2max=0.7, bc=(BC_OUTFLOW,) * 4 + (BC_PERIODIC,) * 2, metric=METRIC_KERR_MKS, a=0.0,
+                 hslope=HSLOPE)
+    x1, _, _ = g.centers()
+    r = np.exp(x1)
+    ut = 1.0 / np.sqrt(1.0 - 2.0 / r)
+    P = np.zeros((8, 7, n + 6, n + 6))
+    P[0], P[1] = 1.3, 0.7
+    P[2] = (ut * (2.0 / r) / (1.0 + 2.0 / r) / r)[None, None, :]
+    P[5] = (0.5 / r ** 2)[None, None, :]
+    return g, P, r
+
+
+def test_emhd_heat_flux_target_of_a_static_fluid_is_its_gravitational_acceleration():
+    """A static fluid at uniform temperature still conducts heat: its
+    acceleration is the static observer's, a = M / (r^2 (1 - 2M/r)^1/2)
+    outward, and with the field radial bh.a = |a|, so the heat-flux target
+    is -|a| sqrt(chi rho tau_R) (heat flows inward, the relativistic
+    Tolman effect), exactly: u^i = 0 leaves only the connection term.  A
+    static flow has no expansion and bh is orthogonal to u, so the
+    anisotropy target is zero up to the centred differences of u_mu, which
+    fall at second order, and the spatial div u is zero."""
+    gam = 4.0 / 3.0
+    rho, theta = 1.3, (gam - 1.0) * 0.7 / 1.3
+    sq, _ = _target_scales(rho, theta)
+    aniso = []
+    for n in (8, 16, 32):
+        g, P, r = _static_schwarzschild(n)
+        c = _emhd_cfg(g, gam, tau_r=EMHD_TAU, chi=EMHD_CHI, nu=EMHD_NU)
+        i = n // 2
+        rr = r[i + 3]
+        xq, xa, divu = oracle.emhd_targets(c, P, i, n // 2, 0)
+        assert xq == pytest.approx(-sq / (rr * rr * math.sqrt(1.0 - 2.0 / rr)), rel=1e-13)
+        assert abs(divu) < 1e-14
+        aniso.append(abs(xa))
+    assert 3.5 < aniso[0] / aniso[1] < 4.5 and 3.5 < aniso[1] / aniso[2] < 4.5, aniso
+
+
+def _flat_cube(n=5):
+    return GridSpec(n, n, n, x1min=-0.5, x1max=0.5, x2min=-0.5, x2max=0.5, x3min=-0.5, x3max=0.5)
+
+
+@pytest.mark.parametrize("field_axis", [0, 1, 2])
+@pytest.mark.parametrize("flow_axis", [0, 1, 2])
+def test_emhd_anisotropy_target_of_a_linear_compression(flow_axis, field_axis):
+    """Flat space, u^a = alpha x^a along one axis (a uniform expansion rate
+    alpha), the zone at x^a = 0 at rest, uniform rho and Theta: div u =
+    alpha, the expansion along the field is alpha if the field lies along
+    the flow and 0 across it, so the anisotropy target is 3 (alpha -
+    alpha/3) = 2 alpha or 3 (0 - alpha/3) = -alpha times sqrt(nu rho tau_R
+    / Theta), and with no acceleration and no temperature gradient the
+    heat-flux target is zero."""
+    gam, rho, u, alpha = 4.0 / 3.0, 1.3, 0.7, 0.3
+    g = _flat_cube()
+    n = g.n1
+    P = np.zeros((8, n + 6, n + 6, n + 6))
+    P[0], P[1], P[5 + field_axis] = rho, u, 0.8
+    shape = [1, 1, 1]
+    shape[2 - flow_axis] = n + 6
+    P[2 + flow_axis] = (alpha * g.dx[flow_axis] * (np.arange(n + 6) - 5)).reshape(shape)
+    c = _emhd_cfg(g, gam, tau_r=EMHD_TAU, chi=EMHD_CHI, nu=EMHD_NU)
+    xq, xa, divu = oracle.emhd_targets(c, P, 2, 2, 2)
+    _, sa = _target_scales(rho, (gam - 1.0) * u / rho)
+    assert divu == pytest.approx(alpha, rel=1e-14)
+    expect = 2.0 * alpha if field_axis == flow_axis else -alpha
+    assert xa == pytest.approx(expect * sa, rel=1e-14)
+    assert xq == 0.0
+
+
+@pytest.mark.parametrize("field_axis", [0, 1, 2])
+@pytest.mark.parametrize("grad_axis", [0, 1, 2])
+def test_emhd_heat_flux_target_of_a_temperature_gradient_follows_the_field(grad_axis, field_axis):
+    """Flat space at rest, Theta = Theta0 (1 + beta x^a) (rho = rho0 / (1 +
+    beta x^a), u uniform): along the field the heat-flux target is
+    -beta sqrt(chi rho0 tau_R) at x^a = 0 (down the gradient), across it
+    zero; no flow, so the anisotropy target and div u are zero."""
+    gam, rho0, u, beta = 4.0 / 3.0, 1.3, 0.7, 0.4
+    g = _flat_cube()
+    n = g.n1
+    P = np.zeros((8, n + 6, n + 6, n + 6))
+    shape = [1, 1, 1]
+    shape[2 - grad_axis] = n + 6
+    P[0] = (rho0 / (1.0 + beta * g.dx[grad_axis] * (np.arange(n + 6) - 5))).reshape(shape)
+    P[1], P[5 + field_axis] = u, 0.8
+    c = _emhd_cfg(g, gam, tau_r=EMHD_TAU, chi=EMHD_CHI, nu=EMHD_NU)
+    xq, xa, divu = oracle.emhd_targets(c, P, 2, 2, 2)
+    sq, _ = _target_scales(rho0, (gam - 1.0) * u / rho0)
+    if grad_axis == field_axis:
+        assert xq == pytest.approx(-beta * sq, rel=1e-14)
+    else:
+        assert xq == 0.0
+    assert xa == 0.0 and divu == 0.0
+
+
+def test_emhd_targets_of_a_moving_zone_converge_to_the_steady_flow_closed_forms():
+    """Flat space, steady flow u^x = alpha x, the zone at x0 != 0 (moving),
+    field along x.  bh is the unit vector orthogonal to u in the t-x plane,
+    bh = (u^x, u^t, 0, 0); the acceleration is a_x = u^x d_x u_x = alpha^2
+    x0 and a_t = u^x d_x u_t = -alpha^3 x0^2 / u^t, so bh.a = alpha^2 x0 /
+    u^t and the heat-flux target is -alpha^2 x0 sqrt(chi rho tau_R) / u^t;
+    bh bh grad u = alpha (the whole expansion is along the field) and div u
+    = alpha, so the anisotropy target is 2 alpha sqrt(nu rho tau_R /
+    Theta).  u_t is not linear in x, so its centred difference brings a
+    second-order error: both targets converge at second order, div u (of
+    the linear u^x) is exact."""
+    gam, rho, u, alpha, x0 = 4.0 / 3.0, 1.3, 0.7, 0.8, 0.6
+    sq, sa = _target_scales(rho, (gam - 1.0) * u / rho)
+    ut = math.sqrt(1.0 + (alpha * x0) ** 2)
+    eq, ea = -alpha * alpha * x0 * sq / ut, 2.0 * alpha * sa
+    errs = []
+    for h in (0.1, 0.05, 0.025):
+        g = GridSpec(5, 1, 1, x1min=x0 - 2.5 * h, x1max=x0 + 2.5 * h)
+        P = np.zeros((8, 7, 7, 11))
+        P[0], P[1], P[5] = rho, u, 0.8
+        P[2] = (alpha * (x0 + h * (np.arange(11) - 5)))[None, None, :]
+        xq, xa, divu = oracle.emhd_targets(_emhd_cfg(g, gam, tau_r=EMHD_TAU, chi=EMHD_CHI, nu=EMHD_NU),
+                                           P, 2, 0, 0)
+        assert divu == pytest.approx(alpha, rel=1e-14)
+        errs.append((abs(xq / eq - 1.0), abs(xa / ea - 1.0)))
+    for a, b in zip(errs, errs[1:]):
+        assert 3.8 < a[0] / b[0] < 4.2 and 3.8 < a[1] / b[1] < 4.2, errs
+    assert errs[-1][0] < 1e-4 and errs[-1][1] < 1e-4
