@@ -1,7 +1,8 @@
 // The library's primitive-variable recoveries (1D_W, Kastaun, the implicit
 // solver's Newton-Raphson with its LDS-layout Jacobian) and its zone-centre
 // metric, compiled for the host from the same source files as the GPU
-// kernels, for a run under AddressSanitizer and UndefinedBehaviorSanitizer.
+// kernels, for runs under AddressSanitizer and UndefinedBehaviorSanitizer,
+// and under MemorySanitizer.
 //
 //   inversion_host <in> <out>
 // in:  int32 ncases, int32 inverter (0 1D_W, 1 Kastaun, 2 implicit),
@@ -59,16 +60,21 @@ int main(int argc, char** argv) {
   std::vector<int> flags(n);
   need(fread(in.data(), sizeof(double), in.size(), f) == in.size(), "short input");
   fclose(f);
-  // one thread's slots of a workgroup's Jacobian array (stride BLOCK)
-  std::vector<double> jac(25 * BLOCK);
   for (int q = 0; q < n; q++) {
     const double* c = &in[(size_t)q * 18];
     PointMetric<double> m;
     metric_point(st, c[0], c[1], m.gcov, m.gcon, m.gdet, m.alpha);
     double P[NVAR];
-    if (g.inverter == GRMHD_INV_IMPLICIT)
-      flags[q] = invert_implicit(g, m, c + 2, c + 10, P, jac.data() + (q % BLOCK));
-    else
+    if (g.inverter == GRMHD_INV_IMPLICIT) {
+      // one thread's slots of a workgroup's Jacobian array (stride BLOCK),
+      // freshly allocated and left uninitialised for every zone, so that a
+      // read of a slot the solver has not written is seen (MemorySanitizer;
+      // AddressSanitizer fills new blocks with garbage)
+      double* jac = (double*)malloc(sizeof(double) * 25 * BLOCK);
+      need(jac != nullptr, "out of memory");
+      flags[q] = invert_implicit(g, m, c + 2, c + 10, P, jac + (q % BLOCK));
+      free(jac);
+    } else
       flags[q] = invert(g, m, c + 2, c + 10, P);
     memcpy(&out[(size_t)q * 8], P, sizeof(P));
   }

@@ -4,7 +4,10 @@
    implicit solver's Newton-Raphson with its LDS-layout Jacobian -- and its
    zone-centre metric, compiled from the same source files as the GPU
    kernels (tests/host/inversion_host.cpp, with a stand-in for the HIP
-   header), on every zone of a torus: conserved variables of the torus with
+   header), once with AddressSanitizer and UndefinedBehaviorSanitizer and
+   once with MemorySanitizer (clang; an uninitialised read anywhere, the
+   Jacobian's storage being fresh and uninitialised for every zone), on
+   every zone of a torus: conserved variables of the torus with
    guesses 3 % off, and conserved variables of the state one oracle step
    later with the step's starting state as the guess (a stage inversion).
    Any out-of-range access, uninitialised use or undefined operation aborts
@@ -34,10 +37,12 @@ from workloads import fm_torus, interior, RECON_MC, RECON_WENO5
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HOST = os.path.join(HERE, "host")
-FLAGS = ["-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-         "-fno-omit-frame-pointer", "-ffp-contract=off", "-Wno-unknown-pragmas"]
+COMMON = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off", "-Wno-unknown-pragmas"]
+FLAGS = COMMON + ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+MSAN_FLAGS = COMMON + ["-fsanitize=memory", "-fsanitize-memory-track-origins=2"]
+CLANG = "/opt/rocm/llvm/bin/clang++"
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
-           UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+           UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1", MSAN_OPTIONS="halt_on_error=1")
 
 
 @pytest.fixture(scope="module")
@@ -51,6 +56,11 @@ def programs(tmp_path_factory):
         subprocess.run(["g++", *FLAGS, "-I", HOST, "-o", exe, os.path.join(HOST, src)], check=True,
                        capture_output=True, text=True)
         out[name] = exe
+    # MemorySanitizer (uninitialised reads) needs clang and its runtime
+    msan = str(d / "inversion_msan")
+    r = subprocess.run([CLANG, *MSAN_FLAGS, "-I", HOST, "-o", msan, os.path.join(HOST, "inversion_host.cpp")],
+                       capture_output=True, text=True) if os.path.exists(CLANG) else None
+    out["inversion_msan"] = msan if r is not None and r.returncode == 0 else None
     out["dir"] = d
     return out
 
@@ -61,7 +71,8 @@ def _run(exe, d, payload, tag):
         f.write(payload)
     r = subprocess.run([exe, inp, outp], capture_output=True, text=True, env=ENV, timeout=600)
     assert r.returncode == 0, r.stderr[-4000:]
-    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
+    for report in ("runtime error", "AddressSanitizer", "MemorySanitizer"):
+        assert report not in r.stderr, r.stderr[-4000:]
     return open(outp, "rb").read()
 
 
@@ -76,10 +87,14 @@ def _inversion_cases(grid, P, U, G):
     return np.ascontiguousarray(cases.T)
 
 
+@pytest.mark.parametrize("sanitizer", ["asan_ubsan", "msan"])
 @pytest.mark.parametrize("inverter", [oracle.INV_1DW, oracle.INV_KASTAUN, oracle.INV_IMPLICIT],
                          ids=["1dw", "kastaun", "implicit"])
 @pytest.mark.parametrize("kind", ["perturbed_guess", "stage"])
-def test_library_recoveries_under_sanitizers(programs, inverter, kind):
+def test_library_recoveries_under_sanitizers(programs, inverter, kind, sanitizer):
+    exe = programs["inversion"] if sanitizer == "asan_ubsan" else programs["inversion_msan"]
+    if exe is None:
+        pytest.skip("no clang with the MemorySanitizer runtime")
     grid, P, _ = fm_torus(16, 24, 8)
     gam = 13 / 9
     c = oracle.cfg(grid, gam=gam, recon=RECON_WENO5, inverter=inverter)
@@ -95,7 +110,7 @@ def test_library_recoveries_under_sanitizers(programs, inverter, kind):
     n = cases.shape[0]
     hdr = struct.pack("4i5d", n, inverter, 1, c.newton_maxit, gam, c.newton_tol, 1.0 - 1.0 / c.kastaun_wmax ** 2,
                       grid.a, grid.hslope)
-    raw = _run(programs["inversion"], programs["dir"], hdr + cases.tobytes(), "inv_%d_%s" % (inverter, kind))
+    raw = _run(exe, programs["dir"], hdr + cases.tobytes(), "inv_%d_%s_%s" % (inverter, kind, sanitizer))
     got = np.frombuffer(raw[:8 * 8 * n], dtype=np.float64).reshape(n, 8)
     flags = np.frombuffer(raw[8 * 8 * n:], dtype=np.int32)
     ref, nfail, rflags = oracle.cons_to_prims(c, U, G)
