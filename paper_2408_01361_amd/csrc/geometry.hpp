@@ -147,4 +147,18 @@ __device__ __forceinline__ void connection_point(const SpaceTime& st, double x1,
     }
 }
 
+// Metric-derivative rows of the geometric source at (x1, x2) (layout NDG):
+// D[(nu - 1) * 10 + s] = d_nu g_s / 2 on the diagonal, d_nu g_s off it.
+__device__ __forceinline__ void source_metric_point(const SpaceTime& st, double x1, double x2, double D[NDG]) {
+  Dual2 gd[10];
+  metric_cov_dual(st, x1, x2, gd);
+  for (int a = 0; a < 4; a++)
+    for (int b = a; b < 4; b++) {
+      const int q = sidx(a, b);
+      const double f = a == b ? 0.5 : 1.0;
+      D[q] = f * gd[q].d1;
+      D[10 + q] = f * gd[q].d2;
+    }
+}
+
 }  // namespace grmhd

@@ -47,9 +47,13 @@ constexpr int NG = 3;
 constexpr int BLOCK = 256;
 constexpr int MAX_PARTIALS = 65536;
 
-// Waves per SIMD the update kernel is compiled for (its register budget).
+// Waves per SIMD the update kernel is compiled for (its register budget):
+// without and with the CFL-rate evaluation of the new state.
 #ifndef UPDATE_WAVES
 #define UPDATE_WAVES 3
+#endif
+#ifndef UPDATE_WAVES_RATE
+#define UPDATE_WAVES_RATE 3
 #endif
 
 // Everything a kernel needs to know about the grid, passed by value.
@@ -154,11 +158,12 @@ __device__ __forceinline__ bool sched_index(const Sched& s, unsigned bid, unsign
 // ------------------------------------------------------------- geometry --
 
 // Tables over the padded (x1, x2) plane: metric at zone centres, x1 faces,
-// x2 faces; sqrt(-g) at (x1, x2) corners; connection at centres.  x3 faces
-// share the centre values (nothing depends on x3).  Pole faces and corners
-// are left zero: nothing reads them.
+// x2 faces; sqrt(-g) at (x1, x2) corners; connection and the geometric
+// source's metric-derivative rows at centres.  x3 faces share the centre
+// values (nothing depends on x3).  Pole faces and corners are left zero:
+// nothing reads them.
 __global__ void k_geometry(Dev g, double* tabC, double* tabF1, double* tabF2, double* corner,
-                           double* conn) {
+                           double* conn, double* dgs) {
   long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (t >= g.plane) return;
   int i = (int)(t % g.s1) - NG, j = (int)(t / g.s1) - NG;
@@ -187,9 +192,14 @@ __global__ void k_geometry(Dev g, double* tabC, double* tabF1, double* tabF2, do
     for (int f = 0; f < G_NF; f++) tabF2[f * g.plane + t] = 0.0;
     corner[t] = 0.0;
   }
-  double cn[40];
-  connection_point(g.st, xc1, xc2, cn);
-  for (int q = 0; q < 40; q++) conn[q * g.plane + t] = cn[q];
+  if (conn) {  // (blocks of a pack have no connection table: nothing there reads it)
+    double cn[40];
+    connection_point(g.st, xc1, xc2, cn);
+    for (int q = 0; q < 40; q++) conn[q * g.plane + t] = cn[q];
+  }
+  double D[NDG];
+  source_metric_point(g.st, xc1, xc2, D);
+  for (int q = 0; q < NDG; q++) dgs[q * g.plane + t] = D[q];
 }
 
 // ------------------------------------------------------------ boundaries --
@@ -1010,26 +1020,17 @@ __device__ __forceinline__ void load_conn(const double* __restrict__ conn, long 
   for (int f = 0; f < 40; f++) cn[f] = conn[f * plane + q];
 }
 
-// sqrt(-g) T^k_l Gamma^l_{nu k} into S[nu]: rows of T formed one at a time,
-// connection coefficients read where they are used; each sum runs over k,
-// then l.
+// Geometric source of the x1 and x2 momentum equations, S[0] and S[1], from
+// the zone's metric-derivative rows (the energy and x3-momentum sources
+// vanish identically in a metric independent of x0 and x3).
 __device__ __forceinline__ void geometric_source(const double p[NVAR], const Fluid<double>& f,
                                                  const PointMetric<double>& m,
-                                                 const double* __restrict__ conn, long plane, long q,
-                                                 double gam, double S[4]) {
-#pragma clang fp contract(off)
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+                                                 const double* __restrict__ dgs, long plane, long q,
+                                                 double gam, double S[2]) {
+  double D[NDG];
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    double Tk[4];
-    tmunu_row(p, f, gam, k, Tk);
-#pragma unroll
-    for (int nu = 0; nu < 4; nu++)
-#pragma unroll
-      for (int l = 0; l < 4; l++) s[nu] += Tk[l] * conn[(l * 10 + sidx(nu, k)) * plane + q];
-  }
-#pragma unroll
-  for (int nu = 0; nu < 4; nu++) S[nu] = m.gdet * s[nu];
+  for (int r = 0; r < NDG; r++) D[r] = x2_offdiag(r % 10) ? 0.0 : dgs[r * plane + q];
+  metric_source(p, f, m, gam, D, S);
 }
 
 // One stage for every interior zone.  STAGE 1: V = (Un + U1)/2 with
@@ -1073,7 +1074,7 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
                                             const FT* __restrict__ F3, const FT* __restrict__ E1,
                                             const FT* __restrict__ E2, const FT* __restrict__ E3,
                                             const double* __restrict__ tabC,
-                                            const double* __restrict__ conn, double dt,
+                                            const double* __restrict__ dgs, double dt,
                                             unsigned long long* fails, unsigned char* __restrict__ flags,
                                             int i, int j, int k, double* rate = nullptr,
                                             unsigned char* __restrict__ mark = nullptr,
@@ -1095,14 +1096,15 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
 
   double L[NVAR];
   {
-    double S[4];
-    geometric_source(p, f, m, conn, g.plane, q2, g.gam, S);
+    double S[2];
+    geometric_source(p, f, m, dgs, g.plane, q2, g.gam, S);
 #pragma unroll
     for (int v = 0; v < 5; v++) {
       double d1 = ((double)F1[v * nz + c + si] - (double)F1[v * nz + c]) / g.dx1;
       double d2 = ((double)F2[v * nz + c + sj] - (double)F2[v * nz + c]) / g.dx2;
       double d3 = ((double)F3[v * nz + c + sk] - (double)F3[v * nz + c]) / g.dx3;
-      L[v] = -((d1 + d2) + d3) + (v == RHO ? 0.0 : S[v - 1]);
+      L[v] = -((d1 + d2) + d3);
+      if (v == U1 || v == U2) L[v] += S[v - U1];
     }
     if constexpr (!FACE) {
       ct_field_rate(g, E1, E2, E3, c, L);
@@ -1162,11 +1164,12 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
 // grid-uniform test of the mark count), and then adds that count to the
 // correction's running total.
 template <int STAGE, typename FT, bool RATE, int MODE, bool FACE, int INTEG = GRMHD_INTEG_SSPRK2>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES, 8)))
+__global__ void __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(RATE ? UPDATE_WAVES_RATE : UPDATE_WAVES, 8)))
 k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ Pout,
          double* __restrict__ V, const FT* __restrict__ F1, const FT* __restrict__ F2,
          const FT* __restrict__ F3, const FT* __restrict__ E1, const FT* __restrict__ E2,
-         const FT* __restrict__ E3, const double* __restrict__ tabC, const double* __restrict__ conn,
+         const FT* __restrict__ E3, const double* __restrict__ tabC, const double* __restrict__ dgs,
          double dt, const double* __restrict__ dt_dev, unsigned long long* fails,
          unsigned char* __restrict__ flags, double* __restrict__ rate_partial,
          unsigned char* __restrict__ mark, const double* __restrict__ ph1,
@@ -1181,14 +1184,14 @@ k_update(Dev g, Sched box, const double* __restrict__ Pin, double* __restrict__ 
   if (dt_dev) dt = *dt_dev;
   if (!RATE) {
     if (in)
-      update_zone<STAGE, FT, false, MODE, FACE, INTEG>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn,
+      update_zone<STAGE, FT, false, MODE, FACE, INTEG>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, dgs,
                                                        dt, fails, flags, i, j, k, nullptr, mark, ph1, ph2,
                                                        ph3, ustar);
     return;
   }
   double r = 0.0, sm = 0.0;
   if (in)
-    update_zone<STAGE, FT, true, MODE, FACE, INTEG>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, conn, dt,
+    update_zone<STAGE, FT, true, MODE, FACE, INTEG>(g, Pin, Pout, V, F1, F2, F3, E1, E2, E3, tabC, dgs, dt,
                                                     fails, flags, i, j, k, &r, mark, ph1, ph2, ph3, ustar);
   block_reduce(r, sm);
   if (threadIdx.x == 0) rate_partial[blockIdx.x] = r;
@@ -1467,7 +1470,7 @@ struct grmhd_ctx {
   // workspace carve (device)
   double *P, *P1, *V;
   void *F[3], *E[3];
-  double *tabC, *tabF1, *tabF2, *corner, *conn;
+  double *tabC, *tabF1, *tabF2, *corner, *conn, *dgs;
   double *pmax, *psum, *result;
   unsigned long long* fails;  // counters, slots C_* (failures, floors, flux-correction marks, ...)
   unsigned char* mark;        // per zone: marked by the flux correction's provisional pass
@@ -1578,6 +1581,7 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, const grmhd_params* 
   double* tabF2 = cv.take<double>(base, G_NF * plane);
   double* corner = cv.take<double>(base, plane);
   double* conn = cv.take<double>(base, NCONN * plane);
+  double* dgs = cv.take<double>(base, NDG * plane);
   double* pmax = cv.take<double>(base, MAX_PARTIALS);
   double* psum = cv.take<double>(base, MAX_PARTIALS);
   double* result = cv.take<double>(base, 8);
@@ -1626,6 +1630,7 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, const grmhd_params* 
     c->P = P; c->P1 = P1; c->V = V;
     for (int d = 0; d < 3; d++) { c->F[d] = F[d]; c->E[d] = E[d]; }
     c->tabC = tabC; c->tabF1 = tabF1; c->tabF2 = tabF2; c->corner = corner; c->conn = conn;
+    c->dgs = dgs;
     c->pmax = pmax; c->psum = psum; c->result = result; c->fails = fails; c->pdt = pdt;
   }
   return cv.off;
@@ -1799,7 +1804,7 @@ int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
   auto go = [&](auto kernel, double* partial) {
     return launch(c, cls, kernel, nb, g, bz, Pin, Pout, c->V, (const FT*)c->F[0], (const FT*)c->F[1],
                   (const FT*)c->F[2], (const FT*)c->E[0], (const FT*)c->E[1], (const FT*)c->E[2],
-                  (const double*)c->tabC, (const double*)c->conn, dt, dt_dev, fails ? fails : c->fails, flags,
+                  (const double*)c->tabC, (const double*)c->dgs, dt, dt_dev, fails ? fails : c->fails, flags,
                   partial, c->mark, p1, p2, p3, c->ustar);
   };
   if constexpr (INTEG != GRMHD_INTEG_SSPRK2) {  // the plain Flux-CT path only
@@ -2141,7 +2146,7 @@ int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* me
   c->dev = make_dev(grid, metric, params);
   Dev& g = c->dev;
   k_geometry<<<blocks_for(g.plane), BLOCK, 0, c->stream>>>(g, c->tabC, c->tabF1, c->tabF2, c->corner,
-                                                           c->conn);
+                                                           c->conn, c->dgs);
   // failure count zero; no dt reduced yet (result[3] = 1)
   static const double result0[8] = {0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
   if (hipMemsetAsync(c->fails, 0, 8 * sizeof(unsigned long long), c->stream) != hipSuccess ||
@@ -2635,7 +2640,7 @@ size_t pack_carve(int nb, const int* n, char* base, grmhd_pack* pk) {
     v.tabF1 = cv.take<double>(base, G_NF * plane);
     v.tabF2 = cv.take<double>(base, G_NF * plane);
     v.corner = cv.take<double>(base, plane);
-    v.conn = cv.take<double>(base, NCONN * plane);
+    v.dgs = cv.take<double>(base, NDG * plane);
     if (pk) {
       pk->views.push_back(v);
       pk->prim_off.push_back(prim_total);
@@ -2793,7 +2798,8 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
     v.o3 = o[2];
     if (g.nz > pk->max_nz) pk->max_nz = (int)g.nz;
     default_tile(n[b], v.t1, v.t2, v.t3);
-    k_geometry<<<blocks_for(g.plane), BLOCK, 0, pk->stream>>>(g, v.tabC, v.tabF1, v.tabF2, v.corner, v.conn);
+    k_geometry<<<blocks_for(g.plane), BLOCK, 0, pk->stream>>>(g, v.tabC, v.tabF1, v.tabF2, v.corner, nullptr,
+                                                               v.dgs);
   }
   if (hip_check() || hipMemsetAsync(pk->d_fails, 0, sizeof(unsigned long long), pk->stream) != hipSuccess ||
       pack_upload(pk) != GRMHD_OK) {

@@ -18,7 +18,7 @@ struct BlockView {
   Dev g;
   double *P, *P1, *V;
   double *F[3], *E[3];
-  double *tabC, *tabF1, *tabF2, *corner, *conn;
+  double *tabC, *tabF1, *tabF2, *corner, *dgs;
   int t1, t2, t3;  // tile shape
   int o1, o2, o3;  // offset of the block's first interior zone in the global grid
 };
@@ -169,7 +169,7 @@ k_pack_update(const BlockView* __restrict__ bv, int nb, const int* __restrict__ 
   const BlockView& b = bv[pack_item(nb, pre, PH_UPDATE, lt)];
   if (tile_pos(phase_box(b.g, PH_UPDATE, 0), b.t1, b.t2, b.t3, lt, i, j, k))
     update_zone<STAGE, double>(b.g, STAGE == 1 ? b.P : b.P1, STAGE == 1 ? b.P1 : b.P, b.V, b.F[0], b.F[1],
-                               b.F[2], b.E[0], b.E[1], b.E[2], b.tabC, b.conn, dt, fails, nullptr, i, j, k);
+                               b.F[2], b.E[0], b.E[1], b.E[2], b.tabC, b.dgs, dt, fails, nullptr, i, j, k);
 }
 
 // Ghost exchange between the blocks of a pack (the blocks tile part or all

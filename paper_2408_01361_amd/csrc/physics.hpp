@@ -39,6 +39,10 @@ struct PointMetric {
 // (x1, x2) plane, so consecutive x1 columns are consecutive addresses.
 enum { G_COV = 0, G_CON = 10, G_DET = 20, G_ALPHA = 21, G_NF = 22 };
 enum { NCONN = 40 };  // Gamma^l_{mn}, m <= n
+// Metric-derivative table of the geometric source: for nu = 1, 2 (row nu - 1)
+// and each symmetric index s = (k, l), d_nu g_kl / 2 if k = l and d_nu g_kl if
+// k < l (the pair (l, k) folded in), so that sum_s T^s D[s] = T^{kl} d_nu g_kl / 2.
+enum { NDG = 20 };
 
 // Both spacetimes of the library (flat space, and Kerr in modified
 // Kerr-Schild coordinates) have g_{2 mu} = g^{2 mu} = 0 for mu != 2: x2 is
@@ -102,6 +106,8 @@ using fdual::fluid_state;
 using f64::tmunu_row;
 using f32::tmunu_row;
 using fdual::tmunu_row;
+using f64::metric_source;
+using fdual::metric_source;
 using f64::prim_to_flux;
 using f32::prim_to_flux;
 using fdual::prim_to_flux;
