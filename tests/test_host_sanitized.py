@@ -15,7 +15,13 @@
    same input (failure flags equal, prims to 1e-10 of the zone's scale plus
    the implicit solver's own stopping resolution, 1e-12 of max(|x|, 1e-3)
    for velocities, with a factor 10).
-2. The oracle itself (tests/host/oracle_driver.cpp), serially: SSPRK2 steps
+2. The library's geometric source of the momentum equations,
+   (sqrt(-g)/2) T^{kl} d_nu g_kl for nu = 1, 2 from its metric-derivative
+   rows (tests/host/source_host.cpp), against the oracle's connection form
+   sqrt(-g) T^k_l Gamma^l_{nu k} on fuzzed Kerr states; the oracle's energy
+   and x3-momentum sources, zero in a stationary axisymmetric metric, must
+   come out zero to roundoff.
+3. The oracle itself (tests/host/oracle_driver.cpp), serially: SSPRK2 steps
    with each recovery, floors and the first-order flux correction,
    face-centred CT, Extended GRMHD, the CFL step and div B.  Results must
    equal the regular (OpenMP) oracle build bit for bit.
@@ -51,7 +57,8 @@ def programs(tmp_path_factory):
         pytest.skip("no g++")
     d = tmp_path_factory.mktemp("sanitized")
     out = {}
-    for name, src in (("inversion", "inversion_host.cpp"), ("oracle", "oracle_driver.cpp")):
+    for name, src in (("inversion", "inversion_host.cpp"), ("oracle", "oracle_driver.cpp"),
+                      ("source", "source_host.cpp")):
         exe = str(d / name)
         subprocess.run(["g++", *FLAGS, "-I", HOST, "-o", exe, os.path.join(HOST, src)], check=True,
                        capture_output=True, text=True)
@@ -179,3 +186,38 @@ def test_oracle_face_ct_emhd_dt_divb_under_sanitizers(programs):
     assert tail[0] == oracle.estimate_dt(c0, P)
     mx, mean = oracle.divb(c0, P)
     assert tail[1] == mx and tail[2] == mean
+
+
+@pytest.mark.parametrize("metric", ["kerr", "flat"])
+def test_library_geometric_source_against_the_oracle(programs, metric):
+    import math
+    from test_oracle_pins import _random_prims
+    from workloads import GridSpec
+    from workloads.torus import torus_grid
+    grid = torus_grid(8, 8, 1) if metric == "kerr" else GridSpec(4, 4, 4)
+    gam = 13.0 / 9.0
+    c = oracle.cfg(grid, gam=gam)
+    rng = np.random.default_rng(4)
+    n = 2000
+    if metric == "kerr":
+        x1, x2 = rng.uniform(math.log(1.05), math.log(1000.0), n), rng.uniform(0.02, 0.98, n)
+    else:
+        x1, x2 = rng.uniform(0.0, 1.0, n), rng.uniform(0.0, 1.0, n)
+    P = _random_prims(rng, n, c, x1, x2)
+    hdr = struct.pack("2i3d", n, int(metric == "kerr"), gam, grid.a, grid.hslope)
+    raw = _run(programs["source"], programs["dir"], hdr + np.column_stack([x1, x2, P]).tobytes(),
+               "source_" + metric)
+    got = np.frombuffer(raw, dtype=np.float64).reshape(n, 2)
+    ref = np.array([oracle.point_source(c, P[q], x1[q], x2[q]) for q in range(n)])
+    if metric == "flat":
+        assert not got.any() and not ref.any()
+        return
+    mag = np.abs(ref[:, 2:4]).sum(axis=1)
+    assert (mag > 0).all()
+    # the two forms differ only in rounding (measured worst 1e-13 of |S1| + |S2|)
+    for v in range(2):
+        assert (np.abs(got[:, v] - ref[:, 2 + v]) <= 1e-12 * mag).all(), v
+    # the oracle's energy and x3-momentum sources cancel to roundoff (measured 5e-15)
+    assert (ref[:, 0] == 0.0).all()
+    assert (np.abs(ref[:, 1]) <= 1e-13 * mag).all() and (np.abs(ref[:, 4]) <= 1e-13 * mag).all()
+    assert (ref[:, 5:] == 0.0).all()
