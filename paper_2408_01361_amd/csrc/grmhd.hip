@@ -363,7 +363,8 @@ __device__ __forceinline__ void face_llf(const Dev& g, const R qL[NVAR], const R
   // zero and nothing reads it
 #pragma unroll
   for (int v = 0; v < NVAR; v++)
-    if (v != B1 + D - 1) F[v * g.nz + c] = (FT)fma((R)-0.5 * cmax, UR[v] - UL[v], (R)0.5 * (FL[v] + FR[v]));
+    if (v != B1 + D - 1)
+      F[v * g.nz + c] = (FT)(m.gdet * fma((R)-0.5 * cmax, UR[v] - UL[v], (R)0.5 * (FL[v] + FR[v])));
 }
 
 template <int D>
@@ -400,11 +401,24 @@ __device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict
 #ifndef FLUX_WAVES
 #define FLUX_WAVES 3
 #endif
+// The LDS-tiled x2 and x3 face sweeps of MC and WENO5 (below; FLUX_TILE 0
+// evaluates those faces one by one, with the same results bit for bit):
+// steps of four zone rows per segment, faces per segment, right-edge row
+// buffers.
+#ifndef TILE_STEPS
+#define TILE_STEPS 4
+#endif
+#ifndef FLUX_TILE
+#define FLUX_TILE 1
+#endif
+constexpr int TILE_FACES = 4 * TILE_STEPS - 1;
+constexpr int TILE_NBUF = 3;
 
 // All three face directions in one launch: workgroups [0, nb1) take x1
-// faces (for MC and WENO5 the shared-edge sweep above), [nb1, nb1 + nb2) x2
-// faces, the rest x3 faces (nb1 and nb2 are multiples of 8, so each part
-// keeps the XCD-aware order of its schedule).
+// faces, [nb1, nb1 + nb2) x2 faces, the rest x3 faces (nb1 and nb2 are
+// multiples of 8, so each part keeps the XCD-aware order of its schedule).
+// For MC and WENO5 the x1 part is the shared-edge sweep and the x2 and x3
+// parts the LDS-tiled sweeps (below); other schemes evaluate face by face.
 template <int RECON, typename R, typename FT, bool FACE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FACE ? 3 : FLUX_WAVES, 8)))
 k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsigned nb3,
@@ -412,18 +426,25 @@ k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsi
            const double* __restrict__ tabF2, const double* __restrict__ tabC, FT* __restrict__ F1,
            FT* __restrict__ F2, FT* __restrict__ F3, const double* __restrict__ ph1,
            const double* __restrict__ ph2, const double* __restrict__ ph3) {
+  constexpr bool shared = RECON == GRMHD_RECON_MC || RECON == GRMHD_RECON_WENO5;
+  constexpr bool tiled = shared && FLUX_TILE;
+  __shared__ R rows[tiled ? TILE_NBUF * 4 * NVAR * 64 : 1];
   const unsigned b = blockIdx.x;
   int i, j, k;
   if (b < nb1) {
-    if (RECON == GRMHD_RECON_MC || RECON == GRMHD_RECON_WENO5)
+    if (shared)
       sweep_x1<RECON, R, FT, FACE>(g, xcd_order(b, nb1), P, tabF1, F1, ph1);
     else if (sched_index(b1, b, nb1, i, j, k))
       flux_face<1, RECON, R, FT>(g, P, tabF1, F1, i, j, k, FACE ? ph1 : nullptr);
   } else if (b < nb1 + nb2) {
-    if (sched_index(b2, b - nb1, nb2, i, j, k))
+    if (tiled)
+      sweep_tile<2, RECON, R, FT, FACE>(g, xcd_order(b - nb1, nb2), P, tabF2, F2, ph2, rows);
+    else if (sched_index(b2, b - nb1, nb2, i, j, k))
       flux_face<2, RECON, R, FT>(g, P, tabF2, F2, i, j, k, FACE ? ph2 : nullptr);
   } else {
-    if (sched_index(b3, b - nb1 - nb2, nb3, i, j, k))
+    if (tiled)
+      sweep_tile<3, RECON, R, FT, FACE>(g, xcd_order(b - nb1 - nb2, nb3), P, tabC, F3, ph3, rows);
+    else if (sched_index(b3, b - nb1 - nb2, nb3, i, j, k))
       flux_face<3, RECON, R, FT>(g, P, tabC, F3, i, j, k, FACE ? ph3 : nullptr);
   }
 }
@@ -520,6 +541,109 @@ __device__ __forceinline__ void sweep_x1(const Dev& g, unsigned lb, const double
     left[B1] = bn;
   }
   face_llf<1, R, FT>(g, qL, left, tabF1, q2, F1, c);
+}
+
+// ------------------------------- x2 and x3 faces with shared edges (LDS) --
+//
+// The same sharing along x2 and x3, where the zone below a face is not in the
+// lane below: a workgroup takes 64 columns of the face box (one per lane:
+// (x1, x3) positions for x2 faces, (x1, x2) for x3 faces, linearised
+// x1-fastest) and marches along the face axis over a segment of faces.  In
+// each step its four wavefronts reconstruct four consecutive zone rows (both
+// edges of all prims, edge_pair), each wavefront's right edges go through
+// LDS to the wavefront of the row above, and every wavefront forms the lower
+// face of its row from that left state and its own left edge.  The first row
+// of a segment is the zone below its first face (reconstructed, no face).
+// The right-edge rows are triple-buffered, so one barrier per step orders
+// everything: the buffer a step writes was last read in the step before the
+// previous one, and every wavefront has passed the barrier in between.
+// The face values are those of the per-face evaluation bit for bit.
+
+// Columns and faces of the tiled part for direction D (2 or 3).
+__host__ __device__ inline long tile_columns(const Dev& g, int D) {
+  return (long)(g.n1 + 2) * ((D == 2 ? g.n3 : g.n2) + 2);
+}
+__host__ __device__ inline int tile_faces(const Dev& g, int D) { return (D == 2 ? g.n2 : g.n3) + 1; }
+// Workgroups of the tiled part: column groups of 64 times segments, rounded
+// up to a multiple of 8.
+inline unsigned tile_blocks(const Dev& g, int D) {
+  const long ncg = (tile_columns(g, D) + 63) / 64;
+  const long nseg = (tile_faces(g, D) + TILE_FACES - 1) / TILE_FACES;
+  return (unsigned)((ncg * nseg + 7) / 8 * 8);
+}
+
+// Both edges of every prim of the zone at padded index c along the axis of
+// stride s: the left edges into left[], the right edges stored to
+// rows[v * 64] as they are formed.
+template <int RECON, typename R>
+__device__ __forceinline__ void zone_edges(const double* __restrict__ P, long nz, long c, long s, R eps,
+                                           R left[NVAR], R* rows) {
+#pragma unroll
+  for (int v = 0; v < NVAR; v++) {
+    const double* q = P + v * nz + c;
+    const R m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s];
+    const R m2 = RECON == GRMHD_RECON_MC ? p0 : (R)q[-2 * s];
+    const R p2 = RECON == GRMHD_RECON_MC ? p0 : (R)q[2 * s];
+    R right;
+    edge_pair<RECON>(m2, m1, p0, p1, p2, eps, left[v], right);
+    rows[v * 64] = right;
+  }
+}
+
+// lb: this workgroup's place in the part (XCD-ordered); nb: workgroups in
+// the part; rows: the LDS right-edge buffers (TILE_NBUF x 4 x NVAR x 64).
+template <int D, int RECON, typename R, typename FT, bool FACE>
+__device__ __forceinline__ void sweep_tile(const Dev& g, unsigned lb, const double* __restrict__ P,
+                                           const double* __restrict__ tab, FT* __restrict__ F,
+                                           const double* __restrict__ ph, R* rows) {
+  const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+  const long ncol = tile_columns(g, D);
+  const int nface = tile_faces(g, D);
+  const unsigned nseg = (unsigned)((nface + TILE_FACES - 1) / TILE_FACES);
+  const unsigned cg = lb / nseg, sg = lb - cg * nseg;
+  const long col = (long)cg * 64 + lane;
+  const bool colvalid = col < ncol;
+  const long cc = colvalid ? col : 0;
+  const int m1 = g.n1 + 2;
+  const int i = (int)(cc % m1) - 1, o = (int)(cc / m1) - 1;   // o: the other transverse index
+  const int fs = (int)sg * TILE_FACES;
+  const int fe = fs + TILE_FACES < nface ? fs + TILE_FACES : nface;
+  // a workgroup past the last segment (rounding) runs no step
+  const int nsteps = fs < nface ? (fe - fs + 1 + 3) / 4 : 0;
+  const long s = D == 2 ? (long)g.s1 : g.plane;
+  for (int t = 0; t < nsteps; t++) {
+    const int r = fs - 1 + 4 * t + w;            // zone row along the face axis
+    const bool rowvalid = r <= fe - 1;
+    const int rr = rowvalid ? r : fe - 1;        // rows past the segment load an in-range stencil
+    const long c = D == 2 ? zid(g, i, rr, o) : zid(g, i, o, rr);
+    R left[NVAR];
+    zone_edges<RECON, R>(P, g.nz, c, s, (R)g.weno_eps, left, rows + ((t % TILE_NBUF) * 4 + w) * NVAR * 64 + lane);
+    __syncthreads();
+    if (!colvalid || !rowvalid || r < fs) continue;
+    // left state: the right edge of the row below (for the first wavefront,
+    // the last row of the previous step)
+    const R* rd = w > 0 ? rows + ((t % TILE_NBUF) * 4 + (w - 1)) * NVAR * 64
+                        : rows + (((t + TILE_NBUF - 1) % TILE_NBUF) * 4 + 3) * NVAR * 64;
+    R qL[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) qL[v] = rd[v * 64 + lane];
+    if (pole_face<D>(g, r)) {
+#pragma unroll
+      for (int v = 0; v < NVAR; v++) F[v * g.nz + c] = (FT)0;
+      continue;
+    }
+    long q2 = D == 2 ? pid(g, i, r) : pid(g, i, o);
+    // x3 faces: the face metric is the same for the whole column; keep its
+    // loads in the step (hoisted out of the loop it would be held through
+    // the reconstruction and spilled)
+    if (D == 3) asm volatile("" : "+v"(q2));
+    if (FACE) {
+      const R bn = (R)(ph[c] / tab[G_DET * g.plane + q2]);
+      qL[B1 + D - 1] = bn;
+      left[B1 + D - 1] = bn;
+    }
+    face_llf<D, R, FT>(g, qL, left, tab, q2, F, c);
+  }
 }
 
 // Flux-CT edge EMFs at the lower (x1, x2, x3) corner of zone (i, j, k):
@@ -1737,7 +1861,9 @@ int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullp
   const bool shared = c->params.recon == GRMHD_RECON_MC || c->params.recon == GRMHD_RECON_WENO5;
   const unsigned n1 = shared ? x1_sweep_blocks((long)(g.n1 + 2) * (g.n2 + 2) * (g.n3 + 2))
                              : round8(blocks_for(b1));
-  const unsigned n2 = round8(blocks_for(b2)), n3 = blocks_for(b3);
+  const bool tiled = shared && FLUX_TILE;
+  const unsigned n2 = tiled ? tile_blocks(g, 2) : round8(blocks_for(b2));
+  const unsigned n3 = tiled ? tile_blocks(g, 3) : blocks_for(b3);
   const double* Pc = P;
   const double* p1 = ph ? ph[0] : nullptr;
   const double* p2 = ph ? ph[1] : nullptr;

@@ -349,8 +349,10 @@ __device__ __forceinline__ Dual weno5(Dual a, Dual b, Dual c, Dual d, Dual e, Du
 // ---------------------------------------------------------- face physics --
 //
 // The state on one side of a face as the flux kernels need it: conserved
-// variables U, the flux F^d along the face normal and the two fast signal
-// speeds, from the reconstructed prims and the face metric.  The same
+// variables U, the flux F^d along the face normal (both without the factor
+// sqrt(-g), which is common to the two sides and applied once to their
+// Lax-Friedrichs combination) and the two fast signal speeds, from the
+// reconstructed prims and the face metric.  The same
 // formulas as fluid_state / prim_to_flux / char_speeds, arranged for the
 // face, where these evaluations dominate the step's arithmetic:
 //   * the face metric holds only the entries that are not identically zero
@@ -404,7 +406,8 @@ __device__ __forceinline__ void load_face_metric(const double* __restrict__ tab,
   m.ialpha = face_rcp(m.alpha);
 }
 
-// U, F^D (D = 1..3) and the signal speeds cp >= cm of the prims p.
+// U / sqrt(-g), F^D / sqrt(-g) (D = 1..3) and the signal speeds cp >= cm of
+// the prims p.
 template <int D, typename R>
 __device__ __forceinline__ void face_side(const R p[NVAR], const FaceMetric<R>& m, R gam, R F[NVAR],
                                           R U[NVAR], R& cp, R& cm) {
@@ -437,30 +440,29 @@ __device__ __forceinline__ void face_side(const R p[NVAR], const FaceMetric<R>& 
   const R ptot = fma((R)0.5, bsq, pg);
   const R ud = D == 1 ? u1 : (D == 2 ? u2 : u3);
   const R bd = D == 1 ? b1 : (D == 2 ? b2 : b3);
-  const R g = m.gdet;
   {
     const R wu = w * ut;
     const R ru = rho * ut;
-    U[RHO] = g * ru;
-    U[UU] = g * (fma(wu, l0, fma(-bt, k0, ptot)) + ru);
-    U[U1] = g * fma(wu, l1, -bt * k1);
-    U[U2] = g * fma(wu, l2, -bt * k2);
-    U[U3] = g * fma(wu, l3, -bt * k3);
-    U[B1] = g * Bc1;
-    U[B2] = g * Bc2;
-    U[B3] = g * Bc3;
+    U[RHO] = ru;
+    U[UU] = fma(wu, l0, fma(-bt, k0, ptot)) + ru;
+    U[U1] = fma(wu, l1, -bt * k1);
+    U[U2] = fma(wu, l2, -bt * k2);
+    U[U3] = fma(wu, l3, -bt * k3);
+    U[B1] = Bc1;
+    U[B2] = Bc2;
+    U[B3] = Bc3;
   }
   {
     const R wu = w * ud;
     const R ru = rho * ud;
-    F[RHO] = g * ru;
-    F[UU] = g * (fma(wu, l0, -bd * k0) + ru);
-    F[U1] = g * fma(wu, l1, fma(-bd, k1, D == 1 ? ptot : (R)0));
-    F[U2] = g * fma(wu, l2, fma(-bd, k2, D == 2 ? ptot : (R)0));
-    F[U3] = g * fma(wu, l3, fma(-bd, k3, D == 3 ? ptot : (R)0));
-    F[B1] = g * fma(b1, ud, -bd * u1);
-    F[B2] = g * fma(b2, ud, -bd * u2);
-    F[B3] = g * fma(b3, ud, -bd * u3);
+    F[RHO] = ru;
+    F[UU] = fma(wu, l0, -bd * k0) + ru;
+    F[U1] = fma(wu, l1, fma(-bd, k1, D == 1 ? ptot : (R)0));
+    F[U2] = fma(wu, l2, fma(-bd, k2, D == 2 ? ptot : (R)0));
+    F[U3] = fma(wu, l3, fma(-bd, k3, D == 3 ? ptot : (R)0));
+    F[B1] = fma(b1, ud, -bd * u1);
+    F[B2] = fma(b2, ud, -bd * u2);
+    F[B3] = fma(b3, ud, -bd * u3);
   }
   // fast speeds: roots v of (u^D - v u^t)^2 (1 - c^2) = c^2 (v^2 g^tt - 2 v g^tD + g^DD),
   // c^2 = cs^2 + vA^2 - cs^2 vA^2, cs^2 = gam p / w, vA^2 = b^2 / (b^2 + w), w = rho + gam u
