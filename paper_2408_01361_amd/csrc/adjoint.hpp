@@ -7,12 +7,13 @@
 // transposed explicitly, Flux-CT is transposed through its edge EMFs, every
 // face flux is transposed through its stencil, and ghost fills are transposed
 // by gathering each ghost's adjoint back onto the zone it was copied from
-// (with the polar sign flips).  Only the local Jacobians of the per-point
-// physics come from forward-mode dual numbers, one input direction at a
-// time: a face flux with respect to each of its two states' prims (then
-// chained with the reconstruction's derivatives with respect to each stencil
-// slot), the source and the conserved variables with respect to one zone's
-// prims.  Every sum is a gather in a fixed order: the result is
+// (with the polar sign flips).  The local derivatives of the per-point
+// physics: a face flux with respect to its two states' prims by a reverse
+// sweep through each state (face_vjp.hpp), chained with the reconstruction's
+// derivatives with respect to each stencil slot (WENO5: its gradient in
+// closed form; MC: dual numbers); the source and the conserved variables
+// with respect to one zone's prims by forward-mode dual numbers, one input
+// direction at a time.  Every sum is a gather in a fixed order: the result is
 // deterministic.
 //
 // Included inside the anonymous namespace of grmhd.hip.
@@ -24,19 +25,10 @@ struct Stencil {
   static constexpr int NSLOT = NVAR * W;                     // stencil inputs of one face
 };
 
-// One face state in dual arithmetic: its flux along D, conserved variables
-// and characteristic speeds.
-template <int D>
-__device__ __forceinline__ void state_dual(const Dual q[NVAR], const PointMetric<double>& m, Dual gam,
-                                           Dual Fx[NVAR], Dual U[NVAR], Dual& cp, Dual& cm) {
-  Fluid<Dual> f;
-  fluid_state(q, m, f);
-  prim_to_flux(q, f, m, gam, D, Fx);
-  prim_to_flux(q, f, m, gam, 0, U);
-  char_speeds(q, f, m, gam, D, cp, cm);
-}
+#include "face_vjp.hpp"
 
-// The same state in plain FP64 (the side of the face that is not seeded).
+// One face state in plain FP64: its flux along D, conserved variables and
+// characteristic speeds.
 template <int D>
 __device__ __forceinline__ void state_real(const double q[NVAR], const PointMetric<double>& m, double gam,
                                            double Fx[NVAR], double U[NVAR], double& cp, double& cm) {
@@ -47,40 +39,9 @@ __device__ __forceinline__ void state_real(const double q[NVAR], const PointMetr
   char_speeds(q, f, m, gam, D, cp, cm);
 }
 
-// lambda . LLF flux, derivative part, from the two face states.
-__device__ __forceinline__ double llf_dot(const Dual FL[NVAR], const Dual UL[NVAR], Dual cpl, Dual cml,
-                                          const Dual FR[NVAR], const Dual UR[NVAR], Dual cpr, Dual cmr,
-                                          const double lam[NVAR]) {
-  Dual cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
-  cmax = fmax(cmax, Dual(0.0));
-  double acc = 0.0;
-#pragma unroll
-  for (int v = 0; v < NVAR; v++) acc += llf(FL[v], FR[v], UL[v], UR[v], cmax).d * lam[v];
-  return acc;
-}
-
-// The same with one state seeded (S: its dual fluxes, conserved variables
-// and speeds) and the other fixed (plain values); left says which side S is.
-__device__ __forceinline__ double llf_dot_one(bool left, const Dual FS[NVAR], const Dual US[NVAR], Dual cps,
-                                              Dual cms, const double FO[NVAR], const double UO[NVAR],
-                                              double cpo, double cmo, const double lam[NVAR]) {
-  const Dual cpl = left ? cps : Dual(cpo), cpr = left ? Dual(cpo) : cps;
-  const Dual cml = left ? cms : Dual(cmo), cmr = left ? Dual(cmo) : cms;
-  Dual cmax = fmax(fmax(cpl, cpr), fmax(-cml, -cmr));
-  cmax = fmax(cmax, Dual(0.0));
-  // d/ds of F = (FL + FR)/2 - cmax (UR - UL)/2 with only S and cmax varying
-  double acc = 0.0;
-#pragma unroll
-  for (int v = 0; v < NVAR; v++) {
-    const double du = left ? UO[v] - US[v].v : US[v].v - UO[v];
-    const double dU = left ? -US[v].d : US[v].d;
-    acc += (0.5 * FS[v].d - 0.5 * (cmax.d * du + cmax.v * dU)) * lam[v];
-  }
-  return acc;
-}
-
 // Derivatives of a face's left and right reconstructed values of one
-// variable with respect to stencil slot s (q holds the W slot values).
+// variable with respect to stencil slot s (q holds the W slot values), by
+// dual numbers (MC; WENO5 takes the closed-form gradient, weno5_grad).
 template <int RECON>
 __device__ __forceinline__ void recon_slot_derivs(const double q[], int s, double eps, double& dL,
                                                   double& dR) {
@@ -177,56 +138,69 @@ __global__ void __launch_bounds__(BLOCK) k_adj_face(Dev g, Box box, const double
   }
   // chain rule through the face states: lambda . dF/d(stencil slot) =
   // sum over the two states of (lambda . dF/dq_state[v]) dq_state[v]/dslot;
-  // the first factor takes one dual evaluation of one state per variable,
-  // the second one dual reconstruction per slot
+  // the first factor by a reverse sweep through each state, the second from
+  // the reconstruction's derivatives with respect to each slot
   PointMetric<double> m;
   load_metric<double>(tab, g.plane, pid(g, i, j), m);
   double qL[NVAR], qR[NVAR];
   recon_pair<RECON, double>(P, nz, c, s, g.weno_eps, qL, qR);
   const double gam = g.gam;
-  double gL[NVAR], gR[NVAR];
-#pragma unroll 1
-  for (int side = 0; side < 2; side++) {
-    const double* qs = side == 0 ? qL : qR;
-    double FO[NVAR], UO[NVAR], cpo, cmo;
-    state_real<D>(side == 0 ? qR : qL, m, gam, FO, UO, cpo, cmo);
-#pragma unroll 1
-    for (int w = 0; w < NVAR; w++) {
-      Dual q[NVAR], Fx[NVAR], U[NVAR], cp, cm;
+  // lambda . dF/dq of both states by one reverse sweep per state: the LLF
+  // flux F = (FL + FR)/2 - cmax (UR - UL)/2 gives the adjoints lambda/2 of
+  // FL and FR, +-cmax lambda/2 of UL and UR, and -lambda.(UR - UL)/2 of
+  // cmax, which goes to the speed that attains it (chosen as the dual-number
+  // fmax chain chooses: the later operand only when strictly larger)
+  double FL[NVAR], UL[NVAR], cpl, cml, FR[NVAR], UR[NVAR], cpr, cmr;
+  state_real<D>(qL, m, gam, FL, UL, cpl, cml);
+  state_real<D>(qR, m, gam, FR, UR, cpr, cmr);
+  const bool s1 = cpr > cpl, s2 = -cmr > -cml;
+  const double m1 = s1 ? cpr : cpl, m2 = s2 ? -cmr : -cml;
+  const bool s3 = m2 > m1;
+  const double m3 = s3 ? m2 : m1;
+  const bool pos = !(0.0 > m3);
+  const double cmax = pos ? m3 : 0.0;
+  double cb = 0.0;
 #pragma unroll
-      for (int v = 0; v < NVAR; v++) q[v] = Dual(qs[v], v == w ? 1.0 : 0.0);
-      state_dual<D>(q, m, Dual(gam), Fx, U, cp, cm);
-      const double gw = llf_dot_one(side == 0, Fx, U, cp, cm, FO, UO, cpo, cmo, lam);
-      if (side == 0)
-        gL[w] = gw;
-      else
-        gR[w] = gw;
-    }
-  }
-  {
-    // gamma: both states
-    Dual a[NVAR], b[NVAR], FLd[NVAR], ULd[NVAR], FRd[NVAR], URd[NVAR], cpl, cml, cpr, cmr;
-    const Dual gd(gam, 1.0);
+  for (int v = 0; v < NVAR; v++) cb += lam[v] * (UR[v] - UL[v]);
+  cb = pos ? -0.5 * cb : 0.0;
+  const double cplb = !s3 && !s1 ? cb : 0.0, cprb = !s3 && s1 ? cb : 0.0;
+  const double cmlb = s3 && !s2 ? -cb : 0.0, cmrb = s3 && s2 ? -cb : 0.0;
+  double FLb[NVAR], ULb[NVAR], FRb[NVAR], URb[NVAR];
 #pragma unroll
-    for (int v = 0; v < NVAR; v++) {
-      a[v] = Dual(qL[v]);
-      b[v] = Dual(qR[v]);
-    }
-    state_dual<D>(a, m, gd, FLd, ULd, cpl, cml);
-    state_dual<D>(b, m, gd, FRd, URd, cpr, cmr);
-    GF[c] += llf_dot(FLd, ULd, cpl, cml, FRd, URd, cpr, cmr, lam);
+  for (int v = 0; v < NVAR; v++) {
+    FLb[v] = FRb[v] = 0.5 * lam[v];
+    ULb[v] = 0.5 * cmax * lam[v];
+    URb[v] = -0.5 * cmax * lam[v];
   }
+  double gL[NVAR], gR[NVAR], gamL, gamR;
+  state_vjp<D>(qL, m, gam, FLb, ULb, cplb, cmlb, gL, gamL);
+  state_vjp<D>(qR, m, gam, FRb, URb, cprb, cmrb, gR, gamR);
+  GF[c] += gamL + gamR;
 #pragma unroll 1
   for (int v = 0; v < NVAR; v++) {
     double qs[St::W];
 #pragma unroll
     for (int z = 0; z < St::W; z++) qs[z] = P[v * nz + c + (z - St::H) * s];
+    double dL[St::W], dR[St::W];
+    if constexpr (RECON == GRMHD_RECON_WENO5) {
+      // the left state is weno5(q0, .., q4), the right one weno5(q5, .., q1):
+      // both gradients in closed form
+      weno5_grad(qs[0], qs[1], qs[2], qs[3], qs[4], g.weno_eps, dL[0], dL[1], dL[2], dL[3], dL[4]);
+      weno5_grad(qs[5], qs[4], qs[3], qs[2], qs[1], g.weno_eps, dR[5], dR[4], dR[3], dR[2], dR[1]);
+      dL[5] = 0.0;
+      dR[0] = 0.0;
+    } else {
 #pragma unroll
-    for (int z = 0; z < St::W; z++) {
-      double dL, dR;
-      recon_slot_derivs<RECON>(qs, z, g.weno_eps, dL, dR);
-      LS[(v * St::W + z) * nz + c] = gL[v] * dL + gR[v] * dR;
+      for (int z = 0; z < St::W; z++) recon_slot_derivs<RECON>(qs, z, g.weno_eps, dL[z], dR[z]);
     }
+    double gl = 0.0, gr = 0.0;
+#pragma unroll
+    for (int u = 0; u < NVAR; u++) {   // compare and select: no register array indexed by v
+      gl = u == v ? gL[u] : gl;
+      gr = u == v ? gR[u] : gr;
+    }
+#pragma unroll
+    for (int z = 0; z < St::W; z++) LS[(v * St::W + z) * nz + c] = gl * dL[z] + gr * dR[z];
   }
 }
 

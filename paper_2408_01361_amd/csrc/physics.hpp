@@ -346,6 +346,43 @@ __device__ __forceinline__ Dual weno5(Dual a, Dual b, Dual c, Dual d, Dual e, Du
   return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
 }
 
+// Partial derivatives g0..g4 of the WENO5 edge value weno5(a, .., e) with
+// respect to the five stencil values, by the chain rule through the weights: with
+// s_k = eps + beta_k, w_k = d_k / s_k^2, W = sum w_k, o_k = w_k / W and
+// v = sum o_k p_k,
+//   dv/dx = sum_k o_k dp_k/dx - 2 sum_k o_k ((p_k - v) / s_k) dbeta_k/dx,
+// where beta_k = 13/12 t_k^2 + 1/4 u_k^2 (t_k, u_k linear in x).  The same
+// function as the dual-number form above, differentiated in closed form.
+__device__ __forceinline__ void weno5_grad(double a, double b, double c, double d, double e, double eps,
+                                           double& g0, double& g1, double& g2, double& g3, double& g4) {
+#pragma clang fp contract(off)
+  const double t0 = (a - 2.0 * b) + c, u0 = (a - 4.0 * b) + 3.0 * c;
+  const double t1 = (b - 2.0 * c) + d, u1 = b - d;
+  const double t2 = (c - 2.0 * d) + e, u2 = (3.0 * c - 4.0 * d) + e;
+  const double k = 13.0 / 12.0;
+  const double s0 = eps + (k * t0 * t0 + 0.25 * u0 * u0);
+  const double s1 = eps + (k * t1 * t1 + 0.25 * u1 * u1);
+  const double s2 = eps + (k * t2 * t2 + 0.25 * u2 * u2);
+  const double w0 = 0.1 / (s0 * s0), w1 = 0.6 / (s1 * s1), w2 = 0.3 / (s2 * s2);
+  const double iW = 1.0 / ((w0 + w1) + w2);
+  const double o0 = w0 * iW, o1 = w1 * iW, o2 = w2 * iW;
+  const double p0 = ((2.0 * a - 7.0 * b) + 11.0 * c) / 6.0;
+  const double p1 = ((-b + 5.0 * c) + 2.0 * d) / 6.0;
+  const double p2 = ((2.0 * c + 5.0 * d) - e) / 6.0;
+  const double v = (o0 * p0 + o1 * p1) + o2 * p2;
+  // -2 o_k (p_k - v) / s_k: the weight of dbeta_k/dx
+  const double r0 = -2.0 * o0 * (p0 - v) / s0;
+  const double r1 = -2.0 * o1 * (p1 - v) / s1;
+  const double r2 = -2.0 * o2 * (p2 - v) / s2;
+  const double h = 13.0 / 6.0;
+  g0 = o0 * (2.0 / 6.0) + r0 * (h * t0 + 0.5 * u0);
+  g1 = (o0 * (-7.0 / 6.0) + o1 * (-1.0 / 6.0)) + (r0 * (-2.0 * h * t0 - 2.0 * u0) + r1 * (h * t1 + 0.5 * u1));
+  g2 = ((o0 * (11.0 / 6.0) + o1 * (5.0 / 6.0)) + o2 * (2.0 / 6.0)) +
+         ((r0 * (h * t0 + 1.5 * u0) + r1 * (-2.0 * h * t1)) + r2 * (h * t2 + 1.5 * u2));
+  g3 = (o1 * (2.0 / 6.0) + o2 * (5.0 / 6.0)) + (r1 * (h * t1 - 0.5 * u1) + r2 * (-2.0 * h * t2 - 2.0 * u2));
+  g4 = o2 * (-1.0 / 6.0) + r2 * (h * t2 + 0.5 * u2);
+}
+
 // ---------------------------------------------------------- face physics --
 //
 // The state on one side of a face as the flux kernels need it: conserved
