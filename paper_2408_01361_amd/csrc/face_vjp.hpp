@@ -56,27 +56,58 @@ __device__ __forceinline__ void state_vjp(const double q[NVAR], const PointMetri
   const double pg = (gam - 1.0) * uu;
   const double w = ((rho + uu) + pg) + bsq;
   const double ptot = pg + 0.5 * bsq;
-  // speeds: roots of A v^2 + B v + C = 0
-  const double we = rho + gam * uu;
-  const double cs2 = gam * pg / we;
-  const double S = bsq + we;
-  const double va2 = bsq / S;
-  const double c2 = (cs2 + va2) - cs2 * va2;
-  const double Au = ucon[D], Bu = ucon[0];
-  const double Asq = gu(D, D), Bsq = gu(0, 0), AB = gu(0, D);
-  const double A = Bu * Bu - c2 * (Bsq + Bu * Bu);
-  const double Bq = -2.0 * (Au * Bu - c2 * (AB + Au * Bu));
-  const double C = Au * Au - c2 * (Asq + Au * Au);
-  double disc = Bq * Bq - (4.0 * A) * C;
-  disc = disc > 0.0 ? disc : 0.0;
-  const double sq = sqrt(disc);
-  const double r1 = (-Bq + sq) / (2.0 * A), r2 = (-Bq - sq) / (2.0 * A);
-
   // ---- reverse
   double ucon_b[4] = {0.0, 0.0, 0.0, 0.0}, ucov_b[4] = {0.0, 0.0, 0.0, 0.0};
   double bcon_b[4] = {0.0, 0.0, 0.0, 0.0}, bcov_b[4] = {0.0, 0.0, 0.0, 0.0};
   double B_b[4] = {0.0, 0.0, 0.0, 0.0};
   double rho_b = 0.0, uu_b = 0.0, gam_b = 0.0, w_b = 0.0, ptot_b = 0.0, pg_b = 0.0, bsq_b = 0.0;
+  // the speeds first (forward and reverse), so that their intermediates
+  // are dead before the flux part
+  {
+    // speeds: roots of A v^2 + B v + C = 0
+    const double we = rho + gam * uu;
+    const double cs2 = gam * pg / we;
+    const double S = bsq + we;
+    const double va2 = bsq / S;
+    const double c2 = (cs2 + va2) - cs2 * va2;
+    const double Au = ucon[D], Bu = ucon[0];
+    const double Asq = gu(D, D), Bsq = gu(0, 0), AB = gu(0, D);
+    const double A = Bu * Bu - c2 * (Bsq + Bu * Bu);
+    const double Bq = -2.0 * (Au * Bu - c2 * (AB + Au * Bu));
+    const double C = Au * Au - c2 * (Asq + Au * Au);
+    double disc = Bq * Bq - (4.0 * A) * C;
+    disc = disc > 0.0 ? disc : 0.0;
+    const double sq = sqrt(disc);
+    const double r1 = (-Bq + sq) / (2.0 * A), r2 = (-Bq - sq) / (2.0 * A);
+    // reverse: cp = max(r1, r2), cm = min(r1, r2)
+    {
+      const bool first = r1 > r2;
+      const double r1b = first ? cpb : cmb, r2b = first ? cmb : cpb;
+      const double i2a = 1.0 / (2.0 * A);
+      double Ab = -(r1b * r1 + r2b * r2) / A;
+      double Bb = -(r1b + r2b) * i2a;
+      const double sqb = (r1b - r2b) * i2a;
+      const double discb = sq > 0.0 ? 0.5 * sqb / sq : 0.0;
+      Bb += discb * 2.0 * Bq;
+      Ab -= discb * 4.0 * C;
+      const double Cb = -discb * 4.0 * A;
+      const double Qb = -2.0 * Bb;   // Bq = -2 Q, Q = Au Bu - c2 (AB + Au Bu)
+      double c2b = -Ab * (Bsq + Bu * Bu) - Qb * (AB + Au * Bu) - Cb * (Asq + Au * Au);
+      const double Bub = Ab * (2.0 * Bu - 2.0 * c2 * Bu) + Qb * (Au - c2 * Au);
+      const double Aub = Qb * (Bu - c2 * Bu) + Cb * (2.0 * Au - 2.0 * c2 * Au);
+      ucon_b[D] += Aub;
+      ucon_b[0] += Bub;
+      const double cs2b = c2b * (1.0 - va2), va2b = c2b * (1.0 - cs2);
+      gam_b += cs2b * pg / we;
+      pg_b += cs2b * gam / we;
+      double web = -cs2b * cs2 / we;
+      bsq_b += va2b * we / (S * S);
+      web -= va2b * bsq / (S * S);
+      rho_b += web;
+      uu_b += web * gam;
+      gam_b += web * uu;
+    }
+  }
   // flux (row D) and conserved variables (row 0):
   // X^e_nu = w u^e u_nu + ptot delta^e_nu - b^e b_nu;
   // Y[RHO] = g rho u^e, Y[UU] = g (X^e_0 + rho u^e), Y[U_i] = g X^e_i
@@ -114,34 +145,6 @@ __device__ __forceinline__ void state_vjp(const double q[NVAR], const PointMetri
 #pragma unroll
       for (int k = 1; k < 4; k++) B_b[k] += g * Y[B1 + k - 1];   // Y[B_k] = g B^k
     }
-  }
-  // speeds: cp = max(r1, r2), cm = min(r1, r2)
-  {
-    const bool first = r1 > r2;
-    const double r1b = first ? cpb : cmb, r2b = first ? cmb : cpb;
-    const double i2a = 1.0 / (2.0 * A);
-    double Ab = -(r1b * r1 + r2b * r2) / A;
-    double Bb = -(r1b + r2b) * i2a;
-    const double sqb = (r1b - r2b) * i2a;
-    const double discb = sq > 0.0 ? 0.5 * sqb / sq : 0.0;
-    Bb += discb * 2.0 * Bq;
-    Ab -= discb * 4.0 * C;
-    const double Cb = -discb * 4.0 * A;
-    const double Qb = -2.0 * Bb;   // Bq = -2 Q, Q = Au Bu - c2 (AB + Au Bu)
-    double c2b = -Ab * (Bsq + Bu * Bu) - Qb * (AB + Au * Bu) - Cb * (Asq + Au * Au);
-    const double Bub = Ab * (2.0 * Bu - 2.0 * c2 * Bu) + Qb * (Au - c2 * Au);
-    const double Aub = Qb * (Bu - c2 * Bu) + Cb * (2.0 * Au - 2.0 * c2 * Au);
-    ucon_b[D] += Aub;
-    ucon_b[0] += Bub;
-    const double cs2b = c2b * (1.0 - va2), va2b = c2b * (1.0 - cs2);
-    gam_b += cs2b * pg / we;
-    pg_b += cs2b * gam / we;
-    double web = -cs2b * cs2 / we;
-    bsq_b += va2b * we / (S * S);
-    web -= va2b * bsq / (S * S);
-    rho_b += web;
-    uu_b += web * gam;
-    gam_b += web * uu;
   }
   // ptot = pg + bsq/2, w = rho + u + pg + bsq, pg = (gam - 1) u
   pg_b += ptot_b + w_b;
