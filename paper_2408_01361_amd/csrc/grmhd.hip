@@ -401,7 +401,7 @@ __device__ __forceinline__ void flux_face(const Dev& g, const double* __restrict
 #ifndef FLUX_WAVES
 #define FLUX_WAVES 3
 #endif
-// The LDS-tiled x2 and x3 face sweeps of MC and WENO5 (below; FLUX_TILE 0
+// The LDS-tiled x2 and x3 face sweeps of WENO5 (below; FLUX_TILE 0
 // evaluates those faces one by one, with the same results bit for bit):
 // steps of four zone rows per segment, faces per segment, right-edge row
 // buffers.
@@ -417,8 +417,9 @@ constexpr int TILE_NBUF = 3;
 // All three face directions in one launch: workgroups [0, nb1) take x1
 // faces, [nb1, nb1 + nb2) x2 faces, the rest x3 faces (nb1 and nb2 are
 // multiples of 8, so each part keeps the XCD-aware order of its schedule).
-// For MC and WENO5 the x1 part is the shared-edge sweep and the x2 and x3
-// parts the LDS-tiled sweeps (below); other schemes evaluate face by face.
+// For MC and WENO5 the x1 part is the shared-edge sweep, for WENO5 the x2
+// and x3 parts are the LDS-tiled sweeps (below); other schemes and parts
+// evaluate face by face.
 template <int RECON, typename R, typename FT, bool FACE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FACE ? 3 : FLUX_WAVES, 8)))
 k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsigned nb3,
@@ -427,7 +428,9 @@ k_flux_all(Dev g, Sched b1, Sched b2, Sched b3, unsigned nb1, unsigned nb2, unsi
            FT* __restrict__ F2, FT* __restrict__ F3, const double* __restrict__ ph1,
            const double* __restrict__ ph2, const double* __restrict__ ph3) {
   constexpr bool shared = RECON == GRMHD_RECON_MC || RECON == GRMHD_RECON_WENO5;
-  constexpr bool tiled = shared && FLUX_TILE;
+  // (WENO5 only: for MC the pair saves little arithmetic and the tile's
+  // registers and LDS cost a wave per SIMD)
+  constexpr bool tiled = RECON == GRMHD_RECON_WENO5 && FLUX_TILE;
   __shared__ R rows[tiled ? TILE_NBUF * 4 * NVAR * 64 : 1];
   const unsigned b = blockIdx.x;
   int i, j, k;
@@ -1861,7 +1864,7 @@ int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullp
   const bool shared = c->params.recon == GRMHD_RECON_MC || c->params.recon == GRMHD_RECON_WENO5;
   const unsigned n1 = shared ? x1_sweep_blocks((long)(g.n1 + 2) * (g.n2 + 2) * (g.n3 + 2))
                              : round8(blocks_for(b1));
-  const bool tiled = shared && FLUX_TILE;
+  const bool tiled = c->params.recon == GRMHD_RECON_WENO5 && FLUX_TILE;
   const unsigned n2 = tiled ? tile_blocks(g, 2) : round8(blocks_for(b2));
   const unsigned n3 = tiled ? tile_blocks(g, 3) : blocks_for(b3);
   const double* Pc = P;
