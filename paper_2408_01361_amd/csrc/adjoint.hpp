@@ -294,7 +294,6 @@ __global__ void __launch_bounds__(BLOCK) k_adj_zone(Dev g, Box box, const double
           acc[v] += (flip && (v == U2 || v == B2)) ? -x : x;
         }
       }
-  // local Jacobians of the source (and the conserved variables) by seeds
   PointMetric<double> m;
   load_metric<double>(tabC, g.plane, pid(g, i, j), m);
   double cn[40];
@@ -305,39 +304,16 @@ __global__ void __launch_bounds__(BLOCK) k_adj_zone(Dev g, Box box, const double
     lL[v] = LL[v * nz + c];
     lU[v] = STAGE1 ? LU0[v * nz + c] : 0.0;
   }
-  double gz = 0.0;
-  for (int sd = 0; sd <= NVAR; sd++) {
-    Dual p[NVAR];
+  // the local terms by one reverse sweep: the source (adjoint lambda_L of
+  // the energy and momentum rows) and, in stage 1, the conserved variables
+  double p[NVAR];
 #pragma unroll
-    for (int v = 0; v < NVAR; v++) p[v] = Dual(Pin[v * nz + c], sd == v ? 1.0 : 0.0);
-    Dual gam(g.gam, sd == NVAR ? 1.0 : 0.0);
-    Fluid<Dual> f;
-    fluid_state(p, m, f);
-    double d = 0.0;
-    // source: sqrt(-g) T^k_l Gamma^l_{nu k}
+  for (int v = 0; v < NVAR; v++) p[v] = Pin[v * nz + c];
+  const double Sb[4] = {lL[UU], lL[U1], lL[U2], lL[U3]};
+  double qb[NVAR], gz;
+  zone_vjp(p, m, g.gam, cn, Sb, STAGE1 ? lU : nullptr, qb, gz);
 #pragma unroll
-    for (int nu = 0; nu < 4; nu++) {
-      Dual sacc(0.0);
-#pragma unroll
-      for (int kk = 0; kk < 4; kk++) {
-        Dual T[4];
-        tmunu_row(p, f, gam, kk, T);
-#pragma unroll
-        for (int l = 0; l < 4; l++) sacc = sacc + T[l] * cn[l * 10 + sidx(nu, kk)];
-      }
-      d += (m.gdet * sacc).d * lL[UU + nu];
-    }
-    if (STAGE1) {
-      Dual U[NVAR];
-      prim_to_flux(p, f, m, gam, 0, U);
-#pragma unroll
-      for (int v = 0; v < NVAR; v++) d += U[v].d * lU[v];
-    }
-    if (sd < NVAR)
-      acc[sd] += d;
-    else
-      gz = d;
-  }
+  for (int v = 0; v < NVAR; v++) acc[v] += qb[v];
 #pragma unroll
   for (int v = 0; v < 5; v++) acc[v] += LG[v * nz + c];
 #pragma unroll
