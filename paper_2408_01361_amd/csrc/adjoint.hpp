@@ -10,11 +10,11 @@
 // (with the polar sign flips).  The local derivatives of the per-point
 // physics: a face flux with respect to its two states' prims by a reverse
 // sweep through each state (face_vjp.hpp), chained with the reconstruction's
-// derivatives with respect to each stencil slot (WENO5: its gradient in
-// closed form; MC: dual numbers); the source and the conserved variables
-// with respect to one zone's prims by forward-mode dual numbers, one input
-// direction at a time.  Every sum is a gather in a fixed order: the result is
-// deterministic.
+// derivatives with respect to each stencil slot (the WENO5 and MC gradients
+// in closed form); the source and the conserved variables with respect to
+// one zone's prims by a reverse sweep through the zone; the inversion's
+// Jacobian by forward-mode dual numbers.  Every sum is a gather in a fixed
+// order: the result is deterministic.
 //
 // Included inside the anonymous namespace of grmhd.hip.
 
@@ -38,27 +38,6 @@ __device__ __forceinline__ void state_real(const double q[NVAR], const PointMetr
   prim_to_flux(q, f, m, gam, 0, U);
   char_speeds(q, f, m, gam, D, cp, cm);
 }
-
-// Derivatives of a face's left and right reconstructed values of one
-// variable with respect to stencil slot s (q holds the W slot values), by
-// dual numbers (MC; WENO5 takes the closed-form gradient, weno5_grad).
-template <int RECON>
-__device__ __forceinline__ void recon_slot_derivs(const double q[], int s, double eps, double& dL,
-                                                  double& dR) {
-  using St = Stencil<RECON>;
-  Dual x[St::W];
-#pragma unroll
-  for (int z = 0; z < St::W; z++) x[z] = Dual(q[z], z == s ? 1.0 : 0.0);
-  if constexpr (RECON == GRMHD_RECON_MC) {
-    dL = mc_left(x[0], x[1], x[2]).d;
-    dR = mc_right(x[1], x[2], x[3]).d;
-  } else {
-    Dual e(eps);
-    dL = weno5(x[0], x[1], x[2], x[3], x[4], e).d;
-    dR = weno5(x[5], x[4], x[3], x[2], x[1], e).d;
-  }
-}
-
 
 // Adjoint of the Flux-CT EMFs on every padded edge position (zero outside
 // the edge box [0, n]^3 and on polar edges), from the stage adjoint lambda_L
@@ -207,8 +186,11 @@ k_adj_face(Dev g, Box box, const double* __restrict__ P,
       dL[5] = 0.0;
       dR[0] = 0.0;
     } else {
-#pragma unroll
-      for (int z = 0; z < St::W; z++) recon_slot_derivs<RECON>(qs, z, g.weno_eps, dL[z], dR[z]);
+      // MC: the left state is mc_left(q0, q1, q2), the right one mc_right(q1, q2, q3)
+      mc_left_grad(qs[0], qs[1], qs[2], dL[0], dL[1], dL[2]);
+      mc_right_grad(qs[1], qs[2], qs[3], dR[1], dR[2], dR[3]);
+      dL[3] = 0.0;
+      dR[0] = 0.0;
     }
     double gl = 0.0, gr = 0.0;
 #pragma unroll

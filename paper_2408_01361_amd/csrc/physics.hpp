@@ -383,6 +383,43 @@ __device__ __forceinline__ void weno5_grad(double a, double b, double c, double 
   g4 = o2 * (-1.0 / 6.0) + r2 * (h * t2 + 0.5 * u2);
 }
 
+// Partial derivatives of the MC edge values with respect to their three
+// stencil values.  The MC slope minmod(2 dl, 2 dr, dc/2) (dl = c - l,
+// dr = r - c, dc = r - l) is, away from its switching points, the selected
+// candidate times a sign: the gradient is that candidate's, chosen by the
+// same comparisons as the evaluation (fmin keeps the first operand on ties,
+// |x| counts x = 0 as positive, a non-positive dl dr gives the zero slope).
+__device__ __forceinline__ void mc_slope_grad(double l, double c, double r, double& gl, double& gc,
+                                              double& gr) {
+  const double dl = c - l, dr = r - c, dc = r - l;
+  const double al = fabs(2.0 * dl), ar = fabs(2.0 * dr), ac = fabs(0.5 * dc);
+  const bool pick_r = ar < al;
+  const double m = pick_r ? ar : al;
+  const bool pick_c = ac < m;
+  const double sg = (dc > 0.0 ? 1.0 : -1.0) * (dl * dr > 0.0 ? 1.0 : 0.0);
+  // d|k x|/dx = k sign(x), sign(0) = +1
+  const double kl = sg * (dl < 0.0 ? -2.0 : 2.0), kr = sg * (dr < 0.0 ? -2.0 : 2.0);
+  const double kc = sg * (dc < 0.0 ? -0.5 : 0.5);
+  gl = pick_c ? -kc : (pick_r ? 0.0 : -kl);
+  gc = pick_c ? 0.0 : (pick_r ? -kr : kl);
+  gr = pick_c ? kc : (pick_r ? kr : 0.0);
+}
+// mc_left(l, c, r) = c + slope/2 and mc_right(l, c, r) = c - slope/2.
+__device__ __forceinline__ void mc_left_grad(double l, double c, double r, double& g0, double& g1, double& g2) {
+  double sl, sc, sr;
+  mc_slope_grad(l, c, r, sl, sc, sr);
+  g0 = 0.5 * sl;
+  g1 = 1.0 + 0.5 * sc;
+  g2 = 0.5 * sr;
+}
+__device__ __forceinline__ void mc_right_grad(double l, double c, double r, double& g0, double& g1, double& g2) {
+  double sl, sc, sr;
+  mc_slope_grad(l, c, r, sl, sc, sr);
+  g0 = -0.5 * sl;
+  g1 = 1.0 - 0.5 * sc;
+  g2 = -0.5 * sr;
+}
+
 // ---------------------------------------------------------- face physics --
 //
 // The state on one side of a face as the flux kernels need it: conserved

@@ -253,12 +253,14 @@ def _weno5_grad_exact(x, eps):
                    N * sum(dw[k][z] for k in range(3))) / W ** 2) for z in range(5)]
 
 
-def test_adjoint_weno5_gradient_closed_form(programs):
-    """Rough, smooth (quadratic), small-scale and step stencils: the closed
+def test_adjoint_reconstruction_gradients_closed_form(programs):
+    """Rough, smooth (quadratic), small-scale and step stencils: the WENO5 closed
     form within 1e-11 of the exact derivative (measured 2.3e-12) and 2e-11
     of the dual-number form, relative to the sum of |exact derivatives|; the
     gradient sums to 1 (the edge value shifts with a constant added to the
-    stencil)."""
+    stencil); the MC edge values' closed-form gradients equal the dual ones
+    bit for bit.  Exact ties between MC's candidates are added on purpose
+    (flat and symmetric stencils)."""
     rng = np.random.default_rng(7)
     m, eps = 100, 1e-26
     xs = np.linspace(-0.2, 0.2, 5)
@@ -269,9 +271,19 @@ def test_adjoint_weno5_gradient_closed_form(programs):
         np.where(rng.random((m, 5)) < 0.5, 1.0, 0.1) * rng.uniform(0.5, 2, (m, 1)) *
         (1 + 1e-3 * rng.normal(size=(m, 5)))])
     n = len(X)
-    raw = _run(programs["weno_grad"], programs["dir"], struct.pack("<id", n, eps) + X.tobytes(), "weno_grad")
-    out = np.frombuffer(raw, dtype=np.float64).reshape(n, 10)
-    closed, dual = out[:, :5], out[:, 5:]
+    # MC's switching points: ties between |2 dl|, |2 dr|, |dc/2|, flat and sign changes
+    T = np.array([[0, 1, 2, 3, 4], [1, 1, 1, 1, 1], [0, 1, 1, 2, 2], [0, 2, 3, 4, 6], [3, 1, 2, 0, 1],
+                  [0, 0, 1, 1, 0], [1, 0, 0, 1, 1], [2, 1, 0, -1, -2]], dtype=np.float64)
+    raw = _run(programs["weno_grad"], programs["dir"],
+               struct.pack("<id", n + len(T), eps) + np.concatenate([X, T]).tobytes(), "weno_grad")
+    extra = np.frombuffer(raw, dtype=np.float64).reshape(n + len(T), 22)[n:]
+    assert np.array_equal(extra[:, 10:16], extra[:, 16:22])
+    raw = raw[:n * 22 * 8]
+    out = np.frombuffer(raw, dtype=np.float64).reshape(n, 22)
+    closed, dual = out[:, :5], out[:, 5:10]
+    # the MC edge values: piecewise linear, so the closed form is the dual
+    # derivative bit for bit (all factors are powers of two)
+    assert np.array_equal(out[:, 10:16], out[:, 16:22])
     exact = np.array([_weno5_grad_exact(x, eps) for x in X])
     scale = np.abs(exact).sum(axis=1)
     assert (np.abs(closed - exact).max(axis=1) <= 1e-11 * scale).all()
