@@ -2614,12 +2614,15 @@ int step_vjp(grmhd_ctx* c, const VjpCarve& w, const double* d_in, double dt, con
   const long nz = g.nz;
   const size_t bytes = sizeof(double) * NVAR * nz;
   int rc;
-  // forward recompute from the checkpoint: A = P^n, B = P^(1), C = P^(n+1)
+  // forward recompute from the checkpoint: A = P^n, B = P^(1), C = P^(n+1).
+  // The updates write interior zones (prims and failure flags); B's ghosts
+  // are filled before they are read, except frozen ones, which keep the
+  // input's (hence the copy only then); C and the flags are read at
+  // interior zones only (the inversion's adjoint).
+  bool frozen = false;
+  for (int f = 0; f < 6; f++) frozen = frozen || c->grid.bc[f] == GRMHD_BC_FROZEN;
   if (hipMemcpyAsync(w.A, d_in, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
-      hipMemcpyAsync(w.B, d_in, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
-      hipMemcpyAsync(w.C, d_in, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
-      hipMemsetAsync(w.fl1, 0, nz, c->stream) != hipSuccess ||
-      hipMemsetAsync(w.fl2, 0, nz, c->stream) != hipSuccess ||
+      (frozen && hipMemcpyAsync(w.B, d_in, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) ||
       hipMemsetAsync(w.GZ, 0, sizeof(double) * nz, c->stream) != hipSuccess ||
       hipMemsetAsync(d_gin, 0, bytes, c->stream) != hipSuccess)
     return GRMHD_E_HIP;
