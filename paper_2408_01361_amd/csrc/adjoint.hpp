@@ -303,6 +303,24 @@ __global__ void __launch_bounds__(BLOCK) k_adj_zone(Dev g, Box box, const double
   GZ[c] += gz;
 }
 
+// Transposed RK combination of one element, from lambda_U of a stage's
+// conserved variables.  mode 0 (stage 2, U^{n+1} = V + (dt/2) L(P1)):
+// lambda_V = lambda_U, lambda_L = (dt/2) lambda_U.  mode 1 (stage 1,
+// U1 = U^n + dt L(P^n), V = (U^n + U1)/2, with lambda_V from stage 2):
+// lambda_U1 = lambda_U + lambda_V/2, lambda_Un = lambda_V/2 + lambda_U1 (into
+// LV), lambda_L = dt lambda_U1.
+__device__ __forceinline__ void rk_transpose(int mode, double dt, double u, double& LV, double& LL) {
+  if (mode == 0) {
+    LV = u;
+    LL = 0.5 * dt * u;
+  } else {
+    const double lu1 = u + 0.5 * LV;
+    const double lu0 = 0.5 * LV + lu1;
+    LV = lu0;
+    LL = dt * lu1;
+  }
+}
+
 // Implicit-function adjoint of the inversion at the recovered prims P:
 // lambda_U = (dU/dP)^-T lambda_P, and -lambda_U . dU/dgamma into GZ.  A zone
 // whose inversion failed kept its guess's hydro prims: lambda goes to the
@@ -311,18 +329,21 @@ __global__ void __launch_bounds__(BLOCK) k_adj_zone(Dev g, Box box, const double
 __global__ void __launch_bounds__(BLOCK) k_adj_ift(Dev g, const double* __restrict__ P,
                                                    const unsigned char* __restrict__ flags,
                                                    const double* __restrict__ tabC,
-                                                   const double* __restrict__ LP,
-                                                   double* __restrict__ LU, double* __restrict__ LG,
-                                                   double* __restrict__ GZ) {
+                                                   const double* __restrict__ LP, int mode, double dt,
+                                                   double* __restrict__ LV, double* __restrict__ LL,
+                                                   double* __restrict__ LG, double* __restrict__ GZ) {
   long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (t >= g.nz) return;
   const long nz = g.nz;
+  // lambda_U of variable v, passed through the transposed RK combination
+  // (rk_transpose) into the stage register's and the stage rate's adjoints
+  auto LU = [&](int v, double u) { rk_transpose(mode, dt, u, LV[v * nz + t], LL[v * nz + t]); };
   int i = (int)(t % g.s1) - NG;
   long r = t / g.s1;
   int j = (int)(r % g.s2) - NG, k = (int)(r / g.s2) - NG;
   if (i < 0 || j < 0 || k < 0 || i >= g.n1 || j >= g.n2 || k >= g.n3) {
 #pragma unroll
-    for (int v = 0; v < NVAR; v++) LU[v * nz + t] = 0.0;
+    for (int v = 0; v < NVAR; v++) LU(v, 0.0);
 #pragma unroll
     for (int v = 0; v < 5; v++) LG[v * nz + t] = 0.0;
     return;
@@ -336,10 +357,10 @@ __global__ void __launch_bounds__(BLOCK) k_adj_ift(Dev g, const double* __restri
 #pragma unroll
     for (int v = 0; v < 5; v++) {
       LG[v * nz + t] = lp[v];
-      LU[v * nz + t] = 0.0;
+      LU(v, 0.0);
     }
 #pragma unroll
-    for (int v = 5; v < NVAR; v++) LU[v * nz + t] = lp[v] / m.gdet;
+    for (int v = 5; v < NVAR; v++) LU(v, lp[v] / m.gdet);
     return;
   }
   // Rows of the hydro conserved variables of the Jacobian: Jh[a][b] =
@@ -426,31 +447,12 @@ __global__ void __launch_bounds__(BLOCK) k_adj_ift(Dev g, const double* __restri
   }
   double gz = 0.0;
 #pragma unroll
-  for (int v = 0; v < NVAR; v++) LU[v * nz + t] = x[v];
+  for (int v = 0; v < NVAR; v++) LU(v, x[v]);
 #pragma unroll
   for (int a = 0; a < 5; a++) gz -= x[a] * Jh[a][NVAR];
 #pragma unroll
   for (int v = 0; v < 5; v++) LG[v * nz + t] = 0.0;
   GZ[t] += gz;
-}
-
-// Elementwise combinations of the reverse RK sweep over all padded zones.
-// mode 0 (after the stage-2 inversion): LV = LU, LL = (dt/2) LU.
-// mode 1 (after the stage-1 inversion): LU1 = LU + LV/2, LU0 = LV/2 + LU1,
-//         LL = dt LU1 (LU0 written into LV).
-__global__ void __launch_bounds__(BLOCK) k_adj_rk(long n, int mode, double dt, double* __restrict__ LU,
-                                                  double* __restrict__ LV, double* __restrict__ LL) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  if (mode == 0) {
-    LV[t] = LU[t];
-    LL[t] = 0.5 * dt * LU[t];
-  } else {
-    double lu1 = LU[t] + 0.5 * LV[t];
-    double lu0 = 0.5 * LV[t] + lu1;
-    LV[t] = lu0;
-    LL[t] = dt * lu1;
-  }
 }
 
 // Sum of the gamma parts: per-block partial sums of GZ + GF1 + GF2 + GF3.

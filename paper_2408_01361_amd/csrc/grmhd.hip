@@ -2551,7 +2551,7 @@ const char* grmhd_strerror(int code) {
 namespace {
 
 struct VjpCarve {
-  double *A, *B, *C, *LU, *LV, *LL, *LP, *LPh, *LG, *LE[3], *LS[3], *GZ, *GF[3];
+  double *A, *B, *C, *LV, *LL, *LP, *LPh, *LG, *LE[3], *LS[3], *GZ, *GF[3];
   unsigned char *fl1, *fl2;
   unsigned long long* fails;
 };
@@ -2564,7 +2564,6 @@ size_t vjp_carve(const grmhd_grid* g, int recon, char* base, VjpCarve* out) {
   v.A = cv.take<double>(base, NVAR * nz);
   v.B = cv.take<double>(base, NVAR * nz);
   v.C = cv.take<double>(base, NVAR * nz);
-  v.LU = cv.take<double>(base, NVAR * nz);
   v.LV = cv.take<double>(base, NVAR * nz);
   v.LL = cv.take<double>(base, NVAR * nz);
   v.LP = cv.take<double>(base, NVAR * nz);
@@ -2635,12 +2634,12 @@ int step_vjp(grmhd_ctx* c, const VjpCarve& w, const double* d_in, double dt, con
   if ((rc = stage_fluxes<double, double>(c, w.B))) return rc;
   if ((rc = stage_update<2, double>(c, w.B, w.C, dt, w.fails, w.fl2))) return rc;
   // reverse sweep
-  k_adj_ift<<<blocks_for(nz), BLOCK, 0, c->stream>>>(g, w.C, w.fl2, c->tabC, d_gout, w.LU, w.LG, w.GZ);
-  k_adj_rk<<<blocks_for(NVAR * nz), BLOCK, 0, c->stream>>>(NVAR * nz, 0, dt, w.LU, w.LV, w.LL);
+  k_adj_ift<<<blocks_for(nz), BLOCK, 0, c->stream>>>(g, w.C, w.fl2, c->tabC, d_gout, 0, dt, w.LV, w.LL, w.LG,
+                                                     w.GZ);
   if ((rc = hip_check())) return rc;
   if ((rc = adj_stage<RECON>(c, w, w.B, false, w.LP))) return rc;
-  k_adj_ift<<<blocks_for(nz), BLOCK, 0, c->stream>>>(g, w.B, w.fl1, c->tabC, w.LP, w.LU, w.LG, w.GZ);
-  k_adj_rk<<<blocks_for(NVAR * nz), BLOCK, 0, c->stream>>>(NVAR * nz, 1, dt, w.LU, w.LV, w.LL);
+  k_adj_ift<<<blocks_for(nz), BLOCK, 0, c->stream>>>(g, w.B, w.fl1, c->tabC, w.LP, 1, dt, w.LV, w.LL, w.LG,
+                                                     w.GZ);
   if ((rc = hip_check())) return rc;
   if ((rc = adj_stage<RECON>(c, w, w.A, true, d_gin))) return rc;
   long nb = blocks_for(nz);
