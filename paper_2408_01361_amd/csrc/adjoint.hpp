@@ -76,8 +76,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_emf(Dev g, const double* __restri
 // from the divergence, field slots through the EMF averages), pushed through
 // the face's local Jacobian onto its stencil: LS[(v*W + s) * nz + face], and
 // the gamma part added to GF[face].
-// Waves per SIMD the face adjoint is compiled for: at 2 it spills 20-76 B
-// per lane and runs about 10 % faster than at 1 (264-274 VGPRs, no spills).
+// Waves per SIMD the face adjoint is compiled for (2: 250-254 VGPRs, no
+// spills; about 10 % faster than 1 wave).
 #ifndef ADJ_FACE_WAVES
 #define ADJ_FACE_WAVES 2
 #endif
