@@ -1518,10 +1518,30 @@ __global__ void __launch_bounds__(BLOCK) k_divb_partial(Dev g, Box box, const do
 // step taken with it leaves the state unchanged).
 __global__ void __launch_bounds__(BLOCK) k_reduce_final(const double* pmax, const double* psum,
                                                         int n, double* out, double cfl) {
-  double mx = 0.0, sm = 0.0;
-  for (int q = threadIdx.x; q < n; q += BLOCK) {
-    mx = fmax(mx, pmax[q]);
-    if (psum) sm += psum[q];
+  // eight independent accumulators per thread, so that its loads are in
+  // flight together instead of each waiting for the previous one
+  constexpr int U = 8;
+  double m[U], a[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) m[u] = a[u] = 0.0;
+  int q = threadIdx.x;
+  for (; q + (U - 1) * BLOCK < n; q += U * BLOCK) {
+#pragma unroll
+    for (int u = 0; u < U; u++) m[u] = fmax(m[u], pmax[q + u * BLOCK]);
+    if (psum) {
+#pragma unroll
+      for (int u = 0; u < U; u++) a[u] += psum[q + u * BLOCK];
+    }
+  }
+  for (; q < n; q += BLOCK) {
+    m[0] = fmax(m[0], pmax[q]);
+    if (psum) a[0] += psum[q];
+  }
+  double mx = m[0], sm = a[0];
+#pragma unroll
+  for (int u = 1; u < U; u++) {
+    mx = fmax(mx, m[u]);
+    sm += a[u];
   }
   block_reduce(mx, sm);
   if (threadIdx.x == 0) {
