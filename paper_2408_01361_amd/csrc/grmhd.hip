@@ -63,6 +63,7 @@ struct Dev {
   long nz;            // padded zones per variable
   long plane;         // s1 * s2
   double dx1, dx2, dx3;
+  double idx1, idx2, idx3;  // 1 / dx_d (the update's differences multiply by them)
   double x1min, x2min;
   int bc[6];
   int pole_lo, pole_hi;
@@ -1188,9 +1189,9 @@ __device__ __forceinline__ void ct_field_rate(const Dev& g, const FT* __restrict
   double f2b3_p = 0.5 * (e(E1, sj) + e(E1, sj + sk)), f2b3_m = 0.5 * (e(E1, 0) + e(E1, sk));
   double f3b1_p = 0.5 * (e(E2, sk) + e(E2, sk + si)), f3b1_m = 0.5 * (e(E2, 0) + e(E2, si));
   double f3b2_p = -0.5 * (e(E1, sk) + e(E1, sk + sj)), f3b2_m = -0.5 * (e(E1, 0) + e(E1, sj));
-  L[B1] = -((f2b1_p - f2b1_m) / g.dx2 + (f3b1_p - f3b1_m) / g.dx3);
-  L[B2] = -((f1b2_p - f1b2_m) / g.dx1 + (f3b2_p - f3b2_m) / g.dx3);
-  L[B3] = -((f1b3_p - f1b3_m) / g.dx1 + (f2b3_p - f2b3_m) / g.dx2);
+  L[B1] = -((f2b1_p - f2b1_m) * g.idx2 + (f3b1_p - f3b1_m) * g.idx3);
+  L[B2] = -((f1b2_p - f1b2_m) * g.idx1 + (f3b2_p - f3b2_m) * g.idx3);
+  L[B3] = -((f1b3_p - f1b3_m) * g.idx1 + (f2b3_p - f2b3_m) * g.idx2);
 }
 
 template <int STAGE, typename FT, bool RATE = false, int MODE = U_PLAIN, bool FACE = false,
@@ -1227,9 +1228,9 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
     geometric_source(p, f, m, dgs, g.plane, q2, g.gam, S);
 #pragma unroll
     for (int v = 0; v < 5; v++) {
-      double d1 = ((double)F1[v * nz + c + si] - (double)F1[v * nz + c]) / g.dx1;
-      double d2 = ((double)F2[v * nz + c + sj] - (double)F2[v * nz + c]) / g.dx2;
-      double d3 = ((double)F3[v * nz + c + sk] - (double)F3[v * nz + c]) / g.dx3;
+      double d1 = ((double)F1[v * nz + c + si] - (double)F1[v * nz + c]) * g.idx1;
+      double d2 = ((double)F2[v * nz + c + sj] - (double)F2[v * nz + c]) * g.idx2;
+      double d3 = ((double)F3[v * nz + c + sk] - (double)F3[v * nz + c]) * g.idx3;
       L[v] = -((d1 + d2) + d3);
       if (v == U1 || v == U2) L[v] += S[v - U1];
     }
@@ -2160,6 +2161,9 @@ Dev make_dev(const grmhd_grid* grid, const grmhd_metric* metric, const grmhd_par
   g.dx1 = (grid->x1max - grid->x1min) / g.n1;
   g.dx2 = (grid->x2max - grid->x2min) / g.n2;
   g.dx3 = (grid->x3max - grid->x3min) / g.n3;
+  g.idx1 = 1.0 / g.dx1;
+  g.idx2 = 1.0 / g.dx2;
+  g.idx3 = 1.0 / g.dx3;
   g.x1min = grid->x1min;
   g.x2min = grid->x2min;
   for (int a = 0; a < 6; a++) g.bc[a] = grid->bc[a];
@@ -2923,6 +2927,9 @@ int grmhd_pack_create(grmhd_pack** out, int nblocks, const int* n, const int* of
     g.dx1 = (x1hi - x1lo) / n[b];
     g.dx2 = (x2hi - x2lo) / n[b];
     g.dx3 = (x3hi - x3lo) / n[b];
+    g.idx1 = 1.0 / g.dx1;
+    g.idx2 = 1.0 / g.dx2;
+    g.idx3 = 1.0 / g.dx3;
     g.x1min = x1lo;
     g.x2min = x2lo;
     for (int a = 0; a < 6; a++) g.bc[a] = GRMHD_BC_FROZEN;
