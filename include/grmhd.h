@@ -5,7 +5,7 @@
  * KHARMA paper): linear-MC or WENO5 reconstruction, local Lax-Friedrichs
  * fluxes of the ideal stress-energy tensor (EGRMHD section, ideal part),
  * Flux-CT magnetic-field transport, geometric source terms from cached
- * metric and connection (Core section, GRCoordinates), and the 1D_W
+ * metric derivatives (Core section, GRCoordinates), and the 1D_W
  * conserved->primitive inversion named in the Algorithm and Performance
  * sections (or, selected per context, the bracketed Kastaun et al. 2021
  * recovery the Algorithm section lists among the robust ones).  Metrics: flat Minkowski (Cartesian) or Kerr (M = 1) in modified
@@ -170,8 +170,11 @@ size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_params* params)
 
 /* Create a context over caller-owned device workspace (>= grmhd_workspace_bytes,
  * 256-byte aligned) and a hipStream_t (NULL = default stream).  Computes the
- * geometry tables on the device (metric and connection at zone centres,
- * faces and corners of every (x1, x2) column).  E_ARG on bad sizes or enums. */
+ * geometry tables on the device (metric at zone centres, faces and corners of
+ * every (x1, x2) column; at zone centres also the x1 and x2 derivatives of the
+ * metric, which the geometric source contracts with the stress-energy
+ * tensor, and the connection, which Extended GRMHD and the adjoint read).
+ * E_ARG on bad sizes or enums. */
 int grmhd_create(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_metric* metric,
                  const grmhd_params* params, void* d_workspace, size_t ws_bytes,
                  void* hip_stream);
