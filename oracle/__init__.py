@@ -61,7 +61,7 @@ RECON_VL = 4
 RECON_MP5 = 5
 RECON_PPM = 6
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
-INTEG_SSPRK2, INTEG_PC, INTEG_RK1 = 0, 1, 2
+INTEG_SSPRK2, INTEG_PC, INTEG_RK1, INTEG_SSPRK54 = 0, 1, 2, 3
 FL_RHO, FL_U, FL_FLUID_FRAME, FL_GAMMA, FL_TEMP = 1, 2, 4, 8, 16
 # floor and ceiling defaults (HARM-family values; the paper states none)
 FLOOR_DEFAULTS = dict(rho_min_geom=1e-6, u_min_geom=1e-8, bsq_over_rho_max=100.0,
@@ -111,6 +111,8 @@ def _declare(lib):
     lib.orc_weno5.restype = C.c_double
     lib.orc_mc_slope.argtypes = [C.c_double] * 3
     lib.orc_mc_slope.restype = C.c_double
+    lib.orc_ssprk54_coefficients.argtypes = [_D]
+    lib.orc_ssprk54_coefficients.restype = None
     lib.orc_wenoz.argtypes = [C.c_double] * 6
     lib.orc_wenoz.restype = C.c_double
     lib.orc_vl_slope.argtypes = [C.c_double] * 3
@@ -166,6 +168,8 @@ def cfg(grid, gam=4.0 / 3.0, recon=0, weno_eps=1e-26, newton_tol=1e-14,
     c.floors, c.fofc = int(bool(floors)), int(bool(fofc))
     c.ct = int(ct)
     c.integrator = int(integrator)
+    if c.integrator == INTEG_SSPRK54 and (c.floors or c.fofc or c.ct != CT_FLUX):
+        raise ValueError("SSPRK(5,4) takes the plain Flux-CT step only")
     c.tau_r, c.chi_emhd, c.nu_emhd = float(tau_r), float(chi_emhd), float(nu_emhd)
     fp = dict(FLOOR_DEFAULTS)
     for k, v in floor_params.items():
@@ -366,6 +370,14 @@ def qr_solve(A, b):
 
 def weno5(a, b, c_, d, e, eps=1e-26):
     return lib().orc_weno5(a, b, c_, d, e, eps)
+
+
+def ssprk54_coefficients():
+    """The SSPRK(5,4) step's Shu-Osher coefficients, as the step uses them:
+    c1, (a_k, b_k, c_k) for k = 2, 3, 4, then d2, d3, e3, d4, e4."""
+    out = np.zeros(15)
+    lib().orc_ssprk54_coefficients(_ptr(out))
+    return out
 
 
 def mc_slope(l, c_, r):

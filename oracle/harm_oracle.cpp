@@ -27,6 +27,7 @@
 // FMA, so every operation is individually rounded).
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <cstdlib>
 #include <vector>
@@ -84,7 +85,8 @@ typedef struct {
   int fofc;            // 1: first-order flux correction of zones a stage would break
   int ct;              // 0: Flux-CT; face-centred CT with 1: averaged, 2: upwinded edge EMFs
   int integrator;      // 0: SSPRK2; 1: predictor-corrector (half-step predictor, then the
-                       // full step from U^n with the predicted state's rates); 2: RK1 (forward Euler)
+                       // full step from U^n with the predicted state's rates); 2: RK1 (forward Euler);
+                       // 3: SSPRK(5,4) (Spiteri & Ruuth 2002)
   double tau_r, chi_emhd, nu_emhd;  // Extended GRMHD closure constants (orc_run_emhd)
 } orc_cfg;
 }
@@ -1536,7 +1538,16 @@ bool marked(const Grid& g, const std::vector<char>& mark, int i, int j, int k) {
 // each stage takes the edge EMFs from the fluxes, advances the faces
 // (phi1 = phin + dt R(Pn); phin+1 = (phin + phi1)/2 + dt R(P1)/2) and sets
 // every zone's conserved field to the mean of its new faces before U_to_P.
+long step_ssprk54(const Grid& g, std::vector<real>& P, real dt, int* flags);
+
 long step(const Grid& g, std::vector<real>& P, real dt, int* flags, std::vector<real>* phi = nullptr) {
+  if (g.c.integrator == 3) {  // the plain Flux-CT path only
+    if (phi || g.c.floors || g.c.fofc) {
+      fprintf(stderr, "oracle: SSPRK(5,4) takes the plain Flux-CT step only\n");
+      abort();
+    }
+    return step_ssprk54(g, P, dt, flags);
+  }
   const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
   std::vector<real> F[3], Fct[3];
   for (int d = 0; d < 3; d++) F[d].assign(NV * g.nz, 0.0);
@@ -1618,6 +1629,77 @@ long step(const Grid& g, std::vector<real>& P, real dt, int* flags, std::vector<
     }
   }
   return g_stats.fails - fails0;
+}
+
+// SSPRK(5,4), the five-stage fourth-order strong-stability-preserving
+// Runge-Kutta method of Spiteri & Ruuth (2002) that the Solvers section lists,
+// in its Shu-Osher form (coefficients as published, 15 digits):
+//   U(1)    = U^n + c1 dt L(P^n)
+//   U(k)    = a_k U^n + b_k U(k-1) + c_k dt L(P(k-1)),   k = 2, 3, 4
+//   U^{n+1} = d2 U(2) + d3 U(3) + e3 dt L(P(3)) + d4 U(4) + e4 dt L(P(4))
+// where every U(k) is followed by U_to_P with the previous stage's prims as
+// the guess (P(k) = U_to_P(U(k))), and a zone whose inversion fails keeps its
+// stage-input prims, as in the other integrators.  The stages take the plain
+// Flux-CT path (no floors, correction or face-centred CT).
+const real SSP54_C1 = 0.391752226571890;
+const real SSP54_A[5] = {0.0, 0.0, 0.444370493651235, 0.620101851488403, 0.178079954393132};
+const real SSP54_B[5] = {0.0, 0.0, 0.555629506348765, 0.379898148511597, 0.821920045606868};
+const real SSP54_C[5] = {0.0, 0.0, 0.368410593050371, 0.251891774271694, 0.544974750228521};
+const real SSP54_D2 = 0.517231671970585, SSP54_D3 = 0.096059710526147, SSP54_E3 = 0.063692468666290,
+           SSP54_D4 = 0.386708617503269, SSP54_E4 = 0.226007483236906;
+
+long step_ssprk54(const Grid& g, std::vector<real>& P, real dt, int* flags) {
+  const int n1 = g.c.n1, n2 = g.c.n2, n3 = g.c.n3;
+  std::vector<real> F[3];
+  for (int d = 0; d < 3; d++) F[d].assign(NV * g.nz, 0.0);
+  std::vector<real> Us[5];  // U^n, U(1) .. U(4)
+  for (int s = 0; s < 5; s++) Us[s].assign(NV * g.nz, 0.0);
+  std::vector<real> dtL3(NV * g.nz, 0.0);  // dt L(P(3)), for the last stage
+  std::vector<real> Pin = P;
+  long fails = 0;
+  for (int stage = 0; stage < 5; stage++) {
+    fill_ghosts(g, Pin);
+    compute_fluxes(g, Pin, F);
+    flux_ct(g, F);
+    std::vector<real> Pout = Pin;
+#pragma omp parallel for collapse(2) schedule(static) num_threads(g.c.nthreads) reduction(+ : fails)
+    for (int k = 0; k < n3; k++)
+      for (int j = 0; j < n2; j++)
+        for (int i = 0; i < n1; i++) {
+          real p[NV], L[NV], Unew[NV], pn[NV];
+          for (int v = 0; v < NV; v++) p[v] = Vc(Pin, g, v, i, j, k);
+          rhs(g, F, p, i, j, k, L);
+          if (stage == 0) {
+            real u0[NV];
+            cons_at(g, p, i, j, u0);
+            for (int v = 0; v < NV; v++) V(Us[0], g, v, i, j, k) = u0[v];
+          }
+          for (int v = 0; v < NV; v++) {
+            const real dtl = dt * L[v];
+            const real un = Vc(Us[0], g, v, i, j, k);
+            if (stage == 0) {
+              Unew[v] = un + SSP54_C1 * dtl;
+            } else if (stage < 4) {
+              const int s = stage + 1;
+              Unew[v] = SSP54_A[s] * un + SSP54_B[s] * Vc(Us[stage], g, v, i, j, k) + SSP54_C[s] * dtl;
+              if (stage == 3) V(dtL3, g, v, i, j, k) = dtl;
+            } else {
+              Unew[v] = SSP54_D2 * Vc(Us[2], g, v, i, j, k) + SSP54_D3 * Vc(Us[3], g, v, i, j, k) +
+                        SSP54_E3 * Vc(dtL3, g, v, i, j, k) + SSP54_D4 * Vc(Us[4], g, v, i, j, k) +
+                        SSP54_E4 * dtl;
+            }
+            if (stage < 4) V(Us[stage + 1], g, v, i, j, k) = Unew[v];
+          }
+          int f = invert(g.c, g.gC[g.id2(i, j)], Unew, p, pn);
+          fails += f;
+          if (flags && f) flags[g.id(i, j, k)] += 1 << stage;
+          for (int v = 0; v < NV; v++) V(Pout, g, v, i, j, k) = pn[v];
+        }
+    Pin.swap(Pout);
+  }
+  P.swap(Pin);
+  g_stats.fails += fails;
+  return fails;
 }
 
 // CFL time step: cfl / max over interior zones of sum_d max(|c+|, |c-|)/dx_d,
@@ -2018,11 +2100,11 @@ long step_emhd(const Grid& g, const EmhdPar& e, std::vector<real>& P, std::vecto
 
 extern "C" {
 
-// Advance the padded prims in place by `nsteps` SSPRK2 steps of size dt
-// (dt <= 0: recompute the CFL dt before each step).  Returns the number of
-// zone inversions that failed; the dt actually used per step go to dts and,
-// when flags is not null, failures are added per padded zone (1: first
-// stage, 2: second stage).
+// Advance the padded prims in place by `nsteps` steps of size dt of the
+// configured integrator (dt <= 0: recompute the CFL dt before each step).
+// Returns the number of zone inversions that failed; the dt actually used per
+// step go to dts and, when flags is not null, failures are added per padded
+// zone (1 << s for a failure in stage s, s counted from 0).
 long orc_run(const orc_cfg* c, double* prims, double dt, int nsteps, double* dts, int* flags) {
   Grid g(*c);
   g_stats = RunStats{0, 0, 0, 0};
@@ -2371,6 +2453,18 @@ double orc_weno5(double a, double b, double c, double d, double e, double eps) {
 }
 
 double orc_mc_slope(double l, double c, double r) { return (double)mc_slope(l, c, r); }
+// The SSPRK(5,4) step's Shu-Osher coefficients as the step uses them:
+// c1, (a_k, b_k, c_k) for k = 2, 3, 4, then d2, d3, e3, d4, e4 (15 values).
+void orc_ssprk54_coefficients(double* out) {
+  int n = 0;
+  out[n++] = (double)SSP54_C1;
+  for (int k = 2; k <= 4; k++) {
+    out[n++] = (double)SSP54_A[k];
+    out[n++] = (double)SSP54_B[k];
+    out[n++] = (double)SSP54_C[k];
+  }
+  for (real x : {SSP54_D2, SSP54_D3, SSP54_E3, SSP54_D4, SSP54_E4}) out[n++] = (double)x;
+}
 double orc_wenoz(double a, double b, double c, double d, double e, double eps) {
   return (double)wenoz(a, b, c, d, e, eps);
 }

@@ -525,7 +525,72 @@ def test_integrators_time_order_and_linear_equivalence():
     assert np.abs(interior(a - b)).sum() < 1e-4 * np.abs(interior(a - r)).sum()
 
 
-@pytest.mark.parametrize("integ", [1, 2])
+def test_ssprk54_coefficients_satisfy_the_fourth_order_conditions():
+    """SSPRK(5,4) (Spiteri & Ruuth 2002, the Solvers section's list): the
+    oracle's Shu-Osher coefficients, turned into the Butcher tableau of the
+    same method (stage Y_k = U^n + dt sum_j A_kj L(Y_j)), meet every
+    order condition up to fourth order to rounding, each combination of
+    earlier stages is consistent (its weights sum to 1), every coefficient
+    is non-negative (what makes the method strong-stability-preserving), and
+    the fifth-order condition b.c^4 = 1/5 fails (it is a fourth-order method).
+    A mistyped digit above 1e-14 breaks at least one of these."""
+    co = oracle.ssprk54_coefficients()
+    c1, (a2, b2, c2), (a3, b3, c3), (a4, b4, c4) = co[0], co[1:4], co[4:7], co[7:10]
+    d2, d3, e3, d4, e4 = co[10:15]
+    assert (co >= 0).all()
+    for a, b in ((a2, b2), (a3, b3), (a4, b4)):
+        assert abs(a + b - 1.0) <= 2e-16
+    assert abs(d2 + d3 + d4 - 1.0) <= 2e-15   # 15-digit values: 1 + 1e-15 in decimal
+    A = np.zeros((5, 5))
+    A[1, 0] = c1
+    for k, (bk, ck) in zip((2, 3, 4), ((b2, c2), (b3, c3), (b4, c4))):
+        A[k] = bk * A[k - 1]    # a_k U^n + b_k Y_{k-1}: U^n's weight is implicit
+        A[k, k - 1] += ck
+    w = d2 * A[2] + d3 * A[3] + d4 * A[4]
+    w[3] += e3
+    w[4] += e4
+    c = A.sum(axis=1)
+    conds = [(w.sum(), 1.0), (w @ c, 1 / 2), (w @ c**2, 1 / 3), (w @ A @ c, 1 / 6),
+             (w @ c**3, 1 / 4), ((w * c) @ A @ c, 1 / 8), (w @ A @ c**2, 1 / 12), (w @ A @ A @ c, 1 / 24)]
+    for got, want in conds:
+        assert abs(got - want) <= 1e-14, (got, want)
+    assert abs(w @ c**4 - 1 / 5) > 1e-4
+
+
+def test_ssprk54_fourth_order_in_time():
+    """On a fixed 16^2 grid (fast mode, amplitude 1e-4) the SSPRK(5,4)
+    step's error against a 256-step run of itself falls at fourth order in
+    dt, with WENO5 and with donor-cell reconstruction (smooth semi-discrete
+    operators; a limiter's switches would blur the order).  Measured slopes
+    3.98 and 4.00 (WENO5), 4.03 and 4.01 (donor cell)."""
+    g, P, _, _ = linear_mode("fast", 16, ndim=2, amp=1e-4)
+    T = 0.2
+    for recon in (RECON_WENO5, oracle.RECON_DONOR):
+        c = oracle.cfg(g, recon=recon, integrator=oracle.INTEG_SSPRK54)
+        ref = oracle.run(c, P, T / 256, 256)[0]
+        e = [np.abs(interior(oracle.run(c, P, T / ns, ns)[0] - ref)).sum() for ns in (4, 8, 16)]
+        slope = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+        assert np.all(np.abs(slope - 4.0) < 0.3), (recon, slope)
+
+
+def test_ssprk54_keeps_a_uniform_state():
+    """A uniform moving, magnetised state in a flat periodic box: every
+    face flux is the same, so every stage's rate is exactly zero and each
+    stage's U is a combination of copies of U^n whose weights sum to 1; two
+    steps return the state to 1e-14 (the inversion's own tolerance) in
+    every zone."""
+    g = GridSpec(8, 6, 4)
+    P = np.zeros((8, 10, 12, 14))
+    P[0], P[1], P[2], P[3], P[4] = 1.0, 0.6, 0.3, -0.2, 0.1
+    P[5], P[6], P[7] = 0.4, 0.1, -0.3
+    c = oracle.cfg(g, recon=RECON_WENO5, integrator=oracle.INTEG_SSPRK54)
+    out, fails, _ = oracle.run(c, P, 0.05, 2)
+    assert fails == 0
+    rel = np.abs(interior(out) - interior(P)) / np.abs(interior(P))
+    assert rel.max() <= 1e-14, rel.max()
+
+
+@pytest.mark.parametrize("integ", [1, 2, 3])
 def test_integrators_conserve_on_a_periodic_grid(integ):
     g = GridSpec(12, 12, 12)
     c = oracle.cfg(g, gam=4 / 3, recon=RECON_WENO5, integrator=integ)
