@@ -433,10 +433,11 @@ def recon_extra(torch, gr, grid, P, gam, steps):
 
 def integrator_extra(torch, gr, grid, P, gam, recon, steps):
     """The headline torus and step with each time integrator (CFL dt each
-    step): SSPRK2, predictor-corrector, RK1."""
+    step): SSPRK2, predictor-corrector, RK1, SSPRK(5,4)."""
     Pt = torch.from_numpy(P).cuda()
     res = {}
-    for name, integ in (("ssprk2", gr.INTEG_SSPRK2), ("pc", gr.INTEG_PC), ("rk1", gr.INTEG_RK1)):
+    for name, integ in (("ssprk2", gr.INTEG_SSPRK2), ("pc", gr.INTEG_PC), ("rk1", gr.INTEG_RK1),
+                        ("ssprk54", gr.INTEG_SSPRK54)):
         s = gr.Grmhd(grid, gam, recon=recon, integrator=integ)
         s.load(Pt)
         for _ in range(10):          # untimed: clocks settle
@@ -446,7 +447,8 @@ def integrator_extra(torch, gr, grid, P, gam, recon, steps):
         res[name] = {"zone_cycles_per_s": grid.n1 * grid.n2 * grid.n3 * steps / el,
                      "ms_per_step": el * 1e3 / steps}
         del s
-    res["workload"] = "the headline torus and step, integrator swapped (a step of RK1 is one stage)"
+    res["workload"] = ("the headline torus and step, integrator swapped (a step of RK1 is one stage, "
+                       "of SSPRK(5,4) five)")
     return res
 
 

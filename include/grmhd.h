@@ -48,7 +48,7 @@ enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_DONOR = 2, GRMHD_R
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1, GRMHD_INV_IMPLICIT = 2 };
 enum { GRMHD_CT_FLUX = 0, GRMHD_CT_FACE_AVG = 1, GRMHD_CT_FACE_GS = 2 };
-enum { GRMHD_INTEG_SSPRK2 = 0, GRMHD_INTEG_PC = 1, GRMHD_INTEG_RK1 = 2 };
+enum { GRMHD_INTEG_SSPRK2 = 0, GRMHD_INTEG_PC = 1, GRMHD_INTEG_RK1 = 2, GRMHD_INTEG_SSPRK54 = 3 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2,
        GRMHD_BC_FROZEN = 3 };
 
@@ -140,8 +140,13 @@ typedef struct {
                          the VJP and the options above take); PC: predictor-
                          corrector, U* = U^n + (dt/2) L(P^n), then
                          U^{n+1} = U^n + dt L(P*); RK1: forward Euler, one
-                         stage per step.  PC and RK1 need Flux-CT without
-                         floors, the correction or the implicit recovery. */
+                         stage per step; SSPRK54: the five-stage fourth-order
+                         SSP Runge-Kutta method of Spiteri & Ruuth (2002) in
+                         Shu-Osher form (three conserved-variable registers
+                         in the workspace instead of one; every stage
+                         inverts its U).  PC, RK1 and SSPRK54 need Flux-CT
+                         without floors, the correction or the implicit
+                         recovery. */
   int egrmhd;         /* 1: Extended GRMHD (Implicit Solver and Extended Theory
                          section): two more zone-centred variables, the
                          rescaled heat flux qt = q (tau_R/(chi rho Theta^2))^1/2

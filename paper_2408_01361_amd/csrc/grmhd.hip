@@ -1194,6 +1194,17 @@ __device__ __forceinline__ void ct_field_rate(const Dev& g, const FT* __restrict
   L[B3] = -((f1b3_p - f1b3_m) * g.idx1 + (f2b3_p - f2b3_m) * g.idx2);
 }
 
+// SSPRK(5,4) of Spiteri & Ruuth (2002), Shu-Osher form, coefficients as
+// published (15 digits): stage k (k = 2, 3, 4) takes A_k U^n + B_k U(k-1) +
+// C_k dt L; the last stage D2 U(2) + D3 U(3) + E3 dt L(P(3)) + D4 U(4) +
+// E4 dt L(P(4)).
+constexpr double SSP54_C1 = 0.391752226571890;
+constexpr double SSP54_A2 = 0.444370493651235, SSP54_B2 = 0.555629506348765, SSP54_C2 = 0.368410593050371;
+constexpr double SSP54_A3 = 0.620101851488403, SSP54_B3 = 0.379898148511597, SSP54_C3 = 0.251891774271694;
+constexpr double SSP54_A4 = 0.178079954393132, SSP54_B4 = 0.821920045606868, SSP54_C4 = 0.544974750228521;
+constexpr double SSP54_D2 = 0.517231671970585, SSP54_D3 = 0.096059710526147, SSP54_E3 = 0.063692468666290,
+                 SSP54_D4 = 0.386708617503269, SSP54_E4 = 0.226007483236906;
+
 template <int STAGE, typename FT, bool RATE = false, int MODE = U_PLAIN, bool FACE = false,
           int INTEG = GRMHD_INTEG_SSPRK2>
 __device__ __forceinline__ void update_zone(const Dev& g, const double* __restrict__ Pin,
@@ -1244,8 +1255,45 @@ __device__ __forceinline__ void update_zone(const Dev& g, const double* __restri
   // SSPRK2: U1 = U^n + dt L(P^n), V = (U^n + U1)/2, U^{n+1} = V + dt L(P1)/2;
   // predictor-corrector: U* = U^n + (dt/2) L(P^n), V = U^n, U^{n+1} = V + dt L(P*);
   // RK1: the first stage alone, no register.
+  // SSPRK(5,4): three registers, R0 = U^n, R1 = the next stage's part
+  // without its rate, R2 = the last stage's, each summed in the order the
+  // method writes its terms:
+  //   1: R0 = U^n,  U(1) = R0 + C1 dtL,  R1 = A2 R0 + B2 U(1)
+  //   2: U(2) = R1 + C2 dtL,  R1 = A3 R0 + B3 U(2),  R2 = D2 U(2)
+  //   3: U(3) = R1 + C3 dtL,  R1 = A4 R0 + B4 U(3),  R2 = R2 + D3 U(3)
+  //   4: U(4) = R1 + C4 dtL,  R2 = (R2 + E3 dtL) + D4 U(4)
+  //   5: U^{n+1} = R2 + E4 dtL
   double U[NVAR];
-  if (STAGE == 1) {
+  if constexpr (INTEG == GRMHD_INTEG_SSPRK54) {
+    double* R0 = V;
+    double* R1 = V + NVAR * nz;
+    double* R2 = V + 2 * NVAR * nz;
+    double U0[NVAR];
+    if constexpr (STAGE == 1) prim_to_flux(p, f, m, g.gam, 0, U0);
+#pragma unroll
+    for (int v = 0; v < NVAR; v++) {
+      const double dtl = dt * L[v];
+      const long o = v * nz + c;
+      if constexpr (STAGE == 1) {
+        U[v] = U0[v] + SSP54_C1 * dtl;
+        R0[o] = U0[v];
+        R1[o] = SSP54_A2 * U0[v] + SSP54_B2 * U[v];
+      } else if constexpr (STAGE == 2) {
+        U[v] = R1[o] + SSP54_C2 * dtl;
+        R1[o] = SSP54_A3 * R0[o] + SSP54_B3 * U[v];
+        R2[o] = SSP54_D2 * U[v];
+      } else if constexpr (STAGE == 3) {
+        U[v] = R1[o] + SSP54_C3 * dtl;
+        R1[o] = SSP54_A4 * R0[o] + SSP54_B4 * U[v];
+        R2[o] = R2[o] + SSP54_D3 * U[v];
+      } else if constexpr (STAGE == 4) {
+        U[v] = R1[o] + SSP54_C4 * dtl;
+        R2[o] = (R2[o] + SSP54_E3 * dtl) + SSP54_D4 * U[v];
+      } else {
+        U[v] = R2[o] + SSP54_E4 * dtl;
+      }
+    }
+  } else if (STAGE == 1) {
     double U0[NVAR];
     prim_to_flux(p, f, m, g.gam, 0, U0);
     const double h = INTEG == GRMHD_INTEG_PC ? 0.5 * dt : dt;
@@ -1696,7 +1744,7 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
   if (p->inverter == GRMHD_INV_IMPLICIT && p->fofc) return false;
   if (p->inverter == GRMHD_INV_KASTAUN && !(p->kastaun_wmax > 1.0)) return false;
   // the other integrators take the plain Flux-CT step
-  if (p->integrator < GRMHD_INTEG_SSPRK2 || p->integrator > GRMHD_INTEG_RK1) return false;
+  if (p->integrator < GRMHD_INTEG_SSPRK2 || p->integrator > GRMHD_INTEG_SSPRK54) return false;
   if (p->integrator != GRMHD_INTEG_SSPRK2 &&
       (p->floors || p->fofc || p->ct != GRMHD_CT_FLUX || p->inverter == GRMHD_INV_IMPLICIT))
     return false;
@@ -1719,7 +1767,8 @@ size_t carve(grmhd_ctx* c, char* base, const grmhd_grid* g, const grmhd_params* 
   long plane = (long)(g->n1 + 2 * NG) * (g->n2 + 2 * NG);
   Carve cv;
   double *P = cv.take<double>(base, NVAR * nz), *P1 = cv.take<double>(base, NVAR * nz);
-  double* V = cv.take<double>(base, NVAR * nz);
+  // the stage registers: one (SSPRK2, predictor-corrector), three (SSPRK(5,4))
+  double* V = cv.take<double>(base, (prm->integrator == GRMHD_INTEG_SSPRK54 ? 3 : 1) * NVAR * nz);
   double* F[3];
   double* E[3];
   for (int d = 0; d < 3; d++) F[d] = cv.take<double>(base, NVAR * nz);
@@ -1958,7 +2007,9 @@ int stage_update(grmhd_ctx* c, const double* Pin, double* Pout, double dt,
                   partial, c->mark, p1, p2, p3, c->ustar);
   };
   if constexpr (INTEG != GRMHD_INTEG_SSPRK2) {  // the plain Flux-CT path only
-    if (rate && nb <= (unsigned)MAX_PARTIALS) return go(k_update<STAGE, FT, true, MODE, false, INTEG>, c->pdt);
+    if constexpr (INTEG != GRMHD_INTEG_SSPRK54 || STAGE == 5) {  // the stage that ends a step
+      if (rate && nb <= (unsigned)MAX_PARTIALS) return go(k_update<STAGE, FT, true, MODE, false, INTEG>, c->pdt);
+    }
     return go(k_update<STAGE, FT, false, MODE, false, INTEG>, (double*)nullptr);
   } else {
     if constexpr (STAGE == 2) {
@@ -1983,6 +2034,16 @@ int stage_floors(grmhd_ctx* c, const double* Pin, double* Pout, bool rate) {
                   (const double*)c->tabC, c->fails, c->mark, c->pdt);
   return launch(c, T_FLOORS, k_floors<STAGE, false, MODE>, nb, g, bz, Pin, Pout, c->V,
                 (const double*)c->tabC, c->fails, c->mark, (double*)nullptr);
+}
+
+// One SSPRK(5,4) stage from the ghost-filled prims Pin: fluxes, EMFs and
+// the update of the plain Flux-CT path.
+template <int STAGE, typename R, typename FT>
+int stage_ssp54(grmhd_ctx* c, const double* Pin, double* Pout, double dt, const double* dt_dev, bool rate) {
+  int rc;
+  if ((rc = stage_fluxes<R, FT>(c, Pin, nullptr, nullptr))) return rc;
+  return stage_update<STAGE, FT, U_PLAIN, GRMHD_INTEG_SSPRK54>(c, Pin, Pout, dt, nullptr, nullptr, dt_dev,
+                                                              rate);
 }
 
 // One RK2 stage from the ghost-filled prims Pin: fluxes, EMFs, update, then
@@ -2096,10 +2157,10 @@ int emhd_stage(grmhd_ctx* c, const double* Pin, double* Xin, double* Pout, doubl
   return implicit(k_implicit_emhd<STAGE, false>, (double*)nullptr);
 }
 
-// One SSPRK2 step with dt from the host, or, when dt_dev is given, with the
-// dt the device reduction left there.  The stage-2 update leaves the
-// CFL-rate partials of the new state, so the next dt needs only the final
-// pass.
+// One step of the configured integrator with dt from the host, or, when
+// dt_dev is given, with the dt the device reduction left there.  The update
+// that ends the step leaves the CFL-rate partials of the new state, so the
+// next dt needs only the final pass.
 template <typename R, typename FT>
 int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
   int rc;
@@ -2112,6 +2173,21 @@ int do_step(grmhd_ctx* c, double dt, const double* dt_dev = nullptr) {
     if ((rc = emhd_stage<1>(c, c->P, c->X, c->P1, c->X1, dt, dt_dev, false))) return rc;
     if ((rc = fill_ghosts(c, c->P1))) return rc;
     if ((rc = emhd_stage<2>(c, c->P1, c->X1, c->P, c->X, dt, dt_dev, true))) return rc;
+  } else if (c->params.integrator == GRMHD_INTEG_SSPRK54) {
+    // five stages, the prims alternating between P1 and P (U^n lives in a
+    // register from the first stage on); the last one's result copied back
+    if ((rc = stage_ssp54<1, R, FT>(c, c->P, c->P1, dt, dt_dev, false))) return rc;
+    if ((rc = fill_ghosts(c, c->P1))) return rc;
+    if ((rc = stage_ssp54<2, R, FT>(c, c->P1, c->P, dt, dt_dev, false))) return rc;
+    if ((rc = fill_ghosts(c, c->P))) return rc;
+    if ((rc = stage_ssp54<3, R, FT>(c, c->P, c->P1, dt, dt_dev, false))) return rc;
+    if ((rc = fill_ghosts(c, c->P1))) return rc;
+    if ((rc = stage_ssp54<4, R, FT>(c, c->P1, c->P, dt, dt_dev, false))) return rc;
+    if ((rc = fill_ghosts(c, c->P))) return rc;
+    if ((rc = stage_ssp54<5, R, FT>(c, c->P, c->P1, dt, dt_dev, true))) return rc;
+    if (hipMemcpyAsync(c->P, c->P1, sizeof(double) * NVAR * g.nz, hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+      return GRMHD_E_HIP;
   } else if (c->params.integrator == GRMHD_INTEG_RK1) {  // one stage, its result copied back to the state
     if ((rc = stage<1, R, FT>(c, c->P, c->P1, dt, dt_dev, true))) return rc;
     if (hipMemcpyAsync(c->P, c->P1, sizeof(double) * NVAR * g.nz, hipMemcpyDeviceToDevice, c->stream) !=

@@ -22,7 +22,7 @@ RECON_MC, RECON_WENO5, RECON_DONOR, RECON_WENOZ, RECON_VL, RECON_MP5, RECON_PPM 
 PREC_FP64, PREC_MIXED = 0, 1
 INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
-INTEG_SSPRK2, INTEG_PC, INTEG_RK1 = 0, 1, 2
+INTEG_SSPRK2, INTEG_PC, INTEG_RK1, INTEG_SSPRK54 = 0, 1, 2, 3
 BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FROZEN = 0, 1, 2, 3
 NG, NVAR = 3, 8
 
@@ -219,7 +219,7 @@ class Grmhd:
     inverter (INV_1DW, INV_KASTAUN, INV_IMPLICIT), floors (with the keyword
     floor parameters of FLOOR_DEFAULTS), fofc (first-order flux correction),
     ct (CT_FLUX, or face-centred CT_FACE_AVG / CT_FACE_GS, whose face fields
-    load_faces takes), integrator (INTEG_SSPRK2, INTEG_PC, INTEG_RK1),
+    load_faces takes), integrator (INTEG_SSPRK2, INTEG_PC, INTEG_RK1, INTEG_SSPRK54),
     egrmhd (Extended GRMHD with the closure constants tau_r, chi_emhd,
     nu_emhd; needs INTEG_PC; its two extra variables via load_extended /
     extended).

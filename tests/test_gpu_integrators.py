@@ -1,10 +1,10 @@
-"""GPU-vs-oracle parity of the other time integrators: predictor-corrector
-and RK1 (forward Euler), through the C ABI.
+"""GPU-vs-oracle parity of the other time integrators: predictor-corrector,
+RK1 (forward Euler) and SSPRK(5,4), through the C ABI.
 
 Bars as for SSPRK2 (parity_util.check): relative L1 per primitive at most
 1e-12 per step, every zone within the per-zone bars, failure counts equal,
 the u~ of a linear mode at rest held to 3x the oracle's own FMA spread on
-the case.  RK1's one stage
+the case.  RK1's one stage (SSPRK(5,4)'s fifth)
 writes the CFL-rate partials itself, so a device-side CFL step must equal
 a host-dt step with the dt the oracle estimates.
 """
@@ -19,7 +19,7 @@ from workloads import linear_mode, fm_torus, bondi, interior, RECON_MC, RECON_WE
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-PC, RK1 = oracle.INTEG_PC, oracle.INTEG_RK1
+PC, RK1, SSP54 = oracle.INTEG_PC, oracle.INTEG_RK1, oracle.INTEG_SSPRK54
 
 
 def _setup():
@@ -38,7 +38,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("integ", [PC, RK1], ids=["pc", "rk1"])
+@pytest.mark.parametrize("integ", [PC, RK1, SSP54], ids=["pc", "rk1", "ssprk54"])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_step_parity_integrators(case, integ):
     torch, gr = _setup()
@@ -57,12 +57,12 @@ def test_step_parity_integrators(case, integ):
     check(out, ref, noisy, label="%s %d" % (case, integ), alt=alt)
 
 
-@pytest.mark.parametrize("integ", [PC, RK1], ids=["pc", "rk1"])
+@pytest.mark.parametrize("integ", [PC, RK1, SSP54], ids=["pc", "rk1", "ssprk54"])
 def test_device_cfl_step_integrators(integ):
     """Device-side CFL steps: each step's dt is the oracle's CFL estimate of
     the state it starts from (the partials the previous step's last stage
-    wrote -- RK1's only stage, PC's corrector), and the steps match the
-    oracle run at those dts."""
+    wrote -- RK1's only stage, PC's corrector, SSPRK(5,4)'s fifth stage),
+    and the steps match the oracle run at those dts."""
     torch, gr = _setup()
     grid, P, _ = fm_torus(24, 24, 8)
     c = oracle.cfg(grid, gam=13 / 9, recon=RECON_WENO5, integrator=integ)
@@ -87,7 +87,7 @@ def test_torus128_integrators_full_step():
     import os
     gam = 13 / 9
     grid, P, _ = fm_torus(128, 128, 128, seed=1, gamma=gam)
-    for integ in (PC, RK1):
+    for integ in (PC, RK1, SSP54):
         s = gr.Grmhd(grid, gam, recon=RECON_WENO5, integrator=integ)
         s.load(torch.from_numpy(P).cuda())
         s.step_cfl()
@@ -105,6 +105,7 @@ def test_torus128_integrators_full_step():
 def test_other_integrators_take_the_plain_path_only():
     torch, gr = _setup()
     grid, P, _ = fm_torus(16, 16, 4)
-    for kw in (dict(floors=True), dict(fofc=True), dict(ct=gr.CT_FACE_AVG), dict(inverter=gr.INV_IMPLICIT)):
-        with pytest.raises(gr.GrmhdError):
-            gr.Grmhd(grid, 13 / 9, integrator=gr.INTEG_PC, **kw)
+    for integ in (gr.INTEG_PC, gr.INTEG_RK1, gr.INTEG_SSPRK54):
+        for kw in (dict(floors=True), dict(fofc=True), dict(ct=gr.CT_FACE_AVG), dict(inverter=gr.INV_IMPLICIT)):
+            with pytest.raises(gr.GrmhdError):
+                gr.Grmhd(grid, 13 / 9, integrator=integ, **kw)

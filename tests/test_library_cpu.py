@@ -118,13 +118,16 @@ def test_integrator_parameters_are_validated():
     mk = lambda integ, **kw: grmhd.make_params(13 / 9, 0.9, 1e-26, 1e-14, 30, grmhd.RECON_WENO5,
                                                grmhd.PREC_FP64, 0, 1e3, integrator=integ, **kw)
     base = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INTEG_SSPRK2)))
-    for integ in (grmhd.INTEG_PC, grmhd.INTEG_RK1):
-        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(integ))) == base
+    nz = 38 ** 3
+    for integ in (grmhd.INTEG_PC, grmhd.INTEG_RK1, grmhd.INTEG_SSPRK54):
+        # SSPRK(5,4) keeps two more conserved-variable registers
+        extra = 2 * 8 * nz * 8 if integ == grmhd.INTEG_SSPRK54 else 0
+        assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(integ))) == base + extra
         # the other integrators take the plain Flux-CT step only
         for kw in (dict(floors=True), dict(fofc=True), dict(ct=grmhd.CT_FACE_GS)):
             assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(integ, **kw))) == 0
         assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(integ))) == 0
-    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(3))) == 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(4))) == 0
     p = mk(grmhd.INTEG_PC)
     p.inverter = grmhd.INV_IMPLICIT
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(p)) == 0
@@ -166,7 +169,7 @@ def test_implicit_recovery_parameters():
     impl = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INV_IMPLICIT)))
     assert impl >= base + 8 * 8 * 38 ** 3          # the stored U* of a stage
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INV_IMPLICIT, fofc=True))) == 0
-    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(3))) == 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(4))) == 0
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(grmhd.INV_IMPLICIT))) == 0
 
 
