@@ -60,6 +60,7 @@ RECON_WENOZ = 3
 RECON_VL = 4
 RECON_MP5 = 5
 RECON_PPM = 6
+RECON_PPMX = 7
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
 INTEG_SSPRK2, INTEG_PC, INTEG_RK1, INTEG_SSPRK54 = 0, 1, 2, 3
 FL_RHO, FL_U, FL_FLUID_FRAME, FL_GAMMA, FL_TEMP = 1, 2, 4, 8, 16
@@ -121,6 +122,8 @@ def _declare(lib):
     lib.orc_mp5.restype = C.c_double
     lib.orc_ppm_edges.argtypes = [C.c_double] * 5 + [C.POINTER(C.c_double)] * 2
     lib.orc_ppm_edges.restype = None
+    lib.orc_ppmx_edges.argtypes = [C.c_double] * 5 + [C.POINTER(C.c_double)] * 2
+    lib.orc_ppmx_edges.restype = None
     L = C.POINTER(C.c_longlong)
     lib.orc_count_face.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, C.c_int, L]
     lib.orc_count_zone_update.argtypes = [P, _D, C.c_int, C.c_int, C.c_int, C.c_double, L]
@@ -400,6 +403,14 @@ def ppm_edges(a, b, c_, d, e):
     """(left, right) edge values of the middle zone."""
     l, r = C.c_double(), C.c_double()
     lib().orc_ppm_edges(a, b, c_, d, e, C.byref(l), C.byref(r))
+    return l.value, r.value
+
+
+def ppmx_edges(a, b, c_, d, e):
+    """PPMX (Colella & Sekora 2008): (left, right) edge values of the
+    middle zone."""
+    l, r = C.c_double(), C.c_double()
+    lib().orc_ppmx_edges(a, b, c_, d, e, C.byref(l), C.byref(r))
     return l.value, r.value
 
 

@@ -57,7 +57,7 @@ enum { RHO = 0, UU = 1, U1 = 2, U2 = 3, U3 = 4, B1 = 5, B2 = 6, B3 = 7 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_POLAR = 2, BC_FROZEN = 3 };
 enum { MINKOWSKI = 0, KERR_MKS = 1 };
 enum { RECON_MC = 0, RECON_WENO5 = 1, RECON_DONOR = 2, RECON_WENOZ = 3, RECON_VL = 4, RECON_MP5 = 5,
-       RECON_PPM = 6 };
+       RECON_PPM = 6, RECON_PPMX = 7 };
 
 }  // namespace
 
@@ -417,6 +417,61 @@ void ppm_edges(real a, real b, real c, real d, real e, real& aL, real& aR) {
     aR = 3.0 * c - 2.0 * aL;
 }
 
+// PPMX: PPM with the extremum-preserving limiter of Colella & Sekora
+// (2008), C = 1.25.  Interface value of the face between y and z from
+// (x, y, z, w): the fourth-order 7/12 (y + z) - 1/12 (x + w); where it does
+// not lie between y and z it becomes (y + z)/2 - D/6 with the second
+// difference D = 3 (y - 2a + z) limited against C (x - 2y + z) and
+// C (y - 2z + w): the smallest magnitude with their common sign, 0 if the
+// signs differ.
+real ppmx_interface(real x, real y, real z, real w) {
+  const real C = 1.25;
+  real a = 7.0 / 12.0 * (y + z) - 1.0 / 12.0 * (x + w);
+  if ((a - y) * (z - a) < 0.0) {
+    real d = 3.0 * (y - 2.0 * a + z), dl = x - 2.0 * y + z, dr = y - 2.0 * z + w;
+    real lim = 0.0;
+    if (d > 0.0 && dl > 0.0 && dr > 0.0) lim = rmin(d, rmin(C * dl, C * dr));
+    if (d < 0.0 && dl < 0.0 && dr < 0.0) lim = -rmin(-d, rmin(-C * dl, -C * dr));
+    a = 0.5 * (y + z) - lim / 6.0;
+  }
+  return a;
+}
+
+// PPMX edge values of zone c from (a, b, c, d, e): the two interface values,
+// then, where the zone holds an extremum (of the parabola, (aR - c)(c - aL)
+// <= 0, or of the data, (d - c)(c - b) <= 0), the parabola's curvature
+// 6 (aL + aR - 2c) limited against C times the second differences centred
+// on b, c and d (smallest magnitude with the common sign, else 0) and both
+// edges' offsets from c scaled by limited / unlimited (c itself when the
+// curvature is 0); elsewhere Colella & Woodward's overshoot correction: an
+// edge more than twice as far from c as the other is moved to c - 2 (other
+// edge - c).
+void ppmx_edges(real a, real b, real c, real d, real e, real& aL, real& aR) {
+  const real C = 1.25;
+  aL = ppmx_interface(a, b, c, d);
+  aR = ppmx_interface(b, c, d, e);
+  if ((aR - c) * (c - aL) <= 0.0 || (d - c) * (c - b) <= 0.0) {
+    real d2 = 6.0 * (aL + aR - 2.0 * c);
+    real d2l = a - 2.0 * b + c, d2c = b - 2.0 * c + d, d2r = c - 2.0 * d + e;
+    real lim = 0.0;
+    if (d2 > 0.0 && d2l > 0.0 && d2c > 0.0 && d2r > 0.0)
+      lim = rmin(d2, rmin(C * d2l, rmin(C * d2c, C * d2r)));
+    if (d2 < 0.0 && d2l < 0.0 && d2c < 0.0 && d2r < 0.0)
+      lim = -rmin(-d2, rmin(-C * d2l, rmin(-C * d2c, -C * d2r)));
+    if (d2 != 0.0) {
+      aL = c + (aL - c) * (lim / d2);
+      aR = c + (aR - c) * (lim / d2);
+    } else {
+      aL = c;
+      aR = c;
+    }
+    return;
+  }
+  const real dl = aL - c, dr = aR - c;
+  if (fabs(dl) >= 2.0 * fabs(dr)) aL = c - 2.0 * dr;
+  if (fabs(dr) >= 2.0 * fabs(dl)) aR = c - 2.0 * dl;
+}
+
 // ------------------------------------------------------------------ grid --
 
 struct Grid {
@@ -561,6 +616,12 @@ void recon_one(const real q[6], int recon, real eps, real& qL, real& qR) {
     ppm_edges(q[0], q[1], q[2], q[3], q[4], l, r);  // zone -1: its right edge
     qL = r;
     ppm_edges(q[1], q[2], q[3], q[4], q[5], l, r);  // zone 0: its left edge
+    qR = l;
+  } else if (recon == RECON_PPMX) {
+    real l, r;
+    ppmx_edges(q[0], q[1], q[2], q[3], q[4], l, r);  // zone -1: its right edge
+    qL = r;
+    ppmx_edges(q[1], q[2], q[3], q[4], q[5], l, r);  // zone 0: its left edge
     qR = l;
   } else {
     qL = weno5(q[0], q[1], q[2], q[3], q[4], eps);
@@ -2470,6 +2531,12 @@ double orc_wenoz(double a, double b, double c, double d, double e, double eps) {
 }
 double orc_vl_slope(double l, double c, double r) { return (double)vl_slope(l, c, r); }
 double orc_mp5(double a, double b, double c, double d, double e) { return (double)mp5(a, b, c, d, e); }
+void orc_ppmx_edges(double a, double b, double c, double d, double e, double* aL, double* aR) {
+  real l, r;
+  ppmx_edges(a, b, c, d, e, l, r);
+  *aL = (double)l;
+  *aR = (double)r;
+}
 void orc_ppm_edges(double a, double b, double c, double d, double e, double* aL, double* aR) {
   real l, r;
   ppm_edges(a, b, c, d, e, l, r);
