@@ -406,7 +406,7 @@ def recon_extra(torch, gr, grid, P, gam, steps):
     Pt = torch.from_numpy(P).cuda()
     res = {}
     names = (("donor", gr.RECON_DONOR), ("mc", gr.RECON_MC), ("vl", gr.RECON_VL),
-             ("ppm", gr.RECON_PPM), ("mp5", gr.RECON_MP5), ("weno5", gr.RECON_WENO5),
+             ("ppm", gr.RECON_PPM), ("ppmx", gr.RECON_PPMX), ("mp5", gr.RECON_MP5), ("weno5", gr.RECON_WENO5),
              ("wenoz", gr.RECON_WENOZ))
     for name, recon in names:
         row = {}

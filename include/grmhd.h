@@ -44,7 +44,7 @@ enum { GRMHD_OK = 0, GRMHD_E_ARG = -1, GRMHD_E_HIP = -2, GRMHD_E_STATE = -3,
        GRMHD_E_NOMEM = -4 };
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KERR_MKS = 1 };
 enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_DONOR = 2, GRMHD_RECON_WENOZ = 3,
-       GRMHD_RECON_VL = 4, GRMHD_RECON_MP5 = 5, GRMHD_RECON_PPM = 6 };
+       GRMHD_RECON_VL = 4, GRMHD_RECON_MP5 = 5, GRMHD_RECON_PPM = 6, GRMHD_RECON_PPMX = 7 };
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_INV_1DW = 0, GRMHD_INV_KASTAUN = 1, GRMHD_INV_IMPLICIT = 2 };
 enum { GRMHD_CT_FLUX = 0, GRMHD_CT_FACE_AVG = 1, GRMHD_CT_FACE_GS = 2 };
@@ -85,8 +85,10 @@ typedef struct {
                          Don 2011), VL (linear, van Leer's harmonic-mean
                          limiter), MP5 (Suresh & Huynh 1997, alpha = 4) and
                          PPM (Colella & Woodward 1984, monotonised-central
-                         slopes and their parabola limiter).  Packs and the
-                         adjoint take MC or WENO5. */
+                         slopes and their parabola limiter), PPMX (PPM with
+                         the extremum-preserving limiter of Colella & Sekora
+                         2008, C = 1.25).  Packs and the adjoint take MC or
+                         WENO5. */
   int precision;      /* GRMHD_PREC_*: MIXED = FP32 reconstruction, fluxes, EMFs */
   int floors;         /* 1: floors and ceilings after every inversion (fields
                          below); 0: none */

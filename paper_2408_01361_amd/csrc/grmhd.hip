@@ -336,6 +336,14 @@ __device__ __forceinline__ void recon_pair(const double* __restrict__ P, long nz
       qL[v] = r;
       ppm_edges(m2, m1, p0, p1, p2, l, r);  // zone i: its left edge
       qR[v] = l;
+    } else if (RECON == GRMHD_RECON_PPMX) {
+      R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
+        p2 = (R)q[2 * s];
+      R l, r;
+      ppmx_edges(m3, m2, m1, p0, p1, l, r);  // zone i-1: its right edge
+      qL[v] = r;
+      ppmx_edges(m2, m1, p0, p1, p2, l, r);  // zone i: its left edge
+      qR[v] = l;
     } else {
       R m3 = (R)q[-3 * s], m2 = (R)q[-2 * s], m1 = (R)q[-s], p0 = (R)q[0], p1 = (R)q[s],
         p2 = (R)q[2 * s];
@@ -1725,7 +1733,7 @@ bool grid_ok(const grmhd_grid* g, const grmhd_params* p) {
       return false;
   }
   if (!(g->x1max > g->x1min && g->x2max > g->x2min && g->x3max > g->x3min)) return false;
-  if (p->recon < GRMHD_RECON_MC || p->recon > GRMHD_RECON_PPM) return false;
+  if (p->recon < GRMHD_RECON_MC || p->recon > GRMHD_RECON_PPMX) return false;
   // the WENO weights' products stay normal in FP64 and the FP32 indicators
   // stay positive for eps >= 1e-36
   if ((p->recon == GRMHD_RECON_WENO5 || p->recon == GRMHD_RECON_WENOZ) &&
@@ -1959,6 +1967,8 @@ int stage_fluxes(grmhd_ctx* c, const double* P, unsigned long long* zero = nullp
     rc = face ? go(k_flux_all<GRMHD_RECON_MP5, R, FT, true>) : go(k_flux_all<GRMHD_RECON_MP5, R, FT, false>);
   else if (c->params.recon == GRMHD_RECON_PPM)
     rc = face ? go(k_flux_all<GRMHD_RECON_PPM, R, FT, true>) : go(k_flux_all<GRMHD_RECON_PPM, R, FT, false>);
+  else if (c->params.recon == GRMHD_RECON_PPMX)
+    rc = face ? go(k_flux_all<GRMHD_RECON_PPMX, R, FT, true>) : go(k_flux_all<GRMHD_RECON_PPMX, R, FT, false>);
   else
     rc = face ? go(k_flux_all<GRMHD_RECON_WENO5, R, FT, true>) : go(k_flux_all<GRMHD_RECON_WENO5, R, FT, false>);
   if (rc) return rc;

@@ -131,6 +131,8 @@ using f64::mp5;
 using f32::mp5;
 using f64::ppm_edges;
 using f32::ppm_edges;
+using f64::ppmx_edges;
+using f32::ppmx_edges;
 using f64::llf;
 using f32::llf;
 using fdual::llf;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libgrmhd.so")
 
 OK, E_ARG, E_HIP, E_STATE, E_NOMEM = 0, -1, -2, -3, -4
 METRIC_MINKOWSKI, METRIC_KERR_MKS = 0, 1
-RECON_MC, RECON_WENO5, RECON_DONOR, RECON_WENOZ, RECON_VL, RECON_MP5, RECON_PPM = range(7)
+RECON_MC, RECON_WENO5, RECON_DONOR, RECON_WENOZ, RECON_VL, RECON_MP5, RECON_PPM, RECON_PPMX = range(8)
 PREC_FP64, PREC_MIXED = 0, 1
 INV_1DW, INV_KASTAUN, INV_IMPLICIT = 0, 1, 2
 CT_FLUX, CT_FACE_AVG, CT_FACE_GS = 0, 1, 2
@@ -214,7 +214,7 @@ class Grmhd:
 
     Options (the fields of grmhd_params in include/grmhd.h): recon
     (RECON_MC, RECON_WENO5, RECON_DONOR, RECON_WENOZ, RECON_VL, RECON_MP5,
-    RECON_PPM), precision
+    RECON_PPM, RECON_PPMX), precision
     (PREC_FP64, PREC_MIXED),
     inverter (INV_1DW, INV_KASTAUN, INV_IMPLICIT), floors (with the keyword
     floor parameters of FLOOR_DEFAULTS), fofc (first-order flux correction),

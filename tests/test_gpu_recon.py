@@ -1,6 +1,6 @@
 """GPU-vs-oracle parity of the further reconstructions: WENO-Z (power 2),
-linear reconstruction with van Leer's limiter, MP5 and PPM, through the C
-ABI.
+linear reconstruction with van Leer's limiter, MP5, PPM and PPMX, through
+the C ABI.
 
 Bars as for MC and WENO5 (parity_util.check): relative L1 per primitive at
 most 1e-12 per step, every zone within the per-zone bars, failure counts
@@ -24,7 +24,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 THREADS = min(16, os.cpu_count() or 1)
-WENOZ, VL, MP5, PPM = oracle.RECON_WENOZ, oracle.RECON_VL, oracle.RECON_MP5, oracle.RECON_PPM
+WENOZ, VL, MP5, PPM, PPMX = (oracle.RECON_WENOZ, oracle.RECON_VL, oracle.RECON_MP5, oracle.RECON_PPM,
+                             oracle.RECON_PPMX)
 
 
 def _setup():
@@ -52,6 +53,10 @@ CASES = {
     "alfven24x20_ppm_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, PPM, NOISY_MODE),
     "torus20x28x6_ppm": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, PPM, ()),
     "bondi32x16_ppm": lambda: (bondi(32, 16)[0:2], 4 / 3, PPM, ()),
+    "fast16_ppmx": lambda: (linear_mode("fast", 16, ndim=3)[0:2], 4 / 3, PPMX, NOISY_MODE),
+    "alfven24x20_ppmx_2d": lambda: (linear_mode("alfven", 24, ndim=2)[0:2], 4 / 3, PPMX, NOISY_MODE),
+    "torus20x28x6_ppmx": lambda: (fm_torus(20, 28, 6)[0:2], 13 / 9, PPMX, ()),
+    "bondi32x16_ppmx": lambda: (bondi(32, 16)[0:2], 4 / 3, PPMX, ()),
 }
 
 
@@ -73,7 +78,7 @@ def test_step_parity_further_reconstructions(case):
     check(out, ref, noisy, label=case, alt=alt)
 
 
-@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM])
+@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM, PPMX])
 def test_flux_parity_further_reconstructions(recon):
     torch, gr = _setup()
     grid, P, _ = fm_torus(16, 16, 8)
@@ -91,7 +96,7 @@ def test_flux_parity_further_reconstructions(recon):
         assert err.max() < 1e-12, (d, err)
 
 
-@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM])
+@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM, PPMX])
 def test_torus128_full_step_further_reconstructions(recon):
     """The benchmark torus (128^3) with each reconstruction: one device-side
     CFL step, every zone against the oracle."""
@@ -111,7 +116,7 @@ def test_torus128_full_step_further_reconstructions(recon):
     assert s.status()[0] == fails
 
 
-@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM])
+@pytest.mark.parametrize("recon", [WENOZ, VL, MP5, PPM, PPMX])
 def test_mixed_precision_further_reconstructions(recon):
     """FP32 reconstruction and fluxes against the FP64 GPU path of the same
     reconstruction (3 steps of a 32 x 32 x 16 torus): density within 1e-4
@@ -139,6 +144,6 @@ def test_mixed_precision_further_reconstructions(recon):
 def test_packs_and_adjoint_take_mc_or_weno5_only():
     torch, gr = _setup()
     g, blocks, _ = torus_pack(nblocks=4, n_global=32, sizes=(8,), probs=(1.0,), seed=4)
-    for recon in (WENOZ, VL, MP5, PPM):
+    for recon in (WENOZ, VL, MP5, PPM, PPMX):
         with pytest.raises(gr.GrmhdError):
             gr.Pack(g, [b["n"] for b in blocks], [b["offset"] for b in blocks], 13 / 9, recon=recon)

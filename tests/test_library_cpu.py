@@ -38,7 +38,7 @@ def test_workspace_and_argument_validation():
     assert nb < 8 * nz * 8 * 8
     bad = grmhd.make_grid(torus_grid(128, 2, 128))   # polar axis needs >= 3 zones
     assert lib.grmhd_workspace_bytes(C.byref(bad), C.byref(p)) == 0
-    p2 = grmhd.grmhd_params(13 / 9, 0.9, 1e-26, 1e-14, 30, 7, grmhd.PREC_FP64, 0)
+    p2 = grmhd.grmhd_params(13 / 9, 0.9, 1e-26, 1e-14, 30, 8, grmhd.PREC_FP64, 0)
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(p2)) == 0
     p3 = grmhd.grmhd_params(13 / 9, 0.9, 1e-26, 1e-14, 30, 0, grmhd.PREC_FP64, 1)
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(p3)) == 0
@@ -92,9 +92,9 @@ def test_reconstruction_choices_are_validated():
                                                      grmhd.PREC_FP64, 0, 1e3)
     base = lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_WENO5)))
     for r in (grmhd.RECON_MC, grmhd.RECON_DONOR, grmhd.RECON_WENOZ, grmhd.RECON_VL, grmhd.RECON_MP5,
-              grmhd.RECON_PPM):
+              grmhd.RECON_PPM, grmhd.RECON_PPMX):
         assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r))) == base
-    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(7))) == 0
+    assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(8))) == 0
     assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(-1))) == 0
     # the WENO regulariser must keep the weight products normal ...
     for r in (grmhd.RECON_WENO5, grmhd.RECON_WENOZ):
@@ -102,10 +102,10 @@ def test_reconstruction_choices_are_validated():
         assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 2.0))) == 0
         assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 1e-36))) == base
     # ... and is not looked at by the other schemes
-    for r in (grmhd.RECON_VL, grmhd.RECON_MP5, grmhd.RECON_PPM):
+    for r in (grmhd.RECON_VL, grmhd.RECON_MP5, grmhd.RECON_PPM, grmhd.RECON_PPMX):
         assert lib.grmhd_workspace_bytes(C.byref(g), C.byref(mk(r, 0.0))) == base
     # the adjoint and packs take MC or WENO5 only
-    for r in (grmhd.RECON_WENOZ, grmhd.RECON_VL, grmhd.RECON_MP5, grmhd.RECON_PPM):
+    for r in (grmhd.RECON_WENOZ, grmhd.RECON_VL, grmhd.RECON_MP5, grmhd.RECON_PPM, grmhd.RECON_PPMX):
         assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(r))) == 0
     assert lib.grmhd_vjp_workspace_bytes(C.byref(g), C.byref(mk(grmhd.RECON_MC))) > 0
 
